@@ -1,0 +1,151 @@
+/*
+ * semiring.h -- C ABI of libsemiring, the MI355X (gfx950) implementation of
+ * the semiring matrix product and transitive closure of
+ *
+ *   M. de Bondt, "Fast algorithms for anti-distance matrices as a
+ *   generalization of Boolean matrices", arXiv 1705.08743.
+ *
+ * Two semirings are supported, both exactly as the paper defines them:
+ *
+ *   SR_BOOL            Boolean matrices (Sec. II): entries {0, 1},
+ *                      a (+) b = max(a, b), a (x) b = min(a, b).
+ *   SR_ANTIDIST_U8     anti-distance matrices (Sec. III), integer-scaled as in
+ *   SR_ANTIDIST_U16    Sec. IV to {0, 1, ..., S} with S = 2^8 - 1 (uint8) or
+ *                      2^16 - 1 (uint16): a (+) b = max(a, b) and
+ *                      a (x) b = max(a + b - S, 0).  Entry S - w encodes a
+ *                      distance w; 0 is "no path" (distance >= S saturates).
+ *
+ * Matrix (+) is entrywise; the product is (A*B)_ij = (+)_k A_ik (x) B_kj
+ * (Sec. II), evaluated as a running (+) of column-times-row products; the
+ * closure is Warshall's / Floyd's algorithm (Sec. II, Sec. III), i.e. the
+ * transitive (not reflexive) closure A (+) A*A (+) A*A*A (+) ...
+ * (eq. trcl).  Every result is exact integer arithmetic, unique and
+ * independent of launch configuration.
+ *
+ * Memory layout (all matrices row-major, caller-owned device memory):
+ *   anti-distance: element (r, c) at base[r * ld + c], ld in ELEMENTS.
+ *   Boolean:       bit-packed 64-bit words; entry (r, c) is bit (c % 64) of
+ *                  word base[r * ld + c / 64] (least significant bit first,
+ *                  the byte/bit order of the paper's Boolean listing,
+ *                  Sec. IV); ld in 64-bit WORDS.  Bits at columns >= the
+ *                  matrix width ("padding bits") must be zero on input and
+ *                  are left zero on output.
+ * Alignment: every base pointer must be 16-byte aligned and every row stride
+ * (ld times the element size) a multiple of 16 bytes, else SR_EALIGN.  A
+ * buffer must span whole rows: rows * ld elements (words), including the
+ * padding of its last row; the kernels read (never write) up to the padded row
+ * end.  Row strides that are multiples of 128 bytes take the fastest tiles.
+ *
+ * Streams and ownership: `stream` is a hipStream_t (NULL = the null stream).
+ * Calls are asynchronous and stream-ordered: a zero return means the work was
+ * validated and enqueued; device-side faults surface at the caller's next
+ * synchronisation.  The library never frees, retains or reallocates caller
+ * buffers.  It keeps lazily allocated internal scratch (uint8 working copies,
+ * batch descriptors) that sr_shutdown() releases.  The library is not
+ * re-entrant for concurrent calls on the SAME stream from several host threads;
+ * distinct streams may be driven from distinct threads.
+ *
+ * Errors: argument errors are detected on the host before anything is
+ * enqueued and return a negative SR_E* code; sr_last_error() then returns a
+ * thread-local message.  No call aborts the process.
+ */
+#ifndef SEMIRING_H
+#define SEMIRING_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Semiring / storage kind (the `kind` argument of every call). */
+typedef enum sr_kind {
+    SR_BOOL = 0,          /* Boolean, bit-packed uint64 words */
+    SR_ANTIDIST_U8 = 1,   /* anti-distance, uint8 entries, S = 255 */
+    SR_ANTIDIST_U16 = 2   /* anti-distance, uint16 entries, S = 65535 */
+} sr_kind;
+
+/* Return codes. */
+enum {
+    SR_OK = 0,
+    SR_EINVAL = -1,        /* bad kind, negative size, ld < width, NULL with nonzero extent */
+    SR_EALIAS = -2,        /* semiring_mul output overlaps an input */
+    SR_EALIGN = -3,        /* base or row stride not 16-byte aligned */
+    SR_ENOMEM = -4,        /* internal scratch allocation failed */
+    SR_EDEVICE = -5,       /* a HIP call or kernel launch failed */
+    SR_EUNSUPPORTED = -6   /* flag combination not implemented */
+};
+
+/* Flags. */
+enum {
+    SR_ACCUMULATE = 1u,    /* semiring_mul: C := C (+) A*B instead of C := A*B */
+    SR_REFLEXIVE = 2u,     /* closure: return I (+) T (eq. rtc); not implemented -> SR_EUNSUPPORTED */
+    SR_BOOL_BITWISE = 4u,  /* Boolean: force the word OR-AND kernels (the default) */
+    SR_BOOL_MFMA = 8u      /* Boolean: request the int8 matrix-core path; not implemented -> SR_EUNSUPPORTED */
+};
+
+/*
+ * semiring_mul -- C := A * B, or C := C (+) A * B with SR_ACCUMULATE.
+ *
+ * Defined in Sec. II (product formula and the multiplication algorithm that
+ * sums column-times-row products) for Boolean matrices and in Sec. III / IV
+ * for anti-distance matrices.  A is R x K (lda), B is K x N (ldb), C is R x N
+ * (ldc); ld in elements (anti-distance) or 64-bit words (Boolean).
+ * K = 0 gives the zero matrix (or leaves C unchanged with SR_ACCUMULATE).
+ * R = 0 or N = 0 is a no-op.  C must not overlap A or B (SR_EALIAS): the
+ * product is out of place, and the in-place form with all three operands the
+ * same matrix is the closure below.
+ * Boolean padding bits of A (columns >= K) and B (columns >= N) must be zero.
+ */
+int semiring_mul(int kind, void *C, int64_t ldc, const void *A, int64_t lda,
+                 const void *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
+                 unsigned flags, void *stream);
+
+/*
+ * semiring_add -- C := A (+) B entrywise (Sec. II matrix addition; the `|`
+ * operator of the entrywise table in Sec. V): max for anti-distance, OR for
+ * Boolean words.  All three are R x N.  C may be exactly A or B (same base and
+ * ld); any other overlap is SR_EALIAS.
+ */
+int semiring_add(int kind, void *C, int64_t ldc, const void *A, int64_t lda,
+                 const void *B, int64_t ldb, int64_t R, int64_t N, void *stream);
+
+/*
+ * closure -- in place, T := A (+) A*A (+) A*A*A (+) ... for the D x D matrix
+ * A held in T (Sec. II eq. trcl; computed by Warshall's algorithm, Sec. II,
+ * which for anti-distance matrices is Floyd's algorithm, Sec. III).  The
+ * result is the transitive, non-reflexive closure: entry (i, j) is the best
+ * product over paths of at least one edge, so the diagonal holds "i lies on a
+ * cycle" (Boolean) or S minus the shortest cycle through i, saturated
+ * (anti-distance).  flags: 0 or SR_BOOL_BITWISE; SR_REFLEXIVE and
+ * SR_BOOL_MFMA return SR_EUNSUPPORTED.  D = 0 is a no-op.
+ */
+int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream);
+
+/*
+ * closure_batched -- `count` independent in-place closures, as closure()
+ * applied to each (T[g], ldt[g], D[g]).  The three arrays are HOST arrays of
+ * length count; T[g] are device pointers, each obeying the alignment rules
+ * above.  Anti-distance kinds only (Boolean returns SR_EUNSUPPORTED).  The
+ * matrices must not overlap each other.  The whole batch is one device-side
+ * work queue: graphs are claimed by workgroups largest-first; graphs of up
+ * to 256 vertices are closed entirely in LDS, larger ones through global
+ * memory by one workgroup each.
+ */
+int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t *D,
+                    int64_t count, unsigned flags, void *stream);
+
+/* Thread-local message describing the last non-SR_OK return on this thread. */
+const char *sr_last_error(void);
+
+/* Library version string. */
+const char *sr_version(void);
+
+/* Release internal scratch on every device (call with no work in flight). */
+void sr_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEMIRING_H */

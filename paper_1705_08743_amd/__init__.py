@@ -1,0 +1,249 @@
+"""Python binding of libsemiring, the gfx950 implementation of the semiring
+product and closure of de Bondt, arXiv 1705.08743 (see include/semiring.h).
+
+Argument marshalling only: every step runs in the HIP kernels of
+``libsemiring.so``; torch supplies device memory and the current stream.  The
+functions mirror the C ABI names and raise ``SemiringError`` on a non-zero
+return.  If the library has not been built, the first call raises: there is no
+fallback.
+
+Matrices are 2-D CUDA (HIP) tensors with unit column stride; the row stride
+``tensor.stride(0)`` is the ABI's leading dimension ``ld``:
+
+* anti-distance (``SR_ANTIDIST_U8`` / ``SR_ANTIDIST_U16``): ``torch.uint8`` /
+  ``torch.uint16`` tensors; the logical shape is the tensor shape, so a view
+  ``X[:, :n]`` of a padded ``(rows, ld)`` buffer is a rows x n matrix.
+* Boolean (``SR_BOOL``): ``torch.int64`` tensors of packed words (entry (r, c)
+  at bit c % 64 of word c // 64, least significant bit first); bit widths are
+  passed explicitly (``K``, ``N``, ``D``) and default to 64 x words.
+"""
+import ctypes
+import os
+
+SR_BOOL = 0
+SR_ANTIDIST_U8 = 1
+SR_ANTIDIST_U16 = 2
+
+SR_OK = 0
+SR_EINVAL = -1
+SR_EALIAS = -2
+SR_EALIGN = -3
+SR_ENOMEM = -4
+SR_EDEVICE = -5
+SR_EUNSUPPORTED = -6
+
+SR_ACCUMULATE = 1
+SR_REFLEXIVE = 2
+SR_BOOL_BITWISE = 4
+SR_BOOL_MFMA = 8
+
+ERROR_NAMES = {
+    SR_EINVAL: "SR_EINVAL", SR_EALIAS: "SR_EALIAS", SR_EALIGN: "SR_EALIGN",
+    SR_ENOMEM: "SR_ENOMEM", SR_EDEVICE: "SR_EDEVICE", SR_EUNSUPPORTED: "SR_EUNSUPPORTED",
+}
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsemiring.so")
+
+EXPORTS = ("semiring_mul", "semiring_add", "closure", "closure_batched",
+           "sr_last_error", "sr_version", "sr_shutdown")
+
+
+class SemiringError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__("%s (%d): %s" % (ERROR_NAMES.get(code, "error"), code, message))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (ctypes); raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libsemiring.so is not built (expected at %s); run "
+                "`python -c 'import __graft_entry__ as g; g.build()'` or "
+                "`python paper_1705_08743_amd/build.py`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        i64, vp, u32, i32 = ctypes.c_int64, ctypes.c_void_p, ctypes.c_uint, ctypes.c_int
+        L.semiring_mul.argtypes = [i32, vp, i64, vp, i64, vp, i64, i64, i64, i64, u32, vp]
+        L.semiring_mul.restype = i32
+        L.semiring_add.argtypes = [i32, vp, i64, vp, i64, vp, i64, i64, i64, vp]
+        L.semiring_add.restype = i32
+        L.closure.argtypes = [i32, vp, i64, i64, u32, vp]
+        L.closure.restype = i32
+        L.closure_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64), i64, u32, vp]
+        L.closure_batched.restype = i32
+        L.sr_last_error.restype = ctypes.c_char_p
+        L.sr_version.restype = ctypes.c_char_p
+        L.sr_shutdown.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != SR_OK:
+        raise SemiringError(rc, lib().sr_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+_DTYPE_KIND = None
+
+
+def kind_of(t):
+    """Semiring kind implied by a tensor's dtype."""
+    torch = _torch()
+    if t.dtype == torch.uint8:
+        return SR_ANTIDIST_U8
+    if t.dtype == torch.uint16:
+        return SR_ANTIDIST_U16
+    if t.dtype == torch.int64:
+        return SR_BOOL
+    raise TypeError("unsupported dtype %s (uint8, uint16 or int64 words)" % t.dtype)
+
+
+def _mat(t, name):
+    if t is None:
+        return None, 0, 0, 0
+    if t.dim() != 2:
+        raise ValueError("%s must be a 2-D tensor" % name)
+    if t.numel() and t.stride(1) != 1:
+        raise ValueError("%s must have unit column stride" % name)
+    if t.numel() and not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    ld = t.stride(0) if t.shape[0] > 1 else max(t.stride(0), t.shape[1])
+    return t.data_ptr() if t.numel() else None, ld, t.shape[0], t.shape[1]
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def semiring_mul(kind, C, A, B, R=None, K=None, N=None, flags=0, stream=None):
+    """C := A * B, or C (+)= A * B with flags=SR_ACCUMULATE (in place on C)."""
+    pc, ldc, rc_, nc = _mat(C, "C")
+    pa, lda, ra, ka = _mat(A, "A")
+    pb, ldb, rb, nb = _mat(B, "B")
+    if kind == SR_BOOL:
+        R = ra if R is None else R
+        K = 64 * ka if K is None else K
+        N = 64 * nc if N is None else N
+    else:
+        R = ra if R is None else R
+        K = ka if K is None else K
+        N = nb if N is None else N
+    _check(lib().semiring_mul(kind, pc, ldc, pa, lda, pb, ldb, R, K, N, flags, _stream(stream)))
+
+
+def semiring_add(kind, C, A, B, R=None, N=None, stream=None):
+    """C := A (+) B entrywise (C may be A or B)."""
+    pc, ldc, _, nc = _mat(C, "C")
+    pa, lda, ra, na = _mat(A, "A")
+    pb, ldb, _, _ = _mat(B, "B")
+    R = ra if R is None else R
+    N = (64 * nc if kind == SR_BOOL else na) if N is None else N
+    _check(lib().semiring_add(kind, pc, ldc, pa, lda, pb, ldb, R, N, _stream(stream)))
+
+
+def closure(kind, T, D=None, flags=0, stream=None):
+    """In-place transitive closure of the D x D matrix held in T."""
+    pt, ldt, rt, ct = _mat(T, "T")
+    D = rt if D is None else D
+    _check(lib().closure(kind, pt, ldt, D, flags, _stream(stream)))
+
+
+def closure_batched(kind, Ts, Ds=None, flags=0, stream=None):
+    """In-place closures of every matrix in the list Ts (one launch)."""
+    n = len(Ts)
+    ptrs = (ctypes.c_void_p * n)()
+    lds = (ctypes.c_int64 * n)()
+    dims = (ctypes.c_int64 * n)()
+    for i, t in enumerate(Ts):
+        p, ld, r, _ = _mat(t, "T[%d]" % i)
+        ptrs[i] = p
+        lds[i] = ld
+        dims[i] = r if Ds is None else Ds[i]
+    _check(lib().closure_batched(kind, ptrs, lds, dims, n, flags, _stream(stream)))
+
+
+def version():
+    return lib().sr_version().decode()
+
+
+def shutdown():
+    lib().sr_shutdown()
+
+
+# ---------------------------------------------------------------------------
+# allocation helpers (device memory comes from torch)
+# ---------------------------------------------------------------------------
+def padded_ld(cols, kind, align_bytes=128):
+    """Row stride (elements, or words for Boolean) for `cols` columns, rounded
+    to `align_bytes` (128 bytes lets every wave tile take the wide path)."""
+    if kind == SR_BOOL:
+        words = (cols + 63) // 64
+        per = max(2, align_bytes // 8)
+        return max(per, -(-words // per) * per)
+    es = 1 if kind == SR_ANTIDIST_U8 else 2
+    per = align_bytes // es
+    return max(per, -(-cols // per) * per)
+
+
+def empty(kind, rows, cols, device="cuda", zero=True):
+    """A rows x cols matrix view of a zero-filled padded device buffer (for
+    Boolean, rows x words with cols bits of payload)."""
+    torch = _torch()
+    dt = {SR_BOOL: torch.int64, SR_ANTIDIST_U8: torch.uint8, SR_ANTIDIST_U16: torch.uint16}[kind]
+    ld = padded_ld(cols, kind)
+    buf = (torch.zeros if zero else torch.empty)((max(rows, 1), ld), dtype=dt, device=device)
+    width = (cols + 63) // 64 if kind == SR_BOOL else cols
+    return buf[:rows, :width]
+
+
+def to_device(kind, host, cols=None, device="cuda"):
+    """Copy a host numpy matrix (uint8 / uint16 entries, or uint64 words) into
+    a padded device buffer; returns the logical view."""
+    import numpy as np
+    torch = _torch()
+    host = np.ascontiguousarray(host)
+    rows = host.shape[0]
+    if kind == SR_BOOL:
+        words = host.shape[1] if cols is None else (cols + 63) // 64
+        cols = 64 * words if cols is None else cols
+        out = empty(kind, rows, cols, device)
+        out.copy_(torch.from_numpy(host[:, :words].view(np.int64)))
+        return out
+    cols = host.shape[1] if cols is None else cols
+    out = empty(kind, rows, cols, device)
+    out.copy_(torch.from_numpy(host[:, :cols]))
+    return out
+
+
+def to_host(t):
+    """Copy a device matrix view to a contiguous numpy array (uint64 words
+    for Boolean)."""
+    import numpy as np
+    a = t.detach().cpu().contiguous().numpy()
+    if a.dtype == np.int64:
+        a = a.view(np.uint64)
+    return a
+
+
+__all__ = [
+    "SR_BOOL", "SR_ANTIDIST_U8", "SR_ANTIDIST_U16", "SR_OK", "SR_EINVAL", "SR_EALIAS",
+    "SR_EALIGN", "SR_ENOMEM", "SR_EDEVICE", "SR_EUNSUPPORTED", "SR_ACCUMULATE",
+    "SR_REFLEXIVE", "SR_BOOL_BITWISE", "SR_BOOL_MFMA", "SemiringError", "lib", "kind_of",
+    "semiring_mul", "semiring_add", "closure", "closure_batched", "version", "shutdown",
+    "padded_ld", "empty", "to_device", "to_host", "EXPORTS", "LIB_PATH",
+]

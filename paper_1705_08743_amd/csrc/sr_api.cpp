@@ -1,0 +1,327 @@
+// C-ABI front end of libsemiring (declared in include/semiring.h): argument
+// validation on the host, dispatch to the HIP launchers, uint8 working copies,
+// error reporting.  No torch types and no C++ exceptions cross this boundary.
+#include <hip/hip_runtime_api.h>
+
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <mutex>
+#include <numeric>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "semiring.h"
+#include "sr_internal.h"
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok() { return SR_OK; }
+
+int device_fail(hipError_t e, const char *what) {
+    return fail(SR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool valid_kind(int kind) {
+    return kind == SR_BOOL || kind == SR_ANTIDIST_U8 || kind == SR_ANTIDIST_U16;
+}
+
+
+// bytes per storage unit of the leading dimension
+int64_t unit_bytes(int kind) {
+    return kind == SR_BOOL ? 8 : (kind == SR_ANTIDIST_U8 ? 1 : 2);
+}
+
+// storage units needed per row for `cols` columns
+int64_t row_units(int kind, int64_t cols) { return kind == SR_BOOL ? (cols + 63) / 64 : cols; }
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Validates one matrix operand: rows x cols with leading dimension ld.
+int check_matrix(int kind, const char *name, const void *p, int64_t ld, int64_t rows,
+                 int64_t cols) {
+    if (rows < 0 || cols < 0) return fail(SR_EINVAL, "%s: negative extent", name);
+    if (ld < row_units(kind, cols))
+        return fail(SR_EINVAL, "%s: ld=%lld is less than the row width (%lld %s)", name,
+                    (long long)ld, (long long)row_units(kind, cols),
+                    kind == SR_BOOL ? "64-bit words" : "elements");
+    if (rows == 0 || cols == 0) return SR_OK;
+    if (p == nullptr) return fail(SR_EINVAL, "%s: NULL pointer with nonzero extent", name);
+    if (!aligned16(p)) return fail(SR_EALIGN, "%s: base pointer not 16-byte aligned", name);
+    if ((ld * unit_bytes(kind)) % 16 != 0)
+        return fail(SR_EALIGN, "%s: row stride of %lld bytes is not a multiple of 16", name,
+                    (long long)(ld * unit_bytes(kind)));
+    return SR_OK;
+}
+
+struct Span {
+    uintptr_t lo, hi;  // [lo, hi)
+};
+
+Span span_of(int kind, const void *p, int64_t ld, int64_t rows) {
+    const uintptr_t b = reinterpret_cast<uintptr_t>(p);
+    return Span{b, b + (uintptr_t)(rows * ld * unit_bytes(kind))};
+}
+
+bool overlap(Span a, Span b) { return a.lo < b.hi && b.lo < a.hi; }
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+// Stream-ordered working memory for uint8 problems (widened to uint16).
+std::once_flag g_pool_once;
+
+void configure_pool() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return;
+    uint64_t threshold = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
+}
+
+int work_alloc(void **p, size_t bytes, hipStream_t st) {
+    std::call_once(g_pool_once, configure_pool);
+    hipError_t e = hipMallocAsync(p, bytes, st);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(SR_ENOMEM, "could not allocate %zu bytes of working memory: %s", bytes,
+                    hipGetErrorString(e));
+    }
+    return SR_OK;
+}
+
+void work_free(void *p, hipStream_t st) {
+    if (p) (void)hipFreeAsync(p, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sr_last_error(void) { return g_err.c_str(); }
+
+const char *sr_version(void) { return "libsemiring 0.1 (gfx950)"; }
+
+void sr_shutdown(void) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (int d = 0; d < n; d++) {
+        if (hipSetDevice(d) != hipSuccess) continue;
+        (void)hipDeviceSynchronize();
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, d) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+    }
+    (void)hipSetDevice(cur);
+}
+
+int semiring_mul(int kind, void *C, int64_t ldc, const void *A, int64_t lda, const void *B,
+                 int64_t ldb, int64_t R, int64_t K, int64_t N, unsigned flags, void *stream) {
+    if (!valid_kind(kind)) return fail(SR_EINVAL, "semiring_mul: invalid kind %d", kind);
+    if (flags & ~(unsigned)(SR_ACCUMULATE | SR_BOOL_BITWISE | SR_BOOL_MFMA))
+        return fail(SR_EINVAL, "semiring_mul: unknown flags 0x%x", flags);
+    if (flags & SR_BOOL_MFMA)
+        return fail(SR_EUNSUPPORTED, "semiring_mul: the int8 matrix-core Boolean path is not built");
+    if (R < 0 || K < 0 || N < 0) return fail(SR_EINVAL, "semiring_mul: negative size");
+    if (R > INT32_MAX || K > INT32_MAX || N > INT32_MAX)
+        return fail(SR_EINVAL, "semiring_mul: sizes above 2^31-1 are not supported");
+    int rc;
+    if ((rc = check_matrix(kind, "C", C, ldc, R, N)) != SR_OK) return rc;
+    if ((rc = check_matrix(kind, "A", A, lda, R, K)) != SR_OK) return rc;
+    if ((rc = check_matrix(kind, "B", B, ldb, K, N)) != SR_OK) return rc;
+    if (R == 0 || N == 0) return ok();
+    const Span sc = span_of(kind, C, ldc, R);
+    if (K > 0 && (overlap(sc, span_of(kind, A, lda, R)) || overlap(sc, span_of(kind, B, ldb, K))))
+        return fail(SR_EALIAS,
+                    "semiring_mul: C overlaps A or B (the in-place form is closure())");
+    const bool acc = (flags & SR_ACCUMULATE) != 0;
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipSuccess;
+    if (kind == SR_BOOL) {
+        e = sr::launch_bool_mul(static_cast<uint64_t *>(C), ldc, static_cast<const uint64_t *>(A),
+                                lda, static_cast<const uint64_t *>(B), ldb, R, K, N, acc, st);
+    } else if (kind == SR_ANTIDIST_U16) {
+        e = sr::launch_ad_mul(false, static_cast<uint16_t *>(C), ldc,
+                              static_cast<const uint16_t *>(A), lda,
+                              static_cast<const uint16_t *>(B), ldb, R, K, N, acc, st);
+    } else {
+        // uint8: widen to uint16 working copies, multiply with S = 255, narrow.
+        const int64_t lk = round_up(std::max<int64_t>(K, 1), 64);
+        const int64_t ln = round_up(N, 64);
+        const size_t bytes = (size_t)(R * lk + K * ln + R * ln) * 2;
+        void *w = nullptr;
+        if ((rc = work_alloc(&w, bytes, st)) != SR_OK) return rc;
+        uint16_t *Aw = static_cast<uint16_t *>(w);
+        uint16_t *Bw = Aw + R * lk;
+        uint16_t *Cw = Bw + K * ln;
+        const uint8_t *A8 = static_cast<const uint8_t *>(A);
+        const uint8_t *B8 = static_cast<const uint8_t *>(B);
+        uint8_t *C8 = static_cast<uint8_t *>(C);
+        if (e == hipSuccess) e = sr::launch_widen_u8(Aw, lk, A8, lda, R, K, st);
+        if (e == hipSuccess) e = sr::launch_widen_u8(Bw, ln, B8, ldb, K, N, st);
+        if (e == hipSuccess && acc) e = sr::launch_widen_u8(Cw, ln, C8, ldc, R, N, st);
+        if (e == hipSuccess) e = sr::launch_ad_mul(true, Cw, ln, Aw, lk, Bw, ln, R, K, N, acc, st);
+        if (e == hipSuccess) e = sr::launch_narrow_u8(C8, ldc, Cw, ln, R, N, st);
+        work_free(w, st);
+    }
+    if (e != hipSuccess) return device_fail(e, "semiring_mul launch");
+    return ok();
+}
+
+int semiring_add(int kind, void *C, int64_t ldc, const void *A, int64_t lda, const void *B,
+                 int64_t ldb, int64_t R, int64_t N, void *stream) {
+    if (!valid_kind(kind)) return fail(SR_EINVAL, "semiring_add: invalid kind %d", kind);
+    if (R < 0 || N < 0) return fail(SR_EINVAL, "semiring_add: negative size");
+    int rc;
+    if ((rc = check_matrix(kind, "C", C, ldc, R, N)) != SR_OK) return rc;
+    if ((rc = check_matrix(kind, "A", A, lda, R, N)) != SR_OK) return rc;
+    if ((rc = check_matrix(kind, "B", B, ldb, R, N)) != SR_OK) return rc;
+    if (R == 0 || N == 0) return ok();
+    const Span sc = span_of(kind, C, ldc, R);
+    const bool same_a = (C == A && ldc == lda), same_b = (C == B && ldc == ldb);
+    if ((!same_a && overlap(sc, span_of(kind, A, lda, R))) ||
+        (!same_b && overlap(sc, span_of(kind, B, ldb, R))))
+        return fail(SR_EALIAS, "semiring_add: C partially overlaps A or B");
+    const int64_t units = row_units(kind, N);
+    hipError_t e = sr::launch_add((int)unit_bytes(kind), C, ldc, A, lda, B, ldb, R, units,
+                                  as_stream(stream));
+    if (e != hipSuccess) return device_fail(e, "semiring_add launch");
+    return ok();
+}
+
+int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream) {
+    if (!valid_kind(kind)) return fail(SR_EINVAL, "closure: invalid kind %d", kind);
+    if (flags & ~(unsigned)(SR_REFLEXIVE | SR_BOOL_BITWISE | SR_BOOL_MFMA))
+        return fail(SR_EINVAL, "closure: unknown flags 0x%x", flags);
+    if (flags & SR_REFLEXIVE)
+        return fail(SR_EUNSUPPORTED, "closure: the reflexive closure I (+) T is not built");
+    if (flags & SR_BOOL_MFMA)
+        return fail(SR_EUNSUPPORTED, "closure: the int8 matrix-core Boolean path is not built");
+    if (D < 0) return fail(SR_EINVAL, "closure: negative size");
+    if (D > INT32_MAX) return fail(SR_EINVAL, "closure: sizes above 2^31-1 are not supported");
+    int rc;
+    if ((rc = check_matrix(kind, "T", T, ldt, D, D)) != SR_OK) return rc;
+    if (D == 0) return ok();
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipSuccess;
+    if (kind == SR_BOOL) {
+        e = sr::launch_bool_closure(static_cast<uint64_t *>(T), ldt, D, st);
+    } else if (kind == SR_ANTIDIST_U16) {
+        e = sr::launch_ad_closure(false, static_cast<uint16_t *>(T), ldt, D, st);
+    } else {
+        const int64_t lw = round_up(D, 64);
+        void *w = nullptr;
+        if ((rc = work_alloc(&w, (size_t)(D * lw) * 2, st)) != SR_OK) return rc;
+        uint16_t *Tw = static_cast<uint16_t *>(w);
+        uint8_t *T8 = static_cast<uint8_t *>(T);
+        e = sr::launch_widen_u8(Tw, lw, T8, ldt, D, D, st);
+        if (e == hipSuccess) e = sr::launch_ad_closure(true, Tw, lw, D, st);
+        if (e == hipSuccess) e = sr::launch_narrow_u8(T8, ldt, Tw, lw, D, D, st);
+        work_free(w, st);
+    }
+    if (e != hipSuccess) return device_fail(e, "closure launch");
+    return ok();
+}
+
+int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t *D, int64_t count,
+                    unsigned flags, void *stream) {
+    if (!valid_kind(kind)) return fail(SR_EINVAL, "closure_batched: invalid kind %d", kind);
+    if (kind == SR_BOOL)
+        return fail(SR_EUNSUPPORTED, "closure_batched: Boolean batches are not built");
+    if (flags & ~(unsigned)SR_REFLEXIVE)
+        return fail(SR_EINVAL, "closure_batched: unknown flags 0x%x", flags);
+    if (flags & SR_REFLEXIVE)
+        return fail(SR_EUNSUPPORTED, "closure_batched: the reflexive closure is not built");
+    if (count < 0) return fail(SR_EINVAL, "closure_batched: negative count");
+    if (count == 0) return ok();
+    if (count > INT32_MAX) return fail(SR_EINVAL, "closure_batched: count above 2^31-1");
+    if (!T || !ldt || !D) return fail(SR_EINVAL, "closure_batched: NULL descriptor array");
+    std::vector<Span> spans;
+    spans.reserve((size_t)count);
+    int32_t max_d = 0;
+    for (int64_t g = 0; g < count; g++) {
+        char name[48];
+        snprintf(name, sizeof name, "T[%lld]", (long long)g);
+        if (D[g] > 65536) return fail(SR_EINVAL, "closure_batched: D[%lld] too large", (long long)g);
+        const int rc = check_matrix(kind, name, T[g], ldt[g], D[g], D[g]);
+        if (rc != SR_OK) return rc;
+        if (D[g] > 0) spans.push_back(span_of(kind, T[g], ldt[g], D[g]));
+        max_d = std::max<int32_t>(max_d, (int32_t)D[g]);
+    }
+    std::sort(spans.begin(), spans.end(), [](Span a, Span b) { return a.lo < b.lo; });
+    for (size_t i = 1; i < spans.size(); i++)
+        if (spans[i].lo < spans[i - 1].hi)
+            return fail(SR_EALIAS, "closure_batched: two matrices of the batch overlap");
+
+    hipStream_t st = as_stream(stream);
+    const bool s8 = kind == SR_ANTIDIST_U8;
+    // largest first (ties keep the caller's order)
+    std::vector<int64_t> order((size_t)count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return D[a] > D[b]; });
+
+    size_t work_elems = 0;
+    if (s8)
+        for (int64_t g = 0; g < count; g++) work_elems += (size_t)(D[g] * round_up(D[g], 8));
+    const size_t desc_bytes = round_up((int64_t)(count * sizeof(sr::BatchDesc)), 256);
+    void *w = nullptr;
+    int rc = work_alloc(&w, desc_bytes + work_elems * 2, st);
+    if (rc != SR_OK) return rc;
+    // Host copy of the descriptors; freed by a stream callback once the upload
+    // has executed, so the call stays asynchronous.
+    auto *hv = new std::vector<sr::BatchDesc>((size_t)count);
+    std::vector<sr::BatchDesc> &h = *hv;
+    uint16_t *arena = reinterpret_cast<uint16_t *>(static_cast<char *>(w) + desc_bytes);
+    size_t off = 0;
+    for (int64_t i = 0; i < count; i++) {
+        const int64_t g = order[(size_t)i];
+        sr::BatchDesc &d = h[(size_t)i];
+        d.D = (int32_t)D[g];
+        d.pad = 0;
+        if (s8) {
+            d.T8 = static_cast<uint8_t *>(T[g]);
+            d.ld8 = ldt[g];
+            d.ld = round_up(D[g], 8);
+            d.T = arena + off;
+            off += (size_t)(D[g] * d.ld);
+        } else {
+            d.T8 = nullptr;
+            d.ld8 = 0;
+            d.T = static_cast<uint16_t *>(T[g]);
+            d.ld = ldt[g];
+        }
+    }
+    sr::BatchDesc *dd = static_cast<sr::BatchDesc *>(w);
+    hipError_t e = hipMemcpyAsync(dd, h.data(), (size_t)count * sizeof(sr::BatchDesc),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipLaunchHostFunc(
+            st, [](void *p) { delete static_cast<std::vector<sr::BatchDesc> *>(p); }, hv);
+    else
+        delete hv;
+    if (e == hipSuccess) e = sr::launch_ad_closure_batched(s8, dd, count, max_d, st);
+    work_free(w, st);
+    if (e != hipSuccess) return device_fail(e, "closure_batched launch");
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Internal interface between the C-ABI front end (sr_api.cpp) and the HIP
+// kernel launchers (sr_antidist.hip, sr_bool.hip, sr_elementwise.hip,
+// sr_batched.hip).  Every launcher enqueues on `stream` and returns the
+// hipError_t of the launch; argument validation has already happened.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace sr {
+
+// Anti-distance entries live in uint16 storage on the device.  `s8` selects
+// the saturation distance: false -> S = 65535 (uint16 data), true -> S = 255
+// (uint8 data widened into uint16 working storage).
+
+// Blocked Floyd-Warshall tile edge for anti-distance closures (elements).
+constexpr int kAdBlock = 128;
+// Blocked Warshall tile edge for Boolean closures (bits).
+constexpr int kBoolBlock = 256;
+
+// C (+)= A * B (accumulate) or C := A * B.  Row strides in elements; every
+// row stride is a multiple of 8 elements (16 bytes).
+hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
+                         const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
+                         bool accumulate, hipStream_t stream);
+
+// In-place closure of the D x D matrix T (uint16 storage).
+hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, hipStream_t stream);
+
+// Individual phases of one blocked Floyd-Warshall round (for tests/timing).
+hipError_t launch_ad_fw_pivot(bool s8, uint16_t *T, int64_t ld, int64_t D, int64_t kb,
+                              hipStream_t stream);
+hipError_t launch_ad_fw_panels(bool s8, uint16_t *T, int64_t ld, int64_t D, int64_t kb,
+                               hipStream_t stream);
+hipError_t launch_ad_fw_update(bool s8, uint16_t *T, int64_t ld, int64_t D, int64_t kb,
+                               hipStream_t stream);
+
+// uint8 <-> uint16 copies of an R x C block (strides in elements).
+hipError_t launch_widen_u8(uint16_t *dst, int64_t ldd, const uint8_t *src, int64_t lds,
+                           int64_t R, int64_t C, hipStream_t stream);
+hipError_t launch_narrow_u8(uint8_t *dst, int64_t ldd, const uint16_t *src, int64_t lds,
+                            int64_t R, int64_t C, hipStream_t stream);
+
+// Boolean, bit-packed: strides in 64-bit words (even), widths in bits.
+hipError_t launch_bool_mul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda,
+                           const uint64_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
+                           bool accumulate, hipStream_t stream);
+hipError_t launch_bool_closure(uint64_t *T, int64_t ld, int64_t D, hipStream_t stream);
+
+// Entrywise (+): elem_bytes 1 or 2 -> max, 8 -> OR of words.  Widths in
+// elements (words for Boolean).
+hipError_t launch_add(int elem_bytes, void *C, int64_t ldc, const void *A, int64_t lda,
+                      const void *B, int64_t ldb, int64_t R, int64_t N, hipStream_t stream);
+
+// Batched anti-distance closure.  `desc` is a device array of `count`
+// descriptors, already ordered largest-first.
+struct BatchDesc {
+    uint16_t *T;    // matrix in uint16 storage (the caller's, or a working copy)
+    int64_t ld;     // row stride of T, elements (multiple of 8)
+    uint8_t *T8;    // uint8 data: the caller's matrix (widened into T, narrowed back)
+    int64_t ld8;    // row stride of T8, elements (multiple of 16)
+    int32_t D;      // vertices
+    int32_t pad;
+};
+hipError_t launch_ad_closure_batched(bool s8, const BatchDesc *desc, int64_t count,
+                                     int32_t max_d, hipStream_t stream);
+
+}  // namespace sr

@@ -1,0 +1,341 @@
+// Device-side building blocks shared by the anti-distance kernels
+// (sr_antidist.hip) and the batched closure (sr_batched.hip).
+//
+// Storage: anti-distance entries in uint16 words.  Two saturation distances:
+//   S = 65535 for uint16 data, S = 255 for uint8 data widened to uint16.
+// Arithmetic (Sec. III, integer-scaled as in Sec. IV):
+//   a (+) b = max(a, b);  a (x) b = max(a + b - S, 0) = b -sat (S - a),
+// the last form being the paper's rewriting of a + b - S as b - (S - a), done
+// here as one packed saturating subtract per two entries.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sr {
+namespace dev {
+
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 as_pair(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ __forceinline__ uint32_t as_word(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+
+// S - a on a packed pair: ~a for S = 65535; a ^ 0xFF for S = 255 (a <= 255).
+template <bool S8>
+__device__ __forceinline__ uint32_t neg_pair(uint32_t a) {
+    return S8 ? (a ^ 0x00FF00FFu) : ~a;
+}
+template <bool S8>
+__device__ __forceinline__ uint16_t neg_one(uint16_t a) {
+    return S8 ? (uint16_t)(a ^ 0xFFu) : (uint16_t)~a;
+}
+
+// B rows are read through the constant address space.  The rows of B used by
+// a tile are uniform across the wavefront, and this makes the compiler read
+// them with scalar loads (SGPR operands) without having to prove that no
+// store in the kernel may alias them.  Where a kernel does write rows it also
+// reads this way (the panel phase of the closure), reading an entry's old or
+// new value gives the same result because the pivot tile is closed.
+#define kconst __attribute__((address_space(4)))
+
+// acc (+)= a (x) b for two entries b of B that share one entry a of A, given
+// na = (S - a) in both halves: v_pk_sub_u16 (clamp) then v_pk_max_u16.
+__device__ __forceinline__ u16x2 step(u16x2 acc, u16x2 b, u16x2 na) {
+    return __builtin_elementwise_max(acc, __builtin_elementwise_sub_sat(b, na));
+}
+
+// A lane's KU consecutive entries of A as one load, and their S - a pairs.
+template <int KU> struct AWord;
+template <> struct AWord<2> {
+    typedef uint32_t type;
+    template <bool S8> __device__ static void negate(type a, uint32_t *na) { na[0] = neg_pair<S8>(a); }
+};
+template <> struct AWord<4> {
+    typedef uint2 type;
+    template <bool S8> __device__ static void negate(type a, uint32_t *na) {
+        na[0] = neg_pair<S8>(a.x);
+        na[1] = neg_pair<S8>(a.y);
+    }
+};
+template <> struct AWord<8> {
+    typedef uint4 type;
+    template <bool S8> __device__ static void negate(type a, uint32_t *na) {
+        na[0] = neg_pair<S8>(a.x);
+        na[1] = neg_pair<S8>(a.y);
+        na[2] = neg_pair<S8>(a.z);
+        na[3] = neg_pair<S8>(a.w);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// One wavefront computes C (+)= A * B for a tile of up to 64 rows (one row per
+// lane) and up to 2*NW columns (NW packed pairs per lane), over K inner steps.
+//
+// The row of B used at inner step k is the same for all 64 lanes, so its
+// words are read with scalar loads and enter each packed instruction as the
+// SGPR operand; each lane reads only its own row of A (2*KU bytes per KU
+// steps) and forms S - a with one XOR per two steps.  The inner loop is
+// therefore one v_pk_sub_u16 and one v_pk_max_u16 per two updates per lane.
+//
+// B is always read as whole 2*NW-column segments: the caller guarantees they
+// lie inside the (padded) rows.  Columns >= ncols of a segment feed only
+// accumulators that are not stored.  FULLC: ncols == 2*NW (whole-vector C
+// access); otherwise C is read and written entry-exactly.  Lanes >= nrows
+// compute on row 0 and store nothing.  nrows, ncols >= 1.  A, B and C rows
+// are 16-byte aligned (row strides multiples of 8 entries).
+// ---------------------------------------------------------------------------
+template <int NW, bool S8, bool FULLC>
+__device__ __forceinline__ void tile_compute(u16x2 (&acc)[NW], const uint16_t *crow,
+                                             const uint16_t *arow, const uint16_t *B, int64_t ldb,
+                                             int ncols, int K, bool accumulate) {
+    static_assert(NW % 4 == 0, "NW must be a multiple of 4");
+    if (accumulate) {
+        if (FULLC) {
+#pragma unroll
+            for (int q = 0; q < NW / 4; q++) {
+                const uint4 v = reinterpret_cast<const uint4 *>(crow)[q];
+                acc[4 * q + 0] = as_pair(v.x);
+                acc[4 * q + 1] = as_pair(v.y);
+                acc[4 * q + 2] = as_pair(v.z);
+                acc[4 * q + 3] = as_pair(v.w);
+            }
+        } else {
+#pragma unroll
+            for (int w = 0; w < NW; w++) {
+                const uint16_t lo = (2 * w < ncols) ? crow[2 * w] : (uint16_t)0;
+                const uint16_t hi = (2 * w + 1 < ncols) ? crow[2 * w + 1] : (uint16_t)0;
+                acc[w] = u16x2{lo, hi};
+            }
+        }
+    } else {
+#pragma unroll
+        for (int w = 0; w < NW; w++) acc[w] = u16x2{0, 0};
+    }
+
+    // KU inner steps per iteration: their KU rows of B occupy KU * NW = 64
+    // SGPRs (at most), which leaves room for addressing without spilling; the
+    // lane's KU entries of A come in one load issued an iteration ahead.
+    constexpr int KU = NW >= 32 ? 2 : (NW >= 16 ? 4 : 8);
+    typedef typename AWord<KU>::type AW;
+    int k = 0;
+    if (K >= KU) {
+        AW anext = *reinterpret_cast<const AW *>(arow);
+        for (; k + KU <= K; k += KU) {
+            const AW acur = anext;
+            if (k + 2 * KU <= K) anext = *reinterpret_cast<const AW *>(arow + k + KU);
+            uint32_t na[KU / 2];
+            AWord<KU>::template negate<S8>(acur, na);
+            const uint16_t *b0 = B + (int64_t)k * ldb;
+#pragma unroll
+            for (int kk = 0; kk < KU; kk++) {
+                const kconst uint32_t *brow = (const kconst uint32_t *)(b0 + kk * ldb);
+                const uint32_t n2 = na[kk >> 1];
+                const uint16_t n = (kk & 1) ? (uint16_t)(n2 >> 16) : (uint16_t)n2;
+                const u16x2 nv = u16x2{n, n};
+#pragma unroll
+                for (int w = 0; w < NW; w++) acc[w] = step(acc[w], as_pair(brow[w]), nv);
+            }
+        }
+    }
+    for (; k < K; k++) {
+        const uint16_t n = neg_one<S8>(arow[k]);
+        const u16x2 nv = u16x2{n, n};
+        const kconst uint32_t *brow = (const kconst uint32_t *)(B + (int64_t)k * ldb);
+#pragma unroll
+        for (int w = 0; w < NW; w++) acc[w] = step(acc[w], as_pair(brow[w]), nv);
+    }
+}
+
+template <int NW, bool FULLC>
+__device__ __forceinline__ void tile_store(const u16x2 (&acc)[NW], uint16_t *crow, int ncols) {
+    if (FULLC) {
+#pragma unroll
+        for (int q = 0; q < NW / 4; q++) {
+            uint4 v;
+            v.x = as_word(acc[4 * q + 0]);
+            v.y = as_word(acc[4 * q + 1]);
+            v.z = as_word(acc[4 * q + 2]);
+            v.w = as_word(acc[4 * q + 3]);
+            reinterpret_cast<uint4 *>(crow)[q] = v;
+        }
+    } else {
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            if (2 * w + 1 < ncols) {
+                reinterpret_cast<uint32_t *>(crow)[w] = as_word(acc[w]);
+            } else if (2 * w < ncols) {
+                crow[2 * w] = acc[w].x;
+            }
+        }
+    }
+}
+
+template <int NW, bool S8, bool FULLC>
+__device__ __forceinline__ void wave_tile_body(uint16_t *C, int64_t ldc, const uint16_t *A,
+                                               int64_t lda, const uint16_t *B, int64_t ldb,
+                                               int nrows, int ncols, int K, bool accumulate,
+                                               bool sync_before_store) {
+    const int lane = threadIdx.x & 63;
+    const bool live = lane < nrows;
+    const int64_t r = live ? lane : 0;
+    uint16_t *crow = C + r * ldc;
+    u16x2 acc[NW];
+    tile_compute<NW, S8, FULLC>(acc, crow, A + r * lda, B, ldb, ncols, K, accumulate);
+    if (sync_before_store) __syncthreads();
+    if (live) tile_store<NW, FULLC>(acc, crow, ncols);
+}
+
+// The 8-column fallback of wave_tile below.
+template <bool S8>
+__device__ __forceinline__ void wave_tile_narrow(uint16_t *C, int64_t ldc,
+                                                           const uint16_t *A, int64_t lda,
+                                                           const uint16_t *B, int64_t ldb,
+                                                           int nrows, int ncols, int K,
+                                                           bool accumulate) {
+    for (int c = 0; c < ncols; c += 8) {
+        const int nc = min(8, ncols - c);
+        if (nc == 8)
+            wave_tile_body<4, S8, true>(C + c, ldc, A, lda, B + c, ldb, nrows, 8, K, accumulate,
+                                        false);
+        else
+            wave_tile_body<4, S8, false>(C + c, ldc, A, lda, B + c, ldb, nrows, nc, K, accumulate,
+                                         false);
+    }
+}
+
+// One wavefront, tile of nrows x ncols at C.  bspan: columns of each B row
+// readable from the tile origin (row length ld minus the tile's first
+// column).  When a whole 2*NW-column segment fits (the usual case) the tile
+// runs as one NW-wide tile; otherwise (the last column chunk of a row whose
+// length is not a multiple of 2*NW) it runs as 8-column tiles, whose 16-byte
+// segments always fit because rows are padded to 16 bytes.
+// With sync_before_store the whole workgroup must call this (it executes one
+// barrier), including waves with no rows.  In the 8-column fallback the
+// sub-tiles store as they finish and the barrier comes last; a row-panel
+// update stays exact under that order because the pivot tile is closed (any
+// mix of old and new operand entries gives the same result).
+template <int NW, bool S8>
+__device__ __forceinline__ void wave_tile(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
+                                          const uint16_t *B, int64_t ldb, int nrows, int ncols,
+                                          int64_t bspan, int K, bool accumulate,
+                                          bool sync_before_store) {
+    if (nrows <= 0 || ncols <= 0) {
+        if (sync_before_store) __syncthreads();
+        return;
+    }
+    if (bspan >= 2 * NW) {
+        if (ncols >= 2 * NW)
+            wave_tile_body<NW, S8, true>(C, ldc, A, lda, B, ldb, nrows, 2 * NW, K, accumulate,
+                                         sync_before_store);
+        else
+            wave_tile_body<NW, S8, false>(C, ldc, A, lda, B, ldb, nrows, ncols, K, accumulate,
+                                          sync_before_store);
+        return;
+    }
+    wave_tile_narrow<S8>(C, ldc, A, lda, B, ldb, nrows, ncols, K, accumulate);
+    if (sync_before_store) __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Warshall closure of one bs x bs tile (bs <= 128) by a 256-thread workgroup,
+// the tile held in registers.  Thread (ty, tx) = (t / 16, t % 16) owns rows
+// 8ty..8ty+7 and columns 8tx..8tx+7 as 8 x 4 packed pairs.
+//
+// Step k needs row k and column k of the tile; neither changes during step k
+// (T_kk (x) x <= x because T_kk <= S, the multiplicative one), so all 64
+// updates of a thread are independent.  The owners of row k and column k
+// publish them in LDS (the column already as broadcast S - value pairs), one
+// barrier per step, with two buffers alternating so that publishing step k+1
+// cannot overwrite what a slower thread still reads for step k.  Entries
+// outside bs x bs are held as 0, the additive zero, and stay 0.
+// lds_row: 2 x 64 words, lds_col: 2 x 128 words.
+// ---------------------------------------------------------------------------
+template <bool S8>
+__device__ __forceinline__ void tile_closure(uint16_t *T, int64_t ld, int bs, uint32_t *lds_row,
+                                             uint32_t *lds_col) {
+    const int t = threadIdx.x;
+    const int tx = t & 15, ty = t >> 4;
+    u16x2 acc[8][4];
+    const int c0 = 8 * tx;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const int row = 8 * ty + i;
+        if (row < bs && c0 < bs) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(T + (int64_t)row * ld + c0);
+            uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                u16x2 p = as_pair(w4[c]);
+                if (c0 + 2 * c >= bs) p.x = 0;
+                if (c0 + 2 * c + 1 >= bs) p.y = 0;
+                acc[i][c] = p;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; c++) acc[i][c] = u16x2{0, 0};
+        }
+    }
+    __syncthreads();  // the LDS buffers may still be read from a previous use
+
+    const int nq = (bs + 7) >> 3;
+    for (int q = 0; q < nq; q++) {
+#pragma unroll
+        for (int s = 0; s < 8; s++) {
+            uint32_t *rb = lds_row + (s & 1) * 64;
+            uint32_t *cb = lds_col + (s & 1) * 128;
+            if (ty == q) {
+                uint4 v;
+                v.x = as_word(acc[s][0]);
+                v.y = as_word(acc[s][1]);
+                v.z = as_word(acc[s][2]);
+                v.w = as_word(acc[s][3]);
+                reinterpret_cast<uint4 *>(rb)[tx] = v;
+            }
+            if (tx == q) {
+                uint32_t c8[8];
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    const uint16_t v = (s & 1) ? acc[i][s >> 1].y : acc[i][s >> 1].x;
+                    c8[i] = (uint32_t)neg_one<S8>(v) * 0x10001u;
+                }
+                reinterpret_cast<uint4 *>(cb)[2 * ty] = uint4{c8[0], c8[1], c8[2], c8[3]};
+                reinterpret_cast<uint4 *>(cb)[2 * ty + 1] = uint4{c8[4], c8[5], c8[6], c8[7]};
+            }
+            __syncthreads();
+            const uint4 b4 = reinterpret_cast<const uint4 *>(rb)[tx];
+            const uint4 n0 = reinterpret_cast<const uint4 *>(cb)[2 * ty];
+            const uint4 n1 = reinterpret_cast<const uint4 *>(cb)[2 * ty + 1];
+            const u16x2 b[4] = {as_pair(b4.x), as_pair(b4.y), as_pair(b4.z), as_pair(b4.w)};
+            const uint32_t nn[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+#pragma unroll
+                for (int c = 0; c < 4; c++) acc[i][c] = step(acc[i][c], b[c], as_pair(nn[i]));
+            }
+        }
+    }
+
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const int row = 8 * ty + i;
+        if (row >= bs || c0 >= bs) continue;
+        uint16_t *dst = T + (int64_t)row * ld + c0;
+        if (c0 + 8 <= bs) {
+            uint4 v;
+            v.x = as_word(acc[i][0]);
+            v.y = as_word(acc[i][1]);
+            v.z = as_word(acc[i][2]);
+            v.w = as_word(acc[i][3]);
+            *reinterpret_cast<uint4 *>(dst) = v;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                if (c0 + 2 * c < bs) dst[2 * c] = acc[i][c].x;
+                if (c0 + 2 * c + 1 < bs) dst[2 * c + 1] = acc[i][c].y;
+            }
+        }
+    }
+}
+
+}  // namespace dev
+}  // namespace sr

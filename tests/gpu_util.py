@@ -1,0 +1,35 @@
+"""Helpers for the GPU parity tests: seeded inputs, device copies, and the
+oracle comparisons (all comparisons are bit-exact)."""
+import os
+
+import numpy as np
+
+import oracle
+import synthgen
+
+S_OF = {1: 255, 2: 65535}
+
+
+def np_dtype(kind):
+    return {1: np.uint8, 2: np.uint16}[kind]
+
+
+def rand_antidist(R, C, kind, gen, p=0.3, wmax=None, heavy=0.0):
+    """Anti-distance entries for a kind: present with probability p, distance
+    uniform in [0, wmax] (default: up to S, so some saturate)."""
+    S = S_OF[kind]
+    wmax = S if wmax is None else wmax
+    present = gen.random((R, C)) < p
+    w = gen.integers(0, wmax + 1, size=(R, C))
+    if heavy:
+        hv = gen.random((R, C)) < heavy
+        w = np.where(hv, gen.integers(S - 999 if S > 1000 else 0, S, size=(R, C)), w)
+    return np.where(present & (w < S), S - w, 0).astype(np_dtype(kind))
+
+
+def rand_bits(R, C, gen, p=0.1):
+    return (gen.random((R, C)) < p).astype(np.uint8)
+
+
+def set_oracle_threads():
+    oracle.set_threads(min(16, os.cpu_count() or 1))

@@ -1,0 +1,151 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/semiring.h declares, and rejects bad arguments on the host before
+anything is enqueued (no compute calls here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1705_08743_amd as sr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "semiring.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1705_08743_amd import build as libbuild
+    if libbuild.needs_build():
+        libbuild.build()
+    return sr.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("semiring_mul", "semiring_add", "closure", "closure_batched", "sr_last_error",
+              "sr_version", "sr_shutdown"):
+        assert n in names
+    assert set(names) == set(sr.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(L):
+    out = subprocess.run(["nm", "-D", "--defined-only", sr.LIB_PATH], stdout=subprocess.PIPE,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for n in declared_functions():
+        assert n in exported, n
+        assert getattr(L, n) is not None
+
+
+def test_version(L):
+    assert "gfx950" in sr.version()
+
+
+NULL = None
+P = 0x7F0000000000  # 16-byte aligned fake device addresses; never dereferenced
+
+
+def mul(L, kind, C, ldc, A, lda, B, ldb, R, K, N, flags=0):
+    return L.semiring_mul(kind, C, ldc, A, lda, B, ldb, R, K, N, flags, None)
+
+
+def test_mul_rejects_bad_arguments(L):
+    U16 = sr.SR_ANTIDIST_U16
+    assert mul(L, 7, P, 8, P + 4096, 8, P + 8192, 8, 4, 4, 4) == sr.SR_EINVAL
+    assert "invalid kind" in L.sr_last_error().decode()
+    assert mul(L, U16, P, 8, P + 4096, 8, P + 8192, 8, -1, 4, 4) == sr.SR_EINVAL
+    assert mul(L, U16, P, 4, P + 4096, 8, P + 8192, 8, 4, 4, 8) == sr.SR_EINVAL  # ldc < N
+    assert mul(L, U16, NULL, 8, P + 4096, 8, P + 8192, 8, 4, 4, 4) == sr.SR_EINVAL
+    assert mul(L, U16, P + 2, 8, P + 4096, 8, P + 8192, 8, 4, 4, 4) == sr.SR_EALIGN
+    assert mul(L, U16, P, 12, P + 4096, 8, P + 8192, 8, 4, 4, 4) == sr.SR_EALIGN  # 24-byte rows
+    assert mul(L, sr.SR_ANTIDIST_U8, P, 8, P + 4096, 16, P + 8192, 16, 4, 4, 4) == sr.SR_EALIGN
+    assert mul(L, sr.SR_BOOL, P, 1, P + 4096, 2, P + 8192, 2, 4, 4, 4) == sr.SR_EALIGN
+    assert mul(L, U16, P, 8, P, 8, P + 8192, 8, 4, 4, 4) == sr.SR_EALIAS
+    assert mul(L, U16, P, 8, P + 4096, 8, P + 16, 8, 4, 4, 4) == sr.SR_EALIAS  # partial overlap
+    assert mul(L, U16, P, 8, P + 4096, 8, P + 8192, 8, 4, 4, 4, 0x100) == sr.SR_EINVAL
+    assert mul(L, sr.SR_BOOL, P, 2, P + 4096, 2, P + 8192, 2, 4, 4, 4,
+               sr.SR_BOOL_MFMA) == sr.SR_EUNSUPPORTED
+
+
+def test_zero_extents_are_noops(L):
+    U16 = sr.SR_ANTIDIST_U16
+    assert mul(L, U16, NULL, 8, NULL, 8, P, 8, 0, 5, 5) == sr.SR_OK
+    assert mul(L, U16, NULL, 8, NULL, 8, NULL, 8, 0, 5, 5) == sr.SR_EINVAL  # B is 5 x 5
+    assert mul(L, U16, NULL, 8, P, 8, NULL, 8, 5, 5, 0) == sr.SR_OK
+    assert L.closure(U16, NULL, 8, 0, 0, None) == sr.SR_OK
+    assert L.semiring_add(U16, NULL, 8, NULL, 8, NULL, 8, 0, 0, None) == sr.SR_OK
+    assert L.closure_batched(U16, None, None, None, 0, 0, None) == sr.SR_OK
+
+
+def test_closure_rejects_bad_arguments(L):
+    U16 = sr.SR_ANTIDIST_U16
+    assert L.closure(U16, P, 8, -1, 0, None) == sr.SR_EINVAL
+    assert L.closure(U16, P, 4, 8, 0, None) == sr.SR_EINVAL
+    assert L.closure(U16, P + 8, 8, 8, 0, None) == sr.SR_EALIGN
+    assert L.closure(U16, P, 8, 8, sr.SR_REFLEXIVE, None) == sr.SR_EUNSUPPORTED
+    assert L.closure(sr.SR_BOOL, P, 2, 8, sr.SR_BOOL_MFMA, None) == sr.SR_EUNSUPPORTED
+    assert L.closure(U16, P, 8, 8, 0x40, None) == sr.SR_EINVAL
+    assert L.closure(sr.SR_BOOL, P, 1, 8, 0, None) == sr.SR_EALIGN
+
+
+def test_add_rejects_bad_arguments(L):
+    U16 = sr.SR_ANTIDIST_U16
+    f = L.semiring_add
+    assert f(U16, P, 8, P + 4096, 8, P + 8192, 4, 4, 8, None) == sr.SR_EINVAL
+    assert f(U16, P + 16, 8, P, 8, P + 8192, 8, 4, 8, None) == sr.SR_EALIAS  # partial overlap
+
+
+def test_batched_rejects_bad_arguments(L):
+    U16 = sr.SR_ANTIDIST_U16
+    n = 2
+    ptrs = (ctypes.c_void_p * n)(P, P + 4096)
+    lds = (ctypes.c_int64 * n)(8, 8)
+    dims = (ctypes.c_int64 * n)(8, 8)
+    f = L.closure_batched
+    assert f(sr.SR_BOOL, ptrs, lds, dims, n, 0, None) == sr.SR_EUNSUPPORTED
+    assert f(U16, ptrs, lds, dims, -1, 0, None) == sr.SR_EINVAL
+    assert f(U16, None, lds, dims, n, 0, None) == sr.SR_EINVAL
+    ptrs2 = (ctypes.c_void_p * n)(P, P + 64)  # 8 x 8 uint16 = 128 bytes: overlap
+    assert f(U16, ptrs2, lds, dims, n, 0, None) == sr.SR_EALIAS
+    dims2 = (ctypes.c_int64 * n)(8, 9)
+    assert f(U16, ptrs, lds, dims2, n, 0, None) == sr.SR_EINVAL  # ld 8 < 9
+    ptrs3 = (ctypes.c_void_p * n)(P, P + 4100)
+    assert f(U16, ptrs3, lds, dims, n, 0, None) == sr.SR_EALIGN
+    assert f(U16, ptrs, lds, dims, n, sr.SR_REFLEXIVE, None) == sr.SR_EUNSUPPORTED
+
+
+def test_error_is_thread_local(L):
+    import threading
+    assert L.closure(sr.SR_ANTIDIST_U16, P, 8, -1, 0, None) == sr.SR_EINVAL
+    msg_main = L.sr_last_error().decode()
+    seen = {}
+
+    def other():
+        seen["msg"] = L.sr_last_error().decode()
+
+    t = threading.Thread(target=other)
+    t.start()
+    t.join()
+    assert seen["msg"] == "no error" and "negative" in msg_main
+
+
+def test_python_binding_raises(L):
+    with pytest.raises(sr.SemiringError) as ei:
+        sr._check(L.closure(sr.SR_ANTIDIST_U16, P, 8, -1, 0, None))
+    assert ei.value.code == sr.SR_EINVAL
+
+
+def test_padded_ld():
+    assert sr.padded_ld(8192, sr.SR_ANTIDIST_U16) == 8192
+    assert sr.padded_ld(37, sr.SR_ANTIDIST_U16) == 64
+    assert sr.padded_ld(37, sr.SR_ANTIDIST_U8) == 128
+    assert sr.padded_ld(256, sr.SR_BOOL) == 16

@@ -1,0 +1,352 @@
+"""Bit-exact parity of the HIP library (through the C ABI) with the oracle.
+
+Sizes span several wave tiles, pivot blocks and ragged tails; every
+comparison is element by element with tolerance 0 (all arithmetic is integer).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1705_08743_amd as sr
+import synthgen
+from gpu_util import S_OF, np_dtype, rand_antidist, rand_bits, set_oracle_threads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+AD_KINDS = [sr.SR_ANTIDIST_U16, sr.SR_ANTIDIST_U8]
+MUL_SHAPES = [(1, 1, 1), (3, 5, 2), (64, 64, 64), (65, 130, 129), (200, 37, 300),
+              (257, 8, 513), (130, 300, 70), (511, 129, 1000)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    set_oracle_threads()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(kind, host, cols=None, ld=None):
+    """Device copy; ld=None pads rows to 128 bytes, else uses exactly ld."""
+    if ld is None:
+        return sr.to_device(kind, host, cols)
+    dt = {sr.SR_ANTIDIST_U8: torch.uint8, sr.SR_ANTIDIST_U16: torch.uint16,
+          sr.SR_BOOL: torch.int64}[kind]
+    buf = torch.zeros((max(host.shape[0], 1), ld), dtype=dt, device="cuda")
+    w = host.shape[1]
+    src = host.view(np.int64) if kind == sr.SR_BOOL else host
+    buf[:host.shape[0], :w].copy_(torch.from_numpy(np.ascontiguousarray(src)))
+    return buf[:host.shape[0], :w]
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return sr.to_host(t)
+
+
+# ---------------------------------------------------------------------------
+# anti-distance product
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", AD_KINDS)
+@pytest.mark.parametrize("R,K,N", MUL_SHAPES)
+def test_ad_mul(kind, R, K, N):
+    gen = synthgen.generator(1000 + R * 7 + K * 3 + N)
+    A = rand_antidist(R, K, kind, gen, p=0.4)
+    B = rand_antidist(K, N, kind, gen, p=0.4)
+    C = sr.empty(kind, R, N)
+    sr.semiring_mul(kind, C, dev(kind, A), dev(kind, B))
+    want = oracle.ad_mul(A, B, S_OF[kind])
+    assert np.array_equal(host(C).astype(np.int64), want)
+
+
+@pytest.mark.parametrize("kind", AD_KINDS)
+def test_ad_mul_accumulate_and_k0(kind):
+    gen = synthgen.generator(1001)
+    A = rand_antidist(70, 45, kind, gen)
+    B = rand_antidist(45, 90, kind, gen)
+    C0 = rand_antidist(70, 90, kind, gen, p=0.5)
+    C = dev(kind, C0)
+    sr.semiring_mul(kind, C, dev(kind, A), dev(kind, B), flags=sr.SR_ACCUMULATE)
+    want = oracle.ad_mul(A, B, S_OF[kind], C=C0)
+    assert np.array_equal(host(C).astype(np.int64), want)
+    # K = 0: the zero matrix, or C unchanged when accumulating
+    Z = dev(kind, C0)
+    sr.semiring_mul(kind, Z, dev(kind, A[:, :0]), dev(kind, B[:0]), K=0)
+    assert not host(Z).any()
+    Z2 = dev(kind, C0)
+    sr.semiring_mul(kind, Z2, dev(kind, A[:, :0]), dev(kind, B[:0]), K=0, flags=sr.SR_ACCUMULATE)
+    assert np.array_equal(host(Z2), C0)
+
+
+@pytest.mark.parametrize("kind", AD_KINDS)
+def test_ad_mul_unpadded_strides(kind):
+    """Row strides that are multiples of 16 bytes but not of the wide tile:
+    the last column chunk takes the 8-column fallback."""
+    gen = synthgen.generator(1002)
+    R, K, N = 150, 77, 200
+    per16 = 16 // np.dtype(np_dtype(kind)).itemsize
+    lda = ((K + per16 - 1) // per16) * per16
+    ldb = ((N + per16 - 1) // per16) * per16
+    A = rand_antidist(R, K, kind, gen)
+    B = rand_antidist(K, N, kind, gen)
+    C = dev(kind, np.zeros((R, N), np_dtype(kind)), ld=ldb)
+    sr.semiring_mul(kind, C, dev(kind, A, ld=lda), dev(kind, B, ld=ldb))
+    assert np.array_equal(host(C).astype(np.int64), oracle.ad_mul(A, B, S_OF[kind]))
+
+
+def test_ad_mul_padding_untouched():
+    """Columns between N and ld belong to the caller and are not written."""
+    kind = sr.SR_ANTIDIST_U16
+    gen = synthgen.generator(1003)
+    A = rand_antidist(40, 30, kind, gen)
+    B = rand_antidist(30, 50, kind, gen)
+    buf = torch.full((40, 64), 7, dtype=torch.uint16, device="cuda")
+    sr.semiring_mul(kind, buf[:, :50], dev(kind, A), dev(kind, B))
+    h = host(buf)
+    assert (h[:, 50:] == 7).all()
+    assert np.array_equal(h[:, :50].astype(np.int64), oracle.ad_mul(A, B, 65535))
+
+
+def test_ad_mul_config2():
+    """Configuration 2: two 1024 x 1024 uint16 random digraphs, p = 0.05,
+    distances in [1, 1000], 1% near 65535."""
+    A = synthgen.cfg_antidist(D=1024, which=0)
+    B = synthgen.cfg_antidist(D=1024, which=1)
+    kind = sr.SR_ANTIDIST_U16
+    C = sr.empty(kind, 1024, 1024)
+    sr.semiring_mul(kind, C, dev(kind, A[:, :1024]), dev(kind, B[:, :1024]))
+    want = oracle.ad_mul(A[:, :1024], B[:, :1024], 65535)
+    assert np.array_equal(host(C).astype(np.int64), want)
+
+
+# ---------------------------------------------------------------------------
+# anti-distance closure
+# ---------------------------------------------------------------------------
+CLO_SIZES = [1, 2, 37, 64, 127, 128, 129, 200, 255, 256, 300, 513]
+
+
+@pytest.mark.parametrize("kind", AD_KINDS)
+@pytest.mark.parametrize("D", CLO_SIZES)
+def test_ad_closure(kind, D):
+    gen = synthgen.generator(2000 + D)
+    p = min(0.5, 4.0 / max(D, 1))
+    A = rand_antidist(D, D, kind, gen, p=p, wmax=S_OF[kind] // 3)
+    T = dev(kind, A)
+    sr.closure(kind, T)
+    want = oracle.ad_closure(A, S_OF[kind])
+    assert np.array_equal(host(T).astype(np.int64), want)
+
+
+@pytest.mark.parametrize("kind", AD_KINDS)
+def test_ad_closure_unpadded_stride(kind):
+    gen = synthgen.generator(2001)
+    D = 300
+    per16 = 16 // np.dtype(np_dtype(kind)).itemsize
+    ld = ((D + per16 - 1) // per16) * per16
+    A = rand_antidist(D, D, kind, gen, p=0.02, wmax=S_OF[kind] // 4)
+    T = dev(kind, A, ld=ld)
+    sr.closure(kind, T)
+    assert np.array_equal(host(T).astype(np.int64), oracle.ad_closure(A, S_OF[kind]))
+
+
+def test_ad_closure_saturation_cycle():
+    """Directed cycle with unit distances: closed form, including saturation
+    (uint8, D = 300 > S) on the diagonal and far entries."""
+    for kind, D in ((sr.SR_ANTIDIST_U8, 300), (sr.SR_ANTIDIST_U16, 257)):
+        S = S_OF[kind]
+        A = np.zeros((D, D), np_dtype(kind))
+        A[np.arange(D), (np.arange(D) + 1) % D] = S - 1
+        T = dev(kind, A)
+        sr.closure(kind, T)
+        i = np.arange(D)[:, None]
+        j = np.arange(D)[None, :]
+        d = ((j - i - 1) % D) + 1
+        want = np.where(d >= S, 0, S - np.minimum(d, S))
+        assert np.array_equal(host(T).astype(np.int64), want)
+
+
+def test_ad_closure_config2():
+    """Configuration 2 closure: D = 1024 uint16 with heavy edges."""
+    A = synthgen.cfg_antidist(D=1024, which=0)[:, :1024]
+    kind = sr.SR_ANTIDIST_U16
+    T = dev(kind, A)
+    sr.closure(kind, T)
+    assert np.array_equal(host(T).astype(np.int64), oracle.ad_closure(A, 65535))
+
+
+def test_ad_closure_u8_config4_style():
+    """uint8 with distances in [1, 200] (saturation after two hops)."""
+    gen = synthgen.generator(2002)
+    D = 700
+    rows, cols = synthgen.bernoulli_edges(D, 0.05, gen)
+    w = gen.integers(1, 201, size=len(rows))
+    A = synthgen.encode_antidist(D, rows, cols, w, np.uint8)
+    T = dev(sr.SR_ANTIDIST_U8, A)
+    sr.closure(sr.SR_ANTIDIST_U8, T)
+    assert np.array_equal(host(T).astype(np.int64), oracle.ad_closure(A, 255))
+
+
+def test_closure_equals_repeated_squaring_on_gpu():
+    """Sec. II: closure(A) = A * (I (+) A)^(D'-1), D' >= D, the power by
+    repeated squaring -- computed here with the GPU product only, compared
+    with the GPU closure (cross-checks the two kernel families)."""
+    kind = sr.SR_ANTIDIST_U16
+    gen = synthgen.generator(2003)
+    D = 150
+    A = rand_antidist(D, D, kind, gen, p=0.02, wmax=20000)
+    P = np.maximum(A, (np.eye(D, dtype=np.uint16) * 65535))
+    dP = dev(kind, P)
+    m = 1
+    while m < D - 1:
+        dQ = sr.empty(kind, D, D)
+        sr.semiring_mul(kind, dQ, dP, dP)
+        dP = dQ
+        m *= 2
+    dR = sr.empty(kind, D, D)
+    sr.semiring_mul(kind, dR, dev(kind, A), dP)
+    T = dev(kind, A)
+    sr.closure(kind, T)
+    assert np.array_equal(host(dR), host(T))
+
+
+# ---------------------------------------------------------------------------
+# Boolean
+# ---------------------------------------------------------------------------
+BOOL_SHAPES = [(1, 1, 1), (5, 70, 3), (64, 64, 64), (100, 200, 300), (257, 33, 1000),
+               (300, 1100, 129)]
+
+
+@pytest.mark.parametrize("R,K,N", BOOL_SHAPES)
+def test_bool_mul(R, K, N):
+    gen = synthgen.generator(3000 + R + K + N)
+    A = rand_bits(R, K, gen, 0.05)
+    B = rand_bits(K, N, gen, 0.05)
+    Aw = synthgen.pack_bits(A, synthgen.aligned_ld_words(K))
+    Bw = synthgen.pack_bits(B, synthgen.aligned_ld_words(N))
+    C = sr.empty(sr.SR_BOOL, R, N)
+    sr.semiring_mul(sr.SR_BOOL, C, dev(sr.SR_BOOL, Aw, cols=K), dev(sr.SR_BOOL, Bw, cols=N),
+                    K=K, N=N)
+    got = host(C)
+    want = oracle.bool_mul_words(Aw, Bw, K, N)
+    nw = (N + 63) // 64
+    assert np.array_equal(got[:, :nw], want[:, :nw])
+    assert synthgen.padding_bits_clear(got, N)
+
+
+def test_bool_mul_accumulate():
+    gen = synthgen.generator(3001)
+    R, K, N = 90, 140, 200
+    A, B, C0 = rand_bits(R, K, gen), rand_bits(K, N, gen), rand_bits(R, N, gen)
+    ldw = synthgen.aligned_ld_words(N)
+    Aw = synthgen.pack_bits(A, synthgen.aligned_ld_words(K))
+    Bw = synthgen.pack_bits(B, ldw)
+    Cw = synthgen.pack_bits(C0, ldw)
+    C = dev(sr.SR_BOOL, Cw, cols=N)
+    sr.semiring_mul(sr.SR_BOOL, C, dev(sr.SR_BOOL, Aw, cols=K), dev(sr.SR_BOOL, Bw, cols=N),
+                    K=K, N=N, flags=sr.SR_ACCUMULATE)
+    want = oracle.bool_mul_words(Aw, Bw, K, N, C=Cw)
+    assert np.array_equal(host(C)[:, :4], want[:, :4])
+
+
+def test_bool_config1():
+    """Configuration 1: 256 x 256, p = 0.02: A * A and the closure."""
+    W = synthgen.cfg_bool256()
+    A = dev(sr.SR_BOOL, W, cols=256)
+    C = sr.empty(sr.SR_BOOL, 256, 256)
+    sr.semiring_mul(sr.SR_BOOL, C, A, A, K=256, N=256)
+    assert np.array_equal(host(C)[:, :4], oracle.bool_mul_words(W, W, 256, 256)[:, :4])
+    sr.closure(sr.SR_BOOL, A, D=256)
+    assert np.array_equal(host(A)[:, :4], oracle.bool_closure_words(W, 256)[:, :4])
+
+
+@pytest.mark.parametrize("D", [1, 5, 63, 64, 65, 200, 256, 257, 300, 600, 1100])
+def test_bool_closure(D):
+    gen = synthgen.generator(3100 + D)
+    A = rand_bits(D, D, gen, min(0.5, 1.5 / max(D, 1)))
+    ldw = synthgen.aligned_ld_words(D)
+    Aw = synthgen.pack_bits(A, ldw)
+    T = dev(sr.SR_BOOL, Aw, cols=D)
+    sr.closure(sr.SR_BOOL, T, D=D)
+    got = host(T)
+    want = oracle.bool_closure_words(Aw, D)
+    nw = (D + 63) // 64
+    assert np.array_equal(got[:, :nw], want[:, :nw])
+    assert synthgen.padding_bits_clear(got, D)
+
+
+def test_bool_closure_matches_antidist_on_01():
+    """Boolean closure = anti-distance closure of the {0, S} matrix / S."""
+    gen = synthgen.generator(3002)
+    D = 333
+    A = rand_bits(D, D, gen, 0.004)
+    T = dev(sr.SR_BOOL, synthgen.pack_bits(A, synthgen.aligned_ld_words(D)), cols=D)
+    sr.closure(sr.SR_BOOL, T, D=D)
+    U = dev(sr.SR_ANTIDIST_U16, (A.astype(np.uint16) * 65535))
+    sr.closure(sr.SR_ANTIDIST_U16, U)
+    assert np.array_equal(synthgen.unpack_bits(host(T), D).astype(np.int64) * 65535,
+                          host(U).astype(np.int64))
+
+
+# ---------------------------------------------------------------------------
+# entrywise (+)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", AD_KINDS)
+def test_add(kind):
+    gen = synthgen.generator(4000)
+    R, N = 77, 333
+    A = rand_antidist(R, N, kind, gen, p=0.6)
+    B = rand_antidist(R, N, kind, gen, p=0.6)
+    C = sr.empty(kind, R, N)
+    dA = dev(kind, A)
+    sr.semiring_add(kind, C, dA, dev(kind, B))
+    assert np.array_equal(host(C), np.maximum(A, B))
+    sr.semiring_add(kind, dA, dA, dev(kind, B))  # in place
+    assert np.array_equal(host(dA), np.maximum(A, B))
+
+
+def test_add_bool():
+    gen = synthgen.generator(4001)
+    R, N = 50, 300
+    A, B = rand_bits(R, N, gen), rand_bits(R, N, gen)
+    ldw = synthgen.aligned_ld_words(N)
+    C = sr.empty(sr.SR_BOOL, R, N)
+    sr.semiring_add(sr.SR_BOOL, C, dev(sr.SR_BOOL, synthgen.pack_bits(A, ldw), cols=N),
+                    dev(sr.SR_BOOL, synthgen.pack_bits(B, ldw), cols=N), N=N)
+    assert np.array_equal(synthgen.unpack_bits(host(C), N), np.maximum(A, B))
+
+
+# ---------------------------------------------------------------------------
+# batched closure
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", AD_KINDS)
+def test_closure_batched(kind):
+    gen = synthgen.generator(5000 + kind)
+    sizes = [1, 5, 32, 33, 64, 100, 128, 129, 200, 257, 300, 45, 600]
+    mats = []
+    for n in sizes:
+        rows, cols = synthgen.bernoulli_edges(n, float(gen.uniform(0.01, 0.2)), gen)
+        w = gen.integers(1, 201, size=len(rows))
+        mats.append(synthgen.encode_antidist(n, rows, cols, w, np_dtype(kind)))
+    devs = [dev(kind, m) for m in mats]
+    sr.closure_batched(kind, devs)
+    torch.cuda.synchronize()
+    for m, d in zip(mats, devs):
+        assert np.array_equal(host(d).astype(np.int64), oracle.ad_closure(m, S_OF[kind])), m.shape
+
+
+def test_closure_batched_matches_solo():
+    """Each graph closed in a batch equals the same graph closed alone."""
+    kind = sr.SR_ANTIDIST_U16
+    batch = synthgen.cfg_batch(count=40, nlo=32, nhi=400, seed=77)
+    mats = [synthgen.encode_antidist(n, r, c, w, np.uint16) for n, r, c, w in batch]
+    a = [dev(kind, m) for m in mats]
+    b = [dev(kind, m) for m in mats]
+    sr.closure_batched(kind, a)
+    for t in b:
+        sr.closure(kind, t)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert np.array_equal(host(x), host(y))
