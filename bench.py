@@ -1,0 +1,387 @@
+#!/usr/bin/env python3
+"""Benchmark of the semiring closure hot path on one MI355X.
+
+Default workload (the headline): anti-distance Floyd-Warshall closure of a
+D = 8192 uint16 random digraph (edge probability 0.05, distances uniform in
+[1, 1000], 1% of edges with distances in [64536, 65534]).  One step = one full
+closure (all three phases of every round) of a fresh copy of the input that is
+already resident in HBM.  Metric: semiring updates per second, D^3 / t.
+
+Other workloads (--workload): bool16384 (Boolean closure, D = 16384, mean
+out-degree 3 plus planted strongly connected blocks), mul1024 (uint16 product
+of two 1024 x 1024 graphs), u8fw8192 (uint8 closure, distances in [1, 200]),
+batched (4096 graphs, log-uniform sizes in [32, 1024], uint16, one launch vs one
+at a time).
+
+Prints one JSON line.  The roofline object is for the dominant kernel (the
+update phase), timed live with hipEvents on its own stream; cpu_baseline is
+the oracle's Warshall loop on a bounded sample of the same input.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 VALU lanes x 2.4 GHz = 3.93e13 32-bit lane operations
+# per second; one packed saturating-subtract + one packed max cover two
+# anti-distance updates, i.e. one lane operation per update.  A v_bitop3_b32
+# covers 32 Boolean updates.  HBM peak 8 TB/s.
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+PEAK_ANTIDIST = VALU_LANE_OPS
+PEAK_BOOL = 32 * VALU_LANE_OPS
+
+# HBM traffic of the update kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# scaled by the same counters on a streaming kernel of known size; valid only
+# for the kernel sources whose hash is recorded with it.
+TRAFFIC = {
+    "fw8192": {"src_hash": None, "bytes_per_launch": None},
+}
+KERNEL_SOURCES = ["paper_1705_08743_amd/csrc/sr_tiles.h",
+                  "paper_1705_08743_amd/csrc/sr_antidist.hip"]
+
+
+def src_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sync_all(torch):
+    if torch.distributed.is_available() and torch.distributed.is_initialized():
+        torch.distributed.barrier()
+    torch.cuda.synchronize()
+
+
+def cpu_baseline_fw(A, S, target_s, threads):
+    """The oracle's Warshall loop on the first m pivots of the same input
+    (bounded sample); returns updates/s and the sample description."""
+    import numpy as np
+    import oracle
+    oracle.set_threads(threads)
+    D = A.shape[0]
+    A32 = np.ascontiguousarray(A[:, :D], dtype=np.int32)
+    m0 = 4
+    t0 = time.perf_counter()
+    oracle.ad_closure(A32, S, k_end=m0)
+    dt = time.perf_counter() - t0
+    m = int(max(m0, min(D, target_s / max(dt / m0, 1e-9))))
+    t0 = time.perf_counter()
+    oracle.ad_closure(A32, S, k_end=m)
+    dt = time.perf_counter() - t0
+    upd = float(m) * D * D
+    return upd / dt, ("first %d of %d Warshall pivots on the same D=%d input (%.3g updates, %.1f s)"
+                      % (m, D, D, upd, dt)), threads
+
+
+def parity_rows(result_host, A, S, nrows, seed):
+    """Sampled rows of the GPU result against the oracle's path definition."""
+    import numpy as np
+    import oracle
+    D = A.shape[0]
+    rows = np.sort(np.random.default_rng(seed).choice(D, size=nrows, replace=False))
+    want = oracle.ad_closure_rows(A[:, :D], S, rows)
+    ok = bool(np.array_equal(result_host[rows, :D].astype(np.int64), want.astype(np.int64)))
+    return {"rows_checked": int(nrows), "bit_exact": ok}
+
+
+def kernel_timing_pass(args, torch, sr, kind, src, bufs, close):
+    """Per-phase launch durations (hipEvents on the launching stream) over
+    `steps` closures run with serialized phases; returns ms, launches, avg
+    and the algorithmic updates per launch for each phase."""
+    for b in bufs:
+        b.copy_(src)
+    sync_all(torch)
+    for ph in (sr.SR_PHASE_PIVOT, sr.SR_PHASE_PANELS, sr.SR_PHASE_UPDATE):
+        sr.sr_profile_read(kind, ph)  # forget anything recorded earlier
+    sr.sr_profile_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        close(bufs[i])
+    sync_all(torch)
+    t1 = time.perf_counter()
+    sr.sr_profile_enable(False)
+    phases = {"serial_ms_per_step": (t1 - t0) * 1e3 / args.steps}
+    for ph, name in ((sr.SR_PHASE_PIVOT, "pivot"), (sr.SR_PHASE_PANELS, "panels"),
+                     (sr.SR_PHASE_UPDATE, "update")):
+        ms, n, u = sr.sr_profile_read(kind, ph)
+        phases[name] = {"ms_per_step": ms / args.steps, "launches": n,
+                        "avg_us": 1e3 * ms / max(n, 1), "updates_per_launch": u / max(n, 1)}
+    return phases
+
+
+def run_fw(args, torch, sr, kind, D, make_input, workload, S, metric):
+    import numpy as np
+    log("generating input D=%d ..." % D)
+    A = make_input()
+    host = np.ascontiguousarray(A[:, :D])
+    src = sr.to_device(kind, host)
+    bufs = [torch.empty_like(src) for _ in range(max(1, args.steps))]
+    warm = torch.empty_like(src)
+    for _ in range(args.warmup):
+        warm.copy_(src)
+        sr.closure(kind, warm)
+    for b in bufs:
+        b.copy_(src)
+    # timed region: the closures as a user runs them (phases overlapped)
+    sync_all(torch)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        sr.closure(kind, bufs[i])
+    sync_all(torch)
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    # kernel-timing pass: the same closures again with the phases serialized
+    # on one stream, each launch bracketed by hipEvents on that stream, so
+    # that a launch's duration is its own
+    phases = kernel_timing_pass(args, torch, sr, kind, src, bufs, lambda t: sr.closure(
+        kind, t, flags=sr.SR_SERIAL_PHASES))
+    up = phases["update"]
+    achieved = up["updates_per_launch"] / (up["avg_us"] * 1e-6) if up["avg_us"] > 0 else 0.0
+    tr = TRAFFIC.get(workload, {})
+    traffic = tr.get("bytes_per_launch") if tr.get("src_hash") == src_hash() else None
+    out = {
+        "metric": metric,
+        "value": float(D) ** 3 / (ms_step * 1e-3),
+        "unit": "updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {sr.SR_ANTIDIST_U16: "u16", sr.SR_ANTIDIST_U8: "u8"}[kind],
+        "data": "synthetic",
+        "roofline": {"bound": "alu", "kernel": "k_ad_fw_update (update phase)",
+                     "achieved": achieved, "peak": PEAK_ANTIDIST, "unit": "updates/s",
+                     "frac": achieved / PEAK_ANTIDIST, "traffic": traffic},
+        "phases": phases,
+        "fraction_of_valu_roofline_whole_step": float(D) ** 3 / (ms_step * 1e-3) / PEAK_ANTIDIST,
+    }
+    if not args.no_parity:
+        out["parity"] = parity_rows(sr.to_host(bufs[-1]), host, S, args.parity_rows, 7)
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host ...")
+        v, sample, cores = cpu_baseline_fw(host, S, args.cpu_seconds, args.cpu_threads)
+        out["cpu_baseline"] = {"value": v, "unit": "updates/s", "cores": cores, "kind": "oracle",
+                               "sample": sample}
+    return out
+
+
+def timed(torch, fn, steps):
+    sync_all(torch)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        fn(i)
+    sync_all(torch)
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def run_bool(args, torch, sr, synthgen):
+    """Boolean closure, D = 16384, bit-packed (32 MiB)."""
+    import numpy as np
+    import oracle
+    D = 16384
+    log("generating Boolean input D=%d ..." % D)
+    W = synthgen.cfg_bool16384(D=D)
+    src = sr.to_device(sr.SR_BOOL, W, cols=D)
+    bufs = [torch.empty_like(src) for _ in range(max(1, args.steps))]
+    warm = torch.empty_like(src)
+    for _ in range(args.warmup):
+        warm.copy_(src)
+        sr.closure(sr.SR_BOOL, warm, D=D)
+    for b in bufs:
+        b.copy_(src)
+    ms = timed(torch, lambda i: sr.closure(sr.SR_BOOL, bufs[i], D=D), args.steps)
+    phases = kernel_timing_pass(args, torch, sr, sr.SR_BOOL, src, bufs, lambda t: sr.closure(
+        sr.SR_BOOL, t, D=D, flags=sr.SR_SERIAL_PHASES))
+    up = phases["update"]
+    achieved = up["updates_per_launch"] / (up["avg_us"] * 1e-6) if up["avg_us"] > 0 else 0.0
+    out = {"metric": "semiring updates/s (D³/t) Boolean Warshall closure D=16384",
+           "value": float(D) ** 3 / (ms * 1e-3), "unit": "updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bits",
+           "data": "synthetic",
+           "config": {"workload": "bool_warshall_D16384", "D": D, "mean_out_degree": 3,
+                      "planted_scc_blocks": "8 x 512", "pivot_block": 256,
+                      "parallelism": "single_gpu"},
+           "roofline": {"bound": "alu", "kernel": "k_bool_fw_update (update phase)",
+                        "achieved": achieved, "peak": PEAK_BOOL, "unit": "updates/s",
+                        "frac": achieved / PEAK_BOOL, "traffic": None},
+           "phases": phases}
+    if not args.no_parity:
+        rows = np.sort(np.random.default_rng(3).choice(D, size=args.parity_rows, replace=False))
+        got = sr.to_host(bufs[-1])[rows, : D // 64]
+        want = oracle.bool_closure_rows_words(W, D, rows)
+        out["parity"] = {"rows_checked": len(rows), "bit_exact": bool(np.array_equal(got, want))}
+    return out
+
+
+def run_mul(args, torch, sr, synthgen):
+    """uint16 product of two 1024 x 1024 graphs (configuration 2)."""
+    import numpy as np
+    import oracle
+    D = 1024
+    A = synthgen.cfg_antidist(D=D, which=0)[:, :D]
+    B = synthgen.cfg_antidist(D=D, which=1)[:, :D]
+    dA = sr.to_device(sr.SR_ANTIDIST_U16, A)
+    dB = sr.to_device(sr.SR_ANTIDIST_U16, B)
+    dC = sr.empty(sr.SR_ANTIDIST_U16, D, D)
+    f = lambda i: sr.semiring_mul(sr.SR_ANTIDIST_U16, dC, dA, dB)
+    for _ in range(args.warmup):
+        f(0)
+    steps = max(args.steps, 50)
+    ms = timed(torch, f, steps)
+    out = {"metric": "semiring updates/s (R*K*N/t) anti-distance product 1024^3 uint16",
+           "value": float(D) ** 3 / (ms * 1e-3), "unit": "updates/s", "n_gpus": 1,
+           "steps": steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u16", "data": "synthetic",
+           "config": {"workload": "antidist_u16_product_1024", "R": D, "K": D, "N": D,
+                      "parallelism": "single_gpu"},
+           "fraction_of_valu_roofline": float(D) ** 3 / (ms * 1e-3) / PEAK_ANTIDIST}
+    if not args.no_parity:
+        out["parity"] = {"full_matrix": True, "bit_exact": bool(np.array_equal(
+            sr.to_host(dC).astype(np.int64), oracle.ad_mul(A, B, 65535)))}
+    return out
+
+
+def run_add(args, torch, sr, synthgen):
+    """Entrywise (+) of two 8192 x 8192 uint16 matrices (reads 256 MiB,
+    writes 128 MiB): the HBM-bound step, and the streaming kernel of known
+    size that calibrates the FETCH_SIZE / WRITE_SIZE counters."""
+    D = 8192
+    kind = sr.SR_ANTIDIST_U16
+    A = sr.to_device(kind, synthgen.cfg_antidist(D=D, which=0))
+    B = sr.to_device(kind, synthgen.cfg_antidist(D=D, which=1))
+    C = sr.empty(kind, D, D)
+    f = lambda i: sr.semiring_add(kind, C, A, B)
+    for _ in range(args.warmup):
+        f(0)
+    steps = max(args.steps, 20)
+    ms = timed(torch, f, steps)
+    nbytes = 3 * D * D * 2
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"metric": "HBM GB/s of semiring_add (entrywise max) 8192x8192 uint16",
+            "value": gbs, "unit": "GB/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u16", "data": "synthetic",
+            "config": {"workload": "antidist_u16_add_8192", "bytes_per_call": nbytes,
+                       "parallelism": "single_gpu"},
+            "roofline": {"bound": "hbm", "kernel": "k_add<2>", "achieved": gbs, "peak": 8000.0,
+                         "unit": "GB/s", "frac": gbs / 8000.0, "traffic": None}}
+
+
+def run_batched(args, torch, sr, synthgen):
+    """4096 graphs, log-uniform sizes in [32, 1024], uint16: one batched launch
+    against one closure() call per graph on the same stream."""
+    import numpy as np
+    import oracle
+    log("generating 4096 graphs ...")
+    batch = synthgen.cfg_batch()
+    mats = [synthgen.encode_antidist(n, r, c, w, np.uint16) for n, r, c, w in batch]
+    kind = sr.SR_ANTIDIST_U16
+    srcs = [sr.to_device(kind, m) for m in mats]
+    work = [sr.empty(kind, t.shape[0], t.shape[1], zero=False) for t in srcs]
+    upd = float(sum(float(m.shape[0]) ** 3 for m in mats))
+
+    def reset():
+        for w_, s_ in zip(work, srcs):
+            w_.copy_(s_)
+
+    for _ in range(max(1, args.warmup)):
+        reset()
+        sr.closure_batched(kind, work)
+    times_b, times_s = [], []
+    for _ in range(max(1, args.steps // 2)):
+        reset()
+        times_b.append(timed(torch, lambda i: sr.closure_batched(kind, work), 1))
+        reset()
+        times_s.append(timed(torch, lambda i: [sr.closure(kind, t) for t in work], 1))
+    tb, ts = min(times_b), min(times_s)
+    out = {"metric": "semiring updates/s (sum n³/t) batched closure, 4096 graphs",
+           "value": upd / (tb * 1e-3), "unit": "updates/s", "n_gpus": 1,
+           "steps": len(times_b), "warmup": args.warmup, "ms_per_step": tb,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16",
+           "data": "synthetic",
+           "config": {"workload": "batched_antidist_u16_4096", "graphs": len(mats),
+                      "n": "log-uniform [32,1024]", "edge_p": "U[0.01,0.2]",
+                      "distances": "U[1,200]", "parallelism": "single_gpu"},
+           "serial_ms": ts, "speedup_vs_serial": ts / tb, "total_updates": upd,
+           "fraction_of_valu_roofline": upd / (tb * 1e-3) / PEAK_ANTIDIST}
+    if not args.no_parity:
+        reset()
+        sr.closure_batched(kind, work)
+        torch.cuda.synchronize()
+        idx = [0, 1, len(mats) // 2, len(mats) - 1]
+        ok = all(np.array_equal(sr.to_host(work[i]).astype(np.int64),
+                                oracle.ad_closure(mats[i], 65535)) for i in idx)
+        out["parity"] = {"graphs_checked": len(idx), "bit_exact": bool(ok)}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="fw8192",
+                    choices=["fw8192", "u8fw8192", "bool16384", "mul1024", "batched", "add8192"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--parity-rows", type=int, default=4)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding design notes); got --gpus %d" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    import paper_1705_08743_amd as sr
+    import synthgen
+    sr.lib()  # fails loudly when the library is not built
+
+    metric = "semiring updates/s (D³/t) anti-distance FW D=8192; served p50/p99 vs serial"
+    if args.workload == "fw8192":
+        out = run_fw(args, torch, sr, sr.SR_ANTIDIST_U16, 8192,
+                     lambda: synthgen.cfg_antidist(D=8192), "fw8192", 65535, metric)
+        out["config"] = {"workload": "antidist_u16_floyd_warshall_D8192", "D": 8192,
+                         "entries": "uint16, S=65535", "edge_p": 0.05,
+                         "distances": "U[1,1000]; 1% U[64536,65534]",
+                         "seed": synthgen.config_seed(2), "pivot_block": 128,
+                         "parallelism": "single_gpu"}
+    elif args.workload == "u8fw8192":
+        out = run_fw(args, torch, sr, sr.SR_ANTIDIST_U8, 8192,
+                     lambda: synthgen.cfg_antidist_u8(D=8192), "u8fw8192", 255,
+                     "semiring updates/s (D³/t) anti-distance FW D=8192 uint8")
+        out["config"] = {"workload": "antidist_u8_floyd_warshall_D8192", "D": 8192,
+                         "entries": "uint8, S=255", "edge_p": 0.05, "distances": "U[1,200]",
+                         "pivot_block": 128, "parallelism": "single_gpu"}
+    elif args.workload == "bool16384":
+        out = run_bool(args, torch, sr, synthgen)
+    elif args.workload == "mul1024":
+        out = run_mul(args, torch, sr, synthgen)
+    elif args.workload == "add8192":
+        out = run_add(args, torch, sr, synthgen)
+    else:
+        out = run_batched(args, torch, sr, synthgen)
+    out["library"] = sr.version()
+    out["device"] = torch.cuda.get_device_name(0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -81,7 +81,9 @@ enum {
     SR_ACCUMULATE = 1u,    /* semiring_mul: C := C (+) A*B instead of C := A*B */
     SR_REFLEXIVE = 2u,     /* closure: return I (+) T (eq. rtc); not implemented -> SR_EUNSUPPORTED */
     SR_BOOL_BITWISE = 4u,  /* Boolean: force the word OR-AND kernels (the default) */
-    SR_BOOL_MFMA = 8u      /* Boolean: request the int8 matrix-core path; not implemented -> SR_EUNSUPPORTED */
+    SR_BOOL_MFMA = 8u,     /* Boolean: request the int8 matrix-core path; not implemented -> SR_EUNSUPPORTED */
+    SR_SERIAL_PHASES = 16u /* closure: enqueue every phase on the caller's stream in order, without
+                              overlapping the next round's pivot and panels on a second stream */
 };
 
 /*
@@ -117,8 +119,13 @@ int semiring_add(int kind, void *C, int64_t ldc, const void *A, int64_t lda,
  * result is the transitive, non-reflexive closure: entry (i, j) is the best
  * product over paths of at least one edge, so the diagonal holds "i lies on a
  * cycle" (Boolean) or S minus the shortest cycle through i, saturated
- * (anti-distance).  flags: 0 or SR_BOOL_BITWISE; SR_REFLEXIVE and
- * SR_BOOL_MFMA return SR_EUNSUPPORTED.  D = 0 is a no-op.
+ * (anti-distance).  flags: SR_BOOL_BITWISE, SR_SERIAL_PHASES; SR_REFLEXIVE
+ * and SR_BOOL_MFMA return SR_EUNSUPPORTED.  D = 0 is a no-op.
+ * By default a closure with more than two pivot blocks forks onto a second,
+ * library-owned stream of default priority (the next round's pivot and panels
+ * overlap the bulk of the current update) and joins back into `stream`
+ * before the call's work completes; the fork/join is event-based, so the
+ * sequence can be captured into a HIP graph from `stream`.
  */
 int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream);
 
@@ -127,13 +134,31 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
  * applied to each (T[g], ldt[g], D[g]).  The three arrays are HOST arrays of
  * length count; T[g] are device pointers, each obeying the alignment rules
  * above.  Anti-distance kinds only (Boolean returns SR_EUNSUPPORTED).  The
- * matrices must not overlap each other.  The whole batch is one device-side
- * work queue: graphs are claimed by workgroups largest-first; graphs of up
- * to 256 vertices are closed entirely in LDS, larger ones through global
- * memory by one workgroup each.
+ * matrices must not overlap each other (SR_EALIAS), D[g] <= 65536.  One
+ * launch closes the whole batch, one workgroup per graph, handed out
+ * largest-first: a graph of up to 128 vertices is one tile closed in
+ * registers and LDS; a larger one runs the blocked Floyd-Warshall of
+ * closure() inside its workgroup.  The descriptor upload is stream-ordered;
+ * uint8 batches use stream-ordered uint16 working copies.
  */
 int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t *D,
                     int64_t count, unsigned flags, void *stream);
+
+/*
+ * Phase timing (a tracing aid, not part of the paper's method).  While
+ * enabled, closure() brackets each launch of its three phases -- the pivot
+ * tile, the panels, the update of the remaining tiles -- with a pair of
+ * hipEvents recorded on the caller's stream, and notes the launch's
+ * algorithmic work in semiring updates (bs^3, 2(D-bs)bs^2 and (D-bs)^2 bs for
+ * a pivot block of bs vertices).  sr_profile_read() waits for the recorded
+ * events of one (kind, phase), returns the summed elapsed milliseconds, the
+ * number of launches and the summed updates, and forgets those records.
+ * kind: SR_BOOL or an anti-distance kind (both anti-distance kinds share one
+ * record set).  Recording adds a few microseconds per launch.
+ */
+enum { SR_PHASE_PIVOT = 0, SR_PHASE_PANELS = 1, SR_PHASE_UPDATE = 2 };
+int sr_profile_enable(int enable);
+int sr_profile_read(int kind, int phase, double *total_ms, int64_t *launches, double *updates);
 
 /* Thread-local message describing the last non-SR_OK return on this thread. */
 const char *sr_last_error(void);

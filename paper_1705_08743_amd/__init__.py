@@ -36,6 +36,7 @@ SR_ACCUMULATE = 1
 SR_REFLEXIVE = 2
 SR_BOOL_BITWISE = 4
 SR_BOOL_MFMA = 8
+SR_SERIAL_PHASES = 16
 
 ERROR_NAMES = {
     SR_EINVAL: "SR_EINVAL", SR_EALIAS: "SR_EALIAS", SR_EALIGN: "SR_EALIGN",
@@ -45,7 +46,11 @@ ERROR_NAMES = {
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsemiring.so")
 
 EXPORTS = ("semiring_mul", "semiring_add", "closure", "closure_batched",
-           "sr_last_error", "sr_version", "sr_shutdown")
+           "sr_profile_enable", "sr_profile_read", "sr_last_error", "sr_version", "sr_shutdown")
+
+SR_PHASE_PIVOT = 0
+SR_PHASE_PANELS = 1
+SR_PHASE_UPDATE = 2
 
 
 class SemiringError(RuntimeError):
@@ -80,6 +85,11 @@ def lib():
         L.sr_last_error.restype = ctypes.c_char_p
         L.sr_version.restype = ctypes.c_char_p
         L.sr_shutdown.restype = None
+        L.sr_profile_enable.argtypes = [i32]
+        L.sr_profile_enable.restype = i32
+        L.sr_profile_read.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
+        L.sr_profile_read.restype = i32
         _lib = L
     return _lib
 
@@ -181,6 +191,20 @@ def version():
     return lib().sr_version().decode()
 
 
+def sr_profile_enable(enable=True):
+    """Start (or stop) recording hipEvents around each closure phase launch."""
+    _check(lib().sr_profile_enable(1 if enable else 0))
+
+
+def sr_profile_read(kind, phase):
+    """(total_ms, launches, updates) of the recorded launches of one phase."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    u = ctypes.c_double()
+    _check(lib().sr_profile_read(kind, phase, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(u)))
+    return ms.value, n.value, u.value
+
+
 def shutdown():
     lib().sr_shutdown()
 
@@ -243,7 +267,9 @@ def to_host(t):
 __all__ = [
     "SR_BOOL", "SR_ANTIDIST_U8", "SR_ANTIDIST_U16", "SR_OK", "SR_EINVAL", "SR_EALIAS",
     "SR_EALIGN", "SR_ENOMEM", "SR_EDEVICE", "SR_EUNSUPPORTED", "SR_ACCUMULATE",
-    "SR_REFLEXIVE", "SR_BOOL_BITWISE", "SR_BOOL_MFMA", "SemiringError", "lib", "kind_of",
+    "SR_REFLEXIVE", "SR_BOOL_BITWISE", "SR_BOOL_MFMA", "SR_SERIAL_PHASES", "SemiringError", "lib", "kind_of",
     "semiring_mul", "semiring_add", "closure", "closure_batched", "version", "shutdown",
+    "sr_profile_enable", "sr_profile_read", "SR_PHASE_PIVOT", "SR_PHASE_PANELS",
+    "SR_PHASE_UPDATE",
     "padded_ld", "empty", "to_device", "to_host", "EXPORTS", "LIB_PATH",
 ]

@@ -18,6 +18,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <algorithm>
 
 #include "sr_internal.h"
@@ -28,23 +31,35 @@ namespace {
 
 using dev::tile_closure;
 using dev::wave_tile;
+using dev::wave_tile_body;
 
 constexpr int kPanelNW = 16;  // 32 columns per wave in the panel phase
 
 // ---------------------------------------------------------------------------
-template <int NW, bool S8>
+// Product: each wave owns 64*TM rows x 2NW columns; the four waves of a
+// workgroup are stacked along the rows and share the column chunk, so they
+// read the same B segments through the scalar cache.
+// FULL: every column chunk of the grid has all 2NW columns (the launcher
+// sends a partial last chunk to a separate FULL = false launch), so the hot
+// kernel carries no edge code.  col_base: first column of chunk 0.
+template <int TM, int NW, bool S8, bool FULL>
 __global__ void __launch_bounds__(256)
 k_ad_mul(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
-         int64_t ldb, int64_t R, int K, int64_t N, int accumulate) {
-    constexpr int CW = 2 * NW;
+         int64_t ldb, int64_t R, int K, int64_t N, int64_t col_base, int accumulate) {
+    constexpr int CW = 2 * NW, RW = 64 * TM;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
-    const int64_t row0 = ((int64_t)blockIdx.y * 4 + wave) * 64;
-    const int64_t col0 = (int64_t)blockIdx.x * CW;
+    const int64_t row0 = ((int64_t)blockIdx.y * 4 + wave) * RW;
+    const int64_t col0 = col_base + (int64_t)blockIdx.x * CW;
     if (row0 >= R) return;
-    const int nrows = (int)min<int64_t>(64, R - row0);
-    const int ncols = (int)min<int64_t>(CW, N - col0);
-    wave_tile<NW, S8>(C + row0 * ldc + col0, ldc, A + row0 * lda, lda, B + col0, ldb, nrows,
-                      ncols, ldb - col0, K, accumulate != 0, false);
+    const int nrows = (int)min<int64_t>(RW, R - row0);
+    if (FULL) {
+        wave_tile_body<TM, NW, S8, true>(C + row0 * ldc + col0, ldc, A + row0 * lda, lda,
+                                         B + col0, ldb, nrows, CW, K, accumulate != 0, false);
+    } else {
+        const int ncols = (int)min<int64_t>(CW, N - col0);
+        wave_tile<TM, NW, S8>(C + row0 * ldc + col0, ldc, A + row0 * lda, lda, B + col0, ldb,
+                              nrows, ncols, ldb - col0, K, accumulate != 0, false);
+    }
 }
 
 template <bool S8>
@@ -74,8 +89,9 @@ k_ad_fw_panels(uint16_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg) {
         const int nrows = min(64, bs - rofs);
         const int ncols = (int)min<int64_t>(CW, (int64_t)D - col0);
         const int64_t r0 = (int64_t)k0 + rofs;
-        wave_tile<NW, S8>(T + r0 * ld + col0, ld, T + r0 * ld + k0, ld, T + (int64_t)k0 * ld + col0,
-                          ld, nrows, ncols, ld - col0, bs, true, true);
+        wave_tile<1, NW, S8>(T + r0 * ld + col0, ld, T + r0 * ld + k0, ld,
+                             T + (int64_t)k0 * ld + col0, ld, nrows, ncols, ld - col0, bs, true,
+                             true);
     } else {
         const int kr0 = k0 / 64, kr1 = (k0 + bs + 63) / 64;
         const int rc = (int)blockIdx.x - n_rowwg;
@@ -84,31 +100,45 @@ k_ad_fw_panels(uint16_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg) {
         const int nrows = (int)min<int64_t>(64, (int64_t)D - row0);
         const int cofs = wave * CW;
         const int ncols = min(CW, bs - cofs);
-        wave_tile<NW, S8>(T + row0 * ld + k0 + cofs, ld, T + row0 * ld + k0, ld,
-                          T + (int64_t)k0 * ld + k0 + cofs, ld, nrows, ncols, ld - k0 - cofs, bs,
-                          true, true);
+        wave_tile<1, NW, S8>(T + row0 * ld + k0 + cofs, ld, T + row0 * ld + k0, ld,
+                             T + (int64_t)k0 * ld + k0 + cofs, ld, nrows, ncols,
+                             ld - k0 - cofs, bs, true, true);
     }
 }
 
-// Phase 3.  Each wave owns a 64-row x 2NW-column tile outside the pivot rows
-// and columns; the four waves of a workgroup share the column chunk, so they
-// read the same pivot-row segments through the scalar cache.
-template <int NW, bool S8>
-__global__ void __launch_bounds__(256) k_ad_fw_update(uint16_t *T, int64_t ld, int D, int k0, int bs) {
-    constexpr int CW = 2 * NW;
+// Phase 3 over a rectangle of tiles: row chunks (64*TM rows) [r_lo, r_hi)
+// minus [r_ex0, r_ex1), column chunks (2NW columns) [c_lo, c_hi) minus
+// [c_ex0, c_ex1); T_ij (+)= T_iK * T_Kj for pivot block K = [k0, k0 + bs).
+// The grid has one column per selected column chunk and ceil(rows / 4) rows
+// of workgroups; the four waves of a workgroup share the column chunk.
+struct Rect {
+    int r_lo, r_hi, r_ex0, r_ex1, c_lo, c_hi, c_ex0, c_ex1;
+};
+
+// FULL: every selected column chunk has all 2NW columns inside D (the
+// launcher sends a partial last chunk to a FULL = false launch).
+template <int TM, int NW, bool S8, bool FULL>
+__global__ void __launch_bounds__(256)
+k_ad_fw_update(uint16_t *T, int64_t ld, int D, int k0, int bs, Rect q) {
+    constexpr int CW = 2 * NW, RW = 64 * TM;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
-    const int kc0 = k0 / CW, kc1 = (k0 + bs + CW - 1) / CW;
-    const int cc = (int)blockIdx.x;
-    const int c = cc < kc0 ? cc : cc + (kc1 - kc0);
-    const int kr0 = k0 / 64, kr1 = (k0 + bs + 63) / 64;
-    const int rc = (int)blockIdx.y * 4 + wave;
-    const int rchunk = rc < kr0 ? rc : rc + (kr1 - kr0);
-    const int64_t row0 = (int64_t)rchunk * 64, col0 = (int64_t)c * CW;
-    if (row0 >= D) return;
-    const int nrows = (int)min<int64_t>(64, (int64_t)D - row0);
-    const int ncols = (int)min<int64_t>(CW, (int64_t)D - col0);
-    wave_tile<NW, S8>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld, T + (int64_t)k0 * ld + col0,
-                      ld, nrows, ncols, ld - col0, bs, true, false);
+    int c = q.c_lo + (int)blockIdx.x;
+    if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
+    int rc = q.r_lo + (int)blockIdx.y * 4 + wave;
+    if (rc >= q.r_ex0) rc += q.r_ex1 - q.r_ex0;
+    if (rc >= q.r_hi || c >= q.c_hi) return;
+    const int64_t row0 = (int64_t)rc * RW, col0 = (int64_t)c * CW;
+    const int nrows = (int)min<int64_t>(RW, (int64_t)D - row0);
+    if (FULL) {
+        wave_tile_body<TM, NW, S8, true>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld,
+                                         T + (int64_t)k0 * ld + col0, ld, nrows, CW, bs, true,
+                                         false);
+    } else {
+        const int ncols = (int)min<int64_t>(CW, (int64_t)D - col0);
+        wave_tile<TM, NW, S8>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld,
+                              T + (int64_t)k0 * ld + col0, ld, nrows, ncols, ld - col0, bs, true,
+                              false);
+    }
 }
 
 // uint8 <-> uint16, 8 entries per thread; rows padded with zeros up to the
@@ -162,109 +192,289 @@ k_narrow(uint8_t *dst, int64_t ldd, const uint16_t *src, int64_t lds, int64_t R,
     }
 }
 
-// Column width of the wave tiles: wider tiles amortise the per-step work that
-// is not a packed update; narrower ones give more waves for small products.
-int pick_nw(int64_t R, int64_t N) {
-    int nw = 32;
-    while (nw > 8) {
-        const int64_t waves = ((R + 63) / 64) * ((N + 2 * nw - 1) / (2 * nw));
-        if (waves >= 4096) break;
-        nw >>= 1;
+// Tile shape of the product: rows per lane and column pairs per wave.  Wider
+// tiles amortise the per-step work that is not a packed update and reuse each
+// scalar-loaded B word for more updates; narrower ones give more waves for
+// small products.
+struct Shape {
+    int tm, nw;
+};
+
+Shape pick_mul_shape(int64_t R, int64_t N) {
+    const Shape cand[] = {{2, 32}, {1, 32}, {1, 16}, {1, 8}};
+    for (const Shape &s : cand) {
+        const int64_t waves = ((R + 64 * s.tm - 1) / (64 * s.tm)) * ((N + 2 * s.nw - 1) / (2 * s.nw));
+        if (waves >= 8192) return s;
     }
-    return nw;
+    return Shape{1, 8};
 }
 
-template <int NW, bool S8>
-hipError_t mul_nw(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
-                  int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, hipStream_t st) {
-    const dim3 grid((unsigned)((N + 2 * NW - 1) / (2 * NW)), (unsigned)((R + 255) / 256));
-    hipLaunchKernelGGL((k_ad_mul<NW, S8>), grid, dim3(256), 0, st, C, ldc, A, lda, B, ldb, R,
-                       (int)K, N, acc ? 1 : 0);
-    return hipGetLastError();
+template <int TM, int NW, bool S8>
+hipError_t mul_shape(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
+                     int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, hipStream_t st) {
+    constexpr int CW = 2 * NW;
+    const unsigned gy = (unsigned)((R + 256 * TM - 1) / (256 * TM));
+    const int64_t nfull = N / CW;
+    if (nfull > 0) {
+        hipLaunchKernelGGL((k_ad_mul<TM, NW, S8, true>), dim3((unsigned)nfull, gy), dim3(256), 0,
+                           st, C, ldc, A, lda, B, ldb, R, (int)K, N, (int64_t)0, acc ? 1 : 0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (N % CW) {
+        // the partial last chunk, as 16-column tiles of one row per lane
+        const int64_t c0 = nfull * CW;
+        const unsigned gx = (unsigned)((N - c0 + 15) / 16);
+        hipLaunchKernelGGL((k_ad_mul<1, 8, S8, false>), dim3(gx, (unsigned)((R + 255) / 256)),
+                           dim3(256), 0, st, C, ldc, A, lda, B, ldb, R, (int)K, N, c0,
+                           acc ? 1 : 0);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 template <bool S8>
 hipError_t mul_s(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
                  int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, hipStream_t st) {
-    switch (pick_nw(R, N)) {
-        case 32: return mul_nw<32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
-        case 16: return mul_nw<16, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
-        default: return mul_nw<8, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
+    const Shape s = pick_mul_shape(R, N);
+    if (s.tm == 2) return mul_shape<2, 32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
+    switch (s.nw) {
+        case 32: return mul_shape<1, 32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
+        case 16: return mul_shape<1, 16, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
+        default: return mul_shape<1, 8, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
     }
 }
 
-struct Round {
-    int k0, bs;
-    int n_rowwg, n_colwg;        // phase 2 grid
-    int upd_x, upd_y;            // phase 3 grid
+// ---------------------------------------------------------------------------
+// Closure driver.
+//
+// Per round kb: pivot(kb), panels(kb), then the update of every tile outside
+// row block kb and column block kb.  With lookahead the update is split:
+//   A(kb): the tiles of row block kb+1 and column block kb+1 (outside block
+//          kb), i.e. next round's pivot and panels;
+//   B(kb): the rest (outside blocks kb and kb+1).
+// pivot(kb+1) and panels(kb+1) need only A(kb), so they run on the caller's
+// stream while B(kb) runs on a second stream; they touch disjoint tiles (and
+// B(kb) reads no tile that panels(kb+1) writes).  A(kb+1) waits for B(kb).
+// The critical path per round is A + pivot + panels; the bulk of the work
+// (B) overlaps it.
+// ---------------------------------------------------------------------------
+struct Plan {
+    int64_t D;
+    int tm, nw;
+    int rw, cw;      // rows / columns of a row / column chunk
+    int nrc, ncc;    // number of row / column chunks
 };
 
-Round plan_round(int64_t D, int64_t kb, int nw) {
-    Round r;
-    r.k0 = (int)(kb * kAdBlock);
-    r.bs = (int)std::min<int64_t>(kAdBlock, D - r.k0);
+// Update-tile shapes compiled in (rows per lane, column pairs per wave); a
+// row chunk (64 * rows per lane) must not exceed the pivot block.
+bool tile_supported(int tm, int nw) {
+    return (tm == 1 || tm == 2) && (nw == 8 || nw == 16 || nw == 32);
+}
+
+// Tuning overrides, read once: SR_AD_TILE="tm,nw" forces the update tile
+// shape (2,32 | 1,32 | 1,16 | 1,8); SR_LOOKAHEAD=0 disables the second stream.
+struct Overrides {
+    int tm = 0, nw = 0;
+    bool lookahead = true;
+    Overrides() {
+        if (const char *t = getenv("SR_AD_TILE")) {
+            int a = 0, b = 0;
+            if (sscanf(t, "%d,%d", &a, &b) == 2 && tile_supported(a, b)) {
+                tm = a;
+                nw = b;
+            }
+        }
+        if (const char *l = getenv("SR_LOOKAHEAD")) lookahead = atoi(l) != 0;
+    }
+};
+
+const Overrides &overrides() {
+    static const Overrides o;
+    return o;
+}
+
+Plan make_plan(int64_t D) {
+    Plan p;
+    p.D = D;
+    if (D >= 2048) {
+        p.tm = 1;
+        p.nw = 16;
+    } else if (D >= 512) {
+        p.tm = 1;
+        p.nw = 16;
+    } else {
+        p.tm = 1;
+        p.nw = 8;
+    }
+    if (overrides().tm) {
+        p.tm = overrides().tm;
+        p.nw = overrides().nw;
+    }
+    p.rw = 64 * p.tm;
+    p.cw = 2 * p.nw;
+    p.nrc = (int)((D + p.rw - 1) / p.rw);
+    p.ncc = (int)((D + p.cw - 1) / p.cw);
+    return p;
+}
+
+int blocks_of(int64_t D) { return (int)((D + kAdBlock - 1) / kAdBlock); }
+int block_k0(int64_t kb) { return (int)(kb * kAdBlock); }
+int block_bs(int64_t D, int64_t kb) { return (int)std::min<int64_t>(kAdBlock, D - kb * kAdBlock); }
+
+// chunks [lo, hi) covering block kb at chunk width w
+void block_chunks(int64_t D, int64_t kb, int w, int *lo, int *hi) {
+    const int k0 = block_k0(kb), bs = block_bs(D, kb);
+    *lo = k0 / w;
+    *hi = (k0 + bs + w - 1) / w;
+}
+
+template <int TM, int NW, bool S8, bool FULL>
+hipError_t update_launch(uint16_t *T, int64_t ld, int64_t D, int k0, int bs, const Rect &q,
+                         hipStream_t st) {
+    const int nr = (q.r_hi - q.r_lo) - (q.r_ex1 - q.r_ex0);
+    const int nc = (q.c_hi - q.c_lo) - (q.c_ex1 - q.c_ex0);
+    if (nr <= 0 || nc <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_ad_fw_update<TM, NW, S8, FULL>), dim3(nc, (nr + 3) / 4), dim3(256), 0,
+                       st, T, ld, (int)D, k0, bs, q);
+    return hipGetLastError();
+}
+
+// The rectangle's full column chunks go to the hot kernel; a partial last
+// chunk of the matrix (D not a multiple of 2NW), if selected, goes to the
+// edge kernel as 16-column tiles of 64 rows.
+template <int TM, int NW, bool S8>
+hipError_t update_rect_t(uint16_t *T, int64_t ld, int64_t D, int k0, int bs, Rect q,
+                         hipStream_t st) {
+    constexpr int CW = 2 * NW;
+    const int last = (int)((D + CW - 1) / CW) - 1;
+    const bool has_partial = (D % CW) != 0 && q.c_lo <= last && last < q.c_hi &&
+                             !(q.c_ex0 <= last && last < q.c_ex1);
+    if (has_partial) {
+        // the last chunk is the final one of the range: drop it from the hot launch
+        q.c_hi = last;
+        q.c_ex0 = std::min(q.c_ex0, q.c_hi);
+        q.c_ex1 = std::min(q.c_ex1, q.c_hi);
+    }
+    hipError_t e = update_launch<TM, NW, S8, true>(T, ld, D, k0, bs, q, st);
+    if (e != hipSuccess || !has_partial) return e;
+    Rect edge;
+    const int r64 = (int)((D + 63) / 64);
+    edge.r_lo = std::min(q.r_lo * TM, r64);
+    edge.r_hi = std::min(q.r_hi * TM, r64);
+    edge.r_ex0 = std::min(q.r_ex0 * TM, edge.r_hi);
+    edge.r_ex1 = std::min(q.r_ex1 * TM, edge.r_hi);
+    edge.c_lo = last * CW / 16;
+    edge.c_hi = (int)((D + 15) / 16);
+    edge.c_ex0 = edge.c_ex1 = edge.c_hi;
+    return update_launch<1, 8, S8, false>(T, ld, D, k0, bs, edge, st);
+}
+
+template <bool S8>
+hipError_t update_rect(const Plan &p, uint16_t *T, int64_t ld, int64_t kb, Rect q,
+                       hipStream_t st, double units) {
+    // an empty exclusion is placed at the end of the range
+    if (q.r_ex1 <= q.r_ex0) q.r_ex0 = q.r_ex1 = q.r_hi;
+    if (q.c_ex1 <= q.c_ex0) q.c_ex0 = q.c_ex1 = q.c_hi;
+    const int k0 = block_k0(kb), bs = block_bs(p.D, kb);
+    const bool prof = prof_on();
+    if (prof) prof_begin(st);
+    hipError_t e;
+    switch (p.tm * 100 + p.nw) {
+        case 232: e = update_rect_t<2, 32, S8>(T, ld, p.D, k0, bs, q, st); break;
+        case 216: e = update_rect_t<2, 16, S8>(T, ld, p.D, k0, bs, q, st); break;
+        case 208: e = update_rect_t<2, 8, S8>(T, ld, p.D, k0, bs, q, st); break;
+        case 132: e = update_rect_t<1, 32, S8>(T, ld, p.D, k0, bs, q, st); break;
+        case 116: e = update_rect_t<1, 16, S8>(T, ld, p.D, k0, bs, q, st); break;
+        default: e = update_rect_t<1, 8, S8>(T, ld, p.D, k0, bs, q, st); break;
+    }
+    if (prof) prof_end(st, 1, 2, units);
+    return e;
+}
+
+template <bool S8>
+hipError_t pivot_s(uint16_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t st) {
+    const int k0 = block_k0(kb), bs = block_bs(D, kb);
+    const bool prof = prof_on();
+    if (prof) prof_begin(st);
+    hipLaunchKernelGGL((k_ad_fw_pivot<S8>), dim3(1), dim3(256), 0, st, T, ld, (int64_t)k0, bs);
+    hipError_t e = hipGetLastError();
+    if (prof) prof_end(st, 1, 0, (double)bs * bs * bs);
+    return e;
+}
+
+template <bool S8>
+hipError_t panels_s(uint16_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t st) {
+    const int k0 = block_k0(kb), bs = block_bs(D, kb);
     const int pcw = 2 * kPanelNW;
     const int64_t nchunk_p = (D + pcw - 1) / pcw;
-    const int kpc = (r.k0 + r.bs + pcw - 1) / pcw - r.k0 / pcw;
-    r.n_rowwg = (int)((nchunk_p - kpc + 1) / 2);
+    const int kpc = (k0 + bs + pcw - 1) / pcw - k0 / pcw;
+    const int n_rowwg = (int)((nchunk_p - kpc + 1) / 2);
     const int64_t nrch = (D + 63) / 64;
-    const int kr = (r.k0 + r.bs + 63) / 64 - r.k0 / 64;
-    r.n_colwg = (int)(nrch - kr);
-    const int cw = 2 * nw;
-    const int64_t nchunk_u = (D + cw - 1) / cw;
-    const int kuc = (r.k0 + r.bs + cw - 1) / cw - r.k0 / cw;
-    r.upd_x = (int)(nchunk_u - kuc);
-    r.upd_y = (int)((nrch - kr + 3) / 4);
-    return r;
-}
-
-int closure_nw(int64_t D) { return D >= 2048 ? 32 : (D >= 512 ? 16 : 8); }
-
-template <bool S8>
-hipError_t pivot_s(uint16_t *T, int64_t ld, const Round &r, hipStream_t st) {
-    hipLaunchKernelGGL((k_ad_fw_pivot<S8>), dim3(1), dim3(256), 0, st, T, ld, (int64_t)r.k0, r.bs);
-    return hipGetLastError();
-}
-
-template <bool S8>
-hipError_t panels_s(uint16_t *T, int64_t ld, int64_t D, const Round &r, hipStream_t st) {
-    const int n = r.n_rowwg + r.n_colwg;
+    const int kr = (k0 + bs + 63) / 64 - k0 / 64;
+    const int n = n_rowwg + (int)(nrch - kr);
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_ad_fw_panels<S8>), dim3(n), dim3(256), 0, st, T, ld, (int)D, r.k0, r.bs,
-                       r.n_rowwg);
-    return hipGetLastError();
-}
-
-template <int NW, bool S8>
-hipError_t update_nw(uint16_t *T, int64_t ld, int64_t D, const Round &r, hipStream_t st) {
-    if (r.upd_x <= 0 || r.upd_y <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_ad_fw_update<NW, S8>), dim3(r.upd_x, r.upd_y), dim3(256), 0, st, T, ld,
-                       (int)D, r.k0, r.bs);
-    return hipGetLastError();
+    const bool prof = prof_on();
+    if (prof) prof_begin(st);
+    hipLaunchKernelGGL((k_ad_fw_panels<S8>), dim3(n), dim3(256), 0, st, T, ld, (int)D, k0, bs,
+                       n_rowwg);
+    hipError_t e = hipGetLastError();
+    if (prof) prof_end(st, 1, 1, 2.0 * (double)(D - bs) * bs * bs);
+    return e;
 }
 
 template <bool S8>
-hipError_t update_s(uint16_t *T, int64_t ld, int64_t D, int nw, const Round &r, hipStream_t st) {
-    switch (nw) {
-        case 32: return update_nw<32, S8>(T, ld, D, r, st);
-        case 16: return update_nw<16, S8>(T, ld, D, r, st);
-        default: return update_nw<8, S8>(T, ld, D, r, st);
-    }
-}
+hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_t st) {
+    const Plan p = make_plan(D);
+    const int nb = blocks_of(D);
+    hipError_t e = pivot_s<S8>(T, ld, D, 0, st);
+    if (e != hipSuccess || nb == 1) return e;
+    if ((e = panels_s<S8>(T, ld, D, 0, st)) != hipSuccess) return e;
 
-template <bool S8>
-hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, hipStream_t st) {
-    const int nw = closure_nw(D);
-    const int64_t nb = (D + kAdBlock - 1) / kAdBlock;
-    for (int64_t kb = 0; kb < nb; kb++) {
-        const Round r = plan_round(D, kb, nw);
-        hipError_t e = pivot_s<S8>(T, ld, r, st);
-        if (e != hipSuccess) return e;
-        if (nb == 1) break;
-        if ((e = panels_s<S8>(T, ld, D, r, st)) != hipSuccess) return e;
-        if ((e = update_s<S8>(T, ld, D, nw, r, st)) != hipSuccess) return e;
+    Aux *aux = (nb > 2 && !serial && overrides().lookahead) ? aux_acquire() : nullptr;
+    for (int kb = 0; kb < nb; kb++) {
+        int rl, rh, cl, ch;
+        block_chunks(D, kb, p.rw, &rl, &rh);
+        block_chunks(D, kb, p.cw, &cl, &ch);
+        const double bs = block_bs(D, kb);
+        if (kb + 1 == nb || !aux) {
+            // whole update of round kb, then the next pivot and panels
+            const double rest = (double)D - bs;
+            e = update_rect<S8>(p, T, ld, kb, Rect{0, p.nrc, rl, rh, 0, p.ncc, cl, ch}, st,
+                                rest * rest * bs);
+            if (e == hipSuccess && kb + 1 < nb) e = pivot_s<S8>(T, ld, D, kb + 1, st);
+            if (e == hipSuccess && kb + 1 < nb) e = panels_s<S8>(T, ld, D, kb + 1, st);
+            if (e != hipSuccess) break;
+            continue;
+        }
+        int rl1, rh1, cl1, ch1;
+        block_chunks(D, kb + 1, p.rw, &rl1, &rh1);
+        block_chunks(D, kb + 1, p.cw, &cl1, &ch1);
+        const double bs1 = block_bs(D, kb + 1);
+        const double rest2 = (double)D - bs - bs1;
+        // B(kb) on the second stream, after panels(kb) (recorded on st)
+        e = hipEventRecord(aux->ev_main, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(aux->stream, aux->ev_main, 0);
+        if (e == hipSuccess)
+            e = update_rect<S8>(p, T, ld, kb, Rect{0, p.nrc, rl, rh1, 0, p.ncc, cl, ch1},
+                                aux->stream, rest2 * rest2 * bs);
+        if (e == hipSuccess) e = hipEventRecord(aux->ev_aux, aux->stream);
+        // A(kb) on st: row block kb+1 (columns outside block kb), then column
+        // block kb+1 (rows outside blocks kb, kb+1)
+        if (e == hipSuccess)
+            e = update_rect<S8>(p, T, ld, kb, Rect{rl1, rh1, rh1, rh1, 0, p.ncc, cl, ch}, st,
+                                bs1 * ((double)D - bs) * bs);
+        if (e == hipSuccess)
+            e = update_rect<S8>(p, T, ld, kb, Rect{0, p.nrc, rl, rh1, cl1, ch1, ch1, ch1}, st,
+                                rest2 * bs1 * bs);
+        if (e == hipSuccess) e = pivot_s<S8>(T, ld, D, kb + 1, st);
+        if (e == hipSuccess) e = panels_s<S8>(T, ld, D, kb + 1, st);
+        // round kb+1's updates need B(kb)
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, aux->ev_aux, 0);
+        if (e != hipSuccess) break;
     }
-    return hipSuccess;
+    if (aux) aux_release(aux);
+    return e;
 }
 
 }  // namespace
@@ -276,27 +486,32 @@ hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, i
               : mul_s<false>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, stream);
 }
 
-hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, hipStream_t stream) {
-    return s8 ? closure_s<true>(T, ld, D, stream) : closure_s<false>(T, ld, D, stream);
+hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, bool serial,
+                             hipStream_t stream) {
+    return s8 ? closure_s<true>(T, ld, D, serial, stream)
+              : closure_s<false>(T, ld, D, serial, stream);
 }
 
 hipError_t launch_ad_fw_pivot(bool s8, uint16_t *T, int64_t ld, int64_t D, int64_t kb,
                               hipStream_t stream) {
-    const Round r = plan_round(D, kb, closure_nw(D));
-    return s8 ? pivot_s<true>(T, ld, r, stream) : pivot_s<false>(T, ld, r, stream);
+    return s8 ? pivot_s<true>(T, ld, D, kb, stream) : pivot_s<false>(T, ld, D, kb, stream);
 }
 
 hipError_t launch_ad_fw_panels(bool s8, uint16_t *T, int64_t ld, int64_t D, int64_t kb,
                                hipStream_t stream) {
-    const Round r = plan_round(D, kb, closure_nw(D));
-    return s8 ? panels_s<true>(T, ld, D, r, stream) : panels_s<false>(T, ld, D, r, stream);
+    return s8 ? panels_s<true>(T, ld, D, kb, stream) : panels_s<false>(T, ld, D, kb, stream);
 }
 
 hipError_t launch_ad_fw_update(bool s8, uint16_t *T, int64_t ld, int64_t D, int64_t kb,
                                hipStream_t stream) {
-    const int nw = closure_nw(D);
-    const Round r = plan_round(D, kb, nw);
-    return s8 ? update_s<true>(T, ld, D, nw, r, stream) : update_s<false>(T, ld, D, nw, r, stream);
+    const Plan p = make_plan(D);
+    int rl, rh, cl, ch;
+    block_chunks(D, kb, p.rw, &rl, &rh);
+    block_chunks(D, kb, p.cw, &cl, &ch);
+    const Rect q{0, p.nrc, rl, rh, 0, p.ncc, cl, ch};
+    const double bs = block_bs(D, kb), rest = (double)D - bs;
+    return s8 ? update_rect<true>(p, T, ld, kb, q, stream, rest * rest * bs)
+              : update_rect<false>(p, T, ld, kb, q, stream, rest * rest * bs);
 }
 
 hipError_t launch_widen_u8(uint16_t *dst, int64_t ldd, const uint8_t *src, int64_t lds, int64_t R,

@@ -120,6 +120,18 @@ const char *sr_last_error(void) { return g_err.c_str(); }
 
 const char *sr_version(void) { return "libsemiring 0.1 (gfx950)"; }
 
+int sr_profile_enable(int enable) { return sr::prof_enable(enable); }
+
+int sr_profile_read(int kind, int phase, double *total_ms, int64_t *launches, double *updates) {
+    if (kind != SR_BOOL && kind != SR_ANTIDIST_U8 && kind != SR_ANTIDIST_U16)
+        return fail(SR_EINVAL, "sr_profile_read: invalid kind %d", kind);
+    if (phase < SR_PHASE_PIVOT || phase > SR_PHASE_UPDATE)
+        return fail(SR_EINVAL, "sr_profile_read: invalid phase %d", phase);
+    if (sr::prof_read(kind == SR_BOOL ? 0 : 1, phase, total_ms, launches, updates) != 0)
+        return fail(SR_EDEVICE, "sr_profile_read: event query failed");
+    return SR_OK;
+}
+
 void sr_shutdown(void) {
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess) return;
@@ -210,8 +222,9 @@ int semiring_add(int kind, void *C, int64_t ldc, const void *A, int64_t lda, con
 
 int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream) {
     if (!valid_kind(kind)) return fail(SR_EINVAL, "closure: invalid kind %d", kind);
-    if (flags & ~(unsigned)(SR_REFLEXIVE | SR_BOOL_BITWISE | SR_BOOL_MFMA))
+    if (flags & ~(unsigned)(SR_REFLEXIVE | SR_BOOL_BITWISE | SR_BOOL_MFMA | SR_SERIAL_PHASES))
         return fail(SR_EINVAL, "closure: unknown flags 0x%x", flags);
+    const bool serial = (flags & SR_SERIAL_PHASES) != 0;
     if (flags & SR_REFLEXIVE)
         return fail(SR_EUNSUPPORTED, "closure: the reflexive closure I (+) T is not built");
     if (flags & SR_BOOL_MFMA)
@@ -224,9 +237,9 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
     hipStream_t st = as_stream(stream);
     hipError_t e = hipSuccess;
     if (kind == SR_BOOL) {
-        e = sr::launch_bool_closure(static_cast<uint64_t *>(T), ldt, D, st);
+        e = sr::launch_bool_closure(static_cast<uint64_t *>(T), ldt, D, serial, st);
     } else if (kind == SR_ANTIDIST_U16) {
-        e = sr::launch_ad_closure(false, static_cast<uint16_t *>(T), ldt, D, st);
+        e = sr::launch_ad_closure(false, static_cast<uint16_t *>(T), ldt, D, serial, st);
     } else {
         const int64_t lw = round_up(D, 64);
         void *w = nullptr;
@@ -234,7 +247,7 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
         uint16_t *Tw = static_cast<uint16_t *>(w);
         uint8_t *T8 = static_cast<uint8_t *>(T);
         e = sr::launch_widen_u8(Tw, lw, T8, ldt, D, D, st);
-        if (e == hipSuccess) e = sr::launch_ad_closure(true, Tw, lw, D, st);
+        if (e == hipSuccess) e = sr::launch_ad_closure(true, Tw, lw, D, serial, st);
         if (e == hipSuccess) e = sr::launch_narrow_u8(T8, ldt, Tw, lw, D, D, st);
         work_free(w, st);
     }

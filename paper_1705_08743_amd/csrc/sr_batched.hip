@@ -57,7 +57,7 @@ __device__ void blocked_closure_wg(uint16_t *T, int64_t ld, int D, uint32_t *lds
                 const int h = it & 1, cc = it >> 1;
                 const int c = cc < kc0 ? cc : cc + kc;
                 const int64_t col0 = (int64_t)c * kBCW, r0 = (int64_t)k0 + 64 * h;
-                wave_tile<kBNW, S8>(T + r0 * ld + col0, ld, T + r0 * ld + k0, ld,
+                wave_tile<1, kBNW, S8>(T + r0 * ld + col0, ld, T + r0 * ld + k0, ld,
                                     T + (int64_t)k0 * ld + col0, ld, min(64, bs - 64 * h),
                                     (int)min<int64_t>(kBCW, D - col0), ld - col0, bs, true, false);
             } else {
@@ -65,7 +65,7 @@ __device__ void blocked_closure_wg(uint16_t *T, int64_t ld, int D, uint32_t *lds
                 const int rr = j >> 2, q = j & 3;
                 const int rch = rr < kr0 ? rr : rr + kr;
                 const int64_t row0 = (int64_t)rch * 64;
-                wave_tile<kBNW, S8>(T + row0 * ld + k0 + q * kBCW, ld, T + row0 * ld + k0, ld,
+                wave_tile<1, kBNW, S8>(T + row0 * ld + k0 + q * kBCW, ld, T + row0 * ld + k0, ld,
                                     T + (int64_t)k0 * ld + k0 + q * kBCW, ld,
                                     (int)min<int64_t>(64, D - row0), min(kBCW, bs - q * kBCW),
                                     ld - k0 - q * kBCW, bs, true, false);
@@ -79,7 +79,7 @@ __device__ void blocked_closure_wg(uint16_t *T, int64_t ld, int D, uint32_t *lds
             const int rch = rr < kr0 ? rr : rr + kr;
             const int c = cc < kc0 ? cc : cc + kc;
             const int64_t row0 = (int64_t)rch * 64, col0 = (int64_t)c * kBCW;
-            wave_tile<kBNW, S8>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld,
+            wave_tile<1, kBNW, S8>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld,
                                 T + (int64_t)k0 * ld + col0, ld, (int)min<int64_t>(64, D - row0),
                                 (int)min<int64_t>(kBCW, D - col0), ld - col0, bs, true, false);
         }

@@ -295,7 +295,9 @@ hipError_t launch_bool_mul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t 
     }
 }
 
-hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, hipStream_t st) {
+hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool serial,
+                               hipStream_t st) {
+    (void)serial;
     uint32_t *T = reinterpret_cast<uint32_t *>(T64);
     const int64_t ld = 2 * ld64;
     const int64_t nb = (D + kBoolBlock - 1) / kBoolBlock;
@@ -306,22 +308,31 @@ hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, hipStream
         const int k0 = (int)(kb * kBoolBlock);
         const int bs = (int)std::min<int64_t>(kBoolBlock, D - k0);
         const int nwv = (int)std::min<int64_t>(8, nwd - k0 / 32);
+        const bool prof = prof_on();
+        const double dbs = bs, rest = (double)(D - bs);
+        if (prof) prof_begin(st);
         hipLaunchKernelGGL(k_bool_fw_pivot, dim3(1), dim3(256), 0, st, T, ld, (int64_t)k0, bs, nwv);
         hipError_t e = hipGetLastError();
+        if (prof) prof_end(st, 0, 0, dbs * dbs * dbs);
         if (e != hipSuccess) return e;
         if (nb == 1) break;
         const int64_t nchunks = (nwd + 7) / 8;
         const int n_rowwg = (int)(nchunks - 1);
         const int kr = (k0 + bs + 63) / 64 - k0 / 64;
         const int n_colwg = (int)((nrch - kr + 3) / 4);
+        if (prof) prof_begin(st);
         hipLaunchKernelGGL(k_bool_fw_panels, dim3(n_rowwg + n_colwg), dim3(256), 0, st, T, ld,
                            (int)D, k0, bs, n_rowwg);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        e = hipGetLastError();
+        if (prof) prof_end(st, 0, 1, 2.0 * rest * dbs * dbs);
+        if (e != hipSuccess) return e;
+        if (prof) prof_begin(st);
         switch (nwb) {
             case 32: e = update_nwb<32>(T, ld, D, k0, bs, st); break;
             case 16: e = update_nwb<16>(T, ld, D, k0, bs, st); break;
             default: e = update_nwb<8>(T, ld, D, k0, bs, st); break;
         }
+        if (prof) prof_end(st, 0, 2, rest * rest * dbs);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -24,8 +24,10 @@ hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, i
                          const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                          bool accumulate, hipStream_t stream);
 
-// In-place closure of the D x D matrix T (uint16 storage).
-hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, hipStream_t stream);
+// In-place closure of the D x D matrix T (uint16 storage).  serial: no
+// second stream (every phase in order on `stream`).
+hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, bool serial,
+                             hipStream_t stream);
 
 // Individual phases of one blocked Floyd-Warshall round (for tests/timing).
 hipError_t launch_ad_fw_pivot(bool s8, uint16_t *T, int64_t ld, int64_t D, int64_t kb,
@@ -45,7 +47,8 @@ hipError_t launch_narrow_u8(uint8_t *dst, int64_t ldd, const uint16_t *src, int6
 hipError_t launch_bool_mul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda,
                            const uint64_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                            bool accumulate, hipStream_t stream);
-hipError_t launch_bool_closure(uint64_t *T, int64_t ld, int64_t D, hipStream_t stream);
+hipError_t launch_bool_closure(uint64_t *T, int64_t ld, int64_t D, bool serial,
+                               hipStream_t stream);
 
 // Entrywise (+): elem_bytes 1 or 2 -> max, 8 -> OR of words.  Widths in
 // elements (words for Boolean).
@@ -64,5 +67,26 @@ struct BatchDesc {
 };
 hipError_t launch_ad_closure_batched(bool s8, const BatchDesc *desc, int64_t count,
                                      int32_t max_d, hipStream_t stream);
+
+// Second stream of a closure (sr_runtime.cpp), per device, created on first
+// use at default priority.  aux_acquire() returns it locked (the caller
+// enqueues its whole fork/join sequence, then calls aux_release) or nullptr
+// when it cannot be created.
+struct Aux {
+    hipStream_t stream;
+    hipEvent_t ev_main;  // recorded on the caller's stream, waited on by `stream`
+    hipEvent_t ev_aux;   // recorded on `stream`, waited on by the caller's stream
+    int device;
+};
+Aux *aux_acquire();
+void aux_release(Aux *a);
+
+// Phase timing (sr_runtime.cpp).  kind: 0 Boolean, 1 anti-distance;
+// phase: 0 pivot, 1 panels, 2 update.  units: semiring updates of the launch.
+bool prof_on();
+void prof_begin(hipStream_t st);
+void prof_end(hipStream_t st, int kind, int phase, double units);
+int prof_enable(int on);
+int prof_read(int kind, int phase, double *ms, int64_t *launches, double *units);
 
 }  // namespace sr

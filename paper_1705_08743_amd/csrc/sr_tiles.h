@@ -68,86 +68,47 @@ template <> struct AWord<8> {
 };
 
 // ---------------------------------------------------------------------------
-// One wavefront computes C (+)= A * B for a tile of up to 64 rows (one row per
-// lane) and up to 2*NW columns (NW packed pairs per lane), over K inner steps.
+// One wavefront computes C (+)= A * B for a tile of up to 64*TM rows (TM rows
+// per lane: lane, lane + 64, ...) and up to 2*NW columns (NW packed pairs per
+// row), over K inner steps.
 //
 // The row of B used at inner step k is the same for all 64 lanes, so its
 // words are read with scalar loads and enter each packed instruction as the
-// SGPR operand; each lane reads only its own row of A (2*KU bytes per KU
-// steps) and forms S - a with one XOR per two steps.  The inner loop is
-// therefore one v_pk_sub_u16 and one v_pk_max_u16 per two updates per lane.
+// SGPR operand; each of those words serves TM packed updates.  Each lane reads
+// only its own rows of A (2*KU bytes per row per KU steps) and forms S - a
+// with one XOR per two steps.  The inner loop is therefore one v_pk_sub_u16
+// and one v_pk_max_u16 per two updates per lane.
 //
 // B is always read as whole 2*NW-column segments: the caller guarantees they
 // lie inside the (padded) rows.  Columns >= ncols of a segment feed only
 // accumulators that are not stored.  FULLC: ncols == 2*NW (whole-vector C
-// access); otherwise C is read and written entry-exactly.  Lanes >= nrows
-// compute on row 0 and store nothing.  nrows, ncols >= 1.  A, B and C rows
+// access); otherwise C is read and written entry-exactly.  Rows >= nrows are
+// computed on a valid row and not stored.  nrows, ncols >= 1.  A, B and C rows
 // are 16-byte aligned (row strides multiples of 8 entries).
 // ---------------------------------------------------------------------------
-template <int NW, bool S8, bool FULLC>
-__device__ __forceinline__ void tile_compute(u16x2 (&acc)[NW], const uint16_t *crow,
-                                             const uint16_t *arow, const uint16_t *B, int64_t ldb,
-                                             int ncols, int K, bool accumulate) {
-    static_assert(NW % 4 == 0, "NW must be a multiple of 4");
-    if (accumulate) {
-        if (FULLC) {
+template <int NW, bool FULLC>
+__device__ __forceinline__ void row_load(u16x2 (&acc)[NW], const uint16_t *crow, int ncols) {
+    if (FULLC) {
 #pragma unroll
-            for (int q = 0; q < NW / 4; q++) {
-                const uint4 v = reinterpret_cast<const uint4 *>(crow)[q];
-                acc[4 * q + 0] = as_pair(v.x);
-                acc[4 * q + 1] = as_pair(v.y);
-                acc[4 * q + 2] = as_pair(v.z);
-                acc[4 * q + 3] = as_pair(v.w);
-            }
-        } else {
-#pragma unroll
-            for (int w = 0; w < NW; w++) {
-                const uint16_t lo = (2 * w < ncols) ? crow[2 * w] : (uint16_t)0;
-                const uint16_t hi = (2 * w + 1 < ncols) ? crow[2 * w + 1] : (uint16_t)0;
-                acc[w] = u16x2{lo, hi};
-            }
+        for (int q = 0; q < NW / 4; q++) {
+            const uint4 v = reinterpret_cast<const uint4 *>(crow)[q];
+            acc[4 * q + 0] = as_pair(v.x);
+            acc[4 * q + 1] = as_pair(v.y);
+            acc[4 * q + 2] = as_pair(v.z);
+            acc[4 * q + 3] = as_pair(v.w);
         }
     } else {
 #pragma unroll
-        for (int w = 0; w < NW; w++) acc[w] = u16x2{0, 0};
-    }
-
-    // KU inner steps per iteration: their KU rows of B occupy KU * NW = 64
-    // SGPRs (at most), which leaves room for addressing without spilling; the
-    // lane's KU entries of A come in one load issued an iteration ahead.
-    constexpr int KU = NW >= 32 ? 2 : (NW >= 16 ? 4 : 8);
-    typedef typename AWord<KU>::type AW;
-    int k = 0;
-    if (K >= KU) {
-        AW anext = *reinterpret_cast<const AW *>(arow);
-        for (; k + KU <= K; k += KU) {
-            const AW acur = anext;
-            if (k + 2 * KU <= K) anext = *reinterpret_cast<const AW *>(arow + k + KU);
-            uint32_t na[KU / 2];
-            AWord<KU>::template negate<S8>(acur, na);
-            const uint16_t *b0 = B + (int64_t)k * ldb;
-#pragma unroll
-            for (int kk = 0; kk < KU; kk++) {
-                const kconst uint32_t *brow = (const kconst uint32_t *)(b0 + kk * ldb);
-                const uint32_t n2 = na[kk >> 1];
-                const uint16_t n = (kk & 1) ? (uint16_t)(n2 >> 16) : (uint16_t)n2;
-                const u16x2 nv = u16x2{n, n};
-#pragma unroll
-                for (int w = 0; w < NW; w++) acc[w] = step(acc[w], as_pair(brow[w]), nv);
-            }
+        for (int w = 0; w < NW; w++) {
+            const uint16_t lo = (2 * w < ncols) ? crow[2 * w] : (uint16_t)0;
+            const uint16_t hi = (2 * w + 1 < ncols) ? crow[2 * w + 1] : (uint16_t)0;
+            acc[w] = u16x2{lo, hi};
         }
-    }
-    for (; k < K; k++) {
-        const uint16_t n = neg_one<S8>(arow[k]);
-        const u16x2 nv = u16x2{n, n};
-        const kconst uint32_t *brow = (const kconst uint32_t *)(B + (int64_t)k * ldb);
-#pragma unroll
-        for (int w = 0; w < NW; w++) acc[w] = step(acc[w], as_pair(brow[w]), nv);
     }
 }
 
 template <int NW, bool FULLC>
-__device__ __forceinline__ void tile_store(const u16x2 (&acc)[NW], uint16_t *crow, int ncols) {
+__device__ __forceinline__ void row_store(const u16x2 (&acc)[NW], uint16_t *crow, int ncols) {
     if (FULLC) {
 #pragma unroll
         for (int q = 0; q < NW / 4; q++) {
@@ -170,36 +131,127 @@ __device__ __forceinline__ void tile_store(const u16x2 (&acc)[NW], uint16_t *cro
     }
 }
 
-template <int NW, bool S8, bool FULLC>
+template <int TM, int NW, bool S8, bool FULLC>
 __device__ __forceinline__ void wave_tile_body(uint16_t *C, int64_t ldc, const uint16_t *A,
                                                int64_t lda, const uint16_t *B, int64_t ldb,
                                                int nrows, int ncols, int K, bool accumulate,
                                                bool sync_before_store) {
+    static_assert(NW % 4 == 0, "NW must be a multiple of 4");
     const int lane = threadIdx.x & 63;
-    const bool live = lane < nrows;
-    const int64_t r = live ? lane : 0;
-    uint16_t *crow = C + r * ldc;
-    u16x2 acc[NW];
-    tile_compute<NW, S8, FULLC>(acc, crow, A + r * lda, B, ldb, ncols, K, accumulate);
+    int64_t r[TM];
+    bool live[TM];
+#pragma unroll
+    for (int t = 0; t < TM; t++) {
+        live[t] = lane + 64 * t < nrows;
+        r[t] = live[t] ? lane + 64 * t : 0;
+    }
+    u16x2 acc[TM][NW];
+#pragma unroll
+    for (int t = 0; t < TM; t++) {
+        if (accumulate) {
+            row_load<NW, FULLC>(acc[t], C + r[t] * ldc, ncols);
+        } else {
+#pragma unroll
+            for (int w = 0; w < NW; w++) acc[t][w] = u16x2{0, 0};
+        }
+    }
+
+    // A is read in groups of AG = 32 entries per row (64 bytes, four 16-byte
+    // loads, issued one group ahead): a lane's loads then cover whole halves
+    // of 128-byte lines instead of returning to the same line eight times, as
+    // 16-byte loads spread over 64 rows would, with the line long evicted.
+    // Inside a group, KU inner steps at a time: their KU rows of B occupy
+    // KU * NW = 64 SGPRs (at most), which leaves room for addressing without
+    // spilling.
+    constexpr int KU = NW >= 32 ? 2 : (NW >= 16 ? 4 : 8);
+    constexpr int AG = 32;
+    const uint16_t *arow[TM];
+#pragma unroll
+    for (int t = 0; t < TM; t++) arow[t] = A + r[t] * lda;
+    int k = 0;
+    if (K >= AG) {
+        uint4 anext[TM][AG / 8];
+#pragma unroll
+        for (int t = 0; t < TM; t++)
+#pragma unroll
+            for (int q = 0; q < AG / 8; q++) anext[t][q] = reinterpret_cast<const uint4 *>(arow[t])[q];
+        for (; k + AG <= K; k += AG) {
+            uint32_t na[TM][AG / 2];
+#pragma unroll
+            for (int t = 0; t < TM; t++)
+#pragma unroll
+                for (int q = 0; q < AG / 8; q++) {
+                    na[t][4 * q + 0] = neg_pair<S8>(anext[t][q].x);
+                    na[t][4 * q + 1] = neg_pair<S8>(anext[t][q].y);
+                    na[t][4 * q + 2] = neg_pair<S8>(anext[t][q].z);
+                    na[t][4 * q + 3] = neg_pair<S8>(anext[t][q].w);
+                }
+            // The prefetch of the next group below is issued only after the
+            // negations above have consumed the current group (empty asm
+            // statements, which emit nothing: the first pins each S - a value
+            // before the second, a memory barrier, orders the loads after
+            // them), so the loads reuse its registers instead of copies.
+#pragma unroll
+            for (int t = 0; t < TM; t++)
+#pragma unroll
+                for (int i = 0; i < AG / 2; i++) asm volatile("" : "+v"(na[t][i]));
+            asm volatile("" ::: "memory");
+            if (k + 2 * AG <= K) {
+#pragma unroll
+                for (int t = 0; t < TM; t++)
+#pragma unroll
+                    for (int q = 0; q < AG / 8; q++)
+                        anext[t][q] = reinterpret_cast<const uint4 *>(arow[t] + k + AG)[q];
+            }
+#pragma unroll
+            for (int kg = 0; kg < AG; kg += KU) {
+                const uint16_t *b0 = B + (int64_t)(k + kg) * ldb;
+#pragma unroll
+                for (int kk = 0; kk < KU; kk++) {
+                    const kconst uint32_t *brow = (const kconst uint32_t *)(b0 + kk * ldb);
+#pragma unroll
+                    for (int t = 0; t < TM; t++) {
+                        const uint32_t n2 = na[t][(kg + kk) >> 1];
+                        const uint16_t n = ((kg + kk) & 1) ? (uint16_t)(n2 >> 16) : (uint16_t)n2;
+                        const u16x2 nv = u16x2{n, n};
+#pragma unroll
+                        for (int w = 0; w < NW; w++)
+                            acc[t][w] = step(acc[t][w], as_pair(brow[w]), nv);
+                    }
+                }
+            }
+        }
+    }
+    for (; k < K; k++) {
+        const kconst uint32_t *brow = (const kconst uint32_t *)(B + (int64_t)k * ldb);
+#pragma unroll
+        for (int t = 0; t < TM; t++) {
+            const uint16_t n = neg_one<S8>(arow[t][k]);
+            const u16x2 nv = u16x2{n, n};
+#pragma unroll
+            for (int w = 0; w < NW; w++) acc[t][w] = step(acc[t][w], as_pair(brow[w]), nv);
+        }
+    }
+
     if (sync_before_store) __syncthreads();
-    if (live) tile_store<NW, FULLC>(acc, crow, ncols);
+#pragma unroll
+    for (int t = 0; t < TM; t++)
+        if (live[t]) row_store<NW, FULLC>(acc[t], C + r[t] * ldc, ncols);
 }
 
 // The 8-column fallback of wave_tile below.
-template <bool S8>
-__device__ __forceinline__ void wave_tile_narrow(uint16_t *C, int64_t ldc,
-                                                           const uint16_t *A, int64_t lda,
-                                                           const uint16_t *B, int64_t ldb,
-                                                           int nrows, int ncols, int K,
-                                                           bool accumulate) {
+template <int TM, bool S8>
+__device__ __forceinline__ void wave_tile_narrow(uint16_t *C, int64_t ldc, const uint16_t *A,
+                                                 int64_t lda, const uint16_t *B, int64_t ldb,
+                                                 int nrows, int ncols, int K, bool accumulate) {
     for (int c = 0; c < ncols; c += 8) {
         const int nc = min(8, ncols - c);
         if (nc == 8)
-            wave_tile_body<4, S8, true>(C + c, ldc, A, lda, B + c, ldb, nrows, 8, K, accumulate,
-                                        false);
+            wave_tile_body<TM, 4, S8, true>(C + c, ldc, A, lda, B + c, ldb, nrows, 8, K,
+                                            accumulate, false);
         else
-            wave_tile_body<4, S8, false>(C + c, ldc, A, lda, B + c, ldb, nrows, nc, K, accumulate,
-                                         false);
+            wave_tile_body<TM, 4, S8, false>(C + c, ldc, A, lda, B + c, ldb, nrows, nc, K,
+                                             accumulate, false);
     }
 }
 
@@ -214,7 +266,7 @@ __device__ __forceinline__ void wave_tile_narrow(uint16_t *C, int64_t ldc,
 // sub-tiles store as they finish and the barrier comes last; a row-panel
 // update stays exact under that order because the pivot tile is closed (any
 // mix of old and new operand entries gives the same result).
-template <int NW, bool S8>
+template <int TM, int NW, bool S8>
 __device__ __forceinline__ void wave_tile(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
                                           const uint16_t *B, int64_t ldb, int nrows, int ncols,
                                           int64_t bspan, int K, bool accumulate,
@@ -225,14 +277,14 @@ __device__ __forceinline__ void wave_tile(uint16_t *C, int64_t ldc, const uint16
     }
     if (bspan >= 2 * NW) {
         if (ncols >= 2 * NW)
-            wave_tile_body<NW, S8, true>(C, ldc, A, lda, B, ldb, nrows, 2 * NW, K, accumulate,
-                                         sync_before_store);
+            wave_tile_body<TM, NW, S8, true>(C, ldc, A, lda, B, ldb, nrows, 2 * NW, K, accumulate,
+                                             sync_before_store);
         else
-            wave_tile_body<NW, S8, false>(C, ldc, A, lda, B, ldb, nrows, ncols, K, accumulate,
-                                          sync_before_store);
+            wave_tile_body<TM, NW, S8, false>(C, ldc, A, lda, B, ldb, nrows, ncols, K, accumulate,
+                                              sync_before_store);
         return;
     }
-    wave_tile_narrow<S8>(C, ldc, A, lda, B, ldb, nrows, ncols, K, accumulate);
+    wave_tile_narrow<TM, S8>(C, ldc, A, lda, B, ldb, nrows, ncols, K, accumulate);
     if (sync_before_store) __syncthreads();
 }
 
