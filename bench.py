@@ -40,17 +40,22 @@ PEAK_BOOL = 32 * VALU_LANE_OPS
 # scaled by the same counters on a streaming kernel of known size; valid only
 # for the kernel sources whose hash is recorded with it.
 TRAFFIC = {
-    "fw8192": {"src_hash": None, "bytes_per_launch": None},
+    # full update launch of the D = 8192 closure (serialized phases):
+    # (FETCH_SIZE 1.692e5 KiB x 2.000 + WRITE_SIZE 1.27e5 KiB x 1.000) per launch
+    "fw8192": {"src_hash": "3546ca2f6edffe41", "bytes_per_launch": 4.765e8},
 }
-KERNEL_SOURCES = ["paper_1705_08743_amd/csrc/sr_tiles.h",
-                  "paper_1705_08743_amd/csrc/sr_antidist.hip"]
-
-
 def src_hash():
+    """Hash of the update kernel's device source: the tile code (sr_tiles.h)
+    and the text of the k_ad_fw_update kernel template (host-side changes
+    elsewhere in sr_antidist.hip do not change the kernel)."""
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+    with open(os.path.join(ROOT, "paper_1705_08743_amd/csrc/sr_tiles.h"), "rb") as f:
+        h.update(f.read())
+    with open(os.path.join(ROOT, "paper_1705_08743_amd/csrc/sr_antidist.hip")) as f:
+        text = f.read()
+    start = text.index("k_ad_fw_update(uint16_t *T")
+    end = text.index("\n}\n", start)
+    h.update(text[start:end].encode())
     return h.hexdigest()[:16]
 
 

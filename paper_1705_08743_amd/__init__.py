@@ -235,6 +235,18 @@ def empty(kind, rows, cols, device="cuda", zero=True):
     return buf[:rows, :width]
 
 
+def clone(t):
+    """A copy of a matrix view with the same row stride (torch's clone of a
+    padded view would drop the padding and could break row alignment)."""
+    torch = _torch()
+    rows, cols = t.shape
+    ld = t.stride(0) if rows > 1 else max(t.stride(0), cols)
+    buf = torch.empty((max(rows, 1), ld), dtype=t.dtype, device=t.device)
+    out = buf[:rows, :cols]
+    out.copy_(t)
+    return out
+
+
 def to_device(kind, host, cols=None, device="cuda"):
     """Copy a host numpy matrix (uint8 / uint16 entries, or uint64 words) into
     a padded device buffer; returns the logical view."""
@@ -271,5 +283,5 @@ __all__ = [
     "semiring_mul", "semiring_add", "closure", "closure_batched", "version", "shutdown",
     "sr_profile_enable", "sr_profile_read", "SR_PHASE_PIVOT", "SR_PHASE_PANELS",
     "SR_PHASE_UPDATE",
-    "padded_ld", "empty", "to_device", "to_host", "EXPORTS", "LIB_PATH",
+    "padded_ld", "empty", "clone", "to_device", "to_host", "EXPORTS", "LIB_PATH",
 ]

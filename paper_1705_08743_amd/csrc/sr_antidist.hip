@@ -431,7 +431,7 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
     if (e != hipSuccess || nb == 1) return e;
     if ((e = panels_s<S8>(T, ld, D, 0, st)) != hipSuccess) return e;
 
-    Aux *aux = (nb > 2 && !serial && overrides().lookahead) ? aux_acquire() : nullptr;
+    Aux *aux = (nb > 2 && !serial && overrides().lookahead) ? aux_acquire(st) : nullptr;
     for (int kb = 0; kb < nb; kb++) {
         int rl, rh, cl, ch;
         block_chunks(D, kb, p.rw, &rl, &rh);

@@ -68,17 +68,18 @@ struct BatchDesc {
 hipError_t launch_ad_closure_batched(bool s8, const BatchDesc *desc, int64_t count,
                                      int32_t max_d, hipStream_t stream);
 
-// Second stream of a closure (sr_runtime.cpp), per device, created on first
-// use at default priority.  aux_acquire() returns it locked (the caller
-// enqueues its whole fork/join sequence, then calls aux_release) or nullptr
-// when it cannot be created.
+// Second stream of a closure (sr_runtime.cpp), one per (device, caller
+// stream), created on first use at default priority.  aux_acquire() returns it
+// locked (the caller enqueues its whole fork/join sequence, then calls
+// aux_release) or nullptr when none can be created.
 struct Aux {
     hipStream_t stream;
     hipEvent_t ev_main;  // recorded on the caller's stream, waited on by `stream`
     hipEvent_t ev_aux;   // recorded on `stream`, waited on by the caller's stream
     int device;
+    int slot;
 };
-Aux *aux_acquire();
+Aux *aux_acquire(hipStream_t caller);
 void aux_release(Aux *a);
 
 // Phase timing (sr_runtime.cpp).  kind: 0 Boolean, 1 anti-distance;

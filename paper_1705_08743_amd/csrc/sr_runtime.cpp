@@ -38,36 +38,58 @@ hipEvent_t get_event() {
     return e;
 }
 
-constexpr int kMaxDevices = 64;
-std::mutex g_aux_mu[kMaxDevices];
-Aux g_aux[kMaxDevices];
-bool g_aux_ready[kMaxDevices];
+// One second stream (with its two events) per (device, caller stream): two
+// closures enqueued on different caller streams then overlap each other as
+// well.  The table is small and never shrinks; each entry is locked while a
+// closure enqueues its fork/join sequence.
+struct AuxEntry {
+    int device;
+    hipStream_t caller;
+    Aux aux;
+    std::mutex mu;
+};
+constexpr int kMaxAux = 64;
+std::mutex g_aux_table_mu;
+AuxEntry g_aux_table[kMaxAux];
+int g_aux_count = 0;
 
 }  // namespace
 
-Aux *aux_acquire() {
+Aux *aux_acquire(hipStream_t caller) {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
-    g_aux_mu[dev].lock();
-    if (!g_aux_ready[dev]) {
-        Aux a{};
-        // default priority: the two streams must not differ in priority
-        if (hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&a.ev_main, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&a.ev_aux, hipEventDisableTiming) != hipSuccess) {
-            (void)hipGetLastError();
-            g_aux_mu[dev].unlock();
-            return nullptr;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    AuxEntry *entry = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_aux_table_mu);
+        for (int i = 0; i < g_aux_count; i++)
+            if (g_aux_table[i].device == dev && g_aux_table[i].caller == caller) {
+                entry = &g_aux_table[i];
+                break;
+            }
+        if (!entry) {
+            if (g_aux_count == kMaxAux) return nullptr;  // table full: no lookahead
+            Aux a{};
+            // default priority: the two streams must not differ in priority
+            if (hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&a.ev_main, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&a.ev_aux, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            a.device = dev;
+            a.slot = g_aux_count;
+            entry = &g_aux_table[g_aux_count++];
+            entry->device = dev;
+            entry->caller = caller;
+            entry->aux = a;
         }
-        a.device = dev;
-        g_aux[dev] = a;
-        g_aux_ready[dev] = true;
     }
-    return &g_aux[dev];
+    entry->mu.lock();
+    return &entry->aux;
 }
 
 void aux_release(Aux *a) {
-    if (a) g_aux_mu[a->device].unlock();
+    if (a) g_aux_table[a->slot].mu.unlock();
 }
 
 bool prof_on() {

@@ -1,0 +1,120 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (default flags: phases overlapped on two streams).
+
+The oracle cannot run the full D^3 loops here in seconds, so it computes
+sampled rows one by one from the path definition of the closure (Dijkstra /
+breadth-first search per source); properties that hold at any size are
+checked on the whole matrix with the GPU product.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1705_08743_amd as sr
+import synthgen
+from gpu_util import set_oracle_threads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    set_oracle_threads()
+
+
+def sample_rows(D, n, seed):
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(D, size=n, replace=False)
+    return np.sort(np.concatenate([rows, [0, D - 1]]).astype(np.int64))
+
+
+@pytest.mark.parametrize("kind", [sr.SR_ANTIDIST_U16, sr.SR_ANTIDIST_U8])
+def test_headline_closure_d8192(kind):
+    D = 8192
+    if kind == sr.SR_ANTIDIST_U16:
+        A = synthgen.cfg_antidist(D=D)[:, :D]
+        S = 65535
+    else:
+        A = synthgen.cfg_antidist_u8(D=D)[:, :D]
+        S = 255
+    dA = sr.to_device(kind, A)
+    T = dA.clone()
+    sr.closure(kind, T)
+    T2 = dA.clone()
+    sr.closure(kind, T2, flags=sr.SR_SERIAL_PHASES)
+    torch.cuda.synchronize()
+    H = sr.to_host(T)
+    # sampled rows against the oracle's path definition
+    rows = sample_rows(D, 10, 11 + kind)
+    want = oracle.ad_closure_rows(A, S, rows)
+    assert np.array_equal(H[rows].astype(np.int64), want.astype(np.int64))
+    # both schedules give the same bits
+    assert torch.equal(T, T2)
+    # properties on the whole matrix: T >= A and T (+) T*T = T
+    assert (H >= A).all()
+    TT = sr.empty(kind, D, D)
+    sr.semiring_mul(kind, TT, T, T)
+    sr.semiring_add(kind, TT, TT, T)
+    torch.cuda.synchronize()
+    assert torch.equal(TT, T)
+
+
+def test_product_config2_full_and_d8192_rows():
+    """uint16 product at D = 8192: sampled rows of A * B against the oracle's
+    multiplication loop on those rows."""
+    D = 8192
+    A = synthgen.cfg_antidist(D=D, which=0)[:, :D]
+    B = synthgen.cfg_antidist(D=D, which=1)[:, :D]
+    C = sr.empty(sr.SR_ANTIDIST_U16, D, D)
+    sr.semiring_mul(sr.SR_ANTIDIST_U16, C, sr.to_device(sr.SR_ANTIDIST_U16, A),
+                    sr.to_device(sr.SR_ANTIDIST_U16, B))
+    torch.cuda.synchronize()
+    rows = sample_rows(D, 6, 5)
+    want = oracle.ad_mul(A[rows], B, 65535)
+    assert np.array_equal(sr.to_host(C)[rows].astype(np.int64), want)
+
+
+def test_bool_closure_config3():
+    """Configuration 3: Boolean D = 16384, mean out-degree 3 plus planted
+    strongly connected blocks; sampled rows against breadth-first search and
+    T | T*T = T on the whole matrix."""
+    D = 16384
+    W = synthgen.cfg_bool16384(D=D)
+    T = sr.to_device(sr.SR_BOOL, W, cols=D)
+    sr.closure(sr.SR_BOOL, T, D=D)
+    torch.cuda.synchronize()
+    H = sr.to_host(T)
+    rows = sample_rows(D, 12, 3)
+    want = oracle.bool_closure_rows_words(W, D, rows)
+    nw = D // 64
+    assert np.array_equal(H[rows, :nw], want[:, :nw])
+    assert synthgen.padding_bits_clear(H[:64], D)
+    TT = sr.empty(sr.SR_BOOL, D, D)
+    sr.semiring_mul(sr.SR_BOOL, TT, T, T, K=D, N=D)
+    sr.semiring_add(sr.SR_BOOL, TT, TT, T, N=D)
+    torch.cuda.synchronize()
+    assert torch.equal(TT, T)
+
+
+def test_batched_config4_sample():
+    """Configuration 4 (4096 graphs, log-uniform sizes) in one launch; a
+    sample of graphs against the oracle, every graph against its solo run."""
+    kind = sr.SR_ANTIDIST_U16
+    batch = synthgen.cfg_batch()
+    mats = [synthgen.encode_antidist(n, r, c, w, np.uint16) for n, r, c, w in batch]
+    devs = [sr.to_device(kind, m) for m in mats]
+    solo = {i: sr.clone(devs[i]) for i in range(0, len(mats), 64)}
+    sr.closure_batched(kind, devs)
+    for t in solo.values():
+        sr.closure(kind, t)
+    torch.cuda.synchronize()
+    for i, t in solo.items():
+        assert torch.equal(devs[i], t), i
+    idx = np.argsort([m.shape[0] for m in mats])
+    for i in list(idx[:3]) + list(idx[-2:]) + [int(idx[len(idx) // 2])]:
+        want = oracle.ad_closure(mats[i], 65535)
+        assert np.array_equal(sr.to_host(devs[i]).astype(np.int64), want), mats[i].shape
