@@ -284,6 +284,77 @@ def run_add(args, torch, sr, synthgen):
                          "unit": "GB/s", "frac": gbs / 8000.0, "traffic": None}}
 
 
+def run_serve(args, torch, sr, synthgen):
+    """Serving: closure requests of log-uniform size in [64, 8192], half
+    Boolean (p = 0.02) and half uint16 anti-distance (configuration-2
+    generator), Poisson arrivals at 80% of the serial service rate; served
+    (continuous batching, footprint admission, concurrent slots) against the
+    same trace solved one at a time."""
+    import numpy as np
+    from paper_1705_08743_amd.serve import ClosureServer, Request
+    kinds = {"bool": sr.SR_BOOL, "u16": sr.SR_ANTIDIST_U16}
+
+    def make(trace):
+        return [(kinds[k], n, synthgen.serving_request(n, k, seed)) for n, k, seed in trace]
+
+    log("generating %d requests ..." % args.serve_requests)
+    reqs = make(synthgen.serving_trace(args.serve_requests))
+    calib = make(synthgen.serving_trace(args.serve_calibration, seed=synthgen.config_seed(5) + 1000))
+    server = ClosureServer(budget_bytes=int(args.serve_budget_gb * (1 << 30)), slots=4)
+    fresh = lambda items, arr: [Request(i, k, n, h, a) for i, ((k, n, h), a) in
+                                enumerate(zip(items, arr))]
+    # warm-up (allocator, code objects), then the serial service time
+    server.run(fresh(calib, np.zeros(len(calib))), "served")
+    cal = server.run(fresh(calib, np.zeros(len(calib))), "serial")
+    mean_service = cal["makespan_s"] / len(calib)
+    rate = 0.8 / mean_service
+    arrivals = synthgen.poisson_arrivals(len(reqs), rate, synthgen.generator(synthgen.config_seed(5) + 7))
+    served_reqs = fresh(reqs, arrivals)
+    served = server.run(served_reqs, "served")
+    serial_reqs = fresh(reqs, arrivals)
+    serial = server.run(serial_reqs, "serial")
+    same = all(np.array_equal(a.result, b.result) for a, b in zip(served_reqs, serial_reqs))
+    del serial_reqs
+    # capacity: the whole trace available at once
+    sat_served = server.run(fresh(reqs, np.zeros(len(reqs))), "served")
+    sat_serial = server.run(fresh(reqs, np.zeros(len(reqs))), "serial")
+    out = {"metric": "served requests/s (closure requests, Poisson at 80% of serial capacity); "
+                     "p50/p99 latency vs serial",
+           "value": served["throughput_rps"], "unit": "requests/s", "n_gpus": 1,
+           "steps": len(reqs), "warmup": 1, "ms_per_step": 1e3 / served["throughput_rps"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u16+bits", "data": "synthetic",
+           "config": {"workload": "serving_mixed_closures", "requests": len(reqs),
+                      "n": "log-uniform [64,8192]", "mix": "50% Boolean p=0.02, 50% uint16 p=0.05",
+                      "arrival_rate_rps": rate, "mean_serial_service_ms": mean_service * 1e3,
+                      "budget_gb": args.serve_budget_gb, "slots": 4, "batch_n": 256,
+                      "parallelism": "single_gpu"},
+           "served": served, "serial": serial,
+           "saturated": {"served_rps": sat_served["throughput_rps"],
+                         "serial_rps": sat_serial["throughput_rps"],
+                         "served_updates_per_s": sat_served["updates_per_s"],
+                         "serial_updates_per_s": sat_serial["updates_per_s"],
+                         "throughput_speedup": sat_served["throughput_rps"] / sat_serial["throughput_rps"],
+                         "batched_requests": sat_served["batched_requests"]},
+           "p99_speedup_vs_serial": serial["p99_ms"] / served["p99_ms"],
+           "p50_speedup_vs_serial": serial["p50_ms"] / served["p50_ms"],
+           "parity": {"served_equals_serial_all_requests": bool(same)}}
+    if not args.no_parity:
+        import oracle
+        small = sorted(range(len(served_reqs)), key=lambda i: served_reqs[i].n)[:4]
+        ok = True
+        for i in small:
+            r = served_reqs[i]
+            if r.kind == sr.SR_BOOL:
+                want = oracle.bool_closure_words(r.host, r.n)[:, :(r.n + 63) // 64]
+                ok &= bool(np.array_equal(r.result.view(np.uint64), want))
+            else:
+                ok &= bool(np.array_equal(r.result.astype(np.int64),
+                                          oracle.ad_closure(r.host[:, :r.n], 65535)))
+        out["parity"]["oracle_smallest_4"] = ok
+    return out
+
+
 def run_batched(args, torch, sr, synthgen):
     """4096 graphs, log-uniform sizes in [32, 1024], uint16: one batched launch
     against one closure() call per graph on the same stream."""
@@ -338,7 +409,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fw8192",
-                    choices=["fw8192", "u8fw8192", "bool16384", "mul1024", "batched", "add8192"])
+                    choices=["fw8192", "u8fw8192", "bool16384", "mul1024", "batched", "add8192",
+                             "serve"])
+    ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--serve-calibration", type=int, default=24)
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--parity-rows", type=int, default=4)
@@ -381,6 +456,8 @@ def main():
         out = run_mul(args, torch, sr, synthgen)
     elif args.workload == "add8192":
         out = run_add(args, torch, sr, synthgen)
+    elif args.workload == "serve":
+        out = run_serve(args, torch, sr, synthgen)
     else:
         out = run_batched(args, torch, sr, synthgen)
     out["library"] = sr.version()

@@ -1,0 +1,89 @@
+"""Serving: each request's result is the same alone and in the mix.
+
+A mixed trace (Boolean and uint16 anti-distance closures of uneven sizes,
+arriving close together) is replayed through the continuously batched server;
+every result must equal the same request closed alone on the device, and the
+oracle's closure.  A small budget forces admission control to queue requests.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1705_08743_amd as sr
+import synthgen
+from gpu_util import set_oracle_threads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    set_oracle_threads()
+
+
+def make_requests(count, nlo, nhi, seed, spacing):
+    from paper_1705_08743_amd.serve import Request
+    trace = synthgen.serving_trace(count, nlo=nlo, nhi=nhi, seed=seed)
+    kinds = {"bool": sr.SR_BOOL, "u16": sr.SR_ANTIDIST_U16}
+    return [Request(i, kinds[k], n, synthgen.serving_request(n, k, s), i * spacing)
+            for i, (n, k, s) in enumerate(trace)]
+
+
+def solo(r):
+    if r.kind == sr.SR_BOOL:
+        t = sr.to_device(sr.SR_BOOL, r.host, cols=r.n)
+        sr.closure(sr.SR_BOOL, t, D=r.n)
+    else:
+        t = sr.to_device(r.kind, r.host[:, :r.n])
+        sr.closure(r.kind, t)
+    torch.cuda.synchronize()
+    return sr.to_host(t)
+
+
+def want(r):
+    if r.kind == sr.SR_BOOL:
+        return oracle.bool_closure_words(r.host, r.n)[:, :(r.n + 63) // 64]
+    return oracle.ad_closure(r.host[:, :r.n], 65535)
+
+
+@pytest.mark.parametrize("budget_mb", [4096, 2])
+def test_served_results_equal_solo_and_oracle(budget_mb):
+    from paper_1705_08743_amd.serve import ClosureServer
+    reqs = make_requests(40, 40, 700, seed=4242, spacing=2e-4)
+    server = ClosureServer(budget_bytes=budget_mb << 20, slots=4, batch_n=256)
+    stats = server.run(reqs, "served")
+    assert stats["requests"] == len(reqs)
+    if budget_mb > 100:
+        assert stats["batched_requests"] > 0  # small requests were batched
+    for r in reqs:
+        got = r.result.view(np.uint64) if r.kind == sr.SR_BOOL else r.result
+        alone = solo(r)
+        if r.kind == sr.SR_BOOL:
+            alone = alone[:, :(r.n + 63) // 64]
+        assert np.array_equal(got, alone), (r.rid, r.n, r.kind)
+        assert np.array_equal(got.astype(np.int64) if r.kind != sr.SR_BOOL else got, want(r)), r.rid
+
+
+def test_serial_mode_matches_served():
+    from paper_1705_08743_amd.serve import ClosureServer, Request
+    reqs = make_requests(16, 64, 1500, seed=99, spacing=0.0)
+    twin = [Request(r.rid, r.kind, r.n, r.host, r.arrival) for r in reqs]
+    server = ClosureServer(budget_bytes=1 << 30)
+    a = server.run(reqs, "served")
+    b = server.run(twin, "serial")
+    for x, y in zip(reqs, twin):
+        assert np.array_equal(x.result, y.result)
+    assert b["batched_requests"] == 0
+    assert a["p99_ms"] > 0 and b["p99_ms"] > 0
+
+
+def test_budget_too_small_is_refused():
+    from paper_1705_08743_amd.serve import ClosureServer
+    reqs = make_requests(2, 300, 301, seed=5, spacing=0.0)
+    server = ClosureServer(budget_bytes=1024)
+    with pytest.raises(ValueError):
+        server.run(reqs, "served")
