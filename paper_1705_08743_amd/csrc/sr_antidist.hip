@@ -29,11 +29,14 @@
 namespace sr {
 namespace {
 
+using dev::fw_panels_wg;
+using dev::fw_update_wg;
+using dev::kPanelNW;
+using dev::Rect;
 using dev::tile_closure;
 using dev::wave_tile;
 using dev::wave_tile_body;
 
-constexpr int kPanelNW = 16;  // 32 columns per wave in the panel phase
 
 // ---------------------------------------------------------------------------
 // Product: each wave owns 64*TM rows x 2NW columns; the four waves of a
@@ -69,76 +72,20 @@ __global__ void __launch_bounds__(256) k_ad_fw_pivot(uint16_t *T, int64_t ld, in
     tile_closure<S8>(T + k0 * ld + k0, ld, bs, lds_row, lds_col);
 }
 
-// Phase 2.  Workgroups [0, n_rowwg) take the row panel: two 64-row halves of
-// the pivot rows times two 32-column chunks (the chunks outside the pivot
-// block, two per workgroup).  The rest take the column panel: one 64-row chunk
-// outside the pivot block times the four 32-column chunks of the pivot block.
-// Every panel tile is read and written by one workgroup only, and a barrier
-// separates its reads from its writes.
+// Phase 2 (the workgroup body is fw_panels_wg in sr_tiles.h).
 template <bool S8>
 __global__ void __launch_bounds__(256)
 k_ad_fw_panels(uint16_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg) {
-    constexpr int NW = kPanelNW, CW = 2 * NW;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
-    if ((int)blockIdx.x < n_rowwg) {
-        const int kc0 = k0 / CW, kc1 = (k0 + bs + CW - 1) / CW;
-        const int cc = 2 * (int)blockIdx.x + (wave >> 1);
-        const int c = cc < kc0 ? cc : cc + (kc1 - kc0);
-        const int64_t col0 = (int64_t)c * CW;
-        const int rofs = (wave & 1) * 64;
-        const int nrows = min(64, bs - rofs);
-        const int ncols = (int)min<int64_t>(CW, (int64_t)D - col0);
-        const int64_t r0 = (int64_t)k0 + rofs;
-        wave_tile<1, NW, S8>(T + r0 * ld + col0, ld, T + r0 * ld + k0, ld,
-                             T + (int64_t)k0 * ld + col0, ld, nrows, ncols, ld - col0, bs, true,
-                             true);
-    } else {
-        const int kr0 = k0 / 64, kr1 = (k0 + bs + 63) / 64;
-        const int rc = (int)blockIdx.x - n_rowwg;
-        const int rchunk = rc < kr0 ? rc : rc + (kr1 - kr0);
-        const int64_t row0 = (int64_t)rchunk * 64;
-        const int nrows = (int)min<int64_t>(64, (int64_t)D - row0);
-        const int cofs = wave * CW;
-        const int ncols = min(CW, bs - cofs);
-        wave_tile<1, NW, S8>(T + row0 * ld + k0 + cofs, ld, T + row0 * ld + k0, ld,
-                             T + (int64_t)k0 * ld + k0 + cofs, ld, nrows, ncols,
-                             ld - k0 - cofs, bs, true, true);
-    }
+    fw_panels_wg<S8>(T, ld, D, k0, bs, n_rowwg, (int)blockIdx.x);
 }
 
-// Phase 3 over a rectangle of tiles: row chunks (64*TM rows) [r_lo, r_hi)
-// minus [r_ex0, r_ex1), column chunks (2NW columns) [c_lo, c_hi) minus
-// [c_ex0, c_ex1); T_ij (+)= T_iK * T_Kj for pivot block K = [k0, k0 + bs).
-// The grid has one column per selected column chunk and ceil(rows / 4) rows
-// of workgroups; the four waves of a workgroup share the column chunk.
-struct Rect {
-    int r_lo, r_hi, r_ex0, r_ex1, c_lo, c_hi, c_ex0, c_ex1;
-};
-
+// Phase 3 over a rectangle of tiles (body: fw_update_wg in sr_tiles.h).
 // FULL: every selected column chunk has all 2NW columns inside D (the
 // launcher sends a partial last chunk to a FULL = false launch).
 template <int TM, int NW, bool S8, bool FULL>
 __global__ void __launch_bounds__(256)
 k_ad_fw_update(uint16_t *T, int64_t ld, int D, int k0, int bs, Rect q) {
-    constexpr int CW = 2 * NW, RW = 64 * TM;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
-    int c = q.c_lo + (int)blockIdx.x;
-    if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
-    int rc = q.r_lo + (int)blockIdx.y * 4 + wave;
-    if (rc >= q.r_ex0) rc += q.r_ex1 - q.r_ex0;
-    if (rc >= q.r_hi || c >= q.c_hi) return;
-    const int64_t row0 = (int64_t)rc * RW, col0 = (int64_t)c * CW;
-    const int nrows = (int)min<int64_t>(RW, (int64_t)D - row0);
-    if (FULL) {
-        wave_tile_body<TM, NW, S8, true>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld,
-                                         T + (int64_t)k0 * ld + col0, ld, nrows, CW, bs, true,
-                                         false);
-    } else {
-        const int ncols = (int)min<int64_t>(CW, (int64_t)D - col0);
-        wave_tile<TM, NW, S8>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld,
-                              T + (int64_t)k0 * ld + col0, ld, nrows, ncols, ld - col0, bs, true,
-                              false);
-    }
+    fw_update_wg<TM, NW, S8, FULL>(T, ld, D, k0, bs, q, (int)blockIdx.x, (int)blockIdx.y);
 }
 
 // uint8 <-> uint16, 8 entries per thread; rows padded with zeros up to the
@@ -406,13 +353,9 @@ hipError_t pivot_s(uint16_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t s
 template <bool S8>
 hipError_t panels_s(uint16_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t st) {
     const int k0 = block_k0(kb), bs = block_bs(D, kb);
-    const int pcw = 2 * kPanelNW;
-    const int64_t nchunk_p = (D + pcw - 1) / pcw;
-    const int kpc = (k0 + bs + pcw - 1) / pcw - k0 / pcw;
-    const int n_rowwg = (int)((nchunk_p - kpc + 1) / 2);
-    const int64_t nrch = (D + 63) / 64;
-    const int kr = (k0 + bs + 63) / 64 - k0 / 64;
-    const int n = n_rowwg + (int)(nrch - kr);
+    int n_rowwg = 0, n_colwg = 0;
+    dev::panel_wgs(D, k0, bs, &n_rowwg, &n_colwg);
+    const int n = n_rowwg + n_colwg;
     if (n <= 0) return hipSuccess;
     const bool prof = prof_on();
     if (prof) prof_begin(st);

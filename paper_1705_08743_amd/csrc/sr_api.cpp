@@ -270,7 +270,6 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
     if (!T || !ldt || !D) return fail(SR_EINVAL, "closure_batched: NULL descriptor array");
     std::vector<Span> spans;
     spans.reserve((size_t)count);
-    int32_t max_d = 0;
     for (int64_t g = 0; g < count; g++) {
         char name[48];
         snprintf(name, sizeof name, "T[%lld]", (long long)g);
@@ -278,7 +277,6 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
         const int rc = check_matrix(kind, name, T[g], ldt[g], D[g], D[g]);
         if (rc != SR_OK) return rc;
         if (D[g] > 0) spans.push_back(span_of(kind, T[g], ldt[g], D[g]));
-        max_d = std::max<int32_t>(max_d, (int32_t)D[g]);
     }
     std::sort(spans.begin(), spans.end(), [](Span a, Span b) { return a.lo < b.lo; });
     for (size_t i = 1; i < spans.size(); i++)
@@ -292,19 +290,8 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return D[a] > D[b]; });
 
+    std::vector<sr::BatchDesc> h((size_t)count);
     size_t work_elems = 0;
-    if (s8)
-        for (int64_t g = 0; g < count; g++) work_elems += (size_t)(D[g] * round_up(D[g], 8));
-    const size_t desc_bytes = round_up((int64_t)(count * sizeof(sr::BatchDesc)), 256);
-    void *w = nullptr;
-    int rc = work_alloc(&w, desc_bytes + work_elems * 2, st);
-    if (rc != SR_OK) return rc;
-    // Host copy of the descriptors; freed by a stream callback once the upload
-    // has executed, so the call stays asynchronous.
-    auto *hv = new std::vector<sr::BatchDesc>((size_t)count);
-    std::vector<sr::BatchDesc> &h = *hv;
-    uint16_t *arena = reinterpret_cast<uint16_t *>(static_cast<char *>(w) + desc_bytes);
-    size_t off = 0;
     for (int64_t i = 0; i < count; i++) {
         const int64_t g = order[(size_t)i];
         sr::BatchDesc &d = h[(size_t)i];
@@ -314,8 +301,8 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
             d.T8 = static_cast<uint8_t *>(T[g]);
             d.ld8 = ldt[g];
             d.ld = round_up(D[g], 8);
-            d.T = arena + off;
-            off += (size_t)(D[g] * d.ld);
+            d.T = nullptr;
+            work_elems += (size_t)(D[g] * d.ld);
         } else {
             d.T8 = nullptr;
             d.ld8 = 0;
@@ -323,15 +310,20 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
             d.ld = ldt[g];
         }
     }
-    sr::BatchDesc *dd = static_cast<sr::BatchDesc *>(w);
-    hipError_t e = hipMemcpyAsync(dd, h.data(), (size_t)count * sizeof(sr::BatchDesc),
-                                  hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipLaunchHostFunc(
-            st, [](void *p) { delete static_cast<std::vector<sr::BatchDesc> *>(p); }, hv);
-    else
-        delete hv;
-    if (e == hipSuccess) e = sr::launch_ad_closure_batched(s8, dd, count, max_d, st);
+    // descriptors and per-round work lists, then the uint16 working copies
+    const size_t plan_bytes = round_up((int64_t)sr::batch_plan_bytes(h.data(), count), 256);
+    void *w = nullptr;
+    int rc = work_alloc(&w, plan_bytes + work_elems * 2, st);
+    if (rc != SR_OK) return rc;
+    if (s8) {
+        uint16_t *arena = reinterpret_cast<uint16_t *>(static_cast<char *>(w) + plan_bytes);
+        size_t off = 0;
+        for (sr::BatchDesc &d : h) {
+            d.T = arena + off;
+            off += (size_t)d.D * (size_t)d.ld;
+        }
+    }
+    hipError_t e = sr::launch_ad_closure_batched(s8, h.data(), count, w, st);
     work_free(w, st);
     if (e != hipSuccess) return device_fail(e, "closure_batched launch");
     return ok();

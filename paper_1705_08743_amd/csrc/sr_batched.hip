@@ -1,25 +1,25 @@
-// Batched anti-distance closure: many independent graphs of uneven size in
-// one launch.  Workgroup g closes graph g of a descriptor array that the host
-// has sorted largest-first, so the hardware dispatcher hands out the longest
-// jobs first and fills the machine with the short ones as it drains
-// (longest-processing-time-first list scheduling).
+// Batched anti-distance closure: many independent graphs of uneven size,
+// closed together by the blocked Floyd-Warshall of sr_antidist.hip run
+// round-synchronously across the whole batch.
 //
-// Per graph (256 threads):
-//   D <= kAdBlock: the whole matrix is one tile closed in registers + LDS
-//                  (the pivot routine of the blocked closure).
-//   D >  kAdBlock: the blocked Floyd-Warshall of sr_antidist.hip inside the
-//                  workgroup: per round the pivot tile, then the panel tiles,
-//                  then the remaining tiles, each phase shared by the four
-//                  waves and separated by workgroup barriers.
-//
-// Inside one phase, waves update panel tiles that other waves read (a row of
-// the pivot rows is both an output and an operand).  This is exact: with
-// T_KK closed, T_Kj (+) T_KK * Y gives the same value for every Y between the
-// old and the new T_Kj, and the same holds for T_iK (+) Y * T_KK; in phase 3
-// the row panel may likewise be read old or new.  Entries are never torn
-// (16-bit entries written by 32/128-bit stores).
+// Round kb is three launches, each covering every graph that still has a
+// round kb (a graph of D vertices has ceil(D / kAdBlock) rounds):
+//   pivot:  one workgroup per graph closes its pivot tile; for a graph of at
+//           most kAdBlock vertices this tile is the whole matrix, so round 0's
+//           pivot launch closes all small graphs outright;
+//   panels: the phase-2 workgroups of all graphs, back to back;
+//   update: the phase-3 workgroups of all graphs, back to back.
+// A workgroup finds its graph and its workgroup index inside that graph by a
+// binary search over per-graph prefix counts built on the host, then runs
+// exactly the workgroup body the single-graph kernels run.  Graphs are sorted
+// largest first, so in every launch the longest work is dispatched first.
+// Every launch has thousands of workgroups (not one per graph), which keeps
+// the large graphs from finishing alone on a few compute units.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "sr_internal.h"
 #include "sr_tiles.h"
@@ -27,76 +27,93 @@
 namespace sr {
 namespace {
 
+using dev::fw_panels_wg;
+using dev::Rect;
 using dev::tile_closure;
-using dev::wave_tile;
 
-constexpr int kBNW = 16;  // 32-column wave tiles
-constexpr int kBCW = 2 * kBNW;
+constexpr int kUTM = 1, kUNW = 16;  // update tiles: 64 rows x 32 columns per wave
 
-template <bool S8>
-__device__ void blocked_closure_wg(uint16_t *T, int64_t ld, int D, uint32_t *lds_row,
-                                   uint32_t *lds_col) {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
-    const int nb = (D + kAdBlock - 1) / kAdBlock;
-    const int nrch = (D + 63) / 64;
-    const int ncch = (D + kBCW - 1) / kBCW;
-    for (int kb = 0; kb < nb; kb++) {
-        const int k0 = kb * kAdBlock;
-        const int bs = min(kAdBlock, D - k0);
-        tile_closure<S8>(T + (int64_t)k0 * ld + k0, ld, bs, lds_row, lds_col);
-        if (nb == 1) break;
-        __syncthreads();
-        const int kr0 = k0 / 64, kr = (k0 + bs + 63) / 64 - kr0;
-        const int kc0 = k0 / kBCW, kc = (k0 + bs + kBCW - 1) / kBCW - kc0;
-        const int nrx = nrch - kr, ncx = ncch - kc;
-        // phase 2: row-panel items (pivot-row half h, column chunk c), then
-        // column-panel items (row chunk r, pivot column chunk q)
-        const int n_row_items = 2 * ncx, n_items2 = n_row_items + 4 * nrx;
-        for (int it = wave; it < n_items2; it += 4) {
-            if (it < n_row_items) {
-                const int h = it & 1, cc = it >> 1;
-                const int c = cc < kc0 ? cc : cc + kc;
-                const int64_t col0 = (int64_t)c * kBCW, r0 = (int64_t)k0 + 64 * h;
-                wave_tile<1, kBNW, S8>(T + r0 * ld + col0, ld, T + r0 * ld + k0, ld,
-                                    T + (int64_t)k0 * ld + col0, ld, min(64, bs - 64 * h),
-                                    (int)min<int64_t>(kBCW, D - col0), ld - col0, bs, true, false);
-            } else {
-                const int j = it - n_row_items;
-                const int rr = j >> 2, q = j & 3;
-                const int rch = rr < kr0 ? rr : rr + kr;
-                const int64_t row0 = (int64_t)rch * 64;
-                wave_tile<1, kBNW, S8>(T + row0 * ld + k0 + q * kBCW, ld, T + row0 * ld + k0, ld,
-                                    T + (int64_t)k0 * ld + k0 + q * kBCW, ld,
-                                    (int)min<int64_t>(64, D - row0), min(kBCW, bs - q * kBCW),
-                                    ld - k0 - q * kBCW, bs, true, false);
-            }
-        }
-        __syncthreads();
-        // phase 3: every (row chunk, column chunk) outside the pivot block
-        const int n_items3 = nrx * ncx;
-        for (int it = wave; it < n_items3; it += 4) {
-            const int rr = it / ncx, cc = it % ncx;
-            const int rch = rr < kr0 ? rr : rr + kr;
-            const int c = cc < kc0 ? cc : cc + kc;
-            const int64_t row0 = (int64_t)rch * 64, col0 = (int64_t)c * kBCW;
-            wave_tile<1, kBNW, S8>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld,
-                                T + (int64_t)k0 * ld + col0, ld, (int)min<int64_t>(64, D - row0),
-                                (int)min<int64_t>(kBCW, D - col0), ld - col0, bs, true, false);
-        }
-        __syncthreads();
+// One entry per graph taking part in a launch; `first` is the graph's first
+// workgroup; a sentinel entry holds the launch's total.
+struct Item {
+    int32_t graph;
+    int32_t first;
+};
+
+__device__ __forceinline__ int find_item(const Item *it, int n, int bid) {
+    int lo = 0, hi = n - 1;  // largest i with it[i].first <= bid
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (it[mid].first <= bid)
+            lo = mid;
+        else
+            hi = mid - 1;
     }
+    return lo;
+}
+
+__host__ __device__ inline int rounds_of(int D) { return (D + kAdBlock - 1) / kAdBlock; }
+
+// The full update rectangle of round kb for a graph of D vertices.
+__host__ __device__ inline Rect update_rect(int D, int kb, int *ncols_sel, int *nrows_sel) {
+    constexpr int RW = 64 * kUTM, CW = 2 * kUNW;
+    const int k0 = kb * kAdBlock, bs = min(kAdBlock, D - k0);
+    Rect q;
+    q.r_lo = 0;
+    q.r_hi = (D + RW - 1) / RW;
+    q.r_ex0 = k0 / RW;
+    q.r_ex1 = (k0 + bs + RW - 1) / RW;
+    q.c_lo = 0;
+    q.c_hi = (D + CW - 1) / CW;
+    q.c_ex0 = k0 / CW;
+    q.c_ex1 = (k0 + bs + CW - 1) / CW;
+    *ncols_sel = (q.c_hi - q.c_lo) - (q.c_ex1 - q.c_ex0);
+    *nrows_sel = (q.r_hi - q.r_lo) - (q.r_ex1 - q.r_ex0);
+    return q;
 }
 
 template <bool S8>
-__global__ void __launch_bounds__(256) k_ad_batched(const BatchDesc *desc) {
+__global__ void __launch_bounds__(256) k_batch_pivot(const BatchDesc *desc, const Item *items, int kb) {
     __shared__ uint32_t lds_row[2 * 64];
     __shared__ uint32_t lds_col[2 * 128];
-    const BatchDesc d = desc[blockIdx.x];
-    if (d.D <= 0) return;
-    if (d.D <= kAdBlock)
-        tile_closure<S8>(d.T, d.ld, d.D, lds_row, lds_col);
+    const BatchDesc d = desc[items[blockIdx.x].graph];
+    const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
+    tile_closure<S8>(d.T + (int64_t)k0 * d.ld + k0, d.ld, bs, lds_row, lds_col);
+}
+
+template <bool S8>
+__global__ void __launch_bounds__(256)
+k_batch_panels(const BatchDesc *desc, const Item *items, int n_items, int kb) {
+    const int i = find_item(items, n_items, (int)blockIdx.x);
+    const BatchDesc d = desc[items[i].graph];
+    const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
+    int n_rowwg = 0, n_colwg = 0;
+    dev::panel_wgs(d.D, k0, bs, &n_rowwg, &n_colwg);
+    fw_panels_wg<S8>(d.T, d.ld, d.D, k0, bs, n_rowwg, (int)blockIdx.x - items[i].first);
+}
+
+// Phase 3: one 64 x 32 tile per wave.  The waves of all graphs are numbered
+// back to back (a graph's tiles row-chunk major), so a workgroup's four waves
+// may belong to different graphs; no wave of the launch idles except in the
+// last workgroup.
+template <bool S8>
+__global__ void __launch_bounds__(256)
+k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, int n_waves) {
+    const int gw = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (gw >= n_waves) return;
+    const int i = find_item(items, n_items, gw);
+    const BatchDesc d = desc[items[i].graph];
+    const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
+    int nc = 0, nr = 0;
+    const Rect q = update_rect(d.D, kb, &nc, &nr);
+    const int local = gw - items[i].first;
+    const int csel = local % nc, rsel = local / nc;
+    int c = csel;
+    if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
+    if ((c + 1) * (2 * kUNW) <= d.D)
+        dev::fw_update_wave<kUTM, kUNW, S8, true>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
     else
-        blocked_closure_wg<S8>(d.T, d.ld, d.D, lds_row, lds_col);
+        dev::fw_update_wave<kUTM, kUNW, S8, false>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
 }
 
 // uint8 <-> uint16 for every graph of a batch (workgroup g: graph g).
@@ -132,20 +149,124 @@ __global__ void __launch_bounds__(256) k_batch_narrow(const BatchDesc *desc) {
     }
 }
 
+// Host plan: per round, the three item lists (offsets into one array).
+struct Launch {
+    int64_t offset;  // index of the first Item
+    int n_items;     // items without the sentinel
+    int n_wg;        // workgroups
+    int n_units;     // update: wave tiles
+};
+
+struct HostPlan {
+    std::vector<Item> items;
+    std::vector<Launch> pivot, panels, update;  // per round
+};
+
+HostPlan build_plan(const BatchDesc *hd, int64_t count) {
+    HostPlan p;
+    int max_rounds = 0;
+    for (int64_t g = 0; g < count; g++) max_rounds = std::max(max_rounds, rounds_of(hd[g].D));
+    for (int kb = 0; kb < max_rounds; kb++) {
+        // pivot: every graph with a round kb
+        Launch lp{(int64_t)p.items.size(), 0, 0, 0};
+        for (int64_t g = 0; g < count; g++)
+            if (hd[g].D > 0 && rounds_of(hd[g].D) > kb) p.items.push_back(Item{(int32_t)g, lp.n_wg++});
+        lp.n_items = lp.n_wg;
+        p.items.push_back(Item{-1, lp.n_wg});
+        p.pivot.push_back(lp);
+        // panels and update: graphs with more than one round
+        Launch la{(int64_t)p.items.size(), 0, 0, 0};
+        for (int64_t g = 0; g < count; g++) {
+            const int D = hd[g].D;
+            if (rounds_of(D) <= std::max(kb, 1)) continue;
+            const int k0 = kb * kAdBlock, bs = std::min(kAdBlock, D - k0);
+            int r = 0, c = 0;
+            dev::panel_wgs(D, k0, bs, &r, &c);
+            if (r + c <= 0) continue;
+            p.items.push_back(Item{(int32_t)g, la.n_wg});
+            la.n_wg += r + c;
+            la.n_items++;
+        }
+        p.items.push_back(Item{-1, la.n_wg});
+        p.panels.push_back(la);
+        Launch lu{(int64_t)p.items.size(), 0, 0, 0};
+        for (int64_t g = 0; g < count; g++) {
+            const int D = hd[g].D;
+            if (rounds_of(D) <= std::max(kb, 1)) continue;
+            int nc = 0, nr = 0;
+            (void)update_rect(D, kb, &nc, &nr);
+            const int waves = nc * nr;
+            if (waves <= 0) continue;
+            p.items.push_back(Item{(int32_t)g, lu.n_units});
+            lu.n_units += waves;
+            lu.n_items++;
+        }
+        p.items.push_back(Item{-1, lu.n_units});
+        lu.n_wg = (lu.n_units + 3) / 4;
+        p.update.push_back(lu);
+    }
+    return p;
+}
+
 }  // namespace
 
-hipError_t launch_ad_closure_batched(bool s8, const BatchDesc *desc, int64_t count, int32_t max_d,
-                                     hipStream_t stream) {
-    (void)max_d;
+size_t batch_plan_bytes(const BatchDesc *host_desc, int64_t count) {
+    const HostPlan p = build_plan(host_desc, count);
+    const size_t desc_bytes = ((size_t)count * sizeof(BatchDesc) + 255) / 256 * 256;
+    return desc_bytes + p.items.size() * sizeof(Item);
+}
+
+hipError_t launch_ad_closure_batched(bool s8, const BatchDesc *host_desc, int64_t count,
+                                     void *dev_buf, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    const dim3 grid((unsigned)count);
-    if (s8) {
-        hipLaunchKernelGGL(k_batch_widen, grid, dim3(256), 0, stream, desc);
-        hipLaunchKernelGGL(k_ad_batched<true>, grid, dim3(256), 0, stream, desc);
-        hipLaunchKernelGGL(k_batch_narrow, grid, dim3(256), 0, stream, desc);
-    } else {
-        hipLaunchKernelGGL(k_ad_batched<false>, grid, dim3(256), 0, stream, desc);
+    const HostPlan p = build_plan(host_desc, count);
+    const size_t desc_bytes = ((size_t)count * sizeof(BatchDesc) + 255) / 256 * 256;
+    // host image of the descriptors and item lists; freed by a stream
+    // callback once the upload has executed
+    auto *img = new std::vector<char>(desc_bytes + p.items.size() * sizeof(Item));
+    std::copy_n(reinterpret_cast<const char *>(host_desc), (size_t)count * sizeof(BatchDesc),
+                img->data());
+    std::copy_n(reinterpret_cast<const char *>(p.items.data()), p.items.size() * sizeof(Item),
+                img->data() + desc_bytes);
+    hipError_t e = hipMemcpyAsync(dev_buf, img->data(), img->size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipLaunchHostFunc(st, [](void *q) { delete static_cast<std::vector<char> *>(q); }, img);
+    else
+        delete img;
+    if (e != hipSuccess) return e;
+    const BatchDesc *desc = static_cast<const BatchDesc *>(dev_buf);
+    const Item *items =
+        reinterpret_cast<const Item *>(static_cast<const char *>(dev_buf) + desc_bytes);
+    if (s8) hipLaunchKernelGGL(k_batch_widen, dim3((unsigned)count), dim3(256), 0, st, desc);
+    for (size_t kb = 0; kb < p.pivot.size(); kb++) {
+        const Launch &a = p.pivot[kb], &b = p.panels[kb], &c = p.update[kb];
+        if (a.n_wg > 0) {
+            if (s8)
+                hipLaunchKernelGGL(k_batch_pivot<true>, dim3(a.n_wg), dim3(256), 0, st, desc,
+                                   items + a.offset, (int)kb);
+            else
+                hipLaunchKernelGGL(k_batch_pivot<false>, dim3(a.n_wg), dim3(256), 0, st, desc,
+                                   items + a.offset, (int)kb);
+        }
+        if (b.n_wg > 0) {
+            if (s8)
+                hipLaunchKernelGGL(k_batch_panels<true>, dim3(b.n_wg), dim3(256), 0, st, desc,
+                                   items + b.offset, b.n_items + 1, (int)kb);
+            else
+                hipLaunchKernelGGL(k_batch_panels<false>, dim3(b.n_wg), dim3(256), 0, st, desc,
+                                   items + b.offset, b.n_items + 1, (int)kb);
+        }
+        if (c.n_wg > 0) {
+            if (s8)
+                hipLaunchKernelGGL(k_batch_update<true>, dim3(c.n_wg), dim3(256), 0, st, desc,
+                                   items + c.offset, c.n_items + 1, (int)kb, c.n_units);
+            else
+                hipLaunchKernelGGL(k_batch_update<false>, dim3(c.n_wg), dim3(256), 0, st, desc,
+                                   items + c.offset, c.n_items + 1, (int)kb, c.n_units);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (s8) hipLaunchKernelGGL(k_batch_narrow, dim3((unsigned)count), dim3(256), 0, st, desc);
     return hipGetLastError();
 }
 

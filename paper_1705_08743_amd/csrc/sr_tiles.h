@@ -389,5 +389,99 @@ __device__ __forceinline__ void tile_closure(uint16_t *T, int64_t ld, int bs, ui
     }
 }
 
+// Number of phase-2 workgroups of a round: row panel (two 32-column chunks
+// outside the pivot block each) and column panel (one 64-row chunk each).
+constexpr int kPanelNW = 16;  // 32 columns per wave in the panel phase
+__host__ __device__ inline void panel_wgs(int64_t D, int k0, int bs, int *n_rowwg, int *n_colwg) {
+    const int pcw = 2 * kPanelNW;
+    const int64_t nchunk_p = (D + pcw - 1) / pcw;
+    const int kpc = (k0 + bs + pcw - 1) / pcw - k0 / pcw;
+    *n_rowwg = (int)((nchunk_p - kpc + 1) / 2);
+    const int64_t nrch = (D + 63) / 64;
+    const int kr = (k0 + bs + 63) / 64 - k0 / 64;
+    *n_colwg = (int)(nrch - kr);
+}
+
+// Phase 2 of a blocked closure round, one workgroup (id bid).  Workgroups
+// [0, n_rowwg) take the row panel: two 64-row halves of
+// the pivot rows times two 32-column chunks (the chunks outside the pivot
+// block, two per workgroup).  The rest take the column panel: one 64-row chunk
+// outside the pivot block times the four 32-column chunks of the pivot block.
+// Every panel tile is read and written by one workgroup only, and a barrier
+// separates its reads from its writes.
+template <bool S8>
+__device__ __forceinline__ void fw_panels_wg(uint16_t *T, int64_t ld, int D, int k0, int bs,
+                                             int n_rowwg, int bid) {
+    constexpr int NW = kPanelNW, CW = 2 * NW;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+    if (bid < n_rowwg) {
+        const int kc0 = k0 / CW, kc1 = (k0 + bs + CW - 1) / CW;
+        const int cc = 2 * bid + (wave >> 1);
+        const int c = cc < kc0 ? cc : cc + (kc1 - kc0);
+        const int64_t col0 = (int64_t)c * CW;
+        const int rofs = (wave & 1) * 64;
+        const int nrows = min(64, bs - rofs);
+        const int ncols = (int)min<int64_t>(CW, (int64_t)D - col0);
+        const int64_t r0 = (int64_t)k0 + rofs;
+        wave_tile<1, NW, S8>(T + r0 * ld + col0, ld, T + r0 * ld + k0, ld,
+                             T + (int64_t)k0 * ld + col0, ld, nrows, ncols, ld - col0, bs, true,
+                             true);
+    } else {
+        const int kr0 = k0 / 64, kr1 = (k0 + bs + 63) / 64;
+        const int rc = bid - n_rowwg;
+        const int rchunk = rc < kr0 ? rc : rc + (kr1 - kr0);
+        const int64_t row0 = (int64_t)rchunk * 64;
+        const int nrows = (int)min<int64_t>(64, (int64_t)D - row0);
+        const int cofs = wave * CW;
+        const int ncols = min(CW, bs - cofs);
+        wave_tile<1, NW, S8>(T + row0 * ld + k0 + cofs, ld, T + row0 * ld + k0, ld,
+                             T + (int64_t)k0 * ld + k0 + cofs, ld, nrows, ncols,
+                             ld - k0 - cofs, bs, true, true);
+    }
+}
+
+// Phase 3 over a rectangle of tiles: row chunks (64*TM rows) [r_lo, r_hi)
+// minus [r_ex0, r_ex1), column chunks (2NW columns) [c_lo, c_hi) minus
+// [c_ex0, c_ex1); T_ij (+)= T_iK * T_Kj for pivot block K = [k0, k0 + bs).
+// Workgroup (bx, by) of a grid with one column per selected column chunk and
+// ceil(rows / 4) rows; the four waves of a workgroup share the column chunk.
+struct Rect {
+    int r_lo, r_hi, r_ex0, r_ex1, c_lo, c_hi, c_ex0, c_ex1;
+};
+
+// FULL: every selected column chunk has all 2NW columns inside D (the
+// launcher sends a partial last chunk to a FULL = false launch).
+// One wave's tile: selected column chunk csel, selected row chunk rsel
+// (wave-uniform).  Out-of-range indices do nothing.
+template <int TM, int NW, bool S8, bool FULL>
+__device__ __forceinline__ void fw_update_wave(uint16_t *T, int64_t ld, int D, int k0, int bs,
+                                               const Rect &q, int csel, int rsel) {
+    constexpr int CW = 2 * NW, RW = 64 * TM;
+    int c = q.c_lo + csel;
+    if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
+    int rc = q.r_lo + rsel;
+    if (rc >= q.r_ex0) rc += q.r_ex1 - q.r_ex0;
+    if (rc >= q.r_hi || c >= q.c_hi) return;
+    const int64_t row0 = (int64_t)rc * RW, col0 = (int64_t)c * CW;
+    const int nrows = (int)min<int64_t>(RW, (int64_t)D - row0);
+    if (FULL) {
+        wave_tile_body<TM, NW, S8, true>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld,
+                                         T + (int64_t)k0 * ld + col0, ld, nrows, CW, bs, true,
+                                         false);
+    } else {
+        const int ncols = (int)min<int64_t>(CW, (int64_t)D - col0);
+        wave_tile<TM, NW, S8>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld,
+                              T + (int64_t)k0 * ld + col0, ld, nrows, ncols, ld - col0, bs, true,
+                              false);
+    }
+}
+
+template <int TM, int NW, bool S8, bool FULL>
+__device__ __forceinline__ void fw_update_wg(uint16_t *T, int64_t ld, int D, int k0, int bs,
+                                             const Rect &q, int bx, int by) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+    fw_update_wave<TM, NW, S8, FULL>(T, ld, D, k0, bs, q, bx, by * 4 + wave);
+}
+
 }  // namespace dev
 }  // namespace sr

@@ -350,3 +350,24 @@ def test_closure_batched_matches_solo():
     torch.cuda.synchronize()
     for x, y in zip(a, b):
         assert np.array_equal(host(x), host(y))
+
+
+@pytest.mark.parametrize("kind", AD_KINDS)
+def test_closure_batched_ragged_rounds(kind):
+    """Graphs with different round counts, ragged last blocks (1025, 130, 257)
+    and an empty graph (D = 0) in one batch."""
+    gen = synthgen.generator(5100 + kind)
+    sizes = [130, 7, 1025, 1, 257, 256, 129, 3]
+    mats = []
+    for n in sizes:
+        rows, cols = synthgen.bernoulli_edges(n, float(gen.uniform(0.005, 0.05)), gen)
+        w = gen.integers(1, 201, size=len(rows))
+        mats.append(synthgen.encode_antidist(n, rows, cols, w, np_dtype(kind)))
+    devs = [dev(kind, m) for m in mats]
+    spare = dev(kind, mats[3])  # a 1 x 1 matrix passed with D = 0: left as it is
+    before = host(spare).copy()
+    sr.closure_batched(kind, devs + [spare], Ds=sizes + [0])
+    torch.cuda.synchronize()
+    for m, d in zip(mats, devs):
+        assert np.array_equal(host(d).astype(np.int64), oracle.ad_closure(m, S_OF[kind])), m.shape
+    assert np.array_equal(host(spare), before)
