@@ -174,7 +174,16 @@ def closure(kind, T, D=None, flags=0, stream=None):
 
 
 def closure_batched(kind, Ts, Ds=None, flags=0, stream=None):
-    """In-place closures of every matrix in the list Ts (one launch)."""
+    """In-place closures of every matrix of a batch (one call): Ts is a list
+    of square matrix tensors, or a BatchArena (whose argument arrays are
+    built once, so a call costs no per-matrix Python work)."""
+    if isinstance(Ts, BatchArena):
+        if Ds is not None:
+            raise ValueError("a BatchArena carries its own sizes")
+        a = Ts
+        _check(lib().closure_batched(kind, a._ptrs_c, a._lds_c, a._dims_c, a.count, flags,
+                                     _stream(stream)))
+        return
     n = len(Ts)
     ptrs = (ctypes.c_void_p * n)()
     lds = (ctypes.c_int64 * n)()
@@ -185,6 +194,78 @@ def closure_batched(kind, Ts, Ds=None, flags=0, stream=None):
         lds[i] = ld
         dims[i] = r if Ds is None else Ds[i]
     _check(lib().closure_batched(kind, ptrs, lds, dims, n, flags, _stream(stream)))
+
+
+class BatchArena:
+    """A batch of square anti-distance matrices back to back in one device
+    buffer: matrix i (sizes[i] vertices) starts at a 256-byte aligned offset
+    and has a row stride of padded_ld(sizes[i]).  The pointer, stride and size
+    arrays that closure_batched passes to the C ABI are built once here, with
+    numpy, so repeated calls on the same batch do no per-matrix marshalling.
+    The arena owns its buffer (``self.buf``, a flat uint8 tensor): the
+    pointers stay valid while the arena is alive."""
+
+    def __init__(self, kind, sizes, device="cuda", zero=True):
+        import numpy as np
+        torch = _torch()
+        if kind not in (SR_ANTIDIST_U8, SR_ANTIDIST_U16):
+            raise ValueError("BatchArena holds anti-distance matrices")
+        self.kind = kind
+        self.es = 1 if kind == SR_ANTIDIST_U8 else 2
+        self.dtype = torch.uint8 if kind == SR_ANTIDIST_U8 else torch.uint16
+        self.sizes = np.asarray(sizes, dtype=np.int64).reshape(-1)
+        if (self.sizes < 0).any():
+            raise ValueError("negative matrix size")
+        self.count = int(self.sizes.size)
+        per = 128 // self.es
+        self.lds = np.maximum(per, -(-self.sizes // per) * per).astype(np.int64)
+        nbytes = -(-(self.sizes * self.lds * self.es) // 256) * 256
+        self.offsets = np.zeros(self.count, dtype=np.int64)
+        if self.count > 1:
+            self.offsets[1:] = np.cumsum(nbytes)[:-1]
+        total = int(nbytes.sum()) if self.count else 0
+        self.buf = (torch.zeros if zero else torch.empty)(max(total, 256), dtype=torch.uint8,
+                                                           device=device)
+        self._ptrs = (self.buf.data_ptr() + self.offsets).astype(np.int64)
+        self._dims = self.sizes.copy()
+        self._ptrs_c = self._ptrs.ctypes.data_as(ctypes.POINTER(ctypes.c_void_p))
+        self._lds_c = self.lds.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        self._dims_c = self._dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+    def __len__(self):
+        return self.count
+
+    def view(self, i):
+        """Matrix i as a sizes[i] x sizes[i] tensor view (row stride lds[i])."""
+        n, ld, off = int(self.sizes[i]), int(self.lds[i]), int(self.offsets[i])
+        flat = self.buf[off:off + n * ld * self.es].view(self.dtype)
+        return flat.view(n, ld)[:, :n]
+
+    def host_image(self, mats):
+        """The arena's bytes (numpy uint8) with the host matrices `mats` in
+        place, padding zero."""
+        import numpy as np
+        img = np.zeros(self.buf.numel(), dtype=np.uint8)
+        np_dt = np.uint8 if self.es == 1 else np.uint16
+        for i, m in enumerate(mats):
+            n, ld, off = int(self.sizes[i]), int(self.lds[i]), int(self.offsets[i])
+            if m.shape[0] != n or m.shape[1] < n:
+                raise ValueError("matrix %d has shape %s, expected %d x %d" % (i, m.shape, n, n))
+            dst = img[off:off + n * ld * self.es].view(np_dt).reshape(n, ld)
+            dst[:, :n] = m[:, :n]
+        return img
+
+    def load(self, mats):
+        """Copy host matrices into the arena (one host-to-device copy)."""
+        torch = _torch()
+        self.buf.copy_(torch.from_numpy(self.host_image(mats)))
+
+    def copy_(self, other):
+        """Copy another arena of the same layout (one device copy)."""
+        import numpy as np
+        if self.kind != other.kind or not np.array_equal(self.sizes, other.sizes):
+            raise ValueError("arena layouts differ")
+        self.buf.copy_(other.buf)
 
 
 def version():
@@ -283,5 +364,5 @@ __all__ = [
     "semiring_mul", "semiring_add", "closure", "closure_batched", "version", "shutdown",
     "sr_profile_enable", "sr_profile_read", "SR_PHASE_PIVOT", "SR_PHASE_PANELS",
     "SR_PHASE_UPDATE",
-    "padded_ld", "empty", "clone", "to_device", "to_host", "EXPORTS", "LIB_PATH",
+    "padded_ld", "empty", "clone", "to_device", "to_host", "BatchArena", "EXPORTS", "LIB_PATH",
 ]

@@ -8,6 +8,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <set>
@@ -271,11 +272,12 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
     std::vector<Span> spans;
     spans.reserve((size_t)count);
     for (int64_t g = 0; g < count; g++) {
-        char name[48];
-        snprintf(name, sizeof name, "T[%lld]", (long long)g);
         if (D[g] > 65536) return fail(SR_EINVAL, "closure_batched: D[%lld] too large", (long long)g);
-        const int rc = check_matrix(kind, name, T[g], ldt[g], D[g], D[g]);
-        if (rc != SR_OK) return rc;
+        if (check_matrix(kind, "T[g]", T[g], ldt[g], D[g], D[g]) != SR_OK) {
+            char name[48];  // formatted only on failure: the check again, naming g
+            snprintf(name, sizeof name, "T[%lld]", (long long)g);
+            return check_matrix(kind, name, T[g], ldt[g], D[g], D[g]);
+        }
         if (D[g] > 0) spans.push_back(span_of(kind, T[g], ldt[g], D[g]));
     }
     std::sort(spans.begin(), spans.end(), [](Span a, Span b) { return a.lo < b.lo; });
@@ -311,7 +313,9 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
         }
     }
     // descriptors and per-round work lists, then the uint16 working copies
-    const size_t plan_bytes = round_up((int64_t)sr::batch_plan_bytes(h.data(), count), 256);
+    std::unique_ptr<sr::BatchPlan, void (*)(sr::BatchPlan *)> plan(
+        sr::batch_plan_create(h.data(), count), sr::batch_plan_destroy);
+    const size_t plan_bytes = round_up((int64_t)sr::batch_plan_bytes(plan.get(), count), 256);
     void *w = nullptr;
     int rc = work_alloc(&w, plan_bytes + work_elems * 2, st);
     if (rc != SR_OK) return rc;
@@ -323,7 +327,7 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
             off += (size_t)d.D * (size_t)d.ld;
         }
     }
-    hipError_t e = sr::launch_ad_closure_batched(s8, h.data(), count, w, st);
+    hipError_t e = sr::launch_ad_closure_batched(s8, plan.get(), h.data(), count, w, st);
     work_free(w, st);
     if (e != hipSuccess) return device_fail(e, "closure_batched launch");
     return ok();

@@ -93,9 +93,9 @@ k_batch_panels(const BatchDesc *desc, const Item *items, int n_items, int kb) {
 }
 
 // Phase 3: one 64 x 32 tile per wave.  The waves of all graphs are numbered
-// back to back (a graph's tiles row-chunk major), so a workgroup's four waves
-// may belong to different graphs; no wave of the launch idles except in the
-// last workgroup.
+// back to back (a graph's tiles column-chunk major), so a workgroup's four
+// waves may belong to different graphs; no wave of the launch idles except in
+// the last workgroup.
 template <bool S8>
 __global__ void __launch_bounds__(256)
 k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, int n_waves) {
@@ -107,7 +107,10 @@ k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, in
     int nc = 0, nr = 0;
     const Rect q = update_rect(d.D, kb, &nc, &nr);
     const int local = gw - items[i].first;
-    const int csel = local % nc, rsel = local / nc;
+    // column-chunk major: consecutive waves (most often the four waves of a
+    // workgroup) share a column chunk, so its pivot-row segment B, read through
+    // the scalar cache, is fetched once for all of them
+    const int rsel = local % nr, csel = local / nr;
     int c = csel;
     if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
     if ((c + 1) * (2 * kUNW) <= d.D)
@@ -157,13 +160,16 @@ struct Launch {
     int n_units;     // update: wave tiles
 };
 
-struct HostPlan {
+}  // namespace
+
+struct BatchPlan {
     std::vector<Item> items;
     std::vector<Launch> pivot, panels, update;  // per round
 };
 
-HostPlan build_plan(const BatchDesc *hd, int64_t count) {
-    HostPlan p;
+namespace {
+
+void build_plan(BatchPlan &p, const BatchDesc *hd, int64_t count) {
     int max_rounds = 0;
     for (int64_t g = 0; g < count; g++) max_rounds = std::max(max_rounds, rounds_of(hd[g].D));
     for (int kb = 0; kb < max_rounds; kb++) {
@@ -205,25 +211,34 @@ HostPlan build_plan(const BatchDesc *hd, int64_t count) {
         lu.n_wg = (lu.n_units + 3) / 4;
         p.update.push_back(lu);
     }
-    return p;
+}
+
+size_t desc_bytes_of(int64_t count) {
+    return ((size_t)count * sizeof(BatchDesc) + 255) / 256 * 256;
 }
 
 }  // namespace
 
-size_t batch_plan_bytes(const BatchDesc *host_desc, int64_t count) {
-    const HostPlan p = build_plan(host_desc, count);
-    const size_t desc_bytes = ((size_t)count * sizeof(BatchDesc) + 255) / 256 * 256;
-    return desc_bytes + p.items.size() * sizeof(Item);
+BatchPlan *batch_plan_create(const BatchDesc *host_desc, int64_t count) {
+    auto *p = new BatchPlan;
+    build_plan(*p, host_desc, count);
+    return p;
 }
 
-hipError_t launch_ad_closure_batched(bool s8, const BatchDesc *host_desc, int64_t count,
-                                     void *dev_buf, hipStream_t st) {
+void batch_plan_destroy(BatchPlan *plan) { delete plan; }
+
+size_t batch_plan_bytes(const BatchPlan *plan, int64_t count) {
+    return desc_bytes_of(count) + plan->items.size() * sizeof(Item);
+}
+
+hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const BatchDesc *host_desc,
+                                     int64_t count, void *dev_buf, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    const HostPlan p = build_plan(host_desc, count);
-    const size_t desc_bytes = ((size_t)count * sizeof(BatchDesc) + 255) / 256 * 256;
+    const BatchPlan &p = *plan;
+    const size_t desc_bytes = desc_bytes_of(count);
     // host image of the descriptors and item lists; freed by a stream
     // callback once the upload has executed
-    auto *img = new std::vector<char>(desc_bytes + p.items.size() * sizeof(Item));
+    auto *img = new std::vector<char>(batch_plan_bytes(plan, count));
     std::copy_n(reinterpret_cast<const char *>(host_desc), (size_t)count * sizeof(BatchDesc),
                 img->data());
     std::copy_n(reinterpret_cast<const char *>(p.items.data()), p.items.size() * sizeof(Item),

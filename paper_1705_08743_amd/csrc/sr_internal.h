@@ -56,9 +56,9 @@ hipError_t launch_add(int elem_bytes, void *C, int64_t ldc, const void *A, int64
                       const void *B, int64_t ldb, int64_t R, int64_t N, hipStream_t stream);
 
 // Batched anti-distance closure.  `host_desc` holds `count` descriptors,
-// already ordered largest-first; the launcher uploads them with its per-round
-// work lists into `dev_buf` (batch_plan_bytes() bytes, 256-byte aligned,
-// owned by the caller and alive until the work has run).
+// already ordered largest-first; the launcher uploads them with the plan's
+// per-round work lists into `dev_buf` (batch_plan_bytes() bytes, 256-byte
+// aligned, owned by the caller and alive until the work has run).
 struct BatchDesc {
     uint16_t *T;    // matrix in uint16 storage (the caller's, or a working copy)
     int64_t ld;     // row stride of T, elements (multiple of 8)
@@ -67,9 +67,13 @@ struct BatchDesc {
     int32_t D;      // vertices
     int32_t pad;
 };
-size_t batch_plan_bytes(const BatchDesc *host_desc, int64_t count);
-hipError_t launch_ad_closure_batched(bool s8, const BatchDesc *host_desc, int64_t count,
-                                     void *dev_buf, hipStream_t stream);
+// Host-side per-round work lists of a batch (they depend on the sizes only).
+struct BatchPlan;
+BatchPlan *batch_plan_create(const BatchDesc *host_desc, int64_t count);
+void batch_plan_destroy(BatchPlan *plan);
+size_t batch_plan_bytes(const BatchPlan *plan, int64_t count);
+hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const BatchDesc *host_desc,
+                                     int64_t count, void *dev_buf, hipStream_t stream);
 
 // Second stream of a closure (sr_runtime.cpp), one per (device, caller
 // stream), created on first use at default priority.  aux_acquire() returns it

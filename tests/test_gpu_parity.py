@@ -371,3 +371,22 @@ def test_closure_batched_ragged_rounds(kind):
     for m, d in zip(mats, devs):
         assert np.array_equal(host(d).astype(np.int64), oracle.ad_closure(m, S_OF[kind])), m.shape
     assert np.array_equal(host(spare), before)
+
+
+@pytest.mark.parametrize("kind", AD_KINDS)
+def test_closure_batched_arena(kind):
+    """A batch held in one BatchArena: same bits as the list form, and the
+    oracle on a sample."""
+    batch = synthgen.cfg_batch(count=50, nlo=1, nhi=600, seed=91 + kind)
+    mats = [synthgen.encode_antidist(n, r, c, w, np_dtype(kind)) for n, r, c, w in batch]
+    arena = sr.BatchArena(kind, [m.shape[0] for m in mats])
+    arena.load(mats)
+    devs = [dev(kind, m) for m in mats]
+    sr.closure_batched(kind, arena)
+    sr.closure_batched(kind, devs)
+    torch.cuda.synchronize()
+    for i, d in enumerate(devs):
+        assert torch.equal(arena.view(i), d), i
+    for i in (0, 7, 23, 49):
+        want = oracle.ad_closure(mats[i], S_OF[kind])
+        assert np.array_equal(host(arena.view(i)).astype(np.int64), want), mats[i].shape
