@@ -66,7 +66,9 @@ k_ad_mul(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_
 }
 
 template <bool S8>
-__global__ void __launch_bounds__(256) k_ad_fw_pivot(uint16_t *T, int64_t ld, int64_t k0, int bs) {
+__global__ void __launch_bounds__(256)
+k_ad_fw_pivot(uint16_t *T, int64_t ld, int64_t k0, int bs, int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
     __shared__ uint32_t lds_row[2 * 64];
     __shared__ uint32_t lds_col[2 * 128];
     tile_closure<S8>(T + k0 * ld + k0, ld, bs, lds_row, lds_col);
@@ -75,7 +77,8 @@ __global__ void __launch_bounds__(256) k_ad_fw_pivot(uint16_t *T, int64_t ld, in
 // Phase 2 (the workgroup body is fw_panels_wg in sr_tiles.h).
 template <bool S8>
 __global__ void __launch_bounds__(256)
-k_ad_fw_panels(uint16_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg) {
+k_ad_fw_panels(uint16_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg, int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
     fw_panels_wg<S8>(T, ld, D, k0, bs, n_rowwg, (int)blockIdx.x);
 }
 
@@ -84,7 +87,8 @@ k_ad_fw_panels(uint16_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg) {
 // launcher sends a partial last chunk to a FULL = false launch).
 template <int TM, int NW, bool S8, bool FULL>
 __global__ void __launch_bounds__(256)
-k_ad_fw_update(uint16_t *T, int64_t ld, int D, int k0, int bs, Rect q) {
+k_ad_fw_update(uint16_t *T, int64_t ld, int D, int k0, int bs, Rect q, int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
     fw_update_wg<TM, NW, S8, FULL>(T, ld, D, k0, bs, q, (int)blockIdx.x, (int)blockIdx.y);
 }
 
@@ -224,6 +228,7 @@ bool tile_supported(int tm, int nw) {
 struct Overrides {
     int tm = 0, nw = 0;
     bool lookahead = true;
+    bool prio = true;  // raise the wave priority of the critical-path kernels
     Overrides() {
         if (const char *t = getenv("SR_AD_TILE")) {
             int a = 0, b = 0;
@@ -233,6 +238,7 @@ struct Overrides {
             }
         }
         if (const char *l = getenv("SR_LOOKAHEAD")) lookahead = atoi(l) != 0;
+        if (const char *v = getenv("SR_PRIO")) prio = atoi(v) != 0;
     }
 };
 
@@ -278,12 +284,12 @@ void block_chunks(int64_t D, int64_t kb, int w, int *lo, int *hi) {
 
 template <int TM, int NW, bool S8, bool FULL>
 hipError_t update_launch(uint16_t *T, int64_t ld, int64_t D, int k0, int bs, const Rect &q,
-                         hipStream_t st) {
+                         int prio, hipStream_t st) {
     const int nr = (q.r_hi - q.r_lo) - (q.r_ex1 - q.r_ex0);
     const int nc = (q.c_hi - q.c_lo) - (q.c_ex1 - q.c_ex0);
     if (nr <= 0 || nc <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_ad_fw_update<TM, NW, S8, FULL>), dim3(nc, (nr + 3) / 4), dim3(256), 0,
-                       st, T, ld, (int)D, k0, bs, q);
+                       st, T, ld, (int)D, k0, bs, q, prio);
     return hipGetLastError();
 }
 
@@ -291,7 +297,7 @@ hipError_t update_launch(uint16_t *T, int64_t ld, int64_t D, int k0, int bs, con
 // chunk of the matrix (D not a multiple of 2NW), if selected, goes to the
 // edge kernel as 16-column tiles of 64 rows.
 template <int TM, int NW, bool S8>
-hipError_t update_rect_t(uint16_t *T, int64_t ld, int64_t D, int k0, int bs, Rect q,
+hipError_t update_rect_t(uint16_t *T, int64_t ld, int64_t D, int k0, int bs, Rect q, int prio,
                          hipStream_t st) {
     constexpr int CW = 2 * NW;
     const int last = (int)((D + CW - 1) / CW) - 1;
@@ -303,7 +309,7 @@ hipError_t update_rect_t(uint16_t *T, int64_t ld, int64_t D, int k0, int bs, Rec
         q.c_ex0 = std::min(q.c_ex0, q.c_hi);
         q.c_ex1 = std::min(q.c_ex1, q.c_hi);
     }
-    hipError_t e = update_launch<TM, NW, S8, true>(T, ld, D, k0, bs, q, st);
+    hipError_t e = update_launch<TM, NW, S8, true>(T, ld, D, k0, bs, q, prio, st);
     if (e != hipSuccess || !has_partial) return e;
     Rect edge;
     const int r64 = (int)((D + 63) / 64);
@@ -314,12 +320,13 @@ hipError_t update_rect_t(uint16_t *T, int64_t ld, int64_t D, int k0, int bs, Rec
     edge.c_lo = last * CW / 16;
     edge.c_hi = (int)((D + 15) / 16);
     edge.c_ex0 = edge.c_ex1 = edge.c_hi;
-    return update_launch<1, 8, S8, false>(T, ld, D, k0, bs, edge, st);
+    return update_launch<1, 8, S8, false>(T, ld, D, k0, bs, edge, prio, st);
 }
 
 template <bool S8>
 hipError_t update_rect(const Plan &p, uint16_t *T, int64_t ld, int64_t kb, Rect q,
-                       hipStream_t st, double units) {
+                       hipStream_t st, double units, bool critical = false) {
+    const int prio = critical && overrides().prio ? 1 : 0;
     // an empty exclusion is placed at the end of the range
     if (q.r_ex1 <= q.r_ex0) q.r_ex0 = q.r_ex1 = q.r_hi;
     if (q.c_ex1 <= q.c_ex0) q.c_ex0 = q.c_ex1 = q.c_hi;
@@ -328,12 +335,12 @@ hipError_t update_rect(const Plan &p, uint16_t *T, int64_t ld, int64_t kb, Rect 
     if (prof) prof_begin(st);
     hipError_t e;
     switch (p.tm * 100 + p.nw) {
-        case 232: e = update_rect_t<2, 32, S8>(T, ld, p.D, k0, bs, q, st); break;
-        case 216: e = update_rect_t<2, 16, S8>(T, ld, p.D, k0, bs, q, st); break;
-        case 208: e = update_rect_t<2, 8, S8>(T, ld, p.D, k0, bs, q, st); break;
-        case 132: e = update_rect_t<1, 32, S8>(T, ld, p.D, k0, bs, q, st); break;
-        case 116: e = update_rect_t<1, 16, S8>(T, ld, p.D, k0, bs, q, st); break;
-        default: e = update_rect_t<1, 8, S8>(T, ld, p.D, k0, bs, q, st); break;
+        case 232: e = update_rect_t<2, 32, S8>(T, ld, p.D, k0, bs, q, prio, st); break;
+        case 216: e = update_rect_t<2, 16, S8>(T, ld, p.D, k0, bs, q, prio, st); break;
+        case 208: e = update_rect_t<2, 8, S8>(T, ld, p.D, k0, bs, q, prio, st); break;
+        case 132: e = update_rect_t<1, 32, S8>(T, ld, p.D, k0, bs, q, prio, st); break;
+        case 116: e = update_rect_t<1, 16, S8>(T, ld, p.D, k0, bs, q, prio, st); break;
+        default: e = update_rect_t<1, 8, S8>(T, ld, p.D, k0, bs, q, prio, st); break;
     }
     if (prof) prof_end(st, 1, 2, units);
     return e;
@@ -344,7 +351,8 @@ hipError_t pivot_s(uint16_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t s
     const int k0 = block_k0(kb), bs = block_bs(D, kb);
     const bool prof = prof_on();
     if (prof) prof_begin(st);
-    hipLaunchKernelGGL((k_ad_fw_pivot<S8>), dim3(1), dim3(256), 0, st, T, ld, (int64_t)k0, bs);
+    hipLaunchKernelGGL((k_ad_fw_pivot<S8>), dim3(1), dim3(256), 0, st, T, ld, (int64_t)k0, bs,
+                       overrides().prio ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (prof) prof_end(st, 1, 0, (double)bs * bs * bs);
     return e;
@@ -360,7 +368,7 @@ hipError_t panels_s(uint16_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t 
     const bool prof = prof_on();
     if (prof) prof_begin(st);
     hipLaunchKernelGGL((k_ad_fw_panels<S8>), dim3(n), dim3(256), 0, st, T, ld, (int)D, k0, bs,
-                       n_rowwg);
+                       n_rowwg, overrides().prio ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (prof) prof_end(st, 1, 1, 2.0 * (double)(D - bs) * bs * bs);
     return e;
@@ -403,13 +411,16 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
                                 aux->stream, rest2 * rest2 * bs);
         if (e == hipSuccess) e = hipEventRecord(aux->ev_aux, aux->stream);
         // A(kb) on st: row block kb+1 (columns outside block kb), then column
-        // block kb+1 (rows outside blocks kb, kb+1)
+        // block kb+1 (rows outside blocks kb, kb+1).  A(kb), pivot(kb+1) and
+        // panels(kb+1) are the critical path: their waves run at a raised
+        // priority, so that the SIMDs they share with B(kb) issue their
+        // instructions first.
         if (e == hipSuccess)
             e = update_rect<S8>(p, T, ld, kb, Rect{rl1, rh1, rh1, rh1, 0, p.ncc, cl, ch}, st,
-                                bs1 * ((double)D - bs) * bs);
+                                bs1 * ((double)D - bs) * bs, true);
         if (e == hipSuccess)
             e = update_rect<S8>(p, T, ld, kb, Rect{0, p.nrc, rl, rh1, cl1, ch1, ch1, ch1}, st,
-                                rest2 * bs1 * bs);
+                                rest2 * bs1 * bs, true);
         if (e == hipSuccess) e = pivot_s<S8>(T, ld, D, kb + 1, st);
         if (e == hipSuccess) e = panels_s<S8>(T, ld, D, kb + 1, st);
         // round kb+1's updates need B(kb)

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <stdlib.h>
+
 #include <algorithm>
 
 #include "sr_internal.h"
@@ -164,57 +166,183 @@ k_bool_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint3
                    K, accumulate != 0, false);
 }
 
-// Pivot tile closure: 256 threads, thread t holds row t of the tile as 8
-// words (256 bits).  Step k: the owner of row k publishes it in LDS (two
-// alternating buffers, one barrier per step); every row with bit k set ORs it
-// in.  Row k does not change during step k.  nwv: valid words of a tile row.
+// One 64-pivot phase of the pivot-tile closure (see k_bool_fw_pivot).  P is
+// the phase, so the words holding the phase's pivot bits are registers known
+// at compile time.
+template <int P>
+__device__ __forceinline__ void pivot_phase(uint32_t (&r)[8], int wave, int lane, int bs,
+                                            uint4 (*pub)[64][2]) {
+    const int kn = min(64, bs - 64 * P);
+    if (kn <= 0) return;  // bs is uniform over the workgroup
+    uint4 (*buf)[2] = pub[P & 1];
+    if (wave == P) {
+        // Warshall steps k in [64P, 64P + kn) on this wave's rows; row k is
+        // lane k - 64P's registers
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int n = min(32, kn - 32 * h);
+            for (int b = 0; b < n; b++) {
+                const int src = 32 * h + b;
+                const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(r[2 * P + h], b, 1);
+                uint32_t rk[8];
+#pragma unroll
+                for (int w = 0; w < 8; w++) rk[w] = __builtin_amdgcn_readlane(r[w], src);
+#pragma unroll
+                for (int w = 0; w < 8; w++) r[w] = __builtin_amdgcn_bitop3_b32(rk[w], m, r[w], 0xEA);
+            }
+        }
+        buf[lane][0] = uint4{r[0], r[1], r[2], r[3]};
+        buf[lane][1] = uint4{r[4], r[5], r[6], r[7]};
+    }
+    __syncthreads();
+    if (wave != P) {
+        // the published rows are closed over this phase's pivots, so each
+        // row k is applied once, in any order
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int n = min(32, kn - 32 * h);
+            const uint32_t a = r[2 * P + h];
+            for (int b = 0; b < n; b++) {
+                const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(a, b, 1);
+                const uint4 p0 = buf[32 * h + b][0], p1 = buf[32 * h + b][1];
+                r[0] = __builtin_amdgcn_bitop3_b32(p0.x, m, r[0], 0xEA);
+                r[1] = __builtin_amdgcn_bitop3_b32(p0.y, m, r[1], 0xEA);
+                r[2] = __builtin_amdgcn_bitop3_b32(p0.z, m, r[2], 0xEA);
+                r[3] = __builtin_amdgcn_bitop3_b32(p0.w, m, r[3], 0xEA);
+                r[4] = __builtin_amdgcn_bitop3_b32(p1.x, m, r[4], 0xEA);
+                r[5] = __builtin_amdgcn_bitop3_b32(p1.y, m, r[5], 0xEA);
+                r[6] = __builtin_amdgcn_bitop3_b32(p1.z, m, r[6], 0xEA);
+                r[7] = __builtin_amdgcn_bitop3_b32(p1.w, m, r[7], 0xEA);
+            }
+        }
+    }
+    // No second barrier: the next phase publishes into the other buffer, and
+    // the phase after it writes this one only after every wave has passed the
+    // next phase's barrier, i.e. has finished reading here.
+}
+
+// Pivot tile closure (bs <= 256): thread t holds row t of the tile as 8 words,
+// wave p rows [64p, 64p + 64).  Warshall's loop blocked by 64 pivots: in
+// phase P, wave P takes the steps k in [64P, 64P + 64) on its own rows over
+// all columns, reading row k from its own lanes (no barrier per step), which
+// closes block P and its row panel; it publishes its rows in LDS, and after
+// one barrier every other wave ORs row k into each of its rows with bit k
+// set.  nwv: valid words of a tile row.
 __global__ void __launch_bounds__(256)
-k_bool_fw_pivot(uint32_t *T, int64_t ld, int64_t k0, int bs, int nwv) {
-    __shared__ uint32_t buf[2 * 8];
+k_bool_fw_pivot(uint32_t *T, int64_t ld, int64_t k0, int bs, int nwv, int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
+    __shared__ uint4 pub[2][64][2];
     uint32_t *tile = T + k0 * ld + (k0 >> 5);
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform per wave
     const bool live = t < bs;
     uint32_t r[8];
 #pragma unroll
     for (int j = 0; j < 8; j++) r[j] = (live && j < nwv) ? tile[(int64_t)t * ld + j] : 0u;
-#pragma unroll
-    for (int w = 0; w < 8; w++) {
-        const int kb = 32 * w;
-        if (kb >= bs) break;
-        const int kn = min(32, bs - kb);
-        for (int b = 0; b < kn; b++) {
-            uint32_t *pb = buf + (b & 1) * 8;
-            if (t == kb + b) {
-                reinterpret_cast<uint4 *>(pb)[0] = uint4{r[0], r[1], r[2], r[3]};
-                reinterpret_cast<uint4 *>(pb)[1] = uint4{r[4], r[5], r[6], r[7]};
-            }
-            __syncthreads();
-            const uint4 p0 = reinterpret_cast<const uint4 *>(pb)[0];
-            const uint4 p1 = reinterpret_cast<const uint4 *>(pb)[1];
-            const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(r[w], b, 1);
-            r[0] |= p0.x & m;
-            r[1] |= p0.y & m;
-            r[2] |= p0.z & m;
-            r[3] |= p0.w & m;
-            r[4] |= p1.x & m;
-            r[5] |= p1.y & m;
-            r[6] |= p1.z & m;
-            r[7] |= p1.w & m;
-        }
-    }
+    pivot_phase<0>(r, wave, lane, bs, pub);
+    pivot_phase<1>(r, wave, lane, bs, pub);
+    pivot_phase<2>(r, wave, lane, bs, pub);
+    pivot_phase<3>(r, wave, lane, bs, pub);
     if (live)
 #pragma unroll
         for (int j = 0; j < 8; j++)
             if (j < nwv) tile[(int64_t)t * ld + j] = r[j];
 }
 
+// An 8-word-wide tile with its B block staged in LDS: all 256 threads of the
+// workgroup call this (it has a barrier); B (K <= 256 rows of 8 words, from
+// the workgroup-uniform pointer B) is the same for the four waves, and each
+// wave updates its own 64-row tile C (|)= A * B (nrows <= 0: nothing).  The B
+// block is copied before any wave stores, so C may overlap B (the row panel:
+// the closed pivot tile makes the result independent of that order).  nw <= 8
+// output words; bspan: words of each B row readable from B.
+__device__ __forceinline__ void bool_tile8_lds(uint32_t *C, int64_t ldc, const uint32_t *A,
+                                               int64_t lda, const uint32_t *B, int64_t ldb,
+                                               int nrows, int nw, int64_t bspan, int K,
+                                               uint4 (*lds)[2]) {
+    const int t = threadIdx.x;
+    if (t < K) {
+        const uint32_t *brow = B + (int64_t)t * ldb;
+        if (bspan >= 8) {
+            lds[t][0] = reinterpret_cast<const uint4 *>(brow)[0];
+            lds[t][1] = reinterpret_cast<const uint4 *>(brow)[1];
+        } else {
+            uint32_t v[8];
+#pragma unroll
+            for (int w = 0; w < 8; w++) v[w] = w < bspan ? brow[w] : 0u;
+            lds[t][0] = uint4{v[0], v[1], v[2], v[3]};
+            lds[t][1] = uint4{v[4], v[5], v[6], v[7]};
+        }
+    }
+    __syncthreads();
+    const int lane = t & 63;
+    if (nrows <= 0 || nw <= 0) return;
+    const bool live = lane < nrows;
+    const int64_t r = live ? lane : 0;
+    uint32_t *crow = C + r * ldc;
+    uint32_t acc[8];
+    if (nw == 8) {
+        const uint4 c0 = reinterpret_cast<const uint4 *>(crow)[0];
+        const uint4 c1 = reinterpret_cast<const uint4 *>(crow)[1];
+        acc[0] = c0.x, acc[1] = c0.y, acc[2] = c0.z, acc[3] = c0.w;
+        acc[4] = c1.x, acc[5] = c1.y, acc[6] = c1.z, acc[7] = c1.w;
+    } else {
+#pragma unroll
+        for (int w = 0; w < 8; w++) acc[w] = w < nw ? crow[w] : 0u;
+    }
+    const uint32_t *arow = A + r * lda;
+    for (int kw = 0; kw < K; kw += 32) {
+        const uint32_t a = arow[kw >> 5];
+        const int n = min(32, K - kw);
+        if (n == 32) {
+#pragma unroll
+            for (int b = 0; b < 32; b++) {
+                const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(a, b, 1);
+                const uint4 p0 = lds[kw + b][0], p1 = lds[kw + b][1];
+                acc[0] = __builtin_amdgcn_bitop3_b32(p0.x, m, acc[0], 0xEA);
+                acc[1] = __builtin_amdgcn_bitop3_b32(p0.y, m, acc[1], 0xEA);
+                acc[2] = __builtin_amdgcn_bitop3_b32(p0.z, m, acc[2], 0xEA);
+                acc[3] = __builtin_amdgcn_bitop3_b32(p0.w, m, acc[3], 0xEA);
+                acc[4] = __builtin_amdgcn_bitop3_b32(p1.x, m, acc[4], 0xEA);
+                acc[5] = __builtin_amdgcn_bitop3_b32(p1.y, m, acc[5], 0xEA);
+                acc[6] = __builtin_amdgcn_bitop3_b32(p1.z, m, acc[6], 0xEA);
+                acc[7] = __builtin_amdgcn_bitop3_b32(p1.w, m, acc[7], 0xEA);
+            }
+        } else {
+            for (int b = 0; b < n; b++) {
+                const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(a, b, 1);
+                const uint4 p0 = lds[kw + b][0], p1 = lds[kw + b][1];
+                acc[0] = __builtin_amdgcn_bitop3_b32(p0.x, m, acc[0], 0xEA);
+                acc[1] = __builtin_amdgcn_bitop3_b32(p0.y, m, acc[1], 0xEA);
+                acc[2] = __builtin_amdgcn_bitop3_b32(p0.z, m, acc[2], 0xEA);
+                acc[3] = __builtin_amdgcn_bitop3_b32(p0.w, m, acc[3], 0xEA);
+                acc[4] = __builtin_amdgcn_bitop3_b32(p1.x, m, acc[4], 0xEA);
+                acc[5] = __builtin_amdgcn_bitop3_b32(p1.y, m, acc[5], 0xEA);
+                acc[6] = __builtin_amdgcn_bitop3_b32(p1.z, m, acc[6], 0xEA);
+                acc[7] = __builtin_amdgcn_bitop3_b32(p1.w, m, acc[7], 0xEA);
+            }
+        }
+    }
+    if (!live) return;
+    if (nw == 8) {
+        reinterpret_cast<uint4 *>(crow)[0] = uint4{acc[0], acc[1], acc[2], acc[3]};
+        reinterpret_cast<uint4 *>(crow)[1] = uint4{acc[4], acc[5], acc[6], acc[7]};
+    } else {
+#pragma unroll
+        for (int w = 0; w < 8; w++)
+            if (w < nw) crow[w] = acc[w];
+    }
+}
+
 // Phase 2.  Workgroups [0, n_rowwg): the 256 pivot rows (4 waves x 64) times
-// one 8-word (256-column) chunk outside the pivot block; reads of the chunk
-// precede its writes (barrier).  The rest: column panel, each wave 64 rows
-// outside the pivot block times the 8 pivot words; a lane reads and writes
-// only its own row.
+// one 8-word (256-column) chunk outside the pivot block.  The rest: column
+// panel, each wave 64 rows outside the pivot block times the 8 pivot words.
+// Either way the workgroup's four waves share one B block (the chunk's pivot
+// rows, or the pivot tile), staged in LDS.
 __global__ void __launch_bounds__(256)
-k_bool_fw_panels(uint32_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg) {
+k_bool_fw_panels(uint32_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg, int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
+    __shared__ uint4 lds[256][2];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
     const int64_t nwd = ((int64_t)D + 31) >> 5;
     const int kw0 = k0 >> 5;
@@ -225,36 +353,61 @@ k_bool_fw_panels(uint32_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg) {
         const int64_t w0 = c * 8;
         const int rofs = wave * 64;
         const int64_t r0 = (int64_t)k0 + rofs;
-        bool_tile<8>(T + r0 * ld + w0, ld, T + r0 * ld + kw0, ld, T + (int64_t)k0 * ld + w0, ld,
-                     min(64, bs - rofs), (int)min<int64_t>(8, nwd - w0), ld - w0, bs, true, true);
+        bool_tile8_lds(T + r0 * ld + w0, ld, T + r0 * ld + kw0, ld, T + (int64_t)k0 * ld + w0, ld,
+                       min(64, bs - rofs), (int)min<int64_t>(8, nwd - w0), ld - w0, bs, lds);
     } else {
         const int kr0 = k0 / 64, kr1 = (k0 + bs + 63) / 64;
         const int rc = ((int)blockIdx.x - n_rowwg) * 4 + wave;
         const int rchunk = rc < kr0 ? rc : rc + (kr1 - kr0);
         const int64_t row0 = (int64_t)rchunk * 64;
-        if (row0 >= D) return;
-        bool_tile<8>(T + row0 * ld + kw0, ld, T + row0 * ld + kw0, ld,
-                     T + (int64_t)k0 * ld + kw0, ld, (int)min<int64_t>(64, (int64_t)D - row0), kpw,
-                     ld - kw0, bs, true, false);
+        const int nrows = (int)min<int64_t>(64, (int64_t)D - row0);  // <= 0 past the end
+        bool_tile8_lds(T + row0 * ld + kw0, ld, T + row0 * ld + kw0, ld,
+                       T + (int64_t)k0 * ld + kw0, ld, nrows, kpw, ld - kw0, bs, lds);
     }
 }
 
-// Phase 3.  Rows outside the pivot block, all column words in chunks of NWB.
-// A chunk may contain pivot columns: there the update recomputes
-// T_iK (|)= T_iK * T_KK, which phase 2 already applied and which cannot
-// change T_iK again (T_KK is closed), so the same bits are written back.
+// Phase 3 over a rectangle: 64-row chunks [r_lo, r_hi) minus [r_ex0, r_ex1),
+// times the 32-bit words [w0a, w0b) and [w1a, w1b), each word range cut into
+// chunks of NWB words (the last one may be partial); T_ij (|)= T_iK * T_Kj for
+// the pivot block K = [k0, k0 + bs).  Workgroups [0, nch0) take chunks of the
+// first word range; each of a workgroup's four waves takes one row chunk.
+struct BRect {
+    int r_lo, r_hi, r_ex0, r_ex1;
+    int w0a, w0b, w1a, w1b;
+};
+
 template <int NWB>
-__global__ void __launch_bounds__(256) k_bool_fw_update(uint32_t *T, int64_t ld, int D, int k0, int bs) {
+__global__ void __launch_bounds__(256)
+k_bool_fw_update(uint32_t *T, int64_t ld, int D, int k0, int bs, BRect q, int nch0, int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
-    const int64_t nwd = ((int64_t)D + 31) >> 5;
-    const int kr0 = k0 / 64, kr1 = (k0 + bs + 63) / 64;
-    const int rc = (int)blockIdx.y * 4 + wave;
-    const int rchunk = rc < kr0 ? rc : rc + (kr1 - kr0);
-    const int64_t row0 = (int64_t)rchunk * 64, w0 = (int64_t)blockIdx.x * NWB;
-    if (row0 >= D) return;
-    bool_tile<NWB>(T + row0 * ld + w0, ld, T + row0 * ld + (k0 >> 5), ld, T + (int64_t)k0 * ld + w0,
-                   ld, (int)min<int64_t>(64, (int64_t)D - row0), (int)min<int64_t>(NWB, nwd - w0),
-                   ld - w0, bs, true, false);
+    int rc = q.r_lo + (int)blockIdx.y * 4 + wave;
+    if (rc >= q.r_ex0) rc += q.r_ex1 - q.r_ex0;
+    const int cx = (int)blockIdx.x;
+    const int w0 = cx < nch0 ? q.w0a + cx * NWB : q.w1a + (cx - nch0) * NWB;
+    const int wend = cx < nch0 ? q.w0b : q.w1b;
+    const int64_t row0 = (int64_t)rc * 64;
+    const int nrows = rc < q.r_hi ? (int)min<int64_t>(64, (int64_t)D - row0) : 0;
+    const int nw = min(NWB, wend - w0);
+    uint32_t *C = T + row0 * ld + w0;
+    const uint32_t *A = T + row0 * ld + (k0 >> 5), *B = T + (int64_t)k0 * ld + w0;
+    if constexpr (NWB == 8) {
+        // narrow chunks (the lookahead parts, small matrices): the four waves
+        // share the chunk's B block through LDS
+        __shared__ uint4 lds[256][2];
+        bool_tile8_lds(C, ld, A, ld, B, ld, nrows, nw, ld - w0, bs, lds);
+    } else {
+        if (nrows <= 0) return;
+        if (nw == NWB) {
+            bool_tile<NWB>(C, ld, A, ld, B, ld, nrows, NWB, ld - w0, bs, true, false);
+        } else {
+            // the partial chunk at the end of a word range, as 8-word tiles,
+            // so that its cost follows its width
+            for (int c = 0; c < nw; c += 8)
+                bool_tile<8>(C + c, ld, A, ld, B + c, ld, nrows, min(8, nw - c), ld - w0 - c, bs,
+                             true, false);
+        }
+    }
 }
 
 template <int NWB>
@@ -267,14 +420,86 @@ hipError_t mul_nwb(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, con
 }
 
 template <int NWB>
-hipError_t update_nwb(uint32_t *T, int64_t ld, int64_t D, int k0, int bs, hipStream_t st) {
+hipError_t update_nwb(uint32_t *T, int64_t ld, int D, int k0, int bs, const BRect &q, int prio,
+                      hipStream_t st) {
+    const int nch0 = q.w0b > q.w0a ? (q.w0b - q.w0a + NWB - 1) / NWB : 0;
+    const int nch1 = q.w1b > q.w1a ? (q.w1b - q.w1a + NWB - 1) / NWB : 0;
+    const int nrows = (q.r_hi - q.r_lo) - (q.r_ex1 - q.r_ex0);
+    const dim3 grid((unsigned)(nch0 + nch1), (unsigned)((nrows + 3) / 4));
+    if (grid.x == 0 || nrows <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_bool_fw_update<NWB>), grid, dim3(256), 0, st, T, ld, D, k0, bs, q, nch0,
+                       prio);
+    return hipGetLastError();
+}
+
+// Rows [lo, hi) of block kb in 64-row chunks, and its 32-bit words.
+struct BBlock {
+    int k0, bs, rl, rh, wl, wh;
+};
+
+BBlock bblock(int64_t D, int64_t kb) {
+    BBlock b;
+    b.k0 = (int)(kb * kBoolBlock);
+    b.bs = (int)std::min<int64_t>(kBoolBlock, D - b.k0);
+    b.rl = b.k0 / 64;
+    b.rh = (b.k0 + b.bs + 63) / 64;
+    b.wl = b.k0 / 32;
+    b.wh = (b.k0 + b.bs + 31) / 32;
+    return b;
+}
+
+// Wave priority of the critical-path kernels (pivot, panels and the
+// lookahead part of the update): raised, unless SR_PRIO=0 (for tuning).
+int crit_prio() {
+    static const int on = [] {
+        const char *v = getenv("SR_PRIO");
+        return v ? (atoi(v) != 0 ? 1 : 0) : 1;
+    }();
+    return on;
+}
+
+hipError_t pivot_b(uint32_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t st) {
+    const BBlock b = bblock(D, kb);
+    const int64_t nwd = (D + 31) / 32;
+    const int nwv = (int)std::min<int64_t>(8, nwd - b.wl);
+    const bool prof = prof_on();
+    if (prof) prof_begin(st);
+    hipLaunchKernelGGL(k_bool_fw_pivot, dim3(1), dim3(256), 0, st, T, ld, (int64_t)b.k0, b.bs, nwv,
+                       crit_prio());
+    hipError_t e = hipGetLastError();
+    if (prof) prof_end(st, 0, 0, (double)b.bs * b.bs * b.bs);
+    return e;
+}
+
+hipError_t panels_b(uint32_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t st) {
+    const BBlock b = bblock(D, kb);
     const int64_t nwd = (D + 31) / 32;
     const int64_t nrch = (D + 63) / 64;
-    const int kr = (k0 + bs + 63) / 64 - k0 / 64;
-    const dim3 grid((unsigned)((nwd + NWB - 1) / NWB), (unsigned)((nrch - kr + 3) / 4));
-    if (grid.x == 0 || grid.y == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_bool_fw_update<NWB>), grid, dim3(256), 0, st, T, ld, (int)D, k0, bs);
-    return hipGetLastError();
+    const int n_rowwg = (int)((nwd + 7) / 8 - 1);
+    const int n_colwg = (int)((nrch - (b.rh - b.rl) + 3) / 4);
+    const bool prof = prof_on();
+    if (prof) prof_begin(st);
+    hipLaunchKernelGGL(k_bool_fw_panels, dim3(n_rowwg + n_colwg), dim3(256), 0, st, T, ld, (int)D,
+                       b.k0, b.bs, n_rowwg, crit_prio());
+    hipError_t e = hipGetLastError();
+    if (prof) prof_end(st, 0, 1, 2.0 * ((double)D - b.bs) * b.bs * b.bs);
+    return e;
+}
+
+hipError_t update_b(uint32_t *T, int64_t ld, int64_t D, int64_t kb, const BRect &q, int nwb,
+                    double units, hipStream_t st, bool critical = false) {
+    const BBlock b = bblock(D, kb);
+    const int prio = critical ? crit_prio() : 0;
+    const bool prof = prof_on();
+    if (prof) prof_begin(st);
+    hipError_t e;
+    switch (nwb) {
+        case 32: e = update_nwb<32>(T, ld, (int)D, b.k0, b.bs, q, prio, st); break;
+        case 16: e = update_nwb<16>(T, ld, (int)D, b.k0, b.bs, q, prio, st); break;
+        default: e = update_nwb<8>(T, ld, (int)D, b.k0, b.bs, q, prio, st); break;
+    }
+    if (prof) prof_end(st, 0, 2, units);
+    return e;
 }
 
 }  // namespace
@@ -295,47 +520,74 @@ hipError_t launch_bool_mul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t 
     }
 }
 
+// Blocked Warshall with one round of lookahead, as for anti-distances: the
+// update of round kb is split into A(kb) -- row block kb+1 and column block
+// kb+1, which the pivot and panels of round kb+1 need -- on the caller's
+// stream, and B(kb) -- everything else -- on a second stream, where it
+// overlaps A(kb), pivot(kb+1) and panels(kb+1).  The writes of B(kb) and of
+// round kb+1's pivot and panels are disjoint, and B(kb) reads only row and
+// column block kb, which round kb+1 does not write.
+// Words per wave in the bulk update: wider tiles need fewer scalar loads per
+// update, narrower ones give more waves to hide their latency.  SR_BOOL_NWB
+// (8, 16 or 32) overrides the choice, for tuning.
+int bool_update_nwb(int64_t D) {
+    static const int forced = [] {
+        const char *v = getenv("SR_BOOL_NWB");
+        const int n = v ? atoi(v) : 0;
+        return (n == 8 || n == 16 || n == 32) ? n : 0;
+    }();
+    if (forced) return forced;
+    return D >= 8192 ? 32 : (D >= 2048 ? 16 : 8);
+}
+
 hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool serial,
                                hipStream_t st) {
-    (void)serial;
     uint32_t *T = reinterpret_cast<uint32_t *>(T64);
     const int64_t ld = 2 * ld64;
     const int64_t nb = (D + kBoolBlock - 1) / kBoolBlock;
-    const int64_t nwd = (D + 31) / 32;
-    const int64_t nrch = (D + 63) / 64;
-    const int nwb = D >= 8192 ? 32 : (D >= 2048 ? 16 : 8);
+    const int nwd = (int)((D + 31) / 32);
+    const int nrc = (int)((D + 63) / 64);
+    const int nwb = bool_update_nwb(D);
+    hipError_t e = pivot_b(T, ld, D, 0, st);
+    if (e != hipSuccess || nb == 1) return e;
+    if ((e = panels_b(T, ld, D, 0, st)) != hipSuccess) return e;
+    Aux *aux = (nb > 2 && !serial) ? aux_acquire(st) : nullptr;
     for (int64_t kb = 0; kb < nb; kb++) {
-        const int k0 = (int)(kb * kBoolBlock);
-        const int bs = (int)std::min<int64_t>(kBoolBlock, D - k0);
-        const int nwv = (int)std::min<int64_t>(8, nwd - k0 / 32);
-        const bool prof = prof_on();
-        const double dbs = bs, rest = (double)(D - bs);
-        if (prof) prof_begin(st);
-        hipLaunchKernelGGL(k_bool_fw_pivot, dim3(1), dim3(256), 0, st, T, ld, (int64_t)k0, bs, nwv);
-        hipError_t e = hipGetLastError();
-        if (prof) prof_end(st, 0, 0, dbs * dbs * dbs);
-        if (e != hipSuccess) return e;
-        if (nb == 1) break;
-        const int64_t nchunks = (nwd + 7) / 8;
-        const int n_rowwg = (int)(nchunks - 1);
-        const int kr = (k0 + bs + 63) / 64 - k0 / 64;
-        const int n_colwg = (int)((nrch - kr + 3) / 4);
-        if (prof) prof_begin(st);
-        hipLaunchKernelGGL(k_bool_fw_panels, dim3(n_rowwg + n_colwg), dim3(256), 0, st, T, ld,
-                           (int)D, k0, bs, n_rowwg);
-        e = hipGetLastError();
-        if (prof) prof_end(st, 0, 1, 2.0 * rest * dbs * dbs);
-        if (e != hipSuccess) return e;
-        if (prof) prof_begin(st);
-        switch (nwb) {
-            case 32: e = update_nwb<32>(T, ld, D, k0, bs, st); break;
-            case 16: e = update_nwb<16>(T, ld, D, k0, bs, st); break;
-            default: e = update_nwb<8>(T, ld, D, k0, bs, st); break;
+        const BBlock b = bblock(D, kb);
+        const double bs = b.bs;
+        if (kb + 1 == nb || !aux) {
+            const double rest = (double)D - bs;
+            e = update_b(T, ld, D, kb, BRect{0, nrc, b.rl, b.rh, 0, b.wl, b.wh, nwd}, nwb,
+                         rest * rest * bs, st);
+            if (e == hipSuccess && kb + 1 < nb) e = pivot_b(T, ld, D, kb + 1, st);
+            if (e == hipSuccess && kb + 1 < nb) e = panels_b(T, ld, D, kb + 1, st);
+            if (e != hipSuccess) break;
+            continue;
         }
-        if (prof) prof_end(st, 0, 2, rest * rest * dbs);
-        if (e != hipSuccess) return e;
+        const BBlock n = bblock(D, kb + 1);
+        const double bs1 = n.bs, rest2 = (double)D - bs - bs1;
+        // B(kb) on the second stream, after panels(kb)
+        e = hipEventRecord(aux->ev_main, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(aux->stream, aux->ev_main, 0);
+        if (e == hipSuccess)
+            e = update_b(T, ld, D, kb, BRect{0, nrc, b.rl, n.rh, 0, b.wl, n.wh, nwd}, nwb,
+                         rest2 * rest2 * bs, aux->stream);
+        if (e == hipSuccess) e = hipEventRecord(aux->ev_aux, aux->stream);
+        // A(kb): row block kb+1 (every word outside block kb), then column
+        // block kb+1 (rows outside blocks kb and kb+1)
+        if (e == hipSuccess)
+            e = update_b(T, ld, D, kb, BRect{n.rl, n.rh, n.rh, n.rh, 0, b.wl, b.wh, nwd}, 8,
+                         bs1 * ((double)D - bs) * bs, st, true);
+        if (e == hipSuccess)
+            e = update_b(T, ld, D, kb, BRect{0, nrc, b.rl, n.rh, n.wl, n.wh, n.wh, n.wh}, 8,
+                         rest2 * bs1 * bs, st, true);
+        if (e == hipSuccess) e = pivot_b(T, ld, D, kb + 1, st);
+        if (e == hipSuccess) e = panels_b(T, ld, D, kb + 1, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, aux->ev_aux, 0);
+        if (e != hipSuccess) break;
     }
-    return hipSuccess;
+    if (aux) aux_release(aux);
+    return e;
 }
 
 }  // namespace sr

@@ -277,6 +277,27 @@ def test_bool_closure(D):
     assert synthgen.padding_bits_clear(got, D)
 
 
+@pytest.mark.parametrize("D", [769, 2100, 4100])
+def test_bool_closure_lookahead_and_serial(D):
+    """Sizes with several lookahead rounds and each word-chunk width (8 and
+    16 words): the overlapped schedule and the serial one give the oracle's
+    bits."""
+    gen = synthgen.generator(3200 + D)
+    A = rand_bits(D, D, gen, 1.2 / D)
+    ldw = synthgen.aligned_ld_words(D)
+    Aw = synthgen.pack_bits(A, ldw)
+    T = dev(sr.SR_BOOL, Aw, cols=D)
+    T2 = sr.clone(T)
+    sr.closure(sr.SR_BOOL, T, D=D)
+    sr.closure(sr.SR_BOOL, T2, D=D, flags=sr.SR_SERIAL_PHASES)
+    want = oracle.bool_closure_words(Aw, D)
+    nw = (D + 63) // 64
+    got = host(T)
+    assert np.array_equal(got[:, :nw], want[:, :nw])
+    assert np.array_equal(host(T2)[:, :nw], want[:, :nw])
+    assert synthgen.padding_bits_clear(got, D)
+
+
 def test_bool_closure_matches_antidist_on_01():
     """Boolean closure = anti-distance closure of the {0, S} matrix / S."""
     gen = synthgen.generator(3002)
