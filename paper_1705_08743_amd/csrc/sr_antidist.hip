@@ -382,6 +382,11 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
     if (e != hipSuccess || nb == 1) return e;
     if ((e = panels_s<S8>(T, ld, D, 0, st)) != hipSuccess) return e;
 
+    // With a second stream, B(kb) -- the update outside row and column
+    // blocks kb+1 -- runs there, queued behind B(kb-1) as soon as panels(kb)
+    // is done, and the caller's stream waits for B(kb-1) only before A(kb),
+    // the rest of round kb's update.  So B(kb) follows B(kb-1) back to back
+    // while the chain A(kb) -> pivot(kb+1) -> panels(kb+1) runs beside it.
     Aux *aux = (nb > 2 && !serial && overrides().lookahead) ? aux_acquire(st) : nullptr;
     for (int kb = 0; kb < nb; kb++) {
         int rl, rh, cl, ch;
@@ -389,10 +394,12 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
         block_chunks(D, kb, p.cw, &cl, &ch);
         const double bs = block_bs(D, kb);
         if (kb + 1 == nb || !aux) {
-            // whole update of round kb, then the next pivot and panels
+            // whole update of round kb (after B(kb-1)), then the next pivot and panels
+            if (aux && kb > 0) e = hipStreamWaitEvent(st, aux->ev_aux[(kb - 1) & 1], 0);
             const double rest = (double)D - bs;
-            e = update_rect<S8>(p, T, ld, kb, Rect{0, p.nrc, rl, rh, 0, p.ncc, cl, ch}, st,
-                                rest * rest * bs);
+            if (e == hipSuccess)
+                e = update_rect<S8>(p, T, ld, kb, Rect{0, p.nrc, rl, rh, 0, p.ncc, cl, ch}, st,
+                                    rest * rest * bs);
             if (e == hipSuccess && kb + 1 < nb) e = pivot_s<S8>(T, ld, D, kb + 1, st);
             if (e == hipSuccess && kb + 1 < nb) e = panels_s<S8>(T, ld, D, kb + 1, st);
             if (e != hipSuccess) break;
@@ -409,7 +416,9 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
         if (e == hipSuccess)
             e = update_rect<S8>(p, T, ld, kb, Rect{0, p.nrc, rl, rh1, 0, p.ncc, cl, ch1},
                                 aux->stream, rest2 * rest2 * bs);
-        if (e == hipSuccess) e = hipEventRecord(aux->ev_aux, aux->stream);
+        if (e == hipSuccess) e = hipEventRecord(aux->ev_aux[kb & 1], aux->stream);
+        // A(kb) writes row block kb+1, which B(kb-1) writes too
+        if (e == hipSuccess && kb > 0) e = hipStreamWaitEvent(st, aux->ev_aux[(kb - 1) & 1], 0);
         // A(kb) on st: row block kb+1 (columns outside block kb), then column
         // block kb+1 (rows outside blocks kb, kb+1).  A(kb), pivot(kb+1) and
         // panels(kb+1) are the critical path: their waves run at a raised
@@ -423,8 +432,6 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
                                 rest2 * bs1 * bs, true);
         if (e == hipSuccess) e = pivot_s<S8>(T, ld, D, kb + 1, st);
         if (e == hipSuccess) e = panels_s<S8>(T, ld, D, kb + 1, st);
-        // round kb+1's updates need B(kb)
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, aux->ev_aux, 0);
         if (e != hipSuccess) break;
     }
     if (aux) aux_release(aux);

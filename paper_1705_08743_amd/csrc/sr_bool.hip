@@ -410,6 +410,105 @@ k_bool_fw_update(uint32_t *T, int64_t ld, int D, int k0, int bs, BRect q, int nc
     }
 }
 
+// The lookahead part of a round's update, A(kb) = rectangles qa (row block
+// kb+1) and qb (column block kb+1), in one launch with short waves: a
+// workgroup owns one 64-row x 8-word tile and its four waves split the inner
+// bits -- wave w takes pivots [64w, 64w + 64) -- so each wave runs a quarter
+// of the steps.  Each wave stages its 64 rows of B in LDS; the four partial
+// ORs are combined in LDS and OR-ed into C by one store per word.  Workgroups
+// [0, nwg_a) take tiles of qa; tile index t -> word chunk t % nch, row chunk
+// t / nch (with the rectangle's row exclusion).
+struct LaTile {
+    int rc, w0, nw;
+};
+
+__device__ __forceinline__ LaTile la_tile(const BRect &q, int t) {
+    const int nch0 = q.w0b > q.w0a ? (q.w0b - q.w0a + 7) / 8 : 0;
+    const int nch1 = q.w1b > q.w1a ? (q.w1b - q.w1a + 7) / 8 : 0;
+    const int nch = nch0 + nch1;
+    const int cx = t % nch;
+    int rc = q.r_lo + t / nch;
+    if (rc >= q.r_ex0) rc += q.r_ex1 - q.r_ex0;
+    LaTile r;
+    r.rc = rc;
+    r.w0 = cx < nch0 ? q.w0a + cx * 8 : q.w1a + (cx - nch0) * 8;
+    r.nw = min(8, (cx < nch0 ? q.w0b : q.w1b) - r.w0);
+    return r;
+}
+
+__host__ __device__ inline int la_tiles(const BRect &q) {
+    const int nch0 = q.w0b > q.w0a ? (q.w0b - q.w0a + 7) / 8 : 0;
+    const int nch1 = q.w1b > q.w1a ? (q.w1b - q.w1a + 7) / 8 : 0;
+    const int nrows = (q.r_hi - q.r_lo) - (q.r_ex1 - q.r_ex0);
+    return nrows > 0 ? (nch0 + nch1) * nrows : 0;
+}
+
+__global__ void __launch_bounds__(256)
+k_bool_fw_lookahead(uint32_t *T, int64_t ld, int D, int k0, int bs, BRect qa, BRect qb, int nwg_a,
+                    int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
+    __shared__ uint4 bl[256][2];       // B rows (pivot rows), 8 words each
+    __shared__ uint32_t red[4][8][64];  // partial ORs: wave, word, lane
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform per wave
+    const int bid = (int)blockIdx.x;
+    const LaTile tile = bid < nwg_a ? la_tile(qa, bid) : la_tile(qb, bid - nwg_a);
+    const int64_t row0 = (int64_t)tile.rc * 64;
+    const int nrows = (int)min<int64_t>(64, (int64_t)D - row0);
+    const int64_t bspan = ld - tile.w0;
+    // stage: thread t copies B row t (pivot row k0 + t), words [w0, w0 + 8)
+    if (t < bs) {
+        const uint32_t *brow = T + (int64_t)(k0 + t) * ld + tile.w0;
+        if (bspan >= 8) {
+            bl[t][0] = reinterpret_cast<const uint4 *>(brow)[0];
+            bl[t][1] = reinterpret_cast<const uint4 *>(brow)[1];
+        } else {
+            uint32_t v[8];
+#pragma unroll
+            for (int w = 0; w < 8; w++) v[w] = w < bspan ? brow[w] : 0u;
+            bl[t][0] = uint4{v[0], v[1], v[2], v[3]};
+            bl[t][1] = uint4{v[4], v[5], v[6], v[7]};
+        }
+    }
+    __syncthreads();
+    const bool live = lane < nrows;
+    const uint32_t *arow = T + (row0 + (live ? lane : 0)) * ld + (k0 >> 5) + 2 * wave;
+    const int kb0 = 64 * wave;
+    const int kn = min(64, bs - kb0);  // this wave's pivots (<= 0: none)
+    uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int n = min(32, kn - 32 * h);
+        if (n <= 0) break;
+        const uint32_t a = arow[h];
+        for (int b = 0; b < n; b++) {
+            const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(a, b, 1);
+            const uint4 p0 = bl[kb0 + 32 * h + b][0], p1 = bl[kb0 + 32 * h + b][1];
+            acc[0] = __builtin_amdgcn_bitop3_b32(p0.x, m, acc[0], 0xEA);
+            acc[1] = __builtin_amdgcn_bitop3_b32(p0.y, m, acc[1], 0xEA);
+            acc[2] = __builtin_amdgcn_bitop3_b32(p0.z, m, acc[2], 0xEA);
+            acc[3] = __builtin_amdgcn_bitop3_b32(p0.w, m, acc[3], 0xEA);
+            acc[4] = __builtin_amdgcn_bitop3_b32(p1.x, m, acc[4], 0xEA);
+            acc[5] = __builtin_amdgcn_bitop3_b32(p1.y, m, acc[5], 0xEA);
+            acc[6] = __builtin_amdgcn_bitop3_b32(p1.z, m, acc[6], 0xEA);
+            acc[7] = __builtin_amdgcn_bitop3_b32(p1.w, m, acc[7], 0xEA);
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < 8; w++) red[wave][w][lane] = acc[w];
+    __syncthreads();
+    // wave w ORs words 2w, 2w+1 of the four partials into C
+    if (!live) return;
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        const int w = 2 * wave + j;
+        if (w < tile.nw) {
+            uint32_t *c = T + (row0 + lane) * ld + tile.w0 + w;
+            *c = *c | red[0][w][lane] | red[1][w][lane] | red[2][w][lane] | red[3][w][lane];
+        }
+    }
+}
+
 template <int NWB>
 hipError_t mul_nwb(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
                    int64_t ldb, int64_t R, int64_t K, int64_t nwords, bool acc, hipStream_t st) {
@@ -526,7 +625,23 @@ hipError_t launch_bool_mul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t 
 // stream, and B(kb) -- everything else -- on a second stream, where it
 // overlaps A(kb), pivot(kb+1) and panels(kb+1).  The writes of B(kb) and of
 // round kb+1's pivot and panels are disjoint, and B(kb) reads only row and
-// column block kb, which round kb+1 does not write.
+// column block kb, which round kb+1 does not write.  B(kb) is queued behind
+// B(kb-1) as soon as panels(kb) is done; the caller's stream waits for
+// B(kb-1) only before A(kb), which writes rows B(kb-1) also writes.
+hipError_t lookahead_b(uint32_t *T, int64_t ld, int64_t D, int64_t kb, const BRect &qa,
+                       const BRect &qb, double units, hipStream_t st) {
+    const BBlock b = bblock(D, kb);
+    const int na = la_tiles(qa), nb = la_tiles(qb);
+    if (na + nb == 0) return hipSuccess;
+    const bool prof = prof_on();
+    if (prof) prof_begin(st);
+    hipLaunchKernelGGL(k_bool_fw_lookahead, dim3(na + nb), dim3(256), 0, st, T, ld, (int)D, b.k0,
+                       b.bs, qa, qb, na, crit_prio());
+    hipError_t e = hipGetLastError();
+    if (prof) prof_end(st, 0, 2, units);
+    return e;
+}
+
 // Words per wave in the bulk update: wider tiles need fewer scalar loads per
 // update, narrower ones give more waves to hide their latency.  SR_BOOL_NWB
 // (8, 16 or 32) overrides the choice, for tuning.
@@ -556,9 +671,11 @@ hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool seri
         const BBlock b = bblock(D, kb);
         const double bs = b.bs;
         if (kb + 1 == nb || !aux) {
+            if (aux && kb > 0) e = hipStreamWaitEvent(st, aux->ev_aux[(kb - 1) & 1], 0);
             const double rest = (double)D - bs;
-            e = update_b(T, ld, D, kb, BRect{0, nrc, b.rl, b.rh, 0, b.wl, b.wh, nwd}, nwb,
-                         rest * rest * bs, st);
+            if (e == hipSuccess)
+                e = update_b(T, ld, D, kb, BRect{0, nrc, b.rl, b.rh, 0, b.wl, b.wh, nwd}, nwb,
+                             rest * rest * bs, st);
             if (e == hipSuccess && kb + 1 < nb) e = pivot_b(T, ld, D, kb + 1, st);
             if (e == hipSuccess && kb + 1 < nb) e = panels_b(T, ld, D, kb + 1, st);
             if (e != hipSuccess) break;
@@ -566,24 +683,23 @@ hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool seri
         }
         const BBlock n = bblock(D, kb + 1);
         const double bs1 = n.bs, rest2 = (double)D - bs - bs1;
-        // B(kb) on the second stream, after panels(kb)
+        // B(kb) on the second stream, after panels(kb), behind B(kb-1)
         e = hipEventRecord(aux->ev_main, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(aux->stream, aux->ev_main, 0);
         if (e == hipSuccess)
             e = update_b(T, ld, D, kb, BRect{0, nrc, b.rl, n.rh, 0, b.wl, n.wh, nwd}, nwb,
                          rest2 * rest2 * bs, aux->stream);
-        if (e == hipSuccess) e = hipEventRecord(aux->ev_aux, aux->stream);
+        if (e == hipSuccess) e = hipEventRecord(aux->ev_aux[kb & 1], aux->stream);
+        // A(kb) writes row block kb+1, which B(kb-1) writes too
+        if (e == hipSuccess && kb > 0) e = hipStreamWaitEvent(st, aux->ev_aux[(kb - 1) & 1], 0);
         // A(kb): row block kb+1 (every word outside block kb), then column
         // block kb+1 (rows outside blocks kb and kb+1)
         if (e == hipSuccess)
-            e = update_b(T, ld, D, kb, BRect{n.rl, n.rh, n.rh, n.rh, 0, b.wl, b.wh, nwd}, 8,
-                         bs1 * ((double)D - bs) * bs, st, true);
-        if (e == hipSuccess)
-            e = update_b(T, ld, D, kb, BRect{0, nrc, b.rl, n.rh, n.wl, n.wh, n.wh, n.wh}, 8,
-                         rest2 * bs1 * bs, st, true);
+            e = lookahead_b(T, ld, D, kb, BRect{n.rl, n.rh, n.rh, n.rh, 0, b.wl, b.wh, nwd},
+                            BRect{0, nrc, b.rl, n.rh, n.wl, n.wh, n.wh, n.wh},
+                            bs1 * ((double)D - bs) * bs + rest2 * bs1 * bs, st);
         if (e == hipSuccess) e = pivot_b(T, ld, D, kb + 1, st);
         if (e == hipSuccess) e = panels_b(T, ld, D, kb + 1, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, aux->ev_aux, 0);
         if (e != hipSuccess) break;
     }
     if (aux) aux_release(aux);

@@ -82,7 +82,9 @@ hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const Batch
 struct Aux {
     hipStream_t stream;
     hipEvent_t ev_main;  // recorded on the caller's stream, waited on by `stream`
-    hipEvent_t ev_aux;   // recorded on `stream`, waited on by the caller's stream
+    hipEvent_t ev_aux[2];  // recorded on `stream`, waited on by the caller's stream
+                           // (two, so that one round's can be waited for after
+                           // the next round's has been recorded)
     int device;
     int slot;
 };

@@ -70,9 +70,13 @@ Aux *aux_acquire(hipStream_t caller) {
             if (g_aux_count == kMaxAux) return nullptr;  // table full: no lookahead
             Aux a{};
             // default priority: the two streams must not differ in priority
+            // The events only order the two streams of one device, so a
+            // device-scope release is enough (no system-scope cache flush).
+            const unsigned evf = hipEventDisableTiming | hipEventReleaseToDevice;
             if (hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&a.ev_main, hipEventDisableTiming) != hipSuccess ||
-                hipEventCreateWithFlags(&a.ev_aux, hipEventDisableTiming) != hipSuccess) {
+                hipEventCreateWithFlags(&a.ev_main, evf) != hipSuccess ||
+                hipEventCreateWithFlags(&a.ev_aux[0], evf) != hipSuccess ||
+                hipEventCreateWithFlags(&a.ev_aux[1], evf) != hipSuccess) {
                 (void)hipGetLastError();
                 return nullptr;
             }
