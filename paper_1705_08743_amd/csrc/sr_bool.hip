@@ -392,8 +392,8 @@ k_bool_fw_update(uint32_t *T, int64_t ld, int D, int k0, int bs, BRect q, int nc
     uint32_t *C = T + row0 * ld + w0;
     const uint32_t *A = T + row0 * ld + (k0 >> 5), *B = T + (int64_t)k0 * ld + w0;
     if constexpr (NWB == 8) {
-        // narrow chunks (the lookahead parts, small matrices): the four waves
-        // share the chunk's B block through LDS
+        // narrow chunks (small matrices): the four waves share the chunk's B
+        // block through LDS
         __shared__ uint4 lds[256][2];
         bool_tile8_lds(C, ld, A, ld, B, ld, nrows, nw, ld - w0, bs, lds);
     } else {
