@@ -38,25 +38,43 @@ PEAK_BOOL = 32 * VALU_LANE_OPS
 
 # HBM traffic of the update kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a streaming kernel of known size; valid only
-# for the kernel sources whose hash is recorded with it.
+# for the kernel sources whose hash is recorded with it (None until measured).
 TRAFFIC = {
-    # full update launch of the D = 8192 closure (serialized phases):
-    # (FETCH_SIZE 1.692e5 KiB x 2.000 + WRITE_SIZE 1.27e5 KiB x 1.000) per launch
-    "fw8192": {"src_hash": "3546ca2f6edffe41", "bytes_per_launch": 4.765e8},
+    # full update launch of the D = 8192 uint16 closure (serialized phases, 8064
+    # workgroups): FETCH_SIZE 1.692e5 KiB x 2.000 + WRITE_SIZE 1.270e5 KiB x 1.000
+    "fw8192": {"src_hash": "5dc0758f2f7c956b", "bytes_per_launch": 4.766e8},
+    "u8fw8192": {"src_hash": None, "bytes_per_launch": None},
+    # full update launches of the D = 16384 Boolean closure (serialized phases),
+    # launch-weighted mean of the 16- and 17-chunk shapes
+    "bool16384": {"src_hash": "319c0dad5dd06799", "bytes_per_launch": 1.109e8},
 }
-def src_hash():
-    """Hash of the update kernel's device source: the tile code (sr_tiles.h)
-    and the text of the k_ad_fw_update kernel template (host-side changes
-    elsewhere in sr_antidist.hip do not change the kernel)."""
+
+
+def src_hash(workload):
+    """Hash of the device source of the workload's update kernel: for
+    anti-distance the tile code (sr_tiles.h) and the text of the
+    k_ad_fw_update kernel template (host-side changes elsewhere in
+    sr_antidist.hip do not change the kernel); for Boolean sr_bool.hip."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1705_08743_amd/csrc/sr_tiles.h"), "rb") as f:
+    csrc = os.path.join(ROOT, "paper_1705_08743_amd/csrc")
+    if workload.startswith("bool"):
+        with open(os.path.join(csrc, "sr_bool.hip"), "rb") as f:
+            h.update(f.read())
+        return h.hexdigest()[:16]
+    with open(os.path.join(csrc, "sr_tiles.h"), "rb") as f:
         h.update(f.read())
-    with open(os.path.join(ROOT, "paper_1705_08743_amd/csrc/sr_antidist.hip")) as f:
+    with open(os.path.join(csrc, "sr_antidist.hip")) as f:
         text = f.read()
     start = text.index("k_ad_fw_update(uint16_t *T")
     end = text.index("\n}\n", start)
     h.update(text[start:end].encode())
     return h.hexdigest()[:16]
+
+
+def traffic_of(workload):
+    tr = TRAFFIC.get(workload, {})
+    ok = tr.get("src_hash") is not None and tr.get("src_hash") == src_hash(workload)
+    return tr.get("bytes_per_launch") if ok else None
 
 
 def log(*a):
@@ -154,8 +172,7 @@ def run_fw(args, torch, sr, kind, D, make_input, workload, S, metric):
         kind, t, flags=sr.SR_SERIAL_PHASES))
     up = phases["update"]
     achieved = up["updates_per_launch"] / (up["avg_us"] * 1e-6) if up["avg_us"] > 0 else 0.0
-    tr = TRAFFIC.get(workload, {})
-    traffic = tr.get("bytes_per_launch") if tr.get("src_hash") == src_hash() else None
+    traffic = traffic_of(workload)
     out = {
         "metric": metric,
         "value": float(D) ** 3 / (ms_step * 1e-3),
@@ -220,7 +237,7 @@ def run_bool(args, torch, sr, synthgen):
                       "parallelism": "single_gpu"},
            "roofline": {"bound": "alu", "kernel": "k_bool_fw_update (update phase)",
                         "achieved": achieved, "peak": PEAK_BOOL, "unit": "updates/s",
-                        "frac": achieved / PEAK_BOOL, "traffic": None},
+                        "frac": achieved / PEAK_BOOL, "traffic": traffic_of("bool16384")},
            "phases": phases}
     if not args.no_parity:
         rows = np.sort(np.random.default_rng(3).choice(D, size=args.parity_rows, replace=False))
