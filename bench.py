@@ -8,10 +8,12 @@ closure (all three phases of every round) of a fresh copy of the input that is
 already resident in HBM.  Metric: semiring updates per second, D^3 / t.
 
 Other workloads (--workload): bool16384 (Boolean closure, D = 16384, mean
-out-degree 3 plus planted strongly connected blocks), mul1024 (uint16 product
-of two 1024 x 1024 graphs), u8fw8192 (uint8 closure, distances in [1, 200]),
-batched (4096 graphs, log-uniform sizes in [32, 1024], uint16, one launch vs one
-at a time).
+out-degree 3 plus planted strongly connected blocks), boolmul16384 (Boolean
+product A * A of that matrix, word-parallel and int8 matrix-core paths),
+mul1024 (uint16 product of two 1024 x 1024 graphs), u8fw8192 (uint8 closure,
+distances in [1, 200]), batched (4096 graphs, log-uniform sizes in [32, 1024],
+uint16, one call vs one at a time), add8192 (entrywise max, HBM-bound), serve
+(continuously batched closure requests vs serial).
 
 Prints one JSON line.  The roofline object is for the dominant kernel (the
 update phase), timed live with hipEvents on its own stream; cpu_baseline is
@@ -35,6 +37,9 @@ if ROOT not in sys.path:
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 PEAK_ANTIDIST = VALU_LANE_OPS
 PEAK_BOOL = 32 * VALU_LANE_OPS
+# dense int8 matrix-core rate (MI355X datasheet: 5.0 POP/s = 2.5e15 MAC/s); one
+# MAC is one Boolean update on the SR_BOOL_MFMA path
+PEAK_I8_MAC = 2.5e15
 
 # HBM traffic of the update kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a streaming kernel of known size; valid only
@@ -275,6 +280,45 @@ def run_mul(args, torch, sr, synthgen):
     return out
 
 
+def run_boolmul(args, torch, sr, synthgen):
+    """Boolean product A * A of configuration 3 (D = 16384, bit-packed), on
+    the word-parallel OR kernels (value) and on the int8 matrix-core path
+    (SR_BOOL_MFMA, reported beside it); sampled rows against the oracle."""
+    import numpy as np
+    import oracle
+    D = 16384
+    W = synthgen.cfg_bool16384(D=D)
+    A = sr.to_device(sr.SR_BOOL, W, cols=D)
+    C1 = sr.empty(sr.SR_BOOL, D, D)
+    C2 = sr.empty(sr.SR_BOOL, D, D)
+    fb = lambda i: sr.semiring_mul(sr.SR_BOOL, C1, A, A, K=D, N=D)
+    fm = lambda i: sr.semiring_mul(sr.SR_BOOL, C2, A, A, K=D, N=D, flags=sr.SR_BOOL_MFMA)
+    for _ in range(max(1, args.warmup)):
+        fb(0)
+        fm(0)
+    tb = timed(torch, fb, args.steps)
+    tm = timed(torch, fm, max(1, args.steps // 2))
+    out = {"metric": "semiring updates/s (R*K*N/t) Boolean product 16384^3",
+           "value": float(D) ** 3 / (tb * 1e-3), "unit": "updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": tb,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bits",
+           "data": "synthetic",
+           "config": {"workload": "bool_product_D16384", "D": D, "parallelism": "single_gpu"},
+           "fraction_of_bitwise_roofline": float(D) ** 3 / (tb * 1e-3) / PEAK_BOOL,
+           "mfma_path": {"ms_per_step": tm, "value": float(D) ** 3 / (tm * 1e-3),
+                         "fraction_of_int8_mfma_peak": float(D) ** 3 / (tm * 1e-3) / PEAK_I8_MAC,
+                         "speedup_vs_bitwise": tb / tm}}
+    torch.cuda.synchronize()
+    out["paths_equal"] = bool(torch.equal(C1, C2))
+    if not args.no_parity:
+        rows = np.array([0, 1, D // 2, D - 1])
+        want = oracle.bool_mul_words(W[rows], W, D, D)
+        nw = D // 64
+        out["parity"] = {"rows_checked": len(rows), "bit_exact": bool(
+            np.array_equal(sr.to_host(C1)[rows, :nw], want[:, :nw]))}
+    return out
+
+
 def run_add(args, torch, sr, synthgen):
     """Entrywise (+) of two 8192 x 8192 uint16 matrices (reads 256 MiB,
     writes 128 MiB): the HBM-bound step, and the streaming kernel of known
@@ -429,8 +473,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fw8192",
-                    choices=["fw8192", "u8fw8192", "bool16384", "mul1024", "batched", "add8192",
-                             "serve"])
+                    choices=["fw8192", "u8fw8192", "bool16384", "boolmul16384", "mul1024", "batched",
+                             "add8192", "serve"])
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--serve-calibration", type=int, default=24)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
@@ -472,6 +516,8 @@ def main():
                          "pivot_block": 128, "parallelism": "single_gpu"}
     elif args.workload == "bool16384":
         out = run_bool(args, torch, sr, synthgen)
+    elif args.workload == "boolmul16384":
+        out = run_boolmul(args, torch, sr, synthgen)
     elif args.workload == "mul1024":
         out = run_mul(args, torch, sr, synthgen)
     elif args.workload == "add8192":

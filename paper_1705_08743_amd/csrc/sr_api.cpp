@@ -152,8 +152,10 @@ int semiring_mul(int kind, void *C, int64_t ldc, const void *A, int64_t lda, con
     if (!valid_kind(kind)) return fail(SR_EINVAL, "semiring_mul: invalid kind %d", kind);
     if (flags & ~(unsigned)(SR_ACCUMULATE | SR_BOOL_BITWISE | SR_BOOL_MFMA))
         return fail(SR_EINVAL, "semiring_mul: unknown flags 0x%x", flags);
-    if (flags & SR_BOOL_MFMA)
-        return fail(SR_EUNSUPPORTED, "semiring_mul: the int8 matrix-core Boolean path is not built");
+    if ((flags & SR_BOOL_MFMA) && (flags & SR_BOOL_BITWISE))
+        return fail(SR_EINVAL, "semiring_mul: SR_BOOL_MFMA and SR_BOOL_BITWISE exclude each other");
+    if ((flags & SR_BOOL_MFMA) && kind != SR_BOOL)
+        return fail(SR_EINVAL, "semiring_mul: SR_BOOL_MFMA applies to SR_BOOL only");
     if (R < 0 || K < 0 || N < 0) return fail(SR_EINVAL, "semiring_mul: negative size");
     if (R > INT32_MAX || K > INT32_MAX || N > INT32_MAX)
         return fail(SR_EINVAL, "semiring_mul: sizes above 2^31-1 are not supported");
@@ -169,7 +171,15 @@ int semiring_mul(int kind, void *C, int64_t ldc, const void *A, int64_t lda, con
     const bool acc = (flags & SR_ACCUMULATE) != 0;
     hipStream_t st = as_stream(stream);
     hipError_t e = hipSuccess;
-    if (kind == SR_BOOL) {
+    if (kind == SR_BOOL && (flags & SR_BOOL_MFMA)) {
+        void *w = nullptr;
+        const size_t bytes = std::max<size_t>(sr::bool_mfma_work_bytes(R, K, N), 256);
+        if ((rc = work_alloc(&w, bytes, st)) != SR_OK) return rc;
+        e = sr::launch_bool_mul_mfma(static_cast<uint64_t *>(C), ldc,
+                                     static_cast<const uint64_t *>(A), lda,
+                                     static_cast<const uint64_t *>(B), ldb, R, K, N, acc, w, st);
+        work_free(w, st);
+    } else if (kind == SR_BOOL) {
         e = sr::launch_bool_mul(static_cast<uint64_t *>(C), ldc, static_cast<const uint64_t *>(A),
                                 lda, static_cast<const uint64_t *>(B), ldb, R, K, N, acc, st);
     } else if (kind == SR_ANTIDIST_U16) {

@@ -50,6 +50,14 @@ hipError_t launch_bool_mul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t 
 hipError_t launch_bool_closure(uint64_t *T, int64_t ld, int64_t D, bool serial,
                                hipStream_t stream);
 
+// Boolean product on the matrix cores (sr_bool_mfma.hip): bits expanded to
+// int8 in `work` (bool_mfma_work_bytes(R, K, N) bytes, 256-byte aligned,
+// alive until the work has run), integer product, threshold.
+size_t bool_mfma_work_bytes(int64_t R, int64_t K, int64_t N);
+hipError_t launch_bool_mul_mfma(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda,
+                                const uint64_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
+                                bool accumulate, void *work, hipStream_t stream);
+
 // Entrywise (+): elem_bytes 1 or 2 -> max, 8 -> OR of words.  Widths in
 // elements (words for Boolean).
 hipError_t launch_add(int elem_bytes, void *C, int64_t ldc, const void *A, int64_t lda,

@@ -72,8 +72,10 @@ def test_mul_rejects_bad_arguments(L):
     assert mul(L, U16, P, 8, P, 8, P + 8192, 8, 4, 4, 4) == sr.SR_EALIAS
     assert mul(L, U16, P, 8, P + 4096, 8, P + 16, 8, 4, 4, 4) == sr.SR_EALIAS  # partial overlap
     assert mul(L, U16, P, 8, P + 4096, 8, P + 8192, 8, 4, 4, 4, 0x100) == sr.SR_EINVAL
+    # the matrix-core path is Boolean only and excludes the bitwise one
+    assert mul(L, U16, P, 8, P + 4096, 8, P + 8192, 8, 4, 4, 4, sr.SR_BOOL_MFMA) == sr.SR_EINVAL
     assert mul(L, sr.SR_BOOL, P, 2, P + 4096, 2, P + 8192, 2, 4, 4, 4,
-               sr.SR_BOOL_MFMA) == sr.SR_EUNSUPPORTED
+               sr.SR_BOOL_MFMA | sr.SR_BOOL_BITWISE) == sr.SR_EINVAL
 
 
 def test_zero_extents_are_noops(L):

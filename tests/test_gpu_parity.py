@@ -411,3 +411,47 @@ def test_closure_batched_arena(kind):
     for i in (0, 7, 23, 49):
         want = oracle.ad_closure(mats[i], S_OF[kind])
         assert np.array_equal(host(arena.view(i)).astype(np.int64), want), mats[i].shape
+
+
+# ---------------------------------------------------------------------------
+# Boolean product on the matrix cores (SR_BOOL_MFMA)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("R,K,N", [(1, 1, 1), (5, 3, 7), (64, 64, 64), (65, 130, 129),
+                                   (200, 37, 300), (257, 300, 513), (128, 1000, 256)])
+def test_bool_mul_mfma(R, K, N):
+    gen = synthgen.generator(6000 + R + K + N)
+    A = rand_bits(R, K, gen, 0.05)
+    B = rand_bits(K, N, gen, 0.05)
+    lda, ldb = synthgen.aligned_ld_words(K), synthgen.aligned_ld_words(N)
+    Aw, Bw = synthgen.pack_bits(A, lda), synthgen.pack_bits(B, ldb)
+    C = sr.empty(sr.SR_BOOL, R, N)
+    sr.semiring_mul(sr.SR_BOOL, C, dev(sr.SR_BOOL, Aw, cols=K), dev(sr.SR_BOOL, Bw, cols=N),
+                    K=K, N=N, flags=sr.SR_BOOL_MFMA)
+    want = oracle.bool_mul_words(Aw, Bw, K, N)
+    nw = (N + 63) // 64
+    got = host(C)
+    assert np.array_equal(got[:, :nw], want[:, :nw])
+    assert synthgen.padding_bits_clear(got, N)
+
+
+def test_bool_mul_mfma_accumulate_and_dense():
+    """Accumulate mode, and dense inputs (counts up to K) equal to the
+    bitwise path."""
+    gen = synthgen.generator(6100)
+    R, K, N = 300, 700, 260
+    for p in (0.02, 0.5):
+        A = rand_bits(R, K, gen, p)
+        B = rand_bits(K, N, gen, p)
+        C0 = rand_bits(R, N, gen, 0.1)
+        ldk, ldn = synthgen.aligned_ld_words(K), synthgen.aligned_ld_words(N)
+        Aw, Bw, Cw = synthgen.pack_bits(A, ldk), synthgen.pack_bits(B, ldn), synthgen.pack_bits(C0, ldn)
+        dA, dB = dev(sr.SR_BOOL, Aw, cols=K), dev(sr.SR_BOOL, Bw, cols=N)
+        C1 = dev(sr.SR_BOOL, Cw, cols=N)
+        C2 = dev(sr.SR_BOOL, Cw, cols=N)
+        sr.semiring_mul(sr.SR_BOOL, C1, dA, dB, K=K, N=N,
+                        flags=sr.SR_BOOL_MFMA | sr.SR_ACCUMULATE)
+        sr.semiring_mul(sr.SR_BOOL, C2, dA, dB, K=K, N=N, flags=sr.SR_ACCUMULATE)
+        want = oracle.bool_mul_words(Aw, Bw, K, N, C=Cw)
+        nw = (N + 63) // 64
+        assert np.array_equal(host(C1)[:, :nw], want[:, :nw])
+        assert torch.equal(C1, C2)
