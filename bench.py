@@ -100,11 +100,16 @@ def cpu_baseline_fw(A, S, target_s, threads):
     oracle.set_threads(threads)
     D = A.shape[0]
     A32 = np.ascontiguousarray(A[:, :D], dtype=np.int32)
-    m0 = 4
+    # size the sample from two short calibration runs: their difference is
+    # the cost of m0 pivots without the fixed per-call cost (copies, threads)
+    m0 = min(D, 32)
     t0 = time.perf_counter()
     oracle.ad_closure(A32, S, k_end=m0)
-    dt = time.perf_counter() - t0
-    m = int(max(m0, min(D, target_s / max(dt / m0, 1e-9))))
+    t1 = time.perf_counter()
+    oracle.ad_closure(A32, S, k_end=2 * m0)
+    t2 = time.perf_counter()
+    per_pivot = max((t2 - t1) - (t1 - t0), 1e-9) / m0
+    m = int(max(m0, min(D, target_s / per_pivot)))
     t0 = time.perf_counter()
     oracle.ad_closure(A32, S, k_end=m)
     dt = time.perf_counter() - t0
