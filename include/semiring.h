@@ -81,7 +81,8 @@ enum {
     SR_ACCUMULATE = 1u,    /* semiring_mul: C := C (+) A*B instead of C := A*B */
     SR_REFLEXIVE = 2u,     /* closure: return I (+) T (eq. rtc); not implemented -> SR_EUNSUPPORTED */
     SR_BOOL_BITWISE = 4u,  /* Boolean: force the word OR-AND kernels (the default) */
-    SR_BOOL_MFMA = 8u,     /* Boolean: request the int8 matrix-core path; not implemented -> SR_EUNSUPPORTED */
+    SR_BOOL_MFMA = 8u,     /* Boolean semiring_mul: the int8 matrix-core path (exact; opt-in);
+                              closure: SR_EUNSUPPORTED; any other kind: SR_EINVAL */
     SR_SERIAL_PHASES = 16u /* closure: enqueue every phase on the caller's stream in order, without
                               overlapping the next round's pivot and panels on a second stream */
 };
@@ -98,6 +99,11 @@ enum {
  * product is out of place, and the in-place form with all three operands the
  * same matrix is the closure below.
  * Boolean padding bits of A (columns >= K) and B (columns >= N) must be zero.
+ * Boolean with SR_BOOL_MFMA: the same product computed as an integer product
+ * of {0, 1} matrices on the matrix cores, thresholded at 1 (count > 0 exactly
+ * when some A_ik = B_kj = 1); it takes stream-ordered working memory of
+ * (R + N) * K bytes (sizes rounded up) and cannot be combined with
+ * SR_BOOL_BITWISE (SR_EINVAL).
  */
 int semiring_mul(int kind, void *C, int64_t ldc, const void *A, int64_t lda,
                  const void *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
@@ -134,12 +140,14 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
  * applied to each (T[g], ldt[g], D[g]).  The three arrays are HOST arrays of
  * length count; T[g] are device pointers, each obeying the alignment rules
  * above.  Anti-distance kinds only (Boolean returns SR_EUNSUPPORTED).  The
- * matrices must not overlap each other (SR_EALIAS), D[g] <= 65536.  One
- * launch closes the whole batch, one workgroup per graph, handed out
- * largest-first: a graph of up to 128 vertices is one tile closed in
- * registers and LDS; a larger one runs the blocked Floyd-Warshall of
- * closure() inside its workgroup.  The descriptor upload is stream-ordered;
- * uint8 batches use stream-ordered uint16 working copies.
+ * matrices must not overlap each other (SR_EALIAS), D[g] <= 65536.  The
+ * batch runs the blocked Floyd-Warshall of closure() round-synchronously: per
+ * round, one pivot, one panels and one update launch cover every graph that
+ * still has that round (largest graphs first), so a graph of up to 128
+ * vertices is closed by the first pivot launch.  The descriptors and the
+ * per-round work lists are built on the host and uploaded stream-ordered
+ * (the call returns without waiting); uint8 batches use stream-ordered
+ * uint16 working copies.
  */
 int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t *D,
                     int64_t count, unsigned flags, void *stream);
