@@ -23,6 +23,14 @@ What it computes (all integer, so every result is exact and unique):
                Warshall loop is too slow.
 * ``add``:     entrywise (+) (Sec. II; the | operator of the table of entrywise
                operations in Sec. V).
+* ``ewise``:   the entrywise operations of that table: and = min, or = max,
+               xor = |a - b|, not = S - a (on Boolean words: AND, OR, XOR, NOT
+               with the padding bits kept zero).
+* ``dist_mul``, ``dist_closure``: the distance-matrix dual the paper adds
+               (addition min, multiplication saturating +, S = no path), by
+               the same multiplication algorithm and Warshall loop.
+* ``reflexive``: I (+) T (eq. rtc), the multiplicative identity's diagonal
+               (S for anti-distance, 1 for Boolean, 0 for distance) added in.
 
 Every function here is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_pins.py`` against brute force, closed forms, invariants and
@@ -63,6 +71,8 @@ def _load():
         lib.o_bool_mul_words.argtypes = [vp, i64, vp, i64, vp, i64, i64, i64, i64, ctypes.c_int]
         lib.o_bool_closure_words.argtypes = [vp, i64, i64]
         lib.o_bool_closure_rows_words.argtypes = [vp, i64, i64, vp, i64, vp, i64]
+        lib.o_dist_mul.argtypes = [vp, i64, vp, i64, vp, i64, i64, i64, i64, i32, ctypes.c_int]
+        lib.o_dist_closure.argtypes = [vp, i64, i64, i32]
         _lib = lib
     return _lib
 
@@ -147,6 +157,89 @@ def ad_closure_rows(A, S, rows):
 def ad_add(A, B):
     """Entrywise (+) = max (Sec. II matrix addition)."""
     return np.maximum(_as_i32(A), _as_i32(B))
+
+
+# --------------------------------------------------------------------------
+# distance matrices (the dual: min, saturating +)
+# --------------------------------------------------------------------------
+def dist_mul(A, B, S, C=None):
+    """Distance product: min over k of min(A_ik + B_kj, S); with C given,
+    min(C, A + B).  Entries 0..S, S = no path.  Returns int32."""
+    A = _as_i32(A)
+    B = _as_i32(B)
+    R, K = A.shape
+    K2, N = B.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ: %d vs %d" % (K, K2))
+    acc = C is not None
+    out = _as_i32(C).copy() if acc else np.full((R, N), int(S), np.int32)
+    if R and N:
+        _load().o_dist_mul(_ptr(A), K, _ptr(B), N, _ptr(out), N, R, K, N, int(S), int(acc))
+    return out
+
+
+def dist_closure(A, S):
+    """Warshall's loop with min and saturating + (distance closure; the
+    diagonal holds the shortest cycle through each vertex, or S)."""
+    T = _as_i32(A).copy()
+    D = T.shape[0]
+    if T.shape != (D, D):
+        raise ValueError("closure needs a square matrix")
+    if D:
+        _load().o_dist_closure(_ptr(T), D, D, int(S))
+    return T
+
+
+# --------------------------------------------------------------------------
+# entrywise operations (table of Sec. V) and the reflexive closure (eq. rtc)
+# --------------------------------------------------------------------------
+def ewise(op, A, B=None, S=None):
+    """Entrywise and = min, or = max, xor = |a - b|, not = S - a."""
+    A = np.asarray(A, np.int64)
+    if op == "not":
+        return (int(S) - A).astype(np.int32)
+    B = np.asarray(B, np.int64)
+    if op == "and":
+        return np.minimum(A, B).astype(np.int32)
+    if op == "or":
+        return np.maximum(A, B).astype(np.int32)
+    if op == "xor":
+        return np.abs(A - B).astype(np.int32)
+    raise ValueError("op is and, or, xor or not")
+
+
+def ewise_words(op, A, N, B=None):
+    """The same operations on bit-packed Boolean rows of N bits (AND, OR, XOR,
+    NOT); padding bits of the result are zero."""
+    A = _as_words(A)
+    if op == "not":
+        out = ~A
+    elif op == "and":
+        out = A & _as_words(B)
+    elif op == "or":
+        out = A | _as_words(B)
+    elif op == "xor":
+        out = A ^ _as_words(B)
+    else:
+        raise ValueError("op is and, or, xor or not")
+    out = out.copy()
+    nw = (N + 63) // 64
+    out[:, nw:] = 0
+    if N % 64:
+        out[:, nw - 1] &= np.uint64((1 << (N % 64)) - 1)
+    return out
+
+
+def reflexive(T, one):
+    """I (+) T: the diagonal combined with the multiplicative identity `one`
+    (anti-distance: max with S; Boolean: max with 1; distance: min with 0)."""
+    out = np.array(T, copy=True)
+    d = np.arange(min(out.shape))
+    if one == 0:
+        out[d, d] = np.minimum(out[d, d], 0)
+    else:
+        out[d, d] = np.maximum(out[d, d], one)
+    return out
 
 
 # --------------------------------------------------------------------------

@@ -21,6 +21,14 @@
  *   Warshall / Floyd (Sec. II, Sec. III): T := A; for each k,
  *       T := T (+) (column k of T) * (row k of T), in place.
  *
+ *   Distance matrices (the dual the paper adds in its section on distance
+ *   matrices): entries in {0, 1, ..., S} with S standing for "no path";
+ *       addition is min (the wedge of the entrywise table), multiplication
+ *       is saturating +: a (x) b = min(a + b, S) ("funny" multiplication);
+ *       the additive zero is the all-S matrix.  Warshall's loop with these
+ *       operations gives the distance closure (minimum lengths over paths of
+ *       at least one edge; minimum loop lengths on the diagonal).
+ *
  * Anti-distance arithmetic is done in int32 in the definition form
  * max(a + b - S, 0), deliberately not in the saturating-subtract form the
  * GPU kernels use.  Matrices are passed as int32 (anti-distance) or as
@@ -113,6 +121,53 @@ void o_ad_closure_steps(int32_t *T, int64_t ld, int64_t D, int32_t S,
 
 void o_ad_closure(int32_t *T, int64_t ld, int64_t D, int32_t S) {
     o_ad_closure_steps(T, ld, D, S, 0, D);
+}
+
+/* ---------------------------------------------------------------------------
+ * Distance-matrix product (the dual with min as addition and saturating + as
+ * multiplication): P := all-S (or C when accumulating); for k:
+ * P := min(P, min(A_{:,k} + B_{k,:}, S)).  int32, same shapes as o_ad_mul.
+ * ------------------------------------------------------------------------- */
+static inline int32_t dist_times(int32_t a, int32_t b, int32_t S) {
+    int32_t t = a + b;
+    return t < S ? t : S;
+}
+
+static inline int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
+
+void o_dist_mul(const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb,
+                int32_t *C, int64_t ldc, int64_t R, int64_t K, int64_t N,
+                int32_t S, int accumulate) {
+    if (!accumulate)
+        for (int64_t i = 0; i < R; i++)
+            for (int64_t j = 0; j < N; j++) C[i * ldc + j] = S;
+    for (int64_t k = 0; k < K; k++) {
+        int64_t i;
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+        for (i = 0; i < R; i++) {
+            int32_t a = A[i * lda + k];
+            for (int64_t j = 0; j < N; j++) {
+                int32_t v = dist_times(a, B[k * ldb + j], S);
+                C[i * ldc + j] = imin(C[i * ldc + j], v);
+            }
+        }
+    }
+}
+
+/* Distance closure: Warshall's loop with min and saturating +, in place
+ * (the distance counterpart of o_ad_closure). */
+void o_dist_closure(int32_t *T, int64_t ld, int64_t D, int32_t S) {
+    for (int64_t k = 0; k < D; k++) {
+        int64_t i;
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+        for (i = 0; i < D; i++) {
+            int32_t tik = T[i * ld + k];
+            for (int64_t j = 0; j < D; j++) {
+                int32_t v = dist_times(tik, T[k * ld + j], S);
+                T[i * ld + j] = imin(T[i * ld + j], v);
+            }
+        }
+    }
 }
 
 /* Rows of the anti-distance closure straight from its definition, the sum
