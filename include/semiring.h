@@ -5,7 +5,7 @@
  *   M. de Bondt, "Fast algorithms for anti-distance matrices as a
  *   generalization of Boolean matrices", arXiv 1705.08743.
  *
- * Two semirings are supported, both exactly as the paper defines them:
+ * Three semirings are supported, as the paper defines them:
  *
  *   SR_BOOL            Boolean matrices (Sec. II): entries {0, 1},
  *                      a (+) b = max(a, b), a (x) b = min(a, b).
@@ -14,6 +14,15 @@
  *                      2^16 - 1 (uint16): a (+) b = max(a, b) and
  *                      a (x) b = max(a + b - S, 0).  Entry S - w encodes a
  *                      distance w; 0 is "no path" (distance >= S saturates).
+ *   SR_DISTANCE_U8     distance matrices, the dual the paper adds beside
+ *   SR_DISTANCE_U16    anti-distance matrices (its section on distance
+ *                      matrices): entries 0..S hold a distance, S is "no
+ *                      path"; a (+) b = min(a, b) and a (x) b = min(a + b, S)
+ *                      ("funny" multiplication; the zero matrix is all S).
+ *                      By the De Morgan laws stated there, not(A + B) =
+ *                      (not A) (x) (not B) with not a = S - a, so these kinds
+ *                      run the anti-distance kernels between two entrywise
+ *                      complements.
  *
  * Matrix (+) is entrywise; the product is (A*B)_ij = (+)_k A_ik (x) B_kj
  * (Sec. II), evaluated as a running (+) of column-times-row products; the
@@ -62,8 +71,20 @@ extern "C" {
 typedef enum sr_kind {
     SR_BOOL = 0,          /* Boolean, bit-packed uint64 words */
     SR_ANTIDIST_U8 = 1,   /* anti-distance, uint8 entries, S = 255 */
-    SR_ANTIDIST_U16 = 2   /* anti-distance, uint16 entries, S = 65535 */
+    SR_ANTIDIST_U16 = 2,  /* anti-distance, uint16 entries, S = 65535 */
+    SR_DISTANCE_U8 = 3,   /* distance, uint8 entries, S = 255 = no path */
+    SR_DISTANCE_U16 = 4   /* distance, uint16 entries, S = 65535 = no path */
 } sr_kind;
+
+/* Entrywise operations (the `op` argument of semiring_ewise): the table of
+ * entrywise operations in Sec. V, on entry values (any non-Boolean kind) or
+ * on bits (SR_BOOL). */
+enum {
+    SR_EW_AND = 0,  /* min(a, b); Boolean AND */
+    SR_EW_OR = 1,   /* max(a, b); Boolean OR */
+    SR_EW_XOR = 2,  /* |a - b|; Boolean XOR */
+    SR_EW_NOT = 3   /* S - a (B unused); Boolean NOT, padding bits stay zero */
+};
 
 /* Return codes. */
 enum {
@@ -79,7 +100,7 @@ enum {
 /* Flags. */
 enum {
     SR_ACCUMULATE = 1u,    /* semiring_mul: C := C (+) A*B instead of C := A*B */
-    SR_REFLEXIVE = 2u,     /* closure: return I (+) T (eq. rtc); not implemented -> SR_EUNSUPPORTED */
+    SR_REFLEXIVE = 2u,     /* closure, closure_batched: return I (+) T (eq. rtc) */
     SR_BOOL_BITWISE = 4u,  /* Boolean: force the word OR-AND kernels (the default) */
     SR_BOOL_MFMA = 8u,     /* Boolean semiring_mul: the int8 matrix-core path (exact; opt-in);
                               closure: SR_EUNSUPPORTED; any other kind: SR_EINVAL */
@@ -112,11 +133,20 @@ int semiring_mul(int kind, void *C, int64_t ldc, const void *A, int64_t lda,
 /*
  * semiring_add -- C := A (+) B entrywise (Sec. II matrix addition; the `|`
  * operator of the entrywise table in Sec. V): max for anti-distance, OR for
- * Boolean words.  All three are R x N.  C may be exactly A or B (same base and
- * ld); any other overlap is SR_EALIAS.
+ * Boolean words, min for distances.  All three are R x N.  C may be exactly A
+ * or B (same base and ld); any other overlap is SR_EALIAS.
  */
 int semiring_add(int kind, void *C, int64_t ldc, const void *A, int64_t lda,
                  const void *B, int64_t ldb, int64_t R, int64_t N, void *stream);
+
+/*
+ * semiring_ewise -- C := A op B (or op A for SR_EW_NOT) entrywise, op from
+ * the table of entrywise operations in Sec. V (SR_EW_*).  Shapes, strides and
+ * aliasing as semiring_add (N in bits for SR_BOOL); for SR_EW_NOT, B and ldb
+ * are ignored.  An op outside SR_EW_AND..SR_EW_NOT is SR_EINVAL.
+ */
+int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_t lda,
+                   const void *B, int64_t ldb, int64_t R, int64_t N, void *stream);
 
 /*
  * closure -- in place, T := A (+) A*A (+) A*A*A (+) ... for the D x D matrix
@@ -124,9 +154,12 @@ int semiring_add(int kind, void *C, int64_t ldc, const void *A, int64_t lda,
  * which for anti-distance matrices is Floyd's algorithm, Sec. III).  The
  * result is the transitive, non-reflexive closure: entry (i, j) is the best
  * product over paths of at least one edge, so the diagonal holds "i lies on a
- * cycle" (Boolean) or S minus the shortest cycle through i, saturated
- * (anti-distance).  flags: SR_BOOL_BITWISE, SR_SERIAL_PHASES; SR_REFLEXIVE
- * and SR_BOOL_MFMA return SR_EUNSUPPORTED.  D = 0 is a no-op.
+ * cycle" (Boolean), S minus the shortest cycle through i, saturated
+ * (anti-distance), or the shortest cycle through i, or S (distance: the
+ * paper's dransclose).  flags: SR_REFLEXIVE (I (+) T, eq. rtc: the diagonal
+ * becomes 1, S, or 0 for distances -- the paper's transclosure /
+ * dransclosure), SR_BOOL_BITWISE, SR_SERIAL_PHASES; SR_BOOL_MFMA returns
+ * SR_EUNSUPPORTED.  D = 0 is a no-op.
  * By default a closure with more than two pivot blocks forks onto a second,
  * library-owned stream of default priority (the next round's pivot and panels
  * overlap the bulk of the current update) and joins back into `stream`
@@ -139,7 +172,8 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
  * closure_batched -- `count` independent in-place closures, as closure()
  * applied to each (T[g], ldt[g], D[g]).  The three arrays are HOST arrays of
  * length count; T[g] are device pointers, each obeying the alignment rules
- * above.  Anti-distance kinds only (Boolean returns SR_EUNSUPPORTED).  The
+ * above.  Anti-distance and distance kinds (Boolean returns
+ * SR_EUNSUPPORTED); flags: SR_REFLEXIVE.  The
  * matrices must not overlap each other (SR_EALIAS), D[g] <= 65536.  The
  * batch runs the blocked Floyd-Warshall of closure() round-synchronously: per
  * round, one pivot, one panels and one update launch cover every graph that

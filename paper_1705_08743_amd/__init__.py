@@ -10,7 +10,8 @@ fallback.
 Matrices are 2-D CUDA (HIP) tensors with unit column stride; the row stride
 ``tensor.stride(0)`` is the ABI's leading dimension ``ld``:
 
-* anti-distance (``SR_ANTIDIST_U8`` / ``SR_ANTIDIST_U16``): ``torch.uint8`` /
+* anti-distance (``SR_ANTIDIST_U8`` / ``SR_ANTIDIST_U16``) and distance
+  (``SR_DISTANCE_U8`` / ``SR_DISTANCE_U16``): ``torch.uint8`` /
   ``torch.uint16`` tensors; the logical shape is the tensor shape, so a view
   ``X[:, :n]`` of a padded ``(rows, ld)`` buffer is a rows x n matrix.
 * Boolean (``SR_BOOL``): ``torch.int64`` tensors of packed words (entry (r, c)
@@ -23,6 +24,16 @@ import os
 SR_BOOL = 0
 SR_ANTIDIST_U8 = 1
 SR_ANTIDIST_U16 = 2
+SR_DISTANCE_U8 = 3
+SR_DISTANCE_U16 = 4
+
+SR_EW_AND = 0
+SR_EW_OR = 1
+SR_EW_XOR = 2
+SR_EW_NOT = 3
+
+_U8_KINDS = (SR_ANTIDIST_U8, SR_DISTANCE_U8)
+_U16_KINDS = (SR_ANTIDIST_U16, SR_DISTANCE_U16)
 
 SR_OK = 0
 SR_EINVAL = -1
@@ -45,7 +56,7 @@ ERROR_NAMES = {
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsemiring.so")
 
-EXPORTS = ("semiring_mul", "semiring_add", "closure", "closure_batched",
+EXPORTS = ("semiring_mul", "semiring_add", "semiring_ewise", "closure", "closure_batched",
            "sr_profile_enable", "sr_profile_read", "sr_last_error", "sr_version", "sr_shutdown")
 
 SR_PHASE_PIVOT = 0
@@ -77,6 +88,8 @@ def lib():
         L.semiring_mul.restype = i32
         L.semiring_add.argtypes = [i32, vp, i64, vp, i64, vp, i64, i64, i64, vp]
         L.semiring_add.restype = i32
+        L.semiring_ewise.argtypes = [i32, i32, vp, i64, vp, i64, vp, i64, i64, i64, vp]
+        L.semiring_ewise.restype = i32
         L.closure.argtypes = [i32, vp, i64, i64, u32, vp]
         L.closure.restype = i32
         L.closure_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
@@ -166,6 +179,17 @@ def semiring_add(kind, C, A, B, R=None, N=None, stream=None):
     _check(lib().semiring_add(kind, pc, ldc, pa, lda, pb, ldb, R, N, _stream(stream)))
 
 
+def semiring_ewise(kind, op, C, A, B=None, R=None, N=None, stream=None):
+    """C := A op B entrywise (op = SR_EW_AND, SR_EW_OR, SR_EW_XOR), or
+    C := not A (SR_EW_NOT, B unused); C may be A or B."""
+    pc, ldc, _, nc = _mat(C, "C")
+    pa, lda, ra, na = _mat(A, "A")
+    pb, ldb = (None, 0) if B is None else _mat(B, "B")[:2]
+    R = ra if R is None else R
+    N = (64 * nc if kind == SR_BOOL else na) if N is None else N
+    _check(lib().semiring_ewise(kind, op, pc, ldc, pa, lda, pb, ldb, R, N, _stream(stream)))
+
+
 def closure(kind, T, D=None, flags=0, stream=None):
     """In-place transitive closure of the D x D matrix held in T."""
     pt, ldt, rt, ct = _mat(T, "T")
@@ -208,11 +232,11 @@ class BatchArena:
     def __init__(self, kind, sizes, device="cuda", zero=True):
         import numpy as np
         torch = _torch()
-        if kind not in (SR_ANTIDIST_U8, SR_ANTIDIST_U16):
-            raise ValueError("BatchArena holds anti-distance matrices")
+        if kind not in _U8_KINDS + _U16_KINDS:
+            raise ValueError("BatchArena holds anti-distance or distance matrices")
         self.kind = kind
-        self.es = 1 if kind == SR_ANTIDIST_U8 else 2
-        self.dtype = torch.uint8 if kind == SR_ANTIDIST_U8 else torch.uint16
+        self.es = 1 if kind in _U8_KINDS else 2
+        self.dtype = torch.uint8 if kind in _U8_KINDS else torch.uint16
         self.sizes = np.asarray(sizes, dtype=np.int64).reshape(-1)
         if (self.sizes < 0).any():
             raise ValueError("negative matrix size")
@@ -300,7 +324,7 @@ def padded_ld(cols, kind, align_bytes=128):
         words = (cols + 63) // 64
         per = max(2, align_bytes // 8)
         return max(per, -(-words // per) * per)
-    es = 1 if kind == SR_ANTIDIST_U8 else 2
+    es = 1 if kind in _U8_KINDS else 2
     per = align_bytes // es
     return max(per, -(-cols // per) * per)
 
@@ -309,7 +333,8 @@ def empty(kind, rows, cols, device="cuda", zero=True):
     """A rows x cols matrix view of a zero-filled padded device buffer (for
     Boolean, rows x words with cols bits of payload)."""
     torch = _torch()
-    dt = {SR_BOOL: torch.int64, SR_ANTIDIST_U8: torch.uint8, SR_ANTIDIST_U16: torch.uint16}[kind]
+    dt = {SR_BOOL: torch.int64, SR_ANTIDIST_U8: torch.uint8, SR_ANTIDIST_U16: torch.uint16,
+          SR_DISTANCE_U8: torch.uint8, SR_DISTANCE_U16: torch.uint16}[kind]
     ld = padded_ld(cols, kind)
     buf = (torch.zeros if zero else torch.empty)((max(rows, 1), ld), dtype=dt, device=device)
     width = (cols + 63) // 64 if kind == SR_BOOL else cols
@@ -358,7 +383,8 @@ def to_host(t):
 
 
 __all__ = [
-    "SR_BOOL", "SR_ANTIDIST_U8", "SR_ANTIDIST_U16", "SR_OK", "SR_EINVAL", "SR_EALIAS",
+    "SR_BOOL", "SR_ANTIDIST_U8", "SR_ANTIDIST_U16", "SR_DISTANCE_U8", "SR_DISTANCE_U16",
+    "SR_EW_AND", "SR_EW_OR", "SR_EW_XOR", "SR_EW_NOT", "semiring_ewise", "SR_OK", "SR_EINVAL", "SR_EALIAS",
     "SR_EALIGN", "SR_ENOMEM", "SR_EDEVICE", "SR_EUNSUPPORTED", "SR_ACCUMULATE",
     "SR_REFLEXIVE", "SR_BOOL_BITWISE", "SR_BOOL_MFMA", "SR_SERIAL_PHASES", "SemiringError", "lib", "kind_of",
     "semiring_mul", "semiring_add", "closure", "closure_batched", "version", "shutdown",

@@ -39,12 +39,23 @@ int device_fail(hipError_t e, const char *what) {
 }
 
 bool valid_kind(int kind) {
-    return kind == SR_BOOL || kind == SR_ANTIDIST_U8 || kind == SR_ANTIDIST_U16;
+    return kind == SR_BOOL || kind == SR_ANTIDIST_U8 || kind == SR_ANTIDIST_U16 ||
+           kind == SR_DISTANCE_U8 || kind == SR_DISTANCE_U16;
 }
 
+bool is_dist(int kind) { return kind == SR_DISTANCE_U8 || kind == SR_DISTANCE_U16; }
+
+// The anti-distance kind of the same width (distance kinds are computed as
+// anti-distance ones through the De Morgan laws: not a = S - a).
+int base_kind(int kind) {
+    if (kind == SR_DISTANCE_U8) return SR_ANTIDIST_U8;
+    if (kind == SR_DISTANCE_U16) return SR_ANTIDIST_U16;
+    return kind;
+}
 
 // bytes per storage unit of the leading dimension
 int64_t unit_bytes(int kind) {
+    kind = base_kind(kind);
     return kind == SR_BOOL ? 8 : (kind == SR_ANTIDIST_U8 ? 1 : 2);
 }
 
@@ -113,6 +124,51 @@ void work_free(void *p, hipStream_t st) {
     if (p) (void)hipFreeAsync(p, st);
 }
 
+// The product after validation; kind is SR_BOOL or an anti-distance kind.
+int mul_compute(int kind, void *C, int64_t ldc, const void *A, int64_t lda, const void *B,
+                int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, bool mfma,
+                hipStream_t st) {
+    int rc;
+    hipError_t e = hipSuccess;
+    if (kind == SR_BOOL && mfma) {
+        void *w = nullptr;
+        const size_t bytes = std::max<size_t>(sr::bool_mfma_work_bytes(R, K, N), 256);
+        if ((rc = work_alloc(&w, bytes, st)) != SR_OK) return rc;
+        e = sr::launch_bool_mul_mfma(static_cast<uint64_t *>(C), ldc,
+                                     static_cast<const uint64_t *>(A), lda,
+                                     static_cast<const uint64_t *>(B), ldb, R, K, N, acc, w, st);
+        work_free(w, st);
+    } else if (kind == SR_BOOL) {
+        e = sr::launch_bool_mul(static_cast<uint64_t *>(C), ldc, static_cast<const uint64_t *>(A),
+                                lda, static_cast<const uint64_t *>(B), ldb, R, K, N, acc, st);
+    } else if (kind == SR_ANTIDIST_U16) {
+        e = sr::launch_ad_mul(false, static_cast<uint16_t *>(C), ldc,
+                              static_cast<const uint16_t *>(A), lda,
+                              static_cast<const uint16_t *>(B), ldb, R, K, N, acc, st);
+    } else {
+        // uint8: widen to uint16 working copies, multiply with S = 255, narrow.
+        const int64_t lk = round_up(std::max<int64_t>(K, 1), 64);
+        const int64_t ln = round_up(N, 64);
+        const size_t bytes = (size_t)(R * lk + K * ln + R * ln) * 2;
+        void *w = nullptr;
+        if ((rc = work_alloc(&w, bytes, st)) != SR_OK) return rc;
+        uint16_t *Aw = static_cast<uint16_t *>(w);
+        uint16_t *Bw = Aw + R * lk;
+        uint16_t *Cw = Bw + K * ln;
+        const uint8_t *A8 = static_cast<const uint8_t *>(A);
+        const uint8_t *B8 = static_cast<const uint8_t *>(B);
+        uint8_t *C8 = static_cast<uint8_t *>(C);
+        if (e == hipSuccess) e = sr::launch_widen_u8(Aw, lk, A8, lda, R, K, st);
+        if (e == hipSuccess) e = sr::launch_widen_u8(Bw, ln, B8, ldb, K, N, st);
+        if (e == hipSuccess && acc) e = sr::launch_widen_u8(Cw, ln, C8, ldc, R, N, st);
+        if (e == hipSuccess) e = sr::launch_ad_mul(true, Cw, ln, Aw, lk, Bw, ln, R, K, N, acc, st);
+        if (e == hipSuccess) e = sr::launch_narrow_u8(C8, ldc, Cw, ln, R, N, st);
+        work_free(w, st);
+    }
+    if (e != hipSuccess) return device_fail(e, "semiring_mul launch");
+    return ok();
+}
+
 }  // namespace
 
 extern "C" {
@@ -124,8 +180,7 @@ const char *sr_version(void) { return "libsemiring 0.1 (gfx950)"; }
 int sr_profile_enable(int enable) { return sr::prof_enable(enable); }
 
 int sr_profile_read(int kind, int phase, double *total_ms, int64_t *launches, double *updates) {
-    if (kind != SR_BOOL && kind != SR_ANTIDIST_U8 && kind != SR_ANTIDIST_U16)
-        return fail(SR_EINVAL, "sr_profile_read: invalid kind %d", kind);
+    if (!valid_kind(kind)) return fail(SR_EINVAL, "sr_profile_read: invalid kind %d", kind);
     if (phase < SR_PHASE_PIVOT || phase > SR_PHASE_UPDATE)
         return fail(SR_EINVAL, "sr_profile_read: invalid phase %d", phase);
     if (sr::prof_read(kind == SR_BOOL ? 0 : 1, phase, total_ms, launches, updates) != 0)
@@ -170,65 +225,75 @@ int semiring_mul(int kind, void *C, int64_t ldc, const void *A, int64_t lda, con
                     "semiring_mul: C overlaps A or B (the in-place form is closure())");
     const bool acc = (flags & SR_ACCUMULATE) != 0;
     hipStream_t st = as_stream(stream);
-    hipError_t e = hipSuccess;
-    if (kind == SR_BOOL && (flags & SR_BOOL_MFMA)) {
-        void *w = nullptr;
-        const size_t bytes = std::max<size_t>(sr::bool_mfma_work_bytes(R, K, N), 256);
-        if ((rc = work_alloc(&w, bytes, st)) != SR_OK) return rc;
-        e = sr::launch_bool_mul_mfma(static_cast<uint64_t *>(C), ldc,
-                                     static_cast<const uint64_t *>(A), lda,
-                                     static_cast<const uint64_t *>(B), ldb, R, K, N, acc, w, st);
+    if (!is_dist(kind)) return mul_compute(kind, C, ldc, A, lda, B, ldb, R, K, N, acc,
+                                           (flags & SR_BOOL_MFMA) != 0, st);
+    // distance product (min, saturating +) by De Morgan:
+    // A + B = not((not A) (x) (not B)), with C complemented around it
+    const int64_t es = unit_bytes(kind);
+    const int64_t lk = round_up(std::max<int64_t>(K, 1), 64), ln = round_up(N, 64);
+    void *w = nullptr;
+    if ((rc = work_alloc(&w, (size_t)(R * lk + K * ln) * (size_t)es, st)) != SR_OK) return rc;
+    char *nA = static_cast<char *>(w);
+    char *nB = nA + R * lk * es;
+    hipError_t e = sr::launch_ewise((int)es, sr::EW_NOT, nA, lk, A, lda, A, lda, R, K, 0, st);
+    if (e == hipSuccess) e = sr::launch_ewise((int)es, sr::EW_NOT, nB, ln, B, ldb, B, ldb, K, N, 0, st);
+    if (e == hipSuccess && acc)
+        e = sr::launch_ewise((int)es, sr::EW_NOT, C, ldc, C, ldc, C, ldc, R, N, 0, st);
+    if (e != hipSuccess) {
         work_free(w, st);
-    } else if (kind == SR_BOOL) {
-        e = sr::launch_bool_mul(static_cast<uint64_t *>(C), ldc, static_cast<const uint64_t *>(A),
-                                lda, static_cast<const uint64_t *>(B), ldb, R, K, N, acc, st);
-    } else if (kind == SR_ANTIDIST_U16) {
-        e = sr::launch_ad_mul(false, static_cast<uint16_t *>(C), ldc,
-                              static_cast<const uint16_t *>(A), lda,
-                              static_cast<const uint16_t *>(B), ldb, R, K, N, acc, st);
-    } else {
-        // uint8: widen to uint16 working copies, multiply with S = 255, narrow.
-        const int64_t lk = round_up(std::max<int64_t>(K, 1), 64);
-        const int64_t ln = round_up(N, 64);
-        const size_t bytes = (size_t)(R * lk + K * ln + R * ln) * 2;
-        void *w = nullptr;
-        if ((rc = work_alloc(&w, bytes, st)) != SR_OK) return rc;
-        uint16_t *Aw = static_cast<uint16_t *>(w);
-        uint16_t *Bw = Aw + R * lk;
-        uint16_t *Cw = Bw + K * ln;
-        const uint8_t *A8 = static_cast<const uint8_t *>(A);
-        const uint8_t *B8 = static_cast<const uint8_t *>(B);
-        uint8_t *C8 = static_cast<uint8_t *>(C);
-        if (e == hipSuccess) e = sr::launch_widen_u8(Aw, lk, A8, lda, R, K, st);
-        if (e == hipSuccess) e = sr::launch_widen_u8(Bw, ln, B8, ldb, K, N, st);
-        if (e == hipSuccess && acc) e = sr::launch_widen_u8(Cw, ln, C8, ldc, R, N, st);
-        if (e == hipSuccess) e = sr::launch_ad_mul(true, Cw, ln, Aw, lk, Bw, ln, R, K, N, acc, st);
-        if (e == hipSuccess) e = sr::launch_narrow_u8(C8, ldc, Cw, ln, R, N, st);
-        work_free(w, st);
+        return device_fail(e, "semiring_mul launch");
     }
-    if (e != hipSuccess) return device_fail(e, "semiring_mul launch");
-    return ok();
+    rc = mul_compute(base_kind(kind), C, ldc, nA, lk, nB, ln, R, K, N, acc, false, st);
+    if (rc == SR_OK) {
+        e = sr::launch_ewise((int)es, sr::EW_NOT, C, ldc, C, ldc, C, ldc, R, N, 0, st);
+        if (e != hipSuccess) rc = device_fail(e, "semiring_mul launch");
+    }
+    work_free(w, st);
+    return rc == SR_OK ? ok() : rc;
 }
 
-int semiring_add(int kind, void *C, int64_t ldc, const void *A, int64_t lda, const void *B,
-                 int64_t ldb, int64_t R, int64_t N, void *stream) {
-    if (!valid_kind(kind)) return fail(SR_EINVAL, "semiring_add: invalid kind %d", kind);
-    if (R < 0 || N < 0) return fail(SR_EINVAL, "semiring_add: negative size");
+}  // extern "C"
+
+namespace {
+
+// Validation shared by semiring_add and semiring_ewise (B unused for NOT).
+int ewise_checked(const char *fn, int kind, int op, void *C, int64_t ldc, const void *A,
+                  int64_t lda, const void *B, int64_t ldb, int64_t R, int64_t N, void *stream) {
+    if (!valid_kind(kind)) return fail(SR_EINVAL, "%s: invalid kind %d", fn, kind);
+    if (op < sr::EW_AND || op > sr::EW_NOT) return fail(SR_EINVAL, "%s: invalid op %d", fn, op);
+    if (R < 0 || N < 0) return fail(SR_EINVAL, "%s: negative size", fn);
+    const bool unary = op == sr::EW_NOT;
     int rc;
     if ((rc = check_matrix(kind, "C", C, ldc, R, N)) != SR_OK) return rc;
     if ((rc = check_matrix(kind, "A", A, lda, R, N)) != SR_OK) return rc;
-    if ((rc = check_matrix(kind, "B", B, ldb, R, N)) != SR_OK) return rc;
+    if (!unary && (rc = check_matrix(kind, "B", B, ldb, R, N)) != SR_OK) return rc;
     if (R == 0 || N == 0) return ok();
     const Span sc = span_of(kind, C, ldc, R);
     const bool same_a = (C == A && ldc == lda), same_b = (C == B && ldc == ldb);
     if ((!same_a && overlap(sc, span_of(kind, A, lda, R))) ||
-        (!same_b && overlap(sc, span_of(kind, B, ldb, R))))
-        return fail(SR_EALIAS, "semiring_add: C partially overlaps A or B");
+        (!unary && !same_b && overlap(sc, span_of(kind, B, ldb, R))))
+        return fail(SR_EALIAS, "%s: C partially overlaps A or B", fn);
     const int64_t units = row_units(kind, N);
-    hipError_t e = sr::launch_add((int)unit_bytes(kind), C, ldc, A, lda, B, ldb, R, units,
-                                  as_stream(stream));
-    if (e != hipSuccess) return device_fail(e, "semiring_add launch");
+    hipError_t e = sr::launch_ewise((int)unit_bytes(kind), op, C, ldc, A, lda, unary ? A : B,
+                                    unary ? lda : ldb, R, units, N, as_stream(stream));
+    if (e != hipSuccess) return device_fail(e, "entrywise launch");
     return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int semiring_add(int kind, void *C, int64_t ldc, const void *A, int64_t lda, const void *B,
+                 int64_t ldb, int64_t R, int64_t N, void *stream) {
+    // (+) is max for anti-distance and Boolean entries, min for distances
+    return ewise_checked("semiring_add", kind, is_dist(kind) ? sr::EW_AND : sr::EW_OR, C, ldc, A,
+                         lda, B, ldb, R, N, stream);
+}
+
+int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_t lda,
+                   const void *B, int64_t ldb, int64_t R, int64_t N, void *stream) {
+    return ewise_checked("semiring_ewise", kind, op, C, ldc, A, lda, B, ldb, R, N, stream);
 }
 
 int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream) {
@@ -236,10 +301,8 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
     if (flags & ~(unsigned)(SR_REFLEXIVE | SR_BOOL_BITWISE | SR_BOOL_MFMA | SR_SERIAL_PHASES))
         return fail(SR_EINVAL, "closure: unknown flags 0x%x", flags);
     const bool serial = (flags & SR_SERIAL_PHASES) != 0;
-    if (flags & SR_REFLEXIVE)
-        return fail(SR_EUNSUPPORTED, "closure: the reflexive closure I (+) T is not built");
     if (flags & SR_BOOL_MFMA)
-        return fail(SR_EUNSUPPORTED, "closure: the int8 matrix-core Boolean path is not built");
+        return fail(SR_EUNSUPPORTED, "closure: the int8 matrix-core path is for products only");
     if (D < 0) return fail(SR_EINVAL, "closure: negative size");
     if (D > INT32_MAX) return fail(SR_EINVAL, "closure: sizes above 2^31-1 are not supported");
     int rc;
@@ -247,11 +310,15 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
     if (D == 0) return ok();
     hipStream_t st = as_stream(stream);
     hipError_t e = hipSuccess;
-    if (kind == SR_BOOL) {
+    const int es = (int)unit_bytes(kind);
+    // distance closure (dransclose) by De Morgan: not closure(not T)
+    if (is_dist(kind)) e = sr::launch_ewise(es, sr::EW_NOT, T, ldt, T, ldt, T, ldt, D, D, 0, st);
+    const int ak = base_kind(kind);
+    if (e == hipSuccess && ak == SR_BOOL) {
         e = sr::launch_bool_closure(static_cast<uint64_t *>(T), ldt, D, serial, st);
-    } else if (kind == SR_ANTIDIST_U16) {
+    } else if (e == hipSuccess && ak == SR_ANTIDIST_U16) {
         e = sr::launch_ad_closure(false, static_cast<uint16_t *>(T), ldt, D, serial, st);
-    } else {
+    } else if (e == hipSuccess) {
         const int64_t lw = round_up(D, 64);
         void *w = nullptr;
         if ((rc = work_alloc(&w, (size_t)(D * lw) * 2, st)) != SR_OK) return rc;
@@ -261,6 +328,14 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
         if (e == hipSuccess) e = sr::launch_ad_closure(true, Tw, lw, D, serial, st);
         if (e == hipSuccess) e = sr::launch_narrow_u8(T8, ldt, Tw, lw, D, D, st);
         work_free(w, st);
+    }
+    if (e == hipSuccess && is_dist(kind))
+        e = sr::launch_ewise(es, sr::EW_NOT, T, ldt, T, ldt, T, ldt, D, D, 0, st);
+    // reflexive closure I (+) T (eq. rtc): the diagonal of the multiplicative
+    // identity -- S (anti-distance), 0 (distance), 1 (Boolean)
+    if (e == hipSuccess && (flags & SR_REFLEXIVE)) {
+        const uint32_t one = is_dist(kind) ? 0u : (kind == SR_ANTIDIST_U8 ? 255u : 65535u);
+        e = sr::launch_diag(es, T, ldt, D, one, st);
     }
     if (e != hipSuccess) return device_fail(e, "closure launch");
     return ok();
@@ -273,8 +348,6 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
         return fail(SR_EUNSUPPORTED, "closure_batched: Boolean batches are not built");
     if (flags & ~(unsigned)SR_REFLEXIVE)
         return fail(SR_EINVAL, "closure_batched: unknown flags 0x%x", flags);
-    if (flags & SR_REFLEXIVE)
-        return fail(SR_EUNSUPPORTED, "closure_batched: the reflexive closure is not built");
     if (count < 0) return fail(SR_EINVAL, "closure_batched: negative count");
     if (count == 0) return ok();
     if (count > INT32_MAX) return fail(SR_EINVAL, "closure_batched: count above 2^31-1");
@@ -296,7 +369,7 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
             return fail(SR_EALIAS, "closure_batched: two matrices of the batch overlap");
 
     hipStream_t st = as_stream(stream);
-    const bool s8 = kind == SR_ANTIDIST_U8;
+    const bool s8 = base_kind(kind) == SR_ANTIDIST_U8;
     // largest first (ties keep the caller's order)
     std::vector<int64_t> order((size_t)count);
     std::iota(order.begin(), order.end(), 0);
@@ -337,7 +410,8 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
             off += (size_t)d.D * (size_t)d.ld;
         }
     }
-    hipError_t e = sr::launch_ad_closure_batched(s8, plan.get(), h.data(), count, w, st);
+    hipError_t e = sr::launch_ad_closure_batched(s8, plan.get(), h.data(), count, w, is_dist(kind),
+                                                 (flags & SR_REFLEXIVE) != 0, st);
     work_free(w, st);
     if (e != hipSuccess) return device_fail(e, "closure_batched launch");
     return ok();

@@ -119,8 +119,10 @@ k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, in
         dev::fw_update_wave<kUTM, kUNW, S8, false>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
 }
 
-// uint8 <-> uint16 for every graph of a batch (workgroup g: graph g).
-__global__ void __launch_bounds__(256) k_batch_widen(const BatchDesc *desc) {
+// uint8 <-> uint16 for every graph of a batch (workgroup g: graph g); with
+// neg the entries are complemented on the way (255 - a: distance <->
+// anti-distance).
+__global__ void __launch_bounds__(256) k_batch_widen(const BatchDesc *desc, int neg) {
     const BatchDesc d = desc[blockIdx.x];
     const int64_t gpr = ((int64_t)d.D + 7) >> 3;
     for (int64_t g = threadIdx.x; g < (int64_t)d.D * gpr; g += 256) {
@@ -128,7 +130,8 @@ __global__ void __launch_bounds__(256) k_batch_widen(const BatchDesc *desc) {
         const uint8_t *s = d.T8 + row * d.ld8 + c0;
         uint16_t v[8];
 #pragma unroll
-        for (int i = 0; i < 8; i++) v[i] = (c0 + i < d.D) ? (uint16_t)s[i] : (uint16_t)0;
+        for (int i = 0; i < 8; i++)
+            v[i] = (c0 + i < d.D) ? (uint16_t)(neg ? (uint8_t)~s[i] : s[i]) : (uint16_t)0;
         uint4 o;
         o.x = v[0] | ((uint32_t)v[1] << 16);
         o.y = v[2] | ((uint32_t)v[3] << 16);
@@ -138,7 +141,7 @@ __global__ void __launch_bounds__(256) k_batch_widen(const BatchDesc *desc) {
     }
 }
 
-__global__ void __launch_bounds__(256) k_batch_narrow(const BatchDesc *desc) {
+__global__ void __launch_bounds__(256) k_batch_narrow(const BatchDesc *desc, int neg) {
     const BatchDesc d = desc[blockIdx.x];
     const int64_t gpr = ((int64_t)d.D + 7) >> 3;
     for (int64_t g = threadIdx.x; g < (int64_t)d.D * gpr; g += 256) {
@@ -148,7 +151,30 @@ __global__ void __launch_bounds__(256) k_batch_narrow(const BatchDesc *desc) {
         uint8_t *dst = d.T8 + row * d.ld8 + c0;
 #pragma unroll
         for (int i = 0; i < 8; i++)
-            if (c0 + i < d.D) dst[i] = (uint8_t)(ww[i >> 1] >> (16 * (i & 1)));
+            if (c0 + i < d.D) {
+                const uint8_t x = (uint8_t)(ww[i >> 1] >> (16 * (i & 1)));
+                dst[i] = neg ? (uint8_t)~x : x;
+            }
+    }
+}
+
+// uint16 entries complemented in place (65535 - a), every graph.
+__global__ void __launch_bounds__(256) k_batch_not(const BatchDesc *desc) {
+    const BatchDesc d = desc[blockIdx.x];
+    for (int64_t g = threadIdx.x; g < (int64_t)d.D * d.D; g += 256) {
+        uint16_t *e = d.T + (g / d.D) * d.ld + (g % d.D);
+        *e = (uint16_t)~*e;
+    }
+}
+
+// Diagonal of every graph := value, on the uint8 (T8) or uint16 (T) matrices.
+__global__ void __launch_bounds__(256) k_batch_diag(const BatchDesc *desc, int u8, uint32_t value) {
+    const BatchDesc d = desc[blockIdx.x];
+    for (int64_t i = threadIdx.x; i < d.D; i += 256) {
+        if (u8)
+            d.T8[i * d.ld8 + i] = (uint8_t)value;
+        else
+            d.T[i * d.ld + i] = (uint16_t)value;
     }
 }
 
@@ -232,7 +258,8 @@ size_t batch_plan_bytes(const BatchPlan *plan, int64_t count) {
 }
 
 hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const BatchDesc *host_desc,
-                                     int64_t count, void *dev_buf, hipStream_t st) {
+                                     int64_t count, void *dev_buf, bool dual, bool reflexive,
+                                     hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const BatchPlan &p = *plan;
     const size_t desc_bytes = desc_bytes_of(count);
@@ -252,7 +279,11 @@ hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const Batch
     const BatchDesc *desc = static_cast<const BatchDesc *>(dev_buf);
     const Item *items =
         reinterpret_cast<const Item *>(static_cast<const char *>(dev_buf) + desc_bytes);
-    if (s8) hipLaunchKernelGGL(k_batch_widen, dim3((unsigned)count), dim3(256), 0, st, desc);
+    const unsigned ng = (unsigned)count;
+    if (s8)
+        hipLaunchKernelGGL(k_batch_widen, dim3(ng), dim3(256), 0, st, desc, dual ? 1 : 0);
+    else if (dual)
+        hipLaunchKernelGGL(k_batch_not, dim3(ng), dim3(256), 0, st, desc);
     for (size_t kb = 0; kb < p.pivot.size(); kb++) {
         const Launch &a = p.pivot[kb], &b = p.panels[kb], &c = p.update[kb];
         if (a.n_wg > 0) {
@@ -281,7 +312,15 @@ hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const Batch
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (s8) hipLaunchKernelGGL(k_batch_narrow, dim3((unsigned)count), dim3(256), 0, st, desc);
+    if (s8)
+        hipLaunchKernelGGL(k_batch_narrow, dim3(ng), dim3(256), 0, st, desc, dual ? 1 : 0);
+    else if (dual)
+        hipLaunchKernelGGL(k_batch_not, dim3(ng), dim3(256), 0, st, desc);
+    if (reflexive) {
+        // the multiplicative identity's diagonal: S (anti-distance), 0 (distance)
+        const uint32_t one = dual ? 0u : (s8 ? 255u : 65535u);
+        hipLaunchKernelGGL(k_batch_diag, dim3(ng), dim3(256), 0, st, desc, s8 ? 1 : 0, one);
+    }
     return hipGetLastError();
 }
 

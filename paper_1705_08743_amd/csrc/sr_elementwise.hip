@@ -1,6 +1,9 @@
-// Entrywise (+) of two matrices (Sec. II matrix addition; the `|` operator of
-// the entrywise table in Sec. V): max for anti-distance entries, OR for
-// Boolean words.  One thread per 16-byte group of a row; HBM-bound.
+// Entrywise operations of the table in Sec. V -- and = min, or = max (the
+// matrix (+) of Sec. II), xor = |a - b|, not = S - a -- on anti-distance or
+// distance entries (uint8 / uint16, where S - a is the bitwise complement) and
+// on Boolean words (AND, OR, XOR, NOT with the padding bits kept zero).  One
+// thread per 16-byte group of a row; HBM-bound.  Also the diagonal write of
+// the reflexive closure I (+) T (eq. rtc).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -12,70 +15,141 @@ namespace {
 typedef uint8_t u8x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 
-template <int ES>
-__device__ __forceinline__ uint32_t op_word(uint32_t a, uint32_t b) {
-    if (ES == 1)
-        return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u8x4, a),
-                                                                      __builtin_bit_cast(u8x4, b)));
-    if (ES == 2)
-        return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
-                                                                      __builtin_bit_cast(u16x2, b)));
-    return a | b;
+template <typename V>
+__device__ __forceinline__ uint32_t lanes_op(int op, uint32_t a, uint32_t b) {
+    const V x = __builtin_bit_cast(V, a), y = __builtin_bit_cast(V, b);
+    V r;
+    if (op == EW_AND)
+        r = __builtin_elementwise_min(x, y);
+    else if (op == EW_OR)
+        r = __builtin_elementwise_max(x, y);
+    else  // EW_XOR: |a - b|
+        r = __builtin_elementwise_max(x, y) - __builtin_elementwise_min(x, y);
+    return __builtin_bit_cast(uint32_t, r);
 }
 
-// Row strides in bytes (multiples of 16); nbytes = valid bytes per row.
-template <int ES>
+// One 32-bit word of a row: OP on entries of ES bytes (1, 2) or on bits (8).
+template <int ES, int OP>
+__device__ __forceinline__ uint32_t op_word(uint32_t a, uint32_t b) {
+    if (OP == EW_NOT) return ~a;
+    if (ES == 1) return lanes_op<u8x4>(OP, a, b);
+    if (ES == 2) return lanes_op<u16x2>(OP, a, b);
+    return OP == EW_AND ? (a & b) : (OP == EW_OR ? (a | b) : (a ^ b));
+}
+
+// Row strides in bytes (multiples of 16); nbytes = valid bytes per row;
+// nbits (Boolean NOT only): valid bits per row, the rest of the row's words
+// are written as zero.
+template <int ES, int OP>
 __global__ void __launch_bounds__(256)
-k_add(uint8_t *C, int64_t ldc, const uint8_t *A, int64_t lda, const uint8_t *B, int64_t ldb,
-      int64_t R, int64_t nbytes) {
+k_ewise(uint8_t *C, int64_t ldc, const uint8_t *A, int64_t lda, const uint8_t *B, int64_t ldb,
+        int64_t R, int64_t nbytes, int64_t nbits) {
     const int64_t gpr = (nbytes + 15) >> 4;
     const int64_t total = R * gpr;
     for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < total;
          g += (int64_t)gridDim.x * 256) {
         const int64_t row = g / gpr, b0 = (g % gpr) * 16;
         const uint4 a = *reinterpret_cast<const uint4 *>(A + row * lda + b0);
-        const uint4 b = *reinterpret_cast<const uint4 *>(B + row * ldb + b0);
-        uint4 c;
-        c.x = op_word<ES>(a.x, b.x);
-        c.y = op_word<ES>(a.y, b.y);
-        c.z = op_word<ES>(a.z, b.z);
-        c.w = op_word<ES>(a.w, b.w);
+        uint4 b = a;
+        if (OP != EW_NOT) b = *reinterpret_cast<const uint4 *>(B + row * ldb + b0);
+        uint32_t cw[4] = {op_word<ES, OP>(a.x, b.x), op_word<ES, OP>(a.y, b.y),
+                          op_word<ES, OP>(a.z, b.z), op_word<ES, OP>(a.w, b.w)};
+        if (ES == 8 && OP == EW_NOT) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int64_t first = 8 * (b0 + 4 * q);  // first bit of this word
+                const int64_t valid = nbits - first;
+                if (valid <= 0)
+                    cw[q] = 0u;
+                else if (valid < 32)
+                    cw[q] &= (1u << valid) - 1u;
+            }
+        }
         uint8_t *dst = C + row * ldc + b0;
         if (b0 + 16 <= nbytes) {
-            *reinterpret_cast<uint4 *>(dst) = c;
+            *reinterpret_cast<uint4 *>(dst) = uint4{cw[0], cw[1], cw[2], cw[3]};
         } else {
-            const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
             for (int i = 0; i < 16 && b0 + i < nbytes; i++)
                 dst[i] = (uint8_t)(cw[i >> 2] >> (8 * (i & 3)));
         }
     }
 }
 
+template <int ES>
+hipError_t ewise_es(int op, uint8_t *c, int64_t ldcb, const uint8_t *a, int64_t ldab,
+                    const uint8_t *b, int64_t ldbb, int64_t R, int64_t nbytes, int64_t nbits,
+                    unsigned blocks, hipStream_t st) {
+    switch (op) {
+        case EW_AND:
+            hipLaunchKernelGGL((k_ewise<ES, EW_AND>), dim3(blocks), dim3(256), 0, st, c, ldcb, a,
+                               ldab, b, ldbb, R, nbytes, nbits);
+            break;
+        case EW_OR:
+            hipLaunchKernelGGL((k_ewise<ES, EW_OR>), dim3(blocks), dim3(256), 0, st, c, ldcb, a,
+                               ldab, b, ldbb, R, nbytes, nbits);
+            break;
+        case EW_XOR:
+            hipLaunchKernelGGL((k_ewise<ES, EW_XOR>), dim3(blocks), dim3(256), 0, st, c, ldcb, a,
+                               ldab, b, ldbb, R, nbytes, nbits);
+            break;
+        default:
+            hipLaunchKernelGGL((k_ewise<ES, EW_NOT>), dim3(blocks), dim3(256), 0, st, c, ldcb, a,
+                               ldab, b, ldbb, R, nbytes, nbits);
+            break;
+    }
+    return hipGetLastError();
+}
+
+// Diagonal of a D x D matrix: entries set to `value` (ES = 1, 2), or bit i of
+// row i set (ES = 8, Boolean words).  One thread per row.
+template <int ES>
+__global__ void __launch_bounds__(256) k_diag(uint8_t *T, int64_t ldb, int64_t D, uint32_t value) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= D) return;
+    uint8_t *row = T + i * ldb;
+    if (ES == 1)
+        row[i] = (uint8_t)value;
+    else if (ES == 2)
+        reinterpret_cast<uint16_t *>(row)[i] = (uint16_t)value;
+    else
+        reinterpret_cast<uint32_t *>(row)[i >> 5] |= 1u << (i & 31);
+}
+
 }  // namespace
 
-hipError_t launch_add(int elem_bytes, void *C, int64_t ldc, const void *A, int64_t lda,
-                      const void *B, int64_t ldb, int64_t R, int64_t N, hipStream_t stream) {
+hipError_t launch_ewise(int elem_bytes, int op, void *C, int64_t ldc, const void *A, int64_t lda,
+                        const void *B, int64_t ldb, int64_t R, int64_t N, int64_t nbits,
+                        hipStream_t stream) {
     const int64_t nbytes = N * elem_bytes;
     const int64_t groups = R * ((nbytes + 15) / 16);
     if (groups == 0) return hipSuccess;
-    const int64_t blocks = groups < 256 * 2048 ? (groups + 255) / 256 : 2048;
+    const unsigned blocks = (unsigned)(groups < 256 * 2048 ? (groups + 255) / 256 : 2048);
     uint8_t *c = static_cast<uint8_t *>(C);
     const uint8_t *a = static_cast<const uint8_t *>(A);
     const uint8_t *b = static_cast<const uint8_t *>(B);
     const int64_t e = elem_bytes;
     switch (elem_bytes) {
-        case 1:
-            hipLaunchKernelGGL(k_add<1>, dim3((unsigned)blocks), dim3(256), 0, stream, c, ldc * e, a,
-                               lda * e, b, ldb * e, R, nbytes);
-            break;
-        case 2:
-            hipLaunchKernelGGL(k_add<2>, dim3((unsigned)blocks), dim3(256), 0, stream, c, ldc * e, a,
-                               lda * e, b, ldb * e, R, nbytes);
-            break;
-        default:
-            hipLaunchKernelGGL(k_add<8>, dim3((unsigned)blocks), dim3(256), 0, stream, c, ldc * e, a,
-                               lda * e, b, ldb * e, R, nbytes);
-            break;
+        case 1: return ewise_es<1>(op, c, ldc * e, a, lda * e, b, ldb * e, R, nbytes, nbits, blocks, stream);
+        case 2: return ewise_es<2>(op, c, ldc * e, a, lda * e, b, ldb * e, R, nbytes, nbits, blocks, stream);
+        default: return ewise_es<8>(op, c, ldc * e, a, lda * e, b, ldb * e, R, nbytes, nbits, blocks, stream);
+    }
+}
+
+hipError_t launch_add(int elem_bytes, void *C, int64_t ldc, const void *A, int64_t lda,
+                      const void *B, int64_t ldb, int64_t R, int64_t N, hipStream_t stream) {
+    return launch_ewise(elem_bytes, EW_OR, C, ldc, A, lda, B, ldb, R, N, 0, stream);
+}
+
+hipError_t launch_diag(int elem_bytes, void *T, int64_t ld, int64_t D, uint32_t value,
+                       hipStream_t stream) {
+    if (D <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((D + 255) / 256));
+    uint8_t *t = static_cast<uint8_t *>(T);
+    const int64_t ldb = ld * elem_bytes;
+    switch (elem_bytes) {
+        case 1: hipLaunchKernelGGL(k_diag<1>, grid, dim3(256), 0, stream, t, ldb, D, value); break;
+        case 2: hipLaunchKernelGGL(k_diag<2>, grid, dim3(256), 0, stream, t, ldb, D, value); break;
+        default: hipLaunchKernelGGL(k_diag<8>, grid, dim3(256), 0, stream, t, ldb, D, value); break;
     }
     return hipGetLastError();
 }

@@ -58,10 +58,23 @@ hipError_t launch_bool_mul_mfma(uint64_t *C, int64_t ldc, const uint64_t *A, int
                                 const uint64_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                                 bool accumulate, void *work, hipStream_t stream);
 
-// Entrywise (+): elem_bytes 1 or 2 -> max, 8 -> OR of words.  Widths in
-// elements (words for Boolean).
+// Entrywise operations (values of the op argument; the table of Sec. V):
+// and = min, or = max, xor = |a - b|, not = S - a; on Boolean words AND, OR,
+// XOR, NOT.
+enum { EW_AND = 0, EW_OR = 1, EW_XOR = 2, EW_NOT = 3 };
+// elem_bytes 1 or 2: entries; 8: Boolean 64-bit words.  Widths N in elements
+// (words for Boolean); nbits: bits per Boolean row (Boolean NOT clears the
+// bits beyond it).  B is not read for EW_NOT.
+hipError_t launch_ewise(int elem_bytes, int op, void *C, int64_t ldc, const void *A, int64_t lda,
+                        const void *B, int64_t ldb, int64_t R, int64_t N, int64_t nbits,
+                        hipStream_t stream);
+// Entrywise (+) (EW_OR).
 hipError_t launch_add(int elem_bytes, void *C, int64_t ldc, const void *A, int64_t lda,
                       const void *B, int64_t ldb, int64_t R, int64_t N, hipStream_t stream);
+// Diagonal of a D x D matrix: entries := value (elem_bytes 1, 2), or bit i of
+// row i set (8).
+hipError_t launch_diag(int elem_bytes, void *T, int64_t ld, int64_t D, uint32_t value,
+                       hipStream_t stream);
 
 // Batched anti-distance closure.  `host_desc` holds `count` descriptors,
 // already ordered largest-first; the launcher uploads them with the plan's
@@ -80,8 +93,12 @@ struct BatchPlan;
 BatchPlan *batch_plan_create(const BatchDesc *host_desc, int64_t count);
 void batch_plan_destroy(BatchPlan *plan);
 size_t batch_plan_bytes(const BatchPlan *plan, int64_t count);
+// dual: the batch holds distance matrices (complemented, S - a, before and
+// after the anti-distance closure); reflexive: the diagonal is then set to
+// the multiplicative identity (S for anti-distance, 0 for distance).
 hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const BatchDesc *host_desc,
-                                     int64_t count, void *dev_buf, hipStream_t stream);
+                                     int64_t count, void *dev_buf, bool dual, bool reflexive,
+                                     hipStream_t stream);
 
 // Second stream of a closure (sr_runtime.cpp), one per (device, caller
 // stream), created on first use at default priority.  aux_acquire() returns it

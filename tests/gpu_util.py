@@ -7,11 +7,21 @@ import numpy as np
 import oracle
 import synthgen
 
-S_OF = {1: 255, 2: 65535}
+S_OF = {1: 255, 2: 65535, 3: 255, 4: 65535}
 
 
 def np_dtype(kind):
-    return {1: np.uint8, 2: np.uint16}[kind]
+    return {1: np.uint8, 2: np.uint16, 3: np.uint8, 4: np.uint16}[kind]
+
+
+def rand_dist(R, C, kind, gen, p=0.3, wmax=None):
+    """Distance entries for a distance kind: present with probability p,
+    distance uniform in [0, wmax], absent = S."""
+    S = S_OF[kind]
+    wmax = S if wmax is None else wmax
+    present = gen.random((R, C)) < p
+    w = gen.integers(0, wmax + 1, size=(R, C))
+    return np.where(present, np.minimum(w, S), S).astype(np_dtype(kind))
 
 
 def rand_antidist(R, C, kind, gen, p=0.3, wmax=None, heavy=0.0):

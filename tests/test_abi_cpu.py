@@ -93,10 +93,28 @@ def test_closure_rejects_bad_arguments(L):
     assert L.closure(U16, P, 8, -1, 0, None) == sr.SR_EINVAL
     assert L.closure(U16, P, 4, 8, 0, None) == sr.SR_EINVAL
     assert L.closure(U16, P + 8, 8, 8, 0, None) == sr.SR_EALIGN
-    assert L.closure(U16, P, 8, 8, sr.SR_REFLEXIVE, None) == sr.SR_EUNSUPPORTED
     assert L.closure(sr.SR_BOOL, P, 2, 8, sr.SR_BOOL_MFMA, None) == sr.SR_EUNSUPPORTED
     assert L.closure(U16, P, 8, 8, 0x40, None) == sr.SR_EINVAL
     assert L.closure(sr.SR_BOOL, P, 1, 8, 0, None) == sr.SR_EALIGN
+
+
+def test_ewise_and_distance_kinds_reject_bad_arguments(L):
+    f = L.semiring_ewise
+    U16 = sr.SR_ANTIDIST_U16
+    assert f(U16, 7, P, 8, P + 4096, 8, P + 8192, 8, 4, 4, None) == sr.SR_EINVAL
+    assert "invalid op" in L.sr_last_error().decode()
+    assert f(U16, -1, P, 8, P + 4096, 8, P + 8192, 8, 4, 4, None) == sr.SR_EINVAL
+    assert f(9, sr.SR_EW_AND, P, 8, P + 4096, 8, P + 8192, 8, 4, 4, None) == sr.SR_EINVAL
+    assert f(U16, sr.SR_EW_OR, P + 2, 8, P + 4096, 8, P + 8192, 8, 4, 4, None) == sr.SR_EALIGN
+    assert f(U16, sr.SR_EW_XOR, P, 8, P + 16, 8, P + 8192, 8, 4, 4, None) == sr.SR_EALIAS
+    assert f(U16, sr.SR_EW_AND, P, 8, P + 4096, 8, NULL, 8, 4, 4, None) == sr.SR_EINVAL
+    assert f(U16, sr.SR_EW_NOT, NULL, 8, NULL, 8, NULL, 8, 0, 4, None) == sr.SR_OK
+    for kind in (sr.SR_DISTANCE_U8, sr.SR_DISTANCE_U16):
+        assert mul(L, kind, P + 1, 16, P + 4096, 16, P + 8192, 16, 4, 4, 4) == sr.SR_EALIGN
+        assert L.closure(kind, P, 2, 8, 0, None) == sr.SR_EINVAL  # ld < D
+        assert L.closure(kind, P, 16, 16, 0x40, None) == sr.SR_EINVAL
+    assert mul(L, sr.SR_DISTANCE_U16, P, 8, P + 4096, 8, P + 8192, 8, 4, 4, 4,
+               sr.SR_BOOL_MFMA) == sr.SR_EINVAL
 
 
 def test_add_rejects_bad_arguments(L):
@@ -122,7 +140,6 @@ def test_batched_rejects_bad_arguments(L):
     assert f(U16, ptrs, lds, dims2, n, 0, None) == sr.SR_EINVAL  # ld 8 < 9
     ptrs3 = (ctypes.c_void_p * n)(P, P + 4100)
     assert f(U16, ptrs3, lds, dims, n, 0, None) == sr.SR_EALIGN
-    assert f(U16, ptrs, lds, dims, n, sr.SR_REFLEXIVE, None) == sr.SR_EUNSUPPORTED
 
 
 def test_error_is_thread_local(L):

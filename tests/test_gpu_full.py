@@ -118,3 +118,27 @@ def test_batched_config4_sample():
     for i in list(idx[:3]) + list(idx[-2:]) + [int(idx[len(idx) // 2])]:
         want = oracle.ad_closure(mats[i], 65535)
         assert np.array_equal(sr.to_host(devs[i]).astype(np.int64), want), mats[i].shape
+
+
+def test_distance_closure_d8192():
+    """Distance form of the headline input (entries = distances, S = no path):
+    sampled rows against the oracle's path definition through the De Morgan
+    law (not dransclose(A) = transclose(not A)), and the reflexive form's
+    diagonal."""
+    D = 8192
+    S = 65535
+    kind = sr.SR_DISTANCE_U16
+    A = (S - synthgen.cfg_antidist(D=D)[:, :D].astype(np.int64)).astype(np.uint16)
+    T = sr.to_device(kind, A)
+    T2 = sr.clone(T)
+    sr.closure(kind, T)
+    sr.closure(kind, T2, flags=sr.SR_REFLEXIVE)
+    torch.cuda.synchronize()
+    H = sr.to_host(T)
+    rows = sample_rows(D, 6, 21)
+    want = S - oracle.ad_closure_rows((S - A.astype(np.int64)).astype(np.int32), S, rows)
+    assert np.array_equal(H[rows].astype(np.int64), want.astype(np.int64))
+    H2 = sr.to_host(T2)
+    assert (np.diagonal(H2) == 0).all()
+    off = ~np.eye(D, dtype=bool)
+    assert np.array_equal(H2[off], H[off])

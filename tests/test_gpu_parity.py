@@ -9,7 +9,7 @@ import pytest
 import oracle
 import paper_1705_08743_amd as sr
 import synthgen
-from gpu_util import S_OF, np_dtype, rand_antidist, rand_bits, set_oracle_threads
+from gpu_util import S_OF, np_dtype, rand_antidist, rand_bits, rand_dist, set_oracle_threads
 
 pytestmark = pytest.mark.gpu
 
@@ -455,3 +455,140 @@ def test_bool_mul_mfma_accumulate_and_dense():
         nw = (N + 63) // 64
         assert np.array_equal(host(C1)[:, :nw], want[:, :nw])
         assert torch.equal(C1, C2)
+
+
+# ---------------------------------------------------------------------------
+# distance matrices (min, saturating +), entrywise operations, reflexive
+# ---------------------------------------------------------------------------
+DIST_KINDS = [sr.SR_DISTANCE_U16, sr.SR_DISTANCE_U8]
+
+
+@pytest.mark.parametrize("kind", DIST_KINDS)
+@pytest.mark.parametrize("R,K,N", [(1, 1, 1), (3, 5, 2), (65, 130, 129), (200, 37, 300),
+                                   (257, 8, 513)])
+def test_dist_mul(kind, R, K, N):
+    gen = synthgen.generator(7000 + R + K + N + kind)
+    S = S_OF[kind]
+    A = rand_dist(R, K, kind, gen, p=0.3)
+    B = rand_dist(K, N, kind, gen, p=0.3)
+    C = sr.empty(kind, R, N)
+    sr.semiring_mul(kind, C, dev(kind, A), dev(kind, B))
+    assert np.array_equal(host(C).astype(np.int64), oracle.dist_mul(A, B, S))
+    C0 = rand_dist(R, N, kind, gen, p=0.5)
+    Cd = dev(kind, C0)
+    sr.semiring_mul(kind, Cd, dev(kind, A), dev(kind, B), flags=sr.SR_ACCUMULATE)
+    assert np.array_equal(host(Cd).astype(np.int64), oracle.dist_mul(A, B, S, C=C0))
+
+
+@pytest.mark.parametrize("kind", DIST_KINDS)
+@pytest.mark.parametrize("D", [1, 2, 37, 129, 300, 513])
+def test_dist_closure(kind, D):
+    gen = synthgen.generator(7100 + D + kind)
+    S = S_OF[kind]
+    A = rand_dist(D, D, kind, gen, p=min(0.5, 3.0 / D), wmax=S // 4)
+    T = dev(kind, A)
+    sr.closure(kind, T)
+    want = oracle.dist_closure(A, S)
+    assert np.array_equal(host(T).astype(np.int64), want)
+    T2 = dev(kind, A)
+    sr.closure(kind, T2, flags=sr.SR_SERIAL_PHASES | sr.SR_REFLEXIVE)
+    assert np.array_equal(host(T2).astype(np.int64), oracle.reflexive(want, 0))
+
+
+@pytest.mark.parametrize("kind", AD_KINDS)
+def test_reflexive_closure_antidist(kind):
+    gen = synthgen.generator(7200 + kind)
+    S = S_OF[kind]
+    for D in (1, 130, 300):
+        A = rand_antidist(D, D, kind, gen, p=min(0.5, 2.0 / D), wmax=S // 3)
+        T = dev(kind, A)
+        sr.closure(kind, T, flags=sr.SR_REFLEXIVE)
+        want = oracle.reflexive(oracle.ad_closure(A, S), S)
+        assert np.array_equal(host(T).astype(np.int64), want), D
+
+
+def test_reflexive_closure_bool():
+    gen = synthgen.generator(7300)
+    for D in (1, 65, 300, 600):
+        A = rand_bits(D, D, gen, min(0.5, 1.5 / D))
+        ldw = synthgen.aligned_ld_words(D)
+        Aw = synthgen.pack_bits(A, ldw)
+        T = dev(sr.SR_BOOL, Aw, cols=D)
+        sr.closure(sr.SR_BOOL, T, D=D, flags=sr.SR_REFLEXIVE)
+        want = oracle.reflexive(oracle.bool_closure(A), 1)
+        got = host(T)
+        assert np.array_equal(synthgen.unpack_bits(got, D), want), D
+        assert synthgen.padding_bits_clear(got, D)
+
+
+@pytest.mark.parametrize("kind", AD_KINDS + DIST_KINDS)
+@pytest.mark.parametrize("op,name", [(sr.SR_EW_AND, "and"), (sr.SR_EW_OR, "or"),
+                                     (sr.SR_EW_XOR, "xor"), (sr.SR_EW_NOT, "not")])
+def test_ewise(kind, op, name):
+    gen = synthgen.generator(7400 + kind * 10 + op)
+    S = S_OF[kind]
+    R, N = 77, 333
+    A = gen.integers(0, S + 1, size=(R, N)).astype(np_dtype(kind))
+    B = gen.integers(0, S + 1, size=(R, N)).astype(np_dtype(kind))
+    A[0, :3] = [0, S, S]
+    B[0, :3] = [S, 0, S]
+    C = sr.empty(kind, R, N)
+    sr.semiring_ewise(kind, op, C, dev(kind, A), None if name == "not" else dev(kind, B))
+    want = oracle.ewise(name, A, None if name == "not" else B, S)
+    assert np.array_equal(host(C).astype(np.int64), want)
+    # in place (C = A)
+    Ad = dev(kind, A)
+    sr.semiring_ewise(kind, op, Ad, Ad, None if name == "not" else dev(kind, B))
+    assert np.array_equal(host(Ad).astype(np.int64), want)
+
+
+@pytest.mark.parametrize("N", [1, 63, 64, 65, 200, 1000])
+@pytest.mark.parametrize("op,name", [(sr.SR_EW_AND, "and"), (sr.SR_EW_OR, "or"),
+                                     (sr.SR_EW_XOR, "xor"), (sr.SR_EW_NOT, "not")])
+def test_ewise_bool(N, op, name):
+    gen = synthgen.generator(7500 + N + op)
+    R = 37
+    ld = synthgen.aligned_ld_words(N)
+    Aw = synthgen.pack_bits(rand_bits(R, N, gen, 0.5), ld)
+    Bw = synthgen.pack_bits(rand_bits(R, N, gen, 0.5), ld)
+    C = sr.empty(sr.SR_BOOL, R, N)
+    sr.semiring_ewise(sr.SR_BOOL, op, C, dev(sr.SR_BOOL, Aw, cols=N),
+                      None if name == "not" else dev(sr.SR_BOOL, Bw, cols=N), N=N)
+    want = oracle.ewise_words(name, Aw, N, None if name == "not" else Bw)
+    nw = (N + 63) // 64
+    got = host(C)
+    assert np.array_equal(got[:, :nw], want[:, :nw])
+    assert synthgen.padding_bits_clear(got, N)
+
+
+@pytest.mark.parametrize("kind", DIST_KINDS)
+def test_dist_add_is_min(kind):
+    gen = synthgen.generator(7600 + kind)
+    A = rand_dist(50, 70, kind, gen, p=0.5)
+    B = rand_dist(50, 70, kind, gen, p=0.5)
+    C = sr.empty(kind, 50, 70)
+    sr.semiring_add(kind, C, dev(kind, A), dev(kind, B))
+    assert np.array_equal(host(C).astype(np.int64), np.minimum(A, B).astype(np.int64))
+
+
+@pytest.mark.parametrize("kind", AD_KINDS + DIST_KINDS)
+def test_closure_batched_dist_and_reflexive(kind):
+    """Batches of distance matrices, and the reflexive flag, for all kinds."""
+    gen = synthgen.generator(7700 + kind)
+    S = S_OF[kind]
+    sizes = [130, 7, 300, 1, 64]
+    if kind in DIST_KINDS:
+        mats = [rand_dist(n, n, kind, gen, p=min(0.5, 3.0 / n), wmax=S // 4) for n in sizes]
+        want = [oracle.reflexive(oracle.dist_closure(m, S), 0) for m in mats]
+    else:
+        mats = [rand_antidist(n, n, kind, gen, p=min(0.5, 3.0 / n), wmax=S // 4) for n in sizes]
+        want = [oracle.reflexive(oracle.ad_closure(m, S), S) for m in mats]
+    devs = [dev(kind, m) for m in mats]
+    sr.closure_batched(kind, devs, flags=sr.SR_REFLEXIVE)
+    for d, w, m in zip(devs, want, mats):
+        assert np.array_equal(host(d).astype(np.int64), w), m.shape
+    plain = [dev(kind, m) for m in mats]
+    sr.closure_batched(kind, plain)
+    for d, m in zip(plain, mats):
+        ref = oracle.dist_closure(m, S) if kind in DIST_KINDS else oracle.ad_closure(m, S)
+        assert np.array_equal(host(d).astype(np.int64), ref), m.shape
