@@ -11,7 +11,8 @@ Other workloads (--workload): bool16384 (Boolean closure, D = 16384, mean
 out-degree 3 plus planted strongly connected blocks), boolmul16384 (Boolean
 product A * A of that matrix, word-parallel and int8 matrix-core paths),
 mul1024 (uint16 product of two 1024 x 1024 graphs), u8fw8192 (uint8 closure,
-distances in [1, 200]), batched (4096 graphs, log-uniform sizes in [32, 1024],
+distances in [1, 200]), dfw8192 (the headline input as a distance matrix,
+closed with min and saturating +), batched (4096 graphs, log-uniform sizes in [32, 1024],
 uint16, one call vs one at a time), add8192 (entrywise max, HBM-bound), serve
 (continuously batched closure requests vs serial).
 
@@ -118,13 +119,18 @@ def cpu_baseline_fw(A, S, target_s, threads):
                       % (m, D, D, upd, dt)), threads
 
 
-def parity_rows(result_host, A, S, nrows, seed):
-    """Sampled rows of the GPU result against the oracle's path definition."""
+def parity_rows(result_host, A, S, nrows, seed, dual=False):
+    """Sampled rows of the GPU result against the oracle's path definition
+    (for distance matrices through the De Morgan law, not closure(not A))."""
     import numpy as np
     import oracle
     D = A.shape[0]
     rows = np.sort(np.random.default_rng(seed).choice(D, size=nrows, replace=False))
-    want = oracle.ad_closure_rows(A[:, :D], S, rows)
+    if dual:
+        nA = (S - A[:, :D].astype(np.int64)).astype(np.int32)
+        want = S - oracle.ad_closure_rows(nA, S, rows).astype(np.int64)
+    else:
+        want = oracle.ad_closure_rows(A[:, :D], S, rows)
     ok = bool(np.array_equal(result_host[rows, :D].astype(np.int64), want.astype(np.int64)))
     return {"rows_checked": int(nrows), "bit_exact": ok}
 
@@ -154,7 +160,7 @@ def kernel_timing_pass(args, torch, sr, kind, src, bufs, close):
     return phases
 
 
-def run_fw(args, torch, sr, kind, D, make_input, workload, S, metric):
+def run_fw(args, torch, sr, kind, D, make_input, workload, S, metric, dual=False):
     import numpy as np
     log("generating input D=%d ..." % D)
     A = make_input()
@@ -190,7 +196,8 @@ def run_fw(args, torch, sr, kind, D, make_input, workload, S, metric):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {sr.SR_ANTIDIST_U16: "u16", sr.SR_ANTIDIST_U8: "u8"}[kind],
+        "dtype": {sr.SR_ANTIDIST_U16: "u16", sr.SR_ANTIDIST_U8: "u8",
+                  sr.SR_DISTANCE_U16: "u16"}[kind],
         "data": "synthetic",
         "roofline": {"bound": "alu", "kernel": "k_ad_fw_update (update phase)",
                      "achieved": achieved, "peak": PEAK_ANTIDIST, "unit": "updates/s",
@@ -199,7 +206,7 @@ def run_fw(args, torch, sr, kind, D, make_input, workload, S, metric):
         "fraction_of_valu_roofline_whole_step": float(D) ** 3 / (ms_step * 1e-3) / PEAK_ANTIDIST,
     }
     if not args.no_parity:
-        out["parity"] = parity_rows(sr.to_host(bufs[-1]), host, S, args.parity_rows, 7)
+        out["parity"] = parity_rows(sr.to_host(bufs[-1]), host, S, args.parity_rows, 7, dual)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
         v, sample, cores = cpu_baseline_fw(host, S, args.cpu_seconds, args.cpu_threads)
@@ -478,8 +485,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fw8192",
-                    choices=["fw8192", "u8fw8192", "bool16384", "boolmul16384", "mul1024", "batched",
-                             "add8192", "serve"])
+                    choices=["fw8192", "u8fw8192", "dfw8192", "bool16384", "boolmul16384", "mul1024",
+                             "batched", "add8192", "serve"])
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--serve-calibration", type=int, default=24)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
@@ -519,6 +526,18 @@ def main():
         out["config"] = {"workload": "antidist_u8_floyd_warshall_D8192", "D": 8192,
                          "entries": "uint8, S=255", "edge_p": 0.05, "distances": "U[1,200]",
                          "pivot_block": 128, "parallelism": "single_gpu"}
+    elif args.workload == "dfw8192":
+        def dist_input():
+            import numpy as np
+            A = synthgen.cfg_antidist(D=8192)[:, :8192]
+            return (65535 - A.astype(np.int64)).astype(np.uint16)
+        out = run_fw(args, torch, sr, sr.SR_DISTANCE_U16, 8192, dist_input, "dfw8192", 65535,
+                     "semiring updates/s (D³/t) distance-matrix closure (min, saturating +) D=8192",
+                     dual=True)
+        out["config"] = {"workload": "distance_u16_closure_D8192", "D": 8192,
+                         "entries": "uint16 distances, 65535 = no path", "edge_p": 0.05,
+                         "distances": "U[1,1000]; 1% U[64536,65534]", "pivot_block": 128,
+                         "parallelism": "single_gpu"}
     elif args.workload == "bool16384":
         out = run_bool(args, torch, sr, synthgen)
     elif args.workload == "boolmul16384":
