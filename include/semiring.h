@@ -104,8 +104,9 @@ enum {
     SR_BOOL_BITWISE = 4u,  /* Boolean: force the word OR-AND kernels (the default) */
     SR_BOOL_MFMA = 8u,     /* Boolean semiring_mul: the int8 matrix-core path (exact; opt-in);
                               closure: SR_EUNSUPPORTED; any other kind: SR_EINVAL */
-    SR_SERIAL_PHASES = 16u /* closure: enqueue every phase on the caller's stream in order, without
-                              overlapping the next round's pivot and panels on a second stream */
+    SR_SERIAL_PHASES = 16u, /* closure: enqueue every phase on the caller's stream in order, without
+                               overlapping the next round's pivot and panels on a second stream */
+    SR_BOOL_M4R = 32u      /* Boolean semiring_mul: the "four Russians" table path */
 };
 
 /*

@@ -48,6 +48,7 @@ SR_REFLEXIVE = 2
 SR_BOOL_BITWISE = 4
 SR_BOOL_MFMA = 8
 SR_SERIAL_PHASES = 16
+SR_BOOL_M4R = 32
 
 ERROR_NAMES = {
     SR_EINVAL: "SR_EINVAL", SR_EALIAS: "SR_EALIAS", SR_EALIGN: "SR_EALIGN",
@@ -384,7 +385,7 @@ def to_host(t):
 
 __all__ = [
     "SR_BOOL", "SR_ANTIDIST_U8", "SR_ANTIDIST_U16", "SR_DISTANCE_U8", "SR_DISTANCE_U16",
-    "SR_EW_AND", "SR_EW_OR", "SR_EW_XOR", "SR_EW_NOT", "semiring_ewise", "SR_OK", "SR_EINVAL", "SR_EALIAS",
+    "SR_BOOL_M4R", "SR_EW_AND", "SR_EW_OR", "SR_EW_XOR", "SR_EW_NOT", "semiring_ewise", "SR_OK", "SR_EINVAL", "SR_EALIAS",
     "SR_EALIGN", "SR_ENOMEM", "SR_EDEVICE", "SR_EUNSUPPORTED", "SR_ACCUMULATE",
     "SR_REFLEXIVE", "SR_BOOL_BITWISE", "SR_BOOL_MFMA", "SR_SERIAL_PHASES", "SemiringError", "lib", "kind_of",
     "semiring_mul", "semiring_add", "closure", "closure_batched", "version", "shutdown",

@@ -126,11 +126,11 @@ void work_free(void *p, hipStream_t st) {
 
 // The product after validation; kind is SR_BOOL or an anti-distance kind.
 int mul_compute(int kind, void *C, int64_t ldc, const void *A, int64_t lda, const void *B,
-                int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, bool mfma,
+                int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, unsigned path,
                 hipStream_t st) {
     int rc;
     hipError_t e = hipSuccess;
-    if (kind == SR_BOOL && mfma) {
+    if (kind == SR_BOOL && path == SR_BOOL_MFMA) {
         void *w = nullptr;
         const size_t bytes = std::max<size_t>(sr::bool_mfma_work_bytes(R, K, N), 256);
         if ((rc = work_alloc(&w, bytes, st)) != SR_OK) return rc;
@@ -139,8 +139,10 @@ int mul_compute(int kind, void *C, int64_t ldc, const void *A, int64_t lda, cons
                                      static_cast<const uint64_t *>(B), ldb, R, K, N, acc, w, st);
         work_free(w, st);
     } else if (kind == SR_BOOL) {
+        const int bp = path == SR_BOOL_M4R ? sr::kBoolPathM4r
+                       : path == SR_BOOL_BITWISE ? sr::kBoolPathBitwise : sr::kBoolPathAuto;
         e = sr::launch_bool_mul(static_cast<uint64_t *>(C), ldc, static_cast<const uint64_t *>(A),
-                                lda, static_cast<const uint64_t *>(B), ldb, R, K, N, acc, st);
+                                lda, static_cast<const uint64_t *>(B), ldb, R, K, N, acc, bp, st);
     } else if (kind == SR_ANTIDIST_U16) {
         e = sr::launch_ad_mul(false, static_cast<uint16_t *>(C), ldc,
                               static_cast<const uint16_t *>(A), lda,
@@ -205,12 +207,13 @@ void sr_shutdown(void) {
 int semiring_mul(int kind, void *C, int64_t ldc, const void *A, int64_t lda, const void *B,
                  int64_t ldb, int64_t R, int64_t K, int64_t N, unsigned flags, void *stream) {
     if (!valid_kind(kind)) return fail(SR_EINVAL, "semiring_mul: invalid kind %d", kind);
-    if (flags & ~(unsigned)(SR_ACCUMULATE | SR_BOOL_BITWISE | SR_BOOL_MFMA))
+    const unsigned paths = flags & (SR_BOOL_BITWISE | SR_BOOL_MFMA | SR_BOOL_M4R);
+    if (flags & ~(unsigned)(SR_ACCUMULATE | SR_BOOL_BITWISE | SR_BOOL_MFMA | SR_BOOL_M4R))
         return fail(SR_EINVAL, "semiring_mul: unknown flags 0x%x", flags);
-    if ((flags & SR_BOOL_MFMA) && (flags & SR_BOOL_BITWISE))
-        return fail(SR_EINVAL, "semiring_mul: SR_BOOL_MFMA and SR_BOOL_BITWISE exclude each other");
-    if ((flags & SR_BOOL_MFMA) && kind != SR_BOOL)
-        return fail(SR_EINVAL, "semiring_mul: SR_BOOL_MFMA applies to SR_BOOL only");
+    if (paths & (paths - 1))
+        return fail(SR_EINVAL, "semiring_mul: at most one of SR_BOOL_BITWISE, SR_BOOL_MFMA, SR_BOOL_M4R");
+    if ((flags & (SR_BOOL_MFMA | SR_BOOL_M4R)) && kind != SR_BOOL)
+        return fail(SR_EINVAL, "semiring_mul: SR_BOOL_MFMA and SR_BOOL_M4R apply to SR_BOOL only");
     if (R < 0 || K < 0 || N < 0) return fail(SR_EINVAL, "semiring_mul: negative size");
     if (R > INT32_MAX || K > INT32_MAX || N > INT32_MAX)
         return fail(SR_EINVAL, "semiring_mul: sizes above 2^31-1 are not supported");
@@ -225,8 +228,7 @@ int semiring_mul(int kind, void *C, int64_t ldc, const void *A, int64_t lda, con
                     "semiring_mul: C overlaps A or B (the in-place form is closure())");
     const bool acc = (flags & SR_ACCUMULATE) != 0;
     hipStream_t st = as_stream(stream);
-    if (!is_dist(kind)) return mul_compute(kind, C, ldc, A, lda, B, ldb, R, K, N, acc,
-                                           (flags & SR_BOOL_MFMA) != 0, st);
+    if (!is_dist(kind)) return mul_compute(kind, C, ldc, A, lda, B, ldb, R, K, N, acc, paths, st);
     // distance product (min, saturating +) by De Morgan:
     // A + B = not((not A) (x) (not B)), with C complemented around it
     const int64_t es = unit_bytes(kind);
@@ -243,7 +245,7 @@ int semiring_mul(int kind, void *C, int64_t ldc, const void *A, int64_t lda, con
         work_free(w, st);
         return device_fail(e, "semiring_mul launch");
     }
-    rc = mul_compute(base_kind(kind), C, ldc, nA, lk, nB, ln, R, K, N, acc, false, st);
+    rc = mul_compute(base_kind(kind), C, ldc, nA, lk, nB, ln, R, K, N, acc, 0u, st);
     if (rc == SR_OK) {
         e = sr::launch_ewise((int)es, sr::EW_NOT, C, ldc, C, ldc, C, ldc, R, N, 0, st);
         if (e != hipSuccess) rc = device_fail(e, "semiring_mul launch");
@@ -298,8 +300,11 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
 
 int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream) {
     if (!valid_kind(kind)) return fail(SR_EINVAL, "closure: invalid kind %d", kind);
-    if (flags & ~(unsigned)(SR_REFLEXIVE | SR_BOOL_BITWISE | SR_BOOL_MFMA | SR_SERIAL_PHASES))
+    if (flags & ~(unsigned)(SR_REFLEXIVE | SR_BOOL_BITWISE | SR_BOOL_MFMA | SR_BOOL_M4R |
+                            SR_SERIAL_PHASES))
         return fail(SR_EINVAL, "closure: unknown flags 0x%x", flags);
+    if ((flags & SR_BOOL_BITWISE) && (flags & SR_BOOL_M4R))
+        return fail(SR_EINVAL, "closure: SR_BOOL_BITWISE and SR_BOOL_M4R exclude each other");
     const bool serial = (flags & SR_SERIAL_PHASES) != 0;
     if (flags & SR_BOOL_MFMA)
         return fail(SR_EUNSUPPORTED, "closure: the int8 matrix-core path is for products only");
@@ -315,7 +320,9 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
     if (is_dist(kind)) e = sr::launch_ewise(es, sr::EW_NOT, T, ldt, T, ldt, T, ldt, D, D, 0, st);
     const int ak = base_kind(kind);
     if (e == hipSuccess && ak == SR_BOOL) {
-        e = sr::launch_bool_closure(static_cast<uint64_t *>(T), ldt, D, serial, st);
+        const int path = (flags & SR_BOOL_M4R) ? sr::kBoolPathM4r
+                         : (flags & SR_BOOL_BITWISE) ? sr::kBoolPathBitwise : sr::kBoolPathAuto;
+        e = sr::launch_bool_closure(static_cast<uint64_t *>(T), ldt, D, serial, path, st);
     } else if (e == hipSuccess && ak == SR_ANTIDIST_U16) {
         e = sr::launch_ad_closure(false, static_cast<uint16_t *>(T), ldt, D, serial, st);
     } else if (e == hipSuccess) {

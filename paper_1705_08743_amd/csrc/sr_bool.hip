@@ -509,6 +509,164 @@ k_bool_fw_lookahead(uint32_t *T, int64_t ld, int D, int k0, int bs, BRect qa, BR
     }
 }
 
+// "Four Russians" tile (the paper mentions the method for the product and
+// leaves it out; here it serves the product and the closure's bulk update,
+// whose operands do not change during the update): C (|)= A * B for 256 rows
+// (thread t: row row0 + t) x kM4rWords words.  For each group of 8 inner
+// bits g, the workgroup builds in LDS the table L_g[v] = OR of the rows
+// 8g + b of B with bit b of v set (256 entries), then every row ORs in the
+// single entry picked by its 8 bits of A: one table read per row and group
+// instead of 8 masked ORs per word.  Table build: thread (p, w) = (t / 16,
+// t % 16) forms the 16 ORs of rows 8g..8g+3 in registers, ORs in its subset
+// p of rows 8g+4..8g+7 and writes entries 16p .. 16p + 15 of word w.  Two
+// tables alternate, so one barrier per group suffices (a table is rewritten
+// only after every thread has passed the next group's barrier).  Rows are
+// padded to kM4rStride words so that the 16-byte reads of 64 random entries
+// spread over the LDS banks.  K inner bits; rows >= K of B and bits >= K of A
+// count as zero; nwords: valid words of a C row from w0.
+constexpr int kM4rWords = 16, kM4rStride = 20;
+
+// TR rows per thread: thread t takes rows t, t + 256, ... (TR * 256 rows).
+// NT tables in LDS: 2 alternate (one barrier per group), 1 is rewritten after
+// a second barrier (half the LDS, so that kernels running beside this one
+// still find room).
+template <int TR, int NT>
+__device__ __forceinline__ void m4r_tile(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda,
+                                         const uint32_t *B, int64_t ldb, int nrows, int nw, int K,
+                                         bool accumulate, uint32_t (*lut)[256][kM4rStride]) {
+    constexpr int CN = kM4rWords;
+    const int t = threadIdx.x;
+    uint32_t acc[TR][CN];
+    const uint32_t *arow[TR];
+    uint32_t *crow[TR];
+    bool live[TR];
+#pragma unroll
+    for (int u = 0; u < TR; u++) {
+        live[u] = t + 256 * u < nrows;
+        const int64_t r = live[u] ? t + 256 * u : 0;
+        crow[u] = C + r * ldc;
+        arow[u] = A + r * lda;
+        if (accumulate && nw == CN) {
+#pragma unroll
+            for (int q = 0; q < CN / 4; q++) {
+                const uint4 v = reinterpret_cast<const uint4 *>(crow[u])[q];
+                acc[u][4 * q] = v.x, acc[u][4 * q + 1] = v.y;
+                acc[u][4 * q + 2] = v.z, acc[u][4 * q + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int w = 0; w < CN; w++) acc[u][w] = (accumulate && w < nw) ? crow[u][w] : 0u;
+        }
+    }
+    // table-builder role of this thread
+    const int bw = t & (CN - 1), bp = t >> 4;
+    const bool wok = bw < nw;
+    const int ngroups = (K + 7) >> 3;
+    // the 8 words of B a group needs are requested one group ahead, and each
+    // row's A word one word ahead, so that their latency overlaps work
+    auto fetch_b = [&](uint32_t(&dst)[8], int g) {
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int k = 8 * g + j;
+            dst[j] = (wok && k < K) ? B[(int64_t)k * ldb + bw] : 0u;
+        }
+    };
+    uint32_t a[TR], an[TR], bn[8];
+    fetch_b(bn, 0);
+#pragma unroll
+    for (int u = 0; u < TR; u++) an[u] = K > 0 ? arow[u][0] : 0u;  // A may be NULL when K = 0
+    for (int g = 0; g < ngroups; g++) {
+        uint32_t (*L)[kM4rStride] = lut[NT == 2 ? (g & 1) : 0];
+        uint32_t b[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) b[j] = bn[j];
+        if (g + 1 < ngroups) fetch_b(bn, g + 1);
+        if ((g & 3) == 0) {
+#pragma unroll
+            for (int u = 0; u < TR; u++) {
+                a[u] = an[u];
+                if (8 * g + 32 < K) an[u] = arow[u][(g >> 2) + 1];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (NT == 1 && g > 0) __syncthreads();  // the previous group's reads are done
+        uint32_t lo[16];
+        lo[0] = 0u;
+#pragma unroll
+        for (int v = 1; v < 16; v++) lo[v] = lo[v & (v - 1)] | b[__builtin_ctz(v)];
+        uint32_t hi = 0u;
+#pragma unroll
+        for (int j = 0; j < 4; j++) hi |= ((bp >> j) & 1) ? b[4 + j] : 0u;
+#pragma unroll
+        for (int v = 0; v < 16; v++) L[16 * bp + v][bw] = hi | lo[v];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < TR; u++) {
+            const uint32_t sel = (a[u] >> (8 * (g & 3))) & 0xFFu;
+            const uint4 *e = reinterpret_cast<const uint4 *>(L[sel]);
+#pragma unroll
+            for (int q = 0; q < CN / 4; q++) {
+                const uint4 v = e[q];
+                acc[u][4 * q] |= v.x, acc[u][4 * q + 1] |= v.y;
+                acc[u][4 * q + 2] |= v.z, acc[u][4 * q + 3] |= v.w;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < TR; u++) {
+        if (!live[u]) continue;
+        if (nw == CN) {
+#pragma unroll
+            for (int q = 0; q < CN / 4; q++)
+                reinterpret_cast<uint4 *>(crow[u])[q] =
+                    uint4{acc[u][4 * q], acc[u][4 * q + 1], acc[u][4 * q + 2], acc[u][4 * q + 3]};
+        } else {
+#pragma unroll
+            for (int w = 0; w < CN; w++)
+                if (w < nw) crow[u][w] = acc[u][w];
+        }
+    }
+}
+
+// Product with the four-Russians tile: workgroup (x, y) = words
+// [16x, 16x + 16) of rows [256 TR y, 256 TR (y + 1)).
+template <int TR>
+__global__ void __launch_bounds__(256)
+k_bool_mul_m4r(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
+               int64_t ldb, int64_t R, int K, int64_t nwords, int accumulate) {
+    __shared__ __align__(16) uint32_t lut[2][256][kM4rStride];
+    const int64_t row0 = (int64_t)blockIdx.y * 256 * TR, w0 = (int64_t)blockIdx.x * kM4rWords;
+    m4r_tile<TR, 2>(C + row0 * ldc + w0, ldc, A + row0 * lda, lda, B + w0, ldb,
+                 (int)min<int64_t>(256 * TR, R - row0), (int)min<int64_t>(kM4rWords, nwords - w0),
+                 K, accumulate != 0, lut);
+}
+
+// Bulk update of a closure round with the four-Russians tile: rows
+// [r0a, r0b) and [r1a, r1b), words [w0a, w0b) and [w1a, w1b), each range cut
+// into tiles of 512 rows x 16 words from its start; T_ij (|)= T_iK * T_Kj for
+// the pivot block K = [k0, k0 + bs).  The tables hold rows of the pivot block,
+// which the update does not write, and each row's A bits are its pivot-block
+// words, outside every tile it writes.
+struct MRect {
+    int r0a, r0b, r1a, r1b;
+    int w0a, w0b, w1a, w1b;
+};
+
+__global__ void __launch_bounds__(256)
+k_bool_fw_update_m4r(uint32_t *T, int64_t ld, int k0, int bs, MRect q, int nwch0, int nrch0,
+                     int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
+    __shared__ __align__(16) uint32_t lut[1][256][kM4rStride];
+    const int bx = (int)blockIdx.x, by = (int)blockIdx.y;
+    const int w0 = bx < nwch0 ? q.w0a + bx * kM4rWords : q.w1a + (bx - nwch0) * kM4rWords;
+    const int wend = bx < nwch0 ? q.w0b : q.w1b;
+    const int r0 = by < nrch0 ? q.r0a + by * 512 : q.r1a + (by - nrch0) * 512;
+    const int rend = by < nrch0 ? q.r0b : q.r1b;
+    m4r_tile<2, 1>(T + (int64_t)r0 * ld + w0, ld, T + (int64_t)r0 * ld + (k0 >> 5), ld,
+                T + (int64_t)k0 * ld + w0, ld, min(512, rend - r0), min(kM4rWords, wend - w0), bs,
+                true, lut);
+}
+
 template <int NWB>
 hipError_t mul_nwb(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
                    int64_t ldb, int64_t R, int64_t K, int64_t nwords, bool acc, hipStream_t st) {
@@ -585,6 +743,27 @@ hipError_t panels_b(uint32_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t 
     return e;
 }
 
+hipError_t update_m4r(uint32_t *T, int64_t ld, int64_t D, const BBlock &b, const BRect &q,
+                      hipStream_t st) {
+    // 64-row chunk ranges -> row ranges
+    MRect m;
+    m.r0a = 64 * q.r_lo;
+    m.r0b = (int)std::min<int64_t>(64 * (int64_t)q.r_ex0, D);
+    m.r1a = (int)std::min<int64_t>(64 * (int64_t)q.r_ex1, D);
+    m.r1b = (int)std::min<int64_t>(64 * (int64_t)q.r_hi, D);
+    m.w0a = q.w0a, m.w0b = q.w0b, m.w1a = q.w1a, m.w1b = q.w1b;
+    const int nr0 = m.r0b > m.r0a ? (m.r0b - m.r0a + 511) / 512 : 0;
+    const int nr1 = m.r1b > m.r1a ? (m.r1b - m.r1a + 511) / 512 : 0;
+    const int nw0 = m.w0b > m.w0a ? (m.w0b - m.w0a + kM4rWords - 1) / kM4rWords : 0;
+    const int nw1 = m.w1b > m.w1a ? (m.w1b - m.w1a + kM4rWords - 1) / kM4rWords : 0;
+    if (nr0 + nr1 == 0 || nw0 + nw1 == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bool_fw_update_m4r, dim3(nw0 + nw1, nr0 + nr1), dim3(256), 0, st, T, ld,
+                       b.k0, b.bs, m, nw0, nr0, 0);
+    return hipGetLastError();
+}
+
+// nwb: word-chunk width of the bit-sliced kernel, or 0 for the
+// four-Russians kernel.
 hipError_t update_b(uint32_t *T, int64_t ld, int64_t D, int64_t kb, const BRect &q, int nwb,
                     double units, hipStream_t st, bool critical = false) {
     const BBlock b = bblock(D, kb);
@@ -592,6 +771,11 @@ hipError_t update_b(uint32_t *T, int64_t ld, int64_t D, int64_t kb, const BRect 
     const bool prof = prof_on();
     if (prof) prof_begin(st);
     hipError_t e;
+    if (nwb == 0) {
+        e = update_m4r(T, ld, D, b, q, st);
+        if (prof) prof_end(st, 0, 2, units);
+        return e;
+    }
     switch (nwb) {
         case 32: e = update_nwb<32>(T, ld, (int)D, b.k0, b.bs, q, prio, st); break;
         case 16: e = update_nwb<16>(T, ld, (int)D, b.k0, b.bs, q, prio, st); break;
@@ -603,9 +787,28 @@ hipError_t update_b(uint32_t *T, int64_t ld, int64_t D, int64_t kb, const BRect 
 
 }  // namespace
 
+hipError_t launch_bool_mul_m4r(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda,
+                               const uint64_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
+                               bool accumulate, hipStream_t stream) {
+    const int64_t nwords = (N + 31) / 32;
+    const dim3 grid((unsigned)((nwords + kM4rWords - 1) / kM4rWords), (unsigned)((R + 511) / 512));
+    hipLaunchKernelGGL(k_bool_mul_m4r<2>, grid, dim3(256), 0, stream,
+                       reinterpret_cast<uint32_t *>(C), 2 * ldc,
+                       reinterpret_cast<const uint32_t *>(A), 2 * lda,
+                       reinterpret_cast<const uint32_t *>(B), 2 * ldb, R, (int)K, nwords,
+                       accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_bool_mul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda,
                            const uint64_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
-                           bool accumulate, hipStream_t stream) {
+                           bool accumulate, int path, hipStream_t stream) {
+    // the four-Russians tables win once their 512-row x 512-column tiles
+    // give the device a few workgroups per compute unit and K is long enough
+    // to amortise each table
+    const int64_t tiles = ((R + 511) / 512) * ((N + 511) / 512);
+    if (path == kBoolPathM4r || (path == kBoolPathAuto && tiles >= 256 && K >= 1024))
+        return launch_bool_mul_m4r(C, ldc, A, lda, B, ldb, R, K, N, accumulate, stream);
     uint32_t *c = reinterpret_cast<uint32_t *>(C);
     const uint32_t *a = reinterpret_cast<const uint32_t *>(A);
     const uint32_t *b = reinterpret_cast<const uint32_t *>(B);
@@ -655,14 +858,17 @@ int bool_update_nwb(int64_t D) {
     return D >= 8192 ? 32 : (D >= 2048 ? 16 : 8);
 }
 
-hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool serial,
+hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool serial, int path,
                                hipStream_t st) {
     uint32_t *T = reinterpret_cast<uint32_t *>(T64);
     const int64_t ld = 2 * ld64;
     const int64_t nb = (D + kBoolBlock - 1) / kBoolBlock;
     const int nwd = (int)((D + 31) / 32);
     const int nrc = (int)((D + 63) / 64);
-    const int nwb = bool_update_nwb(D);
+    // bulk update: the four-Russians tables where the grid of 512 x 512 tiles
+    // fills the device, else the bit-sliced kernel
+    const bool m4r = path == kBoolPathM4r || (path == kBoolPathAuto && D >= 8192);
+    const int nwb = m4r ? 0 : bool_update_nwb(D);
     hipError_t e = pivot_b(T, ld, D, 0, st);
     if (e != hipSuccess || nb == 1) return e;
     if ((e = panels_b(T, ld, D, 0, st)) != hipSuccess) return e;

@@ -93,6 +93,7 @@ k_bool_mul_mfma(uint32_t *C, int64_t ldc, const uint8_t *A8, const uint8_t *B8T,
     const int64_t row0 = (int64_t)blockIdx.y * 128 + 64 * (wave >> 1);
     const int64_t col0 = (int64_t)blockIdx.x * 128 + 64 * (wave & 1);
     if (row0 >= R || col0 >= N) return;
+    if (kp == 0) return;  // no inner index: the host never launches this case
     const int half = 16 * (lane >> 5);
     const uint8_t *a0 = A8 + (row0 + (lane & 31)) * kp + half;
     const uint8_t *a1 = a0 + 32 * kp;
@@ -169,6 +170,11 @@ size_t bool_mfma_work_bytes(int64_t R, int64_t K, int64_t N) {
 hipError_t launch_bool_mul_mfma(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda,
                                 const uint64_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                                 bool accumulate, void *work, hipStream_t st) {
+    // K = 0: the product is the zero matrix; the operand loads of the
+    // product kernel need at least one 64-byte slice, so this case goes to
+    // the bit-sliced kernels (which write the zeros, or leave C as it is)
+    if (K == 0)
+        return launch_bool_mul(C, ldc, A, lda, B, ldb, R, K, N, accumulate, kBoolPathBitwise, st);
     const int64_t kp = (K + 63) / 64 * 64;
     const int64_t rp = (R + 127) / 128 * 128, np = (N + 127) / 128 * 128;
     uint8_t *A8 = static_cast<uint8_t *>(work);

@@ -44,11 +44,21 @@ hipError_t launch_narrow_u8(uint8_t *dst, int64_t ldd, const uint16_t *src, int6
                             int64_t R, int64_t C, hipStream_t stream);
 
 // Boolean, bit-packed: strides in 64-bit words (even), widths in bits.
+// path: kBoolPathAuto (chosen by size), kBoolPathBitwise (the bit-sliced
+// kernels) or kBoolPathM4r (the "four Russians" tables).
+enum { kBoolPathAuto = 0, kBoolPathBitwise = 1, kBoolPathM4r = 2 };
 hipError_t launch_bool_mul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda,
                            const uint64_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
-                           bool accumulate, hipStream_t stream);
-hipError_t launch_bool_closure(uint64_t *T, int64_t ld, int64_t D, bool serial,
+                           bool accumulate, int path, hipStream_t stream);
+// path: kBoolPathAuto, or force the bit-sliced (kBoolPathBitwise) or the
+// four-Russians (kBoolPathM4r) kernels for the bulk update.
+hipError_t launch_bool_closure(uint64_t *T, int64_t ld, int64_t D, bool serial, int path,
                                hipStream_t stream);
+// Boolean product with the "four Russians" tables (sr_bool.hip); `launch_bool_mul`
+// chooses between it and the bit-sliced kernel, path forces one.
+hipError_t launch_bool_mul_m4r(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda,
+                               const uint64_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
+                               bool accumulate, hipStream_t stream);
 
 // Boolean product on the matrix cores (sr_bool_mfma.hip): bits expanded to
 // int8 in `work` (bool_mfma_work_bytes(R, K, N) bytes, 256-byte aligned,

@@ -100,6 +100,39 @@ def test_bool_closure_config3():
     assert torch.equal(TT, T)
 
 
+def test_bool_closure_config3_paths_agree():
+    """At D = 16384 the default bulk update (four-Russians tables) and the
+    bit-sliced one give the same closure."""
+    D = 16384
+    W = synthgen.cfg_bool16384(D=D)
+    T1 = sr.to_device(sr.SR_BOOL, W, cols=D)
+    T2 = sr.clone(T1)
+    sr.closure(sr.SR_BOOL, T1, D=D)
+    sr.closure(sr.SR_BOOL, T2, D=D, flags=sr.SR_BOOL_BITWISE)
+    torch.cuda.synchronize()
+    assert torch.equal(T1, T2)
+
+
+def test_bool_product_d8192_rows():
+    """Boolean product at D = 8192 (the size picks the four-Russians path):
+    sampled rows against the oracle, and the bit-sliced path agrees."""
+    D = 8192
+    gen = synthgen.generator(8192)
+    ld = synthgen.aligned_ld_words(D)
+    Aw = synthgen.pack_bits((gen.random((D, D)) < 0.002).astype(np.uint8), ld)
+    Bw = synthgen.pack_bits((gen.random((D, D)) < 0.002).astype(np.uint8), ld)
+    dA, dB = sr.to_device(sr.SR_BOOL, Aw, cols=D), sr.to_device(sr.SR_BOOL, Bw, cols=D)
+    C1 = sr.empty(sr.SR_BOOL, D, D)
+    C2 = sr.empty(sr.SR_BOOL, D, D)
+    sr.semiring_mul(sr.SR_BOOL, C1, dA, dB, K=D, N=D)
+    sr.semiring_mul(sr.SR_BOOL, C2, dA, dB, K=D, N=D, flags=sr.SR_BOOL_BITWISE)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+    rows = sample_rows(D, 8, 9)
+    want = oracle.bool_mul_words(Aw[rows], Bw, D, D)
+    assert np.array_equal(sr.to_host(C1)[rows, :D // 64], want[:, :D // 64])
+
+
 def test_batched_config4_sample():
     """Configuration 4 (4096 graphs, log-uniform sizes) in one launch; a
     sample of graphs against the oracle, every graph against its solo run."""

@@ -277,19 +277,21 @@ def test_bool_closure(D):
     assert synthgen.padding_bits_clear(got, D)
 
 
+@pytest.mark.parametrize("path", [0, sr.SR_BOOL_BITWISE, sr.SR_BOOL_M4R])
 @pytest.mark.parametrize("D", [769, 2100, 4100])
-def test_bool_closure_lookahead_and_serial(D):
+def test_bool_closure_lookahead_and_serial(D, path):
     """Sizes with several lookahead rounds and each word-chunk width (8 and
-    16 words): the overlapped schedule and the serial one give the oracle's
-    bits."""
+    16 words), with the bulk update by size, bit-sliced, or by the
+    four-Russians tables: the overlapped schedule and the serial one give the
+    oracle's bits."""
     gen = synthgen.generator(3200 + D)
     A = rand_bits(D, D, gen, 1.2 / D)
     ldw = synthgen.aligned_ld_words(D)
     Aw = synthgen.pack_bits(A, ldw)
     T = dev(sr.SR_BOOL, Aw, cols=D)
     T2 = sr.clone(T)
-    sr.closure(sr.SR_BOOL, T, D=D)
-    sr.closure(sr.SR_BOOL, T2, D=D, flags=sr.SR_SERIAL_PHASES)
+    sr.closure(sr.SR_BOOL, T, D=D, flags=path)
+    sr.closure(sr.SR_BOOL, T2, D=D, flags=sr.SR_SERIAL_PHASES | path)
     want = oracle.bool_closure_words(Aw, D)
     nw = (D + 63) // 64
     got = host(T)
@@ -416,9 +418,12 @@ def test_closure_batched_arena(kind):
 # ---------------------------------------------------------------------------
 # Boolean product on the matrix cores (SR_BOOL_MFMA)
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("path", [sr.SR_BOOL_MFMA, sr.SR_BOOL_M4R])
 @pytest.mark.parametrize("R,K,N", [(1, 1, 1), (5, 3, 7), (64, 64, 64), (65, 130, 129),
-                                   (200, 37, 300), (257, 300, 513), (128, 1000, 256)])
-def test_bool_mul_mfma(R, K, N):
+                                   (200, 37, 300), (257, 300, 513), (128, 1000, 256),
+                                   (300, 9, 1100), (4, 0, 70)])
+def test_bool_mul_paths(path, R, K, N):
+    """The matrix-core and four-Russians paths against the oracle."""
     gen = synthgen.generator(6000 + R + K + N)
     A = rand_bits(R, K, gen, 0.05)
     B = rand_bits(K, N, gen, 0.05)
@@ -426,7 +431,7 @@ def test_bool_mul_mfma(R, K, N):
     Aw, Bw = synthgen.pack_bits(A, lda), synthgen.pack_bits(B, ldb)
     C = sr.empty(sr.SR_BOOL, R, N)
     sr.semiring_mul(sr.SR_BOOL, C, dev(sr.SR_BOOL, Aw, cols=K), dev(sr.SR_BOOL, Bw, cols=N),
-                    K=K, N=N, flags=sr.SR_BOOL_MFMA)
+                    K=K, N=N, flags=path)
     want = oracle.bool_mul_words(Aw, Bw, K, N)
     nw = (N + 63) // 64
     got = host(C)
@@ -434,7 +439,8 @@ def test_bool_mul_mfma(R, K, N):
     assert synthgen.padding_bits_clear(got, N)
 
 
-def test_bool_mul_mfma_accumulate_and_dense():
+@pytest.mark.parametrize("path", [sr.SR_BOOL_MFMA, sr.SR_BOOL_M4R])
+def test_bool_mul_paths_accumulate_and_dense(path):
     """Accumulate mode, and dense inputs (counts up to K) equal to the
     bitwise path."""
     gen = synthgen.generator(6100)
@@ -448,8 +454,7 @@ def test_bool_mul_mfma_accumulate_and_dense():
         dA, dB = dev(sr.SR_BOOL, Aw, cols=K), dev(sr.SR_BOOL, Bw, cols=N)
         C1 = dev(sr.SR_BOOL, Cw, cols=N)
         C2 = dev(sr.SR_BOOL, Cw, cols=N)
-        sr.semiring_mul(sr.SR_BOOL, C1, dA, dB, K=K, N=N,
-                        flags=sr.SR_BOOL_MFMA | sr.SR_ACCUMULATE)
+        sr.semiring_mul(sr.SR_BOOL, C1, dA, dB, K=K, N=N, flags=path | sr.SR_ACCUMULATE)
         sr.semiring_mul(sr.SR_BOOL, C2, dA, dB, K=K, N=N, flags=sr.SR_ACCUMULATE)
         want = oracle.bool_mul_words(Aw, Bw, K, N, C=Cw)
         nw = (N + 63) // 64
