@@ -10,8 +10,9 @@ What it computes (all integer, so every result is exact and unique):
 
 * Boolean semiring, Sec. II: (+) = max, (x) = min on {0, 1}.
 * Anti-distance semiring, Sec. III, integer-scaled as in Sec. IV: entries
-  0..S with S = 2^8 - 1 (uint8) or 2^16 - 1 (uint16), (+) = max and
-  a (x) b = max(a + b - S, 0), evaluated in int32 in that definition form.
+  0..S with S = 2^8 - 1 (uint8), 2^16 - 1 (uint16) or 2^32 - 1 (uint32),
+  (+) = max and a (x) b = max(a + b - S, 0), evaluated in that definition
+  form in int32 (int64 for S = 2^32 - 1).
 * ``mul``:     the multiplication algorithm of Sec. II (P := 0, then for every
                k, P := P (+) column k of A times row k of B).
 * ``closure``: Warshall's algorithm of Sec. II (T := A, then for every k,
@@ -49,6 +50,7 @@ from . import build as _build
 
 S_U8 = 2 ** 8 - 1
 S_U16 = 2 ** 16 - 1
+S_U32 = 2 ** 32 - 1
 
 _lib = None
 
@@ -73,6 +75,11 @@ def _load():
         lib.o_bool_closure_rows_words.argtypes = [vp, i64, i64, vp, i64, vp, i64]
         lib.o_dist_mul.argtypes = [vp, i64, vp, i64, vp, i64, i64, i64, i64, i32, ctypes.c_int]
         lib.o_dist_closure.argtypes = [vp, i64, i64, i32]
+        lib.o_ad_mul64.argtypes = [vp, i64, vp, i64, vp, i64, i64, i64, i64, i64, ctypes.c_int]
+        lib.o_ad_closure_steps64.argtypes = [vp, i64, i64, i64, i64, i64]
+        lib.o_dist_mul64.argtypes = [vp, i64, vp, i64, vp, i64, i64, i64, i64, i64, ctypes.c_int]
+        lib.o_dist_closure64.argtypes = [vp, i64, i64, i64]
+        lib.o_ad_closure_rows64.argtypes = [vp, i64, i64, i64, vp, i64, vp]
         _lib = lib
     return _lib
 
@@ -101,11 +108,22 @@ def scale(dtype) -> int:
         return S_U8
     if dtype == np.uint16:
         return S_U16
-    raise ValueError("anti-distance entries are uint8 or uint16, got %s" % dtype)
+    if dtype == np.uint32:
+        return S_U32
+    raise ValueError("anti-distance entries are uint8, uint16 or uint32, got %s" % dtype)
 
 
 def _as_i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _as_i64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _wide(S):
+    """S = 2^32 - 1 needs the int64 loops (a + b does not fit in int32)."""
+    return int(S) > 2 ** 31 - 1
 
 
 # --------------------------------------------------------------------------
@@ -115,16 +133,19 @@ def ad_mul(A, B, S, C=None):
     """(A * B) over the anti-distance semiring; with C given, C (+) A * B.
 
     A: R x K, B: K x N, entries in 0..S (any integer dtype).  Returns int32."""
-    A = _as_i32(A)
-    B = _as_i32(B)
+    wide = _wide(S)
+    conv = _as_i64 if wide else _as_i32
+    A = conv(A)
+    B = conv(B)
     R, K = A.shape
     K2, N = B.shape
     if K != K2:
         raise ValueError("inner dimensions differ: %d vs %d" % (K, K2))
     acc = C is not None
-    out = _as_i32(C).copy() if acc else np.zeros((R, N), np.int32)
+    out = conv(C).copy() if acc else np.zeros((R, N), np.int64 if wide else np.int32)
     if R and N:
-        _load().o_ad_mul(_ptr(A), K, _ptr(B), N, _ptr(out), N, R, K, N, int(S), int(acc))
+        f = _load().o_ad_mul64 if wide else _load().o_ad_mul
+        f(_ptr(A), K, _ptr(B), N, _ptr(out), N, R, K, N, int(S), int(acc))
     return out
 
 
@@ -133,24 +154,28 @@ def ad_closure(A, S, k_end=None):
 
     With k_end given, only the first k_end pivot steps are run (used to time a
     bounded sample of the full loop)."""
-    T = _as_i32(A).copy()
+    wide = _wide(S)
+    T = (_as_i64 if wide else _as_i32)(A).copy()
     D = T.shape[0]
     if T.shape != (D, D):
         raise ValueError("closure needs a square matrix")
     k1 = D if k_end is None else int(k_end)
     if D:
-        _load().o_ad_closure_steps(_ptr(T), D, D, int(S), 0, k1)
+        f = _load().o_ad_closure_steps64 if wide else _load().o_ad_closure_steps
+        f(_ptr(T), D, D, int(S), 0, k1)
     return T
 
 
 def ad_closure_rows(A, S, rows):
     """Rows ``rows`` of the anti-distance closure from its path definition."""
-    A = _as_i32(A)
+    wide = _wide(S)
+    A = (_as_i64 if wide else _as_i32)(A)
     D = A.shape[0]
     rows = np.ascontiguousarray(rows, dtype=np.int64)
-    out = np.zeros((len(rows), D), np.int32)
+    out = np.zeros((len(rows), D), np.int64 if wide else np.int32)
     if len(rows) and D:
-        _load().o_ad_closure_rows(_ptr(A), D, D, int(S), _ptr(rows), len(rows), _ptr(out))
+        f = _load().o_ad_closure_rows64 if wide else _load().o_ad_closure_rows
+        f(_ptr(A), D, D, int(S), _ptr(rows), len(rows), _ptr(out))
     return out
 
 
@@ -165,28 +190,33 @@ def ad_add(A, B):
 def dist_mul(A, B, S, C=None):
     """Distance product: min over k of min(A_ik + B_kj, S); with C given,
     min(C, A + B).  Entries 0..S, S = no path.  Returns int32."""
-    A = _as_i32(A)
-    B = _as_i32(B)
+    wide = _wide(S)
+    conv = _as_i64 if wide else _as_i32
+    A = conv(A)
+    B = conv(B)
     R, K = A.shape
     K2, N = B.shape
     if K != K2:
         raise ValueError("inner dimensions differ: %d vs %d" % (K, K2))
     acc = C is not None
-    out = _as_i32(C).copy() if acc else np.full((R, N), int(S), np.int32)
+    out = conv(C).copy() if acc else np.full((R, N), int(S), np.int64 if wide else np.int32)
     if R and N:
-        _load().o_dist_mul(_ptr(A), K, _ptr(B), N, _ptr(out), N, R, K, N, int(S), int(acc))
+        f = _load().o_dist_mul64 if wide else _load().o_dist_mul
+        f(_ptr(A), K, _ptr(B), N, _ptr(out), N, R, K, N, int(S), int(acc))
     return out
 
 
 def dist_closure(A, S):
     """Warshall's loop with min and saturating + (distance closure; the
     diagonal holds the shortest cycle through each vertex, or S)."""
-    T = _as_i32(A).copy()
+    wide = _wide(S)
+    T = (_as_i64 if wide else _as_i32)(A).copy()
     D = T.shape[0]
     if T.shape != (D, D):
         raise ValueError("closure needs a square matrix")
     if D:
-        _load().o_dist_closure(_ptr(T), D, D, int(S))
+        f = _load().o_dist_closure64 if wide else _load().o_dist_closure
+        f(_ptr(T), D, D, int(S))
     return T
 
 
@@ -194,17 +224,17 @@ def dist_closure(A, S):
 # entrywise operations (table of Sec. V) and the reflexive closure (eq. rtc)
 # --------------------------------------------------------------------------
 def ewise(op, A, B=None, S=None):
-    """Entrywise and = min, or = max, xor = |a - b|, not = S - a."""
+    """Entrywise and = min, or = max, xor = |a - b|, not = S - a (int64)."""
     A = np.asarray(A, np.int64)
     if op == "not":
-        return (int(S) - A).astype(np.int32)
+        return int(S) - A
     B = np.asarray(B, np.int64)
     if op == "and":
-        return np.minimum(A, B).astype(np.int32)
+        return np.minimum(A, B)
     if op == "or":
-        return np.maximum(A, B).astype(np.int32)
+        return np.maximum(A, B)
     if op == "xor":
-        return np.abs(A - B).astype(np.int32)
+        return np.abs(A - B)
     raise ValueError("op is and, or, xor or not")
 
 

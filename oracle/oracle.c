@@ -215,6 +215,118 @@ void o_ad_closure_rows(const int32_t *A, int64_t ld, int64_t D, int32_t S,
 }
 
 /* ---------------------------------------------------------------------------
+ * The same anti-distance and distance loops in int64, for S = 2^32 - 1
+ * (uint32 entries, Sec. IV's scaling with 32-bit storage), where a + b does
+ * not fit in int32.  Same definitions, same order.
+ * ------------------------------------------------------------------------- */
+static inline int64_t ad_times64(int64_t a, int64_t b, int64_t S) {
+    int64_t t = a + b - S;
+    return t > 0 ? t : 0;
+}
+
+static inline int64_t dist_times64(int64_t a, int64_t b, int64_t S) {
+    int64_t t = a + b;
+    return t < S ? t : S;
+}
+
+void o_ad_mul64(const int64_t *A, int64_t lda, const int64_t *B, int64_t ldb, int64_t *C,
+                int64_t ldc, int64_t R, int64_t K, int64_t N, int64_t S, int accumulate) {
+    if (!accumulate)
+        for (int64_t i = 0; i < R; i++)
+            for (int64_t j = 0; j < N; j++) C[i * ldc + j] = 0;
+    for (int64_t k = 0; k < K; k++) {
+        int64_t i;
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+        for (i = 0; i < R; i++) {
+            int64_t a = A[i * lda + k];
+            for (int64_t j = 0; j < N; j++) {
+                int64_t v = ad_times64(a, B[k * ldb + j], S);
+                if (v > C[i * ldc + j]) C[i * ldc + j] = v;
+            }
+        }
+    }
+}
+
+void o_ad_closure_steps64(int64_t *T, int64_t ld, int64_t D, int64_t S, int64_t k_begin,
+                          int64_t k_end) {
+    for (int64_t k = k_begin; k < k_end; k++) {
+        int64_t i;
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+        for (i = 0; i < D; i++) {
+            int64_t tik = T[i * ld + k];
+            for (int64_t j = 0; j < D; j++) {
+                int64_t v = ad_times64(tik, T[k * ld + j], S);
+                if (v > T[i * ld + j]) T[i * ld + j] = v;
+            }
+        }
+    }
+}
+
+void o_dist_mul64(const int64_t *A, int64_t lda, const int64_t *B, int64_t ldb, int64_t *C,
+                  int64_t ldc, int64_t R, int64_t K, int64_t N, int64_t S, int accumulate) {
+    if (!accumulate)
+        for (int64_t i = 0; i < R; i++)
+            for (int64_t j = 0; j < N; j++) C[i * ldc + j] = S;
+    for (int64_t k = 0; k < K; k++) {
+        int64_t i;
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+        for (i = 0; i < R; i++) {
+            int64_t a = A[i * lda + k];
+            for (int64_t j = 0; j < N; j++) {
+                int64_t v = dist_times64(a, B[k * ldb + j], S);
+                if (v < C[i * ldc + j]) C[i * ldc + j] = v;
+            }
+        }
+    }
+}
+
+void o_dist_closure64(int64_t *T, int64_t ld, int64_t D, int64_t S) {
+    for (int64_t k = 0; k < D; k++) {
+        int64_t i;
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+        for (i = 0; i < D; i++) {
+            int64_t tik = T[i * ld + k];
+            for (int64_t j = 0; j < D; j++) {
+                int64_t v = dist_times64(tik, T[k * ld + j], S);
+                if (v < T[i * ld + j]) T[i * ld + j] = v;
+            }
+        }
+    }
+}
+
+/* Rows of the anti-distance closure from the path definition, int64 entries
+ * (as o_ad_closure_rows). */
+void o_ad_closure_rows64(const int64_t *A, int64_t ld, int64_t D, int64_t S,
+                         const int64_t *rows, int64_t nrows, int64_t *out) {
+    int64_t r;
+#pragma omp parallel for num_threads(g_threads) schedule(dynamic)
+    for (r = 0; r < nrows; r++) {
+        int64_t src = rows[r];
+        const int64_t INF = INT64_MAX / 4;
+        int64_t *dist = (int64_t *)malloc(sizeof(int64_t) * (size_t)D);
+        char *done = (char *)calloc((size_t)D, 1);
+        for (int64_t j = 0; j < D; j++) {
+            int64_t a = A[src * ld + j];
+            dist[j] = a > 0 ? S - a : INF;
+        }
+        for (int64_t it = 0; it < D; it++) {
+            int64_t u = -1;
+            for (int64_t j = 0; j < D; j++)
+                if (!done[j] && dist[j] < INF && (u < 0 || dist[j] < dist[u])) u = j;
+            if (u < 0) break;
+            done[u] = 1;
+            for (int64_t j = 0; j < D; j++) {
+                int64_t a = A[u * ld + j];
+                if (a > 0 && dist[u] + (S - a) < dist[j]) dist[j] = dist[u] + (S - a);
+            }
+        }
+        for (int64_t j = 0; j < D; j++) out[r * D + j] = dist[j] >= S ? 0 : S - dist[j];
+        free(dist);
+        free(done);
+    }
+}
+
+/* ---------------------------------------------------------------------------
  * Boolean product on unpacked {0,1} bytes, from the definition of Sec. II:
  *   (A*B)_ij = max_k min(A_ik, B_kj).
  * ------------------------------------------------------------------------- */

@@ -20,7 +20,7 @@ from pins import (
     pin_product_equals_warshall, rand_ad, rand_bool,
 )
 
-SCALES = (255, 65535)
+SCALES = (255, 65535, 2 ** 32 - 1)
 
 
 def o_mul(A, B, S):
@@ -121,6 +121,21 @@ def test_scalar_table_u16_dense():
         [0, 1, 2, 3, 254, 255, 256, 32767, 32768, 65533, 65534, 65535],
         gen.integers(0, 65536, size=180)]))
     pin_ad_mul_scalar_table(o_mul, 65535, a_values=a)
+
+
+def test_scalar_table_u32_sampled():
+    """S = 2^32 - 1 (uint32 entries): the scalar table on sampled operands,
+    extremes and the int32 boundary included, against the listing and De
+    Morgan forms (the int64 loops of the oracle)."""
+    S = 2 ** 32 - 1
+    gen = synthgen.generator(19)
+    special = [0, 1, 2, 2 ** 31 - 1, 2 ** 31, 2 ** 31 + 1, S - 2, S - 1, S]
+    a = np.unique(np.concatenate([special, gen.integers(0, S + 1, size=120)])).astype(np.int64)
+    b = np.unique(np.concatenate([special, gen.integers(0, S + 1, size=120)])).astype(np.int64)
+    C = np.asarray(o_mul(a[:, None], b[None, :], S), np.int64)
+    na = (S - a)[:, None]
+    assert np.array_equal(C, np.where(b[None, :] > na, b[None, :] - na, 0))
+    assert np.array_equal(C, S - np.minimum((S - a)[:, None] + (S - b)[None, :], S))
 
 
 @pytest.mark.parametrize("S", SCALES)

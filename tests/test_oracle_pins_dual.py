@@ -22,7 +22,7 @@ import oracle
 import synthgen
 from pins import rand_ad, rand_bool
 
-SS = (255, 65535)
+SS = (255, 65535, 2 ** 32 - 1)
 
 
 def rand_dist(R, C, S, gen, p=0.3, wmax=None):
@@ -129,7 +129,7 @@ def pin_dist_closure(clo, S, gen):
         assert np.array_equal(S - got, oracle.ad_closure(S - A, S)), D
     # closed form: directed cycle with unit lengths, saturating when D >= S
     for D in (7, 300):
-        if D > 60 and S == 65535:
+        if D > 60 and S > 255:
             continue
         A = np.full((D, D), S, np.int64)
         A[np.arange(D), (np.arange(D) + 1) % D] = 1
