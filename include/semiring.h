@@ -5,17 +5,20 @@
  *   M. de Bondt, "Fast algorithms for anti-distance matrices as a
  *   generalization of Boolean matrices", arXiv 1705.08743.
  *
- * Three semirings are supported, as the paper defines them:
+ * Three semirings (and the distance dual) are supported, as the paper
+ * defines them:
  *
  *   SR_BOOL            Boolean matrices (Sec. II): entries {0, 1},
  *                      a (+) b = max(a, b), a (x) b = min(a, b).
  *   SR_ANTIDIST_U8     anti-distance matrices (Sec. III), integer-scaled as in
- *   SR_ANTIDIST_U16    Sec. IV to {0, 1, ..., S} with S = 2^8 - 1 (uint8) or
- *                      2^16 - 1 (uint16): a (+) b = max(a, b) and
+ *   SR_ANTIDIST_U16    Sec. IV to {0, 1, ..., S} with S = 2^8 - 1 (uint8),
+ *   SR_ANTIDIST_U32    2^16 - 1 (uint16) or 2^32 - 1 (uint32):
+ *                      a (+) b = max(a, b) and
  *                      a (x) b = max(a + b - S, 0).  Entry S - w encodes a
  *                      distance w; 0 is "no path" (distance >= S saturates).
  *   SR_DISTANCE_U8     distance matrices, the dual the paper adds beside
  *   SR_DISTANCE_U16    anti-distance matrices (its section on distance
+ *   SR_DISTANCE_U32
  *                      matrices): entries 0..S hold a distance, S is "no
  *                      path"; a (+) b = min(a, b) and a (x) b = min(a + b, S)
  *                      ("funny" multiplication; the zero matrix is all S).
@@ -73,7 +76,9 @@ typedef enum sr_kind {
     SR_ANTIDIST_U8 = 1,   /* anti-distance, uint8 entries, S = 255 */
     SR_ANTIDIST_U16 = 2,  /* anti-distance, uint16 entries, S = 65535 */
     SR_DISTANCE_U8 = 3,   /* distance, uint8 entries, S = 255 = no path */
-    SR_DISTANCE_U16 = 4   /* distance, uint16 entries, S = 65535 = no path */
+    SR_DISTANCE_U16 = 4,  /* distance, uint16 entries, S = 65535 = no path */
+    SR_ANTIDIST_U32 = 5,  /* anti-distance, uint32 entries, S = 2^32 - 1 */
+    SR_DISTANCE_U32 = 6   /* distance, uint32 entries, S = 2^32 - 1 = no path */
 } sr_kind;
 
 /* Entrywise operations (the `op` argument of semiring_ewise): the table of
@@ -161,11 +166,13 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
  * becomes 1, S, or 0 for distances -- the paper's transclosure /
  * dransclosure), SR_BOOL_BITWISE, SR_SERIAL_PHASES; SR_BOOL_MFMA returns
  * SR_EUNSUPPORTED.  D = 0 is a no-op.
- * By default a closure with more than two pivot blocks forks onto a second,
+ * By default a closure of the 8- and 16-bit and Boolean kinds with more than
+ * two pivot blocks forks onto a second,
  * library-owned stream of default priority (the next round's pivot and panels
  * overlap the bulk of the current update) and joins back into `stream`
  * before the call's work completes; the fork/join is event-based, so the
- * sequence can be captured into a HIP graph from `stream`.
+ * sequence can be captured into a HIP graph from `stream`.  The 32-bit kinds
+ * run every phase in order on `stream`.
  */
 int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream);
 
@@ -173,8 +180,8 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
  * closure_batched -- `count` independent in-place closures, as closure()
  * applied to each (T[g], ldt[g], D[g]).  The three arrays are HOST arrays of
  * length count; T[g] are device pointers, each obeying the alignment rules
- * above.  Anti-distance and distance kinds (Boolean returns
- * SR_EUNSUPPORTED); flags: SR_REFLEXIVE.  The
+ * above.  8- and 16-bit anti-distance and distance kinds (Boolean and the
+ * 32-bit kinds return SR_EUNSUPPORTED); flags: SR_REFLEXIVE.  The
  * matrices must not overlap each other (SR_EALIAS), D[g] <= 65536.  The
  * batch runs the blocked Floyd-Warshall of closure() round-synchronously: per
  * round, one pivot, one panels and one update launch cover every graph that

@@ -10,10 +10,11 @@ fallback.
 Matrices are 2-D CUDA (HIP) tensors with unit column stride; the row stride
 ``tensor.stride(0)`` is the ABI's leading dimension ``ld``:
 
-* anti-distance (``SR_ANTIDIST_U8`` / ``SR_ANTIDIST_U16``) and distance
-  (``SR_DISTANCE_U8`` / ``SR_DISTANCE_U16``): ``torch.uint8`` /
-  ``torch.uint16`` tensors; the logical shape is the tensor shape, so a view
-  ``X[:, :n]`` of a padded ``(rows, ld)`` buffer is a rows x n matrix.
+* anti-distance (``SR_ANTIDIST_U8`` / ``_U16`` / ``_U32``) and distance
+  (``SR_DISTANCE_U8`` / ``_U16`` / ``_U32``): ``torch.uint8`` /
+  ``torch.uint16`` / ``torch.uint32`` tensors; the logical shape is the tensor
+  shape, so a view ``X[:, :n]`` of a padded ``(rows, ld)`` buffer is a
+  rows x n matrix.
 * Boolean (``SR_BOOL``): ``torch.int64`` tensors of packed words (entry (r, c)
   at bit c % 64 of word c // 64, least significant bit first); bit widths are
   passed explicitly (``K``, ``N``, ``D``) and default to 64 x words.
@@ -26,6 +27,8 @@ SR_ANTIDIST_U8 = 1
 SR_ANTIDIST_U16 = 2
 SR_DISTANCE_U8 = 3
 SR_DISTANCE_U16 = 4
+SR_ANTIDIST_U32 = 5
+SR_DISTANCE_U32 = 6
 
 SR_EW_AND = 0
 SR_EW_OR = 1
@@ -34,6 +37,18 @@ SR_EW_NOT = 3
 
 _U8_KINDS = (SR_ANTIDIST_U8, SR_DISTANCE_U8)
 _U16_KINDS = (SR_ANTIDIST_U16, SR_DISTANCE_U16)
+_U32_KINDS = (SR_ANTIDIST_U32, SR_DISTANCE_U32)
+
+
+def elem_bytes(kind):
+    """Bytes per stored entry (8 for Boolean words)."""
+    if kind in _U8_KINDS:
+        return 1
+    if kind in _U16_KINDS:
+        return 2
+    if kind in _U32_KINDS:
+        return 4
+    return 8
 
 SR_OK = 0
 SR_EINVAL = -1
@@ -128,9 +143,11 @@ def kind_of(t):
         return SR_ANTIDIST_U8
     if t.dtype == torch.uint16:
         return SR_ANTIDIST_U16
+    if t.dtype == torch.uint32:
+        return SR_ANTIDIST_U32
     if t.dtype == torch.int64:
         return SR_BOOL
-    raise TypeError("unsupported dtype %s (uint8, uint16 or int64 words)" % t.dtype)
+    raise TypeError("unsupported dtype %s (uint8, uint16, uint32 or int64 words)" % t.dtype)
 
 
 def _mat(t, name):
@@ -234,7 +251,7 @@ class BatchArena:
         import numpy as np
         torch = _torch()
         if kind not in _U8_KINDS + _U16_KINDS:
-            raise ValueError("BatchArena holds anti-distance or distance matrices")
+            raise ValueError("BatchArena holds 8- or 16-bit anti-distance or distance matrices")
         self.kind = kind
         self.es = 1 if kind in _U8_KINDS else 2
         self.dtype = torch.uint8 if kind in _U8_KINDS else torch.uint16
@@ -325,8 +342,7 @@ def padded_ld(cols, kind, align_bytes=128):
         words = (cols + 63) // 64
         per = max(2, align_bytes // 8)
         return max(per, -(-words // per) * per)
-    es = 1 if kind in _U8_KINDS else 2
-    per = align_bytes // es
+    per = align_bytes // elem_bytes(kind)
     return max(per, -(-cols // per) * per)
 
 
@@ -335,7 +351,8 @@ def empty(kind, rows, cols, device="cuda", zero=True):
     Boolean, rows x words with cols bits of payload)."""
     torch = _torch()
     dt = {SR_BOOL: torch.int64, SR_ANTIDIST_U8: torch.uint8, SR_ANTIDIST_U16: torch.uint16,
-          SR_DISTANCE_U8: torch.uint8, SR_DISTANCE_U16: torch.uint16}[kind]
+          SR_DISTANCE_U8: torch.uint8, SR_DISTANCE_U16: torch.uint16,
+          SR_ANTIDIST_U32: torch.uint32, SR_DISTANCE_U32: torch.uint32}[kind]
     ld = padded_ld(cols, kind)
     buf = (torch.zeros if zero else torch.empty)((max(rows, 1), ld), dtype=dt, device=device)
     width = (cols + 63) // 64 if kind == SR_BOOL else cols
@@ -355,7 +372,7 @@ def clone(t):
 
 
 def to_device(kind, host, cols=None, device="cuda"):
-    """Copy a host numpy matrix (uint8 / uint16 entries, or uint64 words) into
+    """Copy a host numpy matrix (uint8 / uint16 / uint32 entries, or uint64 words) into
     a padded device buffer; returns the logical view."""
     import numpy as np
     torch = _torch()
@@ -385,6 +402,7 @@ def to_host(t):
 
 __all__ = [
     "SR_BOOL", "SR_ANTIDIST_U8", "SR_ANTIDIST_U16", "SR_DISTANCE_U8", "SR_DISTANCE_U16",
+    "SR_ANTIDIST_U32", "SR_DISTANCE_U32", "elem_bytes",
     "SR_BOOL_M4R", "SR_EW_AND", "SR_EW_OR", "SR_EW_XOR", "SR_EW_NOT", "semiring_ewise", "SR_OK", "SR_EINVAL", "SR_EALIAS",
     "SR_EALIGN", "SR_ENOMEM", "SR_EDEVICE", "SR_EUNSUPPORTED", "SR_ACCUMULATE",
     "SR_REFLEXIVE", "SR_BOOL_BITWISE", "SR_BOOL_MFMA", "SR_SERIAL_PHASES", "SemiringError", "lib", "kind_of",

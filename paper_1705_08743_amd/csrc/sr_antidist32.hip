@@ -1,0 +1,451 @@
+// Anti-distance semiring with 32-bit entries, S = 2^32 - 1 (the integer
+// scaling of Sec. IV with 32-bit storage).  S - a is the bitwise complement,
+// so a (x) b = max(a + b - S, 0) = b -sat (S - a) is one v_sub_u32 with clamp
+// and (+) is v_max_u32: two VALU lane-operations per update (the 16-bit
+// kernels do two updates per pair of packed operations).
+//
+// Same algorithms as the 16-bit path (Sec. II product and blocked
+// Warshall/Floyd closure in rounds of 128 pivots: pivot tile, panels,
+// update), with 32-bit wave tiles: a wavefront owns 64 rows (lane = row) x CW
+// columns, the B row of each inner step is read with scalar loads and enters
+// every instruction as its SGPR operand, and each lane reads its own row of A
+// in 64-byte groups, one group ahead.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "sr_internal.h"
+#include "sr_tiles.h"  // kconst (scalar reads of B rows), Rect, panel_wgs
+
+namespace sr {
+namespace {
+
+using dev::Rect;
+
+constexpr int kUpdCW = 32;  // columns per wave tile: update and product
+constexpr int kPanCW = 32;  // columns per wave tile: panels (the chunking of panel_wgs)
+constexpr int kRW = 64;     // rows per wave tile
+
+__device__ __forceinline__ uint32_t step32(uint32_t acc, uint32_t b, uint32_t na) {
+    return __builtin_elementwise_max(acc, __builtin_elementwise_sub_sat(b, na));
+}
+
+// ---------------------------------------------------------------------------
+// One wavefront: C (+)= A * B (or C := A * B) for rows [0, nrows), lane = row,
+// and columns [0, ncols), over K inner steps.  The caller guarantees that CW
+// columns of every B row are readable from B (ncols may be less: the extra
+// columns feed accumulators that are not stored).  FULLC: ncols == CW (whole
+// 16-byte C accesses); else C is read and written entry by entry.  Rows >=
+// nrows compute on row 0 and store nothing.  A, B and C rows are 16-byte
+// aligned.  With sync, a workgroup barrier separates every read of the tile's
+// operands from its stores (the whole workgroup must call this).
+// ---------------------------------------------------------------------------
+template <int CW, bool FULLC>
+__device__ __forceinline__ void tile32_body(uint32_t *C, int64_t ldc, const uint32_t *A,
+                                            int64_t lda, const uint32_t *B, int64_t ldb,
+                                            int nrows, int ncols, int K, bool accumulate,
+                                            bool sync) {
+    static_assert(CW % 4 == 0 && CW <= 64, "CW: multiple of 4, at most 64");
+    constexpr int KU = 64 / CW;  // B rows per batch of scalar loads (64 SGPRs)
+    constexpr int AG = 16;       // A entries per lane per group (64 bytes)
+    const int lane = threadIdx.x & 63;
+    const bool live = lane < nrows;
+    const int64_t r = live ? lane : 0;
+    uint32_t *crow = C + r * ldc;
+    uint32_t acc[CW];
+    if (accumulate && FULLC) {
+#pragma unroll
+        for (int q = 0; q < CW / 4; q++) {
+            const uint4 v = reinterpret_cast<const uint4 *>(crow)[q];
+            acc[4 * q] = v.x;
+            acc[4 * q + 1] = v.y;
+            acc[4 * q + 2] = v.z;
+            acc[4 * q + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int w = 0; w < CW; w++) acc[w] = (accumulate && w < ncols) ? crow[w] : 0u;
+    }
+
+    const uint32_t *arow = A + r * lda;
+    int k = 0;
+    if (K >= AG) {
+        uint4 anext[AG / 4];
+#pragma unroll
+        for (int q = 0; q < AG / 4; q++) anext[q] = reinterpret_cast<const uint4 *>(arow)[q];
+        for (; k + AG <= K; k += AG) {
+            uint32_t na[AG];
+#pragma unroll
+            for (int q = 0; q < AG / 4; q++) {
+                na[4 * q] = ~anext[q].x;
+                na[4 * q + 1] = ~anext[q].y;
+                na[4 * q + 2] = ~anext[q].z;
+                na[4 * q + 3] = ~anext[q].w;
+            }
+            // issue the next group's loads only after the complements above
+            // have consumed this group (the empty asm statements emit
+            // nothing: they pin each value, then order the loads after them),
+            // so the loads reuse its registers
+#pragma unroll
+            for (int i = 0; i < AG; i++) asm volatile("" : "+v"(na[i]));
+            asm volatile("" ::: "memory");
+            if (k + 2 * AG <= K) {
+#pragma unroll
+                for (int q = 0; q < AG / 4; q++)
+                    anext[q] = reinterpret_cast<const uint4 *>(arow + k + AG)[q];
+            }
+#pragma unroll
+            for (int kg = 0; kg < AG; kg += KU) {
+#pragma unroll
+                for (int kk = 0; kk < KU; kk++) {
+                    const kconst uint32_t *brow =
+                        (const kconst uint32_t *)(B + (int64_t)(k + kg + kk) * ldb);
+#pragma unroll
+                    for (int w = 0; w < CW; w++) acc[w] = step32(acc[w], brow[w], na[kg + kk]);
+                }
+            }
+        }
+    }
+    for (; k < K; k++) {
+        const uint32_t na = ~arow[k];
+        const kconst uint32_t *brow = (const kconst uint32_t *)(B + (int64_t)k * ldb);
+#pragma unroll
+        for (int w = 0; w < CW; w++) acc[w] = step32(acc[w], brow[w], na);
+    }
+
+    if (sync) __syncthreads();
+    if (!live) return;
+    if (FULLC) {
+#pragma unroll
+        for (int q = 0; q < CW / 4; q++)
+            reinterpret_cast<uint4 *>(crow)[q] =
+                uint4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+    } else {
+#pragma unroll
+        for (int w = 0; w < CW; w++)
+            if (w < ncols) crow[w] = acc[w];
+    }
+}
+
+// A tile of nrows x ncols at C (ncols <= CW).  bspan: entries of each B row
+// readable from B.  When a whole CW-column segment fits the tile runs as one;
+// otherwise (the last columns of a row whose padded length is not a multiple
+// of CW) as 4-column tiles, whose 16-byte segments always fit because rows
+// are padded to 16 bytes.  With sync the whole workgroup must call this (it
+// executes one barrier, after the stores of the 4-column tiles in that case;
+// a panel update stays exact under that order because the pivot tile is
+// closed: any mix of old and new operand entries gives the same result).
+template <int CW>
+__device__ __forceinline__ void tile32(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda,
+                                       const uint32_t *B, int64_t ldb, int nrows, int ncols,
+                                       int64_t bspan, int K, bool accumulate, bool sync) {
+    if (nrows <= 0 || ncols <= 0) {
+        if (sync) __syncthreads();
+        return;
+    }
+    if (bspan >= CW) {
+        if (ncols >= CW)
+            tile32_body<CW, true>(C, ldc, A, lda, B, ldb, nrows, CW, K, accumulate, sync);
+        else
+            tile32_body<CW, false>(C, ldc, A, lda, B, ldb, nrows, ncols, K, accumulate, sync);
+        return;
+    }
+    for (int c = 0; c < ncols; c += 4)
+        tile32_body<4, false>(C + c, ldc, A, lda, B + c, ldb, nrows, min(4, ncols - c), K,
+                              accumulate, false);
+    if (sync) __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Product: grid (column chunks, row groups of 4 waves); the four waves of a
+// workgroup are stacked along the rows and share the column chunk.  FULL:
+// every chunk of the launch has CW columns inside N (a partial last chunk is
+// a separate FULL = false launch).  col_base: first column of chunk 0.
+// ---------------------------------------------------------------------------
+template <int CW, bool FULL>
+__global__ void __launch_bounds__(256)
+k_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
+           int64_t ldb, int64_t R, int K, int64_t N, int64_t col_base, int accumulate) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t row0 = ((int64_t)blockIdx.y * 4 + wave) * kRW;
+    const int64_t col0 = col_base + (int64_t)blockIdx.x * CW;
+    if (row0 >= R) return;
+    const int nrows = (int)min<int64_t>(kRW, R - row0);
+    if (FULL)
+        tile32_body<CW, true>(C + row0 * ldc + col0, ldc, A + row0 * lda, lda, B + col0, ldb,
+                              nrows, CW, K, accumulate != 0, false);
+    else
+        tile32<CW>(C + row0 * ldc + col0, ldc, A + row0 * lda, lda, B + col0, ldb, nrows,
+                   (int)min<int64_t>(CW, N - col0), ldb - col0, K, accumulate != 0, false);
+}
+
+// ---------------------------------------------------------------------------
+// Pivot tile: Warshall closure of the bs x bs tile at T (bs <= 128) by one
+// 256-thread workgroup.  Thread (ty, tx) = (t / 16, t % 16) holds rows
+// 8ty..8ty+7 x columns 8tx..8tx+7 in registers.  Row k and column k do not
+// change during step k (T_kk (x) x <= x since T_kk <= S), so the owners of
+// row k and column k publish them in LDS (the column as S - value), one
+// barrier per step, two buffers alternating so that step k+1's publication
+// cannot overwrite what a slower thread still reads for step k.  Entries
+// outside bs x bs are held as 0, the additive zero, and stay 0.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_ad32_pivot(uint32_t *T, int64_t ld, int bs) {
+    __shared__ uint32_t lds_row[2 * 128];
+    __shared__ uint32_t lds_col[2 * 128];
+    const int t = threadIdx.x;
+    const int tx = t & 15, ty = t >> 4;
+    const int c0 = 8 * tx;
+    uint32_t acc[8][8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const int row = 8 * ty + i;
+        const uint32_t *src = T + (int64_t)row * ld + c0;
+        if (row < bs && c0 + 8 <= bs) {
+            const uint4 v0 = reinterpret_cast<const uint4 *>(src)[0];
+            const uint4 v1 = reinterpret_cast<const uint4 *>(src)[1];
+            acc[i][0] = v0.x, acc[i][1] = v0.y, acc[i][2] = v0.z, acc[i][3] = v0.w;
+            acc[i][4] = v1.x, acc[i][5] = v1.y, acc[i][6] = v1.z, acc[i][7] = v1.w;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 8; c++) acc[i][c] = (row < bs && c0 + c < bs) ? src[c] : 0u;
+        }
+    }
+
+    const int nq = (bs + 7) >> 3;
+    for (int q = 0; q < nq; q++) {
+#pragma unroll
+        for (int s = 0; s < 8; s++) {
+            uint32_t *rb = lds_row + (s & 1) * 128;
+            uint32_t *cb = lds_col + (s & 1) * 128;
+            if (ty == q) {
+                reinterpret_cast<uint4 *>(rb)[2 * tx] =
+                    uint4{acc[s][0], acc[s][1], acc[s][2], acc[s][3]};
+                reinterpret_cast<uint4 *>(rb)[2 * tx + 1] =
+                    uint4{acc[s][4], acc[s][5], acc[s][6], acc[s][7]};
+            }
+            if (tx == q) {
+                reinterpret_cast<uint4 *>(cb)[2 * ty] =
+                    uint4{~acc[0][s], ~acc[1][s], ~acc[2][s], ~acc[3][s]};
+                reinterpret_cast<uint4 *>(cb)[2 * ty + 1] =
+                    uint4{~acc[4][s], ~acc[5][s], ~acc[6][s], ~acc[7][s]};
+            }
+            __syncthreads();
+            const uint4 b0 = reinterpret_cast<const uint4 *>(rb)[2 * tx];
+            const uint4 b1 = reinterpret_cast<const uint4 *>(rb)[2 * tx + 1];
+            const uint4 n0 = reinterpret_cast<const uint4 *>(cb)[2 * ty];
+            const uint4 n1 = reinterpret_cast<const uint4 *>(cb)[2 * ty + 1];
+            const uint32_t b[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+            const uint32_t nn[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+#pragma unroll
+            for (int i = 0; i < 8; i++)
+#pragma unroll
+                for (int c = 0; c < 8; c++) acc[i][c] = step32(acc[i][c], b[c], nn[i]);
+        }
+    }
+
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const int row = 8 * ty + i;
+        if (row >= bs || c0 >= bs) continue;
+        uint32_t *dst = T + (int64_t)row * ld + c0;
+        if (c0 + 8 <= bs) {
+            reinterpret_cast<uint4 *>(dst)[0] = uint4{acc[i][0], acc[i][1], acc[i][2], acc[i][3]};
+            reinterpret_cast<uint4 *>(dst)[1] = uint4{acc[i][4], acc[i][5], acc[i][6], acc[i][7]};
+        } else {
+#pragma unroll
+            for (int c = 0; c < 8; c++)
+                if (c0 + c < bs) dst[c] = acc[i][c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Panels of round K = [k0, k0 + bs), one workgroup (id bid).  Workgroups
+// [0, n_rowwg) take the row panel T_Kj (+)= T_KK * T_Kj: two 64-row halves of
+// the pivot rows times two 32-column chunks outside the pivot block.  The
+// rest take the column panel T_iK (+)= T_iK * T_KK: one 64-row chunk outside
+// the pivot block times the four 32-column chunks of the pivot block.  Each
+// panel tile is written by one workgroup, after a barrier that follows every
+// read of the workgroup's operands.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_ad32_panels(uint32_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg) {
+    constexpr int CW = kPanCW;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int bid = (int)blockIdx.x;
+    if (bid < n_rowwg) {
+        const int kc0 = k0 / CW, kc1 = (k0 + bs + CW - 1) / CW;
+        const int cc = 2 * bid + (wave >> 1);
+        const int c = cc < kc0 ? cc : cc + (kc1 - kc0);
+        const int64_t col0 = (int64_t)c * CW;
+        const int rofs = (wave & 1) * 64;
+        const int nrows = min(64, bs - rofs);
+        const int ncols = (int)min<int64_t>(CW, (int64_t)D - col0);
+        const int64_t r0 = (int64_t)k0 + rofs;
+        tile32<CW>(T + r0 * ld + col0, ld, T + r0 * ld + k0, ld, T + (int64_t)k0 * ld + col0, ld,
+                   nrows, ncols, ld - col0, bs, true, true);
+    } else {
+        const int kr0 = k0 / 64, kr1 = (k0 + bs + 63) / 64;
+        const int rc = bid - n_rowwg;
+        const int rchunk = rc < kr0 ? rc : rc + (kr1 - kr0);
+        const int64_t row0 = (int64_t)rchunk * 64;
+        const int nrows = (int)min<int64_t>(64, (int64_t)D - row0);
+        const int cofs = wave * CW;
+        const int ncols = min(CW, bs - cofs);
+        tile32<CW>(T + row0 * ld + k0 + cofs, ld, T + row0 * ld + k0, ld,
+                   T + (int64_t)k0 * ld + k0 + cofs, ld, nrows, ncols, ld - k0 - cofs, bs, true,
+                   true);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Update of round K over a rectangle of tiles: row chunks (64 rows)
+// [r_lo, r_hi) minus [r_ex0, r_ex1), column chunks (CW columns) [c_lo, c_hi)
+// minus [c_ex0, c_ex1); T_ij (+)= T_iK * T_Kj.  Workgroup (bx, by): column
+// chunk bx of the selection, row chunks 4 by .. 4 by + 3 (one per wave).
+// FULL: every selected column chunk lies inside D.
+// ---------------------------------------------------------------------------
+template <int CW, bool FULL>
+__global__ void __launch_bounds__(256)
+k_ad32_update(uint32_t *T, int64_t ld, int D, int k0, int bs, Rect q) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int c = q.c_lo + (int)blockIdx.x;
+    if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
+    int rc = q.r_lo + (int)blockIdx.y * 4 + wave;
+    if (rc >= q.r_ex0) rc += q.r_ex1 - q.r_ex0;
+    if (rc >= q.r_hi || c >= q.c_hi) return;
+    const int64_t row0 = (int64_t)rc * kRW, col0 = (int64_t)c * CW;
+    const int nrows = (int)min<int64_t>(kRW, (int64_t)D - row0);
+    uint32_t *dst = T + row0 * ld + col0;
+    const uint32_t *a = T + row0 * ld + k0;
+    const uint32_t *b = T + (int64_t)k0 * ld + col0;
+    if (FULL)
+        tile32_body<CW, true>(dst, ld, a, ld, b, ld, nrows, CW, bs, true, false);
+    else
+        tile32<CW>(dst, ld, a, ld, b, ld, nrows, (int)min<int64_t>(CW, (int64_t)D - col0),
+                   ld - col0, bs, true, false);
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+template <int CW>
+hipError_t mul_cw(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
+                  int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, hipStream_t st) {
+    const unsigned gy = (unsigned)((R + 4 * kRW - 1) / (4 * kRW));
+    const int64_t nfull = N / CW;
+    if (nfull > 0) {
+        hipLaunchKernelGGL((k_ad32_mul<CW, true>), dim3((unsigned)nfull, gy), dim3(256), 0, st, C,
+                           ldc, A, lda, B, ldb, R, (int)K, N, (int64_t)0, acc ? 1 : 0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (N % CW) {
+        hipLaunchKernelGGL((k_ad32_mul<CW, false>), dim3(1u, gy), dim3(256), 0, st, C, ldc, A, lda,
+                           B, ldb, R, (int)K, N, nfull * CW, acc ? 1 : 0);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+int blocks_of(int64_t D) { return (int)((D + kAdBlock - 1) / kAdBlock); }
+
+hipError_t update_launch(uint32_t *T, int64_t ld, int64_t D, int k0, int bs, const Rect &q,
+                         bool full, hipStream_t st) {
+    const int nr = (q.r_hi - q.r_lo) - (q.r_ex1 - q.r_ex0);
+    const int nc = (q.c_hi - q.c_lo) - (q.c_ex1 - q.c_ex0);
+    if (nr <= 0 || nc <= 0) return hipSuccess;
+    const dim3 grid((unsigned)nc, (unsigned)((nr + 3) / 4));
+    if (full)
+        hipLaunchKernelGGL((k_ad32_update<kUpdCW, true>), grid, dim3(256), 0, st, T, ld, (int)D,
+                           k0, bs, q);
+    else
+        hipLaunchKernelGGL((k_ad32_update<kUpdCW, false>), grid, dim3(256), 0, st, T, ld, (int)D,
+                           k0, bs, q);
+    return hipGetLastError();
+}
+
+// Round kb's update: every tile outside row block kb and column block kb.
+// The full column chunks go to the hot kernel, a partial last chunk (D not a
+// multiple of the chunk width) to the edge kernel.
+hipError_t update_round(uint32_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t st) {
+    const int k0 = (int)(kb * kAdBlock);
+    const int bs = (int)std::min<int64_t>(kAdBlock, D - k0);
+    const int nrc = (int)((D + kRW - 1) / kRW), ncc = (int)((D + kUpdCW - 1) / kUpdCW);
+    const int rl = k0 / kRW, rh = (k0 + bs + kRW - 1) / kRW;
+    const int cl = k0 / kUpdCW, ch = (k0 + bs + kUpdCW - 1) / kUpdCW;
+    const bool prof = prof_on();
+    if (prof) prof_begin(st);
+    Rect q{0, nrc, rl, rh, 0, ncc, cl, ch};
+    const int last = ncc - 1;
+    const bool partial = (D % kUpdCW) != 0 && !(cl <= last && last < ch);
+    if (partial) {
+        // the last chunk lies after the pivot block: drop it from the hot launch
+        q.c_hi = last;
+        q.c_ex0 = std::min(q.c_ex0, q.c_hi);
+        q.c_ex1 = std::min(q.c_ex1, q.c_hi);
+    }
+    hipError_t e = update_launch(T, ld, D, k0, bs, q, true, st);
+    if (e == hipSuccess && partial)
+        e = update_launch(T, ld, D, k0, bs, Rect{0, nrc, rl, rh, last, last + 1, last + 1, last + 1},
+                          false, st);
+    if (prof) {
+        const double rest = (double)D - bs;
+        prof_end(st, 1, 2, rest * rest * bs);
+    }
+    return e;
+}
+
+hipError_t pivot_round(uint32_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t st) {
+    const int64_t k0 = kb * kAdBlock;
+    const int bs = (int)std::min<int64_t>(kAdBlock, D - k0);
+    const bool prof = prof_on();
+    if (prof) prof_begin(st);
+    hipLaunchKernelGGL(k_ad32_pivot, dim3(1), dim3(256), 0, st, T + k0 * ld + k0, ld, bs);
+    hipError_t e = hipGetLastError();
+    if (prof) prof_end(st, 1, 0, (double)bs * bs * bs);
+    return e;
+}
+
+hipError_t panels_round(uint32_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t st) {
+    const int k0 = (int)(kb * kAdBlock);
+    const int bs = (int)std::min<int64_t>(kAdBlock, D - k0);
+    int n_rowwg = 0, n_colwg = 0;
+    dev::panel_wgs(D, k0, bs, &n_rowwg, &n_colwg);
+    const int n = n_rowwg + n_colwg;
+    if (n <= 0) return hipSuccess;
+    const bool prof = prof_on();
+    if (prof) prof_begin(st);
+    hipLaunchKernelGGL(k_ad32_panels, dim3((unsigned)n), dim3(256), 0, st, T, ld, (int)D, k0, bs,
+                       n_rowwg);
+    hipError_t e = hipGetLastError();
+    if (prof) prof_end(st, 1, 1, 2.0 * (double)(D - bs) * bs * bs);
+    return e;
+}
+
+}  // namespace
+
+hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda,
+                           const uint32_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
+                           bool accumulate, hipStream_t stream) {
+    // 16-column tiles when 32-column ones would leave the chip short of waves
+    const int64_t waves32 = ((R + kRW - 1) / kRW) * ((N + 31) / 32);
+    if (waves32 >= 8192)
+        return mul_cw<32>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, stream);
+    return mul_cw<16>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, stream);
+}
+
+hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, hipStream_t stream) {
+    static_assert(kPanCW == 2 * dev::kPanelNW, "panel chunking of panel_wgs");
+    const int nb = blocks_of(D);
+    hipError_t e = hipSuccess;
+    for (int kb = 0; kb < nb && e == hipSuccess; kb++) {
+        e = pivot_round(T, ld, D, kb, stream);
+        if (e == hipSuccess && nb > 1) e = panels_round(T, ld, D, kb, stream);
+        if (e == hipSuccess && nb > 1) e = update_round(T, ld, D, kb, stream);
+    }
+    return e;
+}
+
+}  // namespace sr

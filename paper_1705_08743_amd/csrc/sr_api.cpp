@@ -38,25 +38,29 @@ int device_fail(hipError_t e, const char *what) {
     return fail(SR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-bool valid_kind(int kind) {
-    return kind == SR_BOOL || kind == SR_ANTIDIST_U8 || kind == SR_ANTIDIST_U16 ||
-           kind == SR_DISTANCE_U8 || kind == SR_DISTANCE_U16;
-}
+bool valid_kind(int kind) { return kind >= SR_BOOL && kind <= SR_DISTANCE_U32; }
 
-bool is_dist(int kind) { return kind == SR_DISTANCE_U8 || kind == SR_DISTANCE_U16; }
+bool is_dist(int kind) {
+    return kind == SR_DISTANCE_U8 || kind == SR_DISTANCE_U16 || kind == SR_DISTANCE_U32;
+}
 
 // The anti-distance kind of the same width (distance kinds are computed as
 // anti-distance ones through the De Morgan laws: not a = S - a).
 int base_kind(int kind) {
     if (kind == SR_DISTANCE_U8) return SR_ANTIDIST_U8;
     if (kind == SR_DISTANCE_U16) return SR_ANTIDIST_U16;
+    if (kind == SR_DISTANCE_U32) return SR_ANTIDIST_U32;
     return kind;
 }
 
 // bytes per storage unit of the leading dimension
 int64_t unit_bytes(int kind) {
-    kind = base_kind(kind);
-    return kind == SR_BOOL ? 8 : (kind == SR_ANTIDIST_U8 ? 1 : 2);
+    switch (base_kind(kind)) {
+        case SR_BOOL: return 8;
+        case SR_ANTIDIST_U8: return 1;
+        case SR_ANTIDIST_U16: return 2;
+        default: return 4;
+    }
 }
 
 // storage units needed per row for `cols` columns
@@ -147,6 +151,9 @@ int mul_compute(int kind, void *C, int64_t ldc, const void *A, int64_t lda, cons
         e = sr::launch_ad_mul(false, static_cast<uint16_t *>(C), ldc,
                               static_cast<const uint16_t *>(A), lda,
                               static_cast<const uint16_t *>(B), ldb, R, K, N, acc, st);
+    } else if (kind == SR_ANTIDIST_U32) {
+        e = sr::launch_ad32_mul(static_cast<uint32_t *>(C), ldc, static_cast<const uint32_t *>(A),
+                                lda, static_cast<const uint32_t *>(B), ldb, R, K, N, acc, st);
     } else {
         // uint8: widen to uint16 working copies, multiply with S = 255, narrow.
         const int64_t lk = round_up(std::max<int64_t>(K, 1), 64);
@@ -325,6 +332,8 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
         e = sr::launch_bool_closure(static_cast<uint64_t *>(T), ldt, D, serial, path, st);
     } else if (e == hipSuccess && ak == SR_ANTIDIST_U16) {
         e = sr::launch_ad_closure(false, static_cast<uint16_t *>(T), ldt, D, serial, st);
+    } else if (e == hipSuccess && ak == SR_ANTIDIST_U32) {
+        e = sr::launch_ad32_closure(static_cast<uint32_t *>(T), ldt, D, st);
     } else if (e == hipSuccess) {
         const int64_t lw = round_up(D, 64);
         void *w = nullptr;
@@ -341,7 +350,10 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
     // reflexive closure I (+) T (eq. rtc): the diagonal of the multiplicative
     // identity -- S (anti-distance), 0 (distance), 1 (Boolean)
     if (e == hipSuccess && (flags & SR_REFLEXIVE)) {
-        const uint32_t one = is_dist(kind) ? 0u : (kind == SR_ANTIDIST_U8 ? 255u : 65535u);
+        const uint32_t one = is_dist(kind) ? 0u
+                             : kind == SR_ANTIDIST_U8  ? 255u
+                             : kind == SR_ANTIDIST_U16 ? 65535u
+                                                       : 0xFFFFFFFFu;
         e = sr::launch_diag(es, T, ldt, D, one, st);
     }
     if (e != hipSuccess) return device_fail(e, "closure launch");
@@ -353,6 +365,8 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
     if (!valid_kind(kind)) return fail(SR_EINVAL, "closure_batched: invalid kind %d", kind);
     if (kind == SR_BOOL)
         return fail(SR_EUNSUPPORTED, "closure_batched: Boolean batches are not built");
+    if (base_kind(kind) == SR_ANTIDIST_U32)
+        return fail(SR_EUNSUPPORTED, "closure_batched: 32-bit batches are not built");
     if (flags & ~(unsigned)SR_REFLEXIVE)
         return fail(SR_EINVAL, "closure_batched: unknown flags 0x%x", flags);
     if (count < 0) return fail(SR_EINVAL, "closure_batched: negative count");

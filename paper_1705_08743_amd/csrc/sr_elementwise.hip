@@ -1,6 +1,7 @@
 // Entrywise operations of the table in Sec. V -- and = min, or = max (the
 // matrix (+) of Sec. II), xor = |a - b|, not = S - a -- on anti-distance or
-// distance entries (uint8 / uint16, where S - a is the bitwise complement) and
+// distance entries (uint8 / uint16 / uint32, where S - a is the bitwise
+// complement) and
 // on Boolean words (AND, OR, XOR, NOT with the padding bits kept zero).  One
 // thread per 16-byte group of a row; HBM-bound.  Also the diagonal write of
 // the reflexive closure I (+) T (eq. rtc).
@@ -28,12 +29,16 @@ __device__ __forceinline__ uint32_t lanes_op(int op, uint32_t a, uint32_t b) {
     return __builtin_bit_cast(uint32_t, r);
 }
 
-// One 32-bit word of a row: OP on entries of ES bytes (1, 2) or on bits (8).
+// One 32-bit word of a row: OP on entries of ES bytes (1, 2, 4) or on bits (8).
 template <int ES, int OP>
 __device__ __forceinline__ uint32_t op_word(uint32_t a, uint32_t b) {
     if (OP == EW_NOT) return ~a;
     if (ES == 1) return lanes_op<u8x4>(OP, a, b);
     if (ES == 2) return lanes_op<u16x2>(OP, a, b);
+    if (ES == 4) {
+        const uint32_t lo = min(a, b), hi = max(a, b);
+        return OP == EW_AND ? lo : (OP == EW_OR ? hi : hi - lo);
+    }
     return OP == EW_AND ? (a & b) : (OP == EW_OR ? (a | b) : (a ^ b));
 }
 
@@ -100,7 +105,7 @@ hipError_t ewise_es(int op, uint8_t *c, int64_t ldcb, const uint8_t *a, int64_t 
     return hipGetLastError();
 }
 
-// Diagonal of a D x D matrix: entries set to `value` (ES = 1, 2), or bit i of
+// Diagonal of a D x D matrix: entries set to `value` (ES = 1, 2, 4), or bit i of
 // row i set (ES = 8, Boolean words).  One thread per row.
 template <int ES>
 __global__ void __launch_bounds__(256) k_diag(uint8_t *T, int64_t ldb, int64_t D, uint32_t value) {
@@ -111,6 +116,8 @@ __global__ void __launch_bounds__(256) k_diag(uint8_t *T, int64_t ldb, int64_t D
         row[i] = (uint8_t)value;
     else if (ES == 2)
         reinterpret_cast<uint16_t *>(row)[i] = (uint16_t)value;
+    else if (ES == 4)
+        reinterpret_cast<uint32_t *>(row)[i] = value;
     else
         reinterpret_cast<uint32_t *>(row)[i >> 5] |= 1u << (i & 31);
 }
@@ -131,6 +138,7 @@ hipError_t launch_ewise(int elem_bytes, int op, void *C, int64_t ldc, const void
     switch (elem_bytes) {
         case 1: return ewise_es<1>(op, c, ldc * e, a, lda * e, b, ldb * e, R, nbytes, nbits, blocks, stream);
         case 2: return ewise_es<2>(op, c, ldc * e, a, lda * e, b, ldb * e, R, nbytes, nbits, blocks, stream);
+        case 4: return ewise_es<4>(op, c, ldc * e, a, lda * e, b, ldb * e, R, nbytes, nbits, blocks, stream);
         default: return ewise_es<8>(op, c, ldc * e, a, lda * e, b, ldb * e, R, nbytes, nbits, blocks, stream);
     }
 }
@@ -149,6 +157,7 @@ hipError_t launch_diag(int elem_bytes, void *T, int64_t ld, int64_t D, uint32_t 
     switch (elem_bytes) {
         case 1: hipLaunchKernelGGL(k_diag<1>, grid, dim3(256), 0, stream, t, ldb, D, value); break;
         case 2: hipLaunchKernelGGL(k_diag<2>, grid, dim3(256), 0, stream, t, ldb, D, value); break;
+        case 4: hipLaunchKernelGGL(k_diag<4>, grid, dim3(256), 0, stream, t, ldb, D, value); break;
         default: hipLaunchKernelGGL(k_diag<8>, grid, dim3(256), 0, stream, t, ldb, D, value); break;
     }
     return hipGetLastError();

@@ -29,6 +29,14 @@ hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, i
 hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, bool serial,
                              hipStream_t stream);
 
+// Anti-distance with uint32 entries and S = 2^32 - 1 (sr_antidist32.hip):
+// product (strides in elements, multiples of 4) and in-place closure (every
+// phase in order on `stream`).
+hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda,
+                           const uint32_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
+                           bool accumulate, hipStream_t stream);
+hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, hipStream_t stream);
+
 // Individual phases of one blocked Floyd-Warshall round (for tests/timing).
 hipError_t launch_ad_fw_pivot(bool s8, uint16_t *T, int64_t ld, int64_t D, int64_t kb,
                               hipStream_t stream);
@@ -72,7 +80,7 @@ hipError_t launch_bool_mul_mfma(uint64_t *C, int64_t ldc, const uint64_t *A, int
 // and = min, or = max, xor = |a - b|, not = S - a; on Boolean words AND, OR,
 // XOR, NOT.
 enum { EW_AND = 0, EW_OR = 1, EW_XOR = 2, EW_NOT = 3 };
-// elem_bytes 1 or 2: entries; 8: Boolean 64-bit words.  Widths N in elements
+// elem_bytes 1, 2 or 4: entries; 8: Boolean 64-bit words.  Widths N in elements
 // (words for Boolean); nbits: bits per Boolean row (Boolean NOT clears the
 // bits beyond it).  B is not read for EW_NOT.
 hipError_t launch_ewise(int elem_bytes, int op, void *C, int64_t ldc, const void *A, int64_t lda,
@@ -81,7 +89,7 @@ hipError_t launch_ewise(int elem_bytes, int op, void *C, int64_t ldc, const void
 // Entrywise (+) (EW_OR).
 hipError_t launch_add(int elem_bytes, void *C, int64_t ldc, const void *A, int64_t lda,
                       const void *B, int64_t ldb, int64_t R, int64_t N, hipStream_t stream);
-// Diagonal of a D x D matrix: entries := value (elem_bytes 1, 2), or bit i of
+// Diagonal of a D x D matrix: entries := value (elem_bytes 1, 2, 4), or bit i of
 // row i set (8).
 hipError_t launch_diag(int elem_bytes, void *T, int64_t ld, int64_t D, uint32_t value,
                        hipStream_t stream);

@@ -7,11 +7,11 @@ import numpy as np
 import oracle
 import synthgen
 
-S_OF = {1: 255, 2: 65535, 3: 255, 4: 65535}
+S_OF = {1: 255, 2: 65535, 3: 255, 4: 65535, 5: 2 ** 32 - 1, 6: 2 ** 32 - 1}
 
 
 def np_dtype(kind):
-    return {1: np.uint8, 2: np.uint16, 3: np.uint8, 4: np.uint16}[kind]
+    return {1: np.uint8, 2: np.uint16, 3: np.uint8, 4: np.uint16, 5: np.uint32, 6: np.uint32}[kind]
 
 
 def rand_dist(R, C, kind, gen, p=0.3, wmax=None):

@@ -168,3 +168,23 @@ def test_padded_ld():
     assert sr.padded_ld(37, sr.SR_ANTIDIST_U16) == 64
     assert sr.padded_ld(37, sr.SR_ANTIDIST_U8) == 128
     assert sr.padded_ld(256, sr.SR_BOOL) == 16
+
+
+def test_u32_kinds_validation(L):
+    """32-bit kinds: 16-byte rows are multiples of 4 entries; batches are
+    not built for them."""
+    for kind in (sr.SR_ANTIDIST_U32, sr.SR_DISTANCE_U32):
+        assert mul(L, kind, P, 6, P + 4096, 4, P + 8192, 4, 4, 4, 4) == sr.SR_EALIGN  # 24-byte rows
+        assert mul(L, kind, P + 8, 4, P + 4096, 4, P + 8192, 4, 4, 4, 4) == sr.SR_EALIGN
+        assert mul(L, kind, P, 4, P + 32, 4, P + 8192, 4, 4, 4, 4) == sr.SR_EALIAS  # 64-byte C
+        assert mul(L, kind, P, 4, P + 4096, 4, P + 8192, 4, 4, 4, 4, sr.SR_BOOL_M4R) == sr.SR_EINVAL
+        assert L.closure(kind, P, 2, 4, 0, None) == sr.SR_EINVAL  # ld < D
+        assert L.closure(kind, P, 4, 4, sr.SR_BOOL_MFMA, None) == sr.SR_EUNSUPPORTED
+        n = 1
+        ptrs = (ctypes.c_void_p * n)(P)
+        lds = (ctypes.c_int64 * n)(4)
+        dims = (ctypes.c_int64 * n)(4)
+        assert L.closure_batched(kind, ptrs, lds, dims, n, 0, None) == sr.SR_EUNSUPPORTED
+    assert sr.padded_ld(37, sr.SR_ANTIDIST_U32) == 64
+    assert sr.padded_ld(37, sr.SR_DISTANCE_U32) == 64
+    assert sr.elem_bytes(sr.SR_ANTIDIST_U32) == 4

@@ -1,0 +1,237 @@
+"""Bit-exact parity of the 32-bit anti-distance and distance kinds
+(S = 2^32 - 1) with the oracle's int64 loops, through the C ABI.
+
+Sizes span several wave tiles (64 rows x 32 columns), pivot blocks of 128 and
+ragged tails; strides include the 16-byte minimum (4 entries), which sends
+the last columns of a row to the 4-column fallback tiles.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1705_08743_amd as sr
+import synthgen
+from gpu_util import rand_antidist, rand_dist, set_oracle_threads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+S = 2 ** 32 - 1
+AD = sr.SR_ANTIDIST_U32
+DI = sr.SR_DISTANCE_U32
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    set_oracle_threads()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(host, ld=None):
+    """Device copy; ld=None pads rows to 128 bytes, else exactly ld entries."""
+    host = np.ascontiguousarray(host, dtype=np.uint32)
+    if ld is None:
+        return sr.to_device(AD, host)
+    buf = torch.zeros((max(host.shape[0], 1), ld), dtype=torch.int32,
+                      device="cuda").view(torch.uint32)
+    buf[:host.shape[0], :host.shape[1]].copy_(torch.from_numpy(host))
+    return buf[:host.shape[0], :host.shape[1]]
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return sr.to_host(t).astype(np.int64)
+
+
+MUL_SHAPES = [(1, 1, 1), (3, 5, 2), (64, 64, 64), (65, 130, 129), (200, 37, 300),
+              (257, 8, 513), (130, 300, 70), (511, 129, 1000), (2100, 64, 2100)]
+
+
+@pytest.mark.parametrize("R,K,N", MUL_SHAPES)
+def test_ad32_mul(R, K, N):
+    gen = synthgen.generator(9000 + R * 7 + K * 3 + N)
+    A = rand_antidist(R, K, AD, gen, p=0.4)
+    B = rand_antidist(K, N, AD, gen, p=0.4)
+    C = sr.empty(AD, R, N)
+    sr.semiring_mul(AD, C, dev(A), dev(B))
+    assert np.array_equal(host(C), oracle.ad_mul(A, B, S))
+
+
+def test_ad32_mul_accumulate_and_k0():
+    gen = synthgen.generator(9001)
+    A = rand_antidist(70, 45, AD, gen)
+    B = rand_antidist(45, 90, AD, gen)
+    C0 = rand_antidist(70, 90, AD, gen, p=0.5)
+    C = dev(C0)
+    sr.semiring_mul(AD, C, dev(A), dev(B), flags=sr.SR_ACCUMULATE)
+    assert np.array_equal(host(C), oracle.ad_mul(A, B, S, C=C0))
+    Z = dev(C0)
+    sr.semiring_mul(AD, Z, dev(A[:, :0]), dev(B[:0]), K=0)
+    assert not host(Z).any()
+    Z2 = dev(C0)
+    sr.semiring_mul(AD, Z2, dev(A[:, :0]), dev(B[:0]), K=0, flags=sr.SR_ACCUMULATE)
+    assert np.array_equal(host(Z2), C0.astype(np.int64))
+
+
+@pytest.mark.parametrize("R,K,N", [(150, 77, 201), (70, 19, 30), (9, 3, 5)])
+def test_ad32_mul_min_strides_and_padding(R, K, N):
+    """Row strides of 16 bytes granularity (not multiples of the 32-column
+    tile); the caller's columns between N and ld are left as they were."""
+    gen = synthgen.generator(9002 + R)
+    lda, ldb = -(-K // 4) * 4, -(-N // 4) * 4
+    A = rand_antidist(R, K, AD, gen)
+    B = rand_antidist(K, N, AD, gen)
+    buf = torch.full((R, ldb + 4), 7, dtype=torch.int32, device="cuda").view(torch.uint32)
+    sr.semiring_mul(AD, buf[:, :N], dev(A, ld=lda), dev(B, ld=ldb))
+    full = host(buf)
+    assert np.array_equal(full[:, :N], oracle.ad_mul(A, B, S))
+    assert (full[:, N:] == 7).all()
+
+
+CLO_SIZES = [1, 2, 37, 64, 127, 128, 129, 200, 255, 256, 300, 513, 1100]
+
+
+@pytest.mark.parametrize("D", CLO_SIZES)
+def test_ad32_closure(D):
+    gen = synthgen.generator(9100 + D)
+    A = rand_antidist(D, D, AD, gen, p=min(0.5, 4.0 / D), wmax=S // 3)
+    T = dev(A)
+    sr.closure(AD, T)
+    assert np.array_equal(host(T), oracle.ad_closure(A, S))
+
+
+@pytest.mark.parametrize("D", [130, 300])
+def test_ad32_closure_min_stride(D):
+    gen = synthgen.generator(9101 + D)
+    A = rand_antidist(D, D, AD, gen, p=0.02, wmax=S // 4)
+    T = dev(A, ld=-(-D // 4) * 4)
+    sr.closure(AD, T)
+    assert np.array_equal(host(T), oracle.ad_closure(A, S))
+
+
+def test_ad32_closure_saturation_cycle():
+    """Directed cycle whose edges have distance just over S/3: closed form,
+    with paths of three or more edges saturating to 0 (no path)."""
+    D = 257
+    w = S // 3 + 1
+    A = np.zeros((D, D), np.uint32)
+    A[np.arange(D), (np.arange(D) + 1) % D] = S - w
+    T = dev(A)
+    sr.closure(AD, T)
+    i = np.arange(D)[:, None]
+    j = np.arange(D)[None, :]
+    hops = ((j - i - 1) % D) + 1
+    want = np.where(hops * w >= S, 0, S - np.minimum(hops * w, S))
+    assert np.array_equal(host(T), want)
+
+
+def test_ad32_closure_agrees_with_u16_on_scaled_input():
+    """Entries S16 - w (uint16) and S32 - w (uint32) encode the same
+    distances; with all path lengths below 65535 the two closures encode the
+    same distances too (a cross-check of the 32-bit and 16-bit kernels)."""
+    gen = synthgen.generator(9102)
+    D = 700
+    rows, cols = synthgen.bernoulli_edges(D, 0.01, gen)
+    w = gen.integers(1, 60, size=len(rows))
+    A16 = synthgen.encode_antidist(D, rows, cols, w, np.uint16)
+    A32 = np.where(A16 > 0, S - (65535 - A16.astype(np.int64)), 0).astype(np.uint32)
+    T16 = sr.to_device(sr.SR_ANTIDIST_U16, A16)
+    T32 = dev(A32)
+    sr.closure(sr.SR_ANTIDIST_U16, T16)
+    sr.closure(AD, T32)
+    h16 = host(T16)
+    h32 = host(T32)
+    d16 = np.where(h16 > 0, 65535 - h16, -1)
+    d32 = np.where(h32 > 0, S - h32, -1)
+    assert np.array_equal(d16, d32)
+
+
+@pytest.mark.parametrize("R,K,N", [(1, 1, 1), (3, 5, 2), (65, 130, 129), (200, 37, 300)])
+def test_dist32_mul(R, K, N):
+    gen = synthgen.generator(9200 + R + K + N)
+    A = rand_dist(R, K, DI, gen, p=0.3)
+    B = rand_dist(K, N, DI, gen, p=0.3)
+    C = sr.empty(DI, R, N)
+    sr.semiring_mul(DI, C, dev(A), dev(B))
+    assert np.array_equal(host(C), oracle.dist_mul(A, B, S))
+    C0 = rand_dist(R, N, DI, gen, p=0.5)
+    Cd = dev(C0)
+    sr.semiring_mul(DI, Cd, dev(A), dev(B), flags=sr.SR_ACCUMULATE)
+    assert np.array_equal(host(Cd), oracle.dist_mul(A, B, S, C=C0))
+
+
+@pytest.mark.parametrize("D", [1, 37, 129, 300])
+def test_dist32_closure_and_reflexive(D):
+    gen = synthgen.generator(9300 + D)
+    A = rand_dist(D, D, DI, gen, p=min(0.5, 3.0 / D), wmax=S // 4)
+    T = dev(A)
+    sr.closure(DI, T)
+    want = oracle.dist_closure(A, S)
+    assert np.array_equal(host(T), want)
+    T2 = dev(A)
+    sr.closure(DI, T2, flags=sr.SR_REFLEXIVE)
+    assert np.array_equal(host(T2), oracle.reflexive(want, 0))
+
+
+def test_ad32_reflexive():
+    gen = synthgen.generator(9400)
+    for D in (1, 130, 300):
+        A = rand_antidist(D, D, AD, gen, p=min(0.5, 2.0 / D), wmax=S // 3)
+        T = dev(A)
+        sr.closure(AD, T, flags=sr.SR_REFLEXIVE)
+        assert np.array_equal(host(T), oracle.reflexive(oracle.ad_closure(A, S), S)), D
+
+
+@pytest.mark.parametrize("kind", [AD, DI])
+@pytest.mark.parametrize("op,name", [(sr.SR_EW_AND, "and"), (sr.SR_EW_OR, "or"),
+                                     (sr.SR_EW_XOR, "xor"), (sr.SR_EW_NOT, "not")])
+def test_ewise32(kind, op, name):
+    gen = synthgen.generator(9500 + kind * 10 + op)
+    R, N = 77, 333
+    A = gen.integers(0, S + 1, size=(R, N)).astype(np.uint32)
+    B = gen.integers(0, S + 1, size=(R, N)).astype(np.uint32)
+    A[0, :3] = [0, S, S]
+    B[0, :3] = [S, 0, S]
+    C = sr.empty(kind, R, N)
+    sr.semiring_ewise(kind, op, C, dev(A), None if name == "not" else dev(B))
+    want = oracle.ewise(name, A, None if name == "not" else B, S)
+    assert np.array_equal(host(C), want)
+    Ad = dev(A)
+    sr.semiring_ewise(kind, op, Ad, Ad, None if name == "not" else dev(B))
+    assert np.array_equal(host(Ad), want)
+
+
+def test_add32():
+    gen = synthgen.generator(9600)
+    A = rand_antidist(50, 70, AD, gen, p=0.5)
+    B = rand_antidist(50, 70, AD, gen, p=0.5)
+    C = sr.empty(AD, 50, 70)
+    sr.semiring_add(AD, C, dev(A), dev(B))
+    assert np.array_equal(host(C), np.maximum(A, B).astype(np.int64))
+    Cd = sr.empty(DI, 50, 70)
+    sr.semiring_add(DI, Cd, dev(A), dev(B))
+    assert np.array_equal(host(Cd), np.minimum(A, B).astype(np.int64))
+
+
+def test_batched32_is_unsupported():
+    T = dev(np.zeros((4, 4), np.uint32))
+    with pytest.raises(sr.SemiringError) as e:
+        sr.closure_batched(AD, [T])
+    assert e.value.code == sr.SR_EUNSUPPORTED
+
+
+def test_ad32_closure_rows_at_d4096():
+    """D = 4096 (32 pivot blocks): sampled rows against the oracle's
+    per-row path computation."""
+    gen = synthgen.generator(9700)
+    D = 4096
+    A = rand_antidist(D, D, AD, gen, p=3.0 / D, wmax=S // 8)
+    T = dev(A)
+    sr.closure(AD, T)
+    rows = np.array([0, 1, 127, 128, 2047, 4000, 4095])
+    got = host(T)[rows]
+    assert np.array_equal(got, oracle.ad_closure_rows(A, S, rows))
