@@ -12,7 +12,8 @@ out-degree 3 plus planted strongly connected blocks), boolmul16384 (Boolean
 product A * A of that matrix, word-parallel and int8 matrix-core paths),
 mul1024 (uint16 product of two 1024 x 1024 graphs), u8fw8192 (uint8 closure,
 distances in [1, 200]), dfw8192 (the headline input as a distance matrix,
-closed with min and saturating +), batched (4096 graphs, log-uniform sizes in [32, 1024],
+closed with min and saturating +), u32fw8192 (the headline distances in
+uint32 entries, S = 2^32 - 1), batched (4096 graphs, log-uniform sizes in [32, 1024],
 uint16, one call vs one at a time), add8192 (entrywise max, HBM-bound), serve
 (continuously batched closure requests vs serial).
 
@@ -37,6 +38,8 @@ if ROOT not in sys.path:
 # covers 32 Boolean updates.  HBM peak 8 TB/s.
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 PEAK_ANTIDIST = VALU_LANE_OPS
+# uint32 entries are not packed: a saturating subtract and a max per update
+PEAK_ANTIDIST32 = VALU_LANE_OPS / 2
 PEAK_BOOL = 32 * VALU_LANE_OPS
 # dense int8 matrix-core rate (MI355X datasheet: 5.0 POP/s = 2.5e15 MAC/s); one
 # MAC is one Boolean update on the SR_BOOL_MFMA path
@@ -50,9 +53,13 @@ TRAFFIC = {
     # workgroups): FETCH_SIZE 1.692e5 KiB x 2.000 + WRITE_SIZE 1.270e5 KiB x 1.000
     "fw8192": {"src_hash": "5dc0758f2f7c956b", "bytes_per_launch": 4.766e8},
     "u8fw8192": {"src_hash": None, "bytes_per_launch": None},
-    # full update launches of the D = 16384 Boolean closure (serialized phases),
-    # launch-weighted mean of the 16- and 17-chunk shapes
-    "bool16384": {"src_hash": "319c0dad5dd06799", "bytes_per_launch": 1.109e8},
+    # full update launch of the D = 8192 uint32 closure (252 x 32 workgroups):
+    # FETCH_SIZE 2.049e5 KiB x 2.000 + WRITE_SIZE 2.807e5 KiB x 1.000
+    "u32fw8192": {"src_hash": "ba43132baf09b2ca", "bytes_per_launch": 7.069e8},
+    # full update launches (four-Russians kernel, 32 x 32 tiles of 512 x 512
+    # bits) of the serialized D = 16384 Boolean closure: FETCH_SIZE 4.392e4 KiB
+    # x 2.000 + WRITE_SIZE 3.178e4 KiB x 1.000
+    "bool16384": {"src_hash": "1ab7eff727a57fcc", "bytes_per_launch": 1.225e8},
 }
 
 
@@ -60,11 +67,16 @@ def src_hash(workload):
     """Hash of the device source of the workload's update kernel: for
     anti-distance the tile code (sr_tiles.h) and the text of the
     k_ad_fw_update kernel template (host-side changes elsewhere in
-    sr_antidist.hip do not change the kernel); for Boolean sr_bool.hip."""
+    sr_antidist.hip do not change the kernel); for Boolean sr_bool.hip; for
+    the uint32 path sr_antidist32.hip."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1705_08743_amd/csrc")
     if workload.startswith("bool"):
         with open(os.path.join(csrc, "sr_bool.hip"), "rb") as f:
+            h.update(f.read())
+        return h.hexdigest()[:16]
+    if workload.startswith("u32"):
+        with open(os.path.join(csrc, "sr_antidist32.hip"), "rb") as f:
             h.update(f.read())
         return h.hexdigest()[:16]
     with open(os.path.join(csrc, "sr_tiles.h"), "rb") as f:
@@ -100,7 +112,7 @@ def cpu_baseline_fw(A, S, target_s, threads):
     import oracle
     oracle.set_threads(threads)
     D = A.shape[0]
-    A32 = np.ascontiguousarray(A[:, :D], dtype=np.int32)
+    A32 = np.ascontiguousarray(A[:, :D], dtype=np.int64 if S > 2 ** 31 - 1 else np.int32)
     # size the sample from two short calibration runs: their difference is
     # the cost of m0 pivots without the fixed per-call cost (copies, threads)
     m0 = min(D, 32)
@@ -160,7 +172,8 @@ def kernel_timing_pass(args, torch, sr, kind, src, bufs, close):
     return phases
 
 
-def run_fw(args, torch, sr, kind, D, make_input, workload, S, metric, dual=False):
+def run_fw(args, torch, sr, kind, D, make_input, workload, S, metric, dual=False,
+           peak=PEAK_ANTIDIST, kernel="k_ad_fw_update (update phase)"):
     import numpy as np
     log("generating input D=%d ..." % D)
     A = make_input()
@@ -197,13 +210,13 @@ def run_fw(args, torch, sr, kind, D, make_input, workload, S, metric, dual=False
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {sr.SR_ANTIDIST_U16: "u16", sr.SR_ANTIDIST_U8: "u8",
-                  sr.SR_DISTANCE_U16: "u16"}[kind],
+                  sr.SR_DISTANCE_U16: "u16", sr.SR_ANTIDIST_U32: "u32"}[kind],
         "data": "synthetic",
-        "roofline": {"bound": "alu", "kernel": "k_ad_fw_update (update phase)",
-                     "achieved": achieved, "peak": PEAK_ANTIDIST, "unit": "updates/s",
-                     "frac": achieved / PEAK_ANTIDIST, "traffic": traffic},
+        "roofline": {"bound": "alu", "kernel": kernel,
+                     "achieved": achieved, "peak": peak, "unit": "updates/s",
+                     "frac": achieved / peak, "traffic": traffic},
         "phases": phases,
-        "fraction_of_valu_roofline_whole_step": float(D) ** 3 / (ms_step * 1e-3) / PEAK_ANTIDIST,
+        "fraction_of_valu_roofline_whole_step": float(D) ** 3 / (ms_step * 1e-3) / peak,
     }
     if not args.no_parity:
         out["parity"] = parity_rows(sr.to_host(bufs[-1]), host, S, args.parity_rows, 7, dual)
@@ -365,7 +378,7 @@ def run_add(args, torch, sr, synthgen):
             "vs_baseline": None, "dtype": "u16", "data": "synthetic",
             "config": {"workload": "antidist_u16_add_8192", "bytes_per_call": nbytes,
                        "parallelism": "single_gpu"},
-            "roofline": {"bound": "hbm", "kernel": "k_add<2>", "achieved": gbs, "peak": 8000.0,
+            "roofline": {"bound": "hbm", "kernel": "k_ewise<2, EW_OR>", "achieved": gbs, "peak": 8000.0,
                          "unit": "GB/s", "frac": gbs / 8000.0, "traffic": None}}
 
 
@@ -497,8 +510,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fw8192",
-                    choices=["fw8192", "u8fw8192", "dfw8192", "bool16384", "boolmul16384", "mul1024",
-                             "batched", "add8192", "serve"])
+                    choices=["fw8192", "u8fw8192", "dfw8192", "u32fw8192", "bool16384",
+                             "boolmul16384", "mul1024", "batched", "add8192", "serve"])
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--serve-calibration", type=int, default=24)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
@@ -548,6 +561,20 @@ def main():
                      dual=True)
         out["config"] = {"workload": "distance_u16_closure_D8192", "D": 8192,
                          "entries": "uint16 distances, 65535 = no path", "edge_p": 0.05,
+                         "distances": "U[1,1000]; 1% U[64536,65534]", "pivot_block": 128,
+                         "parallelism": "single_gpu"}
+    elif args.workload == "u32fw8192":
+        def u32_input():
+            import numpy as np
+            A = synthgen.cfg_antidist(D=8192)[:, :8192].astype(np.int64)
+            # the same distances, encoded with S = 2^32 - 1 (heavy edges no
+            # longer saturate after one more hop)
+            return np.where(A > 0, (2 ** 32 - 1) - (65535 - A), 0).astype(np.uint32)
+        out = run_fw(args, torch, sr, sr.SR_ANTIDIST_U32, 8192, u32_input, "u32fw8192",
+                     2 ** 32 - 1, "semiring updates/s (D³/t) anti-distance FW D=8192 uint32",
+                     peak=PEAK_ANTIDIST32, kernel="k_ad32_update (update phase)")
+        out["config"] = {"workload": "antidist_u32_floyd_warshall_D8192", "D": 8192,
+                         "entries": "uint32, S=2^32-1", "edge_p": 0.05,
                          "distances": "U[1,1000]; 1% U[64536,65534]", "pivot_block": 128,
                          "parallelism": "single_gpu"}
     elif args.workload == "bool16384":

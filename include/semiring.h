@@ -166,13 +166,11 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
  * becomes 1, S, or 0 for distances -- the paper's transclosure /
  * dransclosure), SR_BOOL_BITWISE, SR_SERIAL_PHASES; SR_BOOL_MFMA returns
  * SR_EUNSUPPORTED.  D = 0 is a no-op.
- * By default a closure of the 8- and 16-bit and Boolean kinds with more than
- * two pivot blocks forks onto a second,
+ * By default a closure with more than two pivot blocks forks onto a second,
  * library-owned stream of default priority (the next round's pivot and panels
  * overlap the bulk of the current update) and joins back into `stream`
  * before the call's work completes; the fork/join is event-based, so the
- * sequence can be captured into a HIP graph from `stream`.  The 32-bit kinds
- * run every phase in order on `stream`.
+ * sequence can be captured into a HIP graph from `stream`.
  */
 int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream);
 

@@ -4,14 +4,16 @@
 // and (+) is v_max_u32: two VALU lane-operations per update (the 16-bit
 // kernels do two updates per pair of packed operations).
 //
-// Same algorithms as the 16-bit path (Sec. II product and blocked
-// Warshall/Floyd closure in rounds of 128 pivots: pivot tile, panels,
-// update), with 32-bit wave tiles: a wavefront owns 64 rows (lane = row) x CW
-// columns, the B row of each inner step is read with scalar loads and enters
-// every instruction as its SGPR operand, and each lane reads its own row of A
-// in 64-byte groups, one group ahead.
+// Same algorithms and schedule as the 16-bit path (Sec. II product and
+// blocked Warshall/Floyd closure in rounds of 128 pivots: pivot tile, panels,
+// update, with the next round's pivot and panels run beside the bulk of the
+// current update on a second stream), with 32-bit wave tiles: a wavefront
+// owns 64 rows (lane = row) x CW columns, the B row of each inner step is read
+// with scalar loads and enters every instruction as its SGPR operand, and each
+// lane reads its own row of A in 64-byte groups, one group ahead.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include <algorithm>
 
@@ -190,7 +192,8 @@ k_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint3
 // cannot overwrite what a slower thread still reads for step k.  Entries
 // outside bs x bs are held as 0, the additive zero, and stay 0.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_ad32_pivot(uint32_t *T, int64_t ld, int bs) {
+__global__ void __launch_bounds__(256) k_ad32_pivot(uint32_t *T, int64_t ld, int bs, int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
     __shared__ uint32_t lds_row[2 * 128];
     __shared__ uint32_t lds_col[2 * 128];
     const int t = threadIdx.x;
@@ -270,7 +273,8 @@ __global__ void __launch_bounds__(256) k_ad32_pivot(uint32_t *T, int64_t ld, int
 // read of the workgroup's operands.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
-k_ad32_panels(uint32_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg) {
+k_ad32_panels(uint32_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg, int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
     constexpr int CW = kPanCW;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int bid = (int)blockIdx.x;
@@ -308,7 +312,8 @@ k_ad32_panels(uint32_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg) {
 // ---------------------------------------------------------------------------
 template <int CW, bool FULL>
 __global__ void __launch_bounds__(256)
-k_ad32_update(uint32_t *T, int64_t ld, int D, int k0, int bs, Rect q) {
+k_ad32_update(uint32_t *T, int64_t ld, int D, int k0, int bs, Rect q, int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int c = q.c_lo + (int)blockIdx.x;
     if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
@@ -350,67 +355,92 @@ hipError_t mul_cw(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, cons
 }
 
 int blocks_of(int64_t D) { return (int)((D + kAdBlock - 1) / kAdBlock); }
+int block_k0(int64_t kb) { return (int)(kb * kAdBlock); }
+int block_bs(int64_t D, int64_t kb) { return (int)std::min<int64_t>(kAdBlock, D - kb * kAdBlock); }
+
+// chunks [lo, hi) of width w covering pivot block kb
+void block_chunks(int64_t D, int64_t kb, int w, int *lo, int *hi) {
+    const int k0 = block_k0(kb), bs = block_bs(D, kb);
+    *lo = k0 / w;
+    *hi = (k0 + bs + w - 1) / w;
+}
+
+// SR_PRIO=0 keeps the critical-path kernels at the default wave priority;
+// SR_LOOKAHEAD=0 runs every round's phases in order on the caller's stream.
+struct Tuning32 {
+    bool prio = true, lookahead = true;
+    Tuning32() {
+        if (const char *v = getenv("SR_PRIO")) prio = atoi(v) != 0;
+        if (const char *v = getenv("SR_LOOKAHEAD")) lookahead = atoi(v) != 0;
+    }
+};
+const Tuning32 &tuning() {
+    static const Tuning32 t;
+    return t;
+}
 
 hipError_t update_launch(uint32_t *T, int64_t ld, int64_t D, int k0, int bs, const Rect &q,
-                         bool full, hipStream_t st) {
+                         bool full, int prio, hipStream_t st) {
     const int nr = (q.r_hi - q.r_lo) - (q.r_ex1 - q.r_ex0);
     const int nc = (q.c_hi - q.c_lo) - (q.c_ex1 - q.c_ex0);
     if (nr <= 0 || nc <= 0) return hipSuccess;
     const dim3 grid((unsigned)nc, (unsigned)((nr + 3) / 4));
     if (full)
         hipLaunchKernelGGL((k_ad32_update<kUpdCW, true>), grid, dim3(256), 0, st, T, ld, (int)D,
-                           k0, bs, q);
+                           k0, bs, q, prio);
     else
         hipLaunchKernelGGL((k_ad32_update<kUpdCW, false>), grid, dim3(256), 0, st, T, ld, (int)D,
-                           k0, bs, q);
+                           k0, bs, q, prio);
     return hipGetLastError();
 }
 
-// Round kb's update: every tile outside row block kb and column block kb.
-// The full column chunks go to the hot kernel, a partial last chunk (D not a
-// multiple of the chunk width) to the edge kernel.
-hipError_t update_round(uint32_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t st) {
-    const int k0 = (int)(kb * kAdBlock);
-    const int bs = (int)std::min<int64_t>(kAdBlock, D - k0);
-    const int nrc = (int)((D + kRW - 1) / kRW), ncc = (int)((D + kUpdCW - 1) / kUpdCW);
-    const int rl = k0 / kRW, rh = (k0 + bs + kRW - 1) / kRW;
-    const int cl = k0 / kUpdCW, ch = (k0 + bs + kUpdCW - 1) / kUpdCW;
+// Update of round kb over a rectangle of tiles (64-row chunks x kUpdCW-column
+// chunks, one excluded range of each; an empty range is moved to the end).
+// The full column chunks go to the hot kernel; a partial last chunk of the
+// matrix (D not a multiple of the chunk width), if selected, to the edge
+// kernel.  critical: the launch is on the chain that the next round waits
+// for, its waves run at a raised priority.
+hipError_t update_rect(uint32_t *T, int64_t ld, int64_t D, int64_t kb, Rect q, double units,
+                       bool critical, hipStream_t st) {
+    if (q.r_ex1 <= q.r_ex0) q.r_ex0 = q.r_ex1 = q.r_hi;
+    if (q.c_ex1 <= q.c_ex0) q.c_ex0 = q.c_ex1 = q.c_hi;
+    const int k0 = block_k0(kb), bs = block_bs(D, kb);
+    const int prio = critical && tuning().prio ? 1 : 0;
+    const int last = (int)((D + kUpdCW - 1) / kUpdCW) - 1;
+    const bool partial = (D % kUpdCW) != 0 && q.c_lo <= last && last < q.c_hi &&
+                         !(q.c_ex0 <= last && last < q.c_ex1);
+    Rect hot = q;
+    if (partial) {
+        // the last chunk is the final one of the range: drop it from the hot launch
+        hot.c_hi = last;
+        hot.c_ex0 = std::min(hot.c_ex0, hot.c_hi);
+        hot.c_ex1 = std::min(hot.c_ex1, hot.c_hi);
+    }
     const bool prof = prof_on();
     if (prof) prof_begin(st);
-    Rect q{0, nrc, rl, rh, 0, ncc, cl, ch};
-    const int last = ncc - 1;
-    const bool partial = (D % kUpdCW) != 0 && !(cl <= last && last < ch);
-    if (partial) {
-        // the last chunk lies after the pivot block: drop it from the hot launch
-        q.c_hi = last;
-        q.c_ex0 = std::min(q.c_ex0, q.c_hi);
-        q.c_ex1 = std::min(q.c_ex1, q.c_hi);
+    hipError_t e = update_launch(T, ld, D, k0, bs, hot, true, prio, st);
+    if (e == hipSuccess && partial) {
+        const Rect edge{q.r_lo, q.r_hi, q.r_ex0, q.r_ex1, last, last + 1, last + 1, last + 1};
+        e = update_launch(T, ld, D, k0, bs, edge, false, prio, st);
     }
-    hipError_t e = update_launch(T, ld, D, k0, bs, q, true, st);
-    if (e == hipSuccess && partial)
-        e = update_launch(T, ld, D, k0, bs, Rect{0, nrc, rl, rh, last, last + 1, last + 1, last + 1},
-                          false, st);
-    if (prof) {
-        const double rest = (double)D - bs;
-        prof_end(st, 1, 2, rest * rest * bs);
-    }
+    if (prof) prof_end(st, 1, 2, units);
     return e;
 }
 
 hipError_t pivot_round(uint32_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t st) {
-    const int64_t k0 = kb * kAdBlock;
-    const int bs = (int)std::min<int64_t>(kAdBlock, D - k0);
+    const int64_t k0 = block_k0(kb);
+    const int bs = block_bs(D, kb);
     const bool prof = prof_on();
     if (prof) prof_begin(st);
-    hipLaunchKernelGGL(k_ad32_pivot, dim3(1), dim3(256), 0, st, T + k0 * ld + k0, ld, bs);
+    hipLaunchKernelGGL(k_ad32_pivot, dim3(1), dim3(256), 0, st, T + k0 * ld + k0, ld, bs,
+                       tuning().prio ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (prof) prof_end(st, 1, 0, (double)bs * bs * bs);
     return e;
 }
 
 hipError_t panels_round(uint32_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t st) {
-    const int k0 = (int)(kb * kAdBlock);
-    const int bs = (int)std::min<int64_t>(kAdBlock, D - k0);
+    const int k0 = block_k0(kb), bs = block_bs(D, kb);
     int n_rowwg = 0, n_colwg = 0;
     dev::panel_wgs(D, k0, bs, &n_rowwg, &n_colwg);
     const int n = n_rowwg + n_colwg;
@@ -418,9 +448,69 @@ hipError_t panels_round(uint32_t *T, int64_t ld, int64_t D, int64_t kb, hipStrea
     const bool prof = prof_on();
     if (prof) prof_begin(st);
     hipLaunchKernelGGL(k_ad32_panels, dim3((unsigned)n), dim3(256), 0, st, T, ld, (int)D, k0, bs,
-                       n_rowwg);
+                       n_rowwg, tuning().prio ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (prof) prof_end(st, 1, 1, 2.0 * (double)(D - bs) * bs * bs);
+    return e;
+}
+
+// Closure driver.  Round kb: pivot(kb), panels(kb), update(kb).  With the
+// second stream the update is split as in the 16-bit driver: A(kb), the
+// tiles of row and column block kb+1 (outside block kb), runs on the caller's
+// stream followed by pivot(kb+1) and panels(kb+1); B(kb), the rest, runs on
+// the second stream, queued behind B(kb-1) as soon as panels(kb) is done.
+// A(kb) writes tiles of row block kb+1 that B(kb-1) also writes, so the
+// caller's stream waits for B(kb-1) before A(kb).  B(kb) reads only row and
+// column block kb, which round kb+1 does not write.
+hipError_t closure32(uint32_t *T, int64_t ld, int64_t D, bool serial, hipStream_t st) {
+    const int nb = blocks_of(D);
+    const int nrc = (int)((D + kRW - 1) / kRW), ncc = (int)((D + kUpdCW - 1) / kUpdCW);
+    hipError_t e = pivot_round(T, ld, D, 0, st);
+    if (e != hipSuccess || nb == 1) return e;
+    if ((e = panels_round(T, ld, D, 0, st)) != hipSuccess) return e;
+    Aux *aux = (nb > 2 && !serial && tuning().lookahead) ? aux_acquire(st) : nullptr;
+    for (int kb = 0; kb < nb; kb++) {
+        int rl, rh, cl, ch;
+        block_chunks(D, kb, kRW, &rl, &rh);
+        block_chunks(D, kb, kUpdCW, &cl, &ch);
+        const double bs = block_bs(D, kb);
+        if (kb + 1 == nb || !aux) {
+            if (aux && kb > 0) e = hipStreamWaitEvent(st, aux->ev_aux[(kb - 1) & 1], 0);
+            const double rest = (double)D - bs;
+            if (e == hipSuccess)
+                e = update_rect(T, ld, D, kb, Rect{0, nrc, rl, rh, 0, ncc, cl, ch},
+                                rest * rest * bs, false, st);
+            if (e == hipSuccess && kb + 1 < nb) e = pivot_round(T, ld, D, kb + 1, st);
+            if (e == hipSuccess && kb + 1 < nb) e = panels_round(T, ld, D, kb + 1, st);
+            if (e != hipSuccess) break;
+            continue;
+        }
+        int rl1, rh1, cl1, ch1;
+        block_chunks(D, kb + 1, kRW, &rl1, &rh1);
+        block_chunks(D, kb + 1, kUpdCW, &cl1, &ch1);
+        const double bs1 = block_bs(D, kb + 1);
+        const double rest2 = (double)D - bs - bs1;
+        // B(kb) on the second stream, after panels(kb)
+        e = hipEventRecord(aux->ev_main, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(aux->stream, aux->ev_main, 0);
+        if (e == hipSuccess)
+            e = update_rect(T, ld, D, kb, Rect{0, nrc, rl, rh1, 0, ncc, cl, ch1},
+                            rest2 * rest2 * bs, false, aux->stream);
+        if (e == hipSuccess) e = hipEventRecord(aux->ev_aux[kb & 1], aux->stream);
+        if (e == hipSuccess && kb > 0) e = hipStreamWaitEvent(st, aux->ev_aux[(kb - 1) & 1], 0);
+        // A(kb): row block kb+1 (columns outside block kb), then column block
+        // kb+1 (rows outside blocks kb and kb+1); then the next pivot and panels
+        if (e == hipSuccess)
+            e = update_rect(T, ld, D, kb, Rect{rl1, rh1, rh1, rh1, 0, ncc, cl, ch},
+                            bs1 * ((double)D - bs) * bs, true, st);
+        if (e == hipSuccess)
+            e = update_rect(T, ld, D, kb, Rect{0, nrc, rl, rh1, cl1, ch1, ch1, ch1},
+                            rest2 * bs1 * bs, true, st);
+        if (e == hipSuccess) e = pivot_round(T, ld, D, kb + 1, st);
+        if (e == hipSuccess) e = panels_round(T, ld, D, kb + 1, st);
+        if (e != hipSuccess) break;
+    }
+    if (aux) aux_release(aux);
     return e;
 }
 
@@ -436,16 +526,10 @@ hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t 
     return mul_cw<16>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, stream);
 }
 
-hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, hipStream_t stream) {
+hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, bool serial,
+                               hipStream_t stream) {
     static_assert(kPanCW == 2 * dev::kPanelNW, "panel chunking of panel_wgs");
-    const int nb = blocks_of(D);
-    hipError_t e = hipSuccess;
-    for (int kb = 0; kb < nb && e == hipSuccess; kb++) {
-        e = pivot_round(T, ld, D, kb, stream);
-        if (e == hipSuccess && nb > 1) e = panels_round(T, ld, D, kb, stream);
-        if (e == hipSuccess && nb > 1) e = update_round(T, ld, D, kb, stream);
-    }
-    return e;
+    return closure32(T, ld, D, serial, stream);
 }
 
 }  // namespace sr

@@ -333,7 +333,7 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
     } else if (e == hipSuccess && ak == SR_ANTIDIST_U16) {
         e = sr::launch_ad_closure(false, static_cast<uint16_t *>(T), ldt, D, serial, st);
     } else if (e == hipSuccess && ak == SR_ANTIDIST_U32) {
-        e = sr::launch_ad32_closure(static_cast<uint32_t *>(T), ldt, D, st);
+        e = sr::launch_ad32_closure(static_cast<uint32_t *>(T), ldt, D, serial, st);
     } else if (e == hipSuccess) {
         const int64_t lw = round_up(D, 64);
         void *w = nullptr;

@@ -30,12 +30,13 @@ hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, bool s
                              hipStream_t stream);
 
 // Anti-distance with uint32 entries and S = 2^32 - 1 (sr_antidist32.hip):
-// product (strides in elements, multiples of 4) and in-place closure (every
-// phase in order on `stream`).
+// product (strides in elements, multiples of 4) and in-place closure (serial:
+// every phase in order on `stream`, without the second stream).
 hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda,
                            const uint32_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                            bool accumulate, hipStream_t stream);
-hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, hipStream_t stream);
+hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, bool serial,
+                               hipStream_t stream);
 
 // Individual phases of one blocked Floyd-Warshall round (for tests/timing).
 hipError_t launch_ad_fw_pivot(bool s8, uint16_t *T, int64_t ld, int64_t D, int64_t kb,

@@ -104,6 +104,21 @@ def test_ad32_closure(D):
     assert np.array_equal(host(T), oracle.ad_closure(A, S))
 
 
+@pytest.mark.parametrize("D", [769, 2100])
+def test_ad32_closure_lookahead_and_serial(D):
+    """Several lookahead rounds (second stream) and the serial schedule, both
+    against the oracle; D = 2100 also has a partial last column chunk."""
+    gen = synthgen.generator(9103 + D)
+    A = rand_antidist(D, D, AD, gen, p=2.0 / D, wmax=S // 6)
+    want = oracle.ad_closure(A, S)
+    T = dev(A)
+    sr.closure(AD, T)
+    T2 = dev(A)
+    sr.closure(AD, T2, flags=sr.SR_SERIAL_PHASES)
+    assert np.array_equal(host(T), want)
+    assert np.array_equal(host(T2), want)
+
+
 @pytest.mark.parametrize("D", [130, 300])
 def test_ad32_closure_min_stride(D):
     gen = synthgen.generator(9101 + D)
