@@ -38,8 +38,9 @@ if ROOT not in sys.path:
 # covers 32 Boolean updates.  HBM peak 8 TB/s.
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 PEAK_ANTIDIST = VALU_LANE_OPS
-# uint32 entries are not packed: a saturating subtract and a max per update
-PEAK_ANTIDIST32 = VALU_LANE_OPS / 2
+# uint32 entries are not packed: a saturating subtract per update, and one
+# v_max3_u32 per two updates (1.5 lane operations per update)
+PEAK_ANTIDIST32 = VALU_LANE_OPS / 1.5
 PEAK_BOOL = 32 * VALU_LANE_OPS
 # dense int8 matrix-core rate (MI355X datasheet: 5.0 POP/s = 2.5e15 MAC/s); one
 # MAC is one Boolean update on the SR_BOOL_MFMA path

@@ -1,8 +1,9 @@
 // Anti-distance semiring with 32-bit entries, S = 2^32 - 1 (the integer
 // scaling of Sec. IV with 32-bit storage).  S - a is the bitwise complement,
 // so a (x) b = max(a + b - S, 0) = b -sat (S - a) is one v_sub_u32 with clamp
-// and (+) is v_max_u32: two VALU lane-operations per update (the 16-bit
-// kernels do two updates per pair of packed operations).
+// and (+) is v_max_u32; the products of two inner steps enter the accumulator
+// through one v_max3_u32, so an update costs 1.5 VALU lane-operations (the
+// 16-bit kernels do two updates per pair of packed operations).
 //
 // Same algorithms and schedule as the 16-bit path (Sec. II product and
 // blocked Warshall/Floyd closure in rounds of 128 pivots: pivot tile, panels,
@@ -31,6 +32,15 @@ constexpr int kRW = 64;     // rows per wave tile
 
 __device__ __forceinline__ uint32_t step32(uint32_t acc, uint32_t b, uint32_t na) {
     return __builtin_elementwise_max(acc, __builtin_elementwise_sub_sat(b, na));
+}
+
+// Two inner steps: max(acc, b0 -sat na0, b1 -sat na1), which the compiler
+// emits as two v_sub_u32 (clamp) and one v_max3_u32.
+__device__ __forceinline__ uint32_t step32x2(uint32_t acc, uint32_t b0, uint32_t na0, uint32_t b1,
+                                             uint32_t na1) {
+    return __builtin_elementwise_max(
+        __builtin_elementwise_max(acc, __builtin_elementwise_sub_sat(b0, na0)),
+        __builtin_elementwise_sub_sat(b1, na1));
 }
 
 // ---------------------------------------------------------------------------
@@ -99,12 +109,18 @@ __device__ __forceinline__ void tile32_body(uint32_t *C, int64_t ldc, const uint
             }
 #pragma unroll
             for (int kg = 0; kg < AG; kg += KU) {
+                // two inner steps per accumulator update: the (+) of the
+                // accumulator with both products is one v_max3_u32, so a
+                // pair of updates costs three lane-operations instead of four
 #pragma unroll
-                for (int kk = 0; kk < KU; kk++) {
-                    const kconst uint32_t *brow =
+                for (int kk = 0; kk < KU; kk += 2) {
+                    const kconst uint32_t *b0 =
                         (const kconst uint32_t *)(B + (int64_t)(k + kg + kk) * ldb);
+                    const kconst uint32_t *b1 =
+                        (const kconst uint32_t *)(B + (int64_t)(k + kg + kk + 1) * ldb);
 #pragma unroll
-                    for (int w = 0; w < CW; w++) acc[w] = step32(acc[w], brow[w], na[kg + kk]);
+                    for (int w = 0; w < CW; w++)
+                        acc[w] = step32x2(acc[w], b0[w], na[kg + kk], b1[w], na[kg + kk + 1]);
                 }
             }
         }
