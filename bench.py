@@ -38,6 +38,9 @@ if ROOT not in sys.path:
 # covers 32 Boolean updates.  HBM peak 8 TB/s.
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 PEAK_ANTIDIST = VALU_LANE_OPS
+# uint8 data are held as binary16 values: two inner steps of a packed pair are
+# two v_pk_add_f16 and one v_pk_maximum3_f16 (0.75 lane operations per update)
+PEAK_ANTIDIST_U8 = VALU_LANE_OPS / 0.75
 # uint32 entries are not packed: a saturating subtract per update, and one
 # v_max3_u32 per two updates (1.5 lane operations per update)
 PEAK_ANTIDIST32 = VALU_LANE_OPS / 1.5
@@ -548,7 +551,8 @@ def main():
     elif args.workload == "u8fw8192":
         out = run_fw(args, torch, sr, sr.SR_ANTIDIST_U8, 8192,
                      lambda: synthgen.cfg_antidist_u8(D=8192), "u8fw8192", 255,
-                     "semiring updates/s (D³/t) anti-distance FW D=8192 uint8")
+                     "semiring updates/s (D³/t) anti-distance FW D=8192 uint8",
+                     peak=PEAK_ANTIDIST_U8)
         out["config"] = {"workload": "antidist_u8_floyd_warshall_D8192", "D": 8192,
                          "entries": "uint8, S=255", "edge_p": 0.05, "distances": "U[1,200]",
                          "pivot_block": 128, "parallelism": "single_gpu"}

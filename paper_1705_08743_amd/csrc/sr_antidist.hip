@@ -1,5 +1,6 @@
 // Anti-distance semiring product and blocked Floyd-Warshall closure on
-// gfx950 (uint16 storage; uint8 data are widened by the caller).
+// gfx950 (16-bit storage; uint8 data are widened by the caller into the
+// binary16 working form of sr_tiles.h).
 //
 // Product (Sec. II multiplication algorithm with the Sec. III operations):
 //   C (+)= sum over k of (column k of A) times (row k of B).
@@ -92,8 +93,9 @@ k_ad_fw_update(uint16_t *T, int64_t ld, int D, int k0, int bs, Rect q, int prio)
     fw_update_wg<TM, NW, S8, FULL>(T, ld, D, k0, bs, q, (int)blockIdx.x, (int)blockIdx.y);
 }
 
-// uint8 <-> uint16, 8 entries per thread; rows padded with zeros up to the
-// next multiple of 8 in the destination of a widening.
+// uint8 <-> the 16-bit working form of uint8 data (binary16 values, see
+// sr_tiles.h), 8 entries per thread; rows padded with zeros up to the next
+// multiple of 8 in the destination of a widening.
 __global__ void __launch_bounds__(256)
 k_widen(uint16_t *dst, int64_t ldd, const uint8_t *src, int64_t lds, int64_t R, int64_t C) {
     const int64_t gpr = (C + 7) >> 3;
@@ -106,12 +108,12 @@ k_widen(uint16_t *dst, int64_t ldd, const uint8_t *src, int64_t lds, int64_t R, 
         const uint2 w = *reinterpret_cast<const uint2 *>(s);
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-            v[i] = (uint16_t)((w.x >> (8 * i)) & 0xFFu);
-            v[4 + i] = (uint16_t)((w.y >> (8 * i)) & 0xFFu);
+            v[i] = dev::u8_to_work((w.x >> (8 * i)) & 0xFFu);
+            v[4 + i] = dev::u8_to_work((w.y >> (8 * i)) & 0xFFu);
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < 8; i++) v[i] = (c0 + i < C) ? (uint16_t)s[i] : (uint16_t)0;
+        for (int i = 0; i < 8; i++) v[i] = (c0 + i < C) ? dev::u8_to_work(s[i]) : (uint16_t)0;
     }
     uint4 o;
     o.x = v[0] | ((uint32_t)v[1] << 16);
@@ -129,17 +131,18 @@ k_narrow(uint8_t *dst, int64_t ldd, const uint16_t *src, int64_t lds, int64_t R,
     const int64_t row = g / gpr, c0 = (g % gpr) * 8;
     const uint4 w = *reinterpret_cast<const uint4 *>(src + row * lds + c0);
     const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+    uint8_t b[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) b[i] = dev::work_to_u8((uint16_t)(ww[i >> 1] >> (16 * (i & 1))));
     uint8_t *d = dst + row * ldd + c0;
     if (c0 + 8 <= C) {
         uint2 o;
-        o.x = (ww[0] & 0xFFu) | ((ww[0] >> 8) & 0xFF00u) | ((ww[1] & 0xFFu) << 16) |
-              ((ww[1] >> 16) << 24);
-        o.y = (ww[2] & 0xFFu) | ((ww[2] >> 8) & 0xFF00u) | ((ww[3] & 0xFFu) << 16) |
-              ((ww[3] >> 16) << 24);
+        o.x = b[0] | ((uint32_t)b[1] << 8) | ((uint32_t)b[2] << 16) | ((uint32_t)b[3] << 24);
+        o.y = b[4] | ((uint32_t)b[5] << 8) | ((uint32_t)b[6] << 16) | ((uint32_t)b[7] << 24);
         *reinterpret_cast<uint2 *>(d) = o;
     } else {
         for (int i = 0; i < 8; i++)
-            if (c0 + i < C) d[i] = (uint8_t)(ww[i >> 1] >> (16 * (i & 1)));
+            if (c0 + i < C) d[i] = b[i];
     }
 }
 

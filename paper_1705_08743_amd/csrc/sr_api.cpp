@@ -100,7 +100,8 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
-// Stream-ordered working memory for uint8 problems (widened to uint16).
+// Stream-ordered working memory for uint8 problems (widened to 16-bit
+// working copies).
 std::once_flag g_pool_once;
 
 void configure_pool() {
@@ -155,7 +156,7 @@ int mul_compute(int kind, void *C, int64_t ldc, const void *A, int64_t lda, cons
         e = sr::launch_ad32_mul(static_cast<uint32_t *>(C), ldc, static_cast<const uint32_t *>(A),
                                 lda, static_cast<const uint32_t *>(B), ldb, R, K, N, acc, st);
     } else {
-        // uint8: widen to uint16 working copies, multiply with S = 255, narrow.
+        // uint8: widen to 16-bit working copies, multiply with S = 255, narrow.
         const int64_t lk = round_up(std::max<int64_t>(K, 1), 64);
         const int64_t ln = round_up(N, 64);
         const size_t bytes = (size_t)(R * lk + K * ln + R * ln) * 2;

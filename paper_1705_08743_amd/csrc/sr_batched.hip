@@ -119,9 +119,9 @@ k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, in
         dev::fw_update_wave<kUTM, kUNW, S8, false>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
 }
 
-// uint8 <-> uint16 for every graph of a batch (workgroup g: graph g); with
-// neg the entries are complemented on the way (255 - a: distance <->
-// anti-distance).
+// uint8 <-> the 16-bit working form of uint8 data (binary16 values) for every
+// graph of a batch (workgroup g: graph g); with neg the entries are
+// complemented on the way (255 - a: distance <-> anti-distance).
 __global__ void __launch_bounds__(256) k_batch_widen(const BatchDesc *desc, int neg) {
     const BatchDesc d = desc[blockIdx.x];
     const int64_t gpr = ((int64_t)d.D + 7) >> 3;
@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(256) k_batch_widen(const BatchDesc *desc, int 
         uint16_t v[8];
 #pragma unroll
         for (int i = 0; i < 8; i++)
-            v[i] = (c0 + i < d.D) ? (uint16_t)(neg ? (uint8_t)~s[i] : s[i]) : (uint16_t)0;
+            v[i] = (c0 + i < d.D) ? dev::u8_to_work(neg ? (uint8_t)~s[i] : s[i]) : (uint16_t)0;
         uint4 o;
         o.x = v[0] | ((uint32_t)v[1] << 16);
         o.y = v[2] | ((uint32_t)v[3] << 16);
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(256) k_batch_narrow(const BatchDesc *desc, int
 #pragma unroll
         for (int i = 0; i < 8; i++)
             if (c0 + i < d.D) {
-                const uint8_t x = (uint8_t)(ww[i >> 1] >> (16 * (i & 1)));
+                const uint8_t x = dev::work_to_u8((uint16_t)(ww[i >> 1] >> (16 * (i & 1))));
                 dst[i] = neg ? (uint8_t)~x : x;
             }
     }

@@ -9,9 +9,10 @@
 
 namespace sr {
 
-// Anti-distance entries live in uint16 storage on the device.  `s8` selects
+// Anti-distance entries live in 16-bit storage on the device.  `s8` selects
 // the saturation distance: false -> S = 65535 (uint16 data), true -> S = 255
-// (uint8 data widened into uint16 working storage).
+// (uint8 data widened into a 16-bit working copy that holds each value as a
+// binary16 float; see sr_tiles.h).
 
 // Blocked Floyd-Warshall tile edge for anti-distance closures (elements).
 constexpr int kAdBlock = 128;
@@ -46,7 +47,8 @@ hipError_t launch_ad_fw_panels(bool s8, uint16_t *T, int64_t ld, int64_t D, int6
 hipError_t launch_ad_fw_update(bool s8, uint16_t *T, int64_t ld, int64_t D, int64_t kb,
                                hipStream_t stream);
 
-// uint8 <-> uint16 copies of an R x C block (strides in elements).
+// uint8 <-> 16-bit working copies (binary16 values) of an R x C block
+// (strides in elements).
 hipError_t launch_widen_u8(uint16_t *dst, int64_t ldd, const uint8_t *src, int64_t lds,
                            int64_t R, int64_t C, hipStream_t stream);
 hipError_t launch_narrow_u8(uint8_t *dst, int64_t ldd, const uint16_t *src, int64_t lds,

@@ -1,12 +1,17 @@
 // Device-side building blocks shared by the anti-distance kernels
 // (sr_antidist.hip) and the batched closure (sr_batched.hip).
 //
-// Storage: anti-distance entries in uint16 words.  Two saturation distances:
-//   S = 65535 for uint16 data, S = 255 for uint8 data widened to uint16.
-// Arithmetic (Sec. III, integer-scaled as in Sec. IV):
-//   a (+) b = max(a, b);  a (x) b = max(a + b - S, 0) = b -sat (S - a),
-// the last form being the paper's rewriting of a + b - S as b - (S - a), done
-// here as one packed saturating subtract per two entries.
+// Storage: anti-distance entries in 16-bit words, in one of two forms.
+//   S = 65535 (uint16 data): the entries themselves;
+//     a (x) b = max(a + b - S, 0) = b -sat (S - a), the paper's rewriting of
+//     a + b - S as b - (S - a), done as one packed saturating subtract per
+//     two entries (S - a is the complement), and (+) = max one packed max.
+//   S = 255 (uint8 data, template flag S8): the entries' values as binary16
+//     floats (0..255 are exact, as is every sum and difference below);
+//     a (x) b (+) acc = max(acc, b + (a - 255)): a result below zero can only
+//     lose to acc >= 0, so no clamp is needed, and the products of two inner
+//     steps enter the accumulator through one v_pk_maximum3_f16 -- three
+//     packed operations per four updates instead of four.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,18 +21,33 @@ namespace sr {
 namespace dev {
 
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ u16x2 as_pair(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
 __device__ __forceinline__ uint32_t as_word(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ h16x2 as_h(u16x2 x) { return __builtin_bit_cast(h16x2, x); }
+__device__ __forceinline__ u16x2 as_u(h16x2 x) { return __builtin_bit_cast(u16x2, x); }
 
-// S - a on a packed pair: ~a for S = 65535; a ^ 0xFF for S = 255 (a <= 255).
+// uint8 value <-> its 16-bit working form (binary16 of the value).
+__device__ __forceinline__ uint16_t u8_to_work(uint32_t v) {
+    return __builtin_bit_cast(uint16_t, (_Float16)(float)v);
+}
+__device__ __forceinline__ uint8_t work_to_u8(uint16_t w) {
+    return (uint8_t)(uint32_t)(float)__builtin_bit_cast(_Float16, w);
+}
+
+// The A-side operand of a packed pair: S - a (u16) or a - 255 (S8, binary16).
 template <bool S8>
 __device__ __forceinline__ uint32_t neg_pair(uint32_t a) {
-    return S8 ? (a ^ 0x00FF00FFu) : ~a;
+    if (S8) return as_word(as_u(as_h(as_pair(a)) - h16x2{(_Float16)255.0f, (_Float16)255.0f}));
+    return ~a;
 }
 template <bool S8>
 __device__ __forceinline__ uint16_t neg_one(uint16_t a) {
-    return S8 ? (uint16_t)(a ^ 0xFFu) : (uint16_t)~a;
+    if (S8)
+        return __builtin_bit_cast(uint16_t,
+                                  (_Float16)(__builtin_bit_cast(_Float16, a) - (_Float16)255.0f));
+    return (uint16_t)~a;
 }
 
 // B rows are read through the constant address space.  The rows of B used by
@@ -39,33 +59,20 @@ __device__ __forceinline__ uint16_t neg_one(uint16_t a) {
 #define kconst __attribute__((address_space(4)))
 
 // acc (+)= a (x) b for two entries b of B that share one entry a of A, given
-// na = (S - a) in both halves: v_pk_sub_u16 (clamp) then v_pk_max_u16.
+// na = neg_pair / neg_one of a in both halves: v_pk_sub_u16 (clamp) then
+// v_pk_max_u16; for S8 v_pk_add_f16 then v_pk_maximum_f16.
+template <bool S8>
 __device__ __forceinline__ u16x2 step(u16x2 acc, u16x2 b, u16x2 na) {
+    if (S8) return as_u(__builtin_elementwise_maximum(as_h(acc), as_h(b) + as_h(na)));
     return __builtin_elementwise_max(acc, __builtin_elementwise_sub_sat(b, na));
 }
 
-// A lane's KU consecutive entries of A as one load, and their S - a pairs.
-template <int KU> struct AWord;
-template <> struct AWord<2> {
-    typedef uint32_t type;
-    template <bool S8> __device__ static void negate(type a, uint32_t *na) { na[0] = neg_pair<S8>(a); }
-};
-template <> struct AWord<4> {
-    typedef uint2 type;
-    template <bool S8> __device__ static void negate(type a, uint32_t *na) {
-        na[0] = neg_pair<S8>(a.x);
-        na[1] = neg_pair<S8>(a.y);
-    }
-};
-template <> struct AWord<8> {
-    typedef uint4 type;
-    template <bool S8> __device__ static void negate(type a, uint32_t *na) {
-        na[0] = neg_pair<S8>(a.x);
-        na[1] = neg_pair<S8>(a.y);
-        na[2] = neg_pair<S8>(a.z);
-        na[3] = neg_pair<S8>(a.w);
-    }
-};
+// Two inner steps at once (S8): the two sums enter the accumulator through one
+// v_pk_maximum3_f16.
+__device__ __forceinline__ u16x2 step2_s8(u16x2 acc, u16x2 b0, u16x2 na0, u16x2 b1, u16x2 na1) {
+    return as_u(__builtin_elementwise_maximum(
+        __builtin_elementwise_maximum(as_h(acc), as_h(b0) + as_h(na0)), as_h(b1) + as_h(na1)));
+}
 
 // ---------------------------------------------------------------------------
 // One wavefront computes C (+)= A * B for a tile of up to 64*TM rows (TM rows
@@ -206,17 +213,38 @@ __device__ __forceinline__ void wave_tile_body(uint16_t *C, int64_t ldc, const u
 #pragma unroll
             for (int kg = 0; kg < AG; kg += KU) {
                 const uint16_t *b0 = B + (int64_t)(k + kg) * ldb;
+                if (S8) {
+                    // steps kk and kk + 1 (an even pair: one word of na)
 #pragma unroll
-                for (int kk = 0; kk < KU; kk++) {
-                    const kconst uint32_t *brow = (const kconst uint32_t *)(b0 + kk * ldb);
+                    for (int kk = 0; kk < KU; kk += 2) {
+                        const kconst uint32_t *br0 = (const kconst uint32_t *)(b0 + kk * ldb);
+                        const kconst uint32_t *br1 =
+                            (const kconst uint32_t *)(b0 + (kk + 1) * ldb);
 #pragma unroll
-                    for (int t = 0; t < TM; t++) {
-                        const uint32_t n2 = na[t][(kg + kk) >> 1];
-                        const uint16_t n = ((kg + kk) & 1) ? (uint16_t)(n2 >> 16) : (uint16_t)n2;
-                        const u16x2 nv = u16x2{n, n};
+                        for (int t = 0; t < TM; t++) {
+                            const uint32_t n2 = na[t][(kg + kk) >> 1];
+                            const u16x2 nv0 = u16x2{(uint16_t)n2, (uint16_t)n2};
+                            const u16x2 nv1 = u16x2{(uint16_t)(n2 >> 16), (uint16_t)(n2 >> 16)};
 #pragma unroll
-                        for (int w = 0; w < NW; w++)
-                            acc[t][w] = step(acc[t][w], as_pair(brow[w]), nv);
+                            for (int w = 0; w < NW; w++)
+                                acc[t][w] = step2_s8(acc[t][w], as_pair(br0[w]), nv0,
+                                                     as_pair(br1[w]), nv1);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < KU; kk++) {
+                        const kconst uint32_t *brow = (const kconst uint32_t *)(b0 + kk * ldb);
+#pragma unroll
+                        for (int t = 0; t < TM; t++) {
+                            const uint32_t n2 = na[t][(kg + kk) >> 1];
+                            const uint16_t n =
+                                ((kg + kk) & 1) ? (uint16_t)(n2 >> 16) : (uint16_t)n2;
+                            const u16x2 nv = u16x2{n, n};
+#pragma unroll
+                            for (int w = 0; w < NW; w++)
+                                acc[t][w] = step<S8>(acc[t][w], as_pair(brow[w]), nv);
+                        }
                     }
                 }
             }
@@ -229,7 +257,7 @@ __device__ __forceinline__ void wave_tile_body(uint16_t *C, int64_t ldc, const u
             const uint16_t n = neg_one<S8>(arow[t][k]);
             const u16x2 nv = u16x2{n, n};
 #pragma unroll
-            for (int w = 0; w < NW; w++) acc[t][w] = step(acc[t][w], as_pair(brow[w]), nv);
+            for (int w = 0; w < NW; w++) acc[t][w] = step<S8>(acc[t][w], as_pair(brow[w]), nv);
         }
     }
 
@@ -362,7 +390,7 @@ __device__ __forceinline__ void tile_closure(uint16_t *T, int64_t ld, int bs, ui
 #pragma unroll
             for (int i = 0; i < 8; i++) {
 #pragma unroll
-                for (int c = 0; c < 4; c++) acc[i][c] = step(acc[i][c], b[c], as_pair(nn[i]));
+                for (int c = 0; c < 4; c++) acc[i][c] = step<S8>(acc[i][c], b[c], as_pair(nn[i]));
             }
         }
     }
