@@ -35,6 +35,7 @@ using dev::fw_update_wg;
 using dev::kPanelNW;
 using dev::Rect;
 using dev::tile_closure;
+using dev::u16x2;
 using dev::wave_tile;
 using dev::wave_tile_body;
 
@@ -63,6 +64,45 @@ k_ad_mul(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_
         const int ncols = (int)min<int64_t>(CW, N - col0);
         wave_tile<TM, NW, S8>(C + row0 * ldc + col0, ldc, A + row0 * lda, lda, B + col0, ldb,
                               nrows, ncols, ldb - col0, K, accumulate != 0, false);
+    }
+}
+
+// Product with the inner dimension split over the KS waves of a workgroup,
+// for products with too few output tiles to fill the chip: all KS waves take
+// the same 64-row x 2NW-column tile of C (every chunk of the launch has all
+// 2NW columns inside N), wave w the inner steps [w kq, (w + 1) kq) (kq a
+// multiple of 32); their partial results meet in LDS, where the (+) of the
+// KS partials (and of C when accumulating) is taken.  (+) is max, so
+// splitting the inner loop changes nothing in the result.  All partials are
+// >= 0, so the max of their 16-bit patterns is their max also in the
+// binary16 form.
+template <int NW, int KS, bool S8>
+__global__ void __launch_bounds__(64 * KS)
+k_ad_mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
+                int64_t ldb, int64_t R, int K, int kq, int accumulate) {
+    __shared__ uint4 part[KS][64][NW / 4];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+    const int64_t row0 = (int64_t)blockIdx.y * 64;
+    const int64_t col0 = (int64_t)blockIdx.x * 2 * NW;
+    const int nrows = (int)min<int64_t>(64, R - row0);
+    const int k0 = min(K, wave * kq), k1 = min(K, k0 + kq);
+    // this wave's partial product (rows >= nrows are not written)
+    wave_tile_body<1, NW, S8, true>(reinterpret_cast<uint16_t *>(&part[wave][0][0]), 2 * NW,
+                                    A + row0 * lda + k0, lda, B + (int64_t)k0 * ldb + col0, ldb,
+                                    nrows, 2 * NW, k1 - k0, false, false);
+    __syncthreads();
+    // (+) of the partials, one 32-bit word (two entries) per thread and pass
+    for (int wi = threadIdx.x; wi < 64 * NW; wi += 64 * KS) {
+        const int row = wi / NW, word = wi % NW;
+        if (row >= nrows) continue;
+        u16x2 v = dev::as_pair(reinterpret_cast<const uint32_t *>(&part[0][row][0])[word]);
+#pragma unroll
+        for (int q = 1; q < KS; q++)
+            v = __builtin_elementwise_max(
+                v, dev::as_pair(reinterpret_cast<const uint32_t *>(&part[q][row][0])[word]));
+        uint32_t *dst = reinterpret_cast<uint32_t *>(C + (row0 + row) * ldc + col0) + word;
+        if (accumulate) v = __builtin_elementwise_max(v, dev::as_pair(*dst));
+        *dst = dev::as_word(v);
     }
 }
 
@@ -187,9 +227,40 @@ hipError_t mul_shape(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, c
     return hipSuccess;
 }
 
+// Products with at most 2048 output tiles of 64 x 16 (two waves per SIMD or
+// fewer) but a long inner dimension: 16-column tiles with the inner loop split
+// over eight waves (k_ad_mul_ksplit); a partial last column chunk goes to the
+// edge kernel.
+template <bool S8>
+hipError_t mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
+                      const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc,
+                      hipStream_t st) {
+    constexpr int NW = 8, CW = 2 * NW, KS = 8;
+    const int64_t nfull = N / CW;
+    const int kq = (int)((K + KS * 32 - 1) / (KS * 32) * 32);
+    if (nfull > 0) {
+        hipLaunchKernelGGL((k_ad_mul_ksplit<NW, KS, S8>),
+                           dim3((unsigned)nfull, (unsigned)((R + 63) / 64)), dim3(64 * KS), 0, st,
+                           C, ldc, A, lda, B, ldb, R, (int)K, kq, acc ? 1 : 0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (N % CW) {
+        const int64_t c0 = nfull * CW;
+        hipLaunchKernelGGL((k_ad_mul<1, 8, S8, false>), dim3(1u, (unsigned)((R + 255) / 256)),
+                           dim3(256), 0, st, C, ldc, A, lda, B, ldb, R, (int)K, N, c0,
+                           acc ? 1 : 0);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
 template <bool S8>
 hipError_t mul_s(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
                  int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, hipStream_t st) {
+    const int64_t tiles16 = ((R + 63) / 64) * (N / 16);
+    if (tiles16 > 0 && tiles16 <= 2048 && K >= 256)
+        return mul_ksplit<S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
     const Shape s = pick_mul_shape(R, N);
     if (s.tm == 2) return mul_shape<2, 32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
     switch (s.nw) {

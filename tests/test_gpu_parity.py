@@ -97,6 +97,25 @@ def test_ad_mul_unpadded_strides(kind):
     assert np.array_equal(host(C).astype(np.int64), oracle.ad_mul(A, B, S_OF[kind]))
 
 
+@pytest.mark.parametrize("kind", AD_KINDS)
+@pytest.mark.parametrize("R,K,N", [(64, 1024, 64), (130, 700, 70), (1, 5000, 17),
+                                   (200, 300, 1000), (65, 257, 33), (3, 256, 16)])
+def test_ad_mul_split_inner(kind, R, K, N):
+    """Few output tiles and a long inner dimension: the inner loop is split
+    over the four waves of a workgroup (ragged splits, partial last column
+    chunk), with and without accumulation."""
+    gen = synthgen.generator(1100 + R + K + N)
+    A = rand_antidist(R, K, kind, gen, p=0.05)
+    B = rand_antidist(K, N, kind, gen, p=0.05)
+    C = sr.empty(kind, R, N)
+    sr.semiring_mul(kind, C, dev(kind, A), dev(kind, B))
+    assert np.array_equal(host(C).astype(np.int64), oracle.ad_mul(A, B, S_OF[kind]))
+    C0 = rand_antidist(R, N, kind, gen, p=0.5)
+    Cd = dev(kind, C0)
+    sr.semiring_mul(kind, Cd, dev(kind, A), dev(kind, B), flags=sr.SR_ACCUMULATE)
+    assert np.array_equal(host(Cd).astype(np.int64), oracle.ad_mul(A, B, S_OF[kind], C=C0))
+
+
 def test_ad_mul_padding_untouched():
     """Columns between N and ld belong to the caller and are not written."""
     kind = sr.SR_ANTIDIST_U16
