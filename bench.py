@@ -53,17 +53,15 @@ PEAK_I8_MAC = 2.5e15
 # scaled by the same counters on a streaming kernel of known size; valid only
 # for the kernel sources whose hash is recorded with it (None until measured).
 TRAFFIC = {
-    # full update launch of the D = 8192 uint16 closure (serialized phases, 8064
-    # workgroups): FETCH_SIZE 1.692e5 KiB x 2.000 + WRITE_SIZE 1.270e5 KiB x 1.000
-    "fw8192": {"src_hash": "5dc0758f2f7c956b", "bytes_per_launch": 4.766e8},
-    "u8fw8192": {"src_hash": None, "bytes_per_launch": None},
-    # full update launch of the D = 8192 uint32 closure (252 x 32 workgroups):
-    # FETCH_SIZE 2.049e5 KiB x 2.000 + WRITE_SIZE 2.807e5 KiB x 1.000
-    "u32fw8192": {"src_hash": "ba43132baf09b2ca", "bytes_per_launch": 7.069e8},
+    # full update launch (252 x 32 workgroups, every tile outside the pivot
+    # row and column blocks) of the D = 8192 closure:
+    # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, in bytes
+    "fw8192": {"src_hash": "a808ec9ac96abfe0", "bytes_per_launch": 4.765e8},   # 1.692e5 + 1.270e5 KiB
+    "u8fw8192": {"src_hash": "a808ec9ac96abfe0", "bytes_per_launch": 4.846e8},  # 1.731e5 + 1.270e5 KiB
+    "u32fw8192": {"src_hash": "54a9257487384220", "bytes_per_launch": 7.243e8},  # 2.252e5 + 2.570e5 KiB
     # full update launches (four-Russians kernel, 32 x 32 tiles of 512 x 512
-    # bits) of the serialized D = 16384 Boolean closure: FETCH_SIZE 4.392e4 KiB
-    # x 2.000 + WRITE_SIZE 3.178e4 KiB x 1.000
-    "bool16384": {"src_hash": "1ab7eff727a57fcc", "bytes_per_launch": 1.225e8},
+    # bits) of the serialized D = 16384 Boolean closure
+    "bool16384": {"src_hash": "c7239d8046278996", "bytes_per_launch": 1.225e8},  # 4.395e4 + 3.178e4 KiB
 }
 
 
