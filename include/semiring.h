@@ -170,7 +170,11 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
  * library-owned stream of default priority (the next round's pivot and panels
  * overlap the bulk of the current update) and joins back into `stream`
  * before the call's work completes; the fork/join is event-based, so the
- * sequence can be captured into a HIP graph from `stream`.
+ * sequence can be captured into a HIP graph from `stream` (tested for the
+ * uint16, uint32, distance and Boolean kinds, which allocate nothing; the
+ * uint8 kinds allocate stream-ordered working memory and are not tested
+ * under capture).  Before a capture, call closure() once eagerly on the same
+ * stream: the second stream is created on a stream's first use.
  */
 int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream);
 
