@@ -120,18 +120,38 @@ k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, in
 }
 
 // uint8 <-> the 16-bit working form of uint8 data (binary16 values) for every
-// graph of a batch (workgroup g: graph g); with neg the entries are
-// complemented on the way (255 - a: distance <-> anti-distance).
+// graph of a batch: workgroup (g, y) converts rows [32 y, 32 y + 32) of graph
+// g (the grid has ceil(max D / 32) rows of workgroups; those past a graph's
+// last row exit at once); with neg the entries are complemented on the way
+// (255 - a: distance <-> anti-distance).
+constexpr int kConvRows = 32;
+
 __global__ void __launch_bounds__(256) k_batch_widen(const BatchDesc *desc, int neg) {
     const BatchDesc d = desc[blockIdx.x];
+    const int64_t r0 = (int64_t)blockIdx.y * kConvRows;
+    if (r0 >= d.D) return;
+    const int64_t nr = min<int64_t>(kConvRows, (int64_t)d.D - r0);
     const int64_t gpr = ((int64_t)d.D + 7) >> 3;
-    for (int64_t g = threadIdx.x; g < (int64_t)d.D * gpr; g += 256) {
-        const int64_t row = g / gpr, c0 = (g % gpr) * 8;
+    for (int64_t g = threadIdx.x; g < nr * gpr; g += 256) {
+        const int64_t row = r0 + g / gpr, c0 = (g % gpr) * 8;
         const uint8_t *s = d.T8 + row * d.ld8 + c0;
+        uint8_t b[8];
+        if (c0 + 8 <= d.D) {
+            // 8 bytes at once (rows of T8 are 16-byte aligned, c0 a multiple of 8)
+            const uint2 w = *reinterpret_cast<const uint2 *>(s);
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                b[i] = (uint8_t)(w.x >> (8 * i));
+                b[4 + i] = (uint8_t)(w.y >> (8 * i));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; i++) b[i] = (c0 + i < d.D) ? s[i] : (uint8_t)0;
+        }
         uint16_t v[8];
 #pragma unroll
         for (int i = 0; i < 8; i++)
-            v[i] = (c0 + i < d.D) ? dev::u8_to_work(neg ? (uint8_t)~s[i] : s[i]) : (uint16_t)0;
+            v[i] = (c0 + i < d.D) ? dev::u8_to_work(neg ? (uint8_t)~b[i] : b[i]) : (uint16_t)0;
         uint4 o;
         o.x = v[0] | ((uint32_t)v[1] << 16);
         o.y = v[2] | ((uint32_t)v[3] << 16);
@@ -143,26 +163,42 @@ __global__ void __launch_bounds__(256) k_batch_widen(const BatchDesc *desc, int 
 
 __global__ void __launch_bounds__(256) k_batch_narrow(const BatchDesc *desc, int neg) {
     const BatchDesc d = desc[blockIdx.x];
+    const int64_t r0 = (int64_t)blockIdx.y * kConvRows;
+    if (r0 >= d.D) return;
+    const int64_t nr = min<int64_t>(kConvRows, (int64_t)d.D - r0);
     const int64_t gpr = ((int64_t)d.D + 7) >> 3;
-    for (int64_t g = threadIdx.x; g < (int64_t)d.D * gpr; g += 256) {
-        const int64_t row = g / gpr, c0 = (g % gpr) * 8;
+    for (int64_t g = threadIdx.x; g < nr * gpr; g += 256) {
+        const int64_t row = r0 + g / gpr, c0 = (g % gpr) * 8;
         const uint4 w = *reinterpret_cast<const uint4 *>(d.T + row * d.ld + c0);
         const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
         uint8_t *dst = d.T8 + row * d.ld8 + c0;
+        uint8_t b[8];
 #pragma unroll
-        for (int i = 0; i < 8; i++)
-            if (c0 + i < d.D) {
-                const uint8_t x = dev::work_to_u8((uint16_t)(ww[i >> 1] >> (16 * (i & 1))));
-                dst[i] = neg ? (uint8_t)~x : x;
-            }
+        for (int i = 0; i < 8; i++) {
+            const uint8_t x = dev::work_to_u8((uint16_t)(ww[i >> 1] >> (16 * (i & 1))));
+            b[i] = neg ? (uint8_t)~x : x;
+        }
+        if (c0 + 8 <= d.D) {
+            uint2 o;
+            o.x = b[0] | ((uint32_t)b[1] << 8) | ((uint32_t)b[2] << 16) | ((uint32_t)b[3] << 24);
+            o.y = b[4] | ((uint32_t)b[5] << 8) | ((uint32_t)b[6] << 16) | ((uint32_t)b[7] << 24);
+            *reinterpret_cast<uint2 *>(dst) = o;
+        } else {
+            for (int i = 0; i < 8; i++)
+                if (c0 + i < d.D) dst[i] = b[i];
+        }
     }
 }
 
-// uint16 entries complemented in place (65535 - a), every graph.
+// uint16 entries complemented in place (65535 - a), every graph; workgroup
+// (g, y) takes rows [32 y, 32 y + 32) of graph g, as the conversions above.
 __global__ void __launch_bounds__(256) k_batch_not(const BatchDesc *desc) {
     const BatchDesc d = desc[blockIdx.x];
-    for (int64_t g = threadIdx.x; g < (int64_t)d.D * d.D; g += 256) {
-        uint16_t *e = d.T + (g / d.D) * d.ld + (g % d.D);
+    const int64_t r0 = (int64_t)blockIdx.y * kConvRows;
+    if (r0 >= d.D) return;
+    const int64_t nr = min<int64_t>(kConvRows, (int64_t)d.D - r0);
+    for (int64_t g = threadIdx.x; g < nr * d.D; g += 256) {
+        uint16_t *e = d.T + (r0 + g / d.D) * d.ld + (g % d.D);
         *e = (uint16_t)~*e;
     }
 }
@@ -280,10 +316,13 @@ hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const Batch
     const Item *items =
         reinterpret_cast<const Item *>(static_cast<const char *>(dev_buf) + desc_bytes);
     const unsigned ng = (unsigned)count;
+    int32_t max_d = 0;
+    for (int64_t g = 0; g < count; g++) max_d = std::max(max_d, host_desc[g].D);
+    const dim3 conv(ng, (unsigned)std::max<int64_t>(1, ((int64_t)max_d + kConvRows - 1) / kConvRows));
     if (s8)
-        hipLaunchKernelGGL(k_batch_widen, dim3(ng), dim3(256), 0, st, desc, dual ? 1 : 0);
+        hipLaunchKernelGGL(k_batch_widen, conv, dim3(256), 0, st, desc, dual ? 1 : 0);
     else if (dual)
-        hipLaunchKernelGGL(k_batch_not, dim3(ng), dim3(256), 0, st, desc);
+        hipLaunchKernelGGL(k_batch_not, conv, dim3(256), 0, st, desc);
     for (size_t kb = 0; kb < p.pivot.size(); kb++) {
         const Launch &a = p.pivot[kb], &b = p.panels[kb], &c = p.update[kb];
         if (a.n_wg > 0) {
@@ -313,9 +352,9 @@ hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const Batch
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (s8)
-        hipLaunchKernelGGL(k_batch_narrow, dim3(ng), dim3(256), 0, st, desc, dual ? 1 : 0);
+        hipLaunchKernelGGL(k_batch_narrow, conv, dim3(256), 0, st, desc, dual ? 1 : 0);
     else if (dual)
-        hipLaunchKernelGGL(k_batch_not, dim3(ng), dim3(256), 0, st, desc);
+        hipLaunchKernelGGL(k_batch_not, conv, dim3(256), 0, st, desc);
     if (reflexive) {
         // the multiplicative identity's diagonal: S (anti-distance), 0 (distance)
         const uint32_t one = dual ? 0u : (s8 ? 255u : 65535u);
