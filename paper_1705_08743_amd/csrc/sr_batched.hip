@@ -40,7 +40,26 @@ struct Item {
     int32_t first;
 };
 
-__device__ __forceinline__ int find_item(const Item *it, int n, int bid) {
+// The work lists and descriptors are read-only while a launch runs and every
+// lookup is uniform over a wavefront, so they are read through the constant
+// address space (scalar loads, scalar cache) rather than with vector loads.
+__device__ __forceinline__ const kconst Item *citems(const Item *p) {
+    return (const kconst Item *)p;
+}
+__device__ __forceinline__ BatchDesc cdesc(const BatchDesc *desc, int g) {
+    const kconst BatchDesc *p = (const kconst BatchDesc *)desc + g;
+    BatchDesc d;
+    d.T = p->T;
+    d.ld = p->ld;
+    d.T8 = p->T8;
+    d.ld8 = p->ld8;
+    d.D = p->D;
+    d.pad = 0;
+    return d;
+}
+
+__device__ __forceinline__ int find_item(const Item *items, int n, int bid) {
+    const kconst Item *it = citems(items);
     int lo = 0, hi = n - 1;  // largest i with it[i].first <= bid
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -76,7 +95,7 @@ template <bool S8>
 __global__ void __launch_bounds__(256) k_batch_pivot(const BatchDesc *desc, const Item *items, int kb) {
     __shared__ uint32_t lds_row[2 * 64];
     __shared__ uint32_t lds_col[2 * 128];
-    const BatchDesc d = desc[items[blockIdx.x].graph];
+    const BatchDesc d = cdesc(desc, citems(items)[blockIdx.x].graph);
     const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
     tile_closure<S8>(d.T + (int64_t)k0 * d.ld + k0, d.ld, bs, lds_row, lds_col);
 }
@@ -85,11 +104,11 @@ template <bool S8>
 __global__ void __launch_bounds__(256)
 k_batch_panels(const BatchDesc *desc, const Item *items, int n_items, int kb) {
     const int i = find_item(items, n_items, (int)blockIdx.x);
-    const BatchDesc d = desc[items[i].graph];
+    const BatchDesc d = cdesc(desc, citems(items)[i].graph);
     const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
     int n_rowwg = 0, n_colwg = 0;
     dev::panel_wgs(d.D, k0, bs, &n_rowwg, &n_colwg);
-    fw_panels_wg<S8>(d.T, d.ld, d.D, k0, bs, n_rowwg, (int)blockIdx.x - items[i].first);
+    fw_panels_wg<S8>(d.T, d.ld, d.D, k0, bs, n_rowwg, (int)blockIdx.x - citems(items)[i].first);
 }
 
 // Phase 3: one 64 x 32 tile per wave.  The waves of all graphs are numbered
@@ -102,11 +121,11 @@ k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, in
     const int gw = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (gw >= n_waves) return;
     const int i = find_item(items, n_items, gw);
-    const BatchDesc d = desc[items[i].graph];
+    const BatchDesc d = cdesc(desc, citems(items)[i].graph);
     const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
     int nc = 0, nr = 0;
     const Rect q = update_rect(d.D, kb, &nc, &nr);
-    const int local = gw - items[i].first;
+    const int local = gw - citems(items)[i].first;
     // column-chunk major: consecutive waves (most often the four waves of a
     // workgroup) share a column chunk, so its pivot-row segment B, read through
     // the scalar cache, is fetched once for all of them
