@@ -111,7 +111,9 @@ enum {
                               closure: SR_EUNSUPPORTED; any other kind: SR_EINVAL */
     SR_SERIAL_PHASES = 16u, /* closure: enqueue every phase on the caller's stream in order, without
                                overlapping the next round's pivot and panels on a second stream */
-    SR_BOOL_M4R = 32u      /* Boolean semiring_mul: the "four Russians" table path */
+    SR_BOOL_M4R = 32u,     /* Boolean semiring_mul: the "four Russians" table path */
+    SR_CLOSURE_SQUARING = 64u,  /* closure: repeated squaring, A * (I (+) A)^(2^j), 2^j >= D-1 */
+    SR_CLOSURE_WARSHALL = 128u  /* closure: the blocked Warshall / Floyd loop */
 };
 
 /*
@@ -166,7 +168,16 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
  * becomes 1, S, or 0 for distances -- the paper's transclosure /
  * dransclosure), SR_BOOL_BITWISE, SR_SERIAL_PHASES; SR_BOOL_MFMA returns
  * SR_EUNSUPPORTED.  D = 0 is a no-op.
- * By default a closure with more than two pivot blocks forks onto a second,
+ * Two exact methods compute it.  The blocked Warshall / Floyd loop in rounds of
+ * pivot blocks (SR_CLOSURE_WARSHALL) is the default for large matrices and for
+ * Boolean ones.  Repeated squaring, A * (I (+) A)^(2^j) with 2^j >= D - 1
+ * (eq. trcl, SR_CLOSURE_SQUARING), is the default for anti-distance and
+ * distance matrices with 192 <= D <= 1024 (768 for the 32-bit kinds), where
+ * the loop's chain of D sequential pivot steps costs more than the squarings'
+ * extra products; it allocates stream-ordered working memory (two D x D
+ * matrices) and is not taken while `stream` is being captured, nor with
+ * SR_SERIAL_PHASES.
+ * By default a blocked closure with more than two pivot blocks forks onto a second,
  * library-owned stream of default priority (the next round's pivot and panels
  * overlap the bulk of the current update) and joins back into `stream`
  * before the call's work completes; the fork/join is event-based, so the
@@ -174,7 +185,8 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
  * uint16, uint32, distance and Boolean kinds, which allocate nothing; the
  * uint8 kinds allocate stream-ordered working memory and are not tested
  * under capture).  Before a capture, call closure() once eagerly on the same
- * stream: the second stream is created on a stream's first use.
+ * stream with SR_CLOSURE_WARSHALL: the second stream is created on a stream's
+ * first blocked closure.
  */
 int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream);
 

@@ -64,6 +64,8 @@ SR_BOOL_BITWISE = 4
 SR_BOOL_MFMA = 8
 SR_SERIAL_PHASES = 16
 SR_BOOL_M4R = 32
+SR_CLOSURE_SQUARING = 64
+SR_CLOSURE_WARSHALL = 128
 
 ERROR_NAMES = {
     SR_EINVAL: "SR_EINVAL", SR_EALIAS: "SR_EALIAS", SR_EALIGN: "SR_EALIGN",
@@ -403,7 +405,7 @@ def to_host(t):
 __all__ = [
     "SR_BOOL", "SR_ANTIDIST_U8", "SR_ANTIDIST_U16", "SR_DISTANCE_U8", "SR_DISTANCE_U16",
     "SR_ANTIDIST_U32", "SR_DISTANCE_U32", "elem_bytes",
-    "SR_BOOL_M4R", "SR_EW_AND", "SR_EW_OR", "SR_EW_XOR", "SR_EW_NOT", "semiring_ewise", "SR_OK", "SR_EINVAL", "SR_EALIAS",
+    "SR_BOOL_M4R", "SR_CLOSURE_SQUARING", "SR_CLOSURE_WARSHALL", "SR_EW_AND", "SR_EW_OR", "SR_EW_XOR", "SR_EW_NOT", "semiring_ewise", "SR_OK", "SR_EINVAL", "SR_EALIAS",
     "SR_EALIGN", "SR_ENOMEM", "SR_EDEVICE", "SR_EUNSUPPORTED", "SR_ACCUMULATE",
     "SR_REFLEXIVE", "SR_BOOL_BITWISE", "SR_BOOL_MFMA", "SR_SERIAL_PHASES", "SemiringError", "lib", "kind_of",
     "semiring_mul", "semiring_add", "closure", "closure_batched", "version", "shutdown",

@@ -63,10 +63,11 @@ def test_closure_graph_replays(kind, D):
     T = sr.clone(srcs[0])
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
-    # an eager call on the capture stream first: the library's second stream
-    # for it then exists before the capture starts
+    # an eager blocked-loop call on the capture stream first: the library's
+    # second stream for it then exists before the capture starts (under
+    # capture, closure() takes the blocked loop, which allocates nothing)
     with torch.cuda.stream(s):
-        sr.closure(kind, T, D=D)
+        sr.closure(kind, T, D=D, flags=sr.SR_CLOSURE_WARSHALL)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):

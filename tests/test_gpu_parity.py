@@ -616,3 +616,45 @@ def test_closure_batched_dist_and_reflexive(kind):
     for d, m in zip(plain, mats):
         ref = oracle.dist_closure(m, S) if kind in DIST_KINDS else oracle.ad_closure(m, S)
         assert np.array_equal(host(d).astype(np.int64), ref), m.shape
+
+
+# ---------------------------------------------------------------------------
+# the two closure methods: blocked Warshall loop and repeated squaring
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", [sr.SR_ANTIDIST_U16, sr.SR_ANTIDIST_U8, sr.SR_DISTANCE_U16,
+                                  sr.SR_ANTIDIST_U32, sr.SR_DISTANCE_U32, sr.SR_BOOL])
+@pytest.mark.parametrize("D", [1, 2, 3, 130, 257, 700])
+@pytest.mark.parametrize("method", [sr.SR_CLOSURE_SQUARING, sr.SR_CLOSURE_WARSHALL, 0])
+def test_closure_methods(kind, D, method):
+    """closure() forced to repeated squaring (eq. trcl), forced to the blocked
+    loop, and by default (squaring for anti-distance and distance matrices of
+    192..1024 vertices), each against the oracle; sizes with no squaring
+    (D = 1, 2), one, and several, with ragged tiles; reflexive form too."""
+    gen = synthgen.generator(9900 + 10 * kind + D)
+    S = S_OF.get(kind, 1)
+    if kind == sr.SR_BOOL:
+        A = rand_bits(D, D, gen, min(0.5, 2.0 / D))
+        ldw = synthgen.aligned_ld_words(D)
+        T = dev(sr.SR_BOOL, synthgen.pack_bits(A, ldw), cols=D)
+        want = oracle.bool_closure(A)
+    elif kind in (sr.SR_DISTANCE_U16, sr.SR_DISTANCE_U32):
+        A = rand_dist(D, D, kind, gen, p=min(0.5, 2.0 / D), wmax=S // 5)
+        T = sr.to_device(kind, A)
+        want = oracle.dist_closure(A, S)
+    else:
+        A = rand_antidist(D, D, kind, gen, p=min(0.5, 2.0 / D), wmax=S // 5)
+        T = sr.to_device(kind, A)
+        want = oracle.ad_closure(A, S)
+    T2 = sr.clone(T)
+    sr.closure(kind, T, D=D, flags=method)
+    sr.closure(kind, T2, D=D, flags=method | sr.SR_REFLEXIVE)
+    torch.cuda.synchronize()
+    one = 1 if kind == sr.SR_BOOL else (0 if kind in (sr.SR_DISTANCE_U16, sr.SR_DISTANCE_U32)
+                                         else S)
+    if kind == sr.SR_BOOL:
+        got, got2 = synthgen.unpack_bits(host(T), D), synthgen.unpack_bits(host(T2), D)
+        assert synthgen.padding_bits_clear(host(T), D)
+    else:
+        got, got2 = host(T).astype(np.int64), host(T2).astype(np.int64)
+    assert np.array_equal(got, want)
+    assert np.array_equal(got2, oracle.reflexive(want, one))
