@@ -36,8 +36,19 @@ _UNIT = {SR_BOOL: 8, SR_ANTIDIST_U8: 1, SR_ANTIDIST_U16: 2}
 
 
 def footprint_bytes(kind, n):
-    """Device bytes a request holds while admitted (its padded matrix)."""
-    return n * padded_ld(n, kind) * _UNIT[kind]
+    """Device bytes a request holds while admitted: its padded matrix, plus
+    the library's stream-ordered working memory for its closure (the 16-bit
+    copy of a uint8 matrix, and the two working matrices of repeated
+    squaring, which closure() takes for anti-distance matrices of 192 to 1024
+    vertices)."""
+    b = n * padded_ld(n, kind) * _UNIT[kind]
+    if kind != SR_BOOL:
+        lw = -(-n // 64) * 64
+        if kind == SR_ANTIDIST_U8:
+            b += n * lw * 2
+        if 192 <= n <= 1024:
+            b += 2 * n * lw * 2
+    return b
 
 
 class Request:

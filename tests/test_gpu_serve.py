@@ -50,7 +50,7 @@ def want(r):
     return oracle.ad_closure(r.host[:, :r.n], 65535)
 
 
-@pytest.mark.parametrize("budget_mb", [4096, 2])
+@pytest.mark.parametrize("budget_mb", [4096, 4])
 def test_served_results_equal_solo_and_oracle(budget_mb):
     from paper_1705_08743_amd.serve import ClosureServer
     reqs = make_requests(40, 40, 700, seed=4242, spacing=2e-4)
