@@ -168,15 +168,17 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
  * becomes 1, S, or 0 for distances -- the paper's transclosure /
  * dransclosure), SR_BOOL_BITWISE, SR_SERIAL_PHASES; SR_BOOL_MFMA returns
  * SR_EUNSUPPORTED.  D = 0 is a no-op.
- * Two exact methods compute it.  The blocked Warshall / Floyd loop in rounds of
- * pivot blocks (SR_CLOSURE_WARSHALL) is the default for large matrices and for
- * Boolean ones.  Repeated squaring, A * (I (+) A)^(2^j) with 2^j >= D - 1
- * (eq. trcl, SR_CLOSURE_SQUARING), is the default for anti-distance and
- * distance matrices with 192 <= D <= 1024 (768 for the 32-bit kinds), where
- * the loop's chain of D sequential pivot steps costs more than the squarings'
- * extra products; it allocates stream-ordered working memory (two D x D
- * matrices) and is not taken while `stream` is being captured, nor with
- * SR_SERIAL_PHASES.
+ * Exact methods compute it.  The blocked Warshall / Floyd loop in rounds of
+ * 128 (Boolean: 256) pivots (SR_CLOSURE_WARSHALL) is the default for large
+ * matrices and for Boolean ones.  Repeated squaring, A * (I (+) A)^(2^j) with
+ * 2^j >= D - 1 (eq. trcl, SR_CLOSURE_SQUARING), is the default for
+ * anti-distance and distance matrices with 192 <= D <= 1024 (768 for the
+ * 32-bit kinds), where the loop's chain of D sequential pivot steps costs more
+ * than the squarings' extra products; from there up to D = 4096 (8- and
+ * 16-bit kinds) the loop runs in blocks of 512 pivots, each pivot block closed
+ * by squaring and the panels and update done as products.  Both allocate
+ * stream-ordered working memory (two matrices of the squared size) and are
+ * not taken while `stream` is being captured, nor with SR_SERIAL_PHASES.
  * By default a blocked closure with more than two pivot blocks forks onto a second,
  * library-owned stream of default priority (the next round's pivot and panels
  * overlap the bulk of the current update) and joins back into `stream`

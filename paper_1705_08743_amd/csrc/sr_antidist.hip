@@ -46,11 +46,14 @@ using dev::wave_tile_body;
 // read the same B segments through the scalar cache.
 // FULL: every column chunk of the grid has all 2NW columns (the launcher
 // sends a partial last chunk to a separate FULL = false launch), so the hot
-// kernel carries no edge code.  col_base: first column of chunk 0.
+// kernel carries no edge code.  col_base: first column of chunk 0; bmax:
+// entries of each B row readable from B (the edge tiles may read a whole
+// segment past N, never past bmax).
 template <int TM, int NW, bool S8, bool FULL>
 __global__ void __launch_bounds__(256)
 k_ad_mul(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
-         int64_t ldb, int64_t R, int K, int64_t N, int64_t col_base, int accumulate) {
+         int64_t ldb, int64_t R, int K, int64_t N, int64_t col_base, int accumulate,
+         int64_t bmax) {
     constexpr int CW = 2 * NW, RW = 64 * TM;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
     const int64_t row0 = ((int64_t)blockIdx.y * 4 + wave) * RW;
@@ -63,7 +66,7 @@ k_ad_mul(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_
     } else {
         const int ncols = (int)min<int64_t>(CW, N - col0);
         wave_tile<TM, NW, S8>(C + row0 * ldc + col0, ldc, A + row0 * lda, lda, B + col0, ldb,
-                              nrows, ncols, ldb - col0, K, accumulate != 0, false);
+                              nrows, ncols, bmax - col0, K, accumulate != 0, false);
     }
 }
 
@@ -205,13 +208,15 @@ Shape pick_mul_shape(int64_t R, int64_t N) {
 
 template <int TM, int NW, bool S8>
 hipError_t mul_shape(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
-                     int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, hipStream_t st) {
+                     int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, int64_t bmax,
+                     hipStream_t st) {
     constexpr int CW = 2 * NW;
     const unsigned gy = (unsigned)((R + 256 * TM - 1) / (256 * TM));
     const int64_t nfull = N / CW;
     if (nfull > 0) {
         hipLaunchKernelGGL((k_ad_mul<TM, NW, S8, true>), dim3((unsigned)nfull, gy), dim3(256), 0,
-                           st, C, ldc, A, lda, B, ldb, R, (int)K, N, (int64_t)0, acc ? 1 : 0);
+                           st, C, ldc, A, lda, B, ldb, R, (int)K, N, (int64_t)0, acc ? 1 : 0,
+                           bmax);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -221,7 +226,7 @@ hipError_t mul_shape(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, c
         const unsigned gx = (unsigned)((N - c0 + 15) / 16);
         hipLaunchKernelGGL((k_ad_mul<1, 8, S8, false>), dim3(gx, (unsigned)((R + 255) / 256)),
                            dim3(256), 0, st, C, ldc, A, lda, B, ldb, R, (int)K, N, c0,
-                           acc ? 1 : 0);
+                           acc ? 1 : 0, bmax);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -234,7 +239,7 @@ hipError_t mul_shape(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, c
 template <bool S8>
 hipError_t mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
                       const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc,
-                      hipStream_t st) {
+                      int64_t bmax, hipStream_t st) {
     constexpr int NW = 8, CW = 2 * NW, KS = 8;
     const int64_t nfull = N / CW;
     const int kq = (int)((K + KS * 32 - 1) / (KS * 32) * 32);
@@ -249,7 +254,7 @@ hipError_t mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
         const int64_t c0 = nfull * CW;
         hipLaunchKernelGGL((k_ad_mul<1, 8, S8, false>), dim3(1u, (unsigned)((R + 255) / 256)),
                            dim3(256), 0, st, C, ldc, A, lda, B, ldb, R, (int)K, N, c0,
-                           acc ? 1 : 0);
+                           acc ? 1 : 0, bmax);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -257,16 +262,17 @@ hipError_t mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
 
 template <bool S8>
 hipError_t mul_s(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
-                 int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, hipStream_t st) {
+                 int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, int64_t bmax,
+                 hipStream_t st) {
     const int64_t tiles16 = ((R + 63) / 64) * (N / 16);
     if (tiles16 > 0 && tiles16 <= 2048 && K >= 256)
-        return mul_ksplit<S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
+        return mul_ksplit<S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, st);
     const Shape s = pick_mul_shape(R, N);
-    if (s.tm == 2) return mul_shape<2, 32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
+    if (s.tm == 2) return mul_shape<2, 32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, st);
     switch (s.nw) {
-        case 32: return mul_shape<1, 32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
-        case 16: return mul_shape<1, 16, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
-        default: return mul_shape<1, 8, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, st);
+        case 32: return mul_shape<1, 32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, st);
+        case 16: return mul_shape<1, 16, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, st);
+        default: return mul_shape<1, 8, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, st);
     }
 }
 
@@ -516,9 +522,10 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
 
 hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
                          const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
-                         bool accumulate, hipStream_t stream) {
-    return s8 ? mul_s<true>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, stream)
-              : mul_s<false>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, stream);
+                         bool accumulate, hipStream_t stream, int64_t bspan) {
+    const int64_t bmax = bspan >= 0 ? bspan : ldb;
+    return s8 ? mul_s<true>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, stream)
+              : mul_s<false>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, stream);
 }
 
 hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, bool serial,

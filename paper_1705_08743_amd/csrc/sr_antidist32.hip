@@ -179,12 +179,14 @@ __device__ __forceinline__ void tile32(uint32_t *C, int64_t ldc, const uint32_t 
 // Product: grid (column chunks, row groups of 4 waves); the four waves of a
 // workgroup are stacked along the rows and share the column chunk.  FULL:
 // every chunk of the launch has CW columns inside N (a partial last chunk is
-// a separate FULL = false launch).  col_base: first column of chunk 0.
+// a separate FULL = false launch).  col_base: first column of chunk 0; bmax:
+// entries of each B row readable from B.
 // ---------------------------------------------------------------------------
 template <int CW, bool FULL>
 __global__ void __launch_bounds__(256)
 k_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
-           int64_t ldb, int64_t R, int K, int64_t N, int64_t col_base, int accumulate) {
+           int64_t ldb, int64_t R, int K, int64_t N, int64_t col_base, int accumulate,
+           int64_t bmax) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t row0 = ((int64_t)blockIdx.y * 4 + wave) * kRW;
     const int64_t col0 = col_base + (int64_t)blockIdx.x * CW;
@@ -195,7 +197,7 @@ k_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint3
                               nrows, CW, K, accumulate != 0, false);
     else
         tile32<CW>(C + row0 * ldc + col0, ldc, A + row0 * lda, lda, B + col0, ldb, nrows,
-                   (int)min<int64_t>(CW, N - col0), ldb - col0, K, accumulate != 0, false);
+                   (int)min<int64_t>(CW, N - col0), bmax - col0, K, accumulate != 0, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -353,18 +355,19 @@ k_ad32_update(uint32_t *T, int64_t ld, int D, int k0, int bs, Rect q, int prio) 
 // ---------------------------------------------------------------------------
 template <int CW>
 hipError_t mul_cw(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
-                  int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, hipStream_t st) {
+                  int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, int64_t bmax,
+                  hipStream_t st) {
     const unsigned gy = (unsigned)((R + 4 * kRW - 1) / (4 * kRW));
     const int64_t nfull = N / CW;
     if (nfull > 0) {
         hipLaunchKernelGGL((k_ad32_mul<CW, true>), dim3((unsigned)nfull, gy), dim3(256), 0, st, C,
-                           ldc, A, lda, B, ldb, R, (int)K, N, (int64_t)0, acc ? 1 : 0);
+                           ldc, A, lda, B, ldb, R, (int)K, N, (int64_t)0, acc ? 1 : 0, bmax);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (N % CW) {
         hipLaunchKernelGGL((k_ad32_mul<CW, false>), dim3(1u, gy), dim3(256), 0, st, C, ldc, A, lda,
-                           B, ldb, R, (int)K, N, nfull * CW, acc ? 1 : 0);
+                           B, ldb, R, (int)K, N, nfull * CW, acc ? 1 : 0, bmax);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -534,12 +537,13 @@ hipError_t closure32(uint32_t *T, int64_t ld, int64_t D, bool serial, hipStream_
 
 hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda,
                            const uint32_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
-                           bool accumulate, hipStream_t stream) {
+                           bool accumulate, hipStream_t stream, int64_t bspan) {
+    const int64_t bmax = bspan >= 0 ? bspan : ldb;
     // 16-column tiles when 32-column ones would leave the chip short of waves
     const int64_t waves32 = ((R + kRW - 1) / kRW) * ((N + 31) / 32);
     if (waves32 >= 8192)
-        return mul_cw<32>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, stream);
-    return mul_cw<16>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, stream);
+        return mul_cw<32>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, stream);
+    return mul_cw<16>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, stream);
 }
 
 hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, bool serial,

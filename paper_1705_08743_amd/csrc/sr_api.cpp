@@ -59,6 +59,14 @@ int base_kind(int kind) {
 // for 256 <= D <= 1024, slower at D = 128 and from 1536 on; uint32: 10-25 %
 // faster up to 768; Boolean: the blocked loop is faster at every size).
 constexpr int64_t kSquaringMinD = 192;
+// Big-block closure (pivot blocks of kBigBlock closed by squaring) above the
+// squaring range, up to these sizes (measured: uint16 / uint8 3.1x faster
+// than the 128-pivot loop at D = 1280, 2.6x at 2048, 1.24x at 4096, slower at
+// 6144, with 512 the best of 256 / 512 / 768 / 1024; uint32 slower at every
+// size, so off).
+constexpr int64_t kBigBlock = 512;
+constexpr int64_t kBigBlockMaxD16 = 4096;
+constexpr int64_t kBigBlockMaxD32 = 0;
 constexpr int64_t kSquaringMaxD16 = 1024;
 constexpr int64_t kSquaringMaxD32 = 768;
 
@@ -287,6 +295,30 @@ int64_t squaring_max_d(int ak) {
     return ak == SR_ANTIDIST_U32 ? kSquaringMaxD32 : kSquaringMaxD16;
 }
 
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+// Pivot block of the big-block closure (SR_BIG_BLOCK overrides) and the
+// largest D that takes it by default (SR_BIG_BLOCK_MAX_D overrides).
+int64_t big_block_size() {
+    static const int64_t b = [] {
+        const char *v = getenv("SR_BIG_BLOCK");
+        const int64_t x = v ? (int64_t)atoll(v) : kBigBlock;
+        return x >= 128 ? round_up(x, 64) : kBigBlock;
+    }();
+    return b;
+}
+int64_t big_block_max_d(int ak) {
+    static const int64_t env = [] {
+        const char *v = getenv("SR_BIG_BLOCK_MAX_D");
+        return v ? (int64_t)atoll(v) : (int64_t)-1;
+    }();
+    if (env >= 0) return env;
+    return ak == SR_ANTIDIST_U32 ? kBigBlockMaxD32 : kBigBlockMaxD16;
+}
+
 // Closure by repeated squaring (eq. trcl: T = A * (I (+) A)^m for every
 // m >= D - 1, because a best path never needs more than D - 1 edges before
 // its last one): P := I (+) A, then j squarings P := P * P with 2^j >= D - 1,
@@ -333,6 +365,53 @@ hipError_t closure_by_squaring(int es, bool s8, void *T, int64_t ld, int64_t D, 
     if (e == hipSuccess) e = mul(Q, T, ld, P);
     if (e == hipSuccess)
         e = hipMemcpy2DAsync(T, ld * es, Q, lw * es, row_bytes, D, hipMemcpyDeviceToDevice, st);
+    return e;
+}
+
+// Blocked closure with large pivot blocks (Sec. II / Sec. III Warshall loop
+// blocked by B pivots): per round K = [k0, k0 + bs), the pivot block is closed
+// by repeated squaring, then the panels T_Kj (+)= T_KK * T_Kj and
+// T_iK (+)= T_iK * T_KK, then T_ij (+)= T_iK * T_Kj, all as products on
+// blocks of T.  A panel product's output block is also one of its operands;
+// that is exact because T_KK is closed (T_KK * T_KK <= T_KK), so a mix of old
+// and new operand entries gives the same result, as in the blocked kernels.
+// For sizes where the 128-pivot loop's chain of pivot steps dominates but
+// squaring the whole matrix would cost too many products.  es: 2 (uint16,
+// or the binary16 form when s8) or 4 (uint32).  work: squaring_work_bytes of
+// one block.
+hipError_t closure_big_blocks(int es, bool s8, void *T, int64_t ld, int64_t D, int64_t B,
+                              void *work, hipStream_t st) {
+    char *base = static_cast<char *>(T);
+    auto at = [&](int64_t r, int64_t c) { return base + (r * ld + c) * es; };
+    // C (+)= A * B on blocks of T; B's rows end at column D of T
+    auto mul = [&](int64_t cr, int64_t cc, int64_t ar, int64_t ac, int64_t br, int64_t bc,
+                   int64_t R, int64_t K, int64_t N) -> hipError_t {
+        if (R <= 0 || K <= 0 || N <= 0) return hipSuccess;
+        if (es == 4)
+            return sr::launch_ad32_mul(reinterpret_cast<uint32_t *>(at(cr, cc)), ld,
+                                       reinterpret_cast<const uint32_t *>(at(ar, ac)), ld,
+                                       reinterpret_cast<const uint32_t *>(at(br, bc)), ld, R, K,
+                                       N, true, st, ld - bc);
+        return sr::launch_ad_mul(s8, reinterpret_cast<uint16_t *>(at(cr, cc)), ld,
+                                 reinterpret_cast<const uint16_t *>(at(ar, ac)), ld,
+                                 reinterpret_cast<const uint16_t *>(at(br, bc)), ld, R, K, N, true,
+                                 st, ld - bc);
+    };
+    hipError_t e = hipSuccess;
+    for (int64_t k0 = 0; k0 < D && e == hipSuccess; k0 += B) {
+        const int64_t bs = std::min(B, D - k0), k1 = k0 + bs;
+        e = closure_by_squaring(es, s8, at(k0, k0), ld, bs, work, st);
+        // row panel (left, right of the pivot block), column panel (above, below)
+        if (e == hipSuccess) e = mul(k0, 0, k0, k0, k0, 0, bs, bs, k0);
+        if (e == hipSuccess) e = mul(k0, k1, k0, k0, k0, k1, bs, bs, D - k1);
+        if (e == hipSuccess) e = mul(0, k0, 0, k0, k0, k0, k0, bs, bs);
+        if (e == hipSuccess) e = mul(k1, k0, k1, k0, k0, k0, D - k1, bs, bs);
+        // the four blocks outside the pivot rows and columns
+        const int64_t rows[2][2] = {{0, k0}, {k1, D - k1}};
+        for (const auto &r : rows)
+            for (const auto &c : rows)
+                if (e == hipSuccess) e = mul(r[0], c[0], r[0], k0, k0, c[0], r[1], bs, c[1]);
+    }
     return e;
 }
 
@@ -410,11 +489,33 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
     // while the stream is being captured (it allocates working memory)
     bool squaring = (flags & SR_CLOSURE_SQUARING) != 0;
     if (!squaring && !(flags & SR_CLOSURE_WARSHALL) && !serial && D >= kSquaringMinD &&
-        D <= squaring_max_d(ak)) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        squaring = hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
-    }
-    if (e == hipSuccess && squaring && ak != SR_ANTIDIST_U8) {
+        D <= squaring_max_d(ak))
+        squaring = !capturing(st);
+    // mid sizes: blocks of kBigBlock pivots, each closed by squaring
+    const bool big_blocks = !squaring && !(flags & SR_CLOSURE_WARSHALL) && !serial &&
+                            ak != SR_BOOL && D > squaring_max_d(ak) && D <= big_block_max_d(ak) &&
+                            !capturing(st);
+    if (e == hipSuccess && big_blocks) {
+        const int64_t B = big_block_size();
+        if (ak == SR_ANTIDIST_U8) {
+            const int64_t lw = round_up(D, 64);
+            const size_t tw = (size_t)(D * lw) * 2;
+            void *w = nullptr;
+            if ((rc = work_alloc(&w, tw + squaring_work_bytes(2, B), st)) != SR_OK) return rc;
+            uint16_t *Tw = static_cast<uint16_t *>(w);
+            uint8_t *T8 = static_cast<uint8_t *>(T);
+            e = sr::launch_widen_u8(Tw, lw, T8, ldt, D, D, st);
+            if (e == hipSuccess)
+                e = closure_big_blocks(2, true, Tw, lw, D, B, static_cast<char *>(w) + tw, st);
+            if (e == hipSuccess) e = sr::launch_narrow_u8(T8, ldt, Tw, lw, D, D, st);
+            work_free(w, st);
+        } else {
+            void *w = nullptr;
+            if ((rc = work_alloc(&w, squaring_work_bytes(es, B), st)) != SR_OK) return rc;
+            e = closure_big_blocks(es, false, T, ldt, D, B, w, st);
+            work_free(w, st);
+        }
+    } else if (e == hipSuccess && squaring && ak != SR_ANTIDIST_U8) {
         void *w = nullptr;
         if ((rc = work_alloc(&w, std::max<size_t>(squaring_work_bytes(es, D), 256), st)) != SR_OK)
             return rc;

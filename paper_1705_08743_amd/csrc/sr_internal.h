@@ -20,10 +20,12 @@ constexpr int kAdBlock = 128;
 constexpr int kBoolBlock = 256;
 
 // C (+)= A * B (accumulate) or C := A * B.  Row strides in elements; every
-// row stride is a multiple of 8 elements (16 bytes).
+// row stride is a multiple of 8 elements (16 bytes).  bspan: entries of each
+// B row readable from B (default: ldb; smaller when B is a block inside a
+// wider matrix whose rows end before B's row stride does).
 hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
                          const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
-                         bool accumulate, hipStream_t stream);
+                         bool accumulate, hipStream_t stream, int64_t bspan = -1);
 
 // In-place closure of the D x D matrix T (uint16 storage).  serial: no
 // second stream (every phase in order on `stream`).
@@ -35,7 +37,7 @@ hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, bool s
 // every phase in order on `stream`, without the second stream).
 hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda,
                            const uint32_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
-                           bool accumulate, hipStream_t stream);
+                           bool accumulate, hipStream_t stream, int64_t bspan = -1);
 hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, bool serial,
                                hipStream_t stream);
 

@@ -658,3 +658,28 @@ def test_closure_methods(kind, D, method):
         got, got2 = host(T).astype(np.int64), host(T2).astype(np.int64)
     assert np.array_equal(got, want)
     assert np.array_equal(got2, oracle.reflexive(want, one))
+
+
+@pytest.mark.parametrize("kind", [sr.SR_ANTIDIST_U16, sr.SR_ANTIDIST_U8, sr.SR_DISTANCE_U16,
+                                  sr.SR_ANTIDIST_U32])
+@pytest.mark.parametrize("D", [1100, 1537, 2100])
+def test_closure_big_blocks(kind, D):
+    """Mid sizes (above the whole-matrix squaring range): blocks of 512
+    pivots, each closed by squaring, panels and update as products on blocks
+    of the matrix (a ragged last block), against the oracle and against the
+    forced blocked loop."""
+    gen = synthgen.generator(9950 + 10 * kind + D)
+    S = S_OF[kind]
+    if kind == sr.SR_DISTANCE_U16:
+        A = rand_dist(D, D, kind, gen, p=2.0 / D, wmax=S // 6)
+        want = oracle.dist_closure(A, S)
+    else:
+        A = rand_antidist(D, D, kind, gen, p=2.0 / D, wmax=S // 6)
+        want = oracle.ad_closure(A, S)
+    T = sr.to_device(kind, A)
+    T2 = sr.clone(T)
+    sr.closure(kind, T)
+    sr.closure(kind, T2, flags=sr.SR_CLOSURE_WARSHALL)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(T).astype(np.int64), want)
+    assert np.array_equal(host(T2).astype(np.int64), want)
