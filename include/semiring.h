@@ -113,7 +113,8 @@ enum {
                                overlapping the next round's pivot and panels on a second stream */
     SR_BOOL_M4R = 32u,     /* Boolean semiring_mul: the "four Russians" table path */
     SR_CLOSURE_SQUARING = 64u,  /* closure: repeated squaring, A * (I (+) A)^(2^j), 2^j >= D-1 */
-    SR_CLOSURE_WARSHALL = 128u  /* closure: the blocked Warshall / Floyd loop */
+    SR_CLOSURE_WARSHALL = 128u, /* closure: the blocked Warshall / Floyd loop */
+    SR_CLOSURE_BIG_BLOCKS = 256u /* closure: blocks of 512 pivots closed by squaring (not Boolean) */
 };
 
 /*
@@ -209,6 +210,27 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
  */
 int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t *D,
                     int64_t count, unsigned flags, void *stream);
+
+/*
+ * Autotuning (not part of the paper's method: it chooses between exact
+ * methods that give identical results).  sr_autotune_closure times each
+ * closure method that applies to (kind, D) -- the blocked loop (for Boolean:
+ * with the bit-sliced and with the four-Russians update), big pivot blocks,
+ * repeated squaring -- on a zero matrix of that shape (the kernels' runtimes
+ * do not depend on the entries), once to warm up and twice more, keeps the
+ * fastest for the size class of D (the sizes in (2^(c-1), 2^c]) on the current
+ * device, and returns its flags in *chosen (may be NULL).  closure() without a
+ * method flag then uses it for every D of that class.  sr_autotune_mul does
+ * the same for the Boolean product's paths (SR_BOOL_BITWISE, SR_BOOL_M4R,
+ * SR_BOOL_MFMA) per size class of (R, K, N); any other kind returns
+ * SR_EUNSUPPORTED.  Both allocate, synchronize `stream` and return
+ * SR_EUNSUPPORTED while it is being captured; D in [1, 32768], R, K, N in
+ * [1, 65536] (SR_EINVAL otherwise).  sr_autotune_clear forgets every choice.
+ * The table is per process and thread-safe.
+ */
+int sr_autotune_closure(int kind, int64_t D, unsigned *chosen, void *stream);
+int sr_autotune_mul(int kind, int64_t R, int64_t K, int64_t N, unsigned *chosen, void *stream);
+void sr_autotune_clear(void);
 
 /*
  * Phase timing (a tracing aid, not part of the paper's method).  While

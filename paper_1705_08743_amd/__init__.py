@@ -66,6 +66,7 @@ SR_SERIAL_PHASES = 16
 SR_BOOL_M4R = 32
 SR_CLOSURE_SQUARING = 64
 SR_CLOSURE_WARSHALL = 128
+SR_CLOSURE_BIG_BLOCKS = 256
 
 ERROR_NAMES = {
     SR_EINVAL: "SR_EINVAL", SR_EALIAS: "SR_EALIAS", SR_EALIGN: "SR_EALIGN",
@@ -75,6 +76,7 @@ ERROR_NAMES = {
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsemiring.so")
 
 EXPORTS = ("semiring_mul", "semiring_add", "semiring_ewise", "closure", "closure_batched",
+           "sr_autotune_closure", "sr_autotune_mul", "sr_autotune_clear",
            "sr_profile_enable", "sr_profile_read", "sr_last_error", "sr_version", "sr_shutdown")
 
 SR_PHASE_PIVOT = 0
@@ -113,6 +115,11 @@ def lib():
         L.closure_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                       ctypes.POINTER(i64), i64, u32, vp]
         L.closure_batched.restype = i32
+        L.sr_autotune_closure.argtypes = [i32, i64, ctypes.POINTER(u32), vp]
+        L.sr_autotune_closure.restype = i32
+        L.sr_autotune_mul.argtypes = [i32, i64, i64, i64, ctypes.POINTER(u32), vp]
+        L.sr_autotune_mul.restype = i32
+        L.sr_autotune_clear.restype = None
         L.sr_last_error.restype = ctypes.c_char_p
         L.sr_version.restype = ctypes.c_char_p
         L.sr_shutdown.restype = None
@@ -312,6 +319,27 @@ class BatchArena:
         self.buf.copy_(other.buf)
 
 
+def autotune_closure(kind, D, stream=None):
+    """Time the closure methods for (kind, D) and keep the fastest for D's
+    size class; returns its flags (SR_CLOSURE_* [| SR_BOOL_*])."""
+    out = ctypes.c_uint(0)
+    _check(lib().sr_autotune_closure(kind, D, ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def autotune_mul(kind, R, K, N, stream=None):
+    """Time the Boolean product paths for (R, K, N) and keep the fastest for
+    its size class; returns its flag (SR_BOOL_BITWISE / _M4R / _MFMA)."""
+    out = ctypes.c_uint(0)
+    _check(lib().sr_autotune_mul(kind, R, K, N, ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def autotune_clear():
+    """Forget every autotuned choice."""
+    lib().sr_autotune_clear()
+
+
 def version():
     return lib().sr_version().decode()
 
@@ -405,7 +433,8 @@ def to_host(t):
 __all__ = [
     "SR_BOOL", "SR_ANTIDIST_U8", "SR_ANTIDIST_U16", "SR_DISTANCE_U8", "SR_DISTANCE_U16",
     "SR_ANTIDIST_U32", "SR_DISTANCE_U32", "elem_bytes",
-    "SR_BOOL_M4R", "SR_CLOSURE_SQUARING", "SR_CLOSURE_WARSHALL", "SR_EW_AND", "SR_EW_OR", "SR_EW_XOR", "SR_EW_NOT", "semiring_ewise", "SR_OK", "SR_EINVAL", "SR_EALIAS",
+    "SR_BOOL_M4R", "SR_CLOSURE_SQUARING", "SR_CLOSURE_WARSHALL", "SR_CLOSURE_BIG_BLOCKS",
+    "autotune_closure", "autotune_mul", "autotune_clear", "SR_EW_AND", "SR_EW_OR", "SR_EW_XOR", "SR_EW_NOT", "semiring_ewise", "SR_OK", "SR_EINVAL", "SR_EALIAS",
     "SR_EALIGN", "SR_ENOMEM", "SR_EDEVICE", "SR_EUNSUPPORTED", "SR_ACCUMULATE",
     "SR_REFLEXIVE", "SR_BOOL_BITWISE", "SR_BOOL_MFMA", "SR_SERIAL_PHASES", "SemiringError", "lib", "kind_of",
     "semiring_mul", "semiring_add", "closure", "closure_batched", "version", "shutdown",

@@ -253,7 +253,11 @@ int semiring_mul(int kind, void *C, int64_t ldc, const void *A, int64_t lda, con
                     "semiring_mul: C overlaps A or B (the in-place form is closure())");
     const bool acc = (flags & SR_ACCUMULATE) != 0;
     hipStream_t st = as_stream(stream);
-    if (!is_dist(kind)) return mul_compute(kind, C, ldc, A, lda, B, ldb, R, K, N, acc, paths, st);
+    // Boolean without a forced path: the autotuned choice for this size
+    // class, if any (else the kernels' own size rule)
+    unsigned path = paths;
+    if (kind == SR_BOOL && !path) path = sr::tuned_get(sr::kTuneMul, kind, R, K, N);
+    if (!is_dist(kind)) return mul_compute(kind, C, ldc, A, lda, B, ldb, R, K, N, acc, path, st);
     // distance product (min, saturating +) by De Morgan:
     // A + B = not((not A) (x) (not B)), with C complemented around it
     const int64_t es = unit_bytes(kind);
@@ -462,14 +466,19 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
 
 int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream) {
     if (!valid_kind(kind)) return fail(SR_EINVAL, "closure: invalid kind %d", kind);
+    const unsigned methods = flags & (SR_CLOSURE_SQUARING | SR_CLOSURE_WARSHALL |
+                                      SR_CLOSURE_BIG_BLOCKS);
     if (flags & ~(unsigned)(SR_REFLEXIVE | SR_BOOL_BITWISE | SR_BOOL_MFMA | SR_BOOL_M4R |
-                            SR_SERIAL_PHASES | SR_CLOSURE_SQUARING | SR_CLOSURE_WARSHALL))
+                            SR_SERIAL_PHASES | SR_CLOSURE_SQUARING | SR_CLOSURE_WARSHALL |
+                            SR_CLOSURE_BIG_BLOCKS))
         return fail(SR_EINVAL, "closure: unknown flags 0x%x", flags);
     if ((flags & SR_BOOL_BITWISE) && (flags & SR_BOOL_M4R))
         return fail(SR_EINVAL, "closure: SR_BOOL_BITWISE and SR_BOOL_M4R exclude each other");
-    if ((flags & SR_CLOSURE_SQUARING) && (flags & SR_CLOSURE_WARSHALL))
-        return fail(SR_EINVAL,
-                    "closure: SR_CLOSURE_SQUARING and SR_CLOSURE_WARSHALL exclude each other");
+    if (methods & (methods - 1))
+        return fail(SR_EINVAL, "closure: at most one of SR_CLOSURE_SQUARING, "
+                               "SR_CLOSURE_WARSHALL, SR_CLOSURE_BIG_BLOCKS");
+    if ((flags & SR_CLOSURE_BIG_BLOCKS) && base_kind(kind) == SR_BOOL)
+        return fail(SR_EUNSUPPORTED, "closure: SR_CLOSURE_BIG_BLOCKS is for non-Boolean kinds");
     const bool serial = (flags & SR_SERIAL_PHASES) != 0;
     if (flags & SR_BOOL_MFMA)
         return fail(SR_EUNSUPPORTED, "closure: the int8 matrix-core path is for products only");
@@ -481,62 +490,65 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
     hipStream_t st = as_stream(stream);
     hipError_t e = hipSuccess;
     const int es = (int)unit_bytes(kind);
+    const int ak = base_kind(kind);
+    // The method: forced by a flag; else the autotuned choice for this size
+    // class, if any; else the built-in size rules -- repeated squaring for
+    // small anti-distance matrices (where the blocked loop's chain of D
+    // sequential pivot steps dominates), big pivot blocks closed by squaring
+    // for mid sizes, the blocked loop otherwise.  Squaring and big blocks
+    // allocate working memory, so a stream being captured takes the loop.
+    unsigned method = methods;
+    unsigned bool_path = flags & (SR_BOOL_BITWISE | SR_BOOL_M4R);
+    if (!method && serial) method = SR_CLOSURE_WARSHALL;
+    if (!method) {
+        const unsigned t = sr::tuned_get(sr::kTuneClosure, kind, D, 0, 0);
+        if (t) {
+            method = t & (SR_CLOSURE_SQUARING | SR_CLOSURE_WARSHALL | SR_CLOSURE_BIG_BLOCKS);
+            if (!bool_path) bool_path = t & (SR_BOOL_BITWISE | SR_BOOL_M4R);
+        } else if (D >= kSquaringMinD && D <= squaring_max_d(ak)) {
+            method = SR_CLOSURE_SQUARING;
+        } else if (ak != SR_BOOL && D > squaring_max_d(ak) && D <= big_block_max_d(ak)) {
+            method = SR_CLOSURE_BIG_BLOCKS;
+        } else {
+            method = SR_CLOSURE_WARSHALL;
+        }
+        if (method != SR_CLOSURE_WARSHALL && capturing(st)) method = SR_CLOSURE_WARSHALL;
+    }
     // distance closure (dransclose) by De Morgan: not closure(not T)
     if (is_dist(kind)) e = sr::launch_ewise(es, sr::EW_NOT, T, ldt, T, ldt, T, ldt, D, D, 0, st);
-    const int ak = base_kind(kind);
-    // repeated squaring for small matrices (where the blocked loop's chain of
-    // D sequential pivot steps dominates), unless forced either way; never
-    // while the stream is being captured (it allocates working memory)
-    bool squaring = (flags & SR_CLOSURE_SQUARING) != 0;
-    if (!squaring && !(flags & SR_CLOSURE_WARSHALL) && !serial && D >= kSquaringMinD &&
-        D <= squaring_max_d(ak))
-        squaring = !capturing(st);
-    // mid sizes: blocks of kBigBlock pivots, each closed by squaring
-    const bool big_blocks = !squaring && !(flags & SR_CLOSURE_WARSHALL) && !serial &&
-                            ak != SR_BOOL && D > squaring_max_d(ak) && D <= big_block_max_d(ak) &&
-                            !capturing(st);
-    if (e == hipSuccess && big_blocks) {
-        const int64_t B = big_block_size();
-        if (ak == SR_ANTIDIST_U8) {
-            const int64_t lw = round_up(D, 64);
-            const size_t tw = (size_t)(D * lw) * 2;
-            void *w = nullptr;
-            if ((rc = work_alloc(&w, tw + squaring_work_bytes(2, B), st)) != SR_OK) return rc;
-            uint16_t *Tw = static_cast<uint16_t *>(w);
-            uint8_t *T8 = static_cast<uint8_t *>(T);
-            e = sr::launch_widen_u8(Tw, lw, T8, ldt, D, D, st);
-            if (e == hipSuccess)
-                e = closure_big_blocks(2, true, Tw, lw, D, B, static_cast<char *>(w) + tw, st);
-            if (e == hipSuccess) e = sr::launch_narrow_u8(T8, ldt, Tw, lw, D, D, st);
-            work_free(w, st);
-        } else {
-            void *w = nullptr;
-            if ((rc = work_alloc(&w, squaring_work_bytes(es, B), st)) != SR_OK) return rc;
-            e = closure_big_blocks(es, false, T, ldt, D, B, w, st);
-            work_free(w, st);
-        }
-    } else if (e == hipSuccess && squaring && ak != SR_ANTIDIST_U8) {
-        void *w = nullptr;
-        if ((rc = work_alloc(&w, std::max<size_t>(squaring_work_bytes(es, D), 256), st)) != SR_OK)
-            return rc;
-        e = closure_by_squaring(es, false, T, ldt, D, w, st);
-        work_free(w, st);
-    } else if (e == hipSuccess && squaring) {
-        // uint8: binary16 working copy, squared with S = 255, narrowed back
+    if (e == hipSuccess && method != SR_CLOSURE_WARSHALL) {
+        // squaring or big blocks, on T itself or on the binary16 working copy
+        // of uint8 data
+        const bool big = method == SR_CLOSURE_BIG_BLOCKS;
+        const int64_t B = big ? std::min<int64_t>(big_block_size(), D) : D;
+        const int wes = ak == SR_ANTIDIST_U8 ? 2 : es;
         const int64_t lw = round_up(D, 64);
-        const size_t tw = (size_t)(D * lw) * 2;
+        const size_t tw = ak == SR_ANTIDIST_U8 ? (size_t)(D * lw) * 2 : 0;
         void *w = nullptr;
-        if ((rc = work_alloc(&w, tw + squaring_work_bytes(2, D), st)) != SR_OK) return rc;
-        uint16_t *Tw = static_cast<uint16_t *>(w);
-        uint8_t *T8 = static_cast<uint8_t *>(T);
-        e = sr::launch_widen_u8(Tw, lw, T8, ldt, D, D, st);
+        if ((rc = work_alloc(&w, tw + std::max<size_t>(squaring_work_bytes(wes, B), 256), st)) !=
+            SR_OK)
+            return rc;
+        void *work = static_cast<char *>(w) + tw;
+        void *M = T;
+        int64_t ldm = ldt;
+        if (ak == SR_ANTIDIST_U8) {
+            M = w;
+            ldm = lw;
+            e = sr::launch_widen_u8(static_cast<uint16_t *>(M), lw, static_cast<uint8_t *>(T), ldt,
+                                    D, D, st);
+        }
+        const bool s8 = ak == SR_ANTIDIST_U8;
         if (e == hipSuccess)
-            e = closure_by_squaring(2, true, Tw, lw, D, static_cast<char *>(w) + tw, st);
-        if (e == hipSuccess) e = sr::launch_narrow_u8(T8, ldt, Tw, lw, D, D, st);
+            e = big ? closure_big_blocks(wes, s8, M, ldm, D, B, work, st)
+                    : closure_by_squaring(wes, s8, M, ldm, D, work, st);
+        if (e == hipSuccess && ak == SR_ANTIDIST_U8)
+            e = sr::launch_narrow_u8(static_cast<uint8_t *>(T), ldt, static_cast<uint16_t *>(M),
+                                     lw, D, D, st);
         work_free(w, st);
     } else if (e == hipSuccess && ak == SR_BOOL) {
-        const int path = (flags & SR_BOOL_M4R) ? sr::kBoolPathM4r
-                         : (flags & SR_BOOL_BITWISE) ? sr::kBoolPathBitwise : sr::kBoolPathAuto;
+        const int path = (bool_path & SR_BOOL_M4R) ? sr::kBoolPathM4r
+                         : (bool_path & SR_BOOL_BITWISE) ? sr::kBoolPathBitwise
+                                                         : sr::kBoolPathAuto;
         e = sr::launch_bool_closure(static_cast<uint64_t *>(T), ldt, D, serial, path, st);
     } else if (e == hipSuccess && ak == SR_ANTIDIST_U16) {
         e = sr::launch_ad_closure(false, static_cast<uint16_t *>(T), ldt, D, serial, st);
@@ -645,5 +657,123 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
     if (e != hipSuccess) return device_fail(e, "closure_batched launch");
     return ok();
 }
+
+}  // extern "C"
+
+namespace {
+
+// Times `run` (which enqueues one call on st and returns an SR_* code) once
+// to warm up and `reps` more times with hipEvents on st; returns the fastest
+// in milliseconds, or a negative value when a run fails (an allocation, say).
+template <class Run, class Reset>
+float time_candidate(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int reps, Reset reset, Run run) {
+    float best = -1.0f;
+    for (int i = 0; i <= reps; i++) {
+        if (reset() != hipSuccess) return -1.0f;
+        if (hipEventRecord(e0, st) != hipSuccess) return -1.0f;
+        if (run() != SR_OK) return -1.0f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return -1.0f;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0f;
+        if (i > 0 && (best < 0.0f || ms < best)) best = ms;
+    }
+    return best;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool ok() {
+        return hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+    }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int sr_autotune_closure(int kind, int64_t D, unsigned *chosen, void *stream) {
+    if (!valid_kind(kind)) return fail(SR_EINVAL, "sr_autotune_closure: invalid kind %d", kind);
+    if (D < 1 || D > 32768)
+        return fail(SR_EINVAL, "sr_autotune_closure: D = %lld outside [1, 32768]", (long long)D);
+    hipStream_t st = as_stream(stream);
+    if (capturing(st))
+        return fail(SR_EUNSUPPORTED, "sr_autotune_closure: the stream is being captured");
+    const int ak = base_kind(kind);
+    // a zero matrix of the shape: the runtimes do not depend on the entries
+    const int64_t ld = ak == SR_BOOL ? round_up((D + 63) / 64, 2) : round_up(D, 64);
+    const size_t bytes = (size_t)(D * ld * unit_bytes(kind));
+    std::vector<unsigned> cands;
+    if (ak == SR_BOOL) {
+        cands = {SR_CLOSURE_WARSHALL | SR_BOOL_BITWISE, SR_CLOSURE_WARSHALL | SR_BOOL_M4R};
+    } else {
+        cands = {SR_CLOSURE_WARSHALL};
+        if (D > 512 && D <= 16384) cands.push_back(SR_CLOSURE_BIG_BLOCKS);
+    }
+    if (D >= 2 && D <= 4096) cands.push_back(SR_CLOSURE_SQUARING);
+    EventPair ev;
+    if (!ev.ok()) return device_fail(hipErrorOutOfMemory, "sr_autotune_closure: events");
+    void *T = nullptr;
+    int rc = work_alloc(&T, bytes, st);
+    if (rc != SR_OK) return rc;
+    unsigned pick = 0;
+    float best = 0.0f;
+    for (unsigned c : cands) {
+        const float ms = time_candidate(
+            st, ev.a, ev.b, 2, [&] { return hipMemsetAsync(T, 0, bytes, st); },
+            [&] { return closure(kind, T, ld, D, c, stream); });
+        if (ms >= 0.0f && (!pick || ms < best)) {
+            pick = c;
+            best = ms;
+        }
+    }
+    work_free(T, st);
+    (void)hipStreamSynchronize(st);
+    if (!pick) return fail(SR_EDEVICE, "sr_autotune_closure: no candidate ran");
+    sr::tuned_set(sr::kTuneClosure, kind, D, 0, 0, pick);
+    if (chosen) *chosen = pick;
+    return ok();
+}
+
+int sr_autotune_mul(int kind, int64_t R, int64_t K, int64_t N, unsigned *chosen, void *stream) {
+    if (kind != SR_BOOL)
+        return fail(SR_EUNSUPPORTED, "sr_autotune_mul: only the Boolean product has several paths");
+    if (R < 1 || K < 1 || N < 1 || R > 65536 || K > 65536 || N > 65536)
+        return fail(SR_EINVAL, "sr_autotune_mul: sizes outside [1, 65536]");
+    hipStream_t st = as_stream(stream);
+    if (capturing(st))
+        return fail(SR_EUNSUPPORTED, "sr_autotune_mul: the stream is being captured");
+    const int64_t lk = round_up((K + 63) / 64, 2), ln = round_up((N + 63) / 64, 2);
+    const size_t ba = (size_t)(R * lk * 8), bb = (size_t)(K * ln * 8), bc = (size_t)(R * ln * 8);
+    EventPair ev;
+    if (!ev.ok()) return device_fail(hipErrorOutOfMemory, "sr_autotune_mul: events");
+    void *w = nullptr;
+    int rc = work_alloc(&w, ba + bb + bc, st);
+    if (rc != SR_OK) return rc;
+    char *A = static_cast<char *>(w), *B = A + ba, *C = B + bb;
+    unsigned pick = 0;
+    float best = 0.0f;
+    for (unsigned c : {SR_BOOL_BITWISE, SR_BOOL_M4R, SR_BOOL_MFMA}) {
+        const float ms = time_candidate(
+            st, ev.a, ev.b, 2, [&] { return hipMemsetAsync(w, 0, ba + bb + bc, st); },
+            [&] { return semiring_mul(kind, C, ln, A, lk, B, ln, R, K, N, c, stream); });
+        if (ms >= 0.0f && (!pick || ms < best)) {
+            pick = c;
+            best = ms;
+        }
+    }
+    work_free(w, st);
+    (void)hipStreamSynchronize(st);
+    if (!pick) return fail(SR_EDEVICE, "sr_autotune_mul: no candidate ran");
+    sr::tuned_set(sr::kTuneMul, kind, R, K, N, pick);
+    if (chosen) *chosen = pick;
+    return ok();
+}
+
+void sr_autotune_clear(void) { sr::tuned_clear(); }
 
 }  // extern "C"

@@ -139,6 +139,15 @@ struct Aux {
 Aux *aux_acquire(hipStream_t caller);
 void aux_release(Aux *a);
 
+// Autotuning table (sr_tune.cpp).  op: kTuneClosure (a = D) or kTuneMul
+// (a, b, c = R, K, N); the stored choice is the flag set (SR_CLOSURE_*,
+// SR_BOOL_*) that reproduces the measured-fastest method; 0 = not tuned.
+enum { kTuneClosure = 1, kTuneMul = 2 };
+int size_class(int64_t n);
+unsigned tuned_get(int op, int kind, int64_t a, int64_t b, int64_t c);
+void tuned_set(int op, int kind, int64_t a, int64_t b, int64_t c, unsigned choice);
+void tuned_clear();
+
 // Phase timing (sr_runtime.cpp).  kind: 0 Boolean, 1 anti-distance;
 // phase: 0 pivot, 1 panels, 2 update.  units: semiring updates of the launch.
 bool prof_on();

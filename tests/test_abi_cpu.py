@@ -94,7 +94,7 @@ def test_closure_rejects_bad_arguments(L):
     assert L.closure(U16, P, 4, 8, 0, None) == sr.SR_EINVAL
     assert L.closure(U16, P + 8, 8, 8, 0, None) == sr.SR_EALIGN
     assert L.closure(sr.SR_BOOL, P, 2, 8, sr.SR_BOOL_MFMA, None) == sr.SR_EUNSUPPORTED
-    assert L.closure(U16, P, 8, 8, 0x100, None) == sr.SR_EINVAL
+    assert L.closure(U16, P, 8, 8, 0x400, None) == sr.SR_EINVAL
     assert L.closure(U16, P, 8, 8, sr.SR_CLOSURE_SQUARING | sr.SR_CLOSURE_WARSHALL,
                      None) == sr.SR_EINVAL
     assert L.closure(sr.SR_BOOL, P, 1, 8, 0, None) == sr.SR_EALIGN
@@ -114,7 +114,7 @@ def test_ewise_and_distance_kinds_reject_bad_arguments(L):
     for kind in (sr.SR_DISTANCE_U8, sr.SR_DISTANCE_U16):
         assert mul(L, kind, P + 1, 16, P + 4096, 16, P + 8192, 16, 4, 4, 4) == sr.SR_EALIGN
         assert L.closure(kind, P, 2, 8, 0, None) == sr.SR_EINVAL  # ld < D
-        assert L.closure(kind, P, 16, 16, 0x100, None) == sr.SR_EINVAL
+        assert L.closure(kind, P, 16, 16, 0x400, None) == sr.SR_EINVAL
     assert mul(L, sr.SR_DISTANCE_U16, P, 8, P + 4096, 8, P + 8192, 8, 4, 4, 4,
                sr.SR_BOOL_MFMA) == sr.SR_EINVAL
 
@@ -190,3 +190,17 @@ def test_u32_kinds_validation(L):
     assert sr.padded_ld(37, sr.SR_ANTIDIST_U32) == 64
     assert sr.padded_ld(37, sr.SR_DISTANCE_U32) == 64
     assert sr.elem_bytes(sr.SR_ANTIDIST_U32) == 4
+
+
+def test_autotune_and_method_flags_validation(L):
+    out = ctypes.c_uint(0)
+    assert L.sr_autotune_closure(9, 100, ctypes.byref(out), None) == sr.SR_EINVAL
+    assert L.sr_autotune_closure(sr.SR_ANTIDIST_U16, 0, ctypes.byref(out), None) == sr.SR_EINVAL
+    assert L.sr_autotune_closure(sr.SR_ANTIDIST_U16, 40000, ctypes.byref(out), None) == sr.SR_EINVAL
+    assert L.sr_autotune_mul(sr.SR_ANTIDIST_U16, 8, 8, 8, ctypes.byref(out), None) == sr.SR_EUNSUPPORTED
+    assert L.sr_autotune_mul(sr.SR_BOOL, 0, 8, 8, ctypes.byref(out), None) == sr.SR_EINVAL
+    L.sr_autotune_clear()
+    U16 = sr.SR_ANTIDIST_U16
+    assert L.closure(U16, P, 8, 8, sr.SR_CLOSURE_SQUARING | sr.SR_CLOSURE_BIG_BLOCKS,
+                     None) == sr.SR_EINVAL
+    assert L.closure(sr.SR_BOOL, P, 2, 8, sr.SR_CLOSURE_BIG_BLOCKS, None) == sr.SR_EUNSUPPORTED
