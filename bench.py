@@ -10,11 +10,12 @@ already resident in HBM.  Metric: semiring updates per second, D^3 / t.
 Other workloads (--workload): bool16384 (Boolean closure, D = 16384, mean
 out-degree 3 plus planted strongly connected blocks), boolmul16384 (Boolean
 product A * A of that matrix, word-parallel and int8 matrix-core paths),
-mul1024 (uint16 product of two 1024 x 1024 graphs), u8fw8192 (uint8 closure,
+mul1024 (uint16 product of two 1024 x 1024 graphs), small (latencies of the
+configuration 1 and 2 calls), u8fw8192 (uint8 closure,
 distances in [1, 200]), dfw8192 (the headline input as a distance matrix,
 closed with min and saturating +), u32fw8192 (the headline distances in
-uint32 entries, S = 2^32 - 1), batched (4096 graphs, log-uniform sizes in [32, 1024],
-uint16, one call vs one at a time), add8192 (entrywise max, HBM-bound), serve
+uint32 entries, S = 2^32 - 1), batched (4096 graphs, log-uniform sizes in
+[32, 1024], uint16 one call vs one at a time, then the same batch as uint8), add8192 (entrywise max, HBM-bound), serve
 (continuously batched closure requests vs serial).
 
 Prints one JSON line.  The roofline object is for the dominant kernel (the
@@ -58,7 +59,7 @@ TRAFFIC = {
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, in bytes
     "fw8192": {"src_hash": "a808ec9ac96abfe0", "bytes_per_launch": 4.765e8},   # 1.692e5 + 1.270e5 KiB
     "u8fw8192": {"src_hash": "a808ec9ac96abfe0", "bytes_per_launch": 4.846e8},  # 1.731e5 + 1.270e5 KiB
-    "u32fw8192": {"src_hash": "54a9257487384220", "bytes_per_launch": 7.243e8},  # 2.252e5 + 2.570e5 KiB
+    "u32fw8192": {"src_hash": "52fb5786d930fdd0", "bytes_per_launch": 7.243e8},  # 2.252e5 + 2.570e5 KiB
     # full update launches (four-Russians kernel, 32 x 32 tiles of 512 x 512
     # bits) of the serialized D = 16384 Boolean closure
     "bool16384": {"src_hash": "c7239d8046278996", "bytes_per_launch": 1.225e8},  # 4.395e4 + 3.178e4 KiB
@@ -70,7 +71,8 @@ def src_hash(workload):
     anti-distance the tile code (sr_tiles.h) and the text of the
     k_ad_fw_update kernel template (host-side changes elsewhere in
     sr_antidist.hip do not change the kernel); for Boolean sr_bool.hip; for
-    the uint32 path sr_antidist32.hip."""
+    the uint32 path the update kernel's text and the device code before the
+    product kernel in sr_antidist32.hip."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1705_08743_amd/csrc")
     if workload.startswith("bool"):
@@ -78,8 +80,16 @@ def src_hash(workload):
             h.update(f.read())
         return h.hexdigest()[:16]
     if workload.startswith("u32"):
-        with open(os.path.join(csrc, "sr_antidist32.hip"), "rb") as f:
-            h.update(f.read())
+        # the update kernel and the device code it runs (the step functions,
+        # the wave tiles), not the product kernel or the host side
+        with open(os.path.join(csrc, "sr_antidist32.hip")) as f:
+            text = f.read()
+        a = text.index("__device__ __forceinline__ uint32_t step32(")
+        b = text.index("// Product: grid (column chunks")
+        c = text.index("k_ad32_update(uint32_t *T")
+        d = text.index("\n}\n", c)
+        h.update(text[a:b].encode())
+        h.update(text[c:d].encode())
         return h.hexdigest()[:16]
     with open(os.path.join(csrc, "sr_tiles.h"), "rb") as f:
         h.update(f.read())
@@ -188,14 +198,22 @@ def run_fw(args, torch, sr, kind, D, make_input, workload, S, metric, dual=False
         sr.closure(kind, warm)
     for b in bufs:
         b.copy_(src)
-    # timed region: the closures as a user runs them (phases overlapped)
+    # timed region: the closures as a user runs them (phases overlapped); an
+    # event pair on the caller's stream brackets each closure (the closure
+    # joins its second stream back into that stream) for the per-step median
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
     sync_all(torch)
     t0 = time.perf_counter()
     for i in range(args.steps):
+        evs[i][0].record()
         sr.closure(kind, bufs[i])
+        evs[i][1].record()
     sync_all(torch)
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
+    per_step = sorted(a.elapsed_time(b) for a, b in evs)
+    ms_median = per_step[len(per_step) // 2]
     # kernel-timing pass: the same closures again with the phases serialized
     # on one stream, each launch bracketed by hipEvents on that stream, so
     # that a launch's duration is its own
@@ -209,7 +227,7 @@ def run_fw(args, torch, sr, kind, D, make_input, workload, S, metric, dual=False
         "value": float(D) ** 3 / (ms_step * 1e-3),
         "unit": "updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": ms_step, "ms_median_step": ms_median,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {sr.SR_ANTIDIST_U16: "u16", sr.SR_ANTIDIST_U8: "u8",
                   sr.SR_DISTANCE_U16: "u16", sr.SR_ANTIDIST_U32: "u32"}[kind],
@@ -309,6 +327,72 @@ def run_mul(args, torch, sr, synthgen):
     if not args.no_parity:
         out["parity"] = {"full_matrix": True, "bit_exact": bool(np.array_equal(
             sr.to_host(dC).astype(np.int64), oracle.ad_mul(A, B, 65535)))}
+    return out
+
+
+def run_small(args, torch, sr, synthgen):
+    """Configurations 1 and 2 as latencies (microseconds per call, median of
+    per-call hipEvent pairs): the Boolean D = 256 product A * A and closure,
+    the uint16 D = 1024 product A * B and closure."""
+    import numpy as np
+    import oracle
+    W = synthgen.cfg_bool256()
+    dW = sr.to_device(sr.SR_BOOL, W, cols=256)
+    dWc = sr.clone(dW)
+    dP = sr.empty(sr.SR_BOOL, 256, 256)
+    A = synthgen.cfg_antidist(D=1024, which=0)[:, :1024]
+    B = synthgen.cfg_antidist(D=1024, which=1)[:, :1024]
+    dA = sr.to_device(sr.SR_ANTIDIST_U16, A)
+    dB = sr.to_device(sr.SR_ANTIDIST_U16, B)
+    dAc = sr.clone(dA)
+    dC = sr.empty(sr.SR_ANTIDIST_U16, 1024, 1024)
+    cases = {
+        "bool256_product": (lambda: sr.semiring_mul(sr.SR_BOOL, dP, dW, dW, K=256, N=256), None,
+                            256 ** 3),
+        "bool256_closure": (lambda: sr.closure(sr.SR_BOOL, dWc, D=256), lambda: dWc.copy_(dW),
+                            256 ** 3),
+        "u16_1024_product": (lambda: sr.semiring_mul(sr.SR_ANTIDIST_U16, dC, dA, dB), None,
+                             1024 ** 3),
+        "u16_1024_closure": (lambda: sr.closure(sr.SR_ANTIDIST_U16, dAc), lambda: dAc.copy_(dA),
+                             1024 ** 3),
+    }
+    res = {}
+    steps = max(args.steps, 50)
+    for name, (fn, reset, upd) in cases.items():
+        for _ in range(max(2, args.warmup)):
+            if reset:
+                reset()
+            fn()
+        ts = []
+        for _ in range(steps):
+            if reset:
+                reset()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        ts.sort()
+        med = ts[len(ts) // 2]
+        res[name] = {"us_median": 1e3 * med, "us_min": 1e3 * ts[0], "updates": upd,
+                     "updates_per_s": upd / (med * 1e-3)}
+    torch.cuda.synchronize()
+    out = {"metric": "latency (us per call, median) of the configuration 1 and 2 calls",
+           "value": res["u16_1024_closure"]["us_median"], "unit": "us", "n_gpus": 1,
+           "steps": steps, "warmup": args.warmup,
+           "ms_per_step": res["u16_1024_closure"]["us_median"] * 1e-3,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u16+bits", "data": "synthetic",
+           "config": {"workload": "cfg1_bool256_and_cfg2_u16_1024_latency",
+                      "parallelism": "single_gpu"},
+           "cases": res}
+    if not args.no_parity:
+        ok = np.array_equal(sr.to_host(dWc)[:, :4], oracle.bool_closure_words(W, 256)[:, :4])
+        ok &= np.array_equal(sr.to_host(dP)[:, :4], oracle.bool_mul_words(W, W, 256, 256)[:, :4])
+        ok &= np.array_equal(sr.to_host(dC).astype(np.int64), oracle.ad_mul(A, B, 65535))
+        ok &= np.array_equal(sr.to_host(dAc).astype(np.int64), oracle.ad_closure(A, 65535))
+        out["parity"] = {"all_four_outputs": True, "bit_exact": bool(ok)}
     return out
 
 
@@ -503,6 +587,30 @@ def run_batched(args, torch, sr, synthgen):
         ok = all(np.array_equal(sr.to_host(views[i]).astype(np.int64),
                                 oracle.ad_closure(mats[i], 65535)) for i in idx)
         out["parity"] = {"graphs_checked": len(idx), "bit_exact": bool(ok)}
+    # the same 4096 topologies and distances as uint8 (binary16 working form)
+    mats8 = [synthgen.encode_antidist(n, r, c, w, np.uint8) for n, r, c, w in batch]
+    del work, views
+    src8 = sr.BatchArena(sr.SR_ANTIDIST_U8, sizes)
+    src8.load(mats8)
+    work8 = sr.BatchArena(sr.SR_ANTIDIST_U8, sizes, zero=False)
+    for _ in range(max(1, args.warmup)):
+        work8.copy_(src8)
+        sr.closure_batched(sr.SR_ANTIDIST_U8, work8)
+    times8 = []
+    for _ in range(max(1, args.steps // 2)):
+        work8.copy_(src8)
+        times8.append(timed(torch, lambda i: sr.closure_batched(sr.SR_ANTIDIST_U8, work8), 1))
+    t8 = min(times8)
+    out["uint8"] = {"ms": t8, "value": upd / (t8 * 1e-3),
+                    "fraction_of_valu_roofline_u8": upd / (t8 * 1e-3) / PEAK_ANTIDIST_U8}
+    if not args.no_parity:
+        work8.copy_(src8)
+        sr.closure_batched(sr.SR_ANTIDIST_U8, work8)
+        torch.cuda.synchronize()
+        idx = [0, 1, len(mats8) // 2, len(mats8) - 1]
+        ok8 = all(np.array_equal(sr.to_host(work8.view(i)).astype(np.int64),
+                                 oracle.ad_closure(mats8[i], 255)) for i in idx)
+        out["uint8"]["parity"] = {"graphs_checked": len(idx), "bit_exact": bool(ok8)}
     return out
 
 
@@ -513,7 +621,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fw8192",
                     choices=["fw8192", "u8fw8192", "dfw8192", "u32fw8192", "bool16384",
-                             "boolmul16384", "mul1024", "batched", "add8192", "serve"])
+                             "boolmul16384", "mul1024", "small", "batched", "add8192", "serve"])
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--serve-calibration", type=int, default=24)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
@@ -586,6 +694,8 @@ def main():
         out = run_boolmul(args, torch, sr, synthgen)
     elif args.workload == "mul1024":
         out = run_mul(args, torch, sr, synthgen)
+    elif args.workload == "small":
+        out = run_small(args, torch, sr, synthgen)
     elif args.workload == "add8192":
         out = run_add(args, torch, sr, synthgen)
     elif args.workload == "serve":

@@ -206,7 +206,10 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
  * vertices is closed by the first pivot launch.  The descriptors and the
  * per-round work lists are built on the host and uploaded stream-ordered
  * (the call returns without waiting); uint8 batches use stream-ordered
- * uint16 working copies.
+ * 16-bit working copies (binary16 values).  The rounds are three launches
+ * each, which is what synchronizes the whole grid between phases; their
+ * launch overhead is far below the batch's kernel time, so the batch is not
+ * captured into a graph.
  */
 int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t *D,
                     int64_t count, unsigned flags, void *stream);

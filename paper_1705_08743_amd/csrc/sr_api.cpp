@@ -636,7 +636,7 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
             d.ld = ldt[g];
         }
     }
-    // descriptors and per-round work lists, then the uint16 working copies
+    // descriptors and per-round work lists, then the 16-bit working copies
     std::unique_ptr<sr::BatchPlan, void (*)(sr::BatchPlan *)> plan(
         sr::batch_plan_create(h.data(), count), sr::batch_plan_destroy);
     const size_t plan_bytes = round_up((int64_t)sr::batch_plan_bytes(plan.get(), count), 256);

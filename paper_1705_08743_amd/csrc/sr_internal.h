@@ -1,7 +1,9 @@
 // Internal interface between the C-ABI front end (sr_api.cpp) and the HIP
-// kernel launchers (sr_antidist.hip, sr_bool.hip, sr_elementwise.hip,
-// sr_batched.hip).  Every launcher enqueues on `stream` and returns the
-// hipError_t of the launch; argument validation has already happened.
+// kernel launchers (sr_antidist.hip, sr_antidist32.hip, sr_bool.hip,
+// sr_bool_mfma.hip, sr_elementwise.hip, sr_batched.hip), the runtime pieces
+// (sr_runtime.cpp) and the autotuning table (sr_tune.cpp).  Every launcher
+// enqueues on `stream` and returns the hipError_t of the launch; argument
+// validation has already happened.
 #pragma once
 
 #include <hip/hip_runtime_api.h>
@@ -27,7 +29,7 @@ hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, i
                          const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                          bool accumulate, hipStream_t stream, int64_t bspan = -1);
 
-// In-place closure of the D x D matrix T (uint16 storage).  serial: no
+// In-place closure of the D x D matrix T (16-bit storage).  serial: no
 // second stream (every phase in order on `stream`).
 hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, bool serial,
                              hipStream_t stream);
@@ -104,7 +106,7 @@ hipError_t launch_diag(int elem_bytes, void *T, int64_t ld, int64_t D, uint32_t 
 // per-round work lists into `dev_buf` (batch_plan_bytes() bytes, 256-byte
 // aligned, owned by the caller and alive until the work has run).
 struct BatchDesc {
-    uint16_t *T;    // matrix in uint16 storage (the caller's, or a working copy)
+    uint16_t *T;    // matrix in 16-bit storage (the caller's, or a working copy)
     int64_t ld;     // row stride of T, elements (multiple of 8)
     uint8_t *T8;    // uint8 data: the caller's matrix (widened into T, narrowed back)
     int64_t ld8;    // row stride of T8, elements (multiple of 16)
