@@ -387,6 +387,23 @@ def run_small(args, torch, sr, synthgen):
            "config": {"workload": "cfg1_bool256_and_cfg2_u16_1024_latency",
                       "parallelism": "single_gpu"},
            "cases": res}
+    if not args.no_cpu_baseline:
+        # the oracle on the same four calls, one thread and all threads
+        cpu = {}
+        calls = {"bool256_product": lambda: oracle.bool_mul_words(W, W, 256, 256),
+                 "bool256_closure": lambda: oracle.bool_closure_words(W, 256),
+                 "u16_1024_product": lambda: oracle.ad_mul(A, B, 65535),
+                 "u16_1024_closure": lambda: oracle.ad_closure(A, 65535)}
+        for threads in (1, args.cpu_threads):
+            oracle.set_threads(threads)
+            for name, fn in calls.items():
+                t0 = time.perf_counter()
+                fn()
+                cpu.setdefault(name, {})["ms_%d_threads" % threads] = (time.perf_counter() - t0) * 1e3
+        out["cpu_baseline"] = {"value": 1e6 * cpu["u16_1024_closure"]["ms_%d_threads" % args.cpu_threads]
+                               / 1e3, "unit": "us", "cores": args.cpu_threads, "kind": "oracle",
+                               "sample": "the same four calls, whole (per-call ms in 'calls')",
+                               "calls": cpu}
     if not args.no_parity:
         ok = np.array_equal(sr.to_host(dWc)[:, :4], oracle.bool_closure_words(W, 256)[:, :4])
         ok &= np.array_equal(sr.to_host(dP)[:, :4], oracle.bool_mul_words(W, W, 256, 256)[:, :4])
@@ -587,6 +604,20 @@ def run_batched(args, torch, sr, synthgen):
         ok = all(np.array_equal(sr.to_host(views[i]).astype(np.int64),
                                 oracle.ad_closure(mats[i], 65535)) for i in idx)
         out["parity"] = {"graphs_checked": len(idx), "bit_exact": bool(ok)}
+    if not args.no_cpu_baseline:
+        # the oracle on every 32nd graph of the batch, scaled by the updates
+        oracle.set_threads(args.cpu_threads)
+        sample = list(range(0, len(mats), 32))
+        su = float(sum(float(sizes[i]) ** 3 for i in sample))
+        t0 = time.perf_counter()
+        for i in sample:
+            oracle.ad_closure(mats[i], 65535)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": su / dt, "unit": "updates/s", "cores": args.cpu_threads,
+                               "kind": "oracle",
+                               "sample": "every 32nd graph of the batch (%d graphs, %.3g updates, "
+                                         "%.1f s); whole batch at that rate: %.1f s"
+                                         % (len(sample), su, dt, upd / (su / dt))}
     # the same 4096 topologies and distances as uint8 (binary16 working form)
     mats8 = [synthgen.encode_antidist(n, r, c, w, np.uint8) for n, r, c, w in batch]
     del work, views
