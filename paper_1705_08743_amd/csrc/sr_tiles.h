@@ -241,9 +241,22 @@ __device__ __forceinline__ void wave_tile_body(uint16_t *C, int64_t ldc, const u
                             const uint16_t n =
                                 ((kg + kk) & 1) ? (uint16_t)(n2 >> 16) : (uint16_t)n2;
                             const u16x2 nv = u16x2{n, n};
+                            // the products of four words first, then their
+                            // (+) into the accumulators: no sub -> max pair is
+                            // back to back (which costs a wait state), and
+                            // only four temporaries are live
 #pragma unroll
-                            for (int w = 0; w < NW; w++)
-                                acc[t][w] = step<S8>(acc[t][w], as_pair(brow[w]), nv);
+                            for (int w0 = 0; w0 < NW; w0 += 4) {
+                                u16x2 prod[4];
+#pragma unroll
+                                for (int w = 0; w < 4; w++)
+                                    prod[w] = __builtin_elementwise_sub_sat(as_pair(brow[w0 + w]),
+                                                                            nv);
+#pragma unroll
+                                for (int w = 0; w < 4; w++)
+                                    acc[t][w0 + w] =
+                                        __builtin_elementwise_max(acc[t][w0 + w], prod[w]);
+                            }
                         }
                     }
                 }
