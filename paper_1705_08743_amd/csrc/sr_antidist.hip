@@ -136,6 +136,64 @@ k_ad_fw_update(uint16_t *T, int64_t ld, int D, int k0, int bs, Rect q, int prio)
     fw_update_wg<TM, NW, S8, FULL>(T, ld, D, k0, bs, q, (int)blockIdx.x, (int)blockIdx.y);
 }
 
+// The lookahead part A(kb) of a round (the update of row block kb+1 and of
+// column block kb+1, which the next round's pivot and panels wait for) in one
+// launch of short waves: tiles of 64 rows x 32 columns, workgroups [0, nta)
+// taking the tiles of rectangle qa and the rest those of qb (Rect semantics
+// of fw_update_wave, one tile per workgroup, column-chunk major).  The four
+// waves of a workgroup split the bs inner steps of their tile; their partial
+// results meet in LDS, where the (+) of the four and of the tile is stored.
+// (The same tiles as whole-K waves ran at one wave per SIMD, latency-bound.)
+// The tiles it writes are never its operands (those lie in row and column
+// block kb).  A partial last column chunk runs as one whole-K wave.
+template <bool S8>
+__global__ void __launch_bounds__(256)
+k_ad_fw_lookahead(uint16_t *T, int64_t ld, int D, int k0, int bs, Rect qa, int nta, Rect qb,
+                  int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
+    constexpr int NW = 16;  // packed pairs per row of a tile (32 columns)
+    __shared__ uint4 part[4][64][NW / 4];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int t = (int)blockIdx.x;
+    const bool in_a = t < nta;
+    const Rect q = in_a ? qa : qb;
+    if (!in_a) t -= nta;
+    const int nr = (q.r_hi - q.r_lo) - (q.r_ex1 - q.r_ex0);
+    int rc = q.r_lo + t % nr;
+    if (rc >= q.r_ex0) rc += q.r_ex1 - q.r_ex0;
+    int c = q.c_lo + t / nr;
+    if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
+    if (rc >= q.r_hi || c >= q.c_hi) return;  // (the grid has no such tile)
+    const int64_t row0 = (int64_t)rc * 64, col0 = (int64_t)c * 2 * NW;
+    const int nrows = (int)min<int64_t>(64, (int64_t)D - row0);
+    const int ncols = (int)min<int64_t>(2 * NW, (int64_t)D - col0);
+    uint16_t *C = T + row0 * ld + col0;
+    const uint16_t *A = T + row0 * ld + k0;
+    const uint16_t *B = T + (int64_t)k0 * ld + col0;
+    if (ncols < 2 * NW) {
+        if (wave == 0)
+            wave_tile<1, NW, S8>(C, ld, A, ld, B, ld, nrows, ncols, ld - col0, bs, true, false);
+        return;
+    }
+    const int kq = (bs + 4 * 8 - 1) / (4 * 8) * 8;  // a multiple of 8 entries (16 bytes)
+    const int kk0 = min(bs, wave * kq), kk1 = min(bs, kk0 + kq);
+    wave_tile_body<1, NW, S8, true>(reinterpret_cast<uint16_t *>(&part[wave][0][0]), 2 * NW,
+                                    A + kk0, ld, B + (int64_t)kk0 * ld, ld, nrows, 2 * NW,
+                                    kk1 - kk0, false, false);
+    __syncthreads();
+    for (int wi = threadIdx.x; wi < 64 * NW; wi += 256) {
+        const int row = wi / NW, word = wi % NW;
+        if (row >= nrows) continue;
+        u16x2 v = dev::as_pair(reinterpret_cast<const uint32_t *>(&part[0][row][0])[word]);
+#pragma unroll
+        for (int w = 1; w < 4; w++)
+            v = __builtin_elementwise_max(
+                v, dev::as_pair(reinterpret_cast<const uint32_t *>(&part[w][row][0])[word]));
+        uint32_t *dst = reinterpret_cast<uint32_t *>(C + (int64_t)row * ld) + word;
+        *dst = dev::as_word(__builtin_elementwise_max(v, dev::as_pair(*dst)));
+    }
+}
+
 // uint8 <-> the 16-bit working form of uint8 data (binary16 values, see
 // sr_tiles.h), 8 entries per thread; rows padded with zeros up to the next
 // multiple of 8 in the destination of a widening.
@@ -309,6 +367,7 @@ struct Overrides {
     int tm = 0, nw = 0;
     bool lookahead = true;
     bool prio = true;  // raise the wave priority of the critical-path kernels
+    bool split_lookahead = true;  // A(kb) as one launch of K-split tiles
     Overrides() {
         if (const char *t = getenv("SR_AD_TILE")) {
             int a = 0, b = 0;
@@ -319,6 +378,7 @@ struct Overrides {
         }
         if (const char *l = getenv("SR_LOOKAHEAD")) lookahead = atoi(l) != 0;
         if (const char *v = getenv("SR_PRIO")) prio = atoi(v) != 0;
+        if (const char *v = getenv("SR_SPLIT_LOOKAHEAD")) split_lookahead = atoi(v) != 0;
     }
 };
 
@@ -426,6 +486,30 @@ hipError_t update_rect(const Plan &p, uint16_t *T, int64_t ld, int64_t kb, Rect 
     return e;
 }
 
+// A(kb) as one launch of k_ad_fw_lookahead (plan tiles of 64 x 32).
+template <bool S8>
+hipError_t lookahead_s(const Plan &p, uint16_t *T, int64_t ld, int64_t kb, Rect qa, Rect qb,
+                       double units, hipStream_t st) {
+    auto tiles = [](Rect &q) {
+        if (q.r_ex1 <= q.r_ex0) q.r_ex0 = q.r_ex1 = q.r_hi;
+        if (q.c_ex1 <= q.c_ex0) q.c_ex0 = q.c_ex1 = q.c_hi;
+        const int nr = (q.r_hi - q.r_lo) - (q.r_ex1 - q.r_ex0);
+        const int nc = (q.c_hi - q.c_lo) - (q.c_ex1 - q.c_ex0);
+        return nr > 0 && nc > 0 ? nr * nc : 0;
+    };
+    const int nta = tiles(qa), ntb = tiles(qb);
+    if (nta + ntb == 0) return hipSuccess;
+    if (nta == 0) qa = qb;  // (a rectangle with no tiles is never selected)
+    const int k0 = block_k0(kb), bs = block_bs(p.D, kb);
+    const bool prof = prof_on();
+    if (prof) prof_begin(st);
+    hipLaunchKernelGGL((k_ad_fw_lookahead<S8>), dim3((unsigned)(nta + ntb)), dim3(256), 0, st, T,
+                       ld, (int)p.D, k0, bs, qa, nta, qb, overrides().prio ? 1 : 0);
+    hipError_t e = hipGetLastError();
+    if (prof) prof_end(st, 1, 2, units);
+    return e;
+}
+
 template <bool S8>
 hipError_t pivot_s(uint16_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t st) {
     const int k0 = block_k0(kb), bs = block_bs(D, kb);
@@ -504,12 +588,19 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
         // panels(kb+1) are the critical path: their waves run at a raised
         // priority, so that the SIMDs they share with B(kb) issue their
         // instructions first.
-        if (e == hipSuccess)
-            e = update_rect<S8>(p, T, ld, kb, Rect{rl1, rh1, rh1, rh1, 0, p.ncc, cl, ch}, st,
-                                bs1 * ((double)D - bs) * bs, true);
-        if (e == hipSuccess)
-            e = update_rect<S8>(p, T, ld, kb, Rect{0, p.nrc, rl, rh1, cl1, ch1, ch1, ch1}, st,
-                                rest2 * bs1 * bs, true);
+        const Rect qa{rl1, rh1, rh1, rh1, 0, p.ncc, cl, ch};
+        const Rect qb{0, p.nrc, rl, rh1, cl1, ch1, ch1, ch1};
+        const double ua = bs1 * ((double)D - bs) * bs, ub = rest2 * bs1 * bs;
+        // the K-split form where the chain is the critical path (measured: D =
+        // 2048 2.49 -> 1.50 ms, 4096 5.03 -> 3.50, 6144 8.74 -> 8.26); at 8192
+        // the bulk update hides the chain and the split waves only add
+        // contention (17.14 -> 17.29 ms)
+        if (p.tm == 1 && p.nw == 16 && overrides().split_lookahead && D <= 6144) {
+            if (e == hipSuccess) e = lookahead_s<S8>(p, T, ld, kb, qa, qb, ua + ub, st);
+        } else {
+            if (e == hipSuccess) e = update_rect<S8>(p, T, ld, kb, qa, st, ua, true);
+            if (e == hipSuccess) e = update_rect<S8>(p, T, ld, kb, qb, st, ub, true);
+        }
         if (e == hipSuccess) e = pivot_s<S8>(T, ld, D, kb + 1, st);
         if (e == hipSuccess) e = panels_s<S8>(T, ld, D, kb + 1, st);
         if (e != hipSuccess) break;

@@ -60,12 +60,12 @@ int base_kind(int kind) {
 // faster up to 768; Boolean: the blocked loop is faster at every size).
 constexpr int64_t kSquaringMinD = 192;
 // Big-block closure (pivot blocks of kBigBlock closed by squaring) above the
-// squaring range, up to these sizes (measured: uint16 / uint8 3.1x faster
-// than the 128-pivot loop at D = 1280, 2.6x at 2048, 1.24x at 4096, slower at
-// 6144, with 512 the best of 256 / 512 / 768 / 1024; uint32 slower at every
-// size, so off).
+// squaring range, up to these sizes (measured against the 128-pivot loop with
+// its K-split lookahead: uint16 D = 1536 0.59 vs 1.14 ms, 2048 0.99 vs 1.50,
+// 3072 2.13 vs 2.25, 4096 4.26 vs 3.50; 512 the best block of 256 / 512 /
+// 768 / 1024; uint32 slower at every size, so off).
 constexpr int64_t kBigBlock = 512;
-constexpr int64_t kBigBlockMaxD16 = 4096;
+constexpr int64_t kBigBlockMaxD16 = 3072;
 constexpr int64_t kBigBlockMaxD32 = 0;
 constexpr int64_t kSquaringMaxD16 = 1024;
 constexpr int64_t kSquaringMaxD32 = 768;
