@@ -113,7 +113,7 @@ template <bool S8>
 __global__ void __launch_bounds__(256)
 k_ad_fw_pivot(uint16_t *T, int64_t ld, int64_t k0, int bs, int prio) {
     if (prio) __builtin_amdgcn_s_setprio(2);
-    __shared__ uint32_t lds_row[2 * 64];
+    __shared__ uint32_t lds_row[2 * 128];
     __shared__ uint32_t lds_col[2 * 128];
     tile_closure<S8>(T + k0 * ld + k0, ld, bs, lds_row, lds_col);
 }
@@ -489,7 +489,7 @@ hipError_t update_rect(const Plan &p, uint16_t *T, int64_t ld, int64_t kb, Rect 
 // A(kb) as one launch of k_ad_fw_lookahead (plan tiles of 64 x 32).
 template <bool S8>
 hipError_t lookahead_s(const Plan &p, uint16_t *T, int64_t ld, int64_t kb, Rect qa, Rect qb,
-                       double units, hipStream_t st) {
+                       double units, hipStream_t st, bool record = true) {
     auto tiles = [](Rect &q) {
         if (q.r_ex1 <= q.r_ex0) q.r_ex0 = q.r_ex1 = q.r_hi;
         if (q.c_ex1 <= q.c_ex0) q.c_ex0 = q.c_ex1 = q.c_hi;
@@ -501,13 +501,41 @@ hipError_t lookahead_s(const Plan &p, uint16_t *T, int64_t ld, int64_t kb, Rect 
     if (nta + ntb == 0) return hipSuccess;
     if (nta == 0) qa = qb;  // (a rectangle with no tiles is never selected)
     const int k0 = block_k0(kb), bs = block_bs(p.D, kb);
-    const bool prof = prof_on();
+    const bool prof = record && prof_on();
     if (prof) prof_begin(st);
     hipLaunchKernelGGL((k_ad_fw_lookahead<S8>), dim3((unsigned)(nta + ntb)), dim3(256), 0, st, T,
                        ld, (int)p.D, k0, bs, qa, nta, qb, overrides().prio ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (prof) prof_end(st, 1, 2, units);
     return e;
+}
+
+// Phase 2 as one launch of k_ad_fw_lookahead: the row panel's tiles (rows of
+// block kb, columns outside it) and the column panel's (rows outside block
+// kb, its columns), four waves splitting the inner steps of each tile.  A
+// panel tile is also an operand of its own and of the other panel tiles; that
+// is exact because T_KK is closed (any mix of old and new entries gives the
+// same result), as in the one-wave-per-tile panel kernel.
+template <bool S8>
+hipError_t panels_split_s(const Plan &p, uint16_t *T, int64_t ld, int64_t kb, hipStream_t st) {
+    int rl, rh, cl, ch;
+    block_chunks(p.D, kb, p.rw, &rl, &rh);
+    block_chunks(p.D, kb, p.cw, &cl, &ch);
+    const double bs = block_bs(p.D, kb);
+    const Rect row_panel{rl, rh, rh, rh, 0, p.ncc, cl, ch};
+    const Rect col_panel{0, p.nrc, rl, rh, cl, ch, ch, ch};
+    const bool prof = prof_on();
+    if (prof) prof_begin(st);
+    hipError_t e = lookahead_s<S8>(p, T, ld, kb, row_panel, col_panel, 0.0, st, false);
+    if (prof) prof_end(st, 1, 1, 2.0 * ((double)p.D - bs) * bs * bs);
+    return e;
+}
+
+// Whether phase 2 and the lookahead part run as K-split tiles: where the
+// chain of pivot, panels and lookahead part is the critical path (the bulk
+// update of a round being short), with the plan's 64 x 32 tiles.
+bool split_chain(const Plan &p) {
+    return p.tm == 1 && p.nw == 16 && overrides().split_lookahead && p.D <= 6144;
 }
 
 template <bool S8>
@@ -544,7 +572,10 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
     const int nb = blocks_of(D);
     hipError_t e = pivot_s<S8>(T, ld, D, 0, st);
     if (e != hipSuccess || nb == 1) return e;
-    if ((e = panels_s<S8>(T, ld, D, 0, st)) != hipSuccess) return e;
+    const bool split = split_chain(p);
+    if ((e = split ? panels_split_s<S8>(p, T, ld, 0, st) : panels_s<S8>(T, ld, D, 0, st)) !=
+        hipSuccess)
+        return e;
 
     // With a second stream, B(kb) -- the update outside row and column
     // blocks kb+1 -- runs there, queued behind B(kb-1) as soon as panels(kb)
@@ -565,7 +596,9 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
                 e = update_rect<S8>(p, T, ld, kb, Rect{0, p.nrc, rl, rh, 0, p.ncc, cl, ch}, st,
                                     rest * rest * bs);
             if (e == hipSuccess && kb + 1 < nb) e = pivot_s<S8>(T, ld, D, kb + 1, st);
-            if (e == hipSuccess && kb + 1 < nb) e = panels_s<S8>(T, ld, D, kb + 1, st);
+            if (e == hipSuccess && kb + 1 < nb)
+                e = split ? panels_split_s<S8>(p, T, ld, kb + 1, st)
+                          : panels_s<S8>(T, ld, D, kb + 1, st);
             if (e != hipSuccess) break;
             continue;
         }
@@ -595,14 +628,16 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
         // 2048 2.49 -> 1.50 ms, 4096 5.03 -> 3.50, 6144 8.74 -> 8.26); at 8192
         // the bulk update hides the chain and the split waves only add
         // contention (17.14 -> 17.29 ms)
-        if (p.tm == 1 && p.nw == 16 && overrides().split_lookahead && D <= 6144) {
+        if (split) {
             if (e == hipSuccess) e = lookahead_s<S8>(p, T, ld, kb, qa, qb, ua + ub, st);
         } else {
             if (e == hipSuccess) e = update_rect<S8>(p, T, ld, kb, qa, st, ua, true);
             if (e == hipSuccess) e = update_rect<S8>(p, T, ld, kb, qb, st, ub, true);
         }
         if (e == hipSuccess) e = pivot_s<S8>(T, ld, D, kb + 1, st);
-        if (e == hipSuccess) e = panels_s<S8>(T, ld, D, kb + 1, st);
+        if (e == hipSuccess)
+            e = split ? panels_split_s<S8>(p, T, ld, kb + 1, st)
+                      : panels_s<S8>(T, ld, D, kb + 1, st);
         if (e != hipSuccess) break;
     }
     if (aux) aux_release(aux);

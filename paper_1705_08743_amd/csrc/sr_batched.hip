@@ -93,7 +93,7 @@ __host__ __device__ inline Rect update_rect(int D, int kb, int *ncols_sel, int *
 
 template <bool S8>
 __global__ void __launch_bounds__(256) k_batch_pivot(const BatchDesc *desc, const Item *items, int kb) {
-    __shared__ uint32_t lds_row[2 * 64];
+    __shared__ uint32_t lds_row[2 * 128];
     __shared__ uint32_t lds_col[2 * 128];
     const BatchDesc d = cdesc(desc, citems(items)[blockIdx.x].graph);
     const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);

@@ -336,12 +336,16 @@ __device__ __forceinline__ void wave_tile(uint16_t *C, int64_t ldc, const uint16
 //
 // Step k needs row k and column k of the tile; neither changes during step k
 // (T_kk (x) x <= x because T_kk <= S, the multiplicative one), so all 64
-// updates of a thread are independent.  The owners of row k and column k
-// publish them in LDS (the column already as broadcast S - value pairs), one
-// barrier per step, with two buffers alternating so that publishing step k+1
-// cannot overwrite what a slower thread still reads for step k.  Entries
+// updates of a thread are independent.  Two steps k, k+1 share one barrier:
+// the owners publish rows k and k+1 and the column pair (T_ik, T_i,k+1) as
+// they are before step k, and every thread forms row k+1 and column k+1 as
+// step k leaves them itself --
+//   T'_k+1,j = T_k+1,j (+) T_k+1,k (x) T_kj,   T'_i,k+1 = T_i,k+1 (+) T_ik (x) T_k,k+1
+// -- then applies step k with row k and column k, and step k+1 with the
+// primed row and column.  Two LDS buffer sets alternate, so that publishing
+// the next pair cannot overwrite what a slower thread still reads.  Entries
 // outside bs x bs are held as 0, the additive zero, and stay 0.
-// lds_row: 2 x 64 words, lds_col: 2 x 128 words.
+// lds_row: 2 x 2 x 64 words, lds_col: 2 x 128 words.
 // ---------------------------------------------------------------------------
 template <bool S8>
 __device__ __forceinline__ void tile_closure(uint16_t *T, int64_t ld, int bs, uint32_t *lds_row,
@@ -373,37 +377,51 @@ __device__ __forceinline__ void tile_closure(uint16_t *T, int64_t ld, int bs, ui
     const int nq = (bs + 7) >> 3;
     for (int q = 0; q < nq; q++) {
 #pragma unroll
-        for (int s = 0; s < 8; s++) {
-            uint32_t *rb = lds_row + (s & 1) * 64;
-            uint32_t *cb = lds_col + (s & 1) * 128;
+        for (int s = 0; s < 8; s += 2) {
+            uint32_t *rb = lds_row + ((s >> 1) & 1) * 128;  // row k: rb[0..63], row k+1: rb[64..127]
+            uint32_t *cb = lds_col + ((s >> 1) & 1) * 128;  // (T_ik, T_i,k+1) for row i
             if (ty == q) {
-                uint4 v;
-                v.x = as_word(acc[s][0]);
-                v.y = as_word(acc[s][1]);
-                v.z = as_word(acc[s][2]);
-                v.w = as_word(acc[s][3]);
-                reinterpret_cast<uint4 *>(rb)[tx] = v;
+                reinterpret_cast<uint4 *>(rb)[tx] = uint4{as_word(acc[s][0]), as_word(acc[s][1]),
+                                                          as_word(acc[s][2]), as_word(acc[s][3])};
+                reinterpret_cast<uint4 *>(rb + 64)[tx] =
+                    uint4{as_word(acc[s + 1][0]), as_word(acc[s + 1][1]), as_word(acc[s + 1][2]),
+                          as_word(acc[s + 1][3])};
             }
             if (tx == q) {
-                uint32_t c8[8];
-#pragma unroll
-                for (int i = 0; i < 8; i++) {
-                    const uint16_t v = (s & 1) ? acc[i][s >> 1].y : acc[i][s >> 1].x;
-                    c8[i] = (uint32_t)neg_one<S8>(v) * 0x10001u;
-                }
-                reinterpret_cast<uint4 *>(cb)[2 * ty] = uint4{c8[0], c8[1], c8[2], c8[3]};
-                reinterpret_cast<uint4 *>(cb)[2 * ty + 1] = uint4{c8[4], c8[5], c8[6], c8[7]};
+                // columns k, k+1 are the two halves of packed pair s / 2
+                reinterpret_cast<uint4 *>(cb)[2 * ty] =
+                    uint4{as_word(acc[0][s >> 1]), as_word(acc[1][s >> 1]),
+                          as_word(acc[2][s >> 1]), as_word(acc[3][s >> 1])};
+                reinterpret_cast<uint4 *>(cb)[2 * ty + 1] =
+                    uint4{as_word(acc[4][s >> 1]), as_word(acc[5][s >> 1]),
+                          as_word(acc[6][s >> 1]), as_word(acc[7][s >> 1])};
             }
             __syncthreads();
-            const uint4 b4 = reinterpret_cast<const uint4 *>(rb)[tx];
+            const int k = 8 * q + s;
+            const uint4 r0 = reinterpret_cast<const uint4 *>(rb)[tx];
+            const uint4 r1 = reinterpret_cast<const uint4 *>(rb + 64)[tx];
             const uint4 n0 = reinterpret_cast<const uint4 *>(cb)[2 * ty];
             const uint4 n1 = reinterpret_cast<const uint4 *>(cb)[2 * ty + 1];
-            const u16x2 b[4] = {as_pair(b4.x), as_pair(b4.y), as_pair(b4.z), as_pair(b4.w)};
-            const uint32_t nn[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+            // T_k,k+1 (entry k+1 of row k) and T_k+1,k (entry k of row k+1)
+            const uint16_t a = reinterpret_cast<const uint16_t *>(rb)[k + 1];
+            const uint16_t b = reinterpret_cast<const uint16_t *>(rb + 64)[k];
+            const u16x2 rk[4] = {as_pair(r0.x), as_pair(r0.y), as_pair(r0.z), as_pair(r0.w)};
+            u16x2 rk1[4] = {as_pair(r1.x), as_pair(r1.y), as_pair(r1.z), as_pair(r1.w)};
+            const uint16_t nb = neg_one<S8>(b), na = neg_one<S8>(a);
+#pragma unroll
+            for (int c = 0; c < 4; c++) rk1[c] = step<S8>(rk1[c], rk[c], u16x2{nb, nb});
+            const uint32_t cw[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
 #pragma unroll
             for (int i = 0; i < 8; i++) {
+                const u16x2 cp = as_pair(cw[i]);  // (T_ik, T_i,k+1)
+                // T'_i,k+1 = T_i,k+1 (+) T_ik (x) T_k,k+1, in the high half
+                const u16x2 ck = step<S8>(cp, u16x2{cp.x, cp.x}, u16x2{na, na});
+                const uint16_t m0 = neg_one<S8>(cp.x), m1 = neg_one<S8>(ck.y);
 #pragma unroll
-                for (int c = 0; c < 4; c++) acc[i][c] = step<S8>(acc[i][c], b[c], as_pair(nn[i]));
+                for (int c = 0; c < 4; c++) {
+                    acc[i][c] = step<S8>(acc[i][c], rk[c], u16x2{m0, m0});
+                    acc[i][c] = step<S8>(acc[i][c], rk1[c], u16x2{m1, m1});
+                }
             }
         }
     }

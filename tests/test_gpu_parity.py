@@ -683,3 +683,31 @@ def test_closure_big_blocks(kind, D):
     torch.cuda.synchronize()
     assert np.array_equal(host(T).astype(np.int64), want)
     assert np.array_equal(host(T2).astype(np.int64), want)
+
+
+@pytest.mark.parametrize("kind,D", [(sr.SR_ANTIDIST_U16, 3000), (sr.SR_ANTIDIST_U8, 4100),
+                                    (sr.SR_DISTANCE_U16, 5000), (sr.SR_ANTIDIST_U16, 6144)])
+def test_closure_loop_split_chain(kind, D):
+    """The blocked loop at mid sizes, where the panels and the lookahead part
+    run as K-split tiles: overlapped and serial schedules equal, sampled rows
+    against the oracle's per-row path computation."""
+    gen = synthgen.generator(9990 + kind + D)
+    S = S_OF[kind]
+    if kind == sr.SR_DISTANCE_U16:
+        A = rand_dist(D, D, kind, gen, p=2.0 / D, wmax=S // 8)
+        nA = (S - A.astype(np.int64))
+    else:
+        A = rand_antidist(D, D, kind, gen, p=2.0 / D, wmax=S // 8)
+    T = sr.to_device(kind, A)
+    T2 = sr.clone(T)
+    sr.closure(kind, T, flags=sr.SR_CLOSURE_WARSHALL)
+    sr.closure(kind, T2, flags=sr.SR_SERIAL_PHASES)
+    torch.cuda.synchronize()
+    got = host(T)
+    assert np.array_equal(got, host(T2))
+    rows = np.array([0, 1, 127, 128, D // 2, D - 1])
+    if kind == sr.SR_DISTANCE_U16:
+        want = S - oracle.ad_closure_rows(nA, S, rows).astype(np.int64)
+    else:
+        want = oracle.ad_closure_rows(A, S, rows)
+    assert np.array_equal(got[rows].astype(np.int64), want.astype(np.int64))
