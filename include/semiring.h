@@ -175,7 +175,7 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
  * 2^j >= D - 1 (eq. trcl, SR_CLOSURE_SQUARING), is the default for
  * anti-distance and distance matrices with 192 <= D <= 1024 (768 for the
  * 32-bit kinds), where the loop's chain of D sequential pivot steps costs more
- * than the squarings' extra products; from there up to D = 3072 (8- and
+ * than the squarings' extra products; from there up to D = 2560 (8- and
  * 16-bit kinds) the loop runs in blocks of 512 pivots, each pivot block closed
  * by squaring and the panels and update done as products.  Both allocate
  * stream-ordered working memory (two matrices of the squared size) and are

@@ -61,11 +61,12 @@ int base_kind(int kind) {
 constexpr int64_t kSquaringMinD = 192;
 // Big-block closure (pivot blocks of kBigBlock closed by squaring) above the
 // squaring range, up to these sizes (measured against the 128-pivot loop with
-// its K-split lookahead: uint16 D = 1536 0.59 vs 1.14 ms, 2048 0.99 vs 1.50,
-// 3072 2.13 vs 2.25, 4096 4.26 vs 3.50; 512 the best block of 256 / 512 /
-// 768 / 1024; uint32 slower at every size, so off).
+// its K-split panels and lookahead and paired pivot steps: uint16 D = 1536
+// 0.59 vs 0.95 ms, 2048 0.99 vs 1.24, 3072 2.13 vs 1.99, 4096 4.26 vs 3.29;
+// 512 the best block of 256 / 512 / 768 / 1024; uint32 slower at every size,
+// so off).
 constexpr int64_t kBigBlock = 512;
-constexpr int64_t kBigBlockMaxD16 = 3072;
+constexpr int64_t kBigBlockMaxD16 = 2560;
 constexpr int64_t kBigBlockMaxD32 = 0;
 constexpr int64_t kSquaringMaxD16 = 1024;
 constexpr int64_t kSquaringMaxD32 = 768;
