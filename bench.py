@@ -57,8 +57,8 @@ TRAFFIC = {
     # full update launch (252 x 32 workgroups, every tile outside the pivot
     # row and column blocks) of the D = 8192 closure:
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, in bytes
-    "fw8192": {"src_hash": "9bc56f8d39641d9c", "bytes_per_launch": 4.777e8},   # 1.698e5 + 1.270e5 KiB
-    "u8fw8192": {"src_hash": "9bc56f8d39641d9c", "bytes_per_launch": 4.841e8},  # 1.729e5 + 1.270e5 KiB
+    "fw8192": {"src_hash": "e73cf1ea53376fea", "bytes_per_launch": 4.777e8},   # 1.698e5 + 1.270e5 KiB
+    "u8fw8192": {"src_hash": "e73cf1ea53376fea", "bytes_per_launch": 4.841e8},  # 1.729e5 + 1.270e5 KiB
     "u32fw8192": {"src_hash": "52fb5786d930fdd0", "bytes_per_launch": 7.244e8},  # 2.251e5 + 2.572e5 KiB
     # full update launches (four-Russians kernel, 32 x 32 tiles of 512 x 512
     # bits) of the serialized D = 16384 Boolean closure
@@ -68,9 +68,10 @@ TRAFFIC = {
 
 def src_hash(workload):
     """Hash of the device source of the workload's update kernel: for
-    anti-distance the tile code (sr_tiles.h) and the text of the
-    k_ad_fw_update kernel template (host-side changes elsewhere in
-    sr_antidist.hip do not change the kernel); for Boolean sr_bool.hip; for
+    anti-distance the tile code (sr_tiles.h but the pivot tile's closure) and
+    the text of the k_ad_fw_update kernel template (host-side changes
+    elsewhere in sr_antidist.hip do not change the kernel); for Boolean
+    sr_bool.hip; for
     the uint32 path the update kernel's text and the device code before the
     product kernel in sr_antidist32.hip."""
     h = hashlib.sha256()
@@ -91,8 +92,13 @@ def src_hash(workload):
         h.update(text[a:b].encode())
         h.update(text[c:d].encode())
         return h.hexdigest()[:16]
-    with open(os.path.join(csrc, "sr_tiles.h"), "rb") as f:
-        h.update(f.read())
+    # the tile code the update kernel runs (sr_tiles.h without the pivot
+    # tile's closure) and the update kernel's own text
+    with open(os.path.join(csrc, "sr_tiles.h")) as f:
+        tiles = f.read()
+    a = tiles.rfind("// ----", 0, tiles.index("// Warshall closure of one bs x bs tile"))
+    b = tiles.index("// Number of phase-2 workgroups of a round:")
+    h.update((tiles[:a] + tiles[b:]).encode())
     with open(os.path.join(csrc, "sr_antidist.hip")) as f:
         text = f.read()
     start = text.index("k_ad_fw_update(uint16_t *T")
