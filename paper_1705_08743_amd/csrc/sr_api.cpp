@@ -515,57 +515,48 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
         }
         if (method != SR_CLOSURE_WARSHALL && capturing(st)) method = SR_CLOSURE_WARSHALL;
     }
+    // Working memory first, so that a failed allocation returns before the
+    // caller's matrix is touched: the binary16 copy of uint8 data, and the
+    // two matrices of squaring (of the whole matrix, or of one big block).
+    const bool big = method == SR_CLOSURE_BIG_BLOCKS;
+    const bool squared = method != SR_CLOSURE_WARSHALL;
+    const bool s8 = ak == SR_ANTIDIST_U8;
+    const int64_t lw = round_up(D, 64);
+    const size_t tw = s8 ? (size_t)(D * lw) * 2 : 0;
+    const int wes = s8 ? 2 : es;
+    const int64_t B = big ? std::min<int64_t>(big_block_size(), D) : D;
+    const size_t need = tw + (squared ? squaring_work_bytes(wes, B) : 0);
+    void *w = nullptr;
+    if (need > 0 && (rc = work_alloc(&w, std::max<size_t>(need, 256), st)) != SR_OK) return rc;
     // distance closure (dransclose) by De Morgan: not closure(not T)
     if (is_dist(kind)) e = sr::launch_ewise(es, sr::EW_NOT, T, ldt, T, ldt, T, ldt, D, D, 0, st);
-    if (e == hipSuccess && method != SR_CLOSURE_WARSHALL) {
-        // squaring or big blocks, on T itself or on the binary16 working copy
-        // of uint8 data
-        const bool big = method == SR_CLOSURE_BIG_BLOCKS;
-        const int64_t B = big ? std::min<int64_t>(big_block_size(), D) : D;
-        const int wes = ak == SR_ANTIDIST_U8 ? 2 : es;
-        const int64_t lw = round_up(D, 64);
-        const size_t tw = ak == SR_ANTIDIST_U8 ? (size_t)(D * lw) * 2 : 0;
-        void *w = nullptr;
-        if ((rc = work_alloc(&w, tw + std::max<size_t>(squaring_work_bytes(wes, B), 256), st)) !=
-            SR_OK)
-            return rc;
+    // the matrix the method runs on: T, or the binary16 copy of uint8 data
+    void *M = T;
+    int64_t ldm = ldt;
+    if (e == hipSuccess && s8) {
+        M = w;
+        ldm = lw;
+        e = sr::launch_widen_u8(static_cast<uint16_t *>(M), lw, static_cast<uint8_t *>(T), ldt, D,
+                                D, st);
+    }
+    if (e == hipSuccess && squared) {
         void *work = static_cast<char *>(w) + tw;
-        void *M = T;
-        int64_t ldm = ldt;
-        if (ak == SR_ANTIDIST_U8) {
-            M = w;
-            ldm = lw;
-            e = sr::launch_widen_u8(static_cast<uint16_t *>(M), lw, static_cast<uint8_t *>(T), ldt,
-                                    D, D, st);
-        }
-        const bool s8 = ak == SR_ANTIDIST_U8;
-        if (e == hipSuccess)
-            e = big ? closure_big_blocks(wes, s8, M, ldm, D, B, work, st)
-                    : closure_by_squaring(wes, s8, M, ldm, D, work, st);
-        if (e == hipSuccess && ak == SR_ANTIDIST_U8)
-            e = sr::launch_narrow_u8(static_cast<uint8_t *>(T), ldt, static_cast<uint16_t *>(M),
-                                     lw, D, D, st);
-        work_free(w, st);
+        e = big ? closure_big_blocks(wes, s8, M, ldm, D, B, work, st)
+                : closure_by_squaring(wes, s8, M, ldm, D, work, st);
     } else if (e == hipSuccess && ak == SR_BOOL) {
         const int path = (bool_path & SR_BOOL_M4R) ? sr::kBoolPathM4r
                          : (bool_path & SR_BOOL_BITWISE) ? sr::kBoolPathBitwise
                                                          : sr::kBoolPathAuto;
         e = sr::launch_bool_closure(static_cast<uint64_t *>(T), ldt, D, serial, path, st);
-    } else if (e == hipSuccess && ak == SR_ANTIDIST_U16) {
-        e = sr::launch_ad_closure(false, static_cast<uint16_t *>(T), ldt, D, serial, st);
     } else if (e == hipSuccess && ak == SR_ANTIDIST_U32) {
         e = sr::launch_ad32_closure(static_cast<uint32_t *>(T), ldt, D, serial, st);
     } else if (e == hipSuccess) {
-        const int64_t lw = round_up(D, 64);
-        void *w = nullptr;
-        if ((rc = work_alloc(&w, (size_t)(D * lw) * 2, st)) != SR_OK) return rc;
-        uint16_t *Tw = static_cast<uint16_t *>(w);
-        uint8_t *T8 = static_cast<uint8_t *>(T);
-        e = sr::launch_widen_u8(Tw, lw, T8, ldt, D, D, st);
-        if (e == hipSuccess) e = sr::launch_ad_closure(true, Tw, lw, D, serial, st);
-        if (e == hipSuccess) e = sr::launch_narrow_u8(T8, ldt, Tw, lw, D, D, st);
-        work_free(w, st);
+        e = sr::launch_ad_closure(s8, static_cast<uint16_t *>(M), ldm, D, serial, st);
     }
+    if (e == hipSuccess && s8)
+        e = sr::launch_narrow_u8(static_cast<uint8_t *>(T), ldt, static_cast<uint16_t *>(M), lw, D,
+                                 D, st);
+    work_free(w, st);
     if (e == hipSuccess && is_dist(kind))
         e = sr::launch_ewise(es, sr::EW_NOT, T, ldt, T, ldt, T, ldt, D, D, 0, st);
     // reflexive closure I (+) T (eq. rtc): the diagonal of the multiplicative
