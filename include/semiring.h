@@ -207,12 +207,65 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
  * per-round work lists are built on the host and uploaded stream-ordered
  * (the call returns without waiting); uint8 batches use stream-ordered
  * 16-bit working copies (binary16 values).  The rounds are three launches
- * each, which is what synchronizes the whole grid between phases; their
- * launch overhead is far below the batch's kernel time, so the batch is not
- * captured into a graph.
+ * each, which is what synchronizes the whole grid between phases.  The
+ * update tiles are 64 x 32 entries unless sr_batch_autotune chose another
+ * shape for batches of this class.  For a graph-captured form see the
+ * prepared batches below.
  */
 int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t *D,
                     int64_t count, unsigned flags, void *stream);
+
+/*
+ * Prepared batches -- closure_batched split into a one-time preparation and a
+ * per-closure launch sequence, for a batch whose matrices are closed again
+ * and again (new contents, same matrices and sizes).  The sequence holds
+ * kernel launches only, so it can be captured into a HIP graph and the whole
+ * batch closed by one graph launch.  The closure computed is closure_batched's.
+ *
+ * sr_batch_create validates (kind, T, ldt, D, count, flags) as closure_batched
+ * does, builds the descriptors and per-round work lists with update tiles of
+ * shape `tile` (SR_BATCH_TILE_*; SR_BATCH_TILE_AUTO: the autotuned shape for
+ * batches of this class, else 64 x 32; any other value is SR_EINVAL),
+ * allocates device memory for them -- and for uint8 kinds the 16-bit working
+ * copies, 2 * sum(D[g] * round_up(D[g], 8)) bytes -- with hipMalloc, uploads
+ * them on `stream`, waits for the upload and stores the handle in *out
+ * (NULL on error).  The three arrays are copied (the caller may free them);
+ * the matrices must stay allocated while the handle is used.  SR_EUNSUPPORTED
+ * while `stream` is being captured.
+ *
+ * sr_batch_run enqueues, on `stream`, the in-place closure of the matrices'
+ * current contents: no allocation, copy, memset or host callback.  The
+ * current device must be the one the handle was created on (SR_EINVAL).  Runs
+ * of one handle must not overlap in time (uint8 batches share the working
+ * copies).
+ *
+ * sr_batch_autotune times the batch with each update-tile shape on zero
+ * matrices of the same sizes (allocated for the purpose; the kernels'
+ * runtimes do not depend on the entries), once to warm up and twice more;
+ * keeps the fastest in the handle and in the autotuning table under the size
+ * classes of the largest D and of count (closure_batched and SR_BATCH_TILE_AUTO
+ * then use it), and stores it in *chosen (may be NULL).  It synchronizes
+ * `stream` and returns SR_EUNSUPPORTED while that is being captured; the
+ * matrices of the batch are not touched.
+ *
+ * sr_batch_tile returns the handle's update-tile shape (SR_BATCH_TILE_*).
+ * sr_batch_destroy frees the handle (NULL: no-op); hipFree waits for work in
+ * flight, and a graph that captured runs of the handle must not be replayed
+ * afterwards.
+ */
+typedef struct sr_batch sr_batch;
+enum {
+    SR_BATCH_TILE_AUTO = 0,
+    SR_BATCH_TILE_64x16 = 1,
+    SR_BATCH_TILE_64x32 = 2,
+    SR_BATCH_TILE_64x64 = 3
+};
+int sr_batch_create(int kind, void *const *T, const int64_t *ldt, const int64_t *D,
+                    int64_t count, unsigned flags, int tile, sr_batch **out, void *stream);
+int sr_batch_run(sr_batch *batch, void *stream);
+int sr_batch_autotune(sr_batch *batch, int *chosen, void *stream);
+int sr_batch_tile(const sr_batch *batch);
+void sr_batch_destroy(sr_batch *batch);
 
 /*
  * Autotuning (not part of the paper's method: it chooses between exact

@@ -68,6 +68,12 @@ SR_CLOSURE_SQUARING = 64
 SR_CLOSURE_WARSHALL = 128
 SR_CLOSURE_BIG_BLOCKS = 256
 
+# update-tile shapes of a prepared batch (entries per wave tile)
+SR_BATCH_TILE_AUTO = 0
+SR_BATCH_TILE_64x16 = 1
+SR_BATCH_TILE_64x32 = 2
+SR_BATCH_TILE_64x64 = 3
+
 ERROR_NAMES = {
     SR_EINVAL: "SR_EINVAL", SR_EALIAS: "SR_EALIAS", SR_EALIGN: "SR_EALIGN",
     SR_ENOMEM: "SR_ENOMEM", SR_EDEVICE: "SR_EDEVICE", SR_EUNSUPPORTED: "SR_EUNSUPPORTED",
@@ -77,6 +83,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsemiring
 
 EXPORTS = ("semiring_mul", "semiring_add", "semiring_ewise", "closure", "closure_batched",
            "sr_autotune_closure", "sr_autotune_mul", "sr_autotune_clear",
+           "sr_batch_create", "sr_batch_run", "sr_batch_autotune", "sr_batch_tile",
+           "sr_batch_destroy",
            "sr_profile_enable", "sr_profile_read", "sr_last_error", "sr_version", "sr_shutdown")
 
 SR_PHASE_PIVOT = 0
@@ -120,6 +128,18 @@ def lib():
         L.sr_autotune_mul.argtypes = [i32, i64, i64, i64, ctypes.POINTER(u32), vp]
         L.sr_autotune_mul.restype = i32
         L.sr_autotune_clear.restype = None
+        L.sr_batch_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64), i64, u32, i32,
+                                      ctypes.POINTER(vp), vp]
+        L.sr_batch_create.restype = i32
+        L.sr_batch_run.argtypes = [vp, vp]
+        L.sr_batch_run.restype = i32
+        L.sr_batch_autotune.argtypes = [vp, ctypes.POINTER(i32), vp]
+        L.sr_batch_autotune.restype = i32
+        L.sr_batch_tile.argtypes = [vp]
+        L.sr_batch_tile.restype = i32
+        L.sr_batch_destroy.argtypes = [vp]
+        L.sr_batch_destroy.restype = None
         L.sr_last_error.restype = ctypes.c_char_p
         L.sr_version.restype = ctypes.c_char_p
         L.sr_shutdown.restype = None
@@ -319,6 +339,55 @@ class BatchArena:
         self.buf.copy_(other.buf)
 
 
+class PreparedBatch:
+    """A batch prepared once for repeated closures (sr_batch_create): ``run()``
+    enqueues kernel launches only, so it can be captured into a CUDA/HIP graph
+    (``torch.cuda.CUDAGraph``) and the whole batch closed by one replay.
+    ``arena`` is a BatchArena (kept alive by this object); tile is one of the
+    SR_BATCH_TILE_* shapes.  ``close()`` frees the device plan; a graph that
+    captured ``run()`` must not be replayed after that."""
+
+    def __init__(self, kind, arena, flags=0, tile=SR_BATCH_TILE_AUTO, stream=None):
+        if not isinstance(arena, BatchArena):
+            raise TypeError("PreparedBatch takes a BatchArena")
+        self.kind = kind
+        self.arena = arena
+        self._h = ctypes.c_void_p(None)
+        _check(lib().sr_batch_create(kind, arena._ptrs_c, arena._lds_c, arena._dims_c,
+                                     arena.count, flags, tile, ctypes.byref(self._h),
+                                     _stream(stream)))
+
+    def _handle(self):
+        if not self._h:
+            raise ValueError("the prepared batch has been closed")
+        return self._h
+
+    def run(self, stream=None):
+        """In-place closure of the arena's current contents."""
+        _check(lib().sr_batch_run(self._handle(), _stream(stream)))
+
+    def autotune(self, stream=None):
+        """Time the update-tile shapes, keep the fastest; returns its code."""
+        out = ctypes.c_int(0)
+        _check(lib().sr_batch_autotune(self._handle(), ctypes.byref(out), _stream(stream)))
+        return out.value
+
+    @property
+    def tile(self):
+        return lib().sr_batch_tile(self._handle())
+
+    def close(self):
+        if self._h:
+            lib().sr_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def autotune_closure(kind, D, stream=None):
     """Time the closure methods for (kind, D) and keep the fastest for D's
     size class; returns its flags (SR_CLOSURE_* [| SR_BOOL_*])."""
@@ -434,11 +503,15 @@ __all__ = [
     "SR_BOOL", "SR_ANTIDIST_U8", "SR_ANTIDIST_U16", "SR_DISTANCE_U8", "SR_DISTANCE_U16",
     "SR_ANTIDIST_U32", "SR_DISTANCE_U32", "elem_bytes",
     "SR_BOOL_M4R", "SR_CLOSURE_SQUARING", "SR_CLOSURE_WARSHALL", "SR_CLOSURE_BIG_BLOCKS",
-    "autotune_closure", "autotune_mul", "autotune_clear", "SR_EW_AND", "SR_EW_OR", "SR_EW_XOR", "SR_EW_NOT", "semiring_ewise", "SR_OK", "SR_EINVAL", "SR_EALIAS",
+    "autotune_closure", "autotune_mul", "autotune_clear", "SR_BATCH_TILE_AUTO",
+    "SR_BATCH_TILE_64x16", "SR_BATCH_TILE_64x32", "SR_BATCH_TILE_64x64",
+    "SR_EW_AND", "SR_EW_OR", "SR_EW_XOR", "SR_EW_NOT", "semiring_ewise", "SR_OK", "SR_EINVAL",
+    "SR_EALIAS",
     "SR_EALIGN", "SR_ENOMEM", "SR_EDEVICE", "SR_EUNSUPPORTED", "SR_ACCUMULATE",
     "SR_REFLEXIVE", "SR_BOOL_BITWISE", "SR_BOOL_MFMA", "SR_SERIAL_PHASES", "SemiringError", "lib", "kind_of",
     "semiring_mul", "semiring_add", "closure", "closure_batched", "version", "shutdown",
     "sr_profile_enable", "sr_profile_read", "SR_PHASE_PIVOT", "SR_PHASE_PANELS",
     "SR_PHASE_UPDATE",
-    "padded_ld", "empty", "clone", "to_device", "to_host", "BatchArena", "EXPORTS", "LIB_PATH",
+    "padded_ld", "empty", "clone", "to_device", "to_host", "BatchArena", "PreparedBatch",
+    "EXPORTS", "LIB_PATH",
 ]

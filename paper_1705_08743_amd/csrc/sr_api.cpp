@@ -572,26 +572,30 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
     return ok();
 }
 
-int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t *D, int64_t count,
-                    unsigned flags, void *stream) {
-    if (!valid_kind(kind)) return fail(SR_EINVAL, "closure_batched: invalid kind %d", kind);
-    if (kind == SR_BOOL)
-        return fail(SR_EUNSUPPORTED, "closure_batched: Boolean batches are not built");
+}  // extern "C"
+
+namespace {
+
+// Validates a batch as closure_batched documents (fn names the entry point
+// in the messages).
+int check_batch(const char *fn, int kind, void *const *T, const int64_t *ldt, const int64_t *D,
+                int64_t count, unsigned flags) {
+    if (!valid_kind(kind)) return fail(SR_EINVAL, "%s: invalid kind %d", fn, kind);
+    if (kind == SR_BOOL) return fail(SR_EUNSUPPORTED, "%s: Boolean batches are not built", fn);
     if (base_kind(kind) == SR_ANTIDIST_U32)
-        return fail(SR_EUNSUPPORTED, "closure_batched: 32-bit batches are not built");
-    if (flags & ~(unsigned)SR_REFLEXIVE)
-        return fail(SR_EINVAL, "closure_batched: unknown flags 0x%x", flags);
-    if (count < 0) return fail(SR_EINVAL, "closure_batched: negative count");
+        return fail(SR_EUNSUPPORTED, "%s: 32-bit batches are not built", fn);
+    if (flags & ~(unsigned)SR_REFLEXIVE) return fail(SR_EINVAL, "%s: unknown flags 0x%x", fn, flags);
+    if (count < 0) return fail(SR_EINVAL, "%s: negative count", fn);
     if (count == 0) return ok();
-    if (count > INT32_MAX) return fail(SR_EINVAL, "closure_batched: count above 2^31-1");
-    if (!T || !ldt || !D) return fail(SR_EINVAL, "closure_batched: NULL descriptor array");
+    if (count > INT32_MAX) return fail(SR_EINVAL, "%s: count above 2^31-1", fn);
+    if (!T || !ldt || !D) return fail(SR_EINVAL, "%s: NULL descriptor array", fn);
     std::vector<Span> spans;
     spans.reserve((size_t)count);
     for (int64_t g = 0; g < count; g++) {
-        if (D[g] > 65536) return fail(SR_EINVAL, "closure_batched: D[%lld] too large", (long long)g);
+        if (D[g] > 65536) return fail(SR_EINVAL, "%s: D[%lld] too large", fn, (long long)g);
         if (check_matrix(kind, "T[g]", T[g], ldt[g], D[g], D[g]) != SR_OK) {
             char name[48];  // formatted only on failure: the check again, naming g
-            snprintf(name, sizeof name, "T[%lld]", (long long)g);
+            snprintf(name, sizeof name, "%s: T[%lld]", fn, (long long)g);
             return check_matrix(kind, name, T[g], ldt[g], D[g], D[g]);
         }
         if (D[g] > 0) spans.push_back(span_of(kind, T[g], ldt[g], D[g]));
@@ -599,17 +603,22 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
     std::sort(spans.begin(), spans.end(), [](Span a, Span b) { return a.lo < b.lo; });
     for (size_t i = 1; i < spans.size(); i++)
         if (spans[i].lo < spans[i - 1].hi)
-            return fail(SR_EALIAS, "closure_batched: two matrices of the batch overlap");
+            return fail(SR_EALIAS, "%s: two matrices of the batch overlap", fn);
+    return ok();
+}
 
-    hipStream_t st = as_stream(stream);
+// The batch's descriptors, largest graph first (ties keep the caller's
+// order).  uint8 kinds: T8 is the caller's matrix and T, the 16-bit working
+// copy, is left null for place_working_copies; *work_elems receives the
+// elements those copies take.
+std::vector<sr::BatchDesc> batch_descs(int kind, void *const *T, const int64_t *ldt,
+                                       const int64_t *D, int64_t count, size_t *work_elems) {
     const bool s8 = base_kind(kind) == SR_ANTIDIST_U8;
-    // largest first (ties keep the caller's order)
     std::vector<int64_t> order((size_t)count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return D[a] > D[b]; });
-
     std::vector<sr::BatchDesc> h((size_t)count);
-    size_t work_elems = 0;
+    *work_elems = 0;
     for (int64_t i = 0; i < count; i++) {
         const int64_t g = order[(size_t)i];
         sr::BatchDesc &d = h[(size_t)i];
@@ -620,7 +629,7 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
             d.ld8 = ldt[g];
             d.ld = round_up(D[g], 8);
             d.T = nullptr;
-            work_elems += (size_t)(D[g] * d.ld);
+            *work_elems += (size_t)(D[g] * d.ld);
         } else {
             d.T8 = nullptr;
             d.ld8 = 0;
@@ -628,21 +637,54 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
             d.ld = ldt[g];
         }
     }
+    return h;
+}
+
+// Points the uint8 descriptors' working copies at consecutive pieces of
+// `arena` (16-bit elements; the pieces are multiples of 16 bytes).
+void place_working_copies(std::vector<sr::BatchDesc> &h, void *arena) {
+    uint16_t *a = static_cast<uint16_t *>(arena);
+    size_t off = 0;
+    for (sr::BatchDesc &d : h) {
+        d.T = a + off;
+        off += (size_t)d.D * (size_t)d.ld;
+    }
+}
+
+// Update-tile shape for a batch: SR_BATCH_TILE (1, 2, 3) if set, else the
+// autotuned choice for its class, else the default.
+int batch_tile_for(int kind, const std::vector<sr::BatchDesc> &h) {
+    static const int forced = [] {
+        const char *v = getenv("SR_BATCH_TILE");
+        const int t = v ? atoi(v) : 0;
+        return t >= 1 && t <= 3 ? t : 0;
+    }();
+    if (forced) return forced;
+    const int64_t max_d = h.empty() ? 0 : h.front().D;
+    const unsigned t = sr::tuned_get(sr::kTuneBatch, kind, max_d, (int64_t)h.size(), 0);
+    return t ? (int)t : sr::kBatchTileDefault;
+}
+
+}  // namespace
+
+extern "C" {
+
+int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t *D, int64_t count,
+                    unsigned flags, void *stream) {
+    int rc = check_batch("closure_batched", kind, T, ldt, D, count, flags);
+    if (rc != SR_OK || count == 0) return rc;
+    hipStream_t st = as_stream(stream);
+    const bool s8 = base_kind(kind) == SR_ANTIDIST_U8;
+    size_t work_elems = 0;
+    std::vector<sr::BatchDesc> h = batch_descs(kind, T, ldt, D, count, &work_elems);
     // descriptors and per-round work lists, then the 16-bit working copies
     std::unique_ptr<sr::BatchPlan, void (*)(sr::BatchPlan *)> plan(
-        sr::batch_plan_create(h.data(), count), sr::batch_plan_destroy);
+        sr::batch_plan_create(h.data(), count, batch_tile_for(kind, h)), sr::batch_plan_destroy);
     const size_t plan_bytes = round_up((int64_t)sr::batch_plan_bytes(plan.get(), count), 256);
     void *w = nullptr;
-    int rc = work_alloc(&w, plan_bytes + work_elems * 2, st);
+    rc = work_alloc(&w, plan_bytes + work_elems * 2, st);
     if (rc != SR_OK) return rc;
-    if (s8) {
-        uint16_t *arena = reinterpret_cast<uint16_t *>(static_cast<char *>(w) + plan_bytes);
-        size_t off = 0;
-        for (sr::BatchDesc &d : h) {
-            d.T = arena + off;
-            off += (size_t)d.D * (size_t)d.ld;
-        }
-    }
+    if (s8) place_working_copies(h, static_cast<char *>(w) + plan_bytes);
     hipError_t e = sr::launch_ad_closure_batched(s8, plan.get(), h.data(), count, w, is_dist(kind),
                                                  (flags & SR_REFLEXIVE) != 0, st);
     work_free(w, st);
@@ -767,5 +809,193 @@ int sr_autotune_mul(int kind, int64_t R, int64_t K, int64_t N, unsigned *chosen,
 }
 
 void sr_autotune_clear(void) { sr::tuned_clear(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Prepared batches
+
+struct sr_batch {
+    int kind = 0;
+    int device = 0;
+    bool s8 = false, dual = false, reflexive = false;
+    int64_t count = 0;
+    std::vector<sr::BatchDesc> h;  // largest first; uint8: working copies placed
+    sr::BatchPlan *plan = nullptr;
+    char *dev = nullptr;      // hipMalloc: the plan image (image_cap bytes), then
+    size_t image_cap = 0;     // the uint8 working copies
+    size_t work_elems = 0;
+};
+
+namespace {
+
+// Largest device image over the update-tile shapes (a handle keeps room for
+// any of them, so autotuning can re-plan in place).
+size_t batch_image_cap(const std::vector<sr::BatchDesc> &h) {
+    size_t cap = 256;
+    for (int t = 1; t <= 3; t++) {
+        sr::BatchPlan *p = sr::batch_plan_create(h.data(), (int64_t)h.size(), t);
+        cap = std::max(cap, (size_t)round_up((int64_t)sr::batch_plan_bytes(p, (int64_t)h.size()), 256));
+        sr::batch_plan_destroy(p);
+    }
+    return cap;
+}
+
+// Uploads the image of `plan` for descriptors h to dst on st and waits.
+hipError_t upload_image(const sr::BatchPlan *plan, const std::vector<sr::BatchDesc> &h, void *dst,
+                        hipStream_t st) {
+    std::vector<char> img(sr::batch_plan_bytes(plan, (int64_t)h.size()));
+    sr::batch_plan_image(plan, h.data(), (int64_t)h.size(), img.data());
+    hipError_t e = hipMemcpyAsync(dst, img.data(), img.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+}
+
+void batch_free(sr_batch *b) {
+    if (!b) return;
+    if (b->plan) sr::batch_plan_destroy(b->plan);
+    if (b->dev) (void)hipFree(b->dev);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sr_batch_create(int kind, void *const *T, const int64_t *ldt, const int64_t *D, int64_t count,
+                    unsigned flags, int tile, sr_batch **out, void *stream) {
+    if (!out) return fail(SR_EINVAL, "sr_batch_create: NULL out");
+    *out = nullptr;
+    if (tile < SR_BATCH_TILE_AUTO || tile > SR_BATCH_TILE_64x64)
+        return fail(SR_EINVAL, "sr_batch_create: unknown tile %d", tile);
+    int rc = check_batch("sr_batch_create", kind, T, ldt, D, count, flags);
+    if (rc != SR_OK) return rc;
+    hipStream_t st = as_stream(stream);
+    if (capturing(st))
+        return fail(SR_EUNSUPPORTED, "sr_batch_create: the stream is being captured");
+    std::unique_ptr<sr_batch, void (*)(sr_batch *)> b(new sr_batch, batch_free);
+    b->kind = kind;
+    b->s8 = base_kind(kind) == SR_ANTIDIST_U8;
+    b->dual = is_dist(kind);
+    b->reflexive = (flags & SR_REFLEXIVE) != 0;
+    b->count = count;
+    if (hipGetDevice(&b->device) != hipSuccess)
+        return fail(SR_EDEVICE, "sr_batch_create: no current device");
+    if (count > 0) {
+        b->h = batch_descs(kind, T, ldt, D, count, &b->work_elems);
+        b->image_cap = batch_image_cap(b->h);
+        const size_t bytes = b->image_cap + b->work_elems * 2;
+        if (hipMalloc(reinterpret_cast<void **>(&b->dev), bytes) != hipSuccess) {
+            b->dev = nullptr;
+            (void)hipGetLastError();
+            return fail(SR_ENOMEM, "sr_batch_create: could not allocate %zu bytes", bytes);
+        }
+        if (b->s8) place_working_copies(b->h, b->dev + b->image_cap);
+        b->plan = sr::batch_plan_create(b->h.data(), count,
+                                        tile ? tile : batch_tile_for(kind, b->h));
+        const hipError_t e = upload_image(b->plan, b->h, b->dev, st);
+        if (e != hipSuccess) return device_fail(e, "sr_batch_create upload");
+    }
+    *out = b.release();
+    return ok();
+}
+
+int sr_batch_run(sr_batch *b, void *stream) {
+    if (!b) return fail(SR_EINVAL, "sr_batch_run: NULL batch");
+    if (b->count == 0) return ok();
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+        return fail(SR_EINVAL, "sr_batch_run: the batch belongs to device %d, current is %d",
+                    b->device, dev);
+    const hipError_t e = sr::launch_ad_closure_batched_resident(
+        b->s8, b->plan, b->count, b->dev, b->dual, b->reflexive, as_stream(stream));
+    if (e != hipSuccess) return device_fail(e, "sr_batch_run launch");
+    return ok();
+}
+
+int sr_batch_tile(const sr_batch *b) {
+    return b && b->plan ? sr::batch_plan_tile(b->plan) : SR_BATCH_TILE_AUTO;
+}
+
+int sr_batch_autotune(sr_batch *b, int *chosen, void *stream) {
+    if (!b) return fail(SR_EINVAL, "sr_batch_autotune: NULL batch");
+    hipStream_t st = as_stream(stream);
+    if (capturing(st))
+        return fail(SR_EUNSUPPORTED, "sr_batch_autotune: the stream is being captured");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+        return fail(SR_EINVAL, "sr_batch_autotune: the batch belongs to device %d, current is %d",
+                    b->device, dev);
+    if (b->count == 0) {
+        if (chosen) *chosen = sr_batch_tile(b);
+        return ok();
+    }
+    // zero matrices of the batch's sizes and strides (each 256-byte aligned),
+    // then room for a plan image; uint8 batches reuse the handle's working
+    // copies
+    const int64_t ub = b->s8 ? 1 : 2;
+    std::vector<size_t> offs(b->h.size());
+    size_t mat_bytes = 0;
+    for (size_t i = 0; i < b->h.size(); i++) {
+        offs[i] = mat_bytes;
+        const int64_t ld = b->s8 ? b->h[i].ld8 : b->h[i].ld;
+        mat_bytes += (size_t)round_up((int64_t)b->h[i].D * ld * ub, 256);
+    }
+    mat_bytes = std::max<size_t>(mat_bytes, 256);
+    EventPair ev;
+    if (!ev.ok()) return device_fail(hipErrorOutOfMemory, "sr_batch_autotune: events");
+    void *z = nullptr;
+    int rc = work_alloc(&z, mat_bytes + b->image_cap, st);
+    if (rc != SR_OK) return rc;
+    char *zm = static_cast<char *>(z), *zimg = zm + mat_bytes;
+    std::vector<sr::BatchDesc> th = b->h;
+    for (size_t i = 0; i < th.size(); i++) {
+        if (b->s8)
+            th[i].T8 = reinterpret_cast<uint8_t *>(zm + offs[i]);
+        else
+            th[i].T = reinterpret_cast<uint16_t *>(zm + offs[i]);
+    }
+    int pick = 0;
+    float best = 0.0f;
+    for (int t = 1; t <= 3; t++) {
+        std::unique_ptr<sr::BatchPlan, void (*)(sr::BatchPlan *)> p(
+            sr::batch_plan_create(th.data(), b->count, t), sr::batch_plan_destroy);
+        if (upload_image(p.get(), th, zimg, st) != hipSuccess) continue;
+        const float ms = time_candidate(
+            st, ev.a, ev.b, 2, [&] { return hipMemsetAsync(zm, 0, mat_bytes, st); },
+            [&] {
+                return sr::launch_ad_closure_batched_resident(b->s8, p.get(), b->count, zimg,
+                                                              b->dual, b->reflexive, st) ==
+                               hipSuccess
+                           ? SR_OK
+                           : SR_EDEVICE;
+            });
+        if (ms >= 0.0f && (!pick || ms < best)) {
+            pick = t;
+            best = ms;
+        }
+    }
+    work_free(z, st);
+    (void)hipStreamSynchronize(st);
+    if (!pick) return fail(SR_EDEVICE, "sr_batch_autotune: no candidate ran");
+    if (pick != sr::batch_plan_tile(b->plan)) {
+        sr::BatchPlan *np = sr::batch_plan_create(b->h.data(), b->count, pick);
+        const hipError_t e = upload_image(np, b->h, b->dev, st);
+        if (e != hipSuccess) {
+            // the device image may be partly overwritten: keep the handle
+            // consistent by re-uploading the old plan
+            sr::batch_plan_destroy(np);
+            (void)upload_image(b->plan, b->h, b->dev, st);
+            return device_fail(e, "sr_batch_autotune upload");
+        }
+        sr::batch_plan_destroy(b->plan);
+        b->plan = np;
+    }
+    sr::tuned_set(sr::kTuneBatch, b->kind, b->h.front().D, b->count, 0, (unsigned)pick);
+    if (chosen) *chosen = pick;
+    return ok();
+}
+
+void sr_batch_destroy(sr_batch *b) { batch_free(b); }
 
 }  // extern "C"

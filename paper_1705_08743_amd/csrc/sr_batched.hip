@@ -31,7 +31,10 @@ using dev::fw_panels_wg;
 using dev::Rect;
 using dev::tile_closure;
 
-constexpr int kUTM = 1, kUNW = 16;  // update tiles: 64 rows x 32 columns per wave
+// Update-tile shapes of a batch (rows per lane TM, column pairs per wave NW:
+// a wave's tile is 64 TM rows x 2 NW columns), indexed by the tile code of
+// batch_plan_create (1: 64 x 16, 2: 64 x 32, 3: 64 x 64).
+constexpr int kTileNW[4] = {16, 8, 16, 32};
 
 // One entry per graph taking part in a launch; `first` is the graph's first
 // workgroup; a sentinel entry holds the launch's total.
@@ -73,9 +76,10 @@ __device__ __forceinline__ int find_item(const Item *items, int n, int bid) {
 
 __host__ __device__ inline int rounds_of(int D) { return (D + kAdBlock - 1) / kAdBlock; }
 
-// The full update rectangle of round kb for a graph of D vertices.
-__host__ __device__ inline Rect update_rect(int D, int kb, int *ncols_sel, int *nrows_sel) {
-    constexpr int RW = 64 * kUTM, CW = 2 * kUNW;
+// The full update rectangle of round kb for a graph of D vertices, in wave
+// tiles of RW rows x CW columns.
+__host__ __device__ inline Rect update_rect(int D, int kb, int RW, int CW, int *ncols_sel,
+                                            int *nrows_sel) {
     const int k0 = kb * kAdBlock, bs = min(kAdBlock, D - k0);
     Rect q;
     q.r_lo = 0;
@@ -111,20 +115,21 @@ k_batch_panels(const BatchDesc *desc, const Item *items, int n_items, int kb) {
     fw_panels_wg<S8>(d.T, d.ld, d.D, k0, bs, n_rowwg, (int)blockIdx.x - citems(items)[i].first);
 }
 
-// Phase 3: one 64 x 32 tile per wave.  The waves of all graphs are numbered
-// back to back (a graph's tiles column-chunk major), so a workgroup's four
-// waves may belong to different graphs; no wave of the launch idles except in
-// the last workgroup.
-template <bool S8>
+// Phase 3: one 64 x 2 NW tile per wave.  The waves of all graphs are
+// numbered back to back (a graph's tiles column-chunk major), so a
+// workgroup's four waves may belong to different graphs; no wave of the
+// launch idles except in the last workgroup.
+template <int NW, bool S8>
 __global__ void __launch_bounds__(256)
 k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, int n_waves) {
+    constexpr int CW = 2 * NW;
     const int gw = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (gw >= n_waves) return;
     const int i = find_item(items, n_items, gw);
     const BatchDesc d = cdesc(desc, citems(items)[i].graph);
     const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
     int nc = 0, nr = 0;
-    const Rect q = update_rect(d.D, kb, &nc, &nr);
+    const Rect q = update_rect(d.D, kb, 64, CW, &nc, &nr);
     const int local = gw - citems(items)[i].first;
     // column-chunk major: consecutive waves (most often the four waves of a
     // workgroup) share a column chunk, so its pivot-row segment B, read through
@@ -132,10 +137,10 @@ k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, in
     const int rsel = local % nr, csel = local / nr;
     int c = csel;
     if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
-    if ((c + 1) * (2 * kUNW) <= d.D)
-        dev::fw_update_wave<kUTM, kUNW, S8, true>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
+    if ((c + 1) * CW <= d.D)
+        dev::fw_update_wave<1, NW, S8, true>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
     else
-        dev::fw_update_wave<kUTM, kUNW, S8, false>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
+        dev::fw_update_wave<1, NW, S8, false>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
 }
 
 // uint8 <-> the 16-bit working form of uint8 data (binary16 values) for every
@@ -244,6 +249,8 @@ struct Launch {
 }  // namespace
 
 struct BatchPlan {
+    int tile;   // update-tile code (1, 2, 3)
+    int max_d;  // largest graph
     std::vector<Item> items;
     std::vector<Launch> pivot, panels, update;  // per round
 };
@@ -251,8 +258,13 @@ struct BatchPlan {
 namespace {
 
 void build_plan(BatchPlan &p, const BatchDesc *hd, int64_t count) {
+    const int cw = 2 * kTileNW[p.tile];
     int max_rounds = 0;
-    for (int64_t g = 0; g < count; g++) max_rounds = std::max(max_rounds, rounds_of(hd[g].D));
+    p.max_d = 0;
+    for (int64_t g = 0; g < count; g++) {
+        max_rounds = std::max(max_rounds, rounds_of(hd[g].D));
+        p.max_d = std::max(p.max_d, hd[g].D);
+    }
     for (int kb = 0; kb < max_rounds; kb++) {
         // pivot: every graph with a round kb
         Launch lp{(int64_t)p.items.size(), 0, 0, 0};
@@ -281,7 +293,7 @@ void build_plan(BatchPlan &p, const BatchDesc *hd, int64_t count) {
             const int D = hd[g].D;
             if (rounds_of(D) <= std::max(kb, 1)) continue;
             int nc = 0, nr = 0;
-            (void)update_rect(D, kb, &nc, &nr);
+            (void)update_rect(D, kb, 64, cw, &nc, &nr);
             const int waves = nc * nr;
             if (waves <= 0) continue;
             p.items.push_back(Item{(int32_t)g, lu.n_units});
@@ -300,48 +312,56 @@ size_t desc_bytes_of(int64_t count) {
 
 }  // namespace
 
-BatchPlan *batch_plan_create(const BatchDesc *host_desc, int64_t count) {
+BatchPlan *batch_plan_create(const BatchDesc *host_desc, int64_t count, int tile) {
     auto *p = new BatchPlan;
+    p->tile = tile >= 1 && tile <= 3 ? tile : kBatchTileDefault;
     build_plan(*p, host_desc, count);
     return p;
 }
 
 void batch_plan_destroy(BatchPlan *plan) { delete plan; }
 
+int batch_plan_tile(const BatchPlan *plan) { return plan->tile; }
+
 size_t batch_plan_bytes(const BatchPlan *plan, int64_t count) {
     return desc_bytes_of(count) + plan->items.size() * sizeof(Item);
 }
 
-hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const BatchDesc *host_desc,
-                                     int64_t count, void *dev_buf, bool dual, bool reflexive,
-                                     hipStream_t st) {
+void batch_plan_image(const BatchPlan *plan, const BatchDesc *host_desc, int64_t count, void *dst) {
+    char *out = static_cast<char *>(dst);
+    std::fill_n(out, batch_plan_bytes(plan, count), (char)0);
+    std::copy_n(reinterpret_cast<const char *>(host_desc), (size_t)count * sizeof(BatchDesc), out);
+    std::copy_n(reinterpret_cast<const char *>(plan->items.data()),
+                plan->items.size() * sizeof(Item), out + desc_bytes_of(count));
+}
+
+hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, int64_t count,
+                                              const void *dev_buf, bool dual, bool reflexive,
+                                              hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const BatchPlan &p = *plan;
-    const size_t desc_bytes = desc_bytes_of(count);
-    // host image of the descriptors and item lists; freed by a stream
-    // callback once the upload has executed
-    auto *img = new std::vector<char>(batch_plan_bytes(plan, count));
-    std::copy_n(reinterpret_cast<const char *>(host_desc), (size_t)count * sizeof(BatchDesc),
-                img->data());
-    std::copy_n(reinterpret_cast<const char *>(p.items.data()), p.items.size() * sizeof(Item),
-                img->data() + desc_bytes);
-    hipError_t e = hipMemcpyAsync(dev_buf, img->data(), img->size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipLaunchHostFunc(st, [](void *q) { delete static_cast<std::vector<char> *>(q); }, img);
-    else
-        delete img;
-    if (e != hipSuccess) return e;
     const BatchDesc *desc = static_cast<const BatchDesc *>(dev_buf);
-    const Item *items =
-        reinterpret_cast<const Item *>(static_cast<const char *>(dev_buf) + desc_bytes);
+    const Item *items = reinterpret_cast<const Item *>(static_cast<const char *>(dev_buf) +
+                                                       desc_bytes_of(count));
     const unsigned ng = (unsigned)count;
-    int32_t max_d = 0;
-    for (int64_t g = 0; g < count; g++) max_d = std::max(max_d, host_desc[g].D);
-    const dim3 conv(ng, (unsigned)std::max<int64_t>(1, ((int64_t)max_d + kConvRows - 1) / kConvRows));
+    const dim3 conv(ng, (unsigned)std::max<int64_t>(1, ((int64_t)p.max_d + kConvRows - 1) / kConvRows));
     if (s8)
         hipLaunchKernelGGL(k_batch_widen, conv, dim3(256), 0, st, desc, dual ? 1 : 0);
     else if (dual)
         hipLaunchKernelGGL(k_batch_not, conv, dim3(256), 0, st, desc);
+    // the update kernel of the plan's tile shape, for 16-bit (S8 = false) or
+    // binary16 (S8 = true) working data
+    using UpdateFn = void (*)(const BatchDesc *, const Item *, int, int, int);
+    UpdateFn upd = nullptr;
+    switch (p.tile * 2 + (s8 ? 1 : 0)) {
+        case 2: upd = k_batch_update<8, false>; break;
+        case 3: upd = k_batch_update<8, true>; break;
+        case 6: upd = k_batch_update<32, false>; break;
+        case 7: upd = k_batch_update<32, true>; break;
+        case 5: upd = k_batch_update<16, true>; break;
+        default: upd = k_batch_update<16, false>; break;
+    }
+    hipError_t e;
     for (size_t kb = 0; kb < p.pivot.size(); kb++) {
         const Launch &a = p.pivot[kb], &b = p.panels[kb], &c = p.update[kb];
         if (a.n_wg > 0) {
@@ -360,14 +380,9 @@ hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const Batch
                 hipLaunchKernelGGL(k_batch_panels<false>, dim3(b.n_wg), dim3(256), 0, st, desc,
                                    items + b.offset, b.n_items + 1, (int)kb);
         }
-        if (c.n_wg > 0) {
-            if (s8)
-                hipLaunchKernelGGL(k_batch_update<true>, dim3(c.n_wg), dim3(256), 0, st, desc,
-                                   items + c.offset, c.n_items + 1, (int)kb, c.n_units);
-            else
-                hipLaunchKernelGGL(k_batch_update<false>, dim3(c.n_wg), dim3(256), 0, st, desc,
-                                   items + c.offset, c.n_items + 1, (int)kb, c.n_units);
-        }
+        if (c.n_wg > 0)
+            hipLaunchKernelGGL(upd, dim3(c.n_wg), dim3(256), 0, st, desc, items + c.offset,
+                               c.n_items + 1, (int)kb, c.n_units);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (s8)
@@ -380,6 +395,23 @@ hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const Batch
         hipLaunchKernelGGL(k_batch_diag, dim3(ng), dim3(256), 0, st, desc, s8 ? 1 : 0, one);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const BatchDesc *host_desc,
+                                     int64_t count, void *dev_buf, bool dual, bool reflexive,
+                                     hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    // host image of the descriptors and item lists; freed by a stream
+    // callback once the upload has executed
+    auto *img = new std::vector<char>(batch_plan_bytes(plan, count));
+    batch_plan_image(plan, host_desc, count, img->data());
+    hipError_t e = hipMemcpyAsync(dev_buf, img->data(), img->size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipLaunchHostFunc(st, [](void *q) { delete static_cast<std::vector<char> *>(q); }, img);
+    else
+        delete img;
+    if (e != hipSuccess) return e;
+    return launch_ad_closure_batched_resident(s8, plan, count, dev_buf, dual, reflexive, st);
 }
 
 }  // namespace sr

@@ -113,17 +113,30 @@ struct BatchDesc {
     int32_t D;      // vertices
     int32_t pad;
 };
-// Host-side per-round work lists of a batch (they depend on the sizes only).
+// Host-side per-round work lists of a batch (they depend on the sizes and the
+// update-tile shape only).  tile: 1, 2, 3 = wave tiles of 64 x 16, 64 x 32,
+// 64 x 64 entries (anything else: kBatchTileDefault).
+constexpr int kBatchTileDefault = 2;
 struct BatchPlan;
-BatchPlan *batch_plan_create(const BatchDesc *host_desc, int64_t count);
+BatchPlan *batch_plan_create(const BatchDesc *host_desc, int64_t count, int tile);
 void batch_plan_destroy(BatchPlan *plan);
+int batch_plan_tile(const BatchPlan *plan);
+// Bytes of the device image: the descriptors, then the work lists.
 size_t batch_plan_bytes(const BatchPlan *plan, int64_t count);
+// Writes that image (batch_plan_bytes() bytes) to host memory at dst.
+void batch_plan_image(const BatchPlan *plan, const BatchDesc *host_desc, int64_t count, void *dst);
 // dual: the batch holds distance matrices (complemented, S - a, before and
 // after the anti-distance closure); reflexive: the diagonal is then set to
 // the multiplicative identity (S for anti-distance, 0 for distance).
 hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const BatchDesc *host_desc,
                                      int64_t count, void *dev_buf, bool dual, bool reflexive,
                                      hipStream_t stream);
+// The same closure with the image already in device memory at dev_buf: kernel
+// launches only (no copy, allocation or host callback), so it can be captured
+// into a graph and replayed.
+hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, int64_t count,
+                                              const void *dev_buf, bool dual, bool reflexive,
+                                              hipStream_t stream);
 
 // Second stream of a closure (sr_runtime.cpp), one per (device, caller
 // stream), created on first use at default priority.  aux_acquire() returns it
@@ -141,10 +154,11 @@ struct Aux {
 Aux *aux_acquire(hipStream_t caller);
 void aux_release(Aux *a);
 
-// Autotuning table (sr_tune.cpp).  op: kTuneClosure (a = D) or kTuneMul
-// (a, b, c = R, K, N); the stored choice is the flag set (SR_CLOSURE_*,
-// SR_BOOL_*) that reproduces the measured-fastest method; 0 = not tuned.
-enum { kTuneClosure = 1, kTuneMul = 2 };
+// Autotuning table (sr_tune.cpp).  op: kTuneClosure (a = D), kTuneMul
+// (a, b, c = R, K, N) or kTuneBatch (a = largest D, b = graphs); the stored
+// choice is the flag set (SR_CLOSURE_*, SR_BOOL_*) that reproduces the
+// measured-fastest method, or for a batch its update-tile code; 0 = not tuned.
+enum { kTuneClosure = 1, kTuneMul = 2, kTuneBatch = 3 };
 int size_class(int64_t n);
 unsigned tuned_get(int op, int kind, int64_t a, int64_t b, int64_t c);
 void tuned_set(int op, int kind, int64_t a, int64_t b, int64_t c, unsigned choice);

@@ -204,3 +204,32 @@ def test_autotune_and_method_flags_validation(L):
     assert L.closure(U16, P, 8, 8, sr.SR_CLOSURE_SQUARING | sr.SR_CLOSURE_BIG_BLOCKS,
                      None) == sr.SR_EINVAL
     assert L.closure(sr.SR_BOOL, P, 2, 8, sr.SR_CLOSURE_BIG_BLOCKS, None) == sr.SR_EUNSUPPORTED
+
+
+def test_prepared_batch_validation(L):
+    U16 = sr.SR_ANTIDIST_U16
+    n = 2
+    ptrs = (ctypes.c_void_p * n)(P, P + 4096)
+    lds = (ctypes.c_int64 * n)(8, 8)
+    dims = (ctypes.c_int64 * n)(8, 8)
+    h = ctypes.c_void_p(0x1234)
+    f = L.sr_batch_create
+    assert f(U16, ptrs, lds, dims, n, 0, 0, None, None) == sr.SR_EINVAL  # NULL out
+    assert f(U16, ptrs, lds, dims, n, 0, 4, ctypes.byref(h), None) == sr.SR_EINVAL
+    assert not h.value  # cleared on every error
+    assert f(U16, ptrs, lds, dims, n, 0, -1, ctypes.byref(h), None) == sr.SR_EINVAL
+    assert f(sr.SR_BOOL, ptrs, lds, dims, n, 0, 0, ctypes.byref(h), None) == sr.SR_EUNSUPPORTED
+    assert f(sr.SR_ANTIDIST_U32, ptrs, lds, dims, n, 0, 0, ctypes.byref(h),
+             None) == sr.SR_EUNSUPPORTED
+    assert f(U16, ptrs, lds, dims, -1, 0, 0, ctypes.byref(h), None) == sr.SR_EINVAL
+    assert f(U16, ptrs, lds, dims, n, sr.SR_ACCUMULATE, 0, ctypes.byref(h), None) == sr.SR_EINVAL
+    ptrs2 = (ctypes.c_void_p * n)(P, P + 64)
+    assert f(U16, ptrs2, lds, dims, n, 0, 0, ctypes.byref(h), None) == sr.SR_EALIAS
+    assert "sr_batch_create" in L.sr_last_error().decode()
+    out = ctypes.c_int(0)
+    assert L.sr_batch_run(None, None) == sr.SR_EINVAL
+    assert L.sr_batch_autotune(None, ctypes.byref(out), None) == sr.SR_EINVAL
+    assert L.sr_batch_tile(None) == sr.SR_BATCH_TILE_AUTO
+    L.sr_batch_destroy(None)
+    with pytest.raises(TypeError):
+        sr.PreparedBatch(U16, [])
