@@ -17,6 +17,7 @@
 // the large graphs from finishing alone on a few compute units.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include <algorithm>
 #include <vector>
@@ -76,6 +77,25 @@ __device__ __forceinline__ int find_item(const Item *items, int n, int bid) {
 
 __host__ __device__ inline int rounds_of(int D) { return (D + kAdBlock - 1) / kAdBlock; }
 
+// Workgroup bid of a launch of nwg runs on XCD bid % 8 (workgroups are handed
+// to the eight XCDs in turn).  The renumbering gives each XCD chunks of g
+// consecutive workgroups of the plan (chunk c to XCD c % 8), so that the
+// workgroups of one graph mostly run on one XCD and reuse the graph's pivot
+// row and column blocks from its L2 -- in the plain order consecutive
+// workgroups, most often of the same graph, land on eight different XCDs and
+// each L2 fetches the blocks again -- while every XCD still gets an even mix
+// of the batch's large and small graphs.  Workgroups past the last whole
+// round of 8 chunks keep their number.
+constexpr int kXcdChunk = 64;
+
+__device__ __forceinline__ int xcd_order(int bid, int nwg, int g) {
+    constexpr int kXcd = 8;
+    const int full = nwg / (kXcd * g) * (kXcd * g);
+    if (bid >= full) return bid;
+    const int x = bid % kXcd, j = bid / kXcd;
+    return ((j / g) * kXcd + x) * g + j % g;
+}
+
 // The full update rectangle of round kb for a graph of D vertices, in wave
 // tiles of RW rows x CW columns.
 __host__ __device__ inline Rect update_rect(int D, int kb, int RW, int CW, int *ncols_sel,
@@ -106,13 +126,14 @@ __global__ void __launch_bounds__(256) k_batch_pivot(const BatchDesc *desc, cons
 
 template <bool S8>
 __global__ void __launch_bounds__(256)
-k_batch_panels(const BatchDesc *desc, const Item *items, int n_items, int kb) {
-    const int i = find_item(items, n_items, (int)blockIdx.x);
+k_batch_panels(const BatchDesc *desc, const Item *items, int n_items, int kb, int xmap) {
+    const int bid = xmap ? xcd_order((int)blockIdx.x, (int)gridDim.x, xmap) : (int)blockIdx.x;
+    const int i = find_item(items, n_items, bid);
     const BatchDesc d = cdesc(desc, citems(items)[i].graph);
     const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
     int n_rowwg = 0, n_colwg = 0;
     dev::panel_wgs(d.D, k0, bs, &n_rowwg, &n_colwg);
-    fw_panels_wg<S8>(d.T, d.ld, d.D, k0, bs, n_rowwg, (int)blockIdx.x - citems(items)[i].first);
+    fw_panels_wg<S8>(d.T, d.ld, d.D, k0, bs, n_rowwg, bid - citems(items)[i].first);
 }
 
 // Phase 3: one 64 x 2 NW tile per wave.  The waves of all graphs are
@@ -121,9 +142,11 @@ k_batch_panels(const BatchDesc *desc, const Item *items, int n_items, int kb) {
 // launch idles except in the last workgroup.
 template <int NW, bool S8>
 __global__ void __launch_bounds__(256)
-k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, int n_waves) {
+k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, int n_waves,
+               int xmap) {
     constexpr int CW = 2 * NW;
-    const int gw = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int bid = xmap ? xcd_order((int)blockIdx.x, (int)gridDim.x, xmap) : (int)blockIdx.x;
+    const int gw = bid * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (gw >= n_waves) return;
     const int i = find_item(items, n_items, gw);
     const BatchDesc d = cdesc(desc, citems(items)[i].graph);
@@ -351,7 +374,19 @@ hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, in
         hipLaunchKernelGGL(k_batch_not, conv, dim3(256), 0, st, desc);
     // the update kernel of the plan's tile shape, for 16-bit (S8 = false) or
     // binary16 (S8 = true) working data
-    using UpdateFn = void (*)(const BatchDesc *, const Item *, int, int, int);
+    using UpdateFn = void (*)(const BatchDesc *, const Item *, int, int, int, int);
+    // XCD chunk of the update and panels launches (xcd_order; 0 = the plain
+    // order).  64 workgroups measured best for configuration 4 (uint16 16.6
+    // -> 15.8 ms, uint8 15.9 -> 14.3 ms; 4 / 16 / 256 in between); the
+    // environment variables SR_BATCH_XCD and SR_BATCH_XCDP override them.
+    static const int xmap = [] {
+        const char *v = getenv("SR_BATCH_XCD");
+        return v ? std::max(0, atoi(v)) : kXcdChunk;
+    }();
+    static const int xmapp = [] {
+        const char *v = getenv("SR_BATCH_XCDP");
+        return v ? std::max(0, atoi(v)) : kXcdChunk;
+    }();
     UpdateFn upd = nullptr;
     switch (p.tile * 2 + (s8 ? 1 : 0)) {
         case 2: upd = k_batch_update<8, false>; break;
@@ -375,14 +410,14 @@ hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, in
         if (b.n_wg > 0) {
             if (s8)
                 hipLaunchKernelGGL(k_batch_panels<true>, dim3(b.n_wg), dim3(256), 0, st, desc,
-                                   items + b.offset, b.n_items + 1, (int)kb);
+                                   items + b.offset, b.n_items + 1, (int)kb, xmapp);
             else
                 hipLaunchKernelGGL(k_batch_panels<false>, dim3(b.n_wg), dim3(256), 0, st, desc,
-                                   items + b.offset, b.n_items + 1, (int)kb);
+                                   items + b.offset, b.n_items + 1, (int)kb, xmapp);
         }
         if (c.n_wg > 0)
             hipLaunchKernelGGL(upd, dim3(c.n_wg), dim3(256), 0, st, desc, items + c.offset,
-                               c.n_items + 1, (int)kb, c.n_units);
+                               c.n_items + 1, (int)kb, c.n_units, xmap);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (s8)
