@@ -53,8 +53,9 @@ template <int TM, int NW, bool S8, bool FULL>
 __global__ void __launch_bounds__(256)
 k_ad_mul(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
          int64_t ldb, int64_t R, int K, int64_t N, int64_t col_base, int accumulate,
-         int64_t bmax) {
+         int64_t bmax, const int *gate) {
     constexpr int CW = 2 * NW, RW = 64 * TM;
+    if (gate && *gate == 0) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
     const int64_t row0 = ((int64_t)blockIdx.y * 4 + wave) * RW;
     const int64_t col0 = col_base + (int64_t)blockIdx.x * CW;
@@ -82,8 +83,9 @@ k_ad_mul(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_
 template <int NW, int KS, bool S8>
 __global__ void __launch_bounds__(64 * KS)
 k_ad_mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
-                int64_t ldb, int64_t R, int K, int kq, int accumulate) {
+                int64_t ldb, int64_t R, int K, int kq, int accumulate, const int *gate) {
     __shared__ uint4 part[KS][64][NW / 4];
+    if (gate && *gate == 0) return;  // (uniform over the workgroup: before any barrier)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
     const int64_t row0 = (int64_t)blockIdx.y * 64;
     const int64_t col0 = (int64_t)blockIdx.x * 2 * NW;
@@ -267,14 +269,14 @@ Shape pick_mul_shape(int64_t R, int64_t N) {
 template <int TM, int NW, bool S8>
 hipError_t mul_shape(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
                      int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, int64_t bmax,
-                     hipStream_t st) {
+                     const int *gate, hipStream_t st) {
     constexpr int CW = 2 * NW;
     const unsigned gy = (unsigned)((R + 256 * TM - 1) / (256 * TM));
     const int64_t nfull = N / CW;
     if (nfull > 0) {
         hipLaunchKernelGGL((k_ad_mul<TM, NW, S8, true>), dim3((unsigned)nfull, gy), dim3(256), 0,
                            st, C, ldc, A, lda, B, ldb, R, (int)K, N, (int64_t)0, acc ? 1 : 0,
-                           bmax);
+                           bmax, gate);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -284,7 +286,7 @@ hipError_t mul_shape(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, c
         const unsigned gx = (unsigned)((N - c0 + 15) / 16);
         hipLaunchKernelGGL((k_ad_mul<1, 8, S8, false>), dim3(gx, (unsigned)((R + 255) / 256)),
                            dim3(256), 0, st, C, ldc, A, lda, B, ldb, R, (int)K, N, c0,
-                           acc ? 1 : 0, bmax);
+                           acc ? 1 : 0, bmax, gate);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -297,14 +299,14 @@ hipError_t mul_shape(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, c
 template <bool S8>
 hipError_t mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
                       const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc,
-                      int64_t bmax, hipStream_t st) {
+                      int64_t bmax, const int *gate, hipStream_t st) {
     constexpr int NW = 8, CW = 2 * NW, KS = 8;
     const int64_t nfull = N / CW;
     const int kq = (int)((K + KS * 32 - 1) / (KS * 32) * 32);
     if (nfull > 0) {
         hipLaunchKernelGGL((k_ad_mul_ksplit<NW, KS, S8>),
                            dim3((unsigned)nfull, (unsigned)((R + 63) / 64)), dim3(64 * KS), 0, st,
-                           C, ldc, A, lda, B, ldb, R, (int)K, kq, acc ? 1 : 0);
+                           C, ldc, A, lda, B, ldb, R, (int)K, kq, acc ? 1 : 0, gate);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -312,7 +314,7 @@ hipError_t mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
         const int64_t c0 = nfull * CW;
         hipLaunchKernelGGL((k_ad_mul<1, 8, S8, false>), dim3(1u, (unsigned)((R + 255) / 256)),
                            dim3(256), 0, st, C, ldc, A, lda, B, ldb, R, (int)K, N, c0,
-                           acc ? 1 : 0, bmax);
+                           acc ? 1 : 0, bmax, gate);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -321,16 +323,20 @@ hipError_t mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
 template <bool S8>
 hipError_t mul_s(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
                  int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, int64_t bmax,
-                 hipStream_t st) {
+                 const int *gate, hipStream_t st) {
     const int64_t tiles16 = ((R + 63) / 64) * (N / 16);
     if (tiles16 > 0 && tiles16 <= 2048 && K >= 256)
-        return mul_ksplit<S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, st);
+        return mul_ksplit<S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, st);
     const Shape s = pick_mul_shape(R, N);
-    if (s.tm == 2) return mul_shape<2, 32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, st);
+    if (s.tm == 2)
+        return mul_shape<2, 32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, st);
     switch (s.nw) {
-        case 32: return mul_shape<1, 32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, st);
-        case 16: return mul_shape<1, 16, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, st);
-        default: return mul_shape<1, 8, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, st);
+        case 32:
+            return mul_shape<1, 32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, st);
+        case 16:
+            return mul_shape<1, 16, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, st);
+        default:
+            return mul_shape<1, 8, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, st);
     }
 }
 
@@ -648,10 +654,11 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
 
 hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
                          const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
-                         bool accumulate, hipStream_t stream, int64_t bspan) {
+                         bool accumulate, hipStream_t stream, int64_t bspan,
+                         const int *gate) {
     const int64_t bmax = bspan >= 0 ? bspan : ldb;
-    return s8 ? mul_s<true>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, stream)
-              : mul_s<false>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, stream);
+    return s8 ? mul_s<true>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, stream)
+              : mul_s<false>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, stream);
 }
 
 hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, bool serial,

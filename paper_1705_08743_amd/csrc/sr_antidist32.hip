@@ -186,7 +186,8 @@ template <int CW, bool FULL>
 __global__ void __launch_bounds__(256)
 k_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
            int64_t ldb, int64_t R, int K, int64_t N, int64_t col_base, int accumulate,
-           int64_t bmax) {
+           int64_t bmax, const int *gate) {
+    if (gate && *gate == 0) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t row0 = ((int64_t)blockIdx.y * 4 + wave) * kRW;
     const int64_t col0 = col_base + (int64_t)blockIdx.x * CW;
@@ -356,18 +357,19 @@ k_ad32_update(uint32_t *T, int64_t ld, int D, int k0, int bs, Rect q, int prio) 
 template <int CW>
 hipError_t mul_cw(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
                   int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, int64_t bmax,
-                  hipStream_t st) {
+                  const int *gate, hipStream_t st) {
     const unsigned gy = (unsigned)((R + 4 * kRW - 1) / (4 * kRW));
     const int64_t nfull = N / CW;
     if (nfull > 0) {
         hipLaunchKernelGGL((k_ad32_mul<CW, true>), dim3((unsigned)nfull, gy), dim3(256), 0, st, C,
-                           ldc, A, lda, B, ldb, R, (int)K, N, (int64_t)0, acc ? 1 : 0, bmax);
+                           ldc, A, lda, B, ldb, R, (int)K, N, (int64_t)0, acc ? 1 : 0, bmax,
+                           gate);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (N % CW) {
         hipLaunchKernelGGL((k_ad32_mul<CW, false>), dim3(1u, gy), dim3(256), 0, st, C, ldc, A, lda,
-                           B, ldb, R, (int)K, N, nfull * CW, acc ? 1 : 0, bmax);
+                           B, ldb, R, (int)K, N, nfull * CW, acc ? 1 : 0, bmax, gate);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -537,13 +539,14 @@ hipError_t closure32(uint32_t *T, int64_t ld, int64_t D, bool serial, hipStream_
 
 hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda,
                            const uint32_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
-                           bool accumulate, hipStream_t stream, int64_t bspan) {
+                           bool accumulate, hipStream_t stream, int64_t bspan,
+                           const int *gate) {
     const int64_t bmax = bspan >= 0 ? bspan : ldb;
     // 16-column tiles when 32-column ones would leave the chip short of waves
     const int64_t waves32 = ((R + kRW - 1) / kRW) * ((N + 31) / 32);
     if (waves32 >= 8192)
-        return mul_cw<32>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, stream);
-    return mul_cw<16>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, stream);
+        return mul_cw<32>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, stream);
+    return mul_cw<16>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, stream);
 }
 
 hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, bool serial,

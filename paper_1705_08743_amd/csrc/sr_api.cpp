@@ -328,9 +328,10 @@ int64_t big_block_max_d(int ak) {
 // m >= D - 1, because a best path never needs more than D - 1 edges before
 // its last one): P := I (+) A, then j squarings P := P * P with 2^j >= D - 1,
 // then T := A * P.  Exact like every other path of the library; the
-// products are the semiring_mul kernels.  es: 2 (uint16, or the binary16
-// form of uint8 data when s8), 4 (uint32), 8 (Boolean words; ld in words).
-// work: 2 * D * round_up(D, 64) entries of es bytes (for Boolean, words).
+// products are the semiring_mul kernels.  For anti-distance entries the
+// squarings stop on the device once one leaves P unchanged (below).  es: 2
+// (uint16, or the binary16 form of uint8 data when s8), 4 (uint32), 8
+// (Boolean words; ld in words).  work: squaring_work_bytes(es, D) bytes.
 hipError_t closure_by_squaring(int es, bool s8, void *T, int64_t ld, int64_t D, void *work,
                                hipStream_t st) {
     const int64_t lw = es == 8 ? round_up((D + 63) / 64, 2) : round_up(D, 64);
@@ -363,11 +364,36 @@ hipError_t closure_by_squaring(int es, bool s8, void *T, int64_t ld, int64_t D, 
     };
     int j = 0;
     while ((int64_t(1) << j) < D - 1) j++;
-    for (int i = 0; i < j && e == hipSuccess; i++) {
-        e = mul(Q, P, lw, P);
-        std::swap(P, Q);
+    if (es == 8) {
+        for (int i = 0; i < j && e == hipSuccess; i++) {
+            e = mul(Q, P, lw, P);
+            std::swap(P, Q);
+        }
+        if (e == hipSuccess) e = mul(Q, T, ld, P);
+    } else {
+        // Early exit on the device: changed[i] is set when squaring i changed
+        // P, and squaring i + 1 (and its check) runs only if it was.  Once a
+        // squaring leaves P unchanged, P is idempotent and every later power
+        // equals it; the skipped squarings leave both buffers holding it, so
+        // A * P below is the closure either way.  The host enqueues all j
+        // squarings and never waits.
+        int *changed = reinterpret_cast<int *>(static_cast<char *>(work) + 2 * D * lw * es);
+        if (e == hipSuccess) e = hipMemsetAsync(changed, 0, (size_t)j * sizeof(int), st);
+        for (int i = 0; i < j && e == hipSuccess; i++) {
+            const int *gate = i == 0 ? nullptr : changed + i - 1;
+            e = es == 4 ? sr::launch_ad32_mul(reinterpret_cast<uint32_t *>(Q), lw,
+                                              reinterpret_cast<const uint32_t *>(P), lw,
+                                              reinterpret_cast<const uint32_t *>(P), lw, D, D, D,
+                                              false, st, -1, gate)
+                        : sr::launch_ad_mul(s8, reinterpret_cast<uint16_t *>(Q), lw,
+                                            reinterpret_cast<const uint16_t *>(P), lw,
+                                            reinterpret_cast<const uint16_t *>(P), lw, D, D, D,
+                                            false, st, -1, gate);
+            if (e == hipSuccess) e = sr::launch_changed(es, P, Q, lw, D, D, gate, changed + i, st);
+            std::swap(P, Q);
+        }
+        if (e == hipSuccess) e = mul(Q, T, ld, P);
     }
-    if (e == hipSuccess) e = mul(Q, T, ld, P);
     if (e == hipSuccess)
         e = hipMemcpy2DAsync(T, ld * es, Q, lw * es, row_bytes, D, hipMemcpyDeviceToDevice, st);
     return e;
@@ -422,7 +448,7 @@ hipError_t closure_big_blocks(int es, bool s8, void *T, int64_t ld, int64_t D, i
 
 size_t squaring_work_bytes(int es, int64_t D) {
     const int64_t lw = es == 8 ? round_up((D + 63) / 64, 2) : round_up(D, 64);
-    return (size_t)(2 * D * lw * es);
+    return (size_t)(2 * D * lw * es) + 256;  // P, Q, then the changed[] flags (j <= 64)
 }
 
 // Validation shared by semiring_add and semiring_ewise (B unused for NOT).

@@ -660,6 +660,54 @@ def test_closure_methods(kind, D, method):
     assert np.array_equal(got2, oracle.reflexive(want, one))
 
 
+def _squaring_input(case, kind, D, gen):
+    """Inputs whose repeated squaring stops early or late: 'dense' (every
+    edge, one weight: the first squaring leaves P unchanged), 'path' (a
+    directed path 0 -> 1 -> ... of small weights plus random heavier edges
+    from higher to lower vertices: best paths of D - 1 edges, so no squaring
+    is skipped), 'random' (configuration 2's generator: stops part way)."""
+    S = S_OF[kind]
+    if case == "dense":
+        A = np.full((D, D), S - 3, dtype=np.int64)
+        np.fill_diagonal(A, 0)
+    elif case == "path":
+        A = np.zeros((D, D), dtype=np.int64)
+        for i in range(D - 1):
+            A[i, i + 1] = S - 1
+        back = gen.integers(0, D, size=(D, 2))
+        for a, b in back:
+            if a > b:
+                A[a, b] = S - int(gen.integers(2, 50))
+    elif kind == sr.SR_ANTIDIST_U8:
+        A = synthgen.cfg_antidist_u8(D=D)[:, :D].astype(np.int64)
+    else:
+        # uint32: the same distances, entries S - w
+        A = synthgen.cfg_antidist(D=D)[:, :D].astype(np.int64)
+        A = np.where(A > 0, A + (S - 65535), 0)
+    return A.astype(np_dtype(kind))
+
+
+@pytest.mark.parametrize("kind", [sr.SR_ANTIDIST_U16, sr.SR_ANTIDIST_U8, sr.SR_ANTIDIST_U32,
+                                  sr.SR_DISTANCE_U16])
+@pytest.mark.parametrize("case", ["dense", "path", "random"])
+def test_squaring_early_exit(kind, case):
+    """The squaring closure skips, on the device, the squarings after one
+    that left P unchanged; the result is the closure whether that happens
+    after the first squaring, part way or never."""
+    D = 700 if case == "path" else 1024
+    gen = synthgen.generator(4242 + kind)
+    S = S_OF[kind]
+    A = _squaring_input(case, kind, D, gen)
+    if kind == sr.SR_DISTANCE_U16:
+        A = (S - A.astype(np.int64)).astype(np_dtype(kind))
+        want = oracle.dist_closure(A, S)
+    else:
+        want = oracle.ad_closure(A, S)
+    T = sr.to_device(kind, A)
+    sr.closure(kind, T, D=D, flags=sr.SR_CLOSURE_SQUARING)
+    assert np.array_equal(host(T).astype(np.int64), want)
+
+
 @pytest.mark.parametrize("kind", [sr.SR_ANTIDIST_U16, sr.SR_ANTIDIST_U8, sr.SR_DISTANCE_U16,
                                   sr.SR_ANTIDIST_U32])
 @pytest.mark.parametrize("D", [1100, 1537, 2100])
