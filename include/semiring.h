@@ -177,9 +177,12 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
  * 32-bit kinds), where the loop's chain of D sequential pivot steps costs more
  * than the squarings' extra products; from there up to D = 2560 (8- and
  * 16-bit kinds) the loop runs in blocks of 512 pivots, each pivot block closed
- * by squaring and the panels and update done as products.  Both allocate
- * stream-ordered working memory (two matrices of the squared size) and are
- * not taken while `stream` is being captured, nor with SR_SERIAL_PHASES.
+ * by squaring and the panels and update done as products.  For the
+ * anti-distance and distance kinds the squarings stop early, on the device
+ * and without a host wait, once one leaves the power unchanged (it is then
+ * idempotent, so every later power equals it).  Both allocate stream-ordered
+ * working memory (two matrices of the squared size) and are not taken while
+ * `stream` is being captured, nor with SR_SERIAL_PHASES.
  * By default a blocked closure with more than two pivot blocks forks onto a second,
  * library-owned stream of default priority (the next round's pivot and panels
  * overlap the bulk of the current update) and joins back into `stream`
@@ -272,8 +275,10 @@ void sr_batch_destroy(sr_batch *batch);
  * methods that give identical results).  sr_autotune_closure times each
  * closure method that applies to (kind, D) -- the blocked loop (for Boolean:
  * with the bit-sliced and with the four-Russians update), big pivot blocks,
- * repeated squaring -- on a zero matrix of that shape (the kernels' runtimes
- * do not depend on the entries), once to warm up and twice more, keeps the
+ * repeated squaring -- on a directed path through all D vertices (the
+ * squaring's worst case: it stops early once a squaring changes nothing,
+ * while the other methods' runtimes do not depend on the entries; Boolean:
+ * a zero matrix), once to warm up and twice more, keeps the
  * fastest for the size class of D (the sizes in (2^(c-1), 2^c]) on the current
  * device, and returns its flags in *chosen (may be NULL).  closure() without a
  * method flag then uses it for every D of that class.  sr_autotune_mul does

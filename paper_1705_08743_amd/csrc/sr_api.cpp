@@ -764,7 +764,11 @@ int sr_autotune_closure(int kind, int64_t D, unsigned *chosen, void *stream) {
     if (capturing(st))
         return fail(SR_EUNSUPPORTED, "sr_autotune_closure: the stream is being captured");
     const int ak = base_kind(kind);
-    // a zero matrix of the shape: the runtimes do not depend on the entries
+    // The loop's and the big blocks' runtimes do not depend on the entries;
+    // the squaring stops once a squaring changes nothing (except for
+    // Boolean), so every candidate runs on the worst case for that stop: a
+    // directed path 0 -> 1 -> ... -> D-1 of distance-1 edges, whose best
+    // paths use all D - 1 edges (a Boolean matrix stays zero).
     const int64_t ld = ak == SR_BOOL ? round_up((D + 63) / 64, 2) : round_up(D, 64);
     const size_t bytes = (size_t)(D * ld * unit_bytes(kind));
     std::vector<unsigned> cands;
@@ -782,10 +786,18 @@ int sr_autotune_closure(int kind, int64_t D, unsigned *chosen, void *stream) {
     if (rc != SR_OK) return rc;
     unsigned pick = 0;
     float best = 0.0f;
+    const int es = (int)unit_bytes(kind);
+    const uint32_t edge = is_dist(kind) ? 1u : (es == 1 ? 254u : (es == 2 ? 65534u : 0xFFFFFFFEu));
+    auto path = [&]() -> hipError_t {
+        // absent edges: 0 (anti-distance, Boolean) or S, all bits set (distance)
+        hipError_t e = hipMemsetAsync(T, is_dist(kind) ? 0xFF : 0, bytes, st);
+        if (e == hipSuccess && ak != SR_BOOL && D > 1)
+            e = sr::launch_diag(es, static_cast<char *>(T) + es, ld, D - 1, edge, st);
+        return e;
+    };
     for (unsigned c : cands) {
-        const float ms = time_candidate(
-            st, ev.a, ev.b, 2, [&] { return hipMemsetAsync(T, 0, bytes, st); },
-            [&] { return closure(kind, T, ld, D, c, stream); });
+        const float ms = time_candidate(st, ev.a, ev.b, 2, path,
+                                        [&] { return closure(kind, T, ld, D, c, stream); });
         if (ms >= 0.0f && (!pick || ms < best)) {
             pick = c;
             best = ms;
