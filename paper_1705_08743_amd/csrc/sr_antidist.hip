@@ -53,7 +53,7 @@ template <int TM, int NW, bool S8, bool FULL>
 __global__ void __launch_bounds__(256)
 k_ad_mul(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
          int64_t ldb, int64_t R, int K, int64_t N, int64_t col_base, int accumulate,
-         int64_t bmax, const int *gate) {
+         int64_t bmax, const int *gate, const uint16_t *prev, int *flag) {
     constexpr int CW = 2 * NW, RW = 64 * TM;
     if (gate && *gate == 0) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
@@ -61,13 +61,27 @@ k_ad_mul(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_
     const int64_t col0 = col_base + (int64_t)blockIdx.x * CW;
     if (row0 >= R) return;
     const int nrows = (int)min<int64_t>(RW, R - row0);
+    const int ncols = FULL ? CW : (int)min<int64_t>(CW, N - col0);
     if (FULL) {
         wave_tile_body<TM, NW, S8, true>(C + row0 * ldc + col0, ldc, A + row0 * lda, lda,
                                          B + col0, ldb, nrows, CW, K, accumulate != 0, false);
     } else {
-        const int ncols = (int)min<int64_t>(CW, N - col0);
         wave_tile<TM, NW, S8>(C + row0 * ldc + col0, ldc, A + row0 * lda, lda, B + col0, ldb,
                               nrows, ncols, bmax - col0, K, accumulate != 0, false);
+    }
+    if (prev) {
+        // change check: this lane's rows of the tile just stored, read back,
+        // against the same entries of prev (same layout as C)
+        const int lane = threadIdx.x & 63;
+        bool diff = false;
+        for (int t = 0; t < TM; t++) {
+            const int r = lane + 64 * t;
+            if (r >= nrows) break;
+            const uint16_t *c = C + (row0 + r) * ldc + col0;
+            const uint16_t *p = prev + (row0 + r) * ldc + col0;
+            for (int j = 0; j < ncols; j++) diff |= c[j] != p[j];
+        }
+        if (__any(diff) && lane == 0) *flag = 1;
     }
 }
 
@@ -83,7 +97,8 @@ k_ad_mul(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_
 template <int NW, int KS, bool S8>
 __global__ void __launch_bounds__(64 * KS)
 k_ad_mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
-                int64_t ldb, int64_t R, int K, int kq, int accumulate, const int *gate) {
+                int64_t ldb, int64_t R, int K, int kq, int accumulate, const int *gate,
+                const uint16_t *prev, int *flag) {
     __shared__ uint4 part[KS][64][NW / 4];
     if (gate && *gate == 0) return;  // (uniform over the workgroup: before any barrier)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
@@ -96,7 +111,9 @@ k_ad_mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const 
                                     A + row0 * lda + k0, lda, B + (int64_t)k0 * ldb + col0, ldb,
                                     nrows, 2 * NW, k1 - k0, false, false);
     __syncthreads();
-    // (+) of the partials, one 32-bit word (two entries) per thread and pass
+    // (+) of the partials, one 32-bit word (two entries) per thread and pass;
+    // with prev, each word is also compared with the same word of prev
+    bool diff = false;
     for (int wi = threadIdx.x; wi < 64 * NW; wi += 64 * KS) {
         const int row = wi / NW, word = wi % NW;
         if (row >= nrows) continue;
@@ -108,7 +125,11 @@ k_ad_mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const 
         uint32_t *dst = reinterpret_cast<uint32_t *>(C + (row0 + row) * ldc + col0) + word;
         if (accumulate) v = __builtin_elementwise_max(v, dev::as_pair(*dst));
         *dst = dev::as_word(v);
+        if (prev)
+            diff |= dev::as_word(v) !=
+                    reinterpret_cast<const uint32_t *>(prev + (row0 + row) * ldc + col0)[word];
     }
+    if (prev && __any(diff) && (threadIdx.x & 63) == 0) *flag = 1;
 }
 
 template <bool S8>
@@ -256,6 +277,10 @@ k_narrow(uint8_t *dst, int64_t ldd, const uint16_t *src, int64_t lds, int64_t R,
 struct Shape {
     int tm, nw;
 };
+template <int TM, int NW>
+struct ShapeT {
+    static constexpr int tm = TM, nw = NW;
+};
 
 Shape pick_mul_shape(int64_t R, int64_t N) {
     const Shape cand[] = {{2, 32}, {1, 32}, {1, 16}, {1, 8}};
@@ -269,14 +294,14 @@ Shape pick_mul_shape(int64_t R, int64_t N) {
 template <int TM, int NW, bool S8>
 hipError_t mul_shape(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
                      int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, int64_t bmax,
-                     const int *gate, hipStream_t st) {
+                     const int *gate, const uint16_t *prev, int *flag, hipStream_t st) {
     constexpr int CW = 2 * NW;
     const unsigned gy = (unsigned)((R + 256 * TM - 1) / (256 * TM));
     const int64_t nfull = N / CW;
     if (nfull > 0) {
         hipLaunchKernelGGL((k_ad_mul<TM, NW, S8, true>), dim3((unsigned)nfull, gy), dim3(256), 0,
                            st, C, ldc, A, lda, B, ldb, R, (int)K, N, (int64_t)0, acc ? 1 : 0,
-                           bmax, gate);
+                           bmax, gate, prev, flag);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -286,7 +311,7 @@ hipError_t mul_shape(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, c
         const unsigned gx = (unsigned)((N - c0 + 15) / 16);
         hipLaunchKernelGGL((k_ad_mul<1, 8, S8, false>), dim3(gx, (unsigned)((R + 255) / 256)),
                            dim3(256), 0, st, C, ldc, A, lda, B, ldb, R, (int)K, N, c0,
-                           acc ? 1 : 0, bmax, gate);
+                           acc ? 1 : 0, bmax, gate, prev, flag);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -299,14 +324,16 @@ hipError_t mul_shape(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, c
 template <bool S8>
 hipError_t mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
                       const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc,
-                      int64_t bmax, const int *gate, hipStream_t st) {
+                      int64_t bmax, const int *gate, const uint16_t *prev, int *flag,
+                      hipStream_t st) {
     constexpr int NW = 8, CW = 2 * NW, KS = 8;
     const int64_t nfull = N / CW;
     const int kq = (int)((K + KS * 32 - 1) / (KS * 32) * 32);
     if (nfull > 0) {
         hipLaunchKernelGGL((k_ad_mul_ksplit<NW, KS, S8>),
                            dim3((unsigned)nfull, (unsigned)((R + 63) / 64)), dim3(64 * KS), 0, st,
-                           C, ldc, A, lda, B, ldb, R, (int)K, kq, acc ? 1 : 0, gate);
+                           C, ldc, A, lda, B, ldb, R, (int)K, kq, acc ? 1 : 0, gate, prev,
+                           flag);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -314,7 +341,7 @@ hipError_t mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
         const int64_t c0 = nfull * CW;
         hipLaunchKernelGGL((k_ad_mul<1, 8, S8, false>), dim3(1u, (unsigned)((R + 255) / 256)),
                            dim3(256), 0, st, C, ldc, A, lda, B, ldb, R, (int)K, N, c0,
-                           acc ? 1 : 0, bmax, gate);
+                           acc ? 1 : 0, bmax, gate, prev, flag);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -323,20 +350,21 @@ hipError_t mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
 template <bool S8>
 hipError_t mul_s(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
                  int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, int64_t bmax,
-                 const int *gate, hipStream_t st) {
+                 const int *gate, const uint16_t *prev, int *flag, hipStream_t st) {
     const int64_t tiles16 = ((R + 63) / 64) * (N / 16);
     if (tiles16 > 0 && tiles16 <= 2048 && K >= 256)
-        return mul_ksplit<S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, st);
+        return mul_ksplit<S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, prev, flag, st);
     const Shape s = pick_mul_shape(R, N);
-    if (s.tm == 2)
-        return mul_shape<2, 32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, st);
+    auto run = [&](auto shape) {
+        constexpr int TM = decltype(shape)::tm, NW = decltype(shape)::nw;
+        return mul_shape<TM, NW, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, prev, flag,
+                                     st);
+    };
+    if (s.tm == 2) return run(ShapeT<2, 32>{});
     switch (s.nw) {
-        case 32:
-            return mul_shape<1, 32, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, st);
-        case 16:
-            return mul_shape<1, 16, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, st);
-        default:
-            return mul_shape<1, 8, S8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, st);
+        case 32: return run(ShapeT<1, 32>{});
+        case 16: return run(ShapeT<1, 16>{});
+        default: return run(ShapeT<1, 8>{});
     }
 }
 
@@ -655,10 +683,13 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
 hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
                          const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                          bool accumulate, hipStream_t stream, int64_t bspan,
-                         const int *gate) {
+                         const int *gate, const uint16_t *prev, int *flag) {
     const int64_t bmax = bspan >= 0 ? bspan : ldb;
-    return s8 ? mul_s<true>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, stream)
-              : mul_s<false>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, stream);
+    if (!flag) prev = nullptr;
+    return s8 ? mul_s<true>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, prev, flag,
+                            stream)
+              : mul_s<false>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, prev, flag,
+                             stream);
 }
 
 hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, bool serial,

@@ -186,19 +186,32 @@ template <int CW, bool FULL>
 __global__ void __launch_bounds__(256)
 k_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
            int64_t ldb, int64_t R, int K, int64_t N, int64_t col_base, int accumulate,
-           int64_t bmax, const int *gate) {
+           int64_t bmax, const int *gate, const uint32_t *prev, int *flag) {
     if (gate && *gate == 0) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t row0 = ((int64_t)blockIdx.y * 4 + wave) * kRW;
     const int64_t col0 = col_base + (int64_t)blockIdx.x * CW;
     if (row0 >= R) return;
     const int nrows = (int)min<int64_t>(kRW, R - row0);
+    const int ncols = FULL ? CW : (int)min<int64_t>(CW, N - col0);
     if (FULL)
         tile32_body<CW, true>(C + row0 * ldc + col0, ldc, A + row0 * lda, lda, B + col0, ldb,
                               nrows, CW, K, accumulate != 0, false);
     else
-        tile32<CW>(C + row0 * ldc + col0, ldc, A + row0 * lda, lda, B + col0, ldb, nrows,
-                   (int)min<int64_t>(CW, N - col0), bmax - col0, K, accumulate != 0, false);
+        tile32<CW>(C + row0 * ldc + col0, ldc, A + row0 * lda, lda, B + col0, ldb, nrows, ncols,
+                   bmax - col0, K, accumulate != 0, false);
+    if (prev) {
+        // change check: this lane's row of the tile just stored, read back,
+        // against the same entries of prev (same layout as C)
+        const int lane = threadIdx.x & 63;
+        bool diff = false;
+        if (lane < nrows) {
+            const uint32_t *c = C + (row0 + lane) * ldc + col0;
+            const uint32_t *p = prev + (row0 + lane) * ldc + col0;
+            for (int j = 0; j < ncols; j++) diff |= c[j] != p[j];
+        }
+        if (__any(diff) && lane == 0) *flag = 1;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -357,19 +370,20 @@ k_ad32_update(uint32_t *T, int64_t ld, int D, int k0, int bs, Rect q, int prio) 
 template <int CW>
 hipError_t mul_cw(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
                   int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, int64_t bmax,
-                  const int *gate, hipStream_t st) {
+                  const int *gate, const uint32_t *prev, int *flag, hipStream_t st) {
     const unsigned gy = (unsigned)((R + 4 * kRW - 1) / (4 * kRW));
     const int64_t nfull = N / CW;
     if (nfull > 0) {
         hipLaunchKernelGGL((k_ad32_mul<CW, true>), dim3((unsigned)nfull, gy), dim3(256), 0, st, C,
                            ldc, A, lda, B, ldb, R, (int)K, N, (int64_t)0, acc ? 1 : 0, bmax,
-                           gate);
+                           gate, prev, flag);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (N % CW) {
         hipLaunchKernelGGL((k_ad32_mul<CW, false>), dim3(1u, gy), dim3(256), 0, st, C, ldc, A, lda,
-                           B, ldb, R, (int)K, N, nfull * CW, acc ? 1 : 0, bmax, gate);
+                           B, ldb, R, (int)K, N, nfull * CW, acc ? 1 : 0, bmax, gate, prev,
+                           flag);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -540,13 +554,15 @@ hipError_t closure32(uint32_t *T, int64_t ld, int64_t D, bool serial, hipStream_
 hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda,
                            const uint32_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                            bool accumulate, hipStream_t stream, int64_t bspan,
-                           const int *gate) {
+                           const int *gate, const uint32_t *prev, int *flag) {
     const int64_t bmax = bspan >= 0 ? bspan : ldb;
+    if (!flag) prev = nullptr;
     // 16-column tiles when 32-column ones would leave the chip short of waves
     const int64_t waves32 = ((R + kRW - 1) / kRW) * ((N + 31) / 32);
     if (waves32 >= 8192)
-        return mul_cw<32>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, stream);
-    return mul_cw<16>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, stream);
+        return mul_cw<32>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, prev, flag,
+                          stream);
+    return mul_cw<16>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, prev, flag, stream);
 }
 
 hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, bool serial,

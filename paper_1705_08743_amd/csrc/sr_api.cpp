@@ -348,19 +348,12 @@ hipError_t closure_by_squaring(int es, bool s8, void *T, int64_t ld, int64_t D, 
     // I (+) A: the diagonal becomes the multiplicative one (S, or bit set)
     const uint32_t one = es == 4 ? 0xFFFFFFFFu : (es == 8 ? 1u : (s8 ? 0x5BF8u : 0xFFFFu));
     if (e == hipSuccess) e = sr::launch_diag(es, P, lw, D, one, st);
+    // Boolean products (every squaring runs: the bit-sliced kernels take no gate)
     auto mul = [&](void *C, const void *A, int64_t lda, const void *B) {
-        if (es == 8)
-            return sr::launch_bool_mul(static_cast<uint64_t *>(C), lw,
-                                       static_cast<const uint64_t *>(A), lda,
-                                       static_cast<const uint64_t *>(B), lw, D, D, D, false,
-                                       sr::kBoolPathAuto, st);
-        if (es == 4)
-            return sr::launch_ad32_mul(static_cast<uint32_t *>(C), lw,
-                                       static_cast<const uint32_t *>(A), lda,
-                                       static_cast<const uint32_t *>(B), lw, D, D, D, false, st);
-        return sr::launch_ad_mul(s8, static_cast<uint16_t *>(C), lw,
-                                 static_cast<const uint16_t *>(A), lda,
-                                 static_cast<const uint16_t *>(B), lw, D, D, D, false, st);
+        return sr::launch_bool_mul(static_cast<uint64_t *>(C), lw,
+                                   static_cast<const uint64_t *>(A), lda,
+                                   static_cast<const uint64_t *>(B), lw, D, D, D, false,
+                                   sr::kBoolPathAuto, st);
     };
     int j = 0;
     while ((int64_t(1) << j) < D - 1) j++;
@@ -370,33 +363,42 @@ hipError_t closure_by_squaring(int es, bool s8, void *T, int64_t ld, int64_t D, 
             std::swap(P, Q);
         }
         if (e == hipSuccess) e = mul(Q, T, ld, P);
-    } else {
-        // Early exit on the device: changed[i] is set when squaring i changed
-        // P, and squaring i + 1 (and its check) runs only if it was.  Once a
-        // squaring leaves P unchanged, P is idempotent and every later power
-        // equals it; the skipped squarings leave both buffers holding it, so
-        // A * P below is the closure either way.  The host enqueues all j
-        // squarings and never waits.
-        int *changed = reinterpret_cast<int *>(static_cast<char *>(work) + 2 * D * lw * es);
-        if (e == hipSuccess) e = hipMemsetAsync(changed, 0, (size_t)j * sizeof(int), st);
-        for (int i = 0; i < j && e == hipSuccess; i++) {
-            const int *gate = i == 0 ? nullptr : changed + i - 1;
-            e = es == 4 ? sr::launch_ad32_mul(reinterpret_cast<uint32_t *>(Q), lw,
-                                              reinterpret_cast<const uint32_t *>(P), lw,
-                                              reinterpret_cast<const uint32_t *>(P), lw, D, D, D,
-                                              false, st, -1, gate)
-                        : sr::launch_ad_mul(s8, reinterpret_cast<uint16_t *>(Q), lw,
-                                            reinterpret_cast<const uint16_t *>(P), lw,
-                                            reinterpret_cast<const uint16_t *>(P), lw, D, D, D,
-                                            false, st, -1, gate);
-            if (e == hipSuccess) e = sr::launch_changed(es, P, Q, lw, D, D, gate, changed + i, st);
-            std::swap(P, Q);
-        }
-        if (e == hipSuccess) e = mul(Q, T, ld, P);
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(T, ld * es, Q, lw * es, row_bytes, D, hipMemcpyDeviceToDevice,
+                                 st);
+        return e;
     }
-    if (e == hipSuccess)
-        e = hipMemcpy2DAsync(T, ld * es, Q, lw * es, row_bytes, D, hipMemcpyDeviceToDevice, st);
-    return e;
+    // Early exit on the device: squaring i compares each entry it stores
+    // with P's and sets changed[i] if any differs; squaring i + 1 runs only if
+    // that was set.  Once a squaring leaves P unchanged, P is idempotent and
+    // every later power equals it; the skipped squarings leave both buffers
+    // holding it, so T * P below is the closure either way.  The host
+    // enqueues all j squarings and never waits.
+    int *changed = reinterpret_cast<int *>(static_cast<char *>(work) + 2 * D * lw * es);
+    if (e == hipSuccess) e = hipMemsetAsync(changed, 0, (size_t)j * sizeof(int), st);
+    for (int i = 0; i < j && e == hipSuccess; i++) {
+        const int *gate = i == 0 ? nullptr : changed + i - 1;
+        if (es == 4) {
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(P);
+            e = sr::launch_ad32_mul(reinterpret_cast<uint32_t *>(Q), lw, p, lw, p, lw, D, D, D,
+                                    false, st, -1, gate, p, changed + i);
+        } else {
+            const uint16_t *p = reinterpret_cast<const uint16_t *>(P);
+            e = sr::launch_ad_mul(s8, reinterpret_cast<uint16_t *>(Q), lw, p, lw, p, lw, D, D, D,
+                                  false, st, -1, gate, p, changed + i);
+        }
+        std::swap(P, Q);
+    }
+    // T := T * P in place: P is closed (P * P = P, P >= I), so any mix of old
+    // and new entries of T that the product's waves read gives the same
+    // T * P (T <= mix <= T * P, and (T * P) * P = T * P)
+    if (e != hipSuccess) return e;
+    if (es == 4)
+        return sr::launch_ad32_mul(static_cast<uint32_t *>(T), ld, static_cast<const uint32_t *>(T),
+                                   ld, reinterpret_cast<const uint32_t *>(P), lw, D, D, D, false,
+                                   st);
+    return sr::launch_ad_mul(s8, static_cast<uint16_t *>(T), ld, static_cast<const uint16_t *>(T),
+                             ld, reinterpret_cast<const uint16_t *>(P), lw, D, D, D, false, st);
 }
 
 // Blocked closure with large pivot blocks (Sec. II / Sec. III Warshall loop

@@ -8,8 +8,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <algorithm>
-
 #include "sr_internal.h"
 
 namespace sr {
@@ -124,50 +122,7 @@ __global__ void __launch_bounds__(256) k_diag(uint8_t *T, int64_t ldb, int64_t D
         reinterpret_cast<uint32_t *>(row)[i >> 5] |= 1u << (i & 31);
 }
 
-// Change detection for the repeated-squaring closure: *flag := 1 when P and
-// Q differ in rows [0, R), bytes [0, row_bytes) of each row (rows 16-byte
-// aligned, ldb bytes apart, readable to the next 16-byte boundary).  One
-// thread per 16-byte group; the bytes of a row's last group past row_bytes
-// are masked off.  A launch gated off (*gate == 0) reads nothing.
-__global__ void __launch_bounds__(256)
-k_changed(const uint8_t *P, const uint8_t *Q, int64_t ldb, int64_t R, int64_t row_bytes,
-          const int *gate, int *flag) {
-    if (gate && *gate == 0) return;
-    const int64_t groups = (row_bytes + 15) / 16;
-    bool diff = false;
-    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < R * groups;
-         g += (int64_t)gridDim.x * 256) {
-        const int64_t r = g / groups, c = (g % groups) * 16;
-        const uint4 a = *reinterpret_cast<const uint4 *>(P + r * ldb + c);
-        const uint4 b = *reinterpret_cast<const uint4 *>(Q + r * ldb + c);
-        uint32_t x[4] = {a.x ^ b.x, a.y ^ b.y, a.z ^ b.z, a.w ^ b.w};
-        const int64_t valid = row_bytes - c;  // bytes of the group inside the row
-#pragma unroll
-        for (int w = 0; w < 4; w++) {
-            const int64_t v = valid - 4 * w;
-            if (v <= 0)
-                x[w] = 0;
-            else if (v < 4)
-                x[w] &= (1u << (8 * v)) - 1u;
-        }
-        diff |= (x[0] | x[1] | x[2] | x[3]) != 0;
-    }
-    // one store per wavefront that saw a difference
-    if (__any(diff) && (threadIdx.x & 63) == 0) *flag = 1;
-}
-
 }  // namespace
-
-hipError_t launch_changed(int elem_bytes, const void *P, const void *Q, int64_t ld, int64_t R,
-                          int64_t N, const int *gate, int *flag, hipStream_t stream) {
-    const int64_t row_bytes = N * elem_bytes, groups = (row_bytes + 15) / 16;
-    if (R <= 0 || groups <= 0) return hipSuccess;
-    const int64_t blocks = std::min<int64_t>((R * groups + 255) / 256, 2048);
-    hipLaunchKernelGGL(k_changed, dim3((unsigned)blocks), dim3(256), 0, stream,
-                       static_cast<const uint8_t *>(P), static_cast<const uint8_t *>(Q),
-                       ld * elem_bytes, R, row_bytes, gate, flag);
-    return hipGetLastError();
-}
 
 hipError_t launch_ewise(int elem_bytes, int op, void *C, int64_t ldc, const void *A, int64_t lda,
                         const void *B, int64_t ldb, int64_t R, int64_t N, int64_t nbits,

@@ -26,11 +26,14 @@ constexpr int kBoolBlock = 256;
 // B row readable from B (default: ldb; smaller when B is a block inside a
 // wider matrix whose rows end before B's row stride does).  gate: a device
 // int read by every workgroup at its start; 0 there makes the whole launch a
-// no-op (nullptr: always run).
+// no-op (nullptr: always run).  prev, flag: when flag is given, every stored
+// entry of C is compared with the entry at the same place in prev (same
+// layout as C) and *flag is set to 1 if any differs (never cleared).
 hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
                          const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                          bool accumulate, hipStream_t stream, int64_t bspan = -1,
-                         const int *gate = nullptr);
+                         const int *gate = nullptr, const uint16_t *prev = nullptr,
+                         int *flag = nullptr);
 
 // In-place closure of the D x D matrix T (16-bit storage).  serial: no
 // second stream (every phase in order on `stream`).
@@ -43,7 +46,8 @@ hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, bool s
 hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda,
                            const uint32_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                            bool accumulate, hipStream_t stream, int64_t bspan = -1,
-                           const int *gate = nullptr);
+                           const int *gate = nullptr, const uint32_t *prev = nullptr,
+                           int *flag = nullptr);
 hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, bool serial,
                                hipStream_t stream);
 
@@ -100,11 +104,6 @@ hipError_t launch_ewise(int elem_bytes, int op, void *C, int64_t ldc, const void
 // Entrywise (+) (EW_OR).
 hipError_t launch_add(int elem_bytes, void *C, int64_t ldc, const void *A, int64_t lda,
                       const void *B, int64_t ldb, int64_t R, int64_t N, hipStream_t stream);
-// *flag := 1 when rows [0, R) of P and Q (row stride ld elements of
-// elem_bytes 2 or 4, 16-byte aligned rows) differ in a column < N; nothing is
-// written otherwise, and nothing is read when gate is given and *gate == 0.
-hipError_t launch_changed(int elem_bytes, const void *P, const void *Q, int64_t ld, int64_t R,
-                          int64_t N, const int *gate, int *flag, hipStream_t stream);
 // Diagonal of a D x D matrix: entries := value (elem_bytes 1, 2, 4), or bit i of
 // row i set (8).
 hipError_t launch_diag(int elem_bytes, void *T, int64_t ld, int64_t D, uint32_t value,
