@@ -200,7 +200,7 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
  * closure_batched -- `count` independent in-place closures, as closure()
  * applied to each (T[g], ldt[g], D[g]).  The three arrays are HOST arrays of
  * length count; T[g] are device pointers, each obeying the alignment rules
- * above.  8- and 16-bit anti-distance and distance kinds (Boolean and the
+ * above.  Boolean and 8- and 16-bit anti-distance and distance kinds (the
  * 32-bit kinds return SR_EUNSUPPORTED); flags: SR_REFLEXIVE.  The
  * matrices must not overlap each other (SR_EALIAS), D[g] <= 65536.  The
  * batch runs the blocked Floyd-Warshall of closure() round-synchronously: per
@@ -209,7 +209,14 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
  * vertices is closed by the first pivot launch.  The descriptors and the
  * per-round work lists are built on the host and uploaded stream-ordered
  * (the call returns without waiting); uint8 batches use stream-ordered
- * 16-bit working copies (binary16 values).  The rounds are three launches
+ * 16-bit working copies (binary16 values).  Boolean batches are closed as
+ * anti-distance matrices with S = 255 whose entries are 255 for a set bit
+ * and 0 otherwise (Sec. III: a set bit stands for distance 0, the entry S,
+ * a clear one for distance infinity, the entry 0, and with S = 1 the
+ * anti-distance matrices are the Boolean ones; on {0, S} entries max and (x)
+ * act as OR and AND), in the same binary16 working copies, 2 * D[g] *
+ * round_up(D[g], 8) bytes per graph; bits past column D[g] - 1 must be zero
+ * and stay so.  The rounds are three launches
  * each, which is what synchronizes the whole grid between phases.  The
  * update tiles are 64 x 32 entries unless sr_batch_autotune chose another
  * shape for batches of this class.  For a graph-captured form see the

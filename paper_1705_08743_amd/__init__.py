@@ -268,9 +268,10 @@ def closure_batched(kind, Ts, Ds=None, flags=0, stream=None):
 
 
 class BatchArena:
-    """A batch of square anti-distance matrices back to back in one device
-    buffer: matrix i (sizes[i] vertices) starts at a 256-byte aligned offset
-    and has a row stride of padded_ld(sizes[i]).  The pointer, stride and size
+    """A batch of square matrices back to back in one device buffer: matrix i
+    (sizes[i] vertices) starts at a 256-byte aligned offset and has a row
+    stride of padded_ld(sizes[i]) entries (Boolean: ceil(sizes[i] / 64)
+    64-bit words rounded up to an even count).  The pointer, stride and size
     arrays that closure_batched passes to the C ABI are built once here, with
     numpy, so repeated calls on the same batch do no per-matrix marshalling.
     The arena owns its buffer (``self.buf``, a flat uint8 tensor): the
@@ -279,17 +280,22 @@ class BatchArena:
     def __init__(self, kind, sizes, device="cuda", zero=True):
         import numpy as np
         torch = _torch()
-        if kind not in _U8_KINDS + _U16_KINDS:
-            raise ValueError("BatchArena holds 8- or 16-bit anti-distance or distance matrices")
+        if kind not in _U8_KINDS + _U16_KINDS + (SR_BOOL,):
+            raise ValueError("BatchArena holds Boolean or 8- or 16-bit anti-distance or "
+                             "distance matrices")
         self.kind = kind
-        self.es = 1 if kind in _U8_KINDS else 2
-        self.dtype = torch.uint8 if kind in _U8_KINDS else torch.uint16
+        self.es = {SR_BOOL: 8}.get(kind, 1 if kind in _U8_KINDS else 2)
+        self.dtype = {1: torch.uint8, 2: torch.uint16, 8: torch.int64}[self.es]
         self.sizes = np.asarray(sizes, dtype=np.int64).reshape(-1)
         if (self.sizes < 0).any():
             raise ValueError("negative matrix size")
         self.count = int(self.sizes.size)
-        per = 128 // self.es
-        self.lds = np.maximum(per, -(-self.sizes // per) * per).astype(np.int64)
+        if kind == SR_BOOL:
+            # words per row, even (16-byte rows)
+            self.lds = np.maximum(2, -(-(-(-self.sizes // 64)) // 2) * 2).astype(np.int64)
+        else:
+            per = 128 // self.es
+            self.lds = np.maximum(per, -(-self.sizes // per) * per).astype(np.int64)
         nbytes = -(-(self.sizes * self.lds * self.es) // 256) * 256
         self.offsets = np.zeros(self.count, dtype=np.int64)
         if self.count > 1:
@@ -306,24 +312,30 @@ class BatchArena:
     def __len__(self):
         return self.count
 
+    def _width(self, n):
+        """Stored units of a row of an n-vertex matrix (entries, or words)."""
+        return -(-n // 64) if self.kind == SR_BOOL else n
+
     def view(self, i):
-        """Matrix i as a sizes[i] x sizes[i] tensor view (row stride lds[i])."""
+        """Matrix i as a tensor view of sizes[i] rows (row stride lds[i]):
+        sizes[i] entries per row, or ceil(sizes[i] / 64) int64 words."""
         n, ld, off = int(self.sizes[i]), int(self.lds[i]), int(self.offsets[i])
         flat = self.buf[off:off + n * ld * self.es].view(self.dtype)
-        return flat.view(n, ld)[:, :n]
+        return flat.view(n, ld)[:, :self._width(n)]
 
     def host_image(self, mats):
-        """The arena's bytes (numpy uint8) with the host matrices `mats` in
-        place, padding zero."""
+        """The arena's bytes (numpy uint8) with the host matrices `mats`
+        (entries, or uint64 words for Boolean) in place, padding zero."""
         import numpy as np
         img = np.zeros(self.buf.numel(), dtype=np.uint8)
-        np_dt = np.uint8 if self.es == 1 else np.uint16
+        np_dt = {1: np.uint8, 2: np.uint16, 8: np.uint64}[self.es]
         for i, m in enumerate(mats):
             n, ld, off = int(self.sizes[i]), int(self.lds[i]), int(self.offsets[i])
-            if m.shape[0] != n or m.shape[1] < n:
-                raise ValueError("matrix %d has shape %s, expected %d x %d" % (i, m.shape, n, n))
+            w = self._width(n)
+            if m.shape[0] != n or m.shape[1] < w:
+                raise ValueError("matrix %d has shape %s, expected %d x %d" % (i, m.shape, n, w))
             dst = img[off:off + n * ld * self.es].view(np_dt).reshape(n, ld)
-            dst[:, :n] = m[:, :n]
+            dst[:, :w] = m[:, :w]
         return img
 
     def load(self, mats):

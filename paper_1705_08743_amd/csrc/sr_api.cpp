@@ -609,7 +609,6 @@ namespace {
 int check_batch(const char *fn, int kind, void *const *T, const int64_t *ldt, const int64_t *D,
                 int64_t count, unsigned flags) {
     if (!valid_kind(kind)) return fail(SR_EINVAL, "%s: invalid kind %d", fn, kind);
-    if (kind == SR_BOOL) return fail(SR_EUNSUPPORTED, "%s: Boolean batches are not built", fn);
     if (base_kind(kind) == SR_ANTIDIST_U32)
         return fail(SR_EUNSUPPORTED, "%s: 32-bit batches are not built", fn);
     if (flags & ~(unsigned)SR_REFLEXIVE) return fail(SR_EINVAL, "%s: unknown flags 0x%x", fn, flags);
@@ -635,13 +634,17 @@ int check_batch(const char *fn, int kind, void *const *T, const int64_t *ldt, co
     return ok();
 }
 
+// Batches computed in a 16-bit working copy (binary16 values): uint8 data,
+// and Boolean data as {0, 255} anti-distance matrices.
+bool batch_in_copies(int kind) { return kind == SR_BOOL || base_kind(kind) == SR_ANTIDIST_U8; }
+
 // The batch's descriptors, largest graph first (ties keep the caller's
-// order).  uint8 kinds: T8 is the caller's matrix and T, the 16-bit working
-// copy, is left null for place_working_copies; *work_elems receives the
-// elements those copies take.
+// order).  uint8 and Boolean kinds: T8 is the caller's matrix (ld8 in bytes)
+// and T, the 16-bit working copy, is left null for place_working_copies;
+// *work_elems receives the elements those copies take.
 std::vector<sr::BatchDesc> batch_descs(int kind, void *const *T, const int64_t *ldt,
                                        const int64_t *D, int64_t count, size_t *work_elems) {
-    const bool s8 = base_kind(kind) == SR_ANTIDIST_U8;
+    const bool s8 = batch_in_copies(kind);
     std::vector<int64_t> order((size_t)count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return D[a] > D[b]; });
@@ -654,7 +657,7 @@ std::vector<sr::BatchDesc> batch_descs(int kind, void *const *T, const int64_t *
         d.pad = 0;
         if (s8) {
             d.T8 = static_cast<uint8_t *>(T[g]);
-            d.ld8 = ldt[g];
+            d.ld8 = ldt[g] * unit_bytes(kind);
             d.ld = round_up(D[g], 8);
             d.T = nullptr;
             *work_elems += (size_t)(D[g] * d.ld);
@@ -702,7 +705,7 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
     int rc = check_batch("closure_batched", kind, T, ldt, D, count, flags);
     if (rc != SR_OK || count == 0) return rc;
     hipStream_t st = as_stream(stream);
-    const bool s8 = base_kind(kind) == SR_ANTIDIST_U8;
+    const bool s8 = batch_in_copies(kind);
     size_t work_elems = 0;
     std::vector<sr::BatchDesc> h = batch_descs(kind, T, ldt, D, count, &work_elems);
     // descriptors and per-round work lists, then the 16-bit working copies
@@ -714,7 +717,7 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
     if (rc != SR_OK) return rc;
     if (s8) place_working_copies(h, static_cast<char *>(w) + plan_bytes);
     hipError_t e = sr::launch_ad_closure_batched(s8, plan.get(), h.data(), count, w, is_dist(kind),
-                                                 (flags & SR_REFLEXIVE) != 0, st);
+                                                 (flags & SR_REFLEXIVE) != 0, kind == SR_BOOL, st);
     work_free(w, st);
     if (e != hipSuccess) return device_fail(e, "closure_batched launch");
     return ok();
@@ -858,7 +861,7 @@ void sr_autotune_clear(void) { sr::tuned_clear(); }
 struct sr_batch {
     int kind = 0;
     int device = 0;
-    bool s8 = false, dual = false, reflexive = false;
+    bool s8 = false, dual = false, reflexive = false, bits = false;
     int64_t count = 0;
     std::vector<sr::BatchDesc> h;  // largest first; uint8: working copies placed
     sr::BatchPlan *plan = nullptr;
@@ -915,7 +918,8 @@ int sr_batch_create(int kind, void *const *T, const int64_t *ldt, const int64_t 
         return fail(SR_EUNSUPPORTED, "sr_batch_create: the stream is being captured");
     std::unique_ptr<sr_batch, void (*)(sr_batch *)> b(new sr_batch, batch_free);
     b->kind = kind;
-    b->s8 = base_kind(kind) == SR_ANTIDIST_U8;
+    b->s8 = batch_in_copies(kind);
+    b->bits = kind == SR_BOOL;
     b->dual = is_dist(kind);
     b->reflexive = (flags & SR_REFLEXIVE) != 0;
     b->count = count;
@@ -948,7 +952,7 @@ int sr_batch_run(sr_batch *b, void *stream) {
         return fail(SR_EINVAL, "sr_batch_run: the batch belongs to device %d, current is %d",
                     b->device, dev);
     const hipError_t e = sr::launch_ad_closure_batched_resident(
-        b->s8, b->plan, b->count, b->dev, b->dual, b->reflexive, as_stream(stream));
+        b->s8, b->plan, b->count, b->dev, b->dual, b->reflexive, b->bits, as_stream(stream));
     if (e != hipSuccess) return device_fail(e, "sr_batch_run launch");
     return ok();
 }
@@ -971,8 +975,8 @@ int sr_batch_autotune(sr_batch *b, int *chosen, void *stream) {
         return ok();
     }
     // zero matrices of the batch's sizes and strides (each 256-byte aligned),
-    // then room for a plan image; uint8 batches reuse the handle's working
-    // copies
+    // then room for a plan image; uint8 and Boolean batches reuse the
+    // handle's working copies
     const int64_t ub = b->s8 ? 1 : 2;
     std::vector<size_t> offs(b->h.size());
     size_t mat_bytes = 0;
@@ -1005,7 +1009,8 @@ int sr_batch_autotune(sr_batch *b, int *chosen, void *stream) {
             st, ev.a, ev.b, 2, [&] { return hipMemsetAsync(zm, 0, mat_bytes, st); },
             [&] {
                 return sr::launch_ad_closure_batched_resident(b->s8, p.get(), b->count, zimg,
-                                                              b->dual, b->reflexive, st) ==
+                                                              b->dual, b->reflexive, b->bits,
+                                                              st) ==
                                hipSuccess
                            ? SR_OK
                            : SR_EDEVICE;

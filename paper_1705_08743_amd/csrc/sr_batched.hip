@@ -237,6 +237,60 @@ __global__ void __launch_bounds__(256) k_batch_narrow(const BatchDesc *desc, int
     }
 }
 
+// Boolean data (bit c of a row: bit c % 8 of byte c / 8, i.e. bit c % 64 of
+// 64-bit word c / 64 on this little-endian device; T8 = the bit rows, ld8 in
+// bytes) <-> the binary16 working copy of the anti-distance matrix with S =
+// 255 whose entries are 255 for a set bit and 0 otherwise.  On such matrices
+// (+) = max and (x) (a + b - 255, floored at 0) stay in {0, 255} and act as OR
+// and AND, so the anti-distance closure of the copy is the Boolean closure
+// (Boolean matrices are the anti-distance matrices of S = 1, rescaled).
+// Workgroup (g, y) converts rows [32 y, 32 y + 32) of graph g, one byte of
+// bits (8 columns) per thread and step.
+__global__ void __launch_bounds__(256) k_batch_unpack(const BatchDesc *desc) {
+    const BatchDesc d = desc[blockIdx.x];
+    const int64_t r0 = (int64_t)blockIdx.y * kConvRows;
+    if (r0 >= d.D) return;
+    const int64_t nr = min<int64_t>(kConvRows, (int64_t)d.D - r0);
+    const int64_t gpr = ((int64_t)d.D + 7) >> 3;
+    const uint32_t one = dev::u8_to_work(255);
+    for (int64_t g = threadIdx.x; g < nr * gpr; g += 256) {
+        const int64_t row = r0 + g / gpr, c0 = (g % gpr) * 8;
+        const uint32_t bits = d.T8[row * d.ld8 + (c0 >> 3)];
+        uint32_t v[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) v[i] = (c0 + i < d.D && ((bits >> i) & 1u)) ? one : 0u;
+        uint4 o;
+        o.x = v[0] | (v[1] << 16);
+        o.y = v[2] | (v[3] << 16);
+        o.z = v[4] | (v[5] << 16);
+        o.w = v[6] | (v[7] << 16);
+        *reinterpret_cast<uint4 *>(d.T + row * d.ld + c0) = o;
+    }
+}
+
+// The way back: a set bit for every nonzero entry of columns < D, one byte per
+// thread and step.  Bytes past column D - 1 are not written (their bits are
+// zero by the caller's contract and stay so).
+__global__ void __launch_bounds__(256) k_batch_pack(const BatchDesc *desc) {
+    const BatchDesc d = desc[blockIdx.x];
+    const int64_t r0 = (int64_t)blockIdx.y * kConvRows;
+    if (r0 >= d.D) return;
+    const int64_t nr = min<int64_t>(kConvRows, (int64_t)d.D - r0);
+    const int64_t gpr = ((int64_t)d.D + 7) >> 3;
+    for (int64_t g = threadIdx.x; g < nr * gpr; g += 256) {
+        const int64_t row = r0 + g / gpr, c0 = (g % gpr) * 8;
+        const uint4 w = *reinterpret_cast<const uint4 *>(d.T + row * d.ld + c0);
+        const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+        uint32_t b = 0;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const uint32_t e = (ww[i >> 1] >> (16 * (i & 1))) & 0x7FFFu;  // (a -0 reads as 0)
+            if (c0 + i < d.D && e != 0u) b |= 1u << i;
+        }
+        d.T8[row * d.ld8 + (c0 >> 3)] = (uint8_t)b;
+    }
+}
+
 // uint16 entries complemented in place (65535 - a), every graph; workgroup
 // (g, y) takes rows [32 y, 32 y + 32) of graph g, as the conversions above.
 __global__ void __launch_bounds__(256) k_batch_not(const BatchDesc *desc) {
@@ -360,7 +414,7 @@ void batch_plan_image(const BatchPlan *plan, const BatchDesc *host_desc, int64_t
 
 hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, int64_t count,
                                               const void *dev_buf, bool dual, bool reflexive,
-                                              hipStream_t st) {
+                                              bool bits, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const BatchPlan &p = *plan;
     const BatchDesc *desc = static_cast<const BatchDesc *>(dev_buf);
@@ -368,7 +422,9 @@ hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, in
                                                        desc_bytes_of(count));
     const unsigned ng = (unsigned)count;
     const dim3 conv(ng, (unsigned)std::max<int64_t>(1, ((int64_t)p.max_d + kConvRows - 1) / kConvRows));
-    if (s8)
+    if (bits)
+        hipLaunchKernelGGL(k_batch_unpack, conv, dim3(256), 0, st, desc);
+    else if (s8)
         hipLaunchKernelGGL(k_batch_widen, conv, dim3(256), 0, st, desc, dual ? 1 : 0);
     else if (dual)
         hipLaunchKernelGGL(k_batch_not, conv, dim3(256), 0, st, desc);
@@ -420,6 +476,14 @@ hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, in
                                c.n_items + 1, (int)kb, c.n_units, xmap);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (bits) {
+        // reflexive: the diagonal of the working copy := 255 (a set bit), then back to bits
+        if (reflexive)
+            hipLaunchKernelGGL(k_batch_diag, dim3(ng), dim3(256), 0, st, desc, 0,
+                               (uint32_t)0x5BF8u /* 255 in binary16 */);
+        hipLaunchKernelGGL(k_batch_pack, conv, dim3(256), 0, st, desc);
+        return hipGetLastError();
+    }
     if (s8)
         hipLaunchKernelGGL(k_batch_narrow, conv, dim3(256), 0, st, desc, dual ? 1 : 0);
     else if (dual)
@@ -434,7 +498,7 @@ hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, in
 
 hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const BatchDesc *host_desc,
                                      int64_t count, void *dev_buf, bool dual, bool reflexive,
-                                     hipStream_t st) {
+                                     bool bits, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     // host image of the descriptors and item lists; freed by a stream
     // callback once the upload has executed
@@ -446,7 +510,8 @@ hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const Batch
     else
         delete img;
     if (e != hipSuccess) return e;
-    return launch_ad_closure_batched_resident(s8, plan, count, dev_buf, dual, reflexive, st);
+    return launch_ad_closure_batched_resident(s8, plan, count, dev_buf, dual, reflexive, bits,
+                                              st);
 }
 
 }  // namespace sr

@@ -116,8 +116,9 @@ hipError_t launch_diag(int elem_bytes, void *T, int64_t ld, int64_t D, uint32_t 
 struct BatchDesc {
     uint16_t *T;    // matrix in 16-bit storage (the caller's, or a working copy)
     int64_t ld;     // row stride of T, elements (multiple of 8)
-    uint8_t *T8;    // uint8 data: the caller's matrix (widened into T, narrowed back)
-    int64_t ld8;    // row stride of T8, elements (multiple of 16)
+    uint8_t *T8;    // uint8 data: the caller's matrix (widened into T, narrowed
+                    // back); Boolean data: the caller's bit rows
+    int64_t ld8;    // row stride of T8, bytes (a multiple of 16)
     int32_t D;      // vertices
     int32_t pad;
 };
@@ -135,16 +136,18 @@ size_t batch_plan_bytes(const BatchPlan *plan, int64_t count);
 void batch_plan_image(const BatchPlan *plan, const BatchDesc *host_desc, int64_t count, void *dst);
 // dual: the batch holds distance matrices (complemented, S - a, before and
 // after the anti-distance closure); reflexive: the diagonal is then set to
-// the multiplicative identity (S for anti-distance, 0 for distance).
+// the multiplicative identity (S for anti-distance, 0 for distance, a set bit
+// for Boolean).  bits (with s8): the batch holds Boolean matrices, closed as
+// the {0, 255} anti-distance matrices of their binary16 working copies.
 hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const BatchDesc *host_desc,
                                      int64_t count, void *dev_buf, bool dual, bool reflexive,
-                                     hipStream_t stream);
+                                     bool bits, hipStream_t stream);
 // The same closure with the image already in device memory at dev_buf: kernel
 // launches only (no copy, allocation or host callback), so it can be captured
 // into a graph and replayed.
 hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, int64_t count,
                                               const void *dev_buf, bool dual, bool reflexive,
-                                              hipStream_t stream);
+                                              bool bits, hipStream_t stream);
 
 // Second stream of a closure (sr_runtime.cpp), one per (device, caller
 // stream), created on first use at default priority.  aux_acquire() returns it

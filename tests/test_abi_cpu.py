@@ -133,7 +133,14 @@ def test_batched_rejects_bad_arguments(L):
     lds = (ctypes.c_int64 * n)(8, 8)
     dims = (ctypes.c_int64 * n)(8, 8)
     f = L.closure_batched
-    assert f(sr.SR_BOOL, ptrs, lds, dims, n, 0, None) == sr.SR_EUNSUPPORTED
+    assert f(sr.SR_ANTIDIST_U32, ptrs, lds, dims, n, 0, None) == sr.SR_EUNSUPPORTED
+    assert f(sr.SR_DISTANCE_U32, ptrs, lds, dims, n, 0, None) == sr.SR_EUNSUPPORTED
+    # Boolean batches: ld in 64-bit words, even (16-byte rows)
+    blds = (ctypes.c_int64 * n)(1, 1)
+    bdims = (ctypes.c_int64 * n)(65, 65)
+    assert f(sr.SR_BOOL, ptrs, blds, bdims, n, 0, None) == sr.SR_EINVAL  # 1 word < 2
+    odd = (ctypes.c_int64 * n)(3, 3)
+    assert f(sr.SR_BOOL, ptrs, odd, bdims, n, 0, None) == sr.SR_EALIGN  # 24-byte rows
     assert f(U16, ptrs, lds, dims, -1, 0, None) == sr.SR_EINVAL
     assert f(U16, None, lds, dims, n, 0, None) == sr.SR_EINVAL
     ptrs2 = (ctypes.c_void_p * n)(P, P + 64)  # 8 x 8 uint16 = 128 bytes: overlap
@@ -218,7 +225,8 @@ def test_prepared_batch_validation(L):
     assert f(U16, ptrs, lds, dims, n, 0, 4, ctypes.byref(h), None) == sr.SR_EINVAL
     assert not h.value  # cleared on every error
     assert f(U16, ptrs, lds, dims, n, 0, -1, ctypes.byref(h), None) == sr.SR_EINVAL
-    assert f(sr.SR_BOOL, ptrs, lds, dims, n, 0, 0, ctypes.byref(h), None) == sr.SR_EUNSUPPORTED
+    assert f(sr.SR_BOOL, ptrs, lds, dims, n, sr.SR_ACCUMULATE, 0, ctypes.byref(h),
+             None) == sr.SR_EINVAL
     assert f(sr.SR_ANTIDIST_U32, ptrs, lds, dims, n, 0, 0, ctypes.byref(h),
              None) == sr.SR_EUNSUPPORTED
     assert f(U16, ptrs, lds, dims, -1, 0, 0, ctypes.byref(h), None) == sr.SR_EINVAL

@@ -49,3 +49,25 @@ def test_arena_image_roundtrip():
         b.copy_(sr.BatchArena(kind, [5, 0, 70, 34], device="cpu"))
     with pytest.raises(ValueError):
         a.load([mats[0], mats[2], mats[1], mats[3]])
+
+
+def test_arena_boolean_layout_and_image():
+    """Boolean arenas: rows of ceil(n / 64) words padded to an even count,
+    256-byte aligned matrices, word views and the host image agree."""
+    sizes = [0, 1, 63, 64, 65, 129, 200]
+    gen = np.random.default_rng(5)
+    a = sr.BatchArena(sr.SR_BOOL, sizes, device="cpu")
+    spans = []
+    for i, n in enumerate(sizes):
+        w = -(-n // 64)
+        assert a.offsets[i] % 256 == 0
+        assert a.lds[i] % 2 == 0 and a.lds[i] >= max(w, 2)
+        assert tuple(a.view(i).shape) == (n, w)
+        spans.append((a.offsets[i], a.offsets[i] + n * a.lds[i] * 8))
+    spans.sort()
+    for (lo0, hi0), (lo1, hi1) in zip(spans, spans[1:]):
+        assert hi0 <= lo1
+    mats = [gen.integers(0, 2 ** 63, size=(n, -(-n // 64)), dtype=np.uint64) for n in sizes]
+    a.load(mats)
+    for i, m in enumerate(mats):
+        assert np.array_equal(a.view(i).numpy().view(np.uint64), m)

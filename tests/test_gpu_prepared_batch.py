@@ -235,3 +235,92 @@ def test_prepared_batch_config4_sample():
     del g
     pb.close()
     sr.autotune_clear()
+
+
+# ---------------------------------------------------------------------------
+# Boolean batches: closed as {0, 255} anti-distance matrices in binary16
+# working copies, packed back to bits
+# ---------------------------------------------------------------------------
+BOOL_SIZES = [130, 7, 1025, 1, 257, 256, 129, 3, 0, 64, 600, 383, 65, 63]
+
+
+def _bool_mats(sizes, seed):
+    from gpu_util import rand_bits
+    gen = synthgen.generator(seed)
+    return [rand_bits(n, n, gen, min(0.5, float(gen.uniform(0.5, 3.0)) / max(n, 1)))
+            for n in sizes]
+
+
+def _bool_got(t, n):
+    h = sr.to_host(t)
+    assert synthgen.padding_bits_clear(h, n)
+    return synthgen.unpack_bits(h, n)
+
+
+@pytest.mark.parametrize("flags", [0, sr.SR_REFLEXIVE])
+def test_closure_batched_boolean(flags):
+    """closure_batched on bit-packed matrices: the oracle's Boolean closure
+    (and its reflexive form), padding bits kept clear, and the same bits as
+    closure() of each graph on its own (the bit-sliced kernels)."""
+    mats = _bool_mats(BOOL_SIZES, 6100 + flags)
+    devs, solo = [], []
+    for m in mats:
+        n = m.shape[0]
+        words = synthgen.pack_bits(m, synthgen.aligned_ld_words(max(n, 1)))
+        devs.append(sr.to_device(sr.SR_BOOL, words, cols=max(n, 1))[:n])
+        solo.append(sr.clone(devs[-1]))
+    sr.closure_batched(sr.SR_BOOL, devs, Ds=BOOL_SIZES, flags=flags)
+    for t, n in zip(solo, BOOL_SIZES):
+        if n:
+            sr.closure(sr.SR_BOOL, t, D=n, flags=flags)
+    torch.cuda.synchronize()
+    for t, s_, m in zip(devs, solo, mats):
+        n = m.shape[0]
+        if n == 0:
+            continue
+        want = oracle.bool_closure(m)
+        if flags & sr.SR_REFLEXIVE:
+            want = oracle.reflexive(want, 1)
+        assert np.array_equal(_bool_got(t, n), want), n
+        assert torch.equal(t, s_), n
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_prepared_batch_boolean(tile):
+    """A prepared Boolean batch with each update-tile shape, run eagerly and
+    replayed from a captured graph on fresh contents."""
+    sizes = BOOL_SIZES
+    sets = [_bool_mats(sizes, 6200 + 10 * tile + r) for r in range(3)]
+    packed = [[synthgen.pack_bits(m, max(2, -(-(-(-m.shape[0] // 64)) // 2) * 2)) for m in ms]
+              for ms in sets]
+    srcs = []
+    for ps in packed:
+        a = sr.BatchArena(sr.SR_BOOL, sizes)
+        a.load(ps)
+        srcs.append(a)
+    work = sr.BatchArena(sr.SR_BOOL, sizes, zero=False)
+    work.copy_(srcs[0])
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        pb = sr.PreparedBatch(sr.SR_BOOL, work, tile=tile)
+        pb.run()
+    torch.cuda.synchronize()
+    for i, m in enumerate(sets[0]):
+        if m.shape[0]:
+            assert np.array_equal(_bool_got(work.view(i), m.shape[0]), oracle.bool_closure(m))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        pb.run()
+    torch.cuda.synchronize()
+    for r in (1, 2):
+        work.copy_(srcs[r])
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, m in enumerate(sets[r]):
+            if m.shape[0]:
+                assert np.array_equal(_bool_got(work.view(i), m.shape[0]),
+                                      oracle.bool_closure(m)), (r, i)
+    del g
+    pb.close()
