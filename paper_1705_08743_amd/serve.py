@@ -10,9 +10,10 @@ whose result goes back to the host.  The server:
   small request can pass a large one that does not fit yet;
 * keeps each admitted request's matrix resident on the device from its upload
   to its download (one H2D copy in, the closure in place, one D2H copy out);
-* batches continuously: anti-distance requests of up to ``batch_n`` vertices
-  that are waiting when a slot frees up are closed together by one
-  ``closure_batched`` launch; larger requests each take a slot; all slots run
+* batches continuously: requests of one kind and of up to ``batch_n``
+  vertices that are waiting when a slot frees up are closed together by one
+  ``closure_batched`` launch (Boolean ones as {0, 255} anti-distance matrices
+  in 16-bit working copies); larger requests each take a slot; all slots run
   concurrently on the device (one HIP stream each, default priority), and new
   arrivals are admitted as soon as slots and memory free up, while others are
   still running;
@@ -35,19 +36,23 @@ from . import (SR_ANTIDIST_U16, SR_ANTIDIST_U8, SR_BOOL, closure, closure_batche
 _UNIT = {SR_BOOL: 8, SR_ANTIDIST_U8: 1, SR_ANTIDIST_U16: 2}
 
 
-def footprint_bytes(kind, n):
+def footprint_bytes(kind, n, batch_n=256):
     """Device bytes a request holds while admitted: its padded matrix, plus
     the library's stream-ordered working memory for its closure (the 16-bit
-    copy of a uint8 matrix, and the two working matrices of repeated
+    copy of a uint8 matrix, or of a Boolean one of at most batch_n vertices,
+    which may be closed in a batch; and the two working matrices of repeated
     squaring, which closure() takes for anti-distance matrices of 192 to 1024
     vertices)."""
     b = n * padded_ld(n, kind) * _UNIT[kind]
-    if kind != SR_BOOL:
-        lw = -(-n // 64) * 64
-        if kind == SR_ANTIDIST_U8:
+    lw = -(-n // 64) * 64
+    if kind == SR_BOOL:
+        if n <= batch_n:
             b += n * lw * 2
-        if 192 <= n <= 1024:
-            b += 2 * n * lw * 2
+        return b
+    if kind == SR_ANTIDIST_U8:
+        b += n * lw * 2
+    if 192 <= n <= 1024:
+        b += 2 * n * lw * 2
     return b
 
 
@@ -141,11 +146,11 @@ class ClosureServer:
     # -- admission ----------------------------------------------------------
     def _pick(self, waiting, free_bytes, allow_batch):
         """First-fit choice of the next job from the waiting queue: a batch of
-        small anti-distance requests of one kind, or one request."""
+        small requests of one kind, or one request."""
         for i, r in enumerate(waiting):
             if r.footprint > free_bytes:
                 continue
-            if allow_batch and r.kind != SR_BOOL and r.n <= self.batch_n:
+            if allow_batch and r.n <= self.batch_n:
                 group, used = [], 0
                 for q in waiting:
                     if (q.kind == r.kind and q.n <= self.batch_n and used + q.footprint <= free_bytes
@@ -164,6 +169,7 @@ class ClosureServer:
         if mode not in ("served", "serial"):
             raise ValueError("mode is 'served' or 'serial'")
         for r in requests:
+            r.footprint = footprint_bytes(r.kind, r.n, self.batch_n)
             if r.footprint > self.budget:
                 raise ValueError("request %d needs %d bytes, above the budget" % (r.rid, r.footprint))
             self._prepare(r)

@@ -87,3 +87,20 @@ def test_budget_too_small_is_refused():
     server = ClosureServer(budget_bytes=1024)
     with pytest.raises(ValueError):
         server.run(reqs, "served")
+
+
+def test_boolean_requests_are_batched():
+    """Small Boolean requests that wait together are closed by one batched
+    launch ({0, 255} anti-distance working copies), with the same results as
+    alone and as the oracle."""
+    from paper_1705_08743_amd.serve import ClosureServer, Request
+    trace = synthgen.serving_trace(24, nlo=40, nhi=250, seed=321)
+    reqs = [Request(i, sr.SR_BOOL, n, synthgen.serving_request(n, "bool", s), 0.0)
+            for i, (n, _, s) in enumerate(trace)]
+    server = ClosureServer(budget_bytes=1 << 30, slots=2, batch_n=256)
+    stats = server.run(reqs, "served")
+    assert stats["batched_requests"] > 0
+    for r in reqs:
+        got = r.result.view(np.uint64)
+        assert np.array_equal(got, solo(r)[:, :(r.n + 63) // 64]), (r.rid, r.n)
+        assert np.array_equal(got, want(r)), r.rid
