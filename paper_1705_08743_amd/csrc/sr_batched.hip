@@ -14,7 +14,12 @@
 // exactly the workgroup body the single-graph kernels run.  Graphs are sorted
 // largest first, so in every launch the longest work is dispatched first.
 // Every launch has thousands of workgroups (not one per graph), which keeps
-// the large graphs from finishing alone on a few compute units.
+// the large graphs from finishing alone on a few compute units; the update
+// and panels launches hand their workgroups to the XCDs in chunks (below).
+// uint8 and Boolean batches are converted into 16-bit working copies
+// (binary16 values) before the rounds and back after them.  The launch
+// sequence holds no allocation, copy or host callback once the plan is in
+// device memory, so it can be captured into a graph.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -32,9 +37,9 @@ using dev::fw_panels_wg;
 using dev::Rect;
 using dev::tile_closure;
 
-// Update-tile shapes of a batch (rows per lane TM, column pairs per wave NW:
-// a wave's tile is 64 TM rows x 2 NW columns), indexed by the tile code of
-// batch_plan_create (1: 64 x 16, 2: 64 x 32, 3: 64 x 64).
+// Update-tile shapes of a batch: a wave's tile is 64 rows (one per lane) x
+// 2 NW columns (NW packed pairs), NW indexed by the tile code of
+// batch_plan_create (1: 64 x 16, 2: 64 x 32, 3: 64 x 64; entry 0 unused).
 constexpr int kTileNW[4] = {16, 8, 16, 32};
 
 // One entry per graph taking part in a launch; `first` is the graph's first
