@@ -682,6 +682,13 @@ void place_working_copies(std::vector<sr::BatchDesc> &h, void *arena) {
     }
 }
 
+constexpr const char *kPlanFailure =
+    "could not build the batch's work lists (a launch would number more than 2^31 - 4 "
+    "workgroups, or host memory ran out)";
+
+int closure_batched_impl(int kind, void *const *T, const int64_t *ldt, const int64_t *D,
+                         int64_t count, unsigned flags, void *stream);
+
 // Update-tile shape for a batch: SR_BATCH_TILE (1, 2, 3) if set, else the
 // autotuned choice for its class, else the default.
 int batch_tile_for(int kind, const std::vector<sr::BatchDesc> &h) {
@@ -702,6 +709,19 @@ extern "C" {
 
 int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t *D, int64_t count,
                     unsigned flags, void *stream) {
+    try {
+        return closure_batched_impl(kind, T, ldt, D, count, flags, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(SR_ENOMEM, "closure_batched: out of host memory");
+    }
+}
+
+}  // extern "C"
+
+namespace {
+
+int closure_batched_impl(int kind, void *const *T, const int64_t *ldt, const int64_t *D,
+                         int64_t count, unsigned flags, void *stream) {
     int rc = check_batch("closure_batched", kind, T, ldt, D, count, flags);
     if (rc != SR_OK || count == 0) return rc;
     hipStream_t st = as_stream(stream);
@@ -711,6 +731,7 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
     // descriptors and per-round work lists, then the 16-bit working copies
     std::unique_ptr<sr::BatchPlan, void (*)(sr::BatchPlan *)> plan(
         sr::batch_plan_create(h.data(), count, batch_tile_for(kind, h)), sr::batch_plan_destroy);
+    if (!plan) return fail(SR_EINVAL, "closure_batched: %s", kPlanFailure);
     const size_t plan_bytes = round_up((int64_t)sr::batch_plan_bytes(plan.get(), count), 256);
     void *w = nullptr;
     rc = work_alloc(&w, plan_bytes + work_elems * 2, st);
@@ -723,7 +744,8 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
     return ok();
 }
 
-}  // extern "C"
+}  // namespace
+
 
 namespace {
 
@@ -878,6 +900,7 @@ size_t batch_image_cap(const std::vector<sr::BatchDesc> &h) {
     size_t cap = 256;
     for (int t = 1; t <= 3; t++) {
         sr::BatchPlan *p = sr::batch_plan_create(h.data(), (int64_t)h.size(), t);
+        if (!p) return 0;
         cap = std::max(cap, (size_t)round_up((int64_t)sr::batch_plan_bytes(p, (int64_t)h.size()), 256));
         sr::batch_plan_destroy(p);
     }
@@ -894,6 +917,9 @@ hipError_t upload_image(const sr::BatchPlan *plan, const std::vector<sr::BatchDe
     return e;
 }
 
+int batch_create_impl(int kind, void *const *T, const int64_t *ldt, const int64_t *D,
+                      int64_t count, unsigned flags, int tile, sr_batch **out, void *stream);
+
 void batch_free(sr_batch *b) {
     if (!b) return;
     if (b->plan) sr::batch_plan_destroy(b->plan);
@@ -907,6 +933,20 @@ extern "C" {
 
 int sr_batch_create(int kind, void *const *T, const int64_t *ldt, const int64_t *D, int64_t count,
                     unsigned flags, int tile, sr_batch **out, void *stream) {
+    try {
+        return batch_create_impl(kind, T, ldt, D, count, flags, tile, out, stream);
+    } catch (const std::bad_alloc &) {
+        if (out) *out = nullptr;
+        return fail(SR_ENOMEM, "sr_batch_create: out of host memory");
+    }
+}
+
+}  // extern "C"
+
+namespace {
+
+int batch_create_impl(int kind, void *const *T, const int64_t *ldt, const int64_t *D,
+                      int64_t count, unsigned flags, int tile, sr_batch **out, void *stream) {
     if (!out) return fail(SR_EINVAL, "sr_batch_create: NULL out");
     *out = nullptr;
     if (tile < SR_BATCH_TILE_AUTO || tile > SR_BATCH_TILE_64x64)
@@ -928,6 +968,7 @@ int sr_batch_create(int kind, void *const *T, const int64_t *ldt, const int64_t 
     if (count > 0) {
         b->h = batch_descs(kind, T, ldt, D, count, &b->work_elems);
         b->image_cap = batch_image_cap(b->h);
+        if (!b->image_cap) return fail(SR_EINVAL, "sr_batch_create: %s", kPlanFailure);
         const size_t bytes = b->image_cap + b->work_elems * 2;
         if (hipMalloc(reinterpret_cast<void **>(&b->dev), bytes) != hipSuccess) {
             b->dev = nullptr;
@@ -937,12 +978,19 @@ int sr_batch_create(int kind, void *const *T, const int64_t *ldt, const int64_t 
         if (b->s8) place_working_copies(b->h, b->dev + b->image_cap);
         b->plan = sr::batch_plan_create(b->h.data(), count,
                                         tile ? tile : batch_tile_for(kind, b->h));
+        if (!b->plan) return fail(SR_EINVAL, "sr_batch_create: %s", kPlanFailure);
         const hipError_t e = upload_image(b->plan, b->h, b->dev, st);
         if (e != hipSuccess) return device_fail(e, "sr_batch_create upload");
     }
     *out = b.release();
     return ok();
 }
+
+int batch_autotune_impl(sr_batch *b, int *chosen, void *stream);
+
+}  // namespace
+
+extern "C" {
 
 int sr_batch_run(sr_batch *b, void *stream) {
     if (!b) return fail(SR_EINVAL, "sr_batch_run: NULL batch");
@@ -962,6 +1010,20 @@ int sr_batch_tile(const sr_batch *b) {
 }
 
 int sr_batch_autotune(sr_batch *b, int *chosen, void *stream) {
+    try {
+        return batch_autotune_impl(b, chosen, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(SR_ENOMEM, "sr_batch_autotune: out of host memory");
+    }
+}
+
+void sr_batch_destroy(sr_batch *b) { batch_free(b); }
+
+}  // extern "C"
+
+namespace {
+
+int batch_autotune_impl(sr_batch *b, int *chosen, void *stream) {
     if (!b) return fail(SR_EINVAL, "sr_batch_autotune: NULL batch");
     hipStream_t st = as_stream(stream);
     if (capturing(st))
@@ -1004,7 +1066,7 @@ int sr_batch_autotune(sr_batch *b, int *chosen, void *stream) {
     for (int t = 1; t <= 3; t++) {
         std::unique_ptr<sr::BatchPlan, void (*)(sr::BatchPlan *)> p(
             sr::batch_plan_create(th.data(), b->count, t), sr::batch_plan_destroy);
-        if (upload_image(p.get(), th, zimg, st) != hipSuccess) continue;
+        if (!p || upload_image(p.get(), th, zimg, st) != hipSuccess) continue;
         const float ms = time_candidate(
             st, ev.a, ev.b, 2, [&] { return hipMemsetAsync(zm, 0, mat_bytes, st); },
             [&] {
@@ -1025,6 +1087,7 @@ int sr_batch_autotune(sr_batch *b, int *chosen, void *stream) {
     if (!pick) return fail(SR_EDEVICE, "sr_batch_autotune: no candidate ran");
     if (pick != sr::batch_plan_tile(b->plan)) {
         sr::BatchPlan *np = sr::batch_plan_create(b->h.data(), b->count, pick);
+        if (!np) return fail(SR_EINVAL, "sr_batch_autotune: %s", kPlanFailure);
         const hipError_t e = upload_image(np, b->h, b->dev, st);
         if (e != hipSuccess) {
             // the device image may be partly overwritten: keep the handle
@@ -1041,6 +1104,4 @@ int sr_batch_autotune(sr_batch *b, int *chosen, void *stream) {
     return ok();
 }
 
-void sr_batch_destroy(sr_batch *b) { batch_free(b); }
-
-}  // extern "C"
+}  // namespace

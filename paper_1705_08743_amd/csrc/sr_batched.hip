@@ -25,6 +25,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <new>
 #include <vector>
 
 #include "sr_internal.h"
@@ -339,7 +340,10 @@ struct BatchPlan {
 
 namespace {
 
-void build_plan(BatchPlan &p, const BatchDesc *hd, int64_t count) {
+// false when a launch would number more workgroups (or update waves) than
+// fit the 32-bit work lists.
+bool build_plan(BatchPlan &p, const BatchDesc *hd, int64_t count) {
+    constexpr int64_t kMaxUnits = INT32_MAX - 3;
     const int cw = 2 * kTileNW[p.tile];
     int max_rounds = 0;
     p.max_d = 0;
@@ -350,8 +354,11 @@ void build_plan(BatchPlan &p, const BatchDesc *hd, int64_t count) {
     for (int kb = 0; kb < max_rounds; kb++) {
         // pivot: every graph with a round kb
         Launch lp{(int64_t)p.items.size(), 0, 0, 0};
-        for (int64_t g = 0; g < count; g++)
-            if (hd[g].D > 0 && rounds_of(hd[g].D) > kb) p.items.push_back(Item{(int32_t)g, lp.n_wg++});
+        for (int64_t g = 0; g < count; g++) {
+            if (hd[g].D <= 0 || rounds_of(hd[g].D) <= kb) continue;
+            if (lp.n_wg >= kMaxUnits) return false;
+            p.items.push_back(Item{(int32_t)g, lp.n_wg++});
+        }
         lp.n_items = lp.n_wg;
         p.items.push_back(Item{-1, lp.n_wg});
         p.pivot.push_back(lp);
@@ -364,6 +371,7 @@ void build_plan(BatchPlan &p, const BatchDesc *hd, int64_t count) {
             int r = 0, c = 0;
             dev::panel_wgs(D, k0, bs, &r, &c);
             if (r + c <= 0) continue;
+            if ((int64_t)la.n_wg + r + c > kMaxUnits) return false;
             p.items.push_back(Item{(int32_t)g, la.n_wg});
             la.n_wg += r + c;
             la.n_items++;
@@ -376,8 +384,9 @@ void build_plan(BatchPlan &p, const BatchDesc *hd, int64_t count) {
             if (rounds_of(D) <= std::max(kb, 1)) continue;
             int nc = 0, nr = 0;
             (void)update_rect(D, kb, 64, cw, &nc, &nr);
-            const int waves = nc * nr;
+            const int64_t waves = (int64_t)nc * nr;
             if (waves <= 0) continue;
+            if ((int64_t)lu.n_units + waves > kMaxUnits) return false;
             p.items.push_back(Item{(int32_t)g, lu.n_units});
             lu.n_units += waves;
             lu.n_items++;
@@ -386,6 +395,7 @@ void build_plan(BatchPlan &p, const BatchDesc *hd, int64_t count) {
         lu.n_wg = (lu.n_units + 3) / 4;
         p.update.push_back(lu);
     }
+    return true;
 }
 
 size_t desc_bytes_of(int64_t count) {
@@ -395,9 +405,19 @@ size_t desc_bytes_of(int64_t count) {
 }  // namespace
 
 BatchPlan *batch_plan_create(const BatchDesc *host_desc, int64_t count, int tile) {
-    auto *p = new BatchPlan;
+    auto *p = new (std::nothrow) BatchPlan;
+    if (!p) return nullptr;
     p->tile = tile >= 1 && tile <= 3 ? tile : kBatchTileDefault;
-    build_plan(*p, host_desc, count);
+    bool ok = false;
+    try {
+        ok = build_plan(*p, host_desc, count);
+    } catch (const std::bad_alloc &) {
+        ok = false;
+    }
+    if (!ok) {
+        delete p;
+        return nullptr;
+    }
     return p;
 }
 

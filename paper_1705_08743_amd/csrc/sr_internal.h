@@ -127,6 +127,8 @@ struct BatchDesc {
 // 64 x 64 entries (anything else: kBatchTileDefault).
 constexpr int kBatchTileDefault = 2;
 struct BatchPlan;
+// nullptr when host memory runs out or a launch of the batch would hold more
+// than 2^31 - 4 workgroups (or update waves).
 BatchPlan *batch_plan_create(const BatchDesc *host_desc, int64_t count, int tile);
 void batch_plan_destroy(BatchPlan *plan);
 int batch_plan_tile(const BatchPlan *plan);
