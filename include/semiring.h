@@ -202,7 +202,10 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
  * length count; T[g] are device pointers, each obeying the alignment rules
  * above.  Boolean and 8- and 16-bit anti-distance and distance kinds (the
  * 32-bit kinds return SR_EUNSUPPORTED); flags: SR_REFLEXIVE.  The
- * matrices must not overlap each other (SR_EALIAS), D[g] <= 65536.  The
+ * matrices must not overlap each other (SR_EALIAS), D[g] <= 65536; a batch
+ * one of whose launches would number more than 2^31 - 4 workgroups (or
+ * update waves) is SR_EINVAL, and running out of host memory for its work
+ * lists SR_ENOMEM.  The
  * batch runs the blocked Floyd-Warshall of closure() round-synchronously: per
  * round, one pivot, one panels and one update launch cover every graph that
  * still has that round (largest graphs first), so a graph of up to 128
