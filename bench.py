@@ -59,8 +59,8 @@ TRAFFIC = {
     # full update launch (252 x 32 workgroups, every tile outside the pivot
     # row and column blocks) of the D = 8192 closure:
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, in bytes
-    "fw8192": {"src_hash": "1ec7a3f927a1b60f", "bytes_per_launch": 4.969e8},   # 1.792e5 + 1.270e5 KiB
-    "u8fw8192": {"src_hash": "1ec7a3f927a1b60f", "bytes_per_launch": 4.845e8},  # 1.731e5 + 1.270e5 KiB
+    "fw8192": {"src_hash": "96ded9e9c24175ed", "bytes_per_launch": 4.967e8},   # 1.791e5 + 1.270e5 KiB
+    "u8fw8192": {"src_hash": "96ded9e9c24175ed", "bytes_per_launch": 4.845e8},  # 1.731e5 + 1.270e5 KiB
     "u32fw8192": {"src_hash": "52fb5786d930fdd0", "bytes_per_launch": 7.251e8},  # 2.256e5 + 2.569e5 KiB
     # full update launches (four-Russians kernel, 32 x 32 tiles of 512 x 512
     # bits) of the serialized D = 16384 Boolean closure

@@ -167,9 +167,9 @@ k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, in
     int c = csel;
     if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
     if ((c + 1) * CW <= d.D)
-        dev::fw_update_wave<1, NW, S8, true>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
+        dev::fw_update_wave<1, NW, S8, true, true>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
     else
-        dev::fw_update_wave<1, NW, S8, false>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
+        dev::fw_update_wave<1, NW, S8, false, true>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
 }
 
 // uint8 <-> the 16-bit working form of uint8 data (binary16 values) for every

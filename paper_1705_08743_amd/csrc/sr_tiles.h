@@ -138,7 +138,7 @@ __device__ __forceinline__ void row_store(const u16x2 (&acc)[NW], uint16_t *crow
     }
 }
 
-template <int TM, int NW, bool S8, bool FULLC>
+template <int TM, int NW, bool S8, bool FULLC, bool GROUPB = !S8>
 __device__ __forceinline__ void wave_tile_body(uint16_t *C, int64_t ldc, const uint16_t *A,
                                                int64_t lda, const uint16_t *B, int64_t ldb,
                                                int nrows, int ncols, int K, bool accumulate,
@@ -214,7 +214,20 @@ __device__ __forceinline__ void wave_tile_body(uint16_t *C, int64_t ldc, const u
             for (int kg = 0; kg < AG; kg += KU) {
                 const uint16_t *b0 = B + (int64_t)(k + kg) * ldb;
                 if (S8) {
-                    // steps kk and kk + 1 (an even pair: one word of na)
+                    // steps kk and kk + 1 (an even pair: one word of na); with
+                    // GROUPB the group's B rows are loaded first, as below
+                    // (faster in the batched update, slower in the
+                    // single-matrix closure's, where it is off)
+                    uint32_t bg[GROUPB ? KU : 1][NW];
+                    if constexpr (GROUPB) {
+#pragma unroll
+                        for (int kk = 0; kk < KU; kk++) {
+                            const kconst uint32_t *bp =
+                                (const kconst uint32_t *)(b0 + kk * ldb);
+#pragma unroll
+                            for (int w = 0; w < NW; w++) bg[kk][w] = bp[w];
+                        }
+                    }
 #pragma unroll
                     for (int kk = 0; kk < KU; kk += 2) {
                         const kconst uint32_t *br0 = (const kconst uint32_t *)(b0 + kk * ldb);
@@ -226,9 +239,12 @@ __device__ __forceinline__ void wave_tile_body(uint16_t *C, int64_t ldc, const u
                             const u16x2 nv0 = u16x2{(uint16_t)n2, (uint16_t)n2};
                             const u16x2 nv1 = u16x2{(uint16_t)(n2 >> 16), (uint16_t)(n2 >> 16)};
 #pragma unroll
-                            for (int w = 0; w < NW; w++)
-                                acc[t][w] = step2_s8(acc[t][w], as_pair(br0[w]), nv0,
-                                                     as_pair(br1[w]), nv1);
+                            for (int w = 0; w < NW; w++) {
+                                const uint32_t x0 = GROUPB ? bg[kk][w] : br0[w];
+                                const uint32_t x1 = GROUPB ? bg[kk + 1][w] : br1[w];
+                                acc[t][w] =
+                                    step2_s8(acc[t][w], as_pair(x0), nv0, as_pair(x1), nv1);
+                            }
                         }
                     }
                 } else {
@@ -317,7 +333,7 @@ __device__ __forceinline__ void wave_tile_narrow(uint16_t *C, int64_t ldc, const
 // sub-tiles store as they finish and the barrier comes last; a row-panel
 // update stays exact under that order because the pivot tile is closed (any
 // mix of old and new operand entries gives the same result).
-template <int TM, int NW, bool S8>
+template <int TM, int NW, bool S8, bool GROUPB = !S8>
 __device__ __forceinline__ void wave_tile(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
                                           const uint16_t *B, int64_t ldb, int nrows, int ncols,
                                           int64_t bspan, int K, bool accumulate,
@@ -328,10 +344,12 @@ __device__ __forceinline__ void wave_tile(uint16_t *C, int64_t ldc, const uint16
     }
     if (bspan >= 2 * NW) {
         if (ncols >= 2 * NW)
-            wave_tile_body<TM, NW, S8, true>(C, ldc, A, lda, B, ldb, nrows, 2 * NW, K, accumulate,
+            wave_tile_body<TM, NW, S8, true, GROUPB>(C, ldc, A, lda, B, ldb, nrows, 2 * NW, K,
+                                                     accumulate,
                                              sync_before_store);
         else
-            wave_tile_body<TM, NW, S8, false>(C, ldc, A, lda, B, ldb, nrows, ncols, K, accumulate,
+            wave_tile_body<TM, NW, S8, false, GROUPB>(C, ldc, A, lda, B, ldb, nrows, ncols, K,
+                                                      accumulate,
                                               sync_before_store);
         return;
     }
@@ -522,7 +540,7 @@ struct Rect {
 // launcher sends a partial last chunk to a FULL = false launch).
 // One wave's tile: selected column chunk csel, selected row chunk rsel
 // (wave-uniform).  Out-of-range indices do nothing.
-template <int TM, int NW, bool S8, bool FULL>
+template <int TM, int NW, bool S8, bool FULL, bool GROUPB = !S8>
 __device__ __forceinline__ void fw_update_wave(uint16_t *T, int64_t ld, int D, int k0, int bs,
                                                const Rect &q, int csel, int rsel) {
     constexpr int CW = 2 * NW, RW = 64 * TM;
@@ -534,14 +552,14 @@ __device__ __forceinline__ void fw_update_wave(uint16_t *T, int64_t ld, int D, i
     const int64_t row0 = (int64_t)rc * RW, col0 = (int64_t)c * CW;
     const int nrows = (int)min<int64_t>(RW, (int64_t)D - row0);
     if (FULL) {
-        wave_tile_body<TM, NW, S8, true>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld,
-                                         T + (int64_t)k0 * ld + col0, ld, nrows, CW, bs, true,
-                                         false);
+        wave_tile_body<TM, NW, S8, true, GROUPB>(T + row0 * ld + col0, ld, T + row0 * ld + k0,
+                                                 ld, T + (int64_t)k0 * ld + col0, ld, nrows, CW,
+                                                 bs, true, false);
     } else {
         const int ncols = (int)min<int64_t>(CW, (int64_t)D - col0);
-        wave_tile<TM, NW, S8>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld,
-                              T + (int64_t)k0 * ld + col0, ld, nrows, ncols, ld - col0, bs, true,
-                              false);
+        wave_tile<TM, NW, S8, GROUPB>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld,
+                                      T + (int64_t)k0 * ld + col0, ld, nrows, ncols, ld - col0, bs,
+                                      true, false);
     }
 }
 
