@@ -239,8 +239,9 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
  * does, builds the descriptors and per-round work lists with update tiles of
  * shape `tile` (SR_BATCH_TILE_*; SR_BATCH_TILE_AUTO: the autotuned shape for
  * batches of this class, else 64 x 32; any other value is SR_EINVAL),
- * allocates device memory for them -- and for uint8 kinds the 16-bit working
- * copies, 2 * sum(D[g] * round_up(D[g], 8)) bytes -- with hipMalloc, uploads
+ * allocates device memory for them -- and for uint8 and Boolean kinds the
+ * 16-bit working copies, 2 * sum(D[g] * round_up(D[g], 8)) bytes -- with
+ * hipMalloc, uploads
  * them on `stream`, waits for the upload and stores the handle in *out
  * (NULL on error).  The three arrays are copied (the caller may free them);
  * the matrices must stay allocated while the handle is used.  SR_EUNSUPPORTED
@@ -249,8 +250,8 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
  * sr_batch_run enqueues, on `stream`, the in-place closure of the matrices'
  * current contents: no allocation, copy, memset or host callback.  The
  * current device must be the one the handle was created on (SR_EINVAL).  Runs
- * of one handle must not overlap in time (uint8 batches share the working
- * copies).
+ * of one handle must not overlap in time (uint8 and Boolean batches share the
+ * working copies).
  *
  * sr_batch_autotune times the batch with each update-tile shape on zero
  * matrices of the same sizes (allocated for the purpose; the kernels'
