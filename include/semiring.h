@@ -200,8 +200,7 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
  * closure_batched -- `count` independent in-place closures, as closure()
  * applied to each (T[g], ldt[g], D[g]).  The three arrays are HOST arrays of
  * length count; T[g] are device pointers, each obeying the alignment rules
- * above.  Boolean and 8- and 16-bit anti-distance and distance kinds (the
- * 32-bit kinds return SR_EUNSUPPORTED); flags: SR_REFLEXIVE.  The
+ * above.  Every kind; flags: SR_REFLEXIVE.  The
  * matrices must not overlap each other (SR_EALIAS), D[g] <= 65536; a batch
  * one of whose launches would number more than 2^31 - 4 workgroups (or
  * update waves) is SR_EINVAL, and running out of host memory for its work
@@ -212,7 +211,9 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
  * vertices is closed by the first pivot launch.  The descriptors and the
  * per-round work lists are built on the host and uploaded stream-ordered
  * (the call returns without waiting); uint8 batches use stream-ordered
- * 16-bit working copies (binary16 values).  Boolean batches are closed as
+ * 16-bit working copies (binary16 values); 32-bit batches run the 32-bit
+ * wave tiles of closure() with update tiles of 64 x 32 entries (their only
+ * shape).  Boolean batches are closed as
  * anti-distance matrices with S = 255 whose entries are 255 for a set bit
  * and 0 otherwise (Sec. III: a set bit stands for distance 0, the entry S,
  * a clear one for distance infinity, the entry 0, and with S = 1 the

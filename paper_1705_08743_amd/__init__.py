@@ -280,12 +280,12 @@ class BatchArena:
     def __init__(self, kind, sizes, device="cuda", zero=True):
         import numpy as np
         torch = _torch()
-        if kind not in _U8_KINDS + _U16_KINDS + (SR_BOOL,):
-            raise ValueError("BatchArena holds Boolean or 8- or 16-bit anti-distance or "
-                             "distance matrices")
+        if kind not in _U8_KINDS + _U16_KINDS + _U32_KINDS + (SR_BOOL,):
+            raise ValueError("BatchArena holds Boolean, anti-distance or distance matrices")
         self.kind = kind
-        self.es = {SR_BOOL: 8}.get(kind, 1 if kind in _U8_KINDS else 2)
-        self.dtype = {1: torch.uint8, 2: torch.uint16, 8: torch.int64}[self.es]
+        self.es = {SR_BOOL: 8}.get(kind, 1 if kind in _U8_KINDS else
+                                   (4 if kind in _U32_KINDS else 2))
+        self.dtype = {1: torch.uint8, 2: torch.uint16, 4: torch.uint32, 8: torch.int64}[self.es]
         self.sizes = np.asarray(sizes, dtype=np.int64).reshape(-1)
         if (self.sizes < 0).any():
             raise ValueError("negative matrix size")
@@ -328,7 +328,7 @@ class BatchArena:
         (entries, or uint64 words for Boolean) in place, padding zero."""
         import numpy as np
         img = np.zeros(self.buf.numel(), dtype=np.uint8)
-        np_dt = {1: np.uint8, 2: np.uint16, 8: np.uint64}[self.es]
+        np_dt = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}[self.es]
         for i, m in enumerate(mats):
             n, ld, off = int(self.sizes[i]), int(self.lds[i]), int(self.offsets[i])
             w = self._width(n)

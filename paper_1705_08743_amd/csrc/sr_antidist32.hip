@@ -18,6 +18,7 @@
 
 #include <algorithm>
 
+#include "sr_batch_dev.h"
 #include "sr_internal.h"
 #include "sr_tiles.h"  // kconst (scalar reads of B rows), Rect, panel_wgs
 
@@ -224,10 +225,8 @@ k_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint3
 // cannot overwrite what a slower thread still reads for step k.  Entries
 // outside bs x bs are held as 0, the additive zero, and stay 0.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_ad32_pivot(uint32_t *T, int64_t ld, int bs, int prio) {
-    if (prio) __builtin_amdgcn_s_setprio(2);
-    __shared__ uint32_t lds_row[2 * 128];
-    __shared__ uint32_t lds_col[2 * 128];
+__device__ __forceinline__ void pivot32_tile(uint32_t *T, int64_t ld, int bs, uint32_t *lds_row,
+                                             uint32_t *lds_col) {
     const int t = threadIdx.x;
     const int tx = t & 15, ty = t >> 4;
     const int c0 = 8 * tx;
@@ -295,6 +294,13 @@ __global__ void __launch_bounds__(256) k_ad32_pivot(uint32_t *T, int64_t ld, int
     }
 }
 
+__global__ void __launch_bounds__(256) k_ad32_pivot(uint32_t *T, int64_t ld, int bs, int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
+    __shared__ uint32_t lds_row[2 * 128];
+    __shared__ uint32_t lds_col[2 * 128];
+    pivot32_tile(T, ld, bs, lds_row, lds_col);
+}
+
 // ---------------------------------------------------------------------------
 // Panels of round K = [k0, k0 + bs), one workgroup (id bid).  Workgroups
 // [0, n_rowwg) take the row panel T_Kj (+)= T_KK * T_Kj: two 64-row halves of
@@ -304,12 +310,10 @@ __global__ void __launch_bounds__(256) k_ad32_pivot(uint32_t *T, int64_t ld, int
 // panel tile is written by one workgroup, after a barrier that follows every
 // read of the workgroup's operands.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-k_ad32_panels(uint32_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg, int prio) {
-    if (prio) __builtin_amdgcn_s_setprio(2);
+__device__ __forceinline__ void panels32_wg(uint32_t *T, int64_t ld, int D, int k0, int bs,
+                                            int n_rowwg, int bid) {
     constexpr int CW = kPanCW;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int bid = (int)blockIdx.x;
     if (bid < n_rowwg) {
         const int kc0 = k0 / CW, kc1 = (k0 + bs + CW - 1) / CW;
         const int cc = 2 * bid + (wave >> 1);
@@ -333,6 +337,12 @@ k_ad32_panels(uint32_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg, int p
                    T + (int64_t)k0 * ld + k0 + cofs, ld, nrows, ncols, ld - k0 - cofs, bs, true,
                    true);
     }
+}
+
+__global__ void __launch_bounds__(256)
+k_ad32_panels(uint32_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg, int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(2);
+    panels32_wg(T, ld, D, k0, bs, n_rowwg, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -362,6 +372,80 @@ k_ad32_update(uint32_t *T, int64_t ld, int D, int k0, int bs, Rect q, int prio) 
     else
         tile32<CW>(dst, ld, a, ld, b, ld, nrows, (int)min<int64_t>(CW, (int64_t)D - col0),
                    ld - col0, bs, true, false);
+}
+
+// ---------------------------------------------------------------------------
+// Batched closures of 32-bit matrices: the launches of the batched closure
+// (sr_batched.hip: work lists, XCD-aware order) with the 32-bit workgroup
+// bodies above.  Update tiles are 64 rows x kUpdCW columns, the geometry of
+// the plan's update-tile code 2; the panels use panel_wgs' geometry, as the
+// single-matrix panels do.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_batch32_pivot(const BatchDesc *desc, const BatchItem *items, int kb) {
+    __shared__ uint32_t lds_row[2 * 128];
+    __shared__ uint32_t lds_col[2 * 128];
+    const BatchDesc d = bdev::cdesc(desc, bdev::citems(items)[blockIdx.x].graph);
+    const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
+    pivot32_tile(d.T32 + (int64_t)k0 * d.ld + k0, d.ld, bs, lds_row, lds_col);
+}
+
+__global__ void __launch_bounds__(256)
+k_batch32_panels(const BatchDesc *desc, const BatchItem *items, int n_items, int kb, int xmap) {
+    const int bid = xmap ? bdev::xcd_order((int)blockIdx.x, (int)gridDim.x, xmap) : (int)blockIdx.x;
+    const int i = bdev::find_item(items, n_items, bid);
+    const BatchDesc d = bdev::cdesc(desc, bdev::citems(items)[i].graph);
+    const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
+    int n_rowwg = 0, n_colwg = 0;
+    dev::panel_wgs(d.D, k0, bs, &n_rowwg, &n_colwg);
+    panels32_wg(d.T32, d.ld, d.D, k0, bs, n_rowwg, bid - bdev::citems(items)[i].first);
+}
+
+__global__ void __launch_bounds__(256)
+k_batch32_update(const BatchDesc *desc, const BatchItem *items, int n_items, int kb, int n_waves,
+                 int xmap) {
+    const int bid = xmap ? bdev::xcd_order((int)blockIdx.x, (int)gridDim.x, xmap) : (int)blockIdx.x;
+    const int gw = bid * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (gw >= n_waves) return;
+    const int i = bdev::find_item(items, n_items, gw);
+    const BatchDesc d = bdev::cdesc(desc, bdev::citems(items)[i].graph);
+    const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
+    int nc = 0, nr = 0;
+    const Rect q = bdev::update_rect(d.D, kb, kRW, kUpdCW, &nc, &nr);
+    const int local = gw - bdev::citems(items)[i].first;
+    // column-chunk major, as the 16-bit batch
+    int c = local / nr, rc = local % nr;
+    if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
+    if (rc >= q.r_ex0) rc += q.r_ex1 - q.r_ex0;
+    if (rc >= q.r_hi || c >= q.c_hi) return;
+    const int64_t row0 = (int64_t)rc * kRW, col0 = (int64_t)c * kUpdCW;
+    const int nrows = (int)min<int64_t>(kRW, (int64_t)d.D - row0);
+    uint32_t *dst = d.T32 + row0 * d.ld + col0;
+    const uint32_t *a = d.T32 + row0 * d.ld + k0;
+    const uint32_t *b = d.T32 + (int64_t)k0 * d.ld + col0;
+    if (col0 + kUpdCW <= d.D)
+        tile32_body<kUpdCW, true>(dst, d.ld, a, d.ld, b, d.ld, nrows, kUpdCW, bs, true, false);
+    else
+        tile32<kUpdCW>(dst, d.ld, a, d.ld, b, d.ld, nrows, (int)min<int64_t>(kUpdCW, d.D - col0),
+                       d.ld - col0, bs, true, false);
+}
+
+// Entries of every graph complemented in place (S - a), rows [32 y, 32 y +
+// 32) of graph blockIdx.x; and the diagonal of every graph := value.
+__global__ void __launch_bounds__(256) k_batch32_not(const BatchDesc *desc) {
+    const BatchDesc d = desc[blockIdx.x];
+    const int64_t r0 = (int64_t)blockIdx.y * 32;
+    if (r0 >= d.D) return;
+    const int64_t nr = min<int64_t>(32, (int64_t)d.D - r0);
+    for (int64_t g = threadIdx.x; g < nr * d.D; g += 256) {
+        uint32_t *e = d.T32 + (r0 + g / d.D) * d.ld + (g % d.D);
+        *e = ~*e;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_batch32_diag(const BatchDesc *desc, uint32_t value) {
+    const BatchDesc d = desc[blockIdx.x];
+    for (int64_t i = threadIdx.x; i < d.D; i += 256) d.T32[i * d.ld + i] = value;
 }
 
 // ---------------------------------------------------------------------------
@@ -569,6 +653,40 @@ hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, bool serial,
                                hipStream_t stream) {
     static_assert(kPanCW == 2 * dev::kPanelNW, "panel chunking of panel_wgs");
     return closure32(T, ld, D, serial, stream);
+}
+
+hipError_t launch_ad32_closure_batched_resident(const BatchPlan *plan, int64_t count,
+                                                const void *dev_buf, bool dual, bool reflexive,
+                                                hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const BatchDesc *desc = static_cast<const BatchDesc *>(dev_buf);
+    const BatchItem *items = reinterpret_cast<const BatchItem *>(
+        static_cast<const char *>(dev_buf) + batch_desc_bytes(count));
+    const unsigned ng = (unsigned)count;
+    const dim3 conv(ng, (unsigned)std::max(1, (batch_plan_max_d(plan) + 31) / 32));
+    if (dual) hipLaunchKernelGGL(k_batch32_not, conv, dim3(256), 0, st, desc);
+    const int xmap = bdev::kXcdChunk;
+    hipError_t e;
+    for (int kb = 0; kb < batch_plan_rounds(plan); kb++) {
+        const BatchLaunch a = batch_plan_phase(plan, 0, kb), b = batch_plan_phase(plan, 1, kb),
+                          c = batch_plan_phase(plan, 2, kb);
+        if (a.n_wg > 0)
+            hipLaunchKernelGGL(k_batch32_pivot, dim3(a.n_wg), dim3(256), 0, st, desc,
+                               items + a.offset, kb);
+        if (b.n_wg > 0)
+            hipLaunchKernelGGL(k_batch32_panels, dim3(b.n_wg), dim3(256), 0, st, desc,
+                               items + b.offset, b.n_items + 1, kb, xmap);
+        if (c.n_wg > 0)
+            hipLaunchKernelGGL(k_batch32_update, dim3(c.n_wg), dim3(256), 0, st, desc,
+                               items + c.offset, c.n_items + 1, kb, c.n_units, xmap);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (dual) hipLaunchKernelGGL(k_batch32_not, conv, dim3(256), 0, st, desc);
+    // the multiplicative identity's diagonal: S (anti-distance), 0 (distance)
+    if (reflexive)
+        hipLaunchKernelGGL(k_batch32_diag, dim3(ng), dim3(256), 0, st, desc,
+                           dual ? 0u : 0xFFFFFFFFu);
+    return hipGetLastError();
 }
 
 }  // namespace sr

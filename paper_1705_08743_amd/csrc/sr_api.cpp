@@ -609,8 +609,6 @@ namespace {
 int check_batch(const char *fn, int kind, void *const *T, const int64_t *ldt, const int64_t *D,
                 int64_t count, unsigned flags) {
     if (!valid_kind(kind)) return fail(SR_EINVAL, "%s: invalid kind %d", fn, kind);
-    if (base_kind(kind) == SR_ANTIDIST_U32)
-        return fail(SR_EUNSUPPORTED, "%s: 32-bit batches are not built", fn);
     if (flags & ~(unsigned)SR_REFLEXIVE) return fail(SR_EINVAL, "%s: unknown flags 0x%x", fn, flags);
     if (count < 0) return fail(SR_EINVAL, "%s: negative count", fn);
     if (count == 0) return ok();
@@ -655,12 +653,19 @@ std::vector<sr::BatchDesc> batch_descs(int kind, void *const *T, const int64_t *
         sr::BatchDesc &d = h[(size_t)i];
         d.D = (int32_t)D[g];
         d.pad = 0;
+        d.T32 = nullptr;
         if (s8) {
             d.T8 = static_cast<uint8_t *>(T[g]);
             d.ld8 = ldt[g] * unit_bytes(kind);
             d.ld = round_up(D[g], 8);
             d.T = nullptr;
             *work_elems += (size_t)(D[g] * d.ld);
+        } else if (base_kind(kind) == SR_ANTIDIST_U32) {
+            d.T8 = nullptr;
+            d.ld8 = 0;
+            d.T = nullptr;
+            d.T32 = static_cast<uint32_t *>(T[g]);
+            d.ld = ldt[g];
         } else {
             d.T8 = nullptr;
             d.ld8 = 0;
@@ -691,7 +696,10 @@ int closure_batched_impl(int kind, void *const *T, const int64_t *ldt, const int
 
 // Update-tile shape for a batch: SR_BATCH_TILE (1, 2, 3) if set, else the
 // autotuned choice for its class, else the default.
+bool batch_wide(int kind) { return base_kind(kind) == SR_ANTIDIST_U32; }
+
 int batch_tile_for(int kind, const std::vector<sr::BatchDesc> &h) {
+    if (batch_wide(kind)) return SR_BATCH_TILE_64x32;  // the one 32-bit shape
     static const int forced = [] {
         const char *v = getenv("SR_BATCH_TILE");
         const int t = v ? atoi(v) : 0;
@@ -738,7 +746,8 @@ int closure_batched_impl(int kind, void *const *T, const int64_t *ldt, const int
     if (rc != SR_OK) return rc;
     if (s8) place_working_copies(h, static_cast<char *>(w) + plan_bytes);
     hipError_t e = sr::launch_ad_closure_batched(s8, plan.get(), h.data(), count, w, is_dist(kind),
-                                                 (flags & SR_REFLEXIVE) != 0, kind == SR_BOOL, st);
+                                                 (flags & SR_REFLEXIVE) != 0, kind == SR_BOOL,
+                                                 batch_wide(kind), st);
     work_free(w, st);
     if (e != hipSuccess) return device_fail(e, "closure_batched launch");
     return ok();
@@ -883,7 +892,7 @@ void sr_autotune_clear(void) { sr::tuned_clear(); }
 struct sr_batch {
     int kind = 0;
     int device = 0;
-    bool s8 = false, dual = false, reflexive = false, bits = false;
+    bool s8 = false, dual = false, reflexive = false, bits = false, wide = false;
     int64_t count = 0;
     std::vector<sr::BatchDesc> h;  // largest first; uint8: working copies placed
     sr::BatchPlan *plan = nullptr;
@@ -953,6 +962,8 @@ int batch_create_impl(int kind, void *const *T, const int64_t *ldt, const int64_
         return fail(SR_EINVAL, "sr_batch_create: unknown tile %d", tile);
     int rc = check_batch("sr_batch_create", kind, T, ldt, D, count, flags);
     if (rc != SR_OK) return rc;
+    if (batch_wide(kind) && tile != SR_BATCH_TILE_AUTO && tile != SR_BATCH_TILE_64x32)
+        return fail(SR_EINVAL, "sr_batch_create: 32-bit batches have one tile shape, 64 x 32");
     hipStream_t st = as_stream(stream);
     if (capturing(st))
         return fail(SR_EUNSUPPORTED, "sr_batch_create: the stream is being captured");
@@ -960,6 +971,7 @@ int batch_create_impl(int kind, void *const *T, const int64_t *ldt, const int64_
     b->kind = kind;
     b->s8 = batch_in_copies(kind);
     b->bits = kind == SR_BOOL;
+    b->wide = batch_wide(kind);
     b->dual = is_dist(kind);
     b->reflexive = (flags & SR_REFLEXIVE) != 0;
     b->count = count;
@@ -1000,7 +1012,8 @@ int sr_batch_run(sr_batch *b, void *stream) {
         return fail(SR_EINVAL, "sr_batch_run: the batch belongs to device %d, current is %d",
                     b->device, dev);
     const hipError_t e = sr::launch_ad_closure_batched_resident(
-        b->s8, b->plan, b->count, b->dev, b->dual, b->reflexive, b->bits, as_stream(stream));
+        b->s8, b->plan, b->count, b->dev, b->dual, b->reflexive, b->bits, b->wide,
+        as_stream(stream));
     if (e != hipSuccess) return device_fail(e, "sr_batch_run launch");
     return ok();
 }
@@ -1039,7 +1052,7 @@ int batch_autotune_impl(sr_batch *b, int *chosen, void *stream) {
     // zero matrices of the batch's sizes and strides (each 256-byte aligned),
     // then room for a plan image; uint8 and Boolean batches reuse the
     // handle's working copies
-    const int64_t ub = b->s8 ? 1 : 2;
+    const int64_t ub = b->s8 ? 1 : unit_bytes(b->kind);
     std::vector<size_t> offs(b->h.size());
     size_t mat_bytes = 0;
     for (size_t i = 0; i < b->h.size(); i++) {
@@ -1058,12 +1071,14 @@ int batch_autotune_impl(sr_batch *b, int *chosen, void *stream) {
     for (size_t i = 0; i < th.size(); i++) {
         if (b->s8)
             th[i].T8 = reinterpret_cast<uint8_t *>(zm + offs[i]);
+        else if (b->wide)
+            th[i].T32 = reinterpret_cast<uint32_t *>(zm + offs[i]);
         else
             th[i].T = reinterpret_cast<uint16_t *>(zm + offs[i]);
     }
     int pick = 0;
     float best = 0.0f;
-    for (int t = 1; t <= 3; t++) {
+    for (int t = b->wide ? 2 : 1; t <= (b->wide ? 2 : 3); t++) {
         std::unique_ptr<sr::BatchPlan, void (*)(sr::BatchPlan *)> p(
             sr::batch_plan_create(th.data(), b->count, t), sr::batch_plan_destroy);
         if (!p || upload_image(p.get(), th, zimg, st) != hipSuccess) continue;
@@ -1072,7 +1087,7 @@ int batch_autotune_impl(sr_batch *b, int *chosen, void *stream) {
             [&] {
                 return sr::launch_ad_closure_batched_resident(b->s8, p.get(), b->count, zimg,
                                                               b->dual, b->reflexive, b->bits,
-                                                              st) ==
+                                                              b->wide, st) ==
                                hipSuccess
                            ? SR_OK
                            : SR_EDEVICE;

@@ -28,12 +28,21 @@
 #include <new>
 #include <vector>
 
+#include "sr_batch_dev.h"
 #include "sr_internal.h"
 #include "sr_tiles.h"
 
 namespace sr {
 namespace {
 
+using bdev::cdesc;
+using bdev::citems;
+using bdev::find_item;
+using bdev::Item;
+using bdev::kXcdChunk;
+using bdev::rounds_of;
+using bdev::update_rect;
+using bdev::xcd_order;
 using dev::fw_panels_wg;
 using dev::Rect;
 using dev::tile_closure;
@@ -42,84 +51,6 @@ using dev::tile_closure;
 // 2 NW columns (NW packed pairs), NW indexed by the tile code of
 // batch_plan_create (1: 64 x 16, 2: 64 x 32, 3: 64 x 64; entry 0 unused).
 constexpr int kTileNW[4] = {16, 8, 16, 32};
-
-// One entry per graph taking part in a launch; `first` is the graph's first
-// workgroup; a sentinel entry holds the launch's total.
-struct Item {
-    int32_t graph;
-    int32_t first;
-};
-
-// The work lists and descriptors are read-only while a launch runs and every
-// lookup is uniform over a wavefront, so they are read through the constant
-// address space (scalar loads, scalar cache) rather than with vector loads.
-__device__ __forceinline__ const kconst Item *citems(const Item *p) {
-    return (const kconst Item *)p;
-}
-__device__ __forceinline__ BatchDesc cdesc(const BatchDesc *desc, int g) {
-    const kconst BatchDesc *p = (const kconst BatchDesc *)desc + g;
-    BatchDesc d;
-    d.T = p->T;
-    d.ld = p->ld;
-    d.T8 = p->T8;
-    d.ld8 = p->ld8;
-    d.D = p->D;
-    d.pad = 0;
-    return d;
-}
-
-__device__ __forceinline__ int find_item(const Item *items, int n, int bid) {
-    const kconst Item *it = citems(items);
-    int lo = 0, hi = n - 1;  // largest i with it[i].first <= bid
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (it[mid].first <= bid)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
-__host__ __device__ inline int rounds_of(int D) { return (D + kAdBlock - 1) / kAdBlock; }
-
-// Workgroup bid of a launch of nwg runs on XCD bid % 8 (workgroups are handed
-// to the eight XCDs in turn).  The renumbering gives each XCD chunks of g
-// consecutive workgroups of the plan (chunk c to XCD c % 8), so that the
-// workgroups of one graph mostly run on one XCD and reuse the graph's pivot
-// row and column blocks from its L2 -- in the plain order consecutive
-// workgroups, most often of the same graph, land on eight different XCDs and
-// each L2 fetches the blocks again -- while every XCD still gets an even mix
-// of the batch's large and small graphs.  Workgroups past the last whole
-// round of 8 chunks keep their number.
-constexpr int kXcdChunk = 64;
-
-__device__ __forceinline__ int xcd_order(int bid, int nwg, int g) {
-    constexpr int kXcd = 8;
-    const int full = nwg / (kXcd * g) * (kXcd * g);
-    if (bid >= full) return bid;
-    const int x = bid % kXcd, j = bid / kXcd;
-    return ((j / g) * kXcd + x) * g + j % g;
-}
-
-// The full update rectangle of round kb for a graph of D vertices, in wave
-// tiles of RW rows x CW columns.
-__host__ __device__ inline Rect update_rect(int D, int kb, int RW, int CW, int *ncols_sel,
-                                            int *nrows_sel) {
-    const int k0 = kb * kAdBlock, bs = min(kAdBlock, D - k0);
-    Rect q;
-    q.r_lo = 0;
-    q.r_hi = (D + RW - 1) / RW;
-    q.r_ex0 = k0 / RW;
-    q.r_ex1 = (k0 + bs + RW - 1) / RW;
-    q.c_lo = 0;
-    q.c_hi = (D + CW - 1) / CW;
-    q.c_ex0 = k0 / CW;
-    q.c_ex1 = (k0 + bs + CW - 1) / CW;
-    *ncols_sel = (q.c_hi - q.c_lo) - (q.c_ex1 - q.c_ex0);
-    *nrows_sel = (q.r_hi - q.r_lo) - (q.r_ex1 - q.r_ex0);
-    return q;
-}
 
 template <bool S8>
 __global__ void __launch_bounds__(256) k_batch_pivot(const BatchDesc *desc, const Item *items, int kb) {
@@ -322,12 +253,7 @@ __global__ void __launch_bounds__(256) k_batch_diag(const BatchDesc *desc, int u
 }
 
 // Host plan: per round, the three item lists (offsets into one array).
-struct Launch {
-    int64_t offset;  // index of the first Item
-    int n_items;     // items without the sentinel
-    int n_wg;        // workgroups
-    int n_units;     // update: wave tiles
-};
+using Launch = BatchLaunch;
 
 }  // namespace
 
@@ -425,6 +351,16 @@ void batch_plan_destroy(BatchPlan *plan) { delete plan; }
 
 int batch_plan_tile(const BatchPlan *plan) { return plan->tile; }
 
+size_t batch_desc_bytes(int64_t count) { return desc_bytes_of(count); }
+
+int batch_plan_rounds(const BatchPlan *plan) { return (int)plan->pivot.size(); }
+
+BatchLaunch batch_plan_phase(const BatchPlan *plan, int phase, int kb) {
+    return phase == 0 ? plan->pivot[kb] : (phase == 1 ? plan->panels[kb] : plan->update[kb]);
+}
+
+int batch_plan_max_d(const BatchPlan *plan) { return plan->max_d; }
+
 size_t batch_plan_bytes(const BatchPlan *plan, int64_t count) {
     return desc_bytes_of(count) + plan->items.size() * sizeof(Item);
 }
@@ -439,8 +375,9 @@ void batch_plan_image(const BatchPlan *plan, const BatchDesc *host_desc, int64_t
 
 hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, int64_t count,
                                               const void *dev_buf, bool dual, bool reflexive,
-                                              bool bits, hipStream_t st) {
+                                              bool bits, bool wide, hipStream_t st) {
     if (count <= 0) return hipSuccess;
+    if (wide) return launch_ad32_closure_batched_resident(plan, count, dev_buf, dual, reflexive, st);
     const BatchPlan &p = *plan;
     const BatchDesc *desc = static_cast<const BatchDesc *>(dev_buf);
     const Item *items = reinterpret_cast<const Item *>(static_cast<const char *>(dev_buf) +
@@ -523,7 +460,7 @@ hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, in
 
 hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const BatchDesc *host_desc,
                                      int64_t count, void *dev_buf, bool dual, bool reflexive,
-                                     bool bits, hipStream_t st) {
+                                     bool bits, bool wide, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     // host image of the descriptors and item lists; freed by a stream
     // callback once the upload has executed
@@ -536,7 +473,7 @@ hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const Batch
         delete img;
     if (e != hipSuccess) return e;
     return launch_ad_closure_batched_resident(s8, plan, count, dev_buf, dual, reflexive, bits,
-                                              st);
+                                              wide, st);
 }
 
 }  // namespace sr

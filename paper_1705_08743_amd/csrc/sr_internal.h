@@ -121,6 +121,21 @@ struct BatchDesc {
     int64_t ld8;    // row stride of T8, bytes (a multiple of 16)
     int32_t D;      // vertices
     int32_t pad;
+    uint32_t *T32;  // 32-bit kinds: the caller's matrix (ld in 32-bit elements)
+};
+// One entry of a launch's work list: a graph and its first workgroup (or,
+// for the update, first wave tile); a sentinel entry holds the launch's total.
+struct BatchItem {
+    int32_t graph;
+    int32_t first;
+};
+// One launch of a round: its work list (offset into the plan's item array,
+// entries without the sentinel), workgroups and, for the update, wave tiles.
+struct BatchLaunch {
+    int64_t offset;
+    int n_items;
+    int n_wg;
+    int n_units;
 };
 // Host-side per-round work lists of a batch (they depend on the sizes and the
 // update-tile shape only).  tile: 1, 2, 3 = wave tiles of 64 x 16, 64 x 32,
@@ -132,8 +147,15 @@ struct BatchPlan;
 BatchPlan *batch_plan_create(const BatchDesc *host_desc, int64_t count, int tile);
 void batch_plan_destroy(BatchPlan *plan);
 int batch_plan_tile(const BatchPlan *plan);
-// Bytes of the device image: the descriptors, then the work lists.
+// Bytes of the device image: the descriptors (batch_desc_bytes), then the
+// work lists.
 size_t batch_plan_bytes(const BatchPlan *plan, int64_t count);
+size_t batch_desc_bytes(int64_t count);
+// Rounds of the plan, the launch of phase 0 (pivot), 1 (panels) or 2
+// (update) of round kb, and the largest graph.
+int batch_plan_rounds(const BatchPlan *plan);
+BatchLaunch batch_plan_phase(const BatchPlan *plan, int phase, int kb);
+int batch_plan_max_d(const BatchPlan *plan);
 // Writes that image (batch_plan_bytes() bytes) to host memory at dst.
 void batch_plan_image(const BatchPlan *plan, const BatchDesc *host_desc, int64_t count, void *dst);
 // dual: the batch holds distance matrices (complemented, S - a, before and
@@ -141,15 +163,21 @@ void batch_plan_image(const BatchPlan *plan, const BatchDesc *host_desc, int64_t
 // the multiplicative identity (S for anti-distance, 0 for distance, a set bit
 // for Boolean).  bits (with s8): the batch holds Boolean matrices, closed as
 // the {0, 255} anti-distance matrices of their binary16 working copies.
+// wide: 32-bit matrices (T32), by launch_ad32_closure_batched_resident.
 hipError_t launch_ad_closure_batched(bool s8, const BatchPlan *plan, const BatchDesc *host_desc,
                                      int64_t count, void *dev_buf, bool dual, bool reflexive,
-                                     bool bits, hipStream_t stream);
+                                     bool bits, bool wide, hipStream_t stream);
 // The same closure with the image already in device memory at dev_buf: kernel
 // launches only (no copy, allocation or host callback), so it can be captured
 // into a graph and replayed.
 hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, int64_t count,
                                               const void *dev_buf, bool dual, bool reflexive,
-                                              bool bits, hipStream_t stream);
+                                              bool bits, bool wide, hipStream_t stream);
+// The 32-bit batch (sr_antidist32.hip): the descriptors' T32 matrices, the
+// plan built with update tile 2 (64 x 32 entries), image at dev_buf.
+hipError_t launch_ad32_closure_batched_resident(const BatchPlan *plan, int64_t count,
+                                                const void *dev_buf, bool dual, bool reflexive,
+                                                hipStream_t stream);
 
 // Second stream of a closure (sr_runtime.cpp), one per (device, caller
 // stream), created on first use at default priority.  aux_acquire() returns it

@@ -133,8 +133,7 @@ def test_batched_rejects_bad_arguments(L):
     lds = (ctypes.c_int64 * n)(8, 8)
     dims = (ctypes.c_int64 * n)(8, 8)
     f = L.closure_batched
-    assert f(sr.SR_ANTIDIST_U32, ptrs, lds, dims, n, 0, None) == sr.SR_EUNSUPPORTED
-    assert f(sr.SR_DISTANCE_U32, ptrs, lds, dims, n, 0, None) == sr.SR_EUNSUPPORTED
+    assert f(9, ptrs, lds, dims, n, 0, None) == sr.SR_EINVAL  # no such kind
     # Boolean batches: ld in 64-bit words, even (16-byte rows)
     blds = (ctypes.c_int64 * n)(1, 1)
     bdims = (ctypes.c_int64 * n)(65, 65)
@@ -191,9 +190,15 @@ def test_u32_kinds_validation(L):
         assert L.closure(kind, P, 4, 4, sr.SR_BOOL_MFMA, None) == sr.SR_EUNSUPPORTED
         n = 1
         ptrs = (ctypes.c_void_p * n)(P)
-        lds = (ctypes.c_int64 * n)(4)
+        lds = (ctypes.c_int64 * n)(2)
         dims = (ctypes.c_int64 * n)(4)
-        assert L.closure_batched(kind, ptrs, lds, dims, n, 0, None) == sr.SR_EUNSUPPORTED
+        assert L.closure_batched(kind, ptrs, lds, dims, n, 0, None) == sr.SR_EINVAL  # ld < D
+        odd = (ctypes.c_int64 * n)(6)
+        assert L.closure_batched(kind, ptrs, odd, dims, n, 0, None) == sr.SR_EALIGN
+        h = ctypes.c_void_p(0)
+        lds4 = (ctypes.c_int64 * n)(4)
+        assert L.sr_batch_create(kind, ptrs, lds4, dims, n, 0, sr.SR_BATCH_TILE_64x16,
+                                 ctypes.byref(h), None) == sr.SR_EINVAL  # one 32-bit shape
     assert sr.padded_ld(37, sr.SR_ANTIDIST_U32) == 64
     assert sr.padded_ld(37, sr.SR_DISTANCE_U32) == 64
     assert sr.elem_bytes(sr.SR_ANTIDIST_U32) == 4
@@ -227,8 +232,8 @@ def test_prepared_batch_validation(L):
     assert f(U16, ptrs, lds, dims, n, 0, -1, ctypes.byref(h), None) == sr.SR_EINVAL
     assert f(sr.SR_BOOL, ptrs, lds, dims, n, sr.SR_ACCUMULATE, 0, ctypes.byref(h),
              None) == sr.SR_EINVAL
-    assert f(sr.SR_ANTIDIST_U32, ptrs, lds, dims, n, 0, 0, ctypes.byref(h),
-             None) == sr.SR_EUNSUPPORTED
+    assert f(sr.SR_ANTIDIST_U32, ptrs, lds, dims, n, 0, 3, ctypes.byref(h),
+             None) == sr.SR_EINVAL  # 32-bit batches: 64 x 32 tiles only
     assert f(U16, ptrs, lds, dims, -1, 0, 0, ctypes.byref(h), None) == sr.SR_EINVAL
     assert f(U16, ptrs, lds, dims, n, sr.SR_ACCUMULATE, 0, ctypes.byref(h), None) == sr.SR_EINVAL
     ptrs2 = (ctypes.c_void_p * n)(P, P + 64)

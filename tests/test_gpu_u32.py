@@ -232,11 +232,73 @@ def test_add32():
     assert np.array_equal(host(Cd), np.minimum(A, B).astype(np.int64))
 
 
-def test_batched32_is_unsupported():
-    T = dev(np.zeros((4, 4), np.uint32))
-    with pytest.raises(sr.SemiringError) as e:
-        sr.closure_batched(AD, [T])
-    assert e.value.code == sr.SR_EUNSUPPORTED
+@pytest.mark.parametrize("kind", [AD, sr.SR_DISTANCE_U32])
+@pytest.mark.parametrize("flags", [0, sr.SR_REFLEXIVE])
+def test_batched32(kind, flags):
+    """32-bit batches (list form, and a prepared batch replayed from a
+    captured graph on fresh contents): graphs of 0 to 1025 vertices with
+    ragged tiles, against the oracle's int64 loops and the per-graph
+    closure()."""
+    sizes = [130, 7, 1025, 1, 257, 0, 64, 600, 383, 33]
+    gen = synthgen.generator(9900 + kind + flags)
+
+    def mats_for(seed):
+        g = synthgen.generator(seed)
+        out = []
+        for n in sizes:
+            p = min(0.5, float(g.uniform(1.0, 4.0)) / max(n, 1))
+            out.append(rand_dist(n, n, kind, g, p=p, wmax=S // 7) if kind != AD
+                       else rand_antidist(n, n, kind, g, p=p, wmax=S // 7))
+        return out
+
+    def want(m):
+        w = oracle.dist_closure(m, S) if kind != AD else oracle.ad_closure(m, S)
+        return oracle.reflexive(w, 0 if kind != AD else S) if flags else w
+
+    mats = mats_for(int(gen.integers(1 << 30)))
+    devs = [sr.to_device(kind, m) if m.shape[0] else sr.empty(kind, 0, 0) for m in mats]
+    solo = [sr.clone(t) for t in devs]
+    sr.closure_batched(kind, devs, Ds=sizes, flags=flags)
+    for t, n in zip(solo, sizes):
+        if n:
+            sr.closure(kind, t, flags=flags)
+    torch.cuda.synchronize()
+    for t, s_, m in zip(devs, solo, mats):
+        if m.shape[0]:
+            assert np.array_equal(sr.to_host(t).astype(np.int64), want(m)), m.shape
+            assert np.array_equal(sr.to_host(t), sr.to_host(s_)), m.shape
+    # prepared and graph-captured
+    sets = [mats_for(int(gen.integers(1 << 30))) for _ in range(2)]
+    srcs = []
+    for ms in sets:
+        a = sr.BatchArena(kind, sizes)
+        a.load(ms)
+        srcs.append(a)
+    work = sr.BatchArena(kind, sizes, zero=False)
+    work.copy_(srcs[0])
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        pb = sr.PreparedBatch(kind, work, flags=flags)
+        assert pb.autotune() == sr.SR_BATCH_TILE_64x32
+        pb.run()
+    torch.cuda.synchronize()
+    for i, m in enumerate(sets[0]):
+        if m.shape[0]:
+            assert np.array_equal(sr.to_host(work.view(i)).astype(np.int64), want(m)), i
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        pb.run()
+    work.copy_(srcs[1])
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    for i, m in enumerate(sets[1]):
+        if m.shape[0]:
+            assert np.array_equal(sr.to_host(work.view(i)).astype(np.int64), want(m)), i
+    del g
+    pb.close()
+    sr.autotune_clear()
 
 
 def test_ad32_closure_rows_at_d4096():
