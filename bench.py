@@ -61,7 +61,7 @@ TRAFFIC = {
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, in bytes
     "fw8192": {"src_hash": "96ded9e9c24175ed", "bytes_per_launch": 4.967e8},   # 1.791e5 + 1.270e5 KiB
     "u8fw8192": {"src_hash": "96ded9e9c24175ed", "bytes_per_launch": 4.845e8},  # 1.731e5 + 1.270e5 KiB
-    "u32fw8192": {"src_hash": "52fb5786d930fdd0", "bytes_per_launch": 7.251e8},  # 2.256e5 + 2.569e5 KiB
+    "u32fw8192": {"src_hash": "c4166400949ed0ba", "bytes_per_launch": 7.185e8},  # 2.219e5 + 2.579e5 KiB
     # full update launches (four-Russians kernel, 32 x 32 tiles of 512 x 512
     # bits) of the serialized D = 16384 Boolean closure
     "bool16384": {"src_hash": "c7239d8046278996", "bytes_per_launch": 1.226e8},  # 4.397e4 + 3.178e4 KiB

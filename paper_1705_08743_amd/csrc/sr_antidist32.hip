@@ -113,15 +113,22 @@ __device__ __forceinline__ void tile32_body(uint32_t *C, int64_t ldc, const uint
                 // two inner steps per accumulator update: the (+) of the
                 // accumulator with both products is one v_max3_u32, so a
                 // pair of updates costs three lane-operations instead of four
+                // this group's B rows, loaded before its updates (one wait
+                // per group, as in the 16-bit tiles)
+                uint32_t bg[KU][CW];
+#pragma unroll
+                for (int kk = 0; kk < KU; kk++) {
+                    const kconst uint32_t *bp =
+                        (const kconst uint32_t *)(B + (int64_t)(k + kg + kk) * ldb);
+#pragma unroll
+                    for (int w = 0; w < CW; w++) bg[kk][w] = bp[w];
+                }
 #pragma unroll
                 for (int kk = 0; kk < KU; kk += 2) {
-                    const kconst uint32_t *b0 =
-                        (const kconst uint32_t *)(B + (int64_t)(k + kg + kk) * ldb);
-                    const kconst uint32_t *b1 =
-                        (const kconst uint32_t *)(B + (int64_t)(k + kg + kk + 1) * ldb);
 #pragma unroll
                     for (int w = 0; w < CW; w++)
-                        acc[w] = step32x2(acc[w], b0[w], na[kg + kk], b1[w], na[kg + kk + 1]);
+                        acc[w] = step32x2(acc[w], bg[kk][w], na[kg + kk], bg[kk + 1][w],
+                                          na[kg + kk + 1]);
                 }
             }
         }
