@@ -304,6 +304,11 @@ def test_prepared_batch_boolean(tile):
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
         pb = sr.PreparedBatch(sr.SR_BOOL, work, tile=tile)
+        if tile == sr.SR_BATCH_TILE_64x64:
+            # the autotuner on a Boolean batch leaves its matrices untouched
+            before = work.buf.clone()
+            assert pb.autotune() in TILES
+            assert torch.equal(work.buf, before)
         pb.run()
     torch.cuda.synchronize()
     for i, m in enumerate(sets[0]):
