@@ -254,7 +254,8 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
  * of one handle must not overlap in time (uint8 and Boolean batches share the
  * working copies).
  *
- * sr_batch_autotune times the batch with each update-tile shape on zero
+ * sr_batch_autotune times the batch with each update-tile shape (32-bit
+ * batches have one, 64 x 32) on zero
  * matrices of the same sizes (allocated for the purpose; the kernels'
  * runtimes do not depend on the entries), once to warm up and twice more;
  * keeps the fastest in the handle and in the autotuning table under the size
