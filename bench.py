@@ -585,9 +585,10 @@ def prepared_graph(torch, sr, kind, arena):
 
 
 def run_batched(args, torch, sr, synthgen):
-    """4096 graphs, log-uniform sizes in [32, 1024], uint16 (and uint8): the
-    prepared batch replayed as one graph launch, against one closure_batched
-    call and against one closure() call per graph on the same stream."""
+    """4096 graphs, log-uniform sizes in [32, 1024], uint16 (then uint8,
+    Boolean and uint32): the prepared batch replayed as one graph launch,
+    against one closure_batched call and against one closure() call per graph
+    on the same stream."""
     import numpy as np
     import oracle
     log("generating 4096 graphs ...")
@@ -696,6 +697,47 @@ def run_batched(args, torch, sr, synthgen):
         out["uint8"]["parity"] = {"graphs_checked": len(idx), "bit_exact": bool(ok8)}
     del g8
     pb8.close()
+    del work8, src8
+    # the same topologies as Boolean graphs (bit-packed, closed as {0, 255}
+    # anti-distance matrices) and with 32-bit entries, each as one graph launch
+    for name, kind in (("boolean", sr.SR_BOOL), ("uint32", sr.SR_ANTIDIST_U32)):
+        if kind == sr.SR_BOOL:
+            hm = []
+            for n, r, c, w in batch:
+                d = np.zeros((n, n), np.uint8)
+                d[r, c] = 1
+                hm.append(synthgen.pack_bits(d, synthgen.aligned_ld_words(max(n, 1))))
+        else:
+            hm = [synthgen.encode_antidist(n, r, c, w, np.uint32) for n, r, c, w in batch]
+        srcx = sr.BatchArena(kind, sizes)
+        srcx.load(hm)
+        workx = sr.BatchArena(kind, sizes, zero=False)
+        workx.copy_(srcx)
+        pbx, gx, tilex = prepared_graph(torch, sr, kind, workx)
+        tx = []
+        for _ in range(max(1, args.steps // 2)):
+            workx.copy_(srcx)
+            tx.append(timed(torch, lambda i: gx.replay(), 1))
+        out[name] = {"ms": min(tx), "value": upd / (min(tx) * 1e-3),
+                     "update_tile": TILE_NAMES.get(tilex, str(tilex))}
+        if kind == sr.SR_ANTIDIST_U32:
+            out[name]["fraction_of_valu_roofline_u32"] = upd / (min(tx) * 1e-3) / PEAK_ANTIDIST32
+        if not args.no_parity:
+            workx.copy_(srcx)
+            gx.replay()
+            torch.cuda.synchronize()
+            idx = [0, 1, len(hm) // 2, len(hm) - 1]
+            if kind == sr.SR_BOOL:
+                ok = all(np.array_equal(
+                    synthgen.unpack_bits(sr.to_host(workx.view(i)), sizes[i]),
+                    oracle.bool_closure(synthgen.unpack_bits(hm[i], sizes[i]))) for i in idx)
+            else:
+                ok = all(np.array_equal(sr.to_host(workx.view(i)).astype(np.int64),
+                                        oracle.ad_closure(hm[i], 2 ** 32 - 1)) for i in idx)
+            out[name]["parity"] = {"graphs_checked": len(idx), "bit_exact": bool(ok)}
+        del gx
+        pbx.close()
+        del workx, srcx
     return out
 
 

@@ -28,7 +28,8 @@ import numpy as np
 
 SEED_BASE = 170508743
 
-S_BY_DTYPE = {np.dtype(np.uint8): 255, np.dtype(np.uint16): 65535}
+S_BY_DTYPE = {np.dtype(np.uint8): 255, np.dtype(np.uint16): 65535,
+              np.dtype(np.uint32): 2 ** 32 - 1}
 
 
 def generator(seed):
