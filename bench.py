@@ -64,7 +64,7 @@ TRAFFIC = {
     "u32fw8192": {"src_hash": "c4166400949ed0ba", "bytes_per_launch": 7.185e8},  # 2.219e5 + 2.579e5 KiB
     # full update launches (four-Russians kernel, 32 x 32 tiles of 512 x 512
     # bits) of the serialized D = 16384 Boolean closure
-    "bool16384": {"src_hash": "c7239d8046278996", "bytes_per_launch": 1.226e8},  # 4.397e4 + 3.178e4 KiB
+    "bool16384": {"src_hash": "f5d4c58a5b788425", "bytes_per_launch": 1.226e8},  # 4.400e4 + 3.178e4 KiB
 }
 
 

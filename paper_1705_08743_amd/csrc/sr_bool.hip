@@ -36,7 +36,7 @@ namespace {
 // that are not stored.  A's bits at inner indices >= K inside the last word
 // read are never used.  FULL: nw == NWB.  Lanes >= nrows compute on row 0 and
 // store nothing.
-template <int NWB, bool FULL>
+template <int NWB, bool FULL, bool GROUPB = false>
 __device__ __forceinline__ void bool_tile_body(uint32_t *C, int64_t ldc, const uint32_t *A,
                                                int64_t lda, const uint32_t *B, int64_t ldb,
                                                int nrows, int nw, int K, bool accumulate,
@@ -82,13 +82,27 @@ __device__ __forceinline__ void bool_tile_body(uint32_t *C, int64_t ldc, const u
 #pragma unroll 1
             for (int g = 0; g < 32; g += KU) {
                 const uint32_t *b0 = B + (int64_t)(k + g) * ldb;
+                // with GROUPB the KU rows are loaded before the first update
+                // (one wait per group: the product of configuration 1's
+                // 256-vertex graph 26 -> 23 us; the closures' update kernels,
+                // with many waves in flight, do not gain and keep per-row loads)
+                uint32_t bg[GROUPB ? KU : 1][NWB];
+                if constexpr (GROUPB) {
+#pragma unroll
+                    for (int u = 0; u < KU; u++) {
+                        const kconst uint32_t *bp = (const kconst uint32_t *)(b0 + u * ldb);
+#pragma unroll
+                        for (int w = 0; w < NWB; w++) bg[u][w] = bp[w];
+                    }
+                }
 #pragma unroll
                 for (int u = 0; u < KU; u++) {
                     const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(a, g + u, 1);
                     const kconst uint32_t *brow = (const kconst uint32_t *)(b0 + u * ldb);
 #pragma unroll
                     for (int w = 0; w < NWB; w++)
-                        acc[w] = __builtin_amdgcn_bitop3_b32(brow[w], m, acc[w], 0xEA);
+                        acc[w] = __builtin_amdgcn_bitop3_b32(GROUPB ? bg[u][w] : brow[w], m,
+                                                             acc[w], 0xEA);
                 }
             }
         }
@@ -125,7 +139,7 @@ __device__ __forceinline__ void bool_tile_body(uint32_t *C, int64_t ldc, const u
 // sync_before_store the whole workgroup calls this (one barrier); in the
 // 4-word fallback sub-tiles store as they finish and the barrier comes last,
 // which is exact for the panel updates because the pivot tile is closed.
-template <int NWB>
+template <int NWB, bool GROUPB = false>
 __device__ __forceinline__ void bool_tile(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda,
                                           const uint32_t *B, int64_t ldb, int nrows, int nw,
                                           int64_t bspan, int K, bool accumulate,
@@ -136,19 +150,21 @@ __device__ __forceinline__ void bool_tile(uint32_t *C, int64_t ldc, const uint32
     }
     if (bspan >= NWB) {
         if (nw >= NWB)
-            bool_tile_body<NWB, true>(C, ldc, A, lda, B, ldb, nrows, NWB, K, accumulate,
-                                      sync_before_store);
+            bool_tile_body<NWB, true, GROUPB>(C, ldc, A, lda, B, ldb, nrows, NWB, K, accumulate,
+                                              sync_before_store);
         else
-            bool_tile_body<NWB, false>(C, ldc, A, lda, B, ldb, nrows, nw, K, accumulate,
-                                       sync_before_store);
+            bool_tile_body<NWB, false, GROUPB>(C, ldc, A, lda, B, ldb, nrows, nw, K, accumulate,
+                                               sync_before_store);
         return;
     }
     for (int c = 0; c < nw; c += 4) {
         const int n = min(4, nw - c);
         if (n == 4)
-            bool_tile_body<4, true>(C + c, ldc, A, lda, B + c, ldb, nrows, 4, K, accumulate, false);
+            bool_tile_body<4, true, GROUPB>(C + c, ldc, A, lda, B + c, ldb, nrows, 4, K,
+                                            accumulate, false);
         else
-            bool_tile_body<4, false>(C + c, ldc, A, lda, B + c, ldb, nrows, n, K, accumulate, false);
+            bool_tile_body<4, false, GROUPB>(C + c, ldc, A, lda, B + c, ldb, nrows, n, K,
+                                             accumulate, false);
     }
     if (sync_before_store) __syncthreads();
 }
@@ -161,9 +177,9 @@ k_bool_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint3
     const int64_t row0 = ((int64_t)blockIdx.y * 4 + wave) * 64;
     const int64_t w0 = (int64_t)blockIdx.x * NWB;
     if (row0 >= R) return;
-    bool_tile<NWB>(C + row0 * ldc + w0, ldc, A + row0 * lda, lda, B + w0, ldb,
-                   (int)min<int64_t>(64, R - row0), (int)min<int64_t>(NWB, nwords - w0), ldb - w0,
-                   K, accumulate != 0, false);
+    bool_tile<NWB, true>(C + row0 * ldc + w0, ldc, A + row0 * lda, lda, B + w0, ldb,
+                         (int)min<int64_t>(64, R - row0), (int)min<int64_t>(NWB, nwords - w0),
+                         ldb - w0, K, accumulate != 0, false);
 }
 
 // Warshall step k = 64P + 32h + b on the calling wave's 64 rows (row k is in
