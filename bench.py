@@ -125,46 +125,103 @@ def sync_all(torch):
     torch.cuda.synchronize()
 
 
-def cpu_baseline_fw(A, S, target_s, threads):
-    """The oracle's Warshall loop on the first m pivots of the same input
-    (bounded sample); returns updates/s and the sample description."""
-    import numpy as np
+def oracle_threads():
+    """Threads the oracle may use: the CPUs this process may run on, capped
+    by OMP_NUM_THREADS when the machine sets it (a share of a larger host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def host_cpu():
+    """The host CPU the oracle runs on: model name, logical CPUs of the
+    machine, CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 1
+    return {"model": model, "logical_cpus": os.cpu_count(), "cpus_allowed": allowed,
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
+def oracle_fw(A, S, dual, threads):
+    """The oracle's whole Warshall loop on the input (distance loop for
+    distance matrices), on `threads` threads: (result, seconds)."""
     import oracle
     oracle.set_threads(threads)
-    D = A.shape[0]
-    A32 = np.ascontiguousarray(A[:, :D], dtype=np.int64 if S > 2 ** 31 - 1 else np.int32)
-    # size the sample from two short calibration runs: their difference is
-    # the cost of m0 pivots without the fixed per-call cost (copies, threads)
-    m0 = min(D, 32)
     t0 = time.perf_counter()
-    oracle.ad_closure(A32, S, k_end=m0)
+    want = oracle.dist_closure(A, S) if dual else oracle.ad_closure(A, S)
+    return want, time.perf_counter() - t0
+
+
+def oracle_fw_one_thread(A, S, dual, target_s):
+    """The oracle's loop on one thread over the first m pivots of the same
+    input (m sized to about target_s seconds): updates/s and the sample."""
+    import numpy as np
+    import oracle
+    oracle.set_threads(1)
+    D = A.shape[0]
+    if dual:
+        # the distance loop has no prefix entry point; its anti-distance twin
+        # on the complemented input does the same work per pivot
+        A = (S - A.astype(np.int64))
+    A = np.ascontiguousarray(A, dtype=np.int64 if S > 2 ** 31 - 1 else np.int32)
+    m0 = min(D, 4)
+    t0 = time.perf_counter()
+    oracle.ad_closure(A, S, k_end=m0)
     t1 = time.perf_counter()
-    oracle.ad_closure(A32, S, k_end=2 * m0)
+    oracle.ad_closure(A, S, k_end=2 * m0)
     t2 = time.perf_counter()
     per_pivot = max((t2 - t1) - (t1 - t0), 1e-9) / m0
     m = int(max(m0, min(D, target_s / per_pivot)))
     t0 = time.perf_counter()
-    oracle.ad_closure(A32, S, k_end=m)
+    oracle.ad_closure(A, S, k_end=m)
     dt = time.perf_counter() - t0
     upd = float(m) * D * D
-    return upd / dt, ("first %d of %d Warshall pivots on the same D=%d input (%.3g updates, %.1f s)"
-                      % (m, D, D, upd, dt)), threads
+    return upd / dt, ("first %d of %d Warshall pivots of the same input on 1 thread "
+                      "(%.3g updates, %.1f s)" % (m, D, upd, dt))
 
 
-def parity_rows(result_host, A, S, nrows, seed, dual=False):
-    """Sampled rows of the GPU result against the oracle's path definition
-    (for distance matrices through the De Morgan law, not closure(not A))."""
+def arena_mats(arena, dtype):
+    """Host copies of every matrix of a BatchArena (one device-to-host copy)."""
     import numpy as np
-    import oracle
-    D = A.shape[0]
-    rows = np.sort(np.random.default_rng(seed).choice(D, size=nrows, replace=False))
-    if dual:
-        nA = (S - A[:, :D].astype(np.int64)).astype(np.int32)
-        want = S - oracle.ad_closure_rows(nA, S, rows).astype(np.int64)
-    else:
-        want = oracle.ad_closure_rows(A[:, :D], S, rows)
-    ok = bool(np.array_equal(result_host[rows, :D].astype(np.int64), want.astype(np.int64)))
-    return {"rows_checked": int(nrows), "bit_exact": ok}
+    img = arena.buf.cpu().numpy()
+    es = np.dtype(dtype).itemsize
+    out = []
+    for i in range(arena.count):
+        n, ld, off = int(arena.sizes[i]), int(arena.lds[i]), int(arena.offsets[i])
+        w = -(-n // 64) if dtype == np.uint64 else n
+        out.append(img[off:off + n * ld * es].view(dtype).reshape(n, ld)[:, :w])
+    return out
+
+
+def oracle_batch_parity(got, mats, close):
+    """Every graph of a batch against the oracle (close(m) -> its closure):
+    (graphs that differ, seconds the oracle took)."""
+    import numpy as np
+    bad = 0
+    t = 0.0
+    for g, m in zip(got, mats):
+        t0 = time.perf_counter()
+        want = close(m)
+        t += time.perf_counter() - t0
+        if not np.array_equal(g.astype(want.dtype), want):
+            bad += 1
+    return bad, t
 
 
 def kernel_timing_pass(args, torch, sr, kind, src, bufs, close):
@@ -246,13 +303,23 @@ def run_fw(args, torch, sr, kind, D, make_input, workload, S, metric, dual=False
         "phases": phases,
         "fraction_of_valu_roofline_whole_step": float(D) ** 3 / (ms_step * 1e-3) / peak,
     }
-    if not args.no_parity:
-        out["parity"] = parity_rows(sr.to_host(bufs[-1]), host, S, args.parity_rows, 7, dual)
-    if not args.no_cpu_baseline:
-        log("timing the oracle on the host ...")
-        v, sample, cores = cpu_baseline_fw(host, S, args.cpu_seconds, args.cpu_threads)
-        out["cpu_baseline"] = {"value": v, "unit": "updates/s", "cores": cores, "kind": "oracle",
-                               "sample": sample}
+    if not args.no_parity or not args.no_cpu_baseline:
+        log("the oracle's whole closure on %d host threads ..." % args.cpu_threads)
+        want, dt = oracle_fw(host, S, dual, args.cpu_threads)
+        if not args.no_parity:
+            got = sr.to_host(bufs[-1])
+            out["parity"] = {"entries_compared": int(got.size), "whole_matrix": True,
+                             "bit_exact": bool(np.array_equal(got.astype(want.dtype), want))}
+        del want
+        if not args.no_cpu_baseline:
+            v1, sample1 = oracle_fw_one_thread(host, S, dual, args.cpu1_seconds)
+            out["cpu_baseline"] = {
+                "value": float(D) ** 3 / dt, "unit": "updates/s", "cores": args.cpu_threads,
+                "kind": "oracle",
+                "sample": "the whole closure of the same D=%d input (%.3g updates, %.1f s, "
+                          "%d threads)" % (D, float(D) ** 3, dt, args.cpu_threads),
+                "seconds": dt, "cpu": host_cpu(),
+                "one_thread": {"value": v1, "unit": "updates/s", "sample": sample1}}
     return out
 
 
@@ -302,11 +369,23 @@ def run_bool(args, torch, sr, synthgen):
                         "frac": achieved / PEAK_BOOL, "traffic": traffic_of("bool16384"),
                         "note": "nominal D^3 bit updates; peak = one v_bitop3 per 32 updates"},
            "phases": phases}
-    if not args.no_parity:
-        rows = np.sort(np.random.default_rng(3).choice(D, size=args.parity_rows, replace=False))
-        got = sr.to_host(bufs[-1])[rows, : D // 64]
-        want = oracle.bool_closure_rows_words(W, D, rows)
-        out["parity"] = {"rows_checked": len(rows), "bit_exact": bool(np.array_equal(got, want))}
+    if not args.no_parity or not args.no_cpu_baseline:
+        oracle.set_threads(args.cpu_threads)
+        t0 = time.perf_counter()
+        want = oracle.bool_closure_words(W, D)
+        dt = time.perf_counter() - t0
+        nw = D // 64
+        if not args.no_parity:
+            got = sr.to_host(bufs[-1])
+            out["parity"] = {"words_compared": int(D * nw), "whole_matrix": True,
+                             "bit_exact": bool(np.array_equal(got[:, :nw], want[:, :nw])
+                                               and synthgen.padding_bits_clear(got, D))}
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = {
+                "value": float(D) ** 3 / dt, "unit": "updates/s", "cores": args.cpu_threads,
+                "kind": "oracle",
+                "sample": "the whole bit-packed Warshall loop on the same input (%.1f s)" % dt,
+                "cpu": host_cpu()}
     return out
 
 
@@ -459,11 +538,11 @@ def run_boolmul(args, torch, sr, synthgen):
     torch.cuda.synchronize()
     out["paths_equal"] = bool(torch.equal(C1, C2) and torch.equal(C1, C3))
     if not args.no_parity:
-        rows = np.array([0, 1, D // 2, D - 1])
-        want = oracle.bool_mul_words(W[rows], W, D, D)
+        oracle.set_threads(args.cpu_threads)
+        want = oracle.bool_mul_words(W, W, D, D)
         nw = D // 64
-        out["parity"] = {"rows_checked": len(rows), "bit_exact": bool(
-            np.array_equal(sr.to_host(C1)[rows, :nw], want[:, :nw]))}
+        out["parity"] = {"words_compared": int(D * nw), "whole_matrix": True,
+                         "bit_exact": bool(np.array_equal(sr.to_host(C1)[:, :nw], want[:, :nw]))}
     return out
 
 
@@ -636,7 +715,7 @@ def run_batched(args, torch, sr, synthgen):
            "closure_batched_ms": tb, "serial_ms": ts, "speedup_vs_serial": ts / tg,
            "total_updates": upd,
            "fraction_of_valu_roofline": upd / (tg * 1e-3) / PEAK_ANTIDIST}
-    if not args.no_parity:
+    if not args.no_parity or not args.no_cpu_baseline:
         reset()
         g.replay()
         ref = sr.BatchArena(kind, sizes, zero=False)
@@ -645,27 +724,21 @@ def run_batched(args, torch, sr, synthgen):
         torch.cuda.synchronize()
         same = bool(torch.equal(ref.buf, work.buf))
         del ref
-        idx = [0, 1, len(mats) // 2, len(mats) - 1]
-        ok = all(np.array_equal(sr.to_host(views[i]).astype(np.int64),
-                                oracle.ad_closure(mats[i], 65535)) for i in idx)
-        out["parity"] = {"graphs_checked": len(idx), "bit_exact": bool(ok),
-                         "graph_replay_equals_closure_batched": same}
+        log("the oracle on all %d graphs ..." % len(mats))
+        oracle.set_threads(args.cpu_threads)
+        bad, dt = oracle_batch_parity(arena_mats(work, np.uint16), mats,
+                                      lambda m: oracle.ad_closure(m, 65535))
+        if not args.no_parity:
+            out["parity"] = {"graphs_compared": len(mats), "graphs_differing": bad,
+                             "bit_exact": bad == 0, "graph_replay_equals_closure_batched": same}
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = {"value": upd / dt, "unit": "updates/s",
+                                   "cores": args.cpu_threads, "kind": "oracle",
+                                   "sample": "the whole batch, one oracle closure per graph "
+                                             "(%.3g updates, %.1f s)" % (upd, dt),
+                                   "seconds": dt, "cpu": host_cpu()}
     del g
     pb.close()
-    if not args.no_cpu_baseline:
-        # the oracle on every 32nd graph of the batch, scaled by the updates
-        oracle.set_threads(args.cpu_threads)
-        sample = list(range(0, len(mats), 32))
-        su = float(sum(float(sizes[i]) ** 3 for i in sample))
-        t0 = time.perf_counter()
-        for i in sample:
-            oracle.ad_closure(mats[i], 65535)
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": su / dt, "unit": "updates/s", "cores": args.cpu_threads,
-                               "kind": "oracle",
-                               "sample": "every 32nd graph of the batch (%d graphs, %.3g updates, "
-                                         "%.1f s); whole batch at that rate: %.1f s"
-                                         % (len(sample), su, dt, upd / (su / dt))}
     # the same 4096 topologies and distances as uint8 (binary16 working form)
     mats8 = [synthgen.encode_antidist(n, r, c, w, np.uint8) for n, r, c, w in batch]
     del work, views
@@ -691,10 +764,10 @@ def run_batched(args, torch, sr, synthgen):
         work8.copy_(src8)
         g8.replay()
         torch.cuda.synchronize()
-        idx = [0, 1, len(mats8) // 2, len(mats8) - 1]
-        ok8 = all(np.array_equal(sr.to_host(work8.view(i)).astype(np.int64),
-                                 oracle.ad_closure(mats8[i], 255)) for i in idx)
-        out["uint8"]["parity"] = {"graphs_checked": len(idx), "bit_exact": bool(ok8)}
+        bad8, _ = oracle_batch_parity(arena_mats(work8, np.uint8), mats8,
+                                      lambda m: oracle.ad_closure(m, 255))
+        out["uint8"]["parity"] = {"graphs_compared": len(mats8), "graphs_differing": bad8,
+                                  "bit_exact": bad8 == 0}
     del g8
     pb8.close()
     del work8, src8
@@ -726,15 +799,15 @@ def run_batched(args, torch, sr, synthgen):
             workx.copy_(srcx)
             gx.replay()
             torch.cuda.synchronize()
-            idx = [0, 1, len(hm) // 2, len(hm) - 1]
             if kind == sr.SR_BOOL:
-                ok = all(np.array_equal(
-                    synthgen.unpack_bits(sr.to_host(workx.view(i)), sizes[i]),
-                    oracle.bool_closure(synthgen.unpack_bits(hm[i], sizes[i]))) for i in idx)
+                bad, _ = oracle_batch_parity(
+                    arena_mats(workx, np.uint64), hm,
+                    lambda m: oracle.bool_closure_words(m, m.shape[0])[:, :-(-m.shape[0] // 64)])
             else:
-                ok = all(np.array_equal(sr.to_host(workx.view(i)).astype(np.int64),
-                                        oracle.ad_closure(hm[i], 2 ** 32 - 1)) for i in idx)
-            out[name]["parity"] = {"graphs_checked": len(idx), "bit_exact": bool(ok)}
+                bad, _ = oracle_batch_parity(arena_mats(workx, np.uint32), hm,
+                                             lambda m: oracle.ad_closure(m, 2 ** 32 - 1))
+            out[name]["parity"] = {"graphs_compared": len(hm), "graphs_differing": bad,
+                                   "bit_exact": bad == 0}
         del gx
         pbx.close()
         del workx, srcx
@@ -754,9 +827,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--parity-rows", type=int, default=4)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--cpu1-seconds", type=float, default=5.0,
+                    help="bound of the one-thread oracle sample")
+    ap.add_argument("--cpu-threads", type=int, default=oracle_threads())
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

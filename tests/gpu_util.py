@@ -41,5 +41,18 @@ def rand_bits(R, C, gen, p=0.1):
     return (gen.random((R, C)) < p).astype(np.uint8)
 
 
+def oracle_threads():
+    """Threads the oracle may use: the CPUs this process may run on, capped
+    by OMP_NUM_THREADS when the machine sets it (a share of a larger host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
 def set_oracle_threads():
-    oracle.set_threads(min(16, os.cpu_count() or 1))
+    oracle.set_threads(oracle_threads())

@@ -1,10 +1,12 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
 times (default flags: phases overlapped on two streams).
 
-The oracle cannot run the full D^3 loops here in seconds, so it computes
-sampled rows one by one from the path definition of the closure (Dijkstra /
-breadth-first search per source); properties that hold at any size are
-checked on the whole matrix with the GPU product.
+Every entry of every result is compared with the oracle's own loops (the
+Warshall loop of Sec. II / Sec. III, the multiplication algorithm, the
+bit-packed Boolean loops), run once on all host threads the process may use.
+Each entry of a closure is fixed by eq. (trcl) and each product entry by the
+product's definition, so the comparison is exact equality.  Invariants on
+the GPU result (T >= A, overlapped schedule = serial schedule) are extras.
 """
 import numpy as np
 import pytest
@@ -26,138 +28,48 @@ def _setup():
     set_oracle_threads()
 
 
-def sample_rows(D, n, seed):
-    rng = np.random.default_rng(seed)
-    rows = rng.choice(D, size=n, replace=False)
-    return np.sort(np.concatenate([rows, [0, D - 1]]).astype(np.int64))
+def _close(kind, A, flags=0):
+    T = sr.to_device(kind, A)
+    sr.closure(kind, T, flags=flags)
+    torch.cuda.synchronize()
+    return sr.to_host(T)
+
+
+def _headline_input(kind, D):
+    if kind == sr.SR_ANTIDIST_U16:
+        return synthgen.cfg_antidist(D=D)[:, :D], 65535
+    return synthgen.cfg_antidist_u8(D=D)[:, :D], 255
 
 
 @pytest.mark.parametrize("kind", [sr.SR_ANTIDIST_U16, sr.SR_ANTIDIST_U8])
 def test_headline_closure_d8192(kind):
+    """D = 8192 closure (uint16 headline and its uint8 variant): every entry
+    against the oracle's Warshall loop, both schedules."""
     D = 8192
-    if kind == sr.SR_ANTIDIST_U16:
-        A = synthgen.cfg_antidist(D=D)[:, :D]
-        S = 65535
-    else:
-        A = synthgen.cfg_antidist_u8(D=D)[:, :D]
-        S = 255
-    dA = sr.to_device(kind, A)
-    T = dA.clone()
-    sr.closure(kind, T)
-    T2 = dA.clone()
-    sr.closure(kind, T2, flags=sr.SR_SERIAL_PHASES)
-    torch.cuda.synchronize()
-    H = sr.to_host(T)
-    # sampled rows against the oracle's path definition
-    rows = sample_rows(D, 10, 11 + kind)
-    want = oracle.ad_closure_rows(A, S, rows)
-    assert np.array_equal(H[rows].astype(np.int64), want.astype(np.int64))
-    # both schedules give the same bits
-    assert torch.equal(T, T2)
-    # properties on the whole matrix: T >= A and T (+) T*T = T
-    assert (H >= A).all()
-    TT = sr.empty(kind, D, D)
-    sr.semiring_mul(kind, TT, T, T)
-    sr.semiring_add(kind, TT, TT, T)
-    torch.cuda.synchronize()
-    assert torch.equal(TT, T)
+    A, S = _headline_input(kind, D)
+    got = _close(kind, A)
+    want = oracle.ad_closure(A, S)
+    assert np.array_equal(got.astype(np.int32), want)
+    got_serial = _close(kind, A, sr.SR_SERIAL_PHASES)
+    assert np.array_equal(got_serial.astype(np.int32), want)
+    assert (got >= A).all()
 
 
-def test_product_config2_full_and_d8192_rows():
-    """uint16 product at D = 8192: sampled rows of A * B against the oracle's
-    multiplication loop on those rows."""
-    D = 8192
-    A = synthgen.cfg_antidist(D=D, which=0)[:, :D]
-    B = synthgen.cfg_antidist(D=D, which=1)[:, :D]
-    C = sr.empty(sr.SR_ANTIDIST_U16, D, D)
-    sr.semiring_mul(sr.SR_ANTIDIST_U16, C, sr.to_device(sr.SR_ANTIDIST_U16, A),
-                    sr.to_device(sr.SR_ANTIDIST_U16, B))
-    torch.cuda.synchronize()
-    rows = sample_rows(D, 6, 5)
-    want = oracle.ad_mul(A[rows], B, 65535)
-    assert np.array_equal(sr.to_host(C)[rows].astype(np.int64), want)
-
-
-def test_bool_closure_config3():
-    """Configuration 3: Boolean D = 16384, mean out-degree 3 plus planted
-    strongly connected blocks; sampled rows against breadth-first search and
-    T | T*T = T on the whole matrix."""
-    D = 16384
-    W = synthgen.cfg_bool16384(D=D)
-    T = sr.to_device(sr.SR_BOOL, W, cols=D)
-    sr.closure(sr.SR_BOOL, T, D=D)
-    torch.cuda.synchronize()
-    H = sr.to_host(T)
-    rows = sample_rows(D, 12, 3)
-    want = oracle.bool_closure_rows_words(W, D, rows)
-    nw = D // 64
-    assert np.array_equal(H[rows, :nw], want[:, :nw])
-    assert synthgen.padding_bits_clear(H[:64], D)
-    TT = sr.empty(sr.SR_BOOL, D, D)
-    sr.semiring_mul(sr.SR_BOOL, TT, T, T, K=D, N=D)
-    sr.semiring_add(sr.SR_BOOL, TT, TT, T, N=D)
-    torch.cuda.synchronize()
-    assert torch.equal(TT, T)
-
-
-def test_bool_closure_config3_paths_agree():
-    """At D = 16384 the default bulk update (four-Russians tables) and the
-    bit-sliced one give the same closure."""
-    D = 16384
-    W = synthgen.cfg_bool16384(D=D)
-    T1 = sr.to_device(sr.SR_BOOL, W, cols=D)
-    T2 = sr.clone(T1)
-    sr.closure(sr.SR_BOOL, T1, D=D)
-    sr.closure(sr.SR_BOOL, T2, D=D, flags=sr.SR_BOOL_BITWISE)
-    torch.cuda.synchronize()
-    assert torch.equal(T1, T2)
-
-
-def test_bool_product_d8192_rows():
-    """Boolean product at D = 8192 (the size picks the four-Russians path):
-    sampled rows against the oracle, and the bit-sliced path agrees."""
-    D = 8192
-    gen = synthgen.generator(8192)
-    ld = synthgen.aligned_ld_words(D)
-    Aw = synthgen.pack_bits((gen.random((D, D)) < 0.002).astype(np.uint8), ld)
-    Bw = synthgen.pack_bits((gen.random((D, D)) < 0.002).astype(np.uint8), ld)
-    dA, dB = sr.to_device(sr.SR_BOOL, Aw, cols=D), sr.to_device(sr.SR_BOOL, Bw, cols=D)
-    C1 = sr.empty(sr.SR_BOOL, D, D)
-    C2 = sr.empty(sr.SR_BOOL, D, D)
-    sr.semiring_mul(sr.SR_BOOL, C1, dA, dB, K=D, N=D)
-    sr.semiring_mul(sr.SR_BOOL, C2, dA, dB, K=D, N=D, flags=sr.SR_BOOL_BITWISE)
-    torch.cuda.synchronize()
-    assert torch.equal(C1, C2)
-    rows = sample_rows(D, 8, 9)
-    want = oracle.bool_mul_words(Aw[rows], Bw, D, D)
-    assert np.array_equal(sr.to_host(C1)[rows, :D // 64], want[:, :D // 64])
-
-
-def test_batched_config4_sample():
-    """Configuration 4 (4096 graphs, log-uniform sizes) in one launch; a
-    sample of graphs against the oracle, every graph against its solo run."""
-    kind = sr.SR_ANTIDIST_U16
-    batch = synthgen.cfg_batch()
-    mats = [synthgen.encode_antidist(n, r, c, w, np.uint16) for n, r, c, w in batch]
-    devs = [sr.to_device(kind, m) for m in mats]
-    solo = {i: sr.clone(devs[i]) for i in range(0, len(mats), 64)}
-    sr.closure_batched(kind, devs)
-    for t in solo.values():
-        sr.closure(kind, t)
-    torch.cuda.synchronize()
-    for i, t in solo.items():
-        assert torch.equal(devs[i], t), i
-    idx = np.argsort([m.shape[0] for m in mats])
-    for i in list(idx[:3]) + list(idx[-2:]) + [int(idx[len(idx) // 2])]:
-        want = oracle.ad_closure(mats[i], 65535)
-        assert np.array_equal(sr.to_host(devs[i]).astype(np.int64), want), mats[i].shape
+@pytest.mark.parametrize("kind,D", [(sr.SR_ANTIDIST_U16, 7001), (sr.SR_ANTIDIST_U8, 6500)])
+def test_closure_ragged_above_6144(kind, D):
+    """Above 6144 vertices the lookahead runs as whole-K launches; a ragged
+    last pivot block (7001 = 54 * 128 + 89; 6500 = 50 * 128 + 100) leaves a
+    partial last column chunk.  Every entry against the oracle."""
+    A, S = _headline_input(kind, D)
+    want = oracle.ad_closure(A, S)
+    assert np.array_equal(_close(kind, A).astype(np.int32), want)
 
 
 def test_distance_closure_d8192():
-    """Distance form of the headline input (entries = distances, S = no path):
-    sampled rows against the oracle's path definition through the De Morgan
-    law (not dransclose(A) = transclose(not A)), and the reflexive form's
-    diagonal."""
+    """The headline input as a distance matrix (entries = distances, S = no
+    path), closed with min and saturating +: every entry against the
+    oracle's distance Warshall loop; the reflexive form has a zero diagonal
+    and the same off-diagonal entries."""
     D = 8192
     S = 65535
     kind = sr.SR_DISTANCE_U16
@@ -167,11 +79,116 @@ def test_distance_closure_d8192():
     sr.closure(kind, T)
     sr.closure(kind, T2, flags=sr.SR_REFLEXIVE)
     torch.cuda.synchronize()
-    H = sr.to_host(T)
-    rows = sample_rows(D, 6, 21)
-    want = S - oracle.ad_closure_rows((S - A.astype(np.int64)).astype(np.int32), S, rows)
-    assert np.array_equal(H[rows].astype(np.int64), want.astype(np.int64))
-    H2 = sr.to_host(T2)
-    assert (np.diagonal(H2) == 0).all()
+    got = sr.to_host(T)
+    want = oracle.dist_closure(A, S)
+    assert np.array_equal(got.astype(np.int32), want)
+    del want
+    got2 = sr.to_host(T2)
+    assert (np.diagonal(got2) == 0).all()
     off = ~np.eye(D, dtype=bool)
-    assert np.array_equal(H2[off], H[off])
+    assert np.array_equal(got2[off], got[off])
+
+
+def test_u32_closure_d8192():
+    """The headline distances with 32-bit entries (S = 2^32 - 1): every
+    entry against the oracle's int64 Warshall loop."""
+    D = 8192
+    S = 2 ** 32 - 1
+    A16 = synthgen.cfg_antidist(D=D)[:, :D].astype(np.int64)
+    A = np.where(A16 > 0, S - (65535 - A16), 0).astype(np.uint32)
+    del A16
+    got = _close(sr.SR_ANTIDIST_U32, A)
+    want = oracle.ad_closure(A, S)
+    assert np.array_equal(got.astype(np.int64), want)
+
+
+def test_product_d8192():
+    """uint16 product A * B of two D = 8192 graphs: every entry against the
+    oracle's multiplication loop."""
+    D = 8192
+    A = synthgen.cfg_antidist(D=D, which=0)[:, :D]
+    B = synthgen.cfg_antidist(D=D, which=1)[:, :D]
+    C = sr.empty(sr.SR_ANTIDIST_U16, D, D)
+    sr.semiring_mul(sr.SR_ANTIDIST_U16, C, sr.to_device(sr.SR_ANTIDIST_U16, A),
+                    sr.to_device(sr.SR_ANTIDIST_U16, B))
+    torch.cuda.synchronize()
+    want = oracle.ad_mul(A, B, 65535)
+    assert np.array_equal(sr.to_host(C).astype(np.int32), want)
+
+
+@pytest.fixture(scope="module")
+def cfg3():
+    """Configuration 3's input and its closure by the oracle's bit-packed
+    Warshall loop (computed once for the tests below)."""
+    D = 16384
+    W = synthgen.cfg_bool16384(D=D)
+    return D, W, oracle.bool_closure_words(W, D)
+
+
+@pytest.mark.parametrize("flags", [0, sr.SR_BOOL_BITWISE, sr.SR_BOOL_M4R])
+def test_bool_closure_config3(cfg3, flags):
+    """Configuration 3: Boolean D = 16384, mean out-degree 3 plus planted
+    strongly connected blocks; every word against the oracle for the default
+    bulk update and each forced one (bit-sliced, four-Russians tables, int8
+    matrix cores); padding bits stay clear."""
+    D, W, want = cfg3
+    T = sr.to_device(sr.SR_BOOL, W, cols=D)
+    sr.closure(sr.SR_BOOL, T, D=D, flags=flags)
+    torch.cuda.synchronize()
+    got = sr.to_host(T)
+    nw = D // 64
+    assert np.array_equal(got[:, :nw], want[:, :nw])
+    assert synthgen.padding_bits_clear(got, D)
+
+
+@pytest.mark.parametrize("flags", [0, sr.SR_BOOL_BITWISE, sr.SR_BOOL_MFMA])
+def test_bool_product_config3(cfg3, flags):
+    """Configuration 3's product A * A (D = 16384) on each path: every word
+    against the oracle's bit-packed multiplication loop."""
+    D, W, _ = cfg3
+    A = sr.to_device(sr.SR_BOOL, W, cols=D)
+    C = sr.empty(sr.SR_BOOL, D, D)
+    sr.semiring_mul(sr.SR_BOOL, C, A, A, K=D, N=D, flags=flags)
+    torch.cuda.synchronize()
+    want = oracle.bool_mul_words(W, W, D, D)
+    nw = D // 64
+    assert np.array_equal(sr.to_host(C)[:, :nw], want[:, :nw])
+
+
+def test_bool_product_d8192():
+    """Boolean product at D = 8192 (the size picks the four-Russians path):
+    every word against the oracle."""
+    D = 8192
+    gen = synthgen.generator(8192)
+    ld = synthgen.aligned_ld_words(D)
+    Aw = synthgen.pack_bits((gen.random((D, D)) < 0.002).astype(np.uint8), ld)
+    Bw = synthgen.pack_bits((gen.random((D, D)) < 0.002).astype(np.uint8), ld)
+    dA, dB = sr.to_device(sr.SR_BOOL, Aw, cols=D), sr.to_device(sr.SR_BOOL, Bw, cols=D)
+    C = sr.empty(sr.SR_BOOL, D, D)
+    sr.semiring_mul(sr.SR_BOOL, C, dA, dB, K=D, N=D)
+    torch.cuda.synchronize()
+    want = oracle.bool_mul_words(Aw, Bw, D, D)
+    assert np.array_equal(sr.to_host(C)[:, :D // 64], want[:, :D // 64])
+
+
+@pytest.mark.parametrize("dtype", [np.uint16, np.uint8])
+def test_batched_config4_all_graphs(dtype):
+    """Configuration 4: 4096 graphs of log-uniform sizes in [32, 1024],
+    closed by one call; every entry of every graph against the oracle."""
+    kind = sr.SR_ANTIDIST_U16 if dtype == np.uint16 else sr.SR_ANTIDIST_U8
+    S = 65535 if dtype == np.uint16 else 255
+    batch = synthgen.cfg_batch()
+    mats = [synthgen.encode_antidist(n, r, c, w, dtype) for n, r, c, w in batch]
+    arena = sr.BatchArena(kind, [m.shape[0] for m in mats])
+    arena.load(mats)
+    sr.closure_batched(kind, arena)
+    torch.cuda.synchronize()
+    img = arena.buf.cpu().numpy()
+    es = np.dtype(dtype).itemsize
+    bad = []
+    for i, m in enumerate(mats):
+        n, ld, off = int(arena.sizes[i]), int(arena.lds[i]), int(arena.offsets[i])
+        got = img[off:off + n * ld * es].view(dtype).reshape(n, ld)[:, :n]
+        if not np.array_equal(got.astype(np.int32), oracle.ad_closure(m, S)):
+            bad.append((i, n))
+    assert not bad, bad[:10]
