@@ -197,6 +197,28 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
 int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream);
 
 /*
+ * closure_noalloc -- closure() without any allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, flags, result and errors
+ * as closure().  The working memory closure() would allocate (the binary16
+ * copy of uint8 data: 2 * D * round_up(D, 64) bytes; the squaring closure's
+ * two matrices: 2 * D * round_up(D, 64) * entry bytes + 256, for uint8 data
+ * 2-byte entries; a big pivot block's: 2 * 512 * 512 * 2 + 256) comes from a
+ * static device array of 32 MiB that each device the library runs on holds
+ * until the process ends.  A method chosen by default whose working memory
+ * does not fit falls back to the blocked loop; if that still does not fit (a
+ * uint8 or uint8-distance matrix above 4096 vertices), or a forced method
+ * (SR_CLOSURE_SQUARING, SR_CLOSURE_BIG_BLOCKS) does not, the call returns
+ * SR_EINVAL before enqueueing anything.  No stream or event is created either:
+ * the second stream of the overlapped schedule is used only if an earlier
+ * closure() on the same stream created it, else the phases run in order on
+ * `stream`.  Every call on one device shares that device's array (the
+ * closure clears what must start at zero): calls whose work overlaps in
+ * time on one device race and must be serialized by the caller.
+ */
+int closure_noalloc(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream);
+
+/*
  * closure_batched -- `count` independent in-place closures, as closure()
  * applied to each (T[g], ldt[g], D[g]).  The three arrays are HOST arrays of
  * length count; T[g] are device pointers, each obeying the alignment rules

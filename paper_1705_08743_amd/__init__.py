@@ -81,7 +81,8 @@ ERROR_NAMES = {
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsemiring.so")
 
-EXPORTS = ("semiring_mul", "semiring_add", "semiring_ewise", "closure", "closure_batched",
+EXPORTS = ("semiring_mul", "semiring_add", "semiring_ewise", "closure", "closure_noalloc",
+           "closure_batched",
            "sr_autotune_closure", "sr_autotune_mul", "sr_autotune_clear",
            "sr_batch_create", "sr_batch_run", "sr_batch_autotune", "sr_batch_tile",
            "sr_batch_destroy",
@@ -120,6 +121,8 @@ def lib():
         L.semiring_ewise.restype = i32
         L.closure.argtypes = [i32, vp, i64, i64, u32, vp]
         L.closure.restype = i32
+        L.closure_noalloc.argtypes = [i32, vp, i64, i64, u32, vp]
+        L.closure_noalloc.restype = i32
         L.closure_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                       ctypes.POINTER(i64), i64, u32, vp]
         L.closure_batched.restype = i32
@@ -242,6 +245,15 @@ def closure(kind, T, D=None, flags=0, stream=None):
     pt, ldt, rt, ct = _mat(T, "T")
     D = rt if D is None else D
     _check(lib().closure(kind, pt, ldt, D, flags, _stream(stream)))
+
+
+def closure_noalloc(kind, T, D=None, flags=0, stream=None):
+    """closure() without allocation: working memory from the library's static
+    per-device scratch (32 MiB); raises SemiringError (SR_EINVAL) for sizes
+    whose working memory does not fit."""
+    pt, ldt, rt, ct = _mat(T, "T")
+    D = rt if D is None else D
+    _check(lib().closure_noalloc(kind, pt, ldt, D, flags, _stream(stream)))
 
 
 def closure_batched(kind, Ts, Ds=None, flags=0, stream=None):

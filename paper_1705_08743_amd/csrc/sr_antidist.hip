@@ -601,7 +601,8 @@ hipError_t panels_s(uint16_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t 
 }
 
 template <bool S8>
-hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_t st) {
+hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_t st,
+                     bool aux_create) {
     const Plan p = make_plan(D);
     const int nb = blocks_of(D);
     hipError_t e = pivot_s<S8>(T, ld, D, 0, st);
@@ -616,7 +617,7 @@ hipError_t closure_s(uint16_t *T, int64_t ld, int64_t D, bool serial, hipStream_
     // is done, and the caller's stream waits for B(kb-1) only before A(kb),
     // the rest of round kb's update.  So B(kb) follows B(kb-1) back to back
     // while the chain A(kb) -> pivot(kb+1) -> panels(kb+1) runs beside it.
-    Aux *aux = (nb > 2 && !serial && overrides().lookahead) ? aux_acquire(st) : nullptr;
+    Aux *aux = (nb > 2 && !serial && overrides().lookahead) ? aux_acquire(st, aux_create) : nullptr;
     for (int kb = 0; kb < nb; kb++) {
         int rl, rh, cl, ch;
         block_chunks(D, kb, p.rw, &rl, &rh);
@@ -693,9 +694,9 @@ hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, i
 }
 
 hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, bool serial,
-                             hipStream_t stream) {
-    return s8 ? closure_s<true>(T, ld, D, serial, stream)
-              : closure_s<false>(T, ld, D, serial, stream);
+                             hipStream_t stream, bool aux_create) {
+    return s8 ? closure_s<true>(T, ld, D, serial, stream, aux_create)
+              : closure_s<false>(T, ld, D, serial, stream, aux_create);
 }
 
 hipError_t launch_ad_fw_pivot(bool s8, uint16_t *T, int64_t ld, int64_t D, int64_t kb,

@@ -588,13 +588,14 @@ hipError_t panels_round(uint32_t *T, int64_t ld, int64_t D, int64_t kb, hipStrea
 // A(kb) writes tiles of row block kb+1 that B(kb-1) also writes, so the
 // caller's stream waits for B(kb-1) before A(kb).  B(kb) reads only row and
 // column block kb, which round kb+1 does not write.
-hipError_t closure32(uint32_t *T, int64_t ld, int64_t D, bool serial, hipStream_t st) {
+hipError_t closure32(uint32_t *T, int64_t ld, int64_t D, bool serial, hipStream_t st,
+                     bool aux_create) {
     const int nb = blocks_of(D);
     const int nrc = (int)((D + kRW - 1) / kRW), ncc = (int)((D + kUpdCW - 1) / kUpdCW);
     hipError_t e = pivot_round(T, ld, D, 0, st);
     if (e != hipSuccess || nb == 1) return e;
     if ((e = panels_round(T, ld, D, 0, st)) != hipSuccess) return e;
-    Aux *aux = (nb > 2 && !serial && tuning().lookahead) ? aux_acquire(st) : nullptr;
+    Aux *aux = (nb > 2 && !serial && tuning().lookahead) ? aux_acquire(st, aux_create) : nullptr;
     for (int kb = 0; kb < nb; kb++) {
         int rl, rh, cl, ch;
         block_chunks(D, kb, kRW, &rl, &rh);
@@ -657,9 +658,9 @@ hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t 
 }
 
 hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, bool serial,
-                               hipStream_t stream) {
+                               hipStream_t stream, bool aux_create) {
     static_assert(kPanCW == 2 * dev::kPanelNW, "panel chunking of panel_wgs");
-    return closure32(T, ld, D, serial, stream);
+    return closure32(T, ld, D, serial, stream, aux_create);
 }
 
 hipError_t launch_ad32_closure_batched_resident(const BatchPlan *plan, int64_t count,

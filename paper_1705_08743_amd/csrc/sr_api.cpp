@@ -23,13 +23,18 @@ namespace {
 
 thread_local std::string g_err = "no error";
 
-int fail(int code, const char *fmt, ...) {
+int vfail(int code, const char *fmt, va_list ap) {
     char buf[512];
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    g_err = buf;
+    return code;
+}
+
+int fail(int code, const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vfail(code, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -344,7 +349,8 @@ hipError_t closure_by_squaring(int es, bool s8, void *T, int64_t ld, int64_t D, 
     // zeroed (the products write only the words that hold columns < D)
     hipError_t e = hipMemcpy2DAsync(P, lw * es, T, ld * es, es == 8 ? lw * 8 : row_bytes, D,
                                     hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess && es == 8) e = hipMemsetAsync(Q, 0, (size_t)(D * lw * es), st);
+    if (e == hipSuccess && es == 8)
+        e = sr::launch_fill32(reinterpret_cast<uint32_t *>(Q), D * lw * 2, 0u, st);
     // I (+) A: the diagonal becomes the multiplicative one (S, or bit set)
     const uint32_t one = es == 4 ? 0xFFFFFFFFu : (es == 8 ? 1u : (s8 ? 0x5BF8u : 0xFFFFu));
     if (e == hipSuccess) e = sr::launch_diag(es, P, lw, D, one, st);
@@ -375,7 +381,8 @@ hipError_t closure_by_squaring(int es, bool s8, void *T, int64_t ld, int64_t D, 
     // holding it, so T * P below is the closure either way.  The host
     // enqueues all j squarings and never waits.
     int *changed = reinterpret_cast<int *>(static_cast<char *>(work) + 2 * D * lw * es);
-    if (e == hipSuccess) e = hipMemsetAsync(changed, 0, (size_t)j * sizeof(int), st);
+    if (e == hipSuccess)
+        e = sr::launch_fill32(reinterpret_cast<uint32_t *>(changed), j, 0u, st);
     for (int i = 0; i < j && e == hipSuccess; i++) {
         const int *gate = i == 0 ? nullptr : changed + i - 1;
         if (es == 4) {
@@ -479,40 +486,30 @@ int ewise_checked(const char *fn, int kind, int op, void *C, int64_t ldc, const 
 
 }  // namespace
 
-extern "C" {
+namespace sr {
 
-int semiring_add(int kind, void *C, int64_t ldc, const void *A, int64_t lda, const void *B,
-                 int64_t ldb, int64_t R, int64_t N, void *stream) {
-    // (+) is max for anti-distance and Boolean entries, min for distances
-    return ewise_checked("semiring_add", kind, is_dist(kind) ? sr::EW_AND : sr::EW_OR, C, ldc, A,
-                         lda, B, ldb, R, N, stream);
-}
-
-int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_t lda,
-                   const void *B, int64_t ldb, int64_t R, int64_t N, void *stream) {
-    return ewise_checked("semiring_ewise", kind, op, C, ldc, A, lda, B, ldb, R, N, stream);
-}
-
-int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream) {
-    if (!valid_kind(kind)) return fail(SR_EINVAL, "closure: invalid kind %d", kind);
+int closure_run(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream,
+                int (*fixed_work)(void **), size_t fixed_bytes, const char *fn) {
+    const bool fixed = fixed_work != nullptr;
+    if (!valid_kind(kind)) return fail(SR_EINVAL, "%s: invalid kind %d", fn, kind);
     const unsigned methods = flags & (SR_CLOSURE_SQUARING | SR_CLOSURE_WARSHALL |
                                       SR_CLOSURE_BIG_BLOCKS);
     if (flags & ~(unsigned)(SR_REFLEXIVE | SR_BOOL_BITWISE | SR_BOOL_MFMA | SR_BOOL_M4R |
                             SR_SERIAL_PHASES | SR_CLOSURE_SQUARING | SR_CLOSURE_WARSHALL |
                             SR_CLOSURE_BIG_BLOCKS))
-        return fail(SR_EINVAL, "closure: unknown flags 0x%x", flags);
+        return fail(SR_EINVAL, "%s: unknown flags 0x%x", fn, flags);
     if ((flags & SR_BOOL_BITWISE) && (flags & SR_BOOL_M4R))
-        return fail(SR_EINVAL, "closure: SR_BOOL_BITWISE and SR_BOOL_M4R exclude each other");
+        return fail(SR_EINVAL, "%s: SR_BOOL_BITWISE and SR_BOOL_M4R exclude each other", fn);
     if (methods & (methods - 1))
-        return fail(SR_EINVAL, "closure: at most one of SR_CLOSURE_SQUARING, "
-                               "SR_CLOSURE_WARSHALL, SR_CLOSURE_BIG_BLOCKS");
+        return fail(SR_EINVAL, "%s: at most one of SR_CLOSURE_SQUARING, "
+                               "SR_CLOSURE_WARSHALL, SR_CLOSURE_BIG_BLOCKS", fn);
     if ((flags & SR_CLOSURE_BIG_BLOCKS) && base_kind(kind) == SR_BOOL)
-        return fail(SR_EUNSUPPORTED, "closure: SR_CLOSURE_BIG_BLOCKS is for non-Boolean kinds");
+        return fail(SR_EUNSUPPORTED, "%s: SR_CLOSURE_BIG_BLOCKS is for non-Boolean kinds", fn);
     const bool serial = (flags & SR_SERIAL_PHASES) != 0;
     if (flags & SR_BOOL_MFMA)
-        return fail(SR_EUNSUPPORTED, "closure: the int8 matrix-core path is for products only");
-    if (D < 0) return fail(SR_EINVAL, "closure: negative size");
-    if (D > INT32_MAX) return fail(SR_EINVAL, "closure: sizes above 2^31-1 are not supported");
+        return fail(SR_EUNSUPPORTED, "%s: the int8 matrix-core path is for products only", fn);
+    if (D < 0) return fail(SR_EINVAL, "%s: negative size", fn);
+    if (D > INT32_MAX) return fail(SR_EINVAL, "%s: sizes above 2^31-1 are not supported", fn);
     int rc;
     if ((rc = check_matrix(kind, "T", T, ldt, D, D)) != SR_OK) return rc;
     if (D == 0) return ok();
@@ -525,7 +522,8 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
     // small anti-distance matrices (where the blocked loop's chain of D
     // sequential pivot steps dominates), big pivot blocks closed by squaring
     // for mid sizes, the blocked loop otherwise.  Squaring and big blocks
-    // allocate working memory, so a stream being captured takes the loop.
+    // allocate working memory, so a stream being captured takes the loop
+    // (unless the caller supplied the working memory).
     unsigned method = methods;
     unsigned bool_path = flags & (SR_BOOL_BITWISE | SR_BOOL_M4R);
     if (!method && serial) method = SR_CLOSURE_WARSHALL;
@@ -541,21 +539,43 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
         } else {
             method = SR_CLOSURE_WARSHALL;
         }
-        if (method != SR_CLOSURE_WARSHALL && capturing(st)) method = SR_CLOSURE_WARSHALL;
+        if (method != SR_CLOSURE_WARSHALL && !fixed && capturing(st))
+            method = SR_CLOSURE_WARSHALL;
     }
     // Working memory first, so that a failed allocation returns before the
     // caller's matrix is touched: the binary16 copy of uint8 data, and the
     // two matrices of squaring (of the whole matrix, or of one big block).
-    const bool big = method == SR_CLOSURE_BIG_BLOCKS;
-    const bool squared = method != SR_CLOSURE_WARSHALL;
     const bool s8 = ak == SR_ANTIDIST_U8;
     const int64_t lw = round_up(D, 64);
     const size_t tw = s8 ? (size_t)(D * lw) * 2 : 0;
     const int wes = s8 ? 2 : es;
-    const int64_t B = big ? std::min<int64_t>(big_block_size(), D) : D;
-    const size_t need = tw + (squared ? squaring_work_bytes(wes, B) : 0);
+    auto need_of = [&](unsigned m) {
+        if (m == SR_CLOSURE_WARSHALL) return tw;
+        const int64_t b = m == SR_CLOSURE_BIG_BLOCKS ? std::min<int64_t>(big_block_size(), D) : D;
+        return tw + squaring_work_bytes(wes, b);
+    };
+    size_t need = need_of(method);
     void *w = nullptr;
-    if (need > 0 && (rc = work_alloc(&w, std::max<size_t>(need, 256), st)) != SR_OK) return rc;
+    if (fixed) {
+        // the caller's buffer: a method chosen by default that needs more
+        // falls back to the loop, which needs only the uint8 working copy
+        if (need > fixed_bytes && !methods && method != SR_CLOSURE_WARSHALL) {
+            method = SR_CLOSURE_WARSHALL;
+            need = need_of(method);
+        }
+        if (need > fixed_bytes)
+            return fail(SR_EINVAL,
+                        "%s: D=%lld needs %zu bytes of working memory, more than the %zu bytes "
+                        "of the static scratch",
+                        fn, (long long)D, need, fixed_bytes);
+        if (need > 0 && (rc = fixed_work(&w)) != SR_OK) return rc;
+    } else if (need > 0 && (rc = work_alloc(&w, std::max<size_t>(need, 256), st)) != SR_OK) {
+        return rc;
+    }
+    const bool big = method == SR_CLOSURE_BIG_BLOCKS;
+    const bool squared = method != SR_CLOSURE_WARSHALL;
+    const int64_t B = big ? std::min<int64_t>(big_block_size(), D) : D;
+    const bool aux_create = !fixed;
     // distance closure (dransclose) by De Morgan: not closure(not T)
     if (is_dist(kind)) e = sr::launch_ewise(es, sr::EW_NOT, T, ldt, T, ldt, T, ldt, D, D, 0, st);
     // the matrix the method runs on: T, or the binary16 copy of uint8 data
@@ -575,16 +595,18 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
         const int path = (bool_path & SR_BOOL_M4R) ? sr::kBoolPathM4r
                          : (bool_path & SR_BOOL_BITWISE) ? sr::kBoolPathBitwise
                                                          : sr::kBoolPathAuto;
-        e = sr::launch_bool_closure(static_cast<uint64_t *>(T), ldt, D, serial, path, st);
+        e = sr::launch_bool_closure(static_cast<uint64_t *>(T), ldt, D, serial, path, st,
+                                     aux_create);
     } else if (e == hipSuccess && ak == SR_ANTIDIST_U32) {
-        e = sr::launch_ad32_closure(static_cast<uint32_t *>(T), ldt, D, serial, st);
+        e = sr::launch_ad32_closure(static_cast<uint32_t *>(T), ldt, D, serial, st, aux_create);
     } else if (e == hipSuccess) {
-        e = sr::launch_ad_closure(s8, static_cast<uint16_t *>(M), ldm, D, serial, st);
+        e = sr::launch_ad_closure(s8, static_cast<uint16_t *>(M), ldm, D, serial, st,
+                                   aux_create);
     }
     if (e == hipSuccess && s8)
         e = sr::launch_narrow_u8(static_cast<uint8_t *>(T), ldt, static_cast<uint16_t *>(M), lw, D,
                                  D, st);
-    work_free(w, st);
+    if (!fixed) work_free(w, st);
     if (e == hipSuccess && is_dist(kind))
         e = sr::launch_ewise(es, sr::EW_NOT, T, ldt, T, ldt, T, ldt, D, D, 0, st);
     // reflexive closure I (+) T (eq. rtc): the diagonal of the multiplicative
@@ -596,8 +618,36 @@ int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *str
                                                        : 0xFFFFFFFFu;
         e = sr::launch_diag(es, T, ldt, D, one, st);
     }
-    if (e != hipSuccess) return device_fail(e, "closure launch");
+    if (e != hipSuccess) return fail(SR_EDEVICE, "%s launch: %s", fn, hipGetErrorString(e));
     return ok();
+}
+
+int report(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vfail(code, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+}  // namespace sr
+
+extern "C" {
+
+int semiring_add(int kind, void *C, int64_t ldc, const void *A, int64_t lda, const void *B,
+                 int64_t ldb, int64_t R, int64_t N, void *stream) {
+    // (+) is max for anti-distance and Boolean entries, min for distances
+    return ewise_checked("semiring_add", kind, is_dist(kind) ? sr::EW_AND : sr::EW_OR, C, ldc, A,
+                         lda, B, ldb, R, N, stream);
+}
+
+int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_t lda,
+                   const void *B, int64_t ldb, int64_t R, int64_t N, void *stream) {
+    return ewise_checked("semiring_ewise", kind, op, C, ldc, A, lda, B, ldb, R, N, stream);
+}
+
+int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream) {
+    return sr::closure_run(kind, T, ldt, D, flags, stream, nullptr, 0, "closure");
 }
 
 }  // extern "C"

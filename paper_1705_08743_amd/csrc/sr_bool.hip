@@ -887,7 +887,7 @@ int bool_update_nwb(int64_t D) {
 }
 
 hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool serial, int path,
-                               hipStream_t st) {
+                               hipStream_t st, bool aux_create) {
     uint32_t *T = reinterpret_cast<uint32_t *>(T64);
     const int64_t ld = 2 * ld64;
     const int64_t nb = (D + kBoolBlock - 1) / kBoolBlock;
@@ -900,7 +900,7 @@ hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool seri
     hipError_t e = pivot_b(T, ld, D, 0, st);
     if (e != hipSuccess || nb == 1) return e;
     if ((e = panels_b(T, ld, D, 0, st)) != hipSuccess) return e;
-    Aux *aux = (nb > 2 && !serial) ? aux_acquire(st) : nullptr;
+    Aux *aux = (nb > 2 && !serial) ? aux_acquire(st, aux_create) : nullptr;
     for (int64_t kb = 0; kb < nb; kb++) {
         const BBlock b = bblock(D, kb);
         const double bs = b.bs;

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sr_internal.h"
 
 namespace sr {
@@ -122,6 +124,12 @@ __global__ void __launch_bounds__(256) k_diag(uint8_t *T, int64_t ldb, int64_t D
         reinterpret_cast<uint32_t *>(row)[i >> 5] |= 1u << (i & 31);
 }
 
+// p[0 .. n) := value, grid-stride over 32-bit words.
+__global__ void __launch_bounds__(256) k_fill32(uint32_t *p, int64_t n, uint32_t value) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = value;
+}
+
 }  // namespace
 
 hipError_t launch_ewise(int elem_bytes, int op, void *C, int64_t ldc, const void *A, int64_t lda,
@@ -160,6 +168,13 @@ hipError_t launch_diag(int elem_bytes, void *T, int64_t ld, int64_t D, uint32_t 
         case 4: hipLaunchKernelGGL(k_diag<4>, grid, dim3(256), 0, stream, t, ldb, D, value); break;
         default: hipLaunchKernelGGL(k_diag<8>, grid, dim3(256), 0, stream, t, ldb, D, value); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill32(uint32_t *p, int64_t n, uint32_t value, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_fill32, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, value);
     return hipGetLastError();
 }
 

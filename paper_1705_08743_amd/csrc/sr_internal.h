@@ -36,9 +36,11 @@ hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, i
                          int *flag = nullptr);
 
 // In-place closure of the D x D matrix T (16-bit storage).  serial: no
-// second stream (every phase in order on `stream`).
+// second stream (every phase in order on `stream`).  aux_create: false to
+// use the second stream only if it exists already (no stream or event is
+// created; this holds for the other closure launchers too).
 hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, bool serial,
-                             hipStream_t stream);
+                             hipStream_t stream, bool aux_create = true);
 
 // Anti-distance with uint32 entries and S = 2^32 - 1 (sr_antidist32.hip):
 // product (strides in elements, multiples of 4) and in-place closure (serial:
@@ -49,7 +51,7 @@ hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t 
                            const int *gate = nullptr, const uint32_t *prev = nullptr,
                            int *flag = nullptr);
 hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, bool serial,
-                               hipStream_t stream);
+                               hipStream_t stream, bool aux_create = true);
 
 // Individual phases of one blocked Floyd-Warshall round (for tests/timing).
 hipError_t launch_ad_fw_pivot(bool s8, uint16_t *T, int64_t ld, int64_t D, int64_t kb,
@@ -76,7 +78,7 @@ hipError_t launch_bool_mul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t 
 // path: kBoolPathAuto, or force the bit-sliced (kBoolPathBitwise) or the
 // four-Russians (kBoolPathM4r) kernels for the bulk update.
 hipError_t launch_bool_closure(uint64_t *T, int64_t ld, int64_t D, bool serial, int path,
-                               hipStream_t stream);
+                               hipStream_t stream, bool aux_create = true);
 // Boolean product with the "four Russians" tables (sr_bool.hip); `launch_bool_mul`
 // chooses between it and the bit-sliced kernel, path forces one.
 hipError_t launch_bool_mul_m4r(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda,
@@ -108,6 +110,21 @@ hipError_t launch_add(int elem_bytes, void *C, int64_t ldc, const void *A, int64
 // row i set (8).
 hipError_t launch_diag(int elem_bytes, void *T, int64_t ld, int64_t D, uint32_t value,
                        hipStream_t stream);
+// p[0 .. n) := value (32-bit words): a kernel, not a memset node, so that a
+// captured graph replays it faithfully.
+hipError_t launch_fill32(uint32_t *p, int64_t n, uint32_t value, hipStream_t stream);
+
+// closure() with its working memory either allocated stream-ordered
+// (work == nullptr) or taken from a caller's buffer of work_bytes bytes
+// (256-byte aligned), which work() returns once every argument, including the
+// size of the working memory, has been checked; then nothing is allocated and
+// no stream or event is created.  fn names the entry point in error
+// messages.  Returns an SR_* code and sets the thread's error message
+// (sr_api.cpp).
+int closure_run(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream,
+                int (*work)(void **), size_t work_bytes, const char *fn);
+// Sets the thread's error message (printf format) and returns code.
+int report(int code, const char *fmt, ...);
 
 // Batched anti-distance closure.  `host_desc` holds `count` descriptors,
 // already ordered largest-first; the launcher uploads them with the plan's
@@ -182,7 +199,8 @@ hipError_t launch_ad32_closure_batched_resident(const BatchPlan *plan, int64_t c
 // Second stream of a closure (sr_runtime.cpp), one per (device, caller
 // stream), created on first use at default priority.  aux_acquire() returns it
 // locked (the caller enqueues its whole fork/join sequence, then calls
-// aux_release) or nullptr when none can be created.
+// aux_release) or nullptr when none can be created -- or, with create =
+// false, when none exists yet for this (device, caller stream).
 struct Aux {
     hipStream_t stream;
     hipEvent_t ev_main;  // recorded on the caller's stream, waited on by `stream`
@@ -192,7 +210,7 @@ struct Aux {
     int device;
     int slot;
 };
-Aux *aux_acquire(hipStream_t caller);
+Aux *aux_acquire(hipStream_t caller, bool create = true);
 void aux_release(Aux *a);
 
 // Autotuning table (sr_tune.cpp).  op: kTuneClosure (a = D), kTuneMul

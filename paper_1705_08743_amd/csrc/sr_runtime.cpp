@@ -55,7 +55,7 @@ int g_aux_count = 0;
 
 }  // namespace
 
-Aux *aux_acquire(hipStream_t caller) {
+Aux *aux_acquire(hipStream_t caller, bool create) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     AuxEntry *entry = nullptr;
@@ -67,7 +67,9 @@ Aux *aux_acquire(hipStream_t caller) {
                 break;
             }
         if (!entry) {
-            if (g_aux_count == kMaxAux) return nullptr;  // table full: no lookahead
+            // none yet: create one, unless the caller may not create streams
+            // (then the closure runs its phases in order on its own stream)
+            if (!create || g_aux_count == kMaxAux) return nullptr;  // table full: no lookahead
             Aux a{};
             // default priority: the two streams must not differ in priority
             // The events only order the two streams of one device, so a

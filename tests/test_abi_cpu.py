@@ -246,3 +246,27 @@ def test_prepared_batch_validation(L):
     L.sr_batch_destroy(None)
     with pytest.raises(TypeError):
         sr.PreparedBatch(U16, [])
+
+
+def test_closure_noalloc_checks_before_any_device_call(L):
+    """closure_noalloc validates like closure() and refuses, on the host, a
+    size whose working memory exceeds its 32 MiB static scratch."""
+    U16, U8 = sr.SR_ANTIDIST_U16, sr.SR_ANTIDIST_U8
+    f = L.closure_noalloc
+    assert f(U16, NULL, 8, 0, 0, None) == sr.SR_OK
+    assert f(U16, P, 8, -1, 0, None) == sr.SR_EINVAL
+    assert f(U16, P, 4, 8, 0, None) == sr.SR_EINVAL
+    assert f(U16, P + 8, 8, 8, 0, None) == sr.SR_EALIGN
+    assert f(sr.SR_BOOL, P, 2, 8, sr.SR_BOOL_MFMA, None) == sr.SR_EUNSUPPORTED
+    assert f(U16, P, 8, 8, 0x400, None) == sr.SR_EINVAL
+    # uint8 data above 4096 vertices: the binary16 working copy alone is
+    # 2 * D * round_up(D, 64) bytes > 32 MiB
+    for kind in (U8, sr.SR_DISTANCE_U8):
+        assert f(kind, P, 4112, 4100, 0, None) == sr.SR_EINVAL
+        msg = L.sr_last_error().decode()
+        assert "closure_noalloc" in msg and "static scratch" in msg
+    # a forced squaring of a 3000-vertex uint16 matrix needs two 3000 x 3008
+    # working matrices (36 MB)
+    assert f(U16, P, 3008, 3000, sr.SR_CLOSURE_SQUARING, None) == sr.SR_EINVAL
+    assert "static scratch" in L.sr_last_error().decode()
+
