@@ -575,9 +575,11 @@ def run_add(args, torch, sr, synthgen):
 def run_serve(args, torch, sr, synthgen):
     """Serving: closure requests of log-uniform size in [64, 8192], half
     Boolean (p = 0.02) and half uint16 anti-distance (configuration-2
-    generator), Poisson arrivals at 80% of the serial service rate; served
-    (continuous batching, footprint admission, concurrent slots) against the
-    same trace solved one at a time."""
+    generator), Poisson arrivals at 80% of the serial service rate of the same
+    trace; served (continuous batching, footprint admission, concurrent
+    slots) against the same trace solved one at a time.  Every served result
+    is compared with the oracle: whole closures up to 2048 vertices, sampled
+    rows (per-source shortest paths / breadth-first search) above."""
     import numpy as np
     from paper_1705_08743_amd.serve import ClosureServer, Request
     kinds = {"bool": sr.SR_BOOL, "u16": sr.SR_ANTIDIST_U16}
@@ -587,25 +589,27 @@ def run_serve(args, torch, sr, synthgen):
 
     log("generating %d requests ..." % args.serve_requests)
     reqs = make(synthgen.serving_trace(args.serve_requests))
-    calib = make(synthgen.serving_trace(args.serve_calibration, seed=synthgen.config_seed(5) + 1000))
     server = ClosureServer(budget_bytes=int(args.serve_budget_gb * (1 << 30)), slots=4)
     fresh = lambda items, arr: [Request(i, k, n, h, a) for i, ((k, n, h), a) in
                                 enumerate(zip(items, arr))]
-    # warm-up (allocator, code objects), then the serial service time
-    server.run(fresh(calib, np.zeros(len(calib))), "served")
-    cal = server.run(fresh(calib, np.zeros(len(calib))), "serial")
-    mean_service = cal["makespan_s"] / len(calib)
+    zeros = np.zeros(len(reqs))
+    # warm-up (allocator, code objects, pinned copies), then the trace's own
+    # serial service time: its serial makespan with every request waiting
+    log("warm-up and serial service time ...")
+    server.run(fresh(reqs, zeros), "served")
+    sat_serial = server.run(fresh(reqs, zeros), "serial")
+    mean_service = sat_serial["makespan_s"] / len(reqs)
     rate = 0.8 / mean_service
     arrivals = synthgen.poisson_arrivals(len(reqs), rate, synthgen.generator(synthgen.config_seed(5) + 7))
+    log("replaying at %.1f requests/s ..." % rate)
     served_reqs = fresh(reqs, arrivals)
     served = server.run(served_reqs, "served")
     serial_reqs = fresh(reqs, arrivals)
     serial = server.run(serial_reqs, "serial")
     same = all(np.array_equal(a.result, b.result) for a, b in zip(served_reqs, serial_reqs))
     del serial_reqs
-    # capacity: the whole trace available at once
-    sat_served = server.run(fresh(reqs, np.zeros(len(reqs))), "served")
-    sat_serial = server.run(fresh(reqs, np.zeros(len(reqs))), "serial")
+    sat_served = server.run(fresh(reqs, zeros), "served")
+    span = float(arrivals[-1] - arrivals[0])
     out = {"metric": "served requests/s (closure requests, Poisson at 80% of serial capacity); "
                      "p50/p99 latency vs serial",
            "value": served["throughput_rps"], "unit": "requests/s", "n_gpus": 1,
@@ -615,6 +619,8 @@ def run_serve(args, torch, sr, synthgen):
            "config": {"workload": "serving_mixed_closures", "requests": len(reqs),
                       "n": "log-uniform [64,8192]", "mix": "50% Boolean p=0.02, 50% uint16 p=0.05",
                       "arrival_rate_rps": rate, "mean_serial_service_ms": mean_service * 1e3,
+                      "offered_load": rate * mean_service,
+                      "realized_load": sat_serial["makespan_s"] / span if span > 0 else None,
                       "budget_gb": args.serve_budget_gb, "slots": 4, "batch_n": 256,
                       "parallelism": "single_gpu"},
            "served": served, "serial": serial,
@@ -628,19 +634,56 @@ def run_serve(args, torch, sr, synthgen):
            "p50_speedup_vs_serial": serial["p50_ms"] / served["p50_ms"],
            "parity": {"served_equals_serial_all_requests": bool(same)}}
     if not args.no_parity:
-        import oracle
-        small = sorted(range(len(served_reqs)), key=lambda i: served_reqs[i].n)[:4]
-        ok = True
-        for i in small:
-            r = served_reqs[i]
-            if r.kind == sr.SR_BOOL:
-                want = oracle.bool_closure_words(r.host, r.n)[:, :(r.n + 63) // 64]
-                ok &= bool(np.array_equal(r.result.view(np.uint64), want))
-            else:
-                ok &= bool(np.array_equal(r.result.astype(np.int64),
-                                          oracle.ad_closure(r.host[:, :r.n], 65535)))
-        out["parity"]["oracle_smallest_4"] = ok
+        log("oracle check of every served result ...")
+        out["parity"].update(serve_oracle_parity(sr, served_reqs, args.cpu_threads))
     return out
+
+
+def serve_oracle_parity(sr, reqs, threads, whole_max=2048, rows_per_request=4):
+    """Every served result against the oracle: the whole closure (Warshall's
+    loop) for requests of at most whole_max vertices, and for larger ones
+    sampled rows from the oracle's per-source path definition (Dijkstra on
+    distances, breadth-first search for Boolean), rows 0, n - 1 and two
+    seeded ones."""
+    import numpy as np
+    import oracle
+    import synthgen
+    oracle.set_threads(threads)
+    gen = synthgen.generator(synthgen.config_seed(5) + 11)
+    whole = rows = entries = 0
+    bad = []
+    for r in reqs:
+        n = r.n
+        if r.kind == sr.SR_BOOL:
+            got = r.result.view(np.uint64)
+            nw = (n + 63) // 64
+            if n <= whole_max:
+                ok = np.array_equal(got, oracle.bool_closure_words(r.host, n)[:, :nw])
+                whole += 1
+                entries += n * n
+            else:
+                sel = sorted({0, n - 1, *gen.integers(0, n, size=rows_per_request - 2).tolist()})
+                want = oracle.bool_closure_rows_words(r.host, n, np.array(sel))
+                ok = np.array_equal(got[sel], want[:, :nw])
+                rows += len(sel)
+                entries += len(sel) * n
+        else:
+            A = r.host[:, :n]
+            if n <= whole_max:
+                ok = np.array_equal(r.result.astype(np.int64), oracle.ad_closure(A, 65535))
+                whole += 1
+                entries += n * n
+            else:
+                sel = sorted({0, n - 1, *gen.integers(0, n, size=rows_per_request - 2).tolist()})
+                want = oracle.ad_closure_rows(A, 65535, np.array(sel))
+                ok = np.array_equal(r.result[sel].astype(np.int64), want)
+                rows += len(sel)
+                entries += len(sel) * n
+        if not ok:
+            bad.append(r.rid)
+    return {"oracle_requests_checked": len(reqs), "oracle_whole_closures": whole,
+            "oracle_sampled_rows": rows, "oracle_entries_compared": int(entries),
+            "oracle_bit_exact": not bad, "oracle_mismatches": bad[:10]}
 
 
 TILE_NAMES = {1: "64x16", 2: "64x32", 3: "64x64"}
@@ -822,8 +865,7 @@ def main():
     ap.add_argument("--workload", default="fw8192",
                     choices=["fw8192", "u8fw8192", "dfw8192", "u32fw8192", "bool16384",
                              "boolmul16384", "mul1024", "small", "batched", "add8192", "serve"])
-    ap.add_argument("--serve-requests", type=int, default=128)
-    ap.add_argument("--serve-calibration", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")

@@ -107,8 +107,9 @@ enum {
     SR_ACCUMULATE = 1u,    /* semiring_mul: C := C (+) A*B instead of C := A*B */
     SR_REFLEXIVE = 2u,     /* closure, closure_batched: return I (+) T (eq. rtc) */
     SR_BOOL_BITWISE = 4u,  /* Boolean: force the word OR-AND kernels (the default) */
-    SR_BOOL_MFMA = 8u,     /* Boolean semiring_mul: the int8 matrix-core path (exact; opt-in);
-                              closure: SR_EUNSUPPORTED; any other kind: SR_EINVAL */
+    SR_BOOL_MFMA = 8u,     /* Boolean semiring_mul, and closure's bulk update: the matrix
+                              cores (counts of common bits, thresholded; exact); any other
+                              kind: SR_EINVAL */
     SR_SERIAL_PHASES = 16u, /* closure: enqueue every phase on the caller's stream in order, without
                                overlapping the next round's pivot and panels on a second stream */
     SR_BOOL_M4R = 32u,     /* Boolean semiring_mul: the "four Russians" table path */
@@ -129,11 +130,13 @@ enum {
  * product is out of place, and the in-place form with all three operands the
  * same matrix is the closure below.
  * Boolean padding bits of A (columns >= K) and B (columns >= N) must be zero.
- * Boolean with SR_BOOL_MFMA: the same product computed as an integer product
- * of {0, 1} matrices on the matrix cores, thresholded at 1 (count > 0 exactly
- * when some A_ik = B_kj = 1); it takes stream-ordered working memory of
- * (R + N) * K bytes (sizes rounded up) and cannot be combined with
- * SR_BOOL_BITWISE (SR_EINVAL).
+ * Boolean with SR_BOOL_MFMA: the same product computed as a product of
+ * {0, 1} matrices on the matrix cores -- counts of common set bits, > 0
+ * exactly when some A_ik = B_kj = 1 -- with 4-bit float operands (or int8
+ * ones when the environment sets SR_MFMA_FORMAT=i8), read straight from the
+ * packed bits; it takes stream-ordered working memory for a bit-transposed
+ * copy of B, round_up(N, 128) * round_up(K, 256) / 8 bytes, and cannot be
+ * combined with SR_BOOL_BITWISE or SR_BOOL_M4R (SR_EINVAL).
  */
 int semiring_mul(int kind, void *C, int64_t ldc, const void *A, int64_t lda,
                  const void *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
@@ -159,42 +162,41 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
 
 /*
  * closure -- in place, T := A (+) A*A (+) A*A*A (+) ... for the D x D matrix
- * A held in T (Sec. II eq. trcl; computed by Warshall's algorithm, Sec. II,
- * which for anti-distance matrices is Floyd's algorithm, Sec. III).  The
- * result is the transitive, non-reflexive closure: entry (i, j) is the best
- * product over paths of at least one edge, so the diagonal holds "i lies on a
- * cycle" (Boolean), S minus the shortest cycle through i, saturated
- * (anti-distance), or the shortest cycle through i, or S (distance: the
- * paper's dransclose).  flags: SR_REFLEXIVE (I (+) T, eq. rtc: the diagonal
- * becomes 1, S, or 0 for distances -- the paper's transclosure /
- * dransclosure), SR_BOOL_BITWISE, SR_SERIAL_PHASES; SR_BOOL_MFMA returns
- * SR_EUNSUPPORTED.  D = 0 is a no-op.
- * Exact methods compute it.  The blocked Warshall / Floyd loop in rounds of
- * 128 (Boolean: 256) pivots (SR_CLOSURE_WARSHALL) is the default for large
- * matrices and for Boolean ones.  Repeated squaring, A * (I (+) A)^(2^j) with
- * 2^j >= D - 1 (eq. trcl, SR_CLOSURE_SQUARING), is the default for
- * anti-distance and distance matrices with 192 <= D <= 1024 (768 for the
- * 32-bit kinds), where the loop's chain of D sequential pivot steps costs more
- * than the squarings' extra products; from there up to D = 2560 (8- and
- * 16-bit kinds) the loop runs in blocks of 512 pivots, each pivot block closed
- * by squaring and the panels and update done as products.  For the
- * anti-distance and distance kinds the squarings stop early, on the device
- * and without a host wait, once one leaves the power unchanged (it is then
- * idempotent, so every later power equals it).  Both allocate stream-ordered
- * working memory (two matrices of the squared size) and are not taken while
- * `stream` is being captured, nor with SR_SERIAL_PHASES.
- * By default a blocked closure with more than two pivot blocks forks onto a second,
- * library-owned stream of default priority (the next round's pivot and panels
- * overlap the bulk of the current update) and joins back into `stream`
- * before the call's work completes; the fork/join is event-based, so the
- * sequence can be captured into a HIP graph from `stream` (tested for the
- * uint16, uint32, distance and Boolean kinds, which allocate nothing; the
- * uint8 kinds allocate stream-ordered working memory and are not tested
- * under capture).  Before a capture, call closure() once eagerly on the same
- * stream with SR_CLOSURE_WARSHALL: the second stream is created on a stream's
- * first blocked closure.
+ * A held in T (Sec. II eq. trcl; Warshall's algorithm, Sec. II, which for
+ * anti-distance matrices is Floyd's, Sec. III): the transitive, non-reflexive
+ * closure, so the diagonal holds "i lies on a cycle" (Boolean), S minus the
+ * shortest cycle through i, saturated (anti-distance), or that cycle's
+ * length, or S (distance: the paper's dransclose).  D = 0 is a no-op.
+ * flags: SR_REFLEXIVE (I (+) T, eq. rtc: diagonal 1, S, or 0 for distances --
+ * the paper's transclosure / dransclosure); SR_SERIAL_PHASES (every phase in
+ * order on `stream`); at most one method -- SR_CLOSURE_WARSHALL (the blocked
+ * loop), SR_CLOSURE_SQUARING (A * (I (+) A)^(2^j), 2^j >= D - 1, eq. trcl),
+ * SR_CLOSURE_BIG_BLOCKS (the loop over blocks of 512 pivots, each closed by
+ * squaring; not Boolean) -- else the autotuned method for D's size class or
+ * the built-in size rules; for Boolean matrices at most one of
+ * SR_BOOL_BITWISE, SR_BOOL_M4R, SR_BOOL_MFMA (the kernels of the loop's bulk
+ * update).  Every method gives the same matrix.
+ * Working memory: the loop on 16-bit, 32-bit and Boolean matrices allocates
+ * nothing; uint8 data, squaring, big blocks and SR_BOOL_MFMA take
+ * stream-ordered working memory (closure_work_bytes() gives the amount), and
+ * on a stream being captured a method chosen by default is one that
+ * allocates nothing.  A blocked closure of more than two pivot blocks forks
+ * onto a second, library-owned stream of default priority (created by the
+ * first such call on `stream`) and joins back before its work completes; the
+ * fork and join are events, so the sequence can be captured (call closure()
+ * once eagerly on the stream first).
  */
 int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream);
+
+/*
+ * closure_work_bytes -- the device working memory, in bytes, that closure()
+ * with these arguments would allocate stream-ordered for the duration of the
+ * call (0 when the method it takes allocates nothing), by the method it would
+ * take now (the autotuning table included; as on a stream that is not being
+ * captured).  For footprint accounting by callers that admit work by device
+ * memory.  A negative SR_E* code for an invalid kind, size or flags.
+ */
+int64_t closure_work_bytes(int kind, int64_t D, unsigned flags);
 
 /*
  * closure_noalloc -- closure() without any allocation, for callers that
@@ -284,7 +286,10 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
  * classes of the largest D and of count (closure_batched and SR_BATCH_TILE_AUTO
  * then use it), and stores it in *chosen (may be NULL).  It synchronizes
  * `stream` and returns SR_EUNSUPPORTED while that is being captured; the
- * matrices of the batch are not touched.
+ * matrices of the batch are not touched.  A new shape's plan is uploaded into
+ * a new device allocation: the previous plan's stays allocated, unchanged,
+ * until sr_batch_destroy, so a graph captured from an earlier sr_batch_run
+ * still replays the closure it captured.
  *
  * sr_batch_tile returns the handle's update-tile shape (SR_BATCH_TILE_*).
  * sr_batch_destroy frees the handle (NULL: no-op); hipFree waits for work in

@@ -81,7 +81,8 @@ ERROR_NAMES = {
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsemiring.so")
 
-EXPORTS = ("semiring_mul", "semiring_add", "semiring_ewise", "closure", "closure_noalloc",
+EXPORTS = ("semiring_mul", "semiring_add", "semiring_ewise", "closure", "closure_work_bytes",
+           "closure_noalloc",
            "closure_batched",
            "sr_autotune_closure", "sr_autotune_mul", "sr_autotune_clear",
            "sr_batch_create", "sr_batch_run", "sr_batch_autotune", "sr_batch_tile",
@@ -123,6 +124,8 @@ def lib():
         L.closure.restype = i32
         L.closure_noalloc.argtypes = [i32, vp, i64, i64, u32, vp]
         L.closure_noalloc.restype = i32
+        L.closure_work_bytes.argtypes = [i32, i64, u32]
+        L.closure_work_bytes.restype = i64
         L.closure_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                       ctypes.POINTER(i64), i64, u32, vp]
         L.closure_batched.restype = i32
@@ -245,6 +248,14 @@ def closure(kind, T, D=None, flags=0, stream=None):
     pt, ldt, rt, ct = _mat(T, "T")
     D = rt if D is None else D
     _check(lib().closure(kind, pt, ldt, D, flags, _stream(stream)))
+
+
+def closure_work_bytes(kind, D, flags=0):
+    """Device bytes closure(kind, D, flags) would allocate for its duration."""
+    n = lib().closure_work_bytes(kind, D, flags)
+    if n < 0:
+        _check(int(n))
+    return int(n)
 
 
 def closure_noalloc(kind, T, D=None, flags=0, stream=None):

@@ -486,11 +486,25 @@ int ewise_checked(const char *fn, int kind, int op, void *C, int64_t ldc, const 
 
 }  // namespace
 
-namespace sr {
+namespace {
 
-int closure_run(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream,
-                int (*fixed_work)(void **), size_t fixed_bytes, const char *fn) {
-    const bool fixed = fixed_work != nullptr;
+// Working memory of a closure by method m: the binary16 copy of uint8 data,
+// then the two matrices of squaring (of the whole matrix, or of one big
+// block), or the transposed pivot rows of the Boolean matrix-core update.
+size_t closure_need(int kind, int64_t D, unsigned m, unsigned bool_path) {
+    const int ak = base_kind(kind);
+    const bool s8 = ak == SR_ANTIDIST_U8;
+    const size_t tw = s8 ? (size_t)(D * round_up(D, 64)) * 2 : 0;
+    if (m == SR_CLOSURE_WARSHALL)
+        return ak == SR_BOOL && (bool_path & SR_BOOL_MFMA) ? sr::bool_mfma_closure_work_bytes(D)
+                                                           : tw;
+    const int wes = s8 ? 2 : (int)unit_bytes(kind);
+    const int64_t b = m == SR_CLOSURE_BIG_BLOCKS ? std::min<int64_t>(big_block_size(), D) : D;
+    return tw + squaring_work_bytes(wes, b);
+}
+
+// Kind, size and flags of a closure call (the matrix is checked apart).
+int check_closure_args(int kind, int64_t D, unsigned flags, const char *fn) {
     if (!valid_kind(kind)) return fail(SR_EINVAL, "%s: invalid kind %d", fn, kind);
     const unsigned methods = flags & (SR_CLOSURE_SQUARING | SR_CLOSURE_WARSHALL |
                                       SR_CLOSURE_BIG_BLOCKS);
@@ -498,40 +512,43 @@ int closure_run(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void 
                             SR_SERIAL_PHASES | SR_CLOSURE_SQUARING | SR_CLOSURE_WARSHALL |
                             SR_CLOSURE_BIG_BLOCKS))
         return fail(SR_EINVAL, "%s: unknown flags 0x%x", fn, flags);
-    if ((flags & SR_BOOL_BITWISE) && (flags & SR_BOOL_M4R))
-        return fail(SR_EINVAL, "%s: SR_BOOL_BITWISE and SR_BOOL_M4R exclude each other", fn);
+    const unsigned paths = flags & (SR_BOOL_BITWISE | SR_BOOL_M4R | SR_BOOL_MFMA);
+    if (paths & (paths - 1))
+        return fail(SR_EINVAL, "%s: at most one of SR_BOOL_BITWISE, SR_BOOL_M4R, SR_BOOL_MFMA", fn);
+    if ((flags & SR_BOOL_MFMA) && base_kind(kind) != SR_BOOL)
+        return fail(SR_EINVAL, "%s: SR_BOOL_MFMA applies to SR_BOOL only", fn);
     if (methods & (methods - 1))
         return fail(SR_EINVAL, "%s: at most one of SR_CLOSURE_SQUARING, "
                                "SR_CLOSURE_WARSHALL, SR_CLOSURE_BIG_BLOCKS", fn);
     if ((flags & SR_CLOSURE_BIG_BLOCKS) && base_kind(kind) == SR_BOOL)
         return fail(SR_EUNSUPPORTED, "%s: SR_CLOSURE_BIG_BLOCKS is for non-Boolean kinds", fn);
-    const bool serial = (flags & SR_SERIAL_PHASES) != 0;
-    if (flags & SR_BOOL_MFMA)
-        return fail(SR_EUNSUPPORTED, "%s: the int8 matrix-core path is for products only", fn);
     if (D < 0) return fail(SR_EINVAL, "%s: negative size", fn);
     if (D > INT32_MAX) return fail(SR_EINVAL, "%s: sizes above 2^31-1 are not supported", fn);
-    int rc;
-    if ((rc = check_matrix(kind, "T", T, ldt, D, D)) != SR_OK) return rc;
-    if (D == 0) return ok();
-    hipStream_t st = as_stream(stream);
-    hipError_t e = hipSuccess;
-    const int es = (int)unit_bytes(kind);
+    return SR_OK;
+}
+
+struct ClosurePlan {
+    unsigned method, bool_path;
+    size_t copy_bytes, work_bytes;
+};
+
+// The method: forced by a flag; else the autotuned choice for this size
+// class, if any; else the built-in size rules -- repeated squaring for small
+// anti-distance matrices (where the blocked loop's chain of D sequential
+// pivot steps dominates), big pivot blocks closed by squaring for mid sizes,
+// the blocked loop otherwise; loop_only (a capture without caller-supplied
+// working memory) turns a default squaring or big-block choice into the loop.
+// Flags are valid (checked by the caller).
+ClosurePlan plan_closure(int kind, int64_t D, unsigned flags, bool loop_only) {
     const int ak = base_kind(kind);
-    // The method: forced by a flag; else the autotuned choice for this size
-    // class, if any; else the built-in size rules -- repeated squaring for
-    // small anti-distance matrices (where the blocked loop's chain of D
-    // sequential pivot steps dominates), big pivot blocks closed by squaring
-    // for mid sizes, the blocked loop otherwise.  Squaring and big blocks
-    // allocate working memory, so a stream being captured takes the loop
-    // (unless the caller supplied the working memory).
-    unsigned method = methods;
-    unsigned bool_path = flags & (SR_BOOL_BITWISE | SR_BOOL_M4R);
-    if (!method && serial) method = SR_CLOSURE_WARSHALL;
+    unsigned method = flags & (SR_CLOSURE_SQUARING | SR_CLOSURE_WARSHALL | SR_CLOSURE_BIG_BLOCKS);
+    unsigned bool_path = flags & (SR_BOOL_BITWISE | SR_BOOL_M4R | SR_BOOL_MFMA);
+    if (!method && (flags & SR_SERIAL_PHASES)) method = SR_CLOSURE_WARSHALL;
     if (!method) {
         const unsigned t = sr::tuned_get(sr::kTuneClosure, kind, D, 0, 0);
         if (t) {
             method = t & (SR_CLOSURE_SQUARING | SR_CLOSURE_WARSHALL | SR_CLOSURE_BIG_BLOCKS);
-            if (!bool_path) bool_path = t & (SR_BOOL_BITWISE | SR_BOOL_M4R);
+            if (!bool_path) bool_path = t & (SR_BOOL_BITWISE | SR_BOOL_M4R | SR_BOOL_MFMA);
         } else if (D >= kSquaringMinD && D <= squaring_max_d(ak)) {
             method = SR_CLOSURE_SQUARING;
         } else if (ak != SR_BOOL && D > squaring_max_d(ak) && D <= big_block_max_d(ak)) {
@@ -539,29 +556,53 @@ int closure_run(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void 
         } else {
             method = SR_CLOSURE_WARSHALL;
         }
-        if (method != SR_CLOSURE_WARSHALL && !fixed && capturing(st))
-            method = SR_CLOSURE_WARSHALL;
+        if (method != SR_CLOSURE_WARSHALL && loop_only) method = SR_CLOSURE_WARSHALL;
     }
-    // Working memory first, so that a failed allocation returns before the
-    // caller's matrix is touched: the binary16 copy of uint8 data, and the
-    // two matrices of squaring (of the whole matrix, or of one big block).
+    ClosurePlan p;
+    p.method = method;
+    p.bool_path = bool_path;
+    p.copy_bytes = ak == SR_ANTIDIST_U8 ? (size_t)(D * round_up(D, 64)) * 2 : 0;
+    p.work_bytes = closure_need(kind, D, method, bool_path);
+    return p;
+}
+
+}  // namespace
+
+namespace sr {
+
+int closure_run(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream,
+                int (*fixed_work)(void **), size_t fixed_bytes, const char *fn) {
+    const bool fixed = fixed_work != nullptr;
+    int rc = check_closure_args(kind, D, flags, fn);
+    if (rc != SR_OK) return rc;
+    const unsigned methods = flags & (SR_CLOSURE_SQUARING | SR_CLOSURE_WARSHALL |
+                                      SR_CLOSURE_BIG_BLOCKS);
+    const bool serial = (flags & SR_SERIAL_PHASES) != 0;
+    if ((rc = check_matrix(kind, "T", T, ldt, D, D)) != SR_OK) return rc;
+    if (D == 0) return ok();
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipSuccess;
+    const int es = (int)unit_bytes(kind);
+    const int ak = base_kind(kind);
+    // The method, the Boolean bulk-update path and the working memory.  A
+    // stream being captured takes the loop unless the caller supplied the
+    // working memory.
+    ClosurePlan pl = plan_closure(kind, D, flags, !fixed && capturing(st));
+    unsigned method = pl.method;
+    const unsigned bool_path = pl.bool_path;
     const bool s8 = ak == SR_ANTIDIST_U8;
     const int64_t lw = round_up(D, 64);
-    const size_t tw = s8 ? (size_t)(D * lw) * 2 : 0;
+    const size_t tw = pl.copy_bytes;
     const int wes = s8 ? 2 : es;
-    auto need_of = [&](unsigned m) {
-        if (m == SR_CLOSURE_WARSHALL) return tw;
-        const int64_t b = m == SR_CLOSURE_BIG_BLOCKS ? std::min<int64_t>(big_block_size(), D) : D;
-        return tw + squaring_work_bytes(wes, b);
-    };
-    size_t need = need_of(method);
+    const bool bool_mfma = ak == SR_BOOL && (bool_path & SR_BOOL_MFMA);
+    size_t need = pl.work_bytes;
     void *w = nullptr;
     if (fixed) {
         // the caller's buffer: a method chosen by default that needs more
         // falls back to the loop, which needs only the uint8 working copy
         if (need > fixed_bytes && !methods && method != SR_CLOSURE_WARSHALL) {
             method = SR_CLOSURE_WARSHALL;
-            need = need_of(method);
+            need = closure_need(kind, D, method, bool_path);
         }
         if (need > fixed_bytes)
             return fail(SR_EINVAL,
@@ -592,11 +633,12 @@ int closure_run(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void 
         e = big ? closure_big_blocks(wes, s8, M, ldm, D, B, work, st)
                 : closure_by_squaring(wes, s8, M, ldm, D, work, st);
     } else if (e == hipSuccess && ak == SR_BOOL) {
-        const int path = (bool_path & SR_BOOL_M4R) ? sr::kBoolPathM4r
+        const int path = (bool_path & SR_BOOL_M4R)       ? sr::kBoolPathM4r
                          : (bool_path & SR_BOOL_BITWISE) ? sr::kBoolPathBitwise
+                         : bool_mfma                     ? sr::kBoolPathMfma
                                                          : sr::kBoolPathAuto;
         e = sr::launch_bool_closure(static_cast<uint64_t *>(T), ldt, D, serial, path, st,
-                                     aux_create);
+                                     aux_create, w);
     } else if (e == hipSuccess && ak == SR_ANTIDIST_U32) {
         e = sr::launch_ad32_closure(static_cast<uint32_t *>(T), ldt, D, serial, st, aux_create);
     } else if (e == hipSuccess) {
@@ -648,6 +690,14 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
 
 int closure(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream) {
     return sr::closure_run(kind, T, ldt, D, flags, stream, nullptr, 0, "closure");
+}
+
+int64_t closure_work_bytes(int kind, int64_t D, unsigned flags) {
+    const int rc = check_closure_args(kind, D, flags, "closure_work_bytes");
+    if (rc != SR_OK) return rc;
+    if (D == 0) return 0;
+    const size_t need = plan_closure(kind, D, flags, false).work_bytes;
+    return need > 0 ? (int64_t)std::max<size_t>(need, 256) : 0;
 }
 
 }  // extern "C"
@@ -859,7 +909,8 @@ int sr_autotune_closure(int kind, int64_t D, unsigned *chosen, void *stream) {
     const size_t bytes = (size_t)(D * ld * unit_bytes(kind));
     std::vector<unsigned> cands;
     if (ak == SR_BOOL) {
-        cands = {SR_CLOSURE_WARSHALL | SR_BOOL_BITWISE, SR_CLOSURE_WARSHALL | SR_BOOL_M4R};
+        cands = {SR_CLOSURE_WARSHALL | SR_BOOL_BITWISE, SR_CLOSURE_WARSHALL | SR_BOOL_M4R,
+                 SR_CLOSURE_WARSHALL | SR_BOOL_MFMA};
     } else {
         cands = {SR_CLOSURE_WARSHALL};
         if (D > 512 && D <= 16384) cands.push_back(SR_CLOSURE_BIG_BLOCKS);
@@ -946,9 +997,14 @@ struct sr_batch {
     int64_t count = 0;
     std::vector<sr::BatchDesc> h;  // largest first; uint8: working copies placed
     sr::BatchPlan *plan = nullptr;
-    char *dev = nullptr;      // hipMalloc: the plan image (image_cap bytes), then
-    size_t image_cap = 0;     // the uint8 working copies
+    char *dev = nullptr;      // hipMalloc: the first plan image (image_cap bytes),
+    size_t image_cap = 0;     // then the uint8 / Boolean working copies
     size_t work_elems = 0;
+    char *image = nullptr;    // the current plan's device image (dev, or one of retired)
+    // images of later plans (sr_batch_autotune): each re-plan uploads into a
+    // fresh allocation, so a graph that captured an earlier run keeps reading
+    // the image (and grid) it was captured with; all are freed by destroy
+    std::vector<char *> retired;
 };
 
 namespace {
@@ -983,6 +1039,7 @@ void batch_free(sr_batch *b) {
     if (!b) return;
     if (b->plan) sr::batch_plan_destroy(b->plan);
     if (b->dev) (void)hipFree(b->dev);
+    for (char *p : b->retired) (void)hipFree(p);
     delete b;
 }
 
@@ -1043,6 +1100,7 @@ int batch_create_impl(int kind, void *const *T, const int64_t *ldt, const int64_
         if (!b->plan) return fail(SR_EINVAL, "sr_batch_create: %s", kPlanFailure);
         const hipError_t e = upload_image(b->plan, b->h, b->dev, st);
         if (e != hipSuccess) return device_fail(e, "sr_batch_create upload");
+        b->image = b->dev;
     }
     *out = b.release();
     return ok();
@@ -1062,7 +1120,7 @@ int sr_batch_run(sr_batch *b, void *stream) {
         return fail(SR_EINVAL, "sr_batch_run: the batch belongs to device %d, current is %d",
                     b->device, dev);
     const hipError_t e = sr::launch_ad_closure_batched_resident(
-        b->s8, b->plan, b->count, b->dev, b->dual, b->reflexive, b->bits, b->wide,
+        b->s8, b->plan, b->count, b->image, b->dual, b->reflexive, b->bits, b->wide,
         as_stream(stream));
     if (e != hipSuccess) return device_fail(e, "sr_batch_run launch");
     return ok();
@@ -1151,18 +1209,24 @@ int batch_autotune_impl(sr_batch *b, int *chosen, void *stream) {
     (void)hipStreamSynchronize(st);
     if (!pick) return fail(SR_EDEVICE, "sr_batch_autotune: no candidate ran");
     if (pick != sr::batch_plan_tile(b->plan)) {
-        sr::BatchPlan *np = sr::batch_plan_create(b->h.data(), b->count, pick);
+        // the new plan goes to a fresh image; the current one stays
+        // allocated (and unchanged) for graphs captured from earlier runs
+        std::unique_ptr<sr::BatchPlan, void (*)(sr::BatchPlan *)> np(
+            sr::batch_plan_create(b->h.data(), b->count, pick), sr::batch_plan_destroy);
         if (!np) return fail(SR_EINVAL, "sr_batch_autotune: %s", kPlanFailure);
-        const hipError_t e = upload_image(np, b->h, b->dev, st);
-        if (e != hipSuccess) {
-            // the device image may be partly overwritten: keep the handle
-            // consistent by re-uploading the old plan
-            sr::batch_plan_destroy(np);
-            (void)upload_image(b->plan, b->h, b->dev, st);
-            return device_fail(e, "sr_batch_autotune upload");
+        const size_t bytes = (size_t)round_up(
+            (int64_t)sr::batch_plan_bytes(np.get(), b->count), 256);
+        char *img = nullptr;
+        if (hipMalloc(reinterpret_cast<void **>(&img), bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SR_ENOMEM, "sr_batch_autotune: could not allocate %zu bytes", bytes);
         }
+        b->retired.push_back(img);
+        const hipError_t e = upload_image(np.get(), b->h, img, st);
+        if (e != hipSuccess) return device_fail(e, "sr_batch_autotune upload");
         sr::batch_plan_destroy(b->plan);
-        b->plan = np;
+        b->plan = np.release();
+        b->image = img;
     }
     sr::tuned_set(sr::kTuneBatch, b->kind, b->h.front().D, b->count, 0, (unsigned)pick);
     if (chosen) *chosen = pick;

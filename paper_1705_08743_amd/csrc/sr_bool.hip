@@ -399,11 +399,6 @@ k_bool_fw_panels(uint32_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg, in
 // chunks of NWB words (the last one may be partial); T_ij (|)= T_iK * T_Kj for
 // the pivot block K = [k0, k0 + bs).  Workgroups [0, nch0) take chunks of the
 // first word range; each of a workgroup's four waves takes one row chunk.
-struct BRect {
-    int r_lo, r_hi, r_ex0, r_ex1;
-    int w0a, w0b, w1a, w1b;
-};
-
 template <int NWB>
 __global__ void __launch_bounds__(256)
 k_bool_fw_update(uint32_t *T, int64_t ld, int D, int k0, int bs, BRect q, int nch0, int prio) {
@@ -790,15 +785,25 @@ hipError_t update_m4r(uint32_t *T, int64_t ld, int64_t D, const BBlock &b, const
     return hipGetLastError();
 }
 
-// nwb: word-chunk width of the bit-sliced kernel, or 0 for the
-// four-Russians kernel.
+// nwb: word-chunk width of the bit-sliced kernel, 0 for the four-Russians
+// kernel, kUpdateMfma for the matrix cores (the pivot rows transposed into
+// pt first, on the same stream).
+constexpr int kUpdateMfma = -1;
 hipError_t update_b(uint32_t *T, int64_t ld, int64_t D, int64_t kb, const BRect &q, int nwb,
-                    double units, hipStream_t st, bool critical = false) {
+                    double units, hipStream_t st, bool critical = false,
+                    uint32_t *pt = nullptr) {
     const BBlock b = bblock(D, kb);
     const int prio = critical ? crit_prio() : 0;
     const bool prof = prof_on();
-    if (prof) prof_begin(st);
     hipError_t e;
+    if (nwb == kUpdateMfma) {
+        e = launch_bool_pivot_transpose(pt, T, ld, D, b.k0, b.bs, st);
+        if (prof) prof_begin(st);
+        if (e == hipSuccess) e = launch_bool_fw_update_mfma(T, ld, D, b.k0, q, pt, st);
+        if (prof) prof_end(st, 0, 2, units);
+        return e;
+    }
+    if (prof) prof_begin(st);
     if (nwb == 0) {
         e = update_m4r(T, ld, D, b, q, st);
         if (prof) prof_end(st, 0, 2, units);
@@ -887,7 +892,7 @@ int bool_update_nwb(int64_t D) {
 }
 
 hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool serial, int path,
-                               hipStream_t st, bool aux_create) {
+                               hipStream_t st, bool aux_create, void *work) {
     uint32_t *T = reinterpret_cast<uint32_t *>(T64);
     const int64_t ld = 2 * ld64;
     const int64_t nb = (D + kBoolBlock - 1) / kBoolBlock;
@@ -896,7 +901,8 @@ hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool seri
     // bulk update: the four-Russians tables where the grid of 512 x 512 tiles
     // fills the device, else the bit-sliced kernel
     const bool m4r = path == kBoolPathM4r || (path == kBoolPathAuto && D >= 8192);
-    const int nwb = m4r ? 0 : bool_update_nwb(D);
+    const int nwb = path == kBoolPathMfma ? kUpdateMfma : m4r ? 0 : bool_update_nwb(D);
+    uint32_t *pt = static_cast<uint32_t *>(work);
     hipError_t e = pivot_b(T, ld, D, 0, st);
     if (e != hipSuccess || nb == 1) return e;
     if ((e = panels_b(T, ld, D, 0, st)) != hipSuccess) return e;
@@ -909,7 +915,7 @@ hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool seri
             const double rest = (double)D - bs;
             if (e == hipSuccess)
                 e = update_b(T, ld, D, kb, BRect{0, nrc, b.rl, b.rh, 0, b.wl, b.wh, nwd}, nwb,
-                             rest * rest * bs, st);
+                             rest * rest * bs, st, false, pt);
             if (e == hipSuccess && kb + 1 < nb) e = pivot_b(T, ld, D, kb + 1, st);
             if (e == hipSuccess && kb + 1 < nb) e = panels_b(T, ld, D, kb + 1, st);
             if (e != hipSuccess) break;
@@ -922,7 +928,7 @@ hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool seri
         if (e == hipSuccess) e = hipStreamWaitEvent(aux->stream, aux->ev_main, 0);
         if (e == hipSuccess)
             e = update_b(T, ld, D, kb, BRect{0, nrc, b.rl, n.rh, 0, b.wl, n.wh, nwd}, nwb,
-                         rest2 * rest2 * bs, aux->stream);
+                         rest2 * rest2 * bs, aux->stream, false, pt);
         if (e == hipSuccess) e = hipEventRecord(aux->ev_aux[kb & 1], aux->stream);
         // A(kb) writes row block kb+1, which B(kb-1) writes too
         if (e == hipSuccess && kb > 0) e = hipStreamWaitEvent(st, aux->ev_aux[(kb - 1) & 1], 0);

@@ -70,28 +70,49 @@ hipError_t launch_narrow_u8(uint8_t *dst, int64_t ldd, const uint16_t *src, int6
 
 // Boolean, bit-packed: strides in 64-bit words (even), widths in bits.
 // path: kBoolPathAuto (chosen by size), kBoolPathBitwise (the bit-sliced
-// kernels) or kBoolPathM4r (the "four Russians" tables).
-enum { kBoolPathAuto = 0, kBoolPathBitwise = 1, kBoolPathM4r = 2 };
+// kernels), kBoolPathM4r (the "four Russians" tables) or, for the closure's
+// bulk update, kBoolPathMfma (the matrix cores).
+enum { kBoolPathAuto = 0, kBoolPathBitwise = 1, kBoolPathM4r = 2, kBoolPathMfma = 3 };
+
+// A rectangle of a Boolean closure's update (phase 3): 64-row chunks
+// [r_lo, r_hi) minus [r_ex0, r_ex1), times the 32-bit words [w0a, w0b) and
+// [w1a, w1b).
+struct BRect {
+    int r_lo, r_hi, r_ex0, r_ex1;
+    int w0a, w0b, w1a, w1b;
+};
 hipError_t launch_bool_mul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda,
                            const uint64_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                            bool accumulate, int path, hipStream_t stream);
-// path: kBoolPathAuto, or force the bit-sliced (kBoolPathBitwise) or the
-// four-Russians (kBoolPathM4r) kernels for the bulk update.
+// path: kBoolPathAuto, or force the bit-sliced (kBoolPathBitwise), the
+// four-Russians (kBoolPathM4r) or the matrix-core (kBoolPathMfma) kernels for
+// the bulk update; the last needs `work`, bool_mfma_closure_work_bytes(D)
+// bytes (256-byte aligned, alive until the work has run).
 hipError_t launch_bool_closure(uint64_t *T, int64_t ld, int64_t D, bool serial, int path,
-                               hipStream_t stream, bool aux_create = true);
+                               hipStream_t stream, bool aux_create = true,
+                               void *work = nullptr);
 // Boolean product with the "four Russians" tables (sr_bool.hip); `launch_bool_mul`
 // chooses between it and the bit-sliced kernel, path forces one.
 hipError_t launch_bool_mul_m4r(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda,
                                const uint64_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                                bool accumulate, hipStream_t stream);
 
-// Boolean product on the matrix cores (sr_bool_mfma.hip): bits expanded to
-// int8 in `work` (bool_mfma_work_bytes(R, K, N) bytes, 256-byte aligned,
-// alive until the work has run), integer product, threshold.
+// Boolean product on the matrix cores (sr_bool_mfma.hip): B bit-transposed
+// into `work` (bool_mfma_work_bytes(R, K, N) bytes, 256-byte aligned, alive
+// until the work has run), counts of common bits on the matrix cores,
+// threshold.
 size_t bool_mfma_work_bytes(int64_t R, int64_t K, int64_t N);
 hipError_t launch_bool_mul_mfma(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t lda,
                                 const uint64_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                                 bool accumulate, void *work, hipStream_t stream);
+// The closure's bulk update on the matrix cores: PT := the transposed pivot
+// rows [k0, k0 + bs) of T (strides in 32-bit words; PT holds
+// bool_mfma_closure_work_bytes(D) bytes), then T_ij (|)= T_iK * T_Kj over q.
+size_t bool_mfma_closure_work_bytes(int64_t D);
+hipError_t launch_bool_pivot_transpose(uint32_t *PT, const uint32_t *T, int64_t ld, int64_t D,
+                                       int k0, int bs, hipStream_t stream);
+hipError_t launch_bool_fw_update_mfma(uint32_t *T, int64_t ld, int64_t D, int k0,
+                                      const BRect &q, const uint32_t *PT, hipStream_t stream);
 
 // Entrywise operations (values of the op argument; the table of Sec. V):
 // and = min, or = max, xor = |a - b|, not = S - a; on Boolean words AND, OR,

@@ -19,62 +19,77 @@ whose result goes back to the host.  The server:
   still running;
 * measures latency from a request's arrival to the completion of its closure
   on the device (hipEvent timestamps on the request's stream, relative to a
-  start event), and separately to the end of its download.
+  start event), and separately to the end of its download;
+* isolates failures: a request whose closure call is refused by the library
+  fails alone (its error is recorded, its slot and memory are released); when
+  a batched call is refused, its requests are closed one by one, so only the
+  bad one fails;
+* cancels queued requests: ``cancel(rid)`` (from any thread) or a request's
+  ``cancel_at`` time removes it from the queue if it has not been admitted
+  yet; it is then never run.
 
 ``mode="serial"`` replays the same trace one solve at a time in arrival order
 on one stream (no batching, no overlap): the baseline the served numbers are
 compared with.  Every result is the same in both modes (integer arithmetic).
 """
 import collections
+import threading
 import time
 
 import numpy as np
 
-from . import (SR_ANTIDIST_U16, SR_ANTIDIST_U8, SR_BOOL, closure, closure_batched, empty,
-               padded_ld)
+from . import (SR_ANTIDIST_U16, SR_ANTIDIST_U8, SR_BOOL, SemiringError, closure,
+               closure_batched, closure_work_bytes, empty, padded_ld)
 
 _UNIT = {SR_BOOL: 8, SR_ANTIDIST_U8: 1, SR_ANTIDIST_U16: 2}
 
 
 def footprint_bytes(kind, n, batch_n=256):
     """Device bytes a request holds while admitted: its padded matrix, plus
-    the library's stream-ordered working memory for its closure (the 16-bit
-    copy of a uint8 matrix, or of a Boolean one of at most batch_n vertices,
-    which may be closed in a batch; and the two working matrices of repeated
-    squaring, which closure() takes for anti-distance matrices of 192 to 1024
-    vertices)."""
+    the library's working memory for its closure -- what closure() allocates
+    for this kind and size (the library's own query, which follows its
+    method rules and autotuning table) or, for a request small enough to be
+    closed in a batch, the batch's 16-bit working copy if that is larger."""
     b = n * padded_ld(n, kind) * _UNIT[kind]
-    lw = -(-n // 64) * 64
-    if kind == SR_BOOL:
-        if n <= batch_n:
-            b += n * lw * 2
-        return b
-    if kind == SR_ANTIDIST_U8:
-        b += n * lw * 2
-    if 192 <= n <= 1024:
-        b += 2 * n * lw * 2
-    return b
+    work = closure_work_bytes(kind, n)
+    if n <= batch_n and kind in (SR_BOOL, SR_ANTIDIST_U8):
+        work = max(work, n * (-(-n // 8) * 8) * 2)
+    return b + work
 
 
 class Request:
     """One closure request: kind, vertex count, host matrix (uint8 / uint16
-    entries, or uint64 Boolean words), arrival time in seconds."""
+    entries, or uint64 Boolean words), arrival time in seconds.
+
+    cancel_at: seconds from the start at which the request is withdrawn if it
+    is still queued (None: never).  inject_fault: the request's closure call
+    is made with a size beyond its matrix, which the library refuses (a
+    failure injected for tests of failure isolation).  After a run, `result`
+    holds the closure, or None with `error` (refused) or `cancelled` set."""
 
     __slots__ = ("rid", "kind", "n", "host", "arrival", "footprint", "result", "t_admit",
-                 "t_compute_done", "t_done", "batch_size", "_dev", "_pin_in", "_pin_out")
+                 "t_compute_done", "t_done", "batch_size", "cancel_at", "inject_fault",
+                 "error", "cancelled", "_dev", "_pin_in", "_pin_out")
 
-    def __init__(self, rid, kind, n, host, arrival=0.0):
+    def __init__(self, rid, kind, n, host, arrival=0.0, cancel_at=None, inject_fault=False):
         self.rid = rid
         self.kind = kind
         self.n = n
         self.host = host
         self.arrival = float(arrival)
         self.footprint = footprint_bytes(kind, n)
+        self.cancel_at = cancel_at
+        self.inject_fault = bool(inject_fault)
+        self._reset()
+
+    def _reset(self):
         self.result = None
         self.t_admit = None
         self.t_compute_done = None
         self.t_done = None
         self.batch_size = 0
+        self.error = None
+        self.cancelled = False
 
 
 class _Job:
@@ -98,6 +113,14 @@ class ClosureServer:
         self.batch_max = int(batch_max)
         self.streams = [torch.cuda.Stream() for _ in range(self.nslots)]
         self._pinned = {}
+        self._cancel_lock = threading.Lock()
+        self._cancel_ids = set()
+
+    def cancel(self, rid):
+        """Withdraw request `rid` if it is still queued (thread-safe; takes
+        effect at the serving loop's next pass)."""
+        with self._cancel_lock:
+            self._cancel_ids.add(rid)
 
     # -- one request's buffers --------------------------------------------
     def _prepare(self, req):
@@ -119,8 +142,22 @@ class ClosureServer:
         req._pin_in = pin[1]
         req._pin_out = torch.empty(pin[1].shape, dtype=pin[1].dtype, pin_memory=True)
 
+    @staticmethod
+    def _dim(r):
+        # an injected fault asks for more vertices than the matrix holds
+        return r.n + (1 << 20) if r.inject_fault else r.n
+
+    def _close_one(self, r, stream):
+        try:
+            closure(r.kind, r._dev, D=self._dim(r), stream=stream)
+        except SemiringError as e:
+            r.error = str(e)
+
     def _launch(self, reqs, slot):
-        """Upload, close and download a group of requests on one stream."""
+        """Upload, close and download a group of requests on one stream.  A
+        refused closure call fails its request alone: the library checks
+        every argument before it enqueues anything, so a refused batch is
+        closed again one request at a time."""
         torch = self.torch
         stream = self.streams[slot]
         ev_compute = torch.cuda.Event(enable_timing=True)
@@ -131,13 +168,18 @@ class ClosureServer:
                 r._dev = empty(r.kind, r.n, cols, zero=False)
                 r._dev.copy_(r._pin_in, non_blocking=True)
             if len(reqs) == 1:
-                r = reqs[0]
-                closure(r.kind, r._dev, D=r.n, stream=stream)
+                self._close_one(reqs[0], stream)
             else:
-                closure_batched(reqs[0].kind, [r._dev for r in reqs], stream=stream)
+                try:
+                    closure_batched(reqs[0].kind, [r._dev for r in reqs],
+                                    Ds=[self._dim(r) for r in reqs], stream=stream)
+                except SemiringError:
+                    for r in reqs:
+                        self._close_one(r, stream)
             ev_compute.record(stream)
             for r in reqs:
-                r._pin_out.copy_(r._dev, non_blocking=True)
+                if r.error is None:
+                    r._pin_out.copy_(r._dev, non_blocking=True)
             ev_done.record(stream)
         for r in reqs:
             r.batch_size = len(reqs)
@@ -169,6 +211,7 @@ class ClosureServer:
         if mode not in ("served", "serial"):
             raise ValueError("mode is 'served' or 'serial'")
         for r in requests:
+            r._reset()
             r.footprint = footprint_bytes(r.kind, r.n, self.batch_n)
             if r.footprint > self.budget:
                 raise ValueError("request %d needs %d bytes, above the budget" % (r.rid, r.footprint))
@@ -188,13 +231,22 @@ class ClosureServer:
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
             progressed = False
+            # withdrawals of queued requests, before any admission
+            with self._cancel_lock:
+                ids = set(self._cancel_ids)
+            for r in list(waiting):
+                if r.rid in ids or (r.cancel_at is not None and r.cancel_at <= now):
+                    waiting.remove(r)
+                    r.cancelled = True
+                    r.t_done = now
+                    progressed = True
             for job in list(inflight):
                 if job.ev_done.query():
                     tc = ev0.elapsed_time(job.ev_compute) * 1e-3
                     td = ev0.elapsed_time(job.ev_done) * 1e-3
                     for r in job.reqs:
                         r.t_compute_done, r.t_done = tc, td
-                        r.result = r._pin_out.numpy()
+                        r.result = r._pin_out.numpy() if r.error is None else None
                         r._dev = None
                     free_bytes += job.bytes
                     free_slots.append(job.slot)
@@ -220,26 +272,37 @@ class ClosureServer:
                         time.sleep(min(wait, 1e-3))
                 else:
                     time.sleep(poll_sleep)
+        with self._cancel_lock:
+            self._cancel_ids.clear()
         return summarize(requests, mode)
 
 
 def summarize(requests, mode):
-    lat = np.array([r.t_compute_done - r.arrival for r in requests])
-    e2e = np.array([r.t_done - r.arrival for r in requests])
+    """Latency percentiles and throughput over the completed requests
+    (failed and cancelled ones are counted apart)."""
+    done = [r for r in requests if not r.cancelled and r.error is None]
+    if not done:
+        return {"mode": mode, "requests": 0,
+                "failed": int(sum(1 for r in requests if r.error is not None)),
+                "cancelled": int(sum(1 for r in requests if r.cancelled))}
+    lat = np.array([r.t_compute_done - r.arrival for r in done])
+    e2e = np.array([r.t_done - r.arrival for r in done])
     first = min(r.arrival for r in requests)
-    last = max(r.t_done for r in requests)
+    last = max(r.t_done for r in done)
     span = last - first
-    updates = float(sum(float(r.n) ** 3 for r in requests))
+    updates = float(sum(float(r.n) ** 3 for r in done))
     return {
         "mode": mode,
-        "requests": len(requests),
+        "requests": len(done),
+        "failed": int(sum(1 for r in requests if r.error is not None)),
+        "cancelled": int(sum(1 for r in requests if r.cancelled)),
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "mean_ms": float(lat.mean() * 1e3),
         "p50_e2e_ms": float(np.percentile(e2e, 50) * 1e3),
         "p99_e2e_ms": float(np.percentile(e2e, 99) * 1e3),
         "makespan_s": span,
-        "throughput_rps": len(requests) / span,
+        "throughput_rps": len(done) / span,
         "updates_per_s": updates / span,
-        "batched_requests": int(sum(1 for r in requests if r.batch_size > 1)),
+        "batched_requests": int(sum(1 for r in done if r.batch_size > 1)),
     }

@@ -25,7 +25,8 @@ def L():
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int64_t|int|void|char)\s*\*?\s*(\w+)\s*\(", text,
+                       flags=re.M)
     return sorted(set(names))
 
 
@@ -93,7 +94,11 @@ def test_closure_rejects_bad_arguments(L):
     assert L.closure(U16, P, 8, -1, 0, None) == sr.SR_EINVAL
     assert L.closure(U16, P, 4, 8, 0, None) == sr.SR_EINVAL
     assert L.closure(U16, P + 8, 8, 8, 0, None) == sr.SR_EALIGN
-    assert L.closure(sr.SR_BOOL, P, 2, 8, sr.SR_BOOL_MFMA, None) == sr.SR_EUNSUPPORTED
+    # one Boolean path at most; the matrix-core path is Boolean only
+    assert L.closure(sr.SR_BOOL, P, 2, 8, sr.SR_BOOL_MFMA | sr.SR_BOOL_BITWISE,
+                     None) == sr.SR_EINVAL
+    assert L.closure(sr.SR_BOOL, P, 2, 8, sr.SR_BOOL_MFMA | sr.SR_BOOL_M4R, None) == sr.SR_EINVAL
+    assert L.closure(U16, P, 8, 8, sr.SR_BOOL_MFMA, None) == sr.SR_EINVAL
     assert L.closure(U16, P, 8, 8, 0x400, None) == sr.SR_EINVAL
     assert L.closure(U16, P, 8, 8, sr.SR_CLOSURE_SQUARING | sr.SR_CLOSURE_WARSHALL,
                      None) == sr.SR_EINVAL
@@ -187,7 +192,7 @@ def test_u32_kinds_validation(L):
         assert mul(L, kind, P, 4, P + 32, 4, P + 8192, 4, 4, 4, 4) == sr.SR_EALIAS  # 64-byte C
         assert mul(L, kind, P, 4, P + 4096, 4, P + 8192, 4, 4, 4, 4, sr.SR_BOOL_M4R) == sr.SR_EINVAL
         assert L.closure(kind, P, 2, 4, 0, None) == sr.SR_EINVAL  # ld < D
-        assert L.closure(kind, P, 4, 4, sr.SR_BOOL_MFMA, None) == sr.SR_EUNSUPPORTED
+        assert L.closure(kind, P, 4, 4, sr.SR_BOOL_MFMA, None) == sr.SR_EINVAL
         n = 1
         ptrs = (ctypes.c_void_p * n)(P)
         lds = (ctypes.c_int64 * n)(2)
@@ -257,7 +262,7 @@ def test_closure_noalloc_checks_before_any_device_call(L):
     assert f(U16, P, 8, -1, 0, None) == sr.SR_EINVAL
     assert f(U16, P, 4, 8, 0, None) == sr.SR_EINVAL
     assert f(U16, P + 8, 8, 8, 0, None) == sr.SR_EALIGN
-    assert f(sr.SR_BOOL, P, 2, 8, sr.SR_BOOL_MFMA, None) == sr.SR_EUNSUPPORTED
+    assert f(U16, P, 8, 8, sr.SR_BOOL_MFMA, None) == sr.SR_EINVAL
     assert f(U16, P, 8, 8, 0x400, None) == sr.SR_EINVAL
     # uint8 data above 4096 vertices: the binary16 working copy alone is
     # 2 * D * round_up(D, 64) bytes > 32 MiB
@@ -269,4 +274,30 @@ def test_closure_noalloc_checks_before_any_device_call(L):
     # working matrices (36 MB)
     assert f(U16, P, 3008, 3000, sr.SR_CLOSURE_SQUARING, None) == sr.SR_EINVAL
     assert "static scratch" in L.sr_last_error().decode()
+
+
+def test_closure_work_bytes(L):
+    """The working-memory query follows closure()'s method rules: nothing for
+    the 16-bit loop and for Boolean matrices, the binary16 copy for uint8
+    data, two squared matrices for squaring, one big block's for big blocks,
+    the transposed pivot rows for the Boolean matrix-core update; invalid
+    arguments give the closure's error codes."""
+    f = L.closure_work_bytes
+    U16, U8 = sr.SR_ANTIDIST_U16, sr.SR_ANTIDIST_U8
+    sr.autotune_clear()
+    assert f(U16, 0, 0) == 0
+    assert f(U16, 8192, 0) == 0
+    assert f(sr.SR_BOOL, 16384, 0) == 0
+    assert f(U16, 1000, 0) == 2 * 1000 * 1024 * 2 + 256                  # squaring
+    assert f(U16, 2000, 0) == 2 * 512 * 512 * 2 + 256                    # big blocks
+    assert f(U8, 8192, 0) == 8192 * 8192 * 2                             # binary16 copy
+    assert f(U8, 1000, 0) == 1000 * 1024 * 2 + 2 * 1000 * 1024 * 2 + 256
+    assert f(sr.SR_ANTIDIST_U32, 700, 0) == 2 * 700 * 704 * 4 + 256
+    assert f(U16, 1000, sr.SR_CLOSURE_WARSHALL) == 0
+    assert f(U16, 1000, sr.SR_SERIAL_PHASES) == 0
+    assert f(sr.SR_BOOL, 16384, sr.SR_BOOL_MFMA) > 0
+    assert f(U16, -1, 0) == sr.SR_EINVAL
+    assert f(9, 10, 0) == sr.SR_EINVAL
+    assert f(U16, 10, sr.SR_BOOL_MFMA) == sr.SR_EINVAL
+    assert sr.closure_work_bytes(U16, 1000) == 2 * 1000 * 1024 * 2 + 256
 

@@ -125,12 +125,17 @@ def cfg3():
     return D, W, oracle.bool_closure_words(W, D)
 
 
-@pytest.mark.parametrize("flags", [0, sr.SR_BOOL_BITWISE, sr.SR_BOOL_M4R])
-def test_bool_closure_config3(cfg3, flags):
+@pytest.mark.parametrize("flags,fmt", [(0, None), (sr.SR_BOOL_BITWISE, None),
+                                       (sr.SR_BOOL_M4R, None), (sr.SR_BOOL_MFMA, "f4"),
+                                       (sr.SR_BOOL_MFMA, "i8")])
+def test_bool_closure_config3(cfg3, flags, fmt, monkeypatch):
     """Configuration 3: Boolean D = 16384, mean out-degree 3 plus planted
     strongly connected blocks; every word against the oracle for the default
-    bulk update and each forced one (bit-sliced, four-Russians tables, int8
-    matrix cores); padding bits stay clear."""
+    bulk update and each forced one (bit-sliced, four-Russians tables, the
+    matrix cores with 4-bit float and with int8 operands); padding bits stay
+    clear."""
+    if fmt:
+        monkeypatch.setenv("SR_MFMA_FORMAT", fmt)
     D, W, want = cfg3
     T = sr.to_device(sr.SR_BOOL, W, cols=D)
     sr.closure(sr.SR_BOOL, T, D=D, flags=flags)
@@ -141,10 +146,13 @@ def test_bool_closure_config3(cfg3, flags):
     assert synthgen.padding_bits_clear(got, D)
 
 
-@pytest.mark.parametrize("flags", [0, sr.SR_BOOL_BITWISE, sr.SR_BOOL_MFMA])
-def test_bool_product_config3(cfg3, flags):
+@pytest.mark.parametrize("flags,fmt", [(0, None), (sr.SR_BOOL_BITWISE, None),
+                                       (sr.SR_BOOL_MFMA, "f4"), (sr.SR_BOOL_MFMA, "i8")])
+def test_bool_product_config3(cfg3, flags, fmt, monkeypatch):
     """Configuration 3's product A * A (D = 16384) on each path: every word
     against the oracle's bit-packed multiplication loop."""
+    if fmt:
+        monkeypatch.setenv("SR_MFMA_FORMAT", fmt)
     D, W, _ = cfg3
     A = sr.to_device(sr.SR_BOOL, W, cols=D)
     C = sr.empty(sr.SR_BOOL, D, D)

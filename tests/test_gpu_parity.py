@@ -296,7 +296,7 @@ def test_bool_closure(D):
     assert synthgen.padding_bits_clear(got, D)
 
 
-@pytest.mark.parametrize("path", [0, sr.SR_BOOL_BITWISE, sr.SR_BOOL_M4R])
+@pytest.mark.parametrize("path", [0, sr.SR_BOOL_BITWISE, sr.SR_BOOL_M4R, sr.SR_BOOL_MFMA])
 @pytest.mark.parametrize("D", [769, 2100, 4100])
 def test_bool_closure_lookahead_and_serial(D, path):
     """Sizes with several lookahead rounds and each word-chunk width (8 and
@@ -437,6 +437,28 @@ def test_closure_batched_arena(kind):
 # ---------------------------------------------------------------------------
 # Boolean product on the matrix cores (SR_BOOL_MFMA)
 # ---------------------------------------------------------------------------
+@pytest.fixture(params=["f4", "i8"])
+def mfma_format(request, monkeypatch):
+    """Operand format of the matrix-core path (4-bit floats or int8)."""
+    monkeypatch.setenv("SR_MFMA_FORMAT", request.param)
+    return request.param
+
+
+@pytest.mark.parametrize("R,K,N", [(1, 1, 1), (5, 3, 7), (64, 64, 64), (65, 130, 129),
+                                   (200, 37, 300), (257, 300, 513), (128, 1000, 256),
+                                   (300, 9, 1100), (4, 0, 70), (70, 2049, 33)])
+def test_bool_mul_mfma(mfma_format, R, K, N):
+    """The matrix-core path in each operand format against the oracle."""
+    test_bool_mul_paths(sr.SR_BOOL_MFMA, R, K, N)
+
+
+@pytest.mark.parametrize("D", [257, 300, 513, 769, 2100, 4100])
+def test_bool_closure_mfma(mfma_format, D):
+    """The Boolean closure with its bulk update on the matrix cores, each
+    operand format, overlapped and serial schedules, against the oracle."""
+    test_bool_closure_lookahead_and_serial(D, sr.SR_BOOL_MFMA)
+
+
 @pytest.mark.parametrize("path", [sr.SR_BOOL_MFMA, sr.SR_BOOL_M4R])
 @pytest.mark.parametrize("R,K,N", [(1, 1, 1), (5, 3, 7), (64, 64, 64), (65, 130, 129),
                                    (200, 37, 300), (257, 300, 513), (128, 1000, 256),
@@ -459,7 +481,7 @@ def test_bool_mul_paths(path, R, K, N):
 
 
 @pytest.mark.parametrize("path", [sr.SR_BOOL_MFMA, sr.SR_BOOL_M4R])
-def test_bool_mul_paths_accumulate_and_dense(path):
+def test_bool_mul_paths_accumulate_and_dense(path, mfma_format):
     """Accumulate mode, and dense inputs (counts up to K) equal to the
     bitwise path."""
     gen = synthgen.generator(6100)

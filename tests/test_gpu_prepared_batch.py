@@ -171,6 +171,57 @@ def test_prepared_batch_graph_replays(kind):
 
 
 @pytest.mark.parametrize("kind", [sr.SR_ANTIDIST_U16, sr.SR_ANTIDIST_U8])
+def test_prepared_batch_graph_survives_autotune(kind):
+    """A graph captured from a run with the 64 x 16 tiles, then the autotuner
+    (which re-plans the handle for its pick): replaying the old graph on fresh
+    contents still gives the oracle's closure, and so does a run with the new
+    plan."""
+    sizes = [int(n) for n, _, _, _ in synthgen.cfg_batch(count=70, nlo=8, nhi=800,
+                                                            seed=5500 + kind)]
+    sets = [_mats(kind, sizes, 5600 + 10 * kind + r) for r in range(3)]
+    srcs = []
+    for mats in sets:
+        a = sr.BatchArena(kind, sizes)
+        a.load(mats)
+        srcs.append(a)
+    work = sr.BatchArena(kind, sizes, zero=False)
+    work.copy_(srcs[0])
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        pb = sr.PreparedBatch(kind, work, tile=sr.SR_BATCH_TILE_64x16)
+        pb.run()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        pb.run()
+    torch.cuda.synchronize()
+    t = pb.autotune()
+    torch.cuda.synchronize()
+    assert t in TILES and pb.tile == t
+    check = [0, 3, 33, 69]
+    work.copy_(srcs[1])
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    for j in check:
+        assert np.array_equal(_host(work.view(j)), _want(kind, sets[1][j])), ("replay", j)
+    eager = sr.BatchArena(kind, sizes, zero=False)
+    eager.copy_(srcs[1])
+    sr.closure_batched(kind, eager)
+    torch.cuda.synchronize()
+    assert torch.equal(eager.buf, work.buf)
+    work.copy_(srcs[2])
+    pb.run()
+    torch.cuda.synchronize()
+    for j in check:
+        assert np.array_equal(_host(work.view(j)), _want(kind, sets[2][j])), ("new plan", j)
+    del g
+    pb.close()
+    sr.autotune_clear()
+
+
+@pytest.mark.parametrize("kind", [sr.SR_ANTIDIST_U16, sr.SR_ANTIDIST_U8])
 def test_prepared_batch_autotune(kind):
     """The autotuner picks one of the tile shapes, leaves the batch's
     matrices untouched, and the batch closes the same afterwards, as does

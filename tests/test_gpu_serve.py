@@ -104,3 +104,64 @@ def test_boolean_requests_are_batched():
         got = r.result.view(np.uint64)
         assert np.array_equal(got, solo(r)[:, :(r.n + 63) // 64]), (r.rid, r.n)
         assert np.array_equal(got, want(r)), r.rid
+
+
+def test_failed_request_fails_alone():
+    """Two requests marked to fail (their closure call is refused by the
+    library): one small enough to be batched with others of its kind, one
+    large.  Each fails alone with its error recorded; every other request,
+    including those batched with the bad one, equals the oracle."""
+    from paper_1705_08743_amd.serve import ClosureServer, Request
+    base = make_requests(30, 40, 900, seed=777, spacing=0.0)
+    small = min((r for r in base if r.n <= 256), key=lambda r: r.rid)
+    large = max(base, key=lambda r: r.n)
+    bad = {small.rid, large.rid}
+    reqs = [Request(r.rid, r.kind, r.n, r.host, 0.0, inject_fault=r.rid in bad) for r in base]
+    server = ClosureServer(budget_bytes=1 << 30, slots=4, batch_n=256)
+    stats = server.run(reqs, "served")
+    assert stats["failed"] == 2 and stats["requests"] == len(reqs) - 2
+    for r in reqs:
+        if r.rid in bad:
+            assert r.result is None and "SR_EINVAL" in r.error, r.rid
+            continue
+        assert r.error is None
+        got = r.result.view(np.uint64) if r.kind == sr.SR_BOOL else r.result
+        assert np.array_equal(got.astype(np.int64) if r.kind != sr.SR_BOOL else got, want(r)), r.rid
+    # the server keeps serving afterwards
+    again = [Request(r.rid, r.kind, r.n, r.host, 0.0) for r in base[:6]]
+    assert server.run(again, "served")["failed"] == 0
+
+
+def test_queued_request_can_be_cancelled():
+    """With a budget that admits one request at a time, a request withdrawn
+    while it is queued (its cancel_at passed; or cancel() called from another
+    thread, which the serving loop applies at its next pass) is never run;
+    the others complete and equal the oracle; a withdrawal time after a
+    request's completion changes nothing."""
+    import threading
+    from paper_1705_08743_amd.serve import ClosureServer, Request, footprint_bytes
+    base = make_requests(8, 500, 700, seed=1357, spacing=0.0)
+    budget = max(footprint_bytes(r.kind, r.n) for r in base)
+    reqs = [Request(r.rid, r.kind, r.n, r.host, 0.0,
+                    cancel_at=0.0 if r.rid == 3 else (100.0 if r.rid == 5 else None))
+            for r in base]
+    server = ClosureServer(budget_bytes=budget, slots=1, batch_n=0)
+    stats = server.run(reqs, "served")
+    assert stats["cancelled"] == 1 and reqs[3].cancelled and reqs[3].result is None
+    assert reqs[3].t_admit is None
+    for r in reqs:
+        if r.rid == 3:
+            continue
+        assert not r.cancelled
+        got = r.result.view(np.uint64) if r.kind == sr.SR_BOOL else r.result
+        assert np.array_equal(got.astype(np.int64) if r.kind != sr.SR_BOOL else got, want(r)), r.rid
+    # cancel() from another thread: the last request, queued behind the
+    # others for the only slot, is withdrawn when the loop sees the request
+    reqs2 = [Request(r.rid, r.kind, r.n, r.host, 0.0) for r in base]
+    t = threading.Timer(0.0, server.cancel, args=(reqs2[-1].rid,))
+    t.start()
+    t.join()
+    stats2 = server.run(reqs2, "served")
+    assert stats2["cancelled"] == 1 and reqs2[-1].cancelled and reqs2[-1].result is None
+    assert all(r.result is not None for r in reqs2[:-1])
+
