@@ -51,6 +51,8 @@ PEAK_BOOL = 32 * VALU_LANE_OPS
 # dense int8 matrix-core rate (MI355X datasheet: 5.0 POP/s = 2.5e15 MAC/s); one
 # MAC is one Boolean update on the SR_BOOL_MFMA path
 PEAK_I8_MAC = 2.5e15
+# dense fp4 matrix-core rate (MI355X datasheet: 10.1 PFLOP/s = 5.05e15 MAC/s)
+PEAK_F4_MAC = 5.05e15
 
 # HBM traffic of the update kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a streaming kernel of known size; valid only
@@ -352,6 +354,28 @@ def run_bool(args, torch, sr, synthgen):
         sr.SR_BOOL, t, D=D, flags=sr.SR_SERIAL_PHASES))
     up = phases["update"]
     achieved = up["updates_per_launch"] / (up["avg_us"] * 1e-6) if up["avg_us"] > 0 else 0.0
+    # configuration 3 compares the bulk update's paths: bit-sliced words,
+    # four-Russians tables, and the matrix cores (4-bit float and int8
+    # operands); the whole closure (overlapped) and its update launches
+    # (serialized phases) for each, every result equal to the default's
+    paths = {}
+    ref = bufs[-1].clone()
+    for name, flags, fmt in (("bitwise", sr.SR_BOOL_BITWISE, None), ("m4r", sr.SR_BOOL_M4R, None),
+                             ("mfma_f4", sr.SR_BOOL_MFMA, "f4"), ("mfma_i8", sr.SR_BOOL_MFMA, "i8")):
+        if fmt:
+            os.environ["SR_MFMA_FORMAT"] = fmt
+        for b in bufs:
+            b.copy_(src)
+        sr.closure(sr.SR_BOOL, warm, D=D, flags=flags)
+        t = timed(torch, lambda i: sr.closure(sr.SR_BOOL, bufs[i], D=D, flags=flags), args.steps)
+        same = bool(torch.equal(bufs[-1], ref))
+        ph = kernel_timing_pass(args, torch, sr, sr.SR_BOOL, src, bufs, lambda x: sr.closure(
+            sr.SR_BOOL, x, D=D, flags=flags | sr.SR_SERIAL_PHASES))
+        u = ph["update"]
+        rate = u["updates_per_launch"] / (u["avg_us"] * 1e-6) if u["avg_us"] > 0 else 0.0
+        paths[name] = {"closure_ms": t, "update_avg_us": u["avg_us"], "update_updates_per_s": rate,
+                       "equal_to_default": same}
+        os.environ.pop("SR_MFMA_FORMAT", None)
     out = {"metric": "semiring updates/s (D³/t) Boolean Warshall closure D=16384",
            "value": float(D) ** 3 / (ms * 1e-3), "unit": "updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -368,7 +392,7 @@ def run_bool(args, torch, sr, synthgen):
                         "achieved": achieved, "peak": PEAK_BOOL, "unit": "updates/s",
                         "frac": achieved / PEAK_BOOL, "traffic": traffic_of("bool16384"),
                         "note": "nominal D^3 bit updates; peak = one v_bitop3 per 32 updates"},
-           "phases": phases}
+           "phases": phases, "bulk_update_paths": paths}
     if not args.no_parity or not args.no_cpu_baseline:
         oracle.set_threads(args.cpu_threads)
         t0 = time.perf_counter()
@@ -502,9 +526,9 @@ def run_small(args, torch, sr, synthgen):
 
 def run_boolmul(args, torch, sr, synthgen):
     """Boolean product A * A of configuration 3 (D = 16384, bit-packed): the
-    default path (value; the four-Russians tables at this size), with the
-    bit-sliced kernels (SR_BOOL_BITWISE) and the int8 matrix-core path
-    (SR_BOOL_MFMA) reported beside it; sampled rows against the oracle."""
+    default path (value), with the bit-sliced, four-Russians and matrix-core
+    (4-bit float and int8 operands) paths reported beside it; every path's
+    product equal, the default's against the oracle's whole product."""
     import numpy as np
     import oracle
     D = 16384
@@ -513,16 +537,26 @@ def run_boolmul(args, torch, sr, synthgen):
     C1 = sr.empty(sr.SR_BOOL, D, D)
     C2 = sr.empty(sr.SR_BOOL, D, D)
     C3 = sr.empty(sr.SR_BOOL, D, D)
+    C4 = sr.empty(sr.SR_BOOL, D, D)
     fb = lambda i: sr.semiring_mul(sr.SR_BOOL, C1, A, A, K=D, N=D)
     fm = lambda i: sr.semiring_mul(sr.SR_BOOL, C2, A, A, K=D, N=D, flags=sr.SR_BOOL_MFMA)
     fw = lambda i: sr.semiring_mul(sr.SR_BOOL, C3, A, A, K=D, N=D, flags=sr.SR_BOOL_BITWISE)
+    fr = lambda i: sr.semiring_mul(sr.SR_BOOL, C4, A, A, K=D, N=D, flags=sr.SR_BOOL_M4R)
     for _ in range(max(1, args.warmup)):
         fb(0)
         fm(0)
         fw(0)
+        fr(0)
     tb = timed(torch, fb, args.steps)
-    tm = timed(torch, fm, max(1, args.steps // 2))
+    tm = timed(torch, fm, args.steps)
     tw = timed(torch, fw, args.steps)
+    tr = timed(torch, fr, args.steps)
+    os.environ["SR_MFMA_FORMAT"] = "i8"
+    C5 = sr.empty(sr.SR_BOOL, D, D)
+    fi = lambda i: sr.semiring_mul(sr.SR_BOOL, C5, A, A, K=D, N=D, flags=sr.SR_BOOL_MFMA)
+    fi(0)
+    ti = timed(torch, fi, args.steps)
+    os.environ.pop("SR_MFMA_FORMAT", None)
     out = {"metric": "semiring updates/s (R*K*N/t) Boolean product 16384^3",
            "value": float(D) ** 3 / (tb * 1e-3), "unit": "updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": tb,
@@ -532,11 +566,20 @@ def run_boolmul(args, torch, sr, synthgen):
            "nominal_updates_vs_bitwise_roofline": float(D) ** 3 / (tb * 1e-3) / PEAK_BOOL,
            "bitwise_path": {"ms_per_step": tw, "value": float(D) ** 3 / (tw * 1e-3),
                             "fraction_of_bitwise_roofline": float(D) ** 3 / (tw * 1e-3) / PEAK_BOOL},
+           "m4r_path": {"ms_per_step": tr, "value": float(D) ** 3 / (tr * 1e-3)},
+           # the matrix-core path: one MAC per nominal update; 4-bit float
+           # operands (MI355X dense fp4: 10.1 PFLOP/s = 5.05e15 MAC/s) and
+           # int8 ones (5.0 POP/s = 2.5e15 MAC/s)
            "mfma_path": {"ms_per_step": tm, "value": float(D) ** 3 / (tm * 1e-3),
-                         "fraction_of_int8_mfma_peak": float(D) ** 3 / (tm * 1e-3) / PEAK_I8_MAC,
-                         "speedup_vs_default": tb / tm}}
+                         "operands": "fp4 e2m1",
+                         "fraction_of_fp4_mfma_peak": float(D) ** 3 / (tm * 1e-3) / PEAK_F4_MAC,
+                         "speedup_vs_default": tb / tm},
+           "mfma_int8_path": {"ms_per_step": ti, "value": float(D) ** 3 / (ti * 1e-3),
+                              "fraction_of_int8_mfma_peak": float(D) ** 3 / (ti * 1e-3) / PEAK_I8_MAC,
+                              "speedup_vs_default": tb / ti}}
     torch.cuda.synchronize()
-    out["paths_equal"] = bool(torch.equal(C1, C2) and torch.equal(C1, C3))
+    out["paths_equal"] = bool(torch.equal(C1, C2) and torch.equal(C1, C3) and torch.equal(C1, C4)
+                              and torch.equal(C1, C5))
     if not args.no_parity:
         oracle.set_threads(args.cpu_threads)
         want = oracle.bool_mul_words(W, W, D, D)

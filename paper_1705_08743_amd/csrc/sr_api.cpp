@@ -62,7 +62,10 @@ int base_kind(int kind) {
 // Default size range of the repeated-squaring closure, from the measured
 // crossover with the blocked loop on MI355X (uint16 / uint8: 2.4-4.6x faster
 // for 256 <= D <= 1024, slower at D = 128 and from 1536 on; uint32: 10-25 %
-// faster up to 768; Boolean: the blocked loop is faster at every size).
+// faster up to 768; Boolean: the blocked loop is faster at every size), and
+// with big pivot blocks (uint16 / uint8, configuration-2 graphs: squaring
+// 159 / 131 us at D = 640, big blocks 226 / 233; at 768 207 / 188 against
+// 183 / 179, at 1024 321 / 290 against 217 / 209).
 constexpr int64_t kSquaringMinD = 192;
 // Big-block closure (pivot blocks of kBigBlock closed by squaring) above the
 // squaring range, up to these sizes (measured against the 128-pivot loop with
@@ -73,7 +76,7 @@ constexpr int64_t kSquaringMinD = 192;
 constexpr int64_t kBigBlock = 512;
 constexpr int64_t kBigBlockMaxD16 = 2560;
 constexpr int64_t kBigBlockMaxD32 = 0;
-constexpr int64_t kSquaringMaxD16 = 1024;
+constexpr int64_t kSquaringMaxD16 = 704;
 constexpr int64_t kSquaringMaxD32 = 768;
 
 // bytes per storage unit of the leading dimension
@@ -752,14 +755,17 @@ std::vector<sr::BatchDesc> batch_descs(int kind, void *const *T, const int64_t *
         const int64_t g = order[(size_t)i];
         sr::BatchDesc &d = h[(size_t)i];
         d.D = (int32_t)D[g];
-        d.pad = 0;
+        d.flags = 0;
         d.T32 = nullptr;
         if (s8) {
             d.T8 = static_cast<uint8_t *>(T[g]);
             d.ld8 = ldt[g] * unit_bytes(kind);
             d.ld = round_up(D[g], 8);
             d.T = nullptr;
-            *work_elems += (size_t)(D[g] * d.ld);
+            if (kind == SR_BOOL && D[g] <= sr::kBoolBatchSmall)
+                d.flags = sr::kDescBits;  // closed on its bits: no working copy
+            else
+                *work_elems += (size_t)(D[g] * d.ld);
         } else if (base_kind(kind) == SR_ANTIDIST_U32) {
             d.T8 = nullptr;
             d.ld8 = 0;
@@ -782,6 +788,7 @@ void place_working_copies(std::vector<sr::BatchDesc> &h, void *arena) {
     uint16_t *a = static_cast<uint16_t *>(arena);
     size_t off = 0;
     for (sr::BatchDesc &d : h) {
+        if (d.flags & sr::kDescBits) continue;
         d.T = a + off;
         off += (size_t)d.D * (size_t)d.ld;
     }

@@ -33,7 +33,7 @@ __device__ __forceinline__ BatchDesc cdesc(const BatchDesc *desc, int g) {
     d.T8 = p->T8;
     d.ld8 = p->ld8;
     d.D = p->D;
-    d.pad = 0;
+    d.flags = p->flags;
     d.T32 = p->T32;
     return d;
 }

@@ -16,8 +16,10 @@
 // Every launch has thousands of workgroups (not one per graph), which keeps
 // the large graphs from finishing alone on a few compute units; the update
 // and panels launches hand their workgroups to the XCDs in chunks (below).
-// uint8 and Boolean batches are converted into 16-bit working copies
-// (binary16 values) before the rounds and back after them.  The launch
+// uint8 batches, and Boolean graphs of more than kBoolBatchSmall vertices,
+// are converted into 16-bit working copies (binary16 values) before the
+// rounds and back after them; smaller Boolean graphs are closed on their bit
+// rows by one workgroup each (k_batch_bool_small).  The launch
 // sequence holds no allocation, copy or host callback once the plan is in
 // device memory, so it can be captured into a graph.
 #include <hip/hip_runtime.h>
@@ -186,7 +188,7 @@ __global__ void __launch_bounds__(256) k_batch_narrow(const BatchDesc *desc, int
 __global__ void __launch_bounds__(256) k_batch_unpack(const BatchDesc *desc) {
     const BatchDesc d = desc[blockIdx.x];
     const int64_t r0 = (int64_t)blockIdx.y * kConvRows;
-    if (r0 >= d.D) return;
+    if (r0 >= d.D || (d.flags & kDescBits)) return;
     const int64_t nr = min<int64_t>(kConvRows, (int64_t)d.D - r0);
     const int64_t gpr = ((int64_t)d.D + 7) >> 3;
     const uint32_t one = dev::u8_to_work(255);
@@ -211,7 +213,7 @@ __global__ void __launch_bounds__(256) k_batch_unpack(const BatchDesc *desc) {
 __global__ void __launch_bounds__(256) k_batch_pack(const BatchDesc *desc) {
     const BatchDesc d = desc[blockIdx.x];
     const int64_t r0 = (int64_t)blockIdx.y * kConvRows;
-    if (r0 >= d.D) return;
+    if (r0 >= d.D || (d.flags & kDescBits)) return;
     const int64_t nr = min<int64_t>(kConvRows, (int64_t)d.D - r0);
     const int64_t gpr = ((int64_t)d.D + 7) >> 3;
     for (int64_t g = threadIdx.x; g < nr * gpr; g += 256) {
@@ -244,12 +246,81 @@ __global__ void __launch_bounds__(256) k_batch_not(const BatchDesc *desc) {
 // Diagonal of every graph := value, on the uint8 (T8) or uint16 (T) matrices.
 __global__ void __launch_bounds__(256) k_batch_diag(const BatchDesc *desc, int u8, uint32_t value) {
     const BatchDesc d = desc[blockIdx.x];
+    if (d.flags & kDescBits) return;  // set by the in-place Boolean kernel
     for (int64_t i = threadIdx.x; i < d.D; i += 256) {
         if (u8)
             d.T8[i * d.ld8 + i] = (uint8_t)value;
         else
             d.T[i * d.ld + i] = (uint16_t)value;
     }
+}
+
+// Boolean graphs of at most 32 NW vertices, closed on their bit rows (Sec. II,
+// Warshall's loop on bit-packed rows): one workgroup of 32 NW threads per
+// graph, thread t holding row t in NW registers.  Step k ORs row k into every
+// row with bit k set; row k is read from LDS, where its owner publishes it
+// right after its own update in step k - 1 (two alternating buffers, one
+// barrier per step: a buffer is rewritten only after every thread has passed
+// the barrier that ends the step reading it).  Rows past D, and the waves
+// that hold only such rows, take no part; bits past column D - 1 are zero on
+// input and stay so.  reflexive: the diagonal bits are set afterwards.
+template <int NW>
+__global__ void __launch_bounds__(32 * NW)
+k_batch_bool_small(const BatchDesc *desc, const Item *items, int reflexive) {
+    __shared__ uint32_t prow[2][NW];
+    const BatchDesc d = cdesc(desc, citems(items)[blockIdx.x].graph);
+    const int n = d.D;
+    const int t = threadIdx.x;
+    const bool live_wave = (t & ~63) < n;  // uniform over the wave
+    uint32_t *row = reinterpret_cast<uint32_t *>(d.T8 + (int64_t)min(t, n - 1) * d.ld8);
+    const int nw = (n + 31) >> 5;  // words holding columns < n
+    uint32_t r[NW];
+#pragma unroll
+    for (int w = 0; w < NW; w++) r[w] = (t < n && w < nw) ? row[w] : 0u;
+    if (t == 0) {
+#pragma unroll
+        for (int w = 0; w < NW; w++) prow[0][w] = r[w];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kw = 0; kw < NW; kw++) {
+        if (32 * kw >= n) break;
+        const int kn = min(32, n - 32 * kw);
+        for (int b = 0; b < kn; b++) {
+            const int k = 32 * kw + b;
+            if (live_wave) {
+                const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(r[kw], b, 1);
+                const uint32_t *pk = prow[k & 1];
+#pragma unroll
+                for (int w = 0; w < NW; w++) r[w] = __builtin_amdgcn_bitop3_b32(pk[w], m, r[w], 0xEA);
+            }
+            if (t == k + 1) {
+#pragma unroll
+                for (int w = 0; w < NW; w++) prow[(k + 1) & 1][w] = r[w];
+            }
+            __syncthreads();
+        }
+    }
+    if (t >= n) return;
+    if (reflexive) {
+#pragma unroll
+        for (int w = 0; w < NW; w++)
+            if (w == (t >> 5)) r[w] |= 1u << (t & 31);
+    }
+#pragma unroll
+    for (int w = 0; w < NW; w++)
+        if (w < nw) row[w] = r[w];
+}
+
+// Size classes of the small Boolean graphs: words per row (and 32 x that
+// threads per workgroup).
+constexpr int kBoolSmallNW[6] = {2, 4, 8, 16, 24, 32};
+constexpr int kBoolSmallClasses = 6;
+
+int bool_small_class(int D) {
+    int c = 0;
+    while (c + 1 < kBoolSmallClasses && 32 * kBoolSmallNW[c] < D) c++;
+    return c;
 }
 
 // Host plan: per round, the three item lists (offsets into one array).
@@ -259,9 +330,10 @@ using Launch = BatchLaunch;
 
 struct BatchPlan {
     int tile;   // update-tile code (1, 2, 3)
-    int max_d;  // largest graph
+    int max_d;  // largest graph closed in rounds (in working copies or in place)
     std::vector<Item> items;
     std::vector<Launch> pivot, panels, update;  // per round
+    Launch small[kBoolSmallClasses];  // Boolean graphs closed on their bits, per class
 };
 
 namespace {
@@ -273,15 +345,28 @@ bool build_plan(BatchPlan &p, const BatchDesc *hd, int64_t count) {
     const int cw = 2 * kTileNW[p.tile];
     int max_rounds = 0;
     p.max_d = 0;
+    // a graph's rounds: none for the Boolean graphs closed on their bits
+    auto rounds = [&](int64_t g) { return (hd[g].flags & kDescBits) ? 0 : rounds_of(hd[g].D); };
     for (int64_t g = 0; g < count; g++) {
-        max_rounds = std::max(max_rounds, rounds_of(hd[g].D));
-        p.max_d = std::max(p.max_d, hd[g].D);
+        max_rounds = std::max(max_rounds, rounds(g));
+        if (!(hd[g].flags & kDescBits)) p.max_d = std::max(p.max_d, hd[g].D);
+    }
+    for (int c = 0; c < kBoolSmallClasses; c++) {
+        Launch ls{(int64_t)p.items.size(), 0, 0, 0};
+        for (int64_t g = 0; g < count; g++) {
+            if (!(hd[g].flags & kDescBits) || hd[g].D <= 0 || bool_small_class(hd[g].D) != c)
+                continue;
+            p.items.push_back(Item{(int32_t)g, ls.n_wg++});
+        }
+        ls.n_items = ls.n_wg;
+        p.items.push_back(Item{-1, ls.n_wg});
+        p.small[c] = ls;
     }
     for (int kb = 0; kb < max_rounds; kb++) {
         // pivot: every graph with a round kb
         Launch lp{(int64_t)p.items.size(), 0, 0, 0};
         for (int64_t g = 0; g < count; g++) {
-            if (hd[g].D <= 0 || rounds_of(hd[g].D) <= kb) continue;
+            if (hd[g].D <= 0 || rounds(g) <= kb) continue;
             if (lp.n_wg >= kMaxUnits) return false;
             p.items.push_back(Item{(int32_t)g, lp.n_wg++});
         }
@@ -292,7 +377,7 @@ bool build_plan(BatchPlan &p, const BatchDesc *hd, int64_t count) {
         Launch la{(int64_t)p.items.size(), 0, 0, 0};
         for (int64_t g = 0; g < count; g++) {
             const int D = hd[g].D;
-            if (rounds_of(D) <= std::max(kb, 1)) continue;
+            if (rounds(g) <= std::max(kb, 1)) continue;
             const int k0 = kb * kAdBlock, bs = std::min(kAdBlock, D - k0);
             int r = 0, c = 0;
             dev::panel_wgs(D, k0, bs, &r, &c);
@@ -307,7 +392,7 @@ bool build_plan(BatchPlan &p, const BatchDesc *hd, int64_t count) {
         Launch lu{(int64_t)p.items.size(), 0, 0, 0};
         for (int64_t g = 0; g < count; g++) {
             const int D = hd[g].D;
-            if (rounds_of(D) <= std::max(kb, 1)) continue;
+            if (rounds(g) <= std::max(kb, 1)) continue;
             int nc = 0, nr = 0;
             (void)update_rect(D, kb, 64, cw, &nc, &nr);
             const int64_t waves = (int64_t)nc * nr;
@@ -384,9 +469,26 @@ hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, in
                                                        desc_bytes_of(count));
     const unsigned ng = (unsigned)count;
     const dim3 conv(ng, (unsigned)std::max<int64_t>(1, ((int64_t)p.max_d + kConvRows - 1) / kConvRows));
-    if (bits)
+    if (bits) {
+        // graphs of at most kBoolBatchSmall vertices: on their bit rows, one
+        // launch per size class
+        for (int c = 0; c < kBoolSmallClasses; c++) {
+            const Launch &l = p.small[c];
+            if (l.n_wg <= 0) continue;
+            const Item *it = items + l.offset;
+            const int rf = reflexive ? 1 : 0;
+            switch (kBoolSmallNW[c]) {
+                case 2: hipLaunchKernelGGL(k_batch_bool_small<2>, dim3(l.n_wg), dim3(64), 0, st, desc, it, rf); break;
+                case 4: hipLaunchKernelGGL(k_batch_bool_small<4>, dim3(l.n_wg), dim3(128), 0, st, desc, it, rf); break;
+                case 8: hipLaunchKernelGGL(k_batch_bool_small<8>, dim3(l.n_wg), dim3(256), 0, st, desc, it, rf); break;
+                case 16: hipLaunchKernelGGL(k_batch_bool_small<16>, dim3(l.n_wg), dim3(512), 0, st, desc, it, rf); break;
+                case 24: hipLaunchKernelGGL(k_batch_bool_small<24>, dim3(l.n_wg), dim3(768), 0, st, desc, it, rf); break;
+                default: hipLaunchKernelGGL(k_batch_bool_small<32>, dim3(l.n_wg), dim3(1024), 0, st, desc, it, rf); break;
+            }
+        }
+        if (p.pivot.empty()) return hipGetLastError();  // no graph above kBoolBatchSmall
         hipLaunchKernelGGL(k_batch_unpack, conv, dim3(256), 0, st, desc);
-    else if (s8)
+    } else if (s8)
         hipLaunchKernelGGL(k_batch_widen, conv, dim3(256), 0, st, desc, dual ? 1 : 0);
     else if (dual)
         hipLaunchKernelGGL(k_batch_not, conv, dim3(256), 0, st, desc);

@@ -259,11 +259,11 @@ __device__ __forceinline__ uint32_t transpose_bits(uint32_t o, uint32_t x) {
 }
 
 // Bit transpose: BT[j][w] bit t = B[32 w + t][j] for j < n_rows_bt, w <
-// 8 * gridDim.y words; zero where 32 w + t >= K or column j of B is past its
-// nwb words.  A wave takes 64 columns (two words of B: lane half h reads
-// word 2 c + h of 32 rows) and 8 words of BT; each ballot over the 32 rows of
-// one bit position is one word of BT, sent to the lane of its column with
-// v_writelane, so a lane ends with 8 consecutive words of its BT row.
+// gridDim.y words; zero where 32 w + t >= K or column j of B is past its nwb
+// words.  A wave takes 64 columns (two words of B: lane half h reads word
+// 2 c + h of 32 rows) and one word of BT: each ballot over the 32 rows of one
+// bit position is that word for one column, sent to the lane of its column
+// with v_writelane.
 __global__ void __launch_bounds__(256)
 k_bit_transpose(uint32_t *BT, int64_t ldbt, const uint32_t *B, int64_t ldb, int64_t K,
                 int64_t nwb, int64_t n_rows_bt) {
@@ -273,17 +273,10 @@ k_bit_transpose(uint32_t *BT, int64_t ldbt, const uint32_t *B, int64_t ldb, int6
     if (64 * c >= n_rows_bt) return;
     const int h = lane >> 5, t = lane & 31;
     const int64_t jw = 2 * c + h;
-    const int64_t wb0 = (int64_t)blockIdx.y * 8;
-    uint32_t out[8];
-#pragma unroll
-    for (int kw = 0; kw < 8; kw++) {
-        const int64_t k = 32 * (wb0 + kw) + t;
-        const uint32_t x = (k < K && jw < nwb) ? B[k * ldb + jw] : 0u;
-        out[kw] = transpose_bits<0>(0u, x);
-    }
-    uint4 *dst = reinterpret_cast<uint4 *>(BT + (64 * c + lane) * ldbt + wb0);
-    dst[0] = uint4{out[0], out[1], out[2], out[3]};
-    dst[1] = uint4{out[4], out[5], out[6], out[7]};
+    const int64_t wb = blockIdx.y;  // the word of BT (32 rows of B) this wave forms
+    const int64_t k = 32 * wb + t;
+    const uint32_t x = (k < K && jw < nwb) ? B[k * ldb + jw] : 0u;
+    BT[(64 * c + lane) * ldbt + wb] = transpose_bits<0>(0u, x);
 }
 
 // Closure update on the matrix cores: T_ij (|)= T_iK * T_Kj over a BRect
@@ -335,7 +328,7 @@ constexpr int kMulBJ = 2;
 
 hipError_t transpose(uint32_t *BT, int64_t ldbt, int64_t n_rows_bt, int ngroups, const uint32_t *B,
                      int64_t ldb, int64_t K, int64_t nwb, hipStream_t st) {
-    const dim3 grid((unsigned)((n_rows_bt / 64 + 3) / 4), (unsigned)ngroups);
+    const dim3 grid((unsigned)((n_rows_bt / 64 + 3) / 4), (unsigned)(8 * ngroups));
     hipLaunchKernelGGL(k_bit_transpose, grid, dim3(256), 0, st, BT, ldbt, B, ldb, K, nwb,
                        n_rows_bt);
     return hipGetLastError();

@@ -158,9 +158,14 @@ struct BatchDesc {
                     // back); Boolean data: the caller's bit rows
     int64_t ld8;    // row stride of T8, bytes (a multiple of 16)
     int32_t D;      // vertices
-    int32_t pad;
+    int32_t flags;  // kDescBits: a Boolean graph closed on its bit rows (T unused)
     uint32_t *T32;  // 32-bit kinds: the caller's matrix (ld in 32-bit elements)
 };
+// Boolean batches: graphs of at most kBoolBatchSmall vertices are closed on
+// their bit rows, one workgroup per graph, with no working copy (flag
+// kDescBits); larger ones in the {0, 255} binary16 working copies.
+constexpr int kBoolBatchSmall = 1024;
+constexpr int32_t kDescBits = 1;
 // One entry of a launch's work list: a graph and its first workgroup (or,
 // for the update, first wave tile); a sentinel entry holds the launch's total.
 struct BatchItem {

@@ -46,15 +46,13 @@ _UNIT = {SR_BOOL: 8, SR_ANTIDIST_U8: 1, SR_ANTIDIST_U16: 2}
 
 def footprint_bytes(kind, n, batch_n=256):
     """Device bytes a request holds while admitted: its padded matrix, plus
-    the library's working memory for its closure -- what closure() allocates
-    for this kind and size (the library's own query, which follows its
-    method rules and autotuning table) or, for a request small enough to be
-    closed in a batch, the batch's 16-bit working copy if that is larger."""
-    b = n * padded_ld(n, kind) * _UNIT[kind]
-    work = closure_work_bytes(kind, n)
-    if n <= batch_n and kind in (SR_BOOL, SR_ANTIDIST_U8):
-        work = max(work, n * (-(-n // 8) * 8) * 2)
-    return b + work
+    the library's working memory for its closure, as the library's own query
+    reports it (it follows closure()'s method rules and autotuning table).  A
+    request closed in a batch needs no more: a uint8 batch's 16-bit working
+    copy is smaller than closure()'s, and Boolean graphs of at most batch_n
+    (<= 1024) vertices are closed on their bits."""
+    del batch_n
+    return n * padded_ld(n, kind) * _UNIT[kind] + closure_work_bytes(kind, n)
 
 
 class Request:

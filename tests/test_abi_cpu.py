@@ -288,16 +288,18 @@ def test_closure_work_bytes(L):
     assert f(U16, 0, 0) == 0
     assert f(U16, 8192, 0) == 0
     assert f(sr.SR_BOOL, 16384, 0) == 0
-    assert f(U16, 1000, 0) == 2 * 1000 * 1024 * 2 + 256                  # squaring
+    assert f(U16, 600, 0) == 2 * 600 * 640 * 2 + 256                     # squaring
     assert f(U16, 2000, 0) == 2 * 512 * 512 * 2 + 256                    # big blocks
     assert f(U8, 8192, 0) == 8192 * 8192 * 2                             # binary16 copy
-    assert f(U8, 1000, 0) == 1000 * 1024 * 2 + 2 * 1000 * 1024 * 2 + 256
+    assert f(U8, 600, 0) == 600 * 640 * 2 + 2 * 600 * 640 * 2 + 256
+    assert f(U8, 1000, 0) == 1000 * 1024 * 2 + 2 * 512 * 512 * 2 + 256
     assert f(sr.SR_ANTIDIST_U32, 700, 0) == 2 * 700 * 704 * 4 + 256
-    assert f(U16, 1000, sr.SR_CLOSURE_WARSHALL) == 0
-    assert f(U16, 1000, sr.SR_SERIAL_PHASES) == 0
+    assert f(U16, 600, sr.SR_CLOSURE_WARSHALL) == 0
+    assert f(U16, 600, sr.SR_SERIAL_PHASES) == 0
+    assert f(U16, 1000, sr.SR_CLOSURE_SQUARING) == 2 * 1000 * 1024 * 2 + 256
     assert f(sr.SR_BOOL, 16384, sr.SR_BOOL_MFMA) > 0
     assert f(U16, -1, 0) == sr.SR_EINVAL
     assert f(9, 10, 0) == sr.SR_EINVAL
     assert f(U16, 10, sr.SR_BOOL_MFMA) == sr.SR_EINVAL
-    assert sr.closure_work_bytes(U16, 1000) == 2 * 1000 * 1024 * 2 + 256
+    assert sr.closure_work_bytes(U16, 600) == 2 * 600 * 640 * 2 + 256
 
