@@ -405,11 +405,19 @@ def run_bool(args, torch, sr, synthgen):
                              "bit_exact": bool(np.array_equal(got[:, :nw], want[:, :nw])
                                                and synthgen.padding_bits_clear(got, D))}
         if not args.no_cpu_baseline:
+            # one thread: the same whole loop (about 16x the all-threads time)
+            oracle.set_threads(1)
+            t1 = time.perf_counter()
+            oracle.bool_closure_words(W, D)
+            dt1 = time.perf_counter() - t1
+            oracle.set_threads(args.cpu_threads)
             out["cpu_baseline"] = {
                 "value": float(D) ** 3 / dt, "unit": "updates/s", "cores": args.cpu_threads,
                 "kind": "oracle",
                 "sample": "the whole bit-packed Warshall loop on the same input (%.1f s)" % dt,
-                "cpu": host_cpu()}
+                "cpu": host_cpu(),
+                "one_thread": {"value": float(D) ** 3 / dt1, "unit": "updates/s",
+                               "sample": "the same whole loop on 1 thread (%.1f s)" % dt1}}
     return out
 
 
@@ -514,7 +522,7 @@ def run_small(args, torch, sr, synthgen):
         out["cpu_baseline"] = {"value": 1e6 * cpu["u16_1024_closure"]["ms_%d_threads" % args.cpu_threads]
                                / 1e3, "unit": "us", "cores": args.cpu_threads, "kind": "oracle",
                                "sample": "the same four calls, whole (per-call ms in 'calls')",
-                               "calls": cpu}
+                               "calls": cpu, "cpu": host_cpu()}
     if not args.no_parity:
         ok = np.array_equal(sr.to_host(dWc)[:, :4], oracle.bool_closure_words(W, 256)[:, :4])
         ok &= np.array_equal(sr.to_host(dP)[:, :4], oracle.bool_mul_words(W, W, 256, 256)[:, :4])
@@ -818,11 +826,23 @@ def run_batched(args, torch, sr, synthgen):
             out["parity"] = {"graphs_compared": len(mats), "graphs_differing": bad,
                              "bit_exact": bad == 0, "graph_replay_equals_closure_batched": same}
         if not args.no_cpu_baseline:
+            # one thread on every 16th graph (a bounded sample of the batch)
+            oracle.set_threads(1)
+            sample = mats[::16]
+            t1 = time.perf_counter()
+            for m in sample:
+                oracle.ad_closure(m, 65535)
+            dt1 = time.perf_counter() - t1
+            oracle.set_threads(args.cpu_threads)
+            upd1 = float(sum(float(m.shape[0]) ** 3 for m in sample))
             out["cpu_baseline"] = {"value": upd / dt, "unit": "updates/s",
                                    "cores": args.cpu_threads, "kind": "oracle",
                                    "sample": "the whole batch, one oracle closure per graph "
                                              "(%.3g updates, %.1f s)" % (upd, dt),
-                                   "seconds": dt, "cpu": host_cpu()}
+                                   "seconds": dt, "cpu": host_cpu(),
+                                   "one_thread": {"value": upd1 / dt1, "unit": "updates/s",
+                                                  "sample": "every 16th graph on 1 thread "
+                                                            "(%.3g updates, %.1f s)" % (upd1, dt1)}}
     del g
     pb.close()
     # the same 4096 topologies and distances as uint8 (binary16 working form)

@@ -314,8 +314,9 @@ void sr_batch_destroy(sr_batch *batch);
  * Autotuning (not part of the paper's method: it chooses between exact
  * methods that give identical results).  sr_autotune_closure times each
  * closure method that applies to (kind, D) -- the blocked loop (for Boolean:
- * with the bit-sliced and with the four-Russians update), big pivot blocks,
- * repeated squaring -- on a directed path through all D vertices (the
+ * with the bit-sliced, the four-Russians and the matrix-core update), big
+ * pivot blocks of 256, 512, 768 and 1024 vertices, repeated squaring -- on a
+ * directed path through all D vertices (the
  * squaring's worst case: it stops early once a squaring changes nothing,
  * while the other methods' runtimes do not depend on the entries; Boolean:
  * a zero matrix), once to warm up and twice more, keeps the
@@ -327,11 +328,27 @@ void sr_batch_destroy(sr_batch *batch);
  * SR_EUNSUPPORTED.  Both allocate, synchronize `stream` and return
  * SR_EUNSUPPORTED while it is being captured; D in [1, 32768], R, K, N in
  * [1, 65536] (SR_EINVAL otherwise).  sr_autotune_clear forgets every choice.
- * The table is per process and thread-safe.
+ * The table is thread-safe and kept per process unless saved (below).
  */
 int sr_autotune_closure(int kind, int64_t D, unsigned *chosen, void *stream);
 int sr_autotune_mul(int kind, int64_t R, int64_t K, int64_t N, unsigned *chosen, void *stream);
 void sr_autotune_clear(void);
+
+/*
+ * sr_autotune_save / sr_autotune_load -- the autotuning table as a JSON file
+ * (one entry per line; keys: the device architecture name, the operation, the
+ * kind and the size classes), so that tuning survives the process: save
+ * writes every entry (atomically, through a temporary file), load merges a
+ * saved file into the table (entries of other architectures are kept but
+ * never match).  SR_EINVAL when the file cannot be written or read.  With the
+ * environment variable SR_AUTOTUNE_FILE set, the library loads that file
+ * when it first consults the table and rewrites it after every autotuning
+ * call.  A tuned big-block closure also keeps its pivot block size (256 to
+ * 1024 vertices, measured by sr_autotune_closure) in the table; *chosen
+ * carries the method flags only.
+ */
+int sr_autotune_save(const char *path);
+int sr_autotune_load(const char *path);
 
 /*
  * Phase timing (a tracing aid, not part of the paper's method).  While

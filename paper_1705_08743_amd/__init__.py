@@ -84,7 +84,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsemiring
 EXPORTS = ("semiring_mul", "semiring_add", "semiring_ewise", "closure", "closure_work_bytes",
            "closure_noalloc",
            "closure_batched",
-           "sr_autotune_closure", "sr_autotune_mul", "sr_autotune_clear",
+           "sr_autotune_closure", "sr_autotune_mul", "sr_autotune_clear", "sr_autotune_save",
+           "sr_autotune_load",
            "sr_batch_create", "sr_batch_run", "sr_batch_autotune", "sr_batch_tile",
            "sr_batch_destroy",
            "sr_profile_enable", "sr_profile_read", "sr_last_error", "sr_version", "sr_shutdown")
@@ -134,6 +135,10 @@ def lib():
         L.sr_autotune_mul.argtypes = [i32, i64, i64, i64, ctypes.POINTER(u32), vp]
         L.sr_autotune_mul.restype = i32
         L.sr_autotune_clear.restype = None
+        L.sr_autotune_save.argtypes = [ctypes.c_char_p]
+        L.sr_autotune_save.restype = i32
+        L.sr_autotune_load.argtypes = [ctypes.c_char_p]
+        L.sr_autotune_load.restype = i32
         L.sr_batch_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                       ctypes.POINTER(i64), i64, u32, i32,
                                       ctypes.POINTER(vp), vp]
@@ -437,6 +442,16 @@ def autotune_mul(kind, R, K, N, stream=None):
     out = ctypes.c_uint(0)
     _check(lib().sr_autotune_mul(kind, R, K, N, ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def autotune_save(path):
+    """Write the autotuning table to `path` (JSON)."""
+    _check(lib().sr_autotune_save(os.fsencode(path)))
+
+
+def autotune_load(path):
+    """Merge the autotuning table saved at `path`."""
+    _check(lib().sr_autotune_load(os.fsencode(path)))
 
 
 def autotune_clear():

@@ -494,7 +494,7 @@ namespace {
 // Working memory of a closure by method m: the binary16 copy of uint8 data,
 // then the two matrices of squaring (of the whole matrix, or of one big
 // block), or the transposed pivot rows of the Boolean matrix-core update.
-size_t closure_need(int kind, int64_t D, unsigned m, unsigned bool_path) {
+size_t closure_need(int kind, int64_t D, unsigned m, unsigned bool_path, int64_t block) {
     const int ak = base_kind(kind);
     const bool s8 = ak == SR_ANTIDIST_U8;
     const size_t tw = s8 ? (size_t)(D * round_up(D, 64)) * 2 : 0;
@@ -502,8 +502,19 @@ size_t closure_need(int kind, int64_t D, unsigned m, unsigned bool_path) {
         return ak == SR_BOOL && (bool_path & SR_BOOL_MFMA) ? sr::bool_mfma_closure_work_bytes(D)
                                                            : tw;
     const int wes = s8 ? 2 : (int)unit_bytes(kind);
-    const int64_t b = m == SR_CLOSURE_BIG_BLOCKS ? std::min<int64_t>(big_block_size(), D) : D;
+    const int64_t b = m == SR_CLOSURE_BIG_BLOCKS ? std::min<int64_t>(block, D) : D;
     return tw + squaring_work_bytes(wes, b);
+}
+
+// An autotuned closure choice holds the method flags and, for big pivot
+// blocks, the block size in units of 64 vertices in bits 16..23 (0: the
+// default size).
+constexpr unsigned kTunedBlockShift = 16;
+constexpr unsigned kTunedMethodMask = 0xFFFFu;
+unsigned tuned_block_code(int64_t block) { return (unsigned)(block / 64) << kTunedBlockShift; }
+int64_t tuned_block(unsigned choice) {
+    const int64_t b = (int64_t)((choice >> kTunedBlockShift) & 0xFFu) * 64;
+    return b > 0 ? b : big_block_size();
 }
 
 // Kind, size and flags of a closure call (the matrix is checked apart).
@@ -532,6 +543,7 @@ int check_closure_args(int kind, int64_t D, unsigned flags, const char *fn) {
 
 struct ClosurePlan {
     unsigned method, bool_path;
+    int64_t block;  // pivot block of the big-block method
     size_t copy_bytes, work_bytes;
 };
 
@@ -542,14 +554,17 @@ struct ClosurePlan {
 // the blocked loop otherwise; loop_only (a capture without caller-supplied
 // working memory) turns a default squaring or big-block choice into the loop.
 // Flags are valid (checked by the caller).
-ClosurePlan plan_closure(int kind, int64_t D, unsigned flags, bool loop_only) {
+ClosurePlan plan_closure(int kind, int64_t D, unsigned flags, bool loop_only,
+                         int64_t block = 0) {
     const int ak = base_kind(kind);
     unsigned method = flags & (SR_CLOSURE_SQUARING | SR_CLOSURE_WARSHALL | SR_CLOSURE_BIG_BLOCKS);
     unsigned bool_path = flags & (SR_BOOL_BITWISE | SR_BOOL_M4R | SR_BOOL_MFMA);
+    int64_t big = block > 0 ? block : big_block_size();
     if (!method && (flags & SR_SERIAL_PHASES)) method = SR_CLOSURE_WARSHALL;
     if (!method) {
         const unsigned t = sr::tuned_get(sr::kTuneClosure, kind, D, 0, 0);
         if (t) {
+            if (block <= 0) big = tuned_block(t);
             method = t & (SR_CLOSURE_SQUARING | SR_CLOSURE_WARSHALL | SR_CLOSURE_BIG_BLOCKS);
             if (!bool_path) bool_path = t & (SR_BOOL_BITWISE | SR_BOOL_M4R | SR_BOOL_MFMA);
         } else if (D >= kSquaringMinD && D <= squaring_max_d(ak)) {
@@ -564,8 +579,9 @@ ClosurePlan plan_closure(int kind, int64_t D, unsigned flags, bool loop_only) {
     ClosurePlan p;
     p.method = method;
     p.bool_path = bool_path;
+    p.block = big;
     p.copy_bytes = ak == SR_ANTIDIST_U8 ? (size_t)(D * round_up(D, 64)) * 2 : 0;
-    p.work_bytes = closure_need(kind, D, method, bool_path);
+    p.work_bytes = closure_need(kind, D, method, bool_path, big);
     return p;
 }
 
@@ -574,7 +590,7 @@ ClosurePlan plan_closure(int kind, int64_t D, unsigned flags, bool loop_only) {
 namespace sr {
 
 int closure_run(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream,
-                int (*fixed_work)(void **), size_t fixed_bytes, const char *fn) {
+                int (*fixed_work)(void **), size_t fixed_bytes, const char *fn, int64_t block) {
     const bool fixed = fixed_work != nullptr;
     int rc = check_closure_args(kind, D, flags, fn);
     if (rc != SR_OK) return rc;
@@ -590,7 +606,7 @@ int closure_run(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void 
     // The method, the Boolean bulk-update path and the working memory.  A
     // stream being captured takes the loop unless the caller supplied the
     // working memory.
-    ClosurePlan pl = plan_closure(kind, D, flags, !fixed && capturing(st));
+    ClosurePlan pl = plan_closure(kind, D, flags, !fixed && capturing(st), block);
     unsigned method = pl.method;
     const unsigned bool_path = pl.bool_path;
     const bool s8 = ak == SR_ANTIDIST_U8;
@@ -605,7 +621,7 @@ int closure_run(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void 
         // falls back to the loop, which needs only the uint8 working copy
         if (need > fixed_bytes && !methods && method != SR_CLOSURE_WARSHALL) {
             method = SR_CLOSURE_WARSHALL;
-            need = closure_need(kind, D, method, bool_path);
+            need = closure_need(kind, D, method, bool_path, pl.block);
         }
         if (need > fixed_bytes)
             return fail(SR_EINVAL,
@@ -618,7 +634,7 @@ int closure_run(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void 
     }
     const bool big = method == SR_CLOSURE_BIG_BLOCKS;
     const bool squared = method != SR_CLOSURE_WARSHALL;
-    const int64_t B = big ? std::min<int64_t>(big_block_size(), D) : D;
+    const int64_t B = big ? std::min<int64_t>(pl.block, D) : D;
     const bool aux_create = !fixed;
     // distance closure (dransclose) by De Morgan: not closure(not T)
     if (is_dist(kind)) e = sr::launch_ewise(es, sr::EW_NOT, T, ldt, T, ldt, T, ldt, D, D, 0, st);
@@ -920,7 +936,11 @@ int sr_autotune_closure(int kind, int64_t D, unsigned *chosen, void *stream) {
                  SR_CLOSURE_WARSHALL | SR_BOOL_MFMA};
     } else {
         cands = {SR_CLOSURE_WARSHALL};
-        if (D > 512 && D <= 16384) cands.push_back(SR_CLOSURE_BIG_BLOCKS);
+        // big pivot blocks of 256 to 1024 vertices (the tuned choice carries
+        // the block size)
+        if (D <= 16384)
+            for (int64_t B : {256, 512, 768, 1024})
+                if (B < D) cands.push_back(SR_CLOSURE_BIG_BLOCKS | tuned_block_code(B));
     }
     if (D >= 2 && D <= 4096) cands.push_back(SR_CLOSURE_SQUARING);
     EventPair ev;
@@ -940,8 +960,10 @@ int sr_autotune_closure(int kind, int64_t D, unsigned *chosen, void *stream) {
         return e;
     };
     for (unsigned c : cands) {
-        const float ms = time_candidate(st, ev.a, ev.b, 2, path,
-                                        [&] { return closure(kind, T, ld, D, c, stream); });
+        const float ms = time_candidate(st, ev.a, ev.b, 2, path, [&] {
+            return sr::closure_run(kind, T, ld, D, c & kTunedMethodMask, stream, nullptr, 0,
+                                   "sr_autotune_closure", tuned_block(c));
+        });
         if (ms >= 0.0f && (!pick || ms < best)) {
             pick = c;
             best = ms;
@@ -951,7 +973,7 @@ int sr_autotune_closure(int kind, int64_t D, unsigned *chosen, void *stream) {
     (void)hipStreamSynchronize(st);
     if (!pick) return fail(SR_EDEVICE, "sr_autotune_closure: no candidate ran");
     sr::tuned_set(sr::kTuneClosure, kind, D, 0, 0, pick);
-    if (chosen) *chosen = pick;
+    if (chosen) *chosen = pick & kTunedMethodMask;
     return ok();
 }
 
@@ -991,6 +1013,20 @@ int sr_autotune_mul(int kind, int64_t R, int64_t K, int64_t N, unsigned *chosen,
 }
 
 void sr_autotune_clear(void) { sr::tuned_clear(); }
+
+int sr_autotune_save(const char *path) {
+    if (!path) return fail(SR_EINVAL, "sr_autotune_save: NULL path");
+    if (sr::tuned_save(path) != 0)
+        return fail(SR_EINVAL, "sr_autotune_save: could not write %s", path);
+    return ok();
+}
+
+int sr_autotune_load(const char *path) {
+    if (!path) return fail(SR_EINVAL, "sr_autotune_load: NULL path");
+    const int n = sr::tuned_load(path);
+    if (n < 0) return fail(SR_EINVAL, "sr_autotune_load: could not read %s", path);
+    return ok();
+}
 
 }  // extern "C"
 

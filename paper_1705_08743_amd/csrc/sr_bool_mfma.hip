@@ -259,11 +259,13 @@ __device__ __forceinline__ uint32_t transpose_bits(uint32_t o, uint32_t x) {
 }
 
 // Bit transpose: BT[j][w] bit t = B[32 w + t][j] for j < n_rows_bt, w <
-// gridDim.y words; zero where 32 w + t >= K or column j of B is past its nwb
-// words.  A wave takes 64 columns (two words of B: lane half h reads word
-// 2 c + h of 32 rows) and one word of BT: each ballot over the 32 rows of one
-// bit position is that word for one column, sent to the lane of its column
-// with v_writelane.
+// KW * gridDim.y words; zero where 32 w + t >= K or column j of B is past its
+// nwb words.  A wave takes 64 columns (two words of B: lane half h reads word
+// 2 c + h of 32 rows) and KW consecutive words of BT: each ballot over the 32
+// rows of one bit position is one word for one column, sent to the lane of
+// its column with v_writelane.  KW = 1 spreads a small transpose over more
+// waves; KW = 4 stores 16 bytes per lane for a large one.
+template <int KW>
 __global__ void __launch_bounds__(256)
 k_bit_transpose(uint32_t *BT, int64_t ldbt, const uint32_t *B, int64_t ldb, int64_t K,
                 int64_t nwb, int64_t n_rows_bt) {
@@ -273,10 +275,20 @@ k_bit_transpose(uint32_t *BT, int64_t ldbt, const uint32_t *B, int64_t ldb, int6
     if (64 * c >= n_rows_bt) return;
     const int h = lane >> 5, t = lane & 31;
     const int64_t jw = 2 * c + h;
-    const int64_t wb = blockIdx.y;  // the word of BT (32 rows of B) this wave forms
-    const int64_t k = 32 * wb + t;
-    const uint32_t x = (k < K && jw < nwb) ? B[k * ldb + jw] : 0u;
-    BT[(64 * c + lane) * ldbt + wb] = transpose_bits<0>(0u, x);
+    const int64_t wb0 = (int64_t)blockIdx.y * KW;
+    uint32_t out[KW];
+#pragma unroll
+    for (int kw = 0; kw < KW; kw++) {
+        const int64_t k = 32 * (wb0 + kw) + t;
+        const uint32_t x = (k < K && jw < nwb) ? B[k * ldb + jw] : 0u;
+        out[kw] = transpose_bits<0>(0u, x);
+    }
+    uint32_t *dst = BT + (64 * c + lane) * ldbt + wb0;
+    if constexpr (KW == 4)
+        *reinterpret_cast<uint4 *>(dst) = uint4{out[0], out[1], out[2], out[3]};
+    else
+#pragma unroll
+        for (int kw = 0; kw < KW; kw++) dst[kw] = out[kw];
 }
 
 // Closure update on the matrix cores: T_ij (|)= T_iK * T_Kj over a BRect
@@ -326,11 +338,18 @@ int mfma_format() {
 
 constexpr int kMulBJ = 2;
 
+// BT := the bit transpose of K x (32 nwb) B into n_rows_bt rows of 8 ngroups
+// words; one word per wave while the grid is small (a round's pivot rows),
+// four for large ones (a product's B).
 hipError_t transpose(uint32_t *BT, int64_t ldbt, int64_t n_rows_bt, int ngroups, const uint32_t *B,
                      int64_t ldb, int64_t K, int64_t nwb, hipStream_t st) {
-    const dim3 grid((unsigned)((n_rows_bt / 64 + 3) / 4), (unsigned)(8 * ngroups));
-    hipLaunchKernelGGL(k_bit_transpose, grid, dim3(256), 0, st, BT, ldbt, B, ldb, K, nwb,
-                       n_rows_bt);
+    const unsigned gx = (unsigned)((n_rows_bt / 64 + 3) / 4);
+    if ((int64_t)gx * ngroups * 8 <= 4096)
+        hipLaunchKernelGGL(k_bit_transpose<1>, dim3(gx, (unsigned)(8 * ngroups)), dim3(256), 0, st,
+                           BT, ldbt, B, ldb, K, nwb, n_rows_bt);
+    else
+        hipLaunchKernelGGL(k_bit_transpose<4>, dim3(gx, (unsigned)(2 * ngroups)), dim3(256), 0, st,
+                           BT, ldbt, B, ldb, K, nwb, n_rows_bt);
     return hipGetLastError();
 }
 

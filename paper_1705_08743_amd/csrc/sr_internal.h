@@ -142,8 +142,10 @@ hipError_t launch_fill32(uint32_t *p, int64_t n, uint32_t value, hipStream_t str
 // no stream or event is created.  fn names the entry point in error
 // messages.  Returns an SR_* code and sets the thread's error message
 // (sr_api.cpp).
+// block: the pivot block of the big-block method (0: the tuned or default
+// size).
 int closure_run(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, void *stream,
-                int (*work)(void **), size_t work_bytes, const char *fn);
+                int (*work)(void **), size_t work_bytes, const char *fn, int64_t block = 0);
 // Sets the thread's error message (printf format) and returns code.
 int report(int code, const char *fmt, ...);
 
@@ -248,6 +250,13 @@ int size_class(int64_t n);
 unsigned tuned_get(int op, int kind, int64_t a, int64_t b, int64_t c);
 void tuned_set(int op, int kind, int64_t a, int64_t b, int64_t c, unsigned choice);
 void tuned_clear();
+// The table as JSON text (every device architecture's entries): tuned_save
+// returns 0 on success; tuned_load merges a file written by tuned_save and
+// returns the number of entries read, or -1 when the file cannot be read.
+// With SR_AUTOTUNE_FILE set, the table is loaded from that file on its first
+// use and written back after every tuned_set.
+int tuned_save(const char *path);
+int tuned_load(const char *path);
 
 // Phase timing (sr_runtime.cpp).  kind: 0 Boolean, 1 anti-distance;
 // phase: 0 pivot, 1 panels, 2 update.  units: semiring updates of the launch.

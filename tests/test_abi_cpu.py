@@ -303,3 +303,53 @@ def test_closure_work_bytes(L):
     assert f(U16, 10, sr.SR_BOOL_MFMA) == sr.SR_EINVAL
     assert sr.closure_work_bytes(U16, 600) == 2 * 600 * 640 * 2 + 256
 
+
+
+def test_autotune_table_save_load(L, tmp_path):
+    """The autotuning table round-trips through its JSON file, and a loaded
+    entry steers closure()'s method and big-block size (seen through the
+    working-memory query; without a device the architecture name is empty)."""
+    U16 = sr.SR_ANTIDIST_U16
+    sr.autotune_clear()
+    src = tmp_path / "tune.json"
+    choice_big768 = sr.SR_CLOSURE_BIG_BLOCKS | ((768 // 64) << 16)
+    src.write_text('{"format": "libsemiring-autotune-1", "entries": [\n'
+                   '{"arch": "", "op": 1, "kind": %d, "class": [10, 0, 0], "choice": %d},\n'
+                   '{"arch": "gfx950", "op": 1, "kind": %d, "class": [9, 0, 0], "choice": %d}\n'
+                   ']}\n' % (U16, choice_big768, U16, sr.SR_CLOSURE_WARSHALL))
+    try:
+        sr.autotune_load(str(src))
+        # size class 10 = (512, 1024]: big blocks of 768 vertices
+        assert sr.closure_work_bytes(U16, 1000) == 2 * 768 * 768 * 2 + 256
+        # the gfx950 entry does not match this (device-less) process
+        assert sr.closure_work_bytes(U16, 600) == 2 * 600 * 640 * 2 + 256
+        out = tmp_path / "saved.json"
+        sr.autotune_save(str(out))
+        text = out.read_text()
+        assert text.startswith('{"format": "libsemiring-autotune-1"')
+        assert '"choice": %d' % choice_big768 in text and '"arch": "gfx950"' in text
+        sr.autotune_clear()
+        assert sr.closure_work_bytes(U16, 1000) == 2 * 512 * 512 * 2 + 256
+        sr.autotune_load(str(out))
+        assert sr.closure_work_bytes(U16, 1000) == 2 * 768 * 768 * 2 + 256
+        with pytest.raises(sr.SemiringError):
+            sr.autotune_load(str(tmp_path / "missing.json"))
+    finally:
+        sr.autotune_clear()
+
+
+def test_autotune_file_environment(tmp_path):
+    """With SR_AUTOTUNE_FILE set, a fresh process loads that table the first
+    time the library consults it."""
+    import sys
+    U16 = sr.SR_ANTIDIST_U16
+    f = tmp_path / "env_tune.json"
+    f.write_text('{"format": "libsemiring-autotune-1", "entries": [\n'
+                 '{"arch": "", "op": 1, "kind": %d, "class": [10, 0, 0], "choice": %d}\n]}\n'
+                 % (U16, sr.SR_CLOSURE_BIG_BLOCKS | ((256 // 64) << 16)))
+    code = ("import paper_1705_08743_amd as sr; "
+            "print(sr.closure_work_bytes(sr.SR_ANTIDIST_U16, 1000))")
+    env = dict(os.environ, SR_AUTOTUNE_FILE=str(f), HIP_VISIBLE_DEVICES="")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, check=True,
+                         stdout=subprocess.PIPE, text=True).stdout.strip()
+    assert int(out.splitlines()[-1]) == 2 * 256 * 256 * 2 + 256

@@ -28,7 +28,8 @@ def _setup():
 
 CLOSURE_METHODS = {sr.SR_CLOSURE_WARSHALL, sr.SR_CLOSURE_SQUARING, sr.SR_CLOSURE_BIG_BLOCKS,
                    sr.SR_CLOSURE_WARSHALL | sr.SR_BOOL_BITWISE,
-                   sr.SR_CLOSURE_WARSHALL | sr.SR_BOOL_M4R}
+                   sr.SR_CLOSURE_WARSHALL | sr.SR_BOOL_M4R,
+                   sr.SR_CLOSURE_WARSHALL | sr.SR_BOOL_MFMA}
 
 
 @pytest.mark.parametrize("kind,D", [(sr.SR_ANTIDIST_U16, 700), (sr.SR_ANTIDIST_U8, 1500),
@@ -38,7 +39,7 @@ def test_autotune_closure_then_default_equals_oracle(kind, D):
     chosen = sr.autotune_closure(kind, D)
     assert chosen in CLOSURE_METHODS
     if kind != sr.SR_BOOL:
-        assert not chosen & (sr.SR_BOOL_BITWISE | sr.SR_BOOL_M4R)
+        assert not chosen & (sr.SR_BOOL_BITWISE | sr.SR_BOOL_M4R | sr.SR_BOOL_MFMA)
     gen = synthgen.generator(9970 + kind + D)
     if kind == sr.SR_BOOL:
         A = rand_bits(D, D, gen, 2.0 / D)
@@ -80,3 +81,27 @@ def test_autotune_bool_mul_then_default_equals_oracle():
     with pytest.raises(sr.SemiringError) as e:
         sr.autotune_mul(sr.SR_ANTIDIST_U16, 8, 8, 8)
     assert e.value.code == sr.SR_EUNSUPPORTED
+
+
+def test_autotune_table_persists(tmp_path):
+    """A tuned closure choice (method and, for big blocks, the pivot block)
+    survives a save, a clear and a load: the working-memory query and the
+    default closure follow it again, and the closure equals the oracle."""
+    kind, D = sr.SR_ANTIDIST_U16, 1500
+    sr.autotune_clear()
+    chosen = sr.autotune_closure(kind, D)
+    tuned_bytes = sr.closure_work_bytes(kind, D)
+    f = tmp_path / "tune.json"
+    sr.autotune_save(str(f))
+    sr.autotune_clear()
+    sr.autotune_load(str(f))
+    assert sr.closure_work_bytes(kind, D) == tuned_bytes
+    assert '"arch": "gfx950"' in f.read_text()
+    gen = synthgen.generator(9990)
+    A = rand_antidist(D, D, kind, gen, p=2.0 / D, wmax=S_OF[kind] // 6)
+    T = sr.to_device(kind, A)
+    sr.closure(kind, T)
+    torch.cuda.synchronize()
+    assert np.array_equal(sr.to_host(T).astype(np.int64), oracle.ad_closure(A, S_OF[kind])), chosen
+    sr.autotune_clear()
+
