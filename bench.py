@@ -64,9 +64,9 @@ TRAFFIC = {
     "fw8192": {"src_hash": "96ded9e9c24175ed", "bytes_per_launch": 4.967e8},   # 1.791e5 + 1.270e5 KiB
     "u8fw8192": {"src_hash": "96ded9e9c24175ed", "bytes_per_launch": 4.845e8},  # 1.731e5 + 1.270e5 KiB
     "u32fw8192": {"src_hash": "c4166400949ed0ba", "bytes_per_launch": 7.185e8},  # 2.219e5 + 2.579e5 KiB
-    # full update launches (four-Russians kernel, 32 x 32 tiles of 512 x 512
-    # bits) of the serialized D = 16384 Boolean closure
-    "bool16384": {"src_hash": "f5d4c58a5b788425", "bytes_per_launch": 1.226e8},  # 4.400e4 + 3.178e4 KiB
+    # full update launches (matrix-core kernel, 4-bit operands) of the
+    # serialized D = 16384 Boolean closure
+    "bool16384": {"src_hash": None, "bytes_per_launch": None},
 }
 
 
@@ -75,13 +75,13 @@ def src_hash(workload):
     anti-distance the tile code (sr_tiles.h but the pivot tile's closure) and
     the text of the k_ad_fw_update kernel template (host-side changes
     elsewhere in sr_antidist.hip do not change the kernel); for Boolean
-    sr_bool.hip; for
+    sr_bool_mfma.hip (the matrix-core update); for
     the uint32 path the update kernel's text and the device code before the
     product kernel in sr_antidist32.hip."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1705_08743_amd/csrc")
     if workload.startswith("bool"):
-        with open(os.path.join(csrc, "sr_bool.hip"), "rb") as f:
+        with open(os.path.join(csrc, "sr_bool_mfma.hip"), "rb") as f:
             h.update(f.read())
         return h.hexdigest()[:16]
     if workload.startswith("u32"):
@@ -384,14 +384,17 @@ def run_bool(args, torch, sr, synthgen):
            "config": {"workload": "bool_warshall_D16384", "D": D, "mean_out_degree": 3,
                       "planted_scc_blocks": "8 x 512", "pivot_block": 256,
                       "parallelism": "single_gpu"},
-           # at this size the update phase runs the four-Russians tables, which
-           # do one table read per row and 8 inner bits instead of 8 masked
-           # ORs: the rate counts nominal bit updates against the bit-sliced
-           # peak, so it can pass what an OR per 32 updates could reach
-           "roofline": {"bound": "alu", "kernel": "k_bool_fw_update_m4r (update phase)",
-                        "achieved": achieved, "peak": PEAK_BOOL, "unit": "updates/s",
-                        "frac": achieved / PEAK_BOOL, "traffic": traffic_of("bool16384"),
-                        "note": "nominal D^3 bit updates; peak = one v_bitop3 per 32 updates"},
+           # at this size the update phase runs on the matrix cores with 4-bit
+           # float operands (one MAC per nominal bit update); with K = 256
+           # inner bits per round a tile's threshold and packing cost more
+           # than its MFMAs, so the fraction of the fp4 peak is low although
+           # the kernel beats the word kernels (bulk_update_paths)
+           "roofline": {"bound": "mfma", "kernel": "k_bool_fw_update_mfma (update phase, fp4)",
+                        "achieved": achieved, "peak": PEAK_F4_MAC, "unit": "MAC/s",
+                        "frac": achieved / PEAK_F4_MAC, "traffic": traffic_of("bool16384"),
+                        "fraction_of_bitwise_peak": achieved / PEAK_BOOL,
+                        "note": "nominal D^3 bit updates = MACs; fp4 dense peak 5.05e15 MAC/s; "
+                                "bitwise peak one v_bitop3 per 32 updates"},
            "phases": phases, "bulk_update_paths": paths}
     if not args.no_parity or not args.no_cpu_baseline:
         oracle.set_threads(args.cpu_threads)

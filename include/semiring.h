@@ -106,7 +106,7 @@ enum {
 enum {
     SR_ACCUMULATE = 1u,    /* semiring_mul: C := C (+) A*B instead of C := A*B */
     SR_REFLEXIVE = 2u,     /* closure, closure_batched: return I (+) T (eq. rtc) */
-    SR_BOOL_BITWISE = 4u,  /* Boolean: force the word OR-AND kernels (the default) */
+    SR_BOOL_BITWISE = 4u,  /* Boolean: force the word OR-AND kernels */
     SR_BOOL_MFMA = 8u,     /* Boolean semiring_mul, and closure's bulk update: the matrix
                               cores (counts of common bits, thresholded; exact); any other
                               kind: SR_EINVAL */
@@ -130,6 +130,8 @@ enum {
  * product is out of place, and the in-place form with all three operands the
  * same matrix is the closure below.
  * Boolean padding bits of A (columns >= K) and B (columns >= N) must be zero.
+ * Boolean without a path flag: the autotuned path for the size class, else
+ * SR_BOOL_MFMA when R, K and N are all at least 512, else the word kernels.
  * Boolean with SR_BOOL_MFMA: the same product computed as a product of
  * {0, 1} matrices on the matrix cores -- counts of common set bits, > 0
  * exactly when some A_ik = B_kj = 1 -- with 4-bit float operands (or int8
@@ -175,7 +177,8 @@ int semiring_ewise(int kind, int op, void *C, int64_t ldc, const void *A, int64_
  * squaring; not Boolean) -- else the autotuned method for D's size class or
  * the built-in size rules; for Boolean matrices at most one of
  * SR_BOOL_BITWISE, SR_BOOL_M4R, SR_BOOL_MFMA (the kernels of the loop's bulk
- * update).  Every method gives the same matrix.
+ * update; by default the matrix cores from 2048 vertices on, the word kernels
+ * below).  Every method gives the same matrix.
  * Working memory: the loop on 16-bit, 32-bit and Boolean matrices allocates
  * nothing; uint8 data, squaring, big blocks and SR_BOOL_MFMA take
  * stream-ordered working memory (closure_work_bytes() gives the amount), and

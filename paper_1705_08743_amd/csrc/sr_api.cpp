@@ -67,6 +67,13 @@ int base_kind(int kind) {
 // 159 / 131 us at D = 640, big blocks 226 / 233; at 768 207 / 188 against
 // 183 / 179, at 1024 321 / 290 against 217 / 209).
 constexpr int64_t kSquaringMinD = 192;
+// Boolean defaults for the matrix cores: products with every dimension at
+// least kBoolMfmaMinDim, and the closure's bulk update from kBoolMfmaClosureD
+// vertices on (configuration-3-like graphs: D = 2048 0.41 vs 0.43 ms, 8192
+// 1.68 vs 1.83, 16384 4.49 vs 4.85 ms against the word kernels' best; equal
+// at 1024).
+constexpr int64_t kBoolMfmaMinDim = 512;
+constexpr int64_t kBoolMfmaClosureD = 2048;
 // Big-block closure (pivot blocks of kBigBlock closed by squaring) above the
 // squaring range, up to these sizes (measured against the 128-pivot loop with
 // its K-split panels and lookahead and paired pivot steps: uint16 D = 1536
@@ -263,9 +270,15 @@ int semiring_mul(int kind, void *C, int64_t ldc, const void *A, int64_t lda, con
     const bool acc = (flags & SR_ACCUMULATE) != 0;
     hipStream_t st = as_stream(stream);
     // Boolean without a forced path: the autotuned choice for this size
-    // class, if any (else the kernels' own size rule)
+    // class, if any; else the matrix cores from 512 on in every dimension
+    // (measured with 4-bit operands against the word kernels: 512^3 34 vs
+    // 36 us, 4096^3 53 vs 197 us, 16384^3 1.92 vs 2.04 ms; 256^3 43 vs
+    // 24 us); else the word kernels' own size rule
     unsigned path = paths;
     if (kind == SR_BOOL && !path) path = sr::tuned_get(sr::kTuneMul, kind, R, K, N);
+    if (kind == SR_BOOL && !path && R >= kBoolMfmaMinDim && K >= kBoolMfmaMinDim &&
+        N >= kBoolMfmaMinDim)
+        path = SR_BOOL_MFMA;
     if (!is_dist(kind)) return mul_compute(kind, C, ldc, A, lda, B, ldb, R, K, N, acc, path, st);
     // distance product (min, saturating +) by De Morgan:
     // A + B = not((not A) (x) (not B)), with C complemented around it
@@ -576,6 +589,12 @@ ClosurePlan plan_closure(int kind, int64_t D, unsigned flags, bool loop_only,
         }
         if (method != SR_CLOSURE_WARSHALL && loop_only) method = SR_CLOSURE_WARSHALL;
     }
+    // the Boolean loop's bulk update: the matrix cores by default for large
+    // matrices, unless the stream is being captured without caller-supplied
+    // working memory (their transposed pivot rows need some)
+    if (ak == SR_BOOL && !bool_path && method == SR_CLOSURE_WARSHALL && D >= kBoolMfmaClosureD &&
+        !loop_only)
+        bool_path = SR_BOOL_MFMA;
     ClosurePlan p;
     p.method = method;
     p.bool_path = bool_path;
