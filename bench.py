@@ -66,7 +66,7 @@ TRAFFIC = {
     "u32fw8192": {"src_hash": "c4166400949ed0ba", "bytes_per_launch": 7.185e8},  # 2.219e5 + 2.579e5 KiB
     # full update launches (matrix-core kernel, 4-bit operands) of the
     # serialized D = 16384 Boolean closure
-    "bool16384": {"src_hash": None, "bytes_per_launch": None},
+    "bool16384": {"src_hash": "5545d8c72a06d2b6", "bytes_per_launch": 7.014e7},  # 1.836e4 + 3.178e4 KiB
 }
 
 
