@@ -95,15 +95,12 @@ k_ad_mul(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_
 // >= 0, so the max of their 16-bit patterns is their max also in the
 // binary16 form.
 template <int NW, int KS, bool S8>
-__global__ void __launch_bounds__(64 * KS)
-k_ad_mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
-                int64_t ldb, int64_t R, int K, int kq, int accumulate, const int *gate,
-                const uint16_t *prev, int *flag) {
-    __shared__ uint4 part[KS][64][NW / 4];
-    if (gate && *gate == 0) return;  // (uniform over the workgroup: before any barrier)
+__device__ __forceinline__ void ksplit_tile(uint4 (*part)[64][NW / 4], uint16_t *C, int64_t ldc,
+                                            const uint16_t *A, int64_t lda, const uint16_t *B,
+                                            int64_t ldb, int64_t R, int K, int kq, int accumulate,
+                                            const uint16_t *prev, int *flag, int64_t row0,
+                                            int64_t col0) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
-    const int64_t row0 = (int64_t)blockIdx.y * 64;
-    const int64_t col0 = (int64_t)blockIdx.x * 2 * NW;
     const int nrows = (int)min<int64_t>(64, R - row0);
     const int k0 = min(K, wave * kq), k1 = min(K, k0 + kq);
     // this wave's partial product (rows >= nrows are not written)
@@ -130,6 +127,47 @@ k_ad_mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const 
                     reinterpret_cast<const uint32_t *>(prev + (row0 + row) * ldc + col0)[word];
     }
     if (prev && __any(diff) && (threadIdx.x & 63) == 0) *flag = 1;
+}
+
+template <int NW, int KS, bool S8>
+__global__ void __launch_bounds__(64 * KS)
+k_ad_mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
+                int64_t ldb, int64_t R, int K, int kq, int accumulate, const int *gate,
+                const uint16_t *prev, int *flag) {
+    __shared__ uint4 part[KS][64][NW / 4];
+    if (gate && *gate == 0) return;  // (uniform over the workgroup: before any barrier)
+    ksplit_tile<NW, KS, S8>(part, C, ldc, A, lda, B, ldb, R, K, kq, accumulate, prev, flag,
+                            (int64_t)blockIdx.y * 64, (int64_t)blockIdx.x * 2 * NW);
+}
+
+// Up to four independent products C_q (+)= A_q * B_q in one launch of the
+// K-split tiles above (the panels, or the blocks of a big-block round, which
+// are each too small to fill the chip): workgroups [end_{q-1}, end_q) take
+// the nx_q x ny_q tiles of product q, row-major.  No product's output may be
+// another's operand; a product's output may be its own operand where the
+// single-product kernel allows it.
+struct KsplitProblem {
+    uint16_t *C;
+    const uint16_t *A, *B;
+    int64_t ldc, lda, ldb, R;
+    int K, kq, nx, end;
+};
+struct KsplitGroup {
+    KsplitProblem p[4];
+    int n, accumulate;
+};
+
+template <int NW, int KS, bool S8>
+__global__ void __launch_bounds__(64 * KS) k_ad_mul_ksplit_group(KsplitGroup g) {
+    __shared__ uint4 part[KS][64][NW / 4];
+    const int b = blockIdx.x;
+    int q = 0;
+    while (q + 1 < g.n && b >= g.p[q].end) q++;
+    const KsplitProblem &p = g.p[q];
+    const int local = b - (q > 0 ? g.p[q - 1].end : 0);
+    ksplit_tile<NW, KS, S8>(part, p.C, p.ldc, p.A, p.lda, p.B, p.ldb, p.R, p.K, p.kq,
+                            g.accumulate, nullptr, nullptr, (int64_t)(local / p.nx) * 64,
+                            (int64_t)(local % p.nx) * 2 * NW);
 }
 
 template <bool S8>
@@ -319,14 +357,18 @@ hipError_t mul_shape(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, c
 
 // Products with at most 2048 output tiles of 64 x 16 (two waves per SIMD or
 // fewer) but a long inner dimension: 16-column tiles with the inner loop split
-// over eight waves (k_ad_mul_ksplit); a partial last column chunk goes to the
-// edge kernel.
-template <bool S8>
-hipError_t mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
-                      const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc,
-                      int64_t bmax, const int *gate, const uint16_t *prev, int *flag,
-                      hipStream_t st) {
-    constexpr int NW = 8, CW = 2 * NW, KS = 8;
+// over the KS waves of a workgroup (k_ad_mul_ksplit); a partial last column
+// chunk goes to the edge kernel.  These launches are latency-bound: with at
+// most 256 tiles (one workgroup per compute unit) sixteen waves split the
+// inner loop, which halves each wave's chain of scalar-load waits; with more
+// tiles eight (measured on 512 x 512 x 512 products and the big-block
+// closure of configuration 2: 175 against 184 us; 1024^3: 39 against 46 us).
+template <bool S8, int KS>
+hipError_t mul_ksplit_ks(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
+                         const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
+                         bool acc, int64_t bmax, const int *gate, const uint16_t *prev, int *flag,
+                         hipStream_t st) {
+    constexpr int NW = 8, CW = 2 * NW;
     const int64_t nfull = N / CW;
     const int kq = (int)((K + KS * 32 - 1) / (KS * 32) * 32);
     if (nfull > 0) {
@@ -348,6 +390,18 @@ hipError_t mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
 }
 
 template <bool S8>
+hipError_t mul_ksplit(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
+                      const uint16_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc,
+                      int64_t bmax, const int *gate, const uint16_t *prev, int *flag,
+                      hipStream_t st) {
+    const int64_t tiles = ((R + 63) / 64) * (N / 16);
+    if (tiles <= 256)
+        return mul_ksplit_ks<S8, 16>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, prev, flag,
+                                     st);
+    return mul_ksplit_ks<S8, 8>(C, ldc, A, lda, B, ldb, R, K, N, acc, bmax, gate, prev, flag, st);
+}
+
+template <bool S8>
 hipError_t mul_s(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const uint16_t *B,
                  int64_t ldb, int64_t R, int64_t K, int64_t N, bool acc, int64_t bmax,
                  const int *gate, const uint16_t *prev, int *flag, hipStream_t st) {
@@ -366,6 +420,64 @@ hipError_t mul_s(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda, const
         case 16: return run(ShapeT<1, 16>{});
         default: return run(ShapeT<1, 8>{});
     }
+}
+
+// Several products in one K-split launch when each has a long enough inner
+// dimension and together they have at most 2048 output tiles of 64 x 16
+// (the K-split rule of mul_s); otherwise one launch each.
+template <bool S8>
+hipError_t mul_group_s(const MulDesc *d, int n, bool acc, hipStream_t st) {
+    constexpr int NW = 8, CW = 2 * NW, KS = 8;
+    int64_t tiles = 0;
+    bool ok = n >= 2 && n <= 4;
+    for (int q = 0; q < n && ok; q++) {
+        ok = d[q].R > 0 && d[q].K >= 256 && d[q].N >= CW && d[q].K <= INT32_MAX;
+        tiles += ((d[q].R + 63) / 64) * (d[q].N / CW);
+    }
+    if (!ok || tiles > 2048) {
+        for (int q = 0; q < n; q++) {
+            if (d[q].R <= 0 || d[q].K <= 0 || d[q].N <= 0) continue;
+            hipError_t e = mul_s<S8>(d[q].C, d[q].ldc, d[q].A, d[q].lda, d[q].B, d[q].ldb, d[q].R,
+                                     d[q].K, d[q].N, acc, d[q].bspan >= 0 ? d[q].bspan : d[q].ldb,
+                                     nullptr, nullptr, nullptr, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    KsplitGroup g{};
+    g.n = n;
+    g.accumulate = acc ? 1 : 0;
+    int end = 0;
+    for (int q = 0; q < n; q++) {
+        KsplitProblem &p = g.p[q];
+        p.C = d[q].C;
+        p.A = d[q].A;
+        p.B = d[q].B;
+        p.ldc = d[q].ldc;
+        p.lda = d[q].lda;
+        p.ldb = d[q].ldb;
+        p.R = d[q].R;
+        p.K = (int)d[q].K;
+        p.kq = (int)((d[q].K + KS * 32 - 1) / (KS * 32) * 32);
+        p.nx = (int)(d[q].N / CW);
+        end += p.nx * (int)((d[q].R + 63) / 64);
+        p.end = end;
+    }
+    hipLaunchKernelGGL((k_ad_mul_ksplit_group<NW, KS, S8>), dim3((unsigned)end), dim3(64 * KS), 0,
+                       st, g);
+    hipError_t e = hipGetLastError();
+    // the partial last column chunks, as in mul_ksplit
+    for (int q = 0; q < n && e == hipSuccess; q++) {
+        if (d[q].N % CW == 0) continue;
+        const int64_t c0 = d[q].N / CW * CW;
+        hipLaunchKernelGGL((k_ad_mul<1, 8, S8, false>), dim3(1u, (unsigned)((d[q].R + 255) / 256)),
+                           dim3(256), 0, st, d[q].C, d[q].ldc, d[q].A, d[q].lda, d[q].B, d[q].ldb,
+                           d[q].R, (int)d[q].K, d[q].N, c0, acc ? 1 : 0,
+                           d[q].bspan >= 0 ? d[q].bspan : d[q].ldb, (const int *)nullptr,
+                           (const uint16_t *)nullptr, (int *)nullptr);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -691,6 +803,12 @@ hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, i
                             stream)
               : mul_s<false>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, prev, flag,
                              stream);
+}
+
+hipError_t launch_ad_mul_group(bool s8, const MulDesc *d, int n, bool accumulate,
+                               hipStream_t stream) {
+    return s8 ? mul_group_s<true>(d, n, accumulate, stream)
+              : mul_group_s<false>(d, n, accumulate, stream);
 }
 
 hipError_t launch_ad_closure(bool s8, uint16_t *T, int64_t ld, int64_t D, bool serial,

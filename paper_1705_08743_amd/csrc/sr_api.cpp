@@ -75,16 +75,19 @@ constexpr int64_t kSquaringMinD = 192;
 constexpr int64_t kBoolMfmaMinDim = 512;
 constexpr int64_t kBoolMfmaClosureD = 2048;
 // Big-block closure (pivot blocks of kBigBlock closed by squaring) above the
-// squaring range, up to these sizes (measured against the 128-pivot loop with
-// its K-split panels and lookahead and paired pivot steps: uint16 D = 1536
-// 0.59 vs 0.95 ms, 2048 0.99 vs 1.24, 3072 2.13 vs 1.99, 4096 4.26 vs 3.29;
-// 512 the best block of 256 / 512 / 768 / 1024; uint32 slower at every size,
-// so off).
+// squaring range, up to these sizes (configuration-2-like graphs, us, against
+// whole-matrix squaring and the 128-pivot loop: uint16 D = 768 149 / 185 /
+// 428, 1024 183 / 288 / 567, 1536 331 / 1135 / 853, 2048 644 / - / 1129,
+// 3072 1607 / - / 1766; uint8 alike; at 4096, where a round's products no
+// longer share a launch, the loop wins (3.3 vs 4.3 ms); 512 the best block
+// of 256 / 512 / 768 / 1024).  uint32 (no K-split product): squaring 776 / big 1007 / loop
+// 1385 at 1024, 1675 / 1788 / 2222 at 1536, big 2942 / loop 3021 at 2048, so
+// squaring up to 1536 and no big blocks.
 constexpr int64_t kBigBlock = 512;
-constexpr int64_t kBigBlockMaxD16 = 2560;
+constexpr int64_t kBigBlockMaxD16 = 3072;
 constexpr int64_t kBigBlockMaxD32 = 0;
 constexpr int64_t kSquaringMaxD16 = 704;
-constexpr int64_t kSquaringMaxD32 = 768;
+constexpr int64_t kSquaringMaxD32 = 1536;
 
 // bytes per storage unit of the leading dimension
 int64_t unit_bytes(int kind) {
@@ -348,9 +351,11 @@ int64_t big_block_max_d(int ak) {
 // Closure by repeated squaring (eq. trcl: T = A * (I (+) A)^m for every
 // m >= D - 1, because a best path never needs more than D - 1 edges before
 // its last one): P := I (+) A, then j squarings P := P * P with 2^j >= D - 1,
-// then T := A * P.  Exact like every other path of the library; the
-// products are the semiring_mul kernels.  For anti-distance entries the
-// squarings stop on the device once one leaves P unchanged (below).  es: 2
+// then T := A * P (for anti-distance entries without a product: P off the
+// diagonal, the best cycle through each vertex on it).  Exact like every
+// other path of the library; the products are the semiring_mul kernels.  For
+// anti-distance entries the squarings stop on the device once one leaves P
+// unchanged (below).  es: 2
 // (uint16, or the binary16 form of uint8 data when s8), 4 (uint32), 8
 // (Boolean words; ld in words).  work: squaring_work_bytes(es, D) bytes.
 hipError_t closure_by_squaring(int es, bool s8, void *T, int64_t ld, int64_t D, void *work,
@@ -359,27 +364,28 @@ hipError_t closure_by_squaring(int es, bool s8, void *T, int64_t ld, int64_t D, 
     const int64_t row_bytes = es == 8 ? (D + 63) / 64 * 8 : D * es;
     char *P = static_cast<char *>(work);
     char *Q = P + D * lw * es;
-    // Boolean rows must carry zero bits up to their padded end (the product
-    // kernels read whole words there): P takes T's rows up to lw <= ldt
-    // words, which are zero past D by the caller's contract, and Q starts
-    // zeroed (the products write only the words that hold columns < D)
-    hipError_t e = hipMemcpy2DAsync(P, lw * es, T, ld * es, es == 8 ? lw * 8 : row_bytes, D,
-                                    hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess && es == 8)
-        e = sr::launch_fill32(reinterpret_cast<uint32_t *>(Q), D * lw * 2, 0u, st);
-    // I (+) A: the diagonal becomes the multiplicative one (S, or bit set)
-    const uint32_t one = es == 4 ? 0xFFFFFFFFu : (es == 8 ? 1u : (s8 ? 0x5BF8u : 0xFFFFu));
-    if (e == hipSuccess) e = sr::launch_diag(es, P, lw, D, one, st);
-    // Boolean products (every squaring runs: the bit-sliced kernels take no gate)
-    auto mul = [&](void *C, const void *A, int64_t lda, const void *B) {
-        return sr::launch_bool_mul(static_cast<uint64_t *>(C), lw,
-                                   static_cast<const uint64_t *>(A), lda,
-                                   static_cast<const uint64_t *>(B), lw, D, D, D, false,
-                                   sr::kBoolPathAuto, st);
-    };
     int j = 0;
     while ((int64_t(1) << j) < D - 1) j++;
+    // I (+) A: the diagonal becomes the multiplicative one (S, or bit set)
+    const uint32_t one = es == 4 ? 0xFFFFFFFFu : (es == 8 ? 1u : (s8 ? 0x5BF8u : 0xFFFFu));
     if (es == 8) {
+        // Boolean rows must carry zero bits up to their padded end (the
+        // product kernels read whole words there): P takes T's rows up to
+        // lw <= ldt words, which are zero past D by the caller's contract, and
+        // Q starts zeroed (the products write only the words that hold
+        // columns < D).  Every squaring runs (the bit-sliced kernels take no
+        // gate), then T := T * P.
+        hipError_t e = hipMemcpy2DAsync(P, lw * es, T, ld * es, lw * 8, D,
+                                        hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess)
+            e = sr::launch_fill32(reinterpret_cast<uint32_t *>(Q), D * lw * 2, 0u, st);
+        if (e == hipSuccess) e = sr::launch_diag(es, P, lw, D, one, st);
+        auto mul = [&](void *C, const void *A, int64_t lda, const void *B) {
+            return sr::launch_bool_mul(static_cast<uint64_t *>(C), lw,
+                                       static_cast<const uint64_t *>(A), lda,
+                                       static_cast<const uint64_t *>(B), lw, D, D, D, false,
+                                       sr::kBoolPathAuto, st);
+        };
         for (int i = 0; i < j && e == hipSuccess; i++) {
             e = mul(Q, P, lw, P);
             std::swap(P, Q);
@@ -394,11 +400,9 @@ hipError_t closure_by_squaring(int es, bool s8, void *T, int64_t ld, int64_t D, 
     // with P's and sets changed[i] if any differs; squaring i + 1 runs only if
     // that was set.  Once a squaring leaves P unchanged, P is idempotent and
     // every later power equals it; the skipped squarings leave both buffers
-    // holding it, so T * P below is the closure either way.  The host
-    // enqueues all j squarings and never waits.
+    // holding it.  The host enqueues all j squarings and never waits.
     int *changed = reinterpret_cast<int *>(static_cast<char *>(work) + 2 * D * lw * es);
-    if (e == hipSuccess)
-        e = sr::launch_fill32(reinterpret_cast<uint32_t *>(changed), j, 0u, st);
+    hipError_t e = sr::launch_power_prep(es, P, lw, T, ld, D, one, changed, j, st);
     for (int i = 0; i < j && e == hipSuccess; i++) {
         const int *gate = i == 0 ? nullptr : changed + i - 1;
         if (es == 4) {
@@ -412,16 +416,10 @@ hipError_t closure_by_squaring(int es, bool s8, void *T, int64_t ld, int64_t D, 
         }
         std::swap(P, Q);
     }
-    // T := T * P in place: P is closed (P * P = P, P >= I), so any mix of old
-    // and new entries of T that the product's waves read gives the same
-    // T * P (T <= mix <= T * P, and (T * P) * P = T * P)
+    // T := A * P without a product: P off the diagonal, the best cycle
+    // through i on it (see launch_power_finish)
     if (e != hipSuccess) return e;
-    if (es == 4)
-        return sr::launch_ad32_mul(static_cast<uint32_t *>(T), ld, static_cast<const uint32_t *>(T),
-                                   ld, reinterpret_cast<const uint32_t *>(P), lw, D, D, D, false,
-                                   st);
-    return sr::launch_ad_mul(s8, static_cast<uint16_t *>(T), ld, static_cast<const uint16_t *>(T),
-                             ld, reinterpret_cast<const uint16_t *>(P), lw, D, D, D, false, st);
+    return sr::launch_power_finish(es, s8, T, ld, P, lw, D, st);
 }
 
 // Blocked closure with large pivot blocks (Sec. II / Sec. III Warshall loop
@@ -453,20 +451,44 @@ hipError_t closure_big_blocks(int es, bool s8, void *T, int64_t ld, int64_t D, i
                                  reinterpret_cast<const uint16_t *>(at(br, bc)), ld, R, K, N, true,
                                  st, ld - bc);
     };
+    // 16-bit entries: the up to four panel products of a round share one
+    // launch, and so do the up to four block products (they are independent:
+    // every panel product writes its own panel, and the block products read
+    // only the finished panels)
+    sr::MulDesc group[4];
+    int ng = 0;
+    auto add = [&](int64_t cr, int64_t cc, int64_t ar, int64_t ac, int64_t br, int64_t bc,
+                   int64_t R, int64_t K, int64_t N) -> hipError_t {
+        if (R <= 0 || K <= 0 || N <= 0) return hipSuccess;
+        if (es == 4) return mul(cr, cc, ar, ac, br, bc, R, K, N);
+        group[ng++] = {reinterpret_cast<uint16_t *>(at(cr, cc)),
+                       reinterpret_cast<const uint16_t *>(at(ar, ac)),
+                       reinterpret_cast<const uint16_t *>(at(br, bc)), ld, ld, ld, R, K, N,
+                       ld - bc};
+        return hipSuccess;
+    };
+    auto flush = [&]() -> hipError_t {
+        if (ng == 0) return hipSuccess;
+        hipError_t e = sr::launch_ad_mul_group(s8, group, ng, true, st);
+        ng = 0;
+        return e;
+    };
     hipError_t e = hipSuccess;
     for (int64_t k0 = 0; k0 < D && e == hipSuccess; k0 += B) {
         const int64_t bs = std::min(B, D - k0), k1 = k0 + bs;
         e = closure_by_squaring(es, s8, at(k0, k0), ld, bs, work, st);
         // row panel (left, right of the pivot block), column panel (above, below)
-        if (e == hipSuccess) e = mul(k0, 0, k0, k0, k0, 0, bs, bs, k0);
-        if (e == hipSuccess) e = mul(k0, k1, k0, k0, k0, k1, bs, bs, D - k1);
-        if (e == hipSuccess) e = mul(0, k0, 0, k0, k0, k0, k0, bs, bs);
-        if (e == hipSuccess) e = mul(k1, k0, k1, k0, k0, k0, D - k1, bs, bs);
+        if (e == hipSuccess) e = add(k0, 0, k0, k0, k0, 0, bs, bs, k0);
+        if (e == hipSuccess) e = add(k0, k1, k0, k0, k0, k1, bs, bs, D - k1);
+        if (e == hipSuccess) e = add(0, k0, 0, k0, k0, k0, k0, bs, bs);
+        if (e == hipSuccess) e = add(k1, k0, k1, k0, k0, k0, D - k1, bs, bs);
+        if (e == hipSuccess) e = flush();
         // the four blocks outside the pivot rows and columns
         const int64_t rows[2][2] = {{0, k0}, {k1, D - k1}};
         for (const auto &r : rows)
             for (const auto &c : rows)
-                if (e == hipSuccess) e = mul(r[0], c[0], r[0], k0, k0, c[0], r[1], bs, c[1]);
+                if (e == hipSuccess) e = add(r[0], c[0], r[0], k0, k0, c[0], r[1], bs, c[1]);
+        if (e == hipSuccess) e = flush();
     }
     return e;
 }

@@ -35,6 +35,17 @@ hipError_t launch_ad_mul(bool s8, uint16_t *C, int64_t ldc, const uint16_t *A, i
                          const int *gate = nullptr, const uint16_t *prev = nullptr,
                          int *flag = nullptr);
 
+// Up to four independent 16-bit products C (+)= A * B (no output is another
+// product's operand), in one launch where they are small enough to share
+// one; bspan as for launch_ad_mul (-1: ldb).
+struct MulDesc {
+    uint16_t *C;
+    const uint16_t *A, *B;
+    int64_t ldc, lda, ldb, R, K, N, bspan;
+};
+hipError_t launch_ad_mul_group(bool s8, const MulDesc *d, int n, bool accumulate,
+                               hipStream_t stream);
+
 // In-place closure of the D x D matrix T (16-bit storage).  serial: no
 // second stream (every phase in order on `stream`).  aux_create: false to
 // use the second stream only if it exists already (no stream or event is
@@ -131,6 +142,15 @@ hipError_t launch_add(int elem_bytes, void *C, int64_t ldc, const void *A, int64
 // row i set (8).
 hipError_t launch_diag(int elem_bytes, void *T, int64_t ld, int64_t D, uint32_t value,
                        hipStream_t stream);
+// The two ends of the closure by repeated squaring (entries of es = 2 or 4
+// bytes; s8: the binary16 form of uint8 data): P := I (+) T with the change
+// flags flags[0 .. nflags) cleared (nflags <= 256); and T := the closure
+// from P = (I (+) T)^m, m >= D - 1 (P off the diagonal, the best cycle
+// through i on it).  Strides in entries, rows 16-byte aligned.
+hipError_t launch_power_prep(int es, void *P, int64_t ldp, const void *T, int64_t ldt, int64_t D,
+                             uint32_t one, int *flags, int nflags, hipStream_t st);
+hipError_t launch_power_finish(int es, bool s8, void *T, int64_t ldt, const void *P, int64_t ldp,
+                               int64_t D, hipStream_t st);
 // p[0 .. n) := value (32-bit words): a kernel, not a memset node, so that a
 // captured graph replays it faithfully.
 hipError_t launch_fill32(uint32_t *p, int64_t n, uint32_t value, hipStream_t stream);

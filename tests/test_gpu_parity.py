@@ -732,7 +732,7 @@ def test_squaring_early_exit(kind, case):
 
 @pytest.mark.parametrize("kind", [sr.SR_ANTIDIST_U16, sr.SR_ANTIDIST_U8, sr.SR_DISTANCE_U16,
                                   sr.SR_ANTIDIST_U32])
-@pytest.mark.parametrize("D", [1100, 1537, 2100])
+@pytest.mark.parametrize("D", [1024, 1100, 1537, 2100])
 def test_closure_big_blocks(kind, D):
     """Mid sizes (above the whole-matrix squaring range): blocks of 512
     pivots, each closed by squaring, panels and update as products on blocks
@@ -753,6 +753,34 @@ def test_closure_big_blocks(kind, D):
     torch.cuda.synchronize()
     assert np.array_equal(host(T).astype(np.int64), want)
     assert np.array_equal(host(T2).astype(np.int64), want)
+
+
+@pytest.mark.parametrize("kind", [sr.SR_ANTIDIST_U16, sr.SR_ANTIDIST_U8, sr.SR_ANTIDIST_U32])
+@pytest.mark.parametrize("B,D", [(256, 1024), (256, 1300), (768, 1024), (1024, 2000)])
+def test_closure_big_blocks_tuned_block(kind, B, D, tmp_path):
+    """Big pivot blocks of a tuned size (an autotuning entry loaded from its
+    JSON file): with blocks of 256 a round's four panel products and four
+    block products each share one launch; ragged last blocks take one
+    launch per product.  Against the oracle."""
+    gen = synthgen.generator(9970 + 10 * kind + B + D)
+    S = S_OF[kind]
+    A = rand_antidist(D, D, kind, gen, p=3.0 / D, wmax=S // 6)
+    want = oracle.ad_closure(A, S)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cls = int(np.ceil(np.log2(D)))
+    f = tmp_path / "tune.json"
+    f.write_text('{"format": "libsemiring-autotune-1", "entries": [\n'
+                 '{"arch": "%s", "op": 1, "kind": %d, "class": [%d, 0, 0], "choice": %d}\n]}\n'
+                 % (arch, kind, cls, sr.SR_CLOSURE_BIG_BLOCKS | ((B // 64) << 16)))
+    sr.autotune_clear()
+    try:
+        sr.autotune_load(str(f))
+        T = sr.to_device(kind, A)
+        sr.closure(kind, T)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(T).astype(np.int64), want)
+    finally:
+        sr.autotune_clear()
 
 
 @pytest.mark.parametrize("kind,D", [(sr.SR_ANTIDIST_U16, 3000), (sr.SR_ANTIDIST_U8, 4100),
