@@ -459,6 +459,39 @@ def test_bool_closure_mfma(mfma_format, D):
     test_bool_closure_lookahead_and_serial(D, sr.SR_BOOL_MFMA)
 
 
+@pytest.mark.parametrize("case", ["cycle", "descending", "random"])
+@pytest.mark.parametrize("D", [257, 512, 513, 1024, 1100, 2048, 2304, 3000])
+def test_bool_closure_mfma_chains(mfma_format, D, case):
+    """The closure with its bulk update on the matrix cores on inputs whose
+    paths chain through every pivot block ('cycle': one cycle through a random
+    order of all vertices, closure all ones; 'descending': i -> i - 1 plus
+    sparse edges, the order the blocked loop resolves last) and on random
+    ones; even and odd block counts, ragged last blocks; against the oracle,
+    overlapped and serial schedules."""
+    gen = synthgen.generator(3300 + D + len(case))
+    if case == "cycle":
+        order = gen.permutation(D)
+        A = np.zeros((D, D), dtype=np.uint8)
+        A[order, np.roll(order, -1)] = 1
+    elif case == "descending":
+        A = rand_bits(D, D, gen, 0.3 / D)
+        A[np.arange(1, D), np.arange(D - 1)] = 1
+    else:
+        A = rand_bits(D, D, gen, 1.5 / D)
+    ldw = synthgen.aligned_ld_words(D)
+    Aw = synthgen.pack_bits(A, ldw)
+    T = dev(sr.SR_BOOL, Aw, cols=D)
+    T2 = sr.clone(T)
+    sr.closure(sr.SR_BOOL, T, D=D, flags=sr.SR_BOOL_MFMA)
+    sr.closure(sr.SR_BOOL, T2, D=D, flags=sr.SR_BOOL_MFMA | sr.SR_SERIAL_PHASES)
+    want = oracle.bool_closure_words(Aw, D)
+    nw = (D + 63) // 64
+    got = host(T)
+    assert np.array_equal(got[:, :nw], want[:, :nw])
+    assert np.array_equal(host(T2)[:, :nw], want[:, :nw])
+    assert synthgen.padding_bits_clear(got, D)
+
+
 @pytest.mark.parametrize("path", [sr.SR_BOOL_MFMA, sr.SR_BOOL_M4R])
 @pytest.mark.parametrize("R,K,N", [(1, 1, 1), (5, 3, 7), (64, 64, 64), (65, 130, 129),
                                    (200, 37, 300), (257, 300, 513), (128, 1000, 256),

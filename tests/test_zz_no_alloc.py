@@ -75,8 +75,12 @@ def _same(kind, got, want, D):
 # (kind, first D, second D): the first sizes take the working memory of the
 # squaring closure (uint16 1024, uint32 700), of big pivot blocks (uint16
 # distances 1500), of the uint8 working copy plus big blocks (2100) or the
-# whole 32 MiB (uint8 4096, the loop); Boolean needs none.
+# whole 32 MiB (uint8 4096, the loop), or the transposed pivot rows of the
+# matrix-core update (Boolean 2100; first, so that in a fresh process it
+# runs before any call has made the second stream: every phase on the
+# caller's stream); Boolean 1100 needs none.
 CASES = [
+    (sr.SR_BOOL, 2100, 1100),
     (sr.SR_ANTIDIST_U16, 1024, 700),
     (sr.SR_ANTIDIST_U8, 2100, 300),
     (sr.SR_ANTIDIST_U8, 4096, 1000),
