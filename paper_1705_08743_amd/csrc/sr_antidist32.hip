@@ -222,6 +222,46 @@ k_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint3
     }
 }
 
+// Product with the inner dimension split over the KS waves of a workgroup,
+// for products with too few output tiles to fill the chip (the K-split
+// kernel of the 16-bit path, with 32-bit tiles): all KS waves take the same
+// 64-row x CW-column tile of C (every chunk of the launch has CW columns
+// inside N), wave w the inner steps [w kq, (w + 1) kq) (kq a multiple of 32);
+// their partial results meet in LDS, where the (+) of the KS partials (and of
+// C when accumulating) is taken.  (+) is max, so splitting the inner loop
+// changes nothing in the result.  With prev, each stored word is compared
+// with prev's (the squaring's change flag).
+template <int CW, int KS>
+__global__ void __launch_bounds__(64 * KS)
+k_ad32_mul_ksplit(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
+                  int64_t ldb, int64_t R, int K, int kq, int accumulate, const int *gate,
+                  const uint32_t *prev, int *flag) {
+    __shared__ uint32_t part[KS][kRW][CW];
+    if (gate && *gate == 0) return;  // (uniform over the workgroup: before any barrier)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t row0 = (int64_t)blockIdx.y * kRW;
+    const int64_t col0 = (int64_t)blockIdx.x * CW;
+    const int nrows = (int)min<int64_t>(kRW, R - row0);
+    const int k0 = min(K, wave * kq), k1 = min(K, k0 + kq);
+    // this wave's partial product (rows >= nrows are not written)
+    tile32_body<CW, true>(&part[wave][0][0], CW, A + row0 * lda + k0, lda,
+                          B + (int64_t)k0 * ldb + col0, ldb, nrows, CW, k1 - k0, false, false);
+    __syncthreads();
+    bool diff = false;
+    for (int wi = threadIdx.x; wi < kRW * CW; wi += 64 * KS) {
+        const int row = wi / CW, col = wi % CW;
+        if (row >= nrows) continue;
+        uint32_t v = part[0][row][col];
+#pragma unroll
+        for (int q = 1; q < KS; q++) v = max(v, part[q][row][col]);
+        uint32_t *dst = C + (row0 + row) * ldc + col0 + col;
+        if (accumulate) v = max(v, *dst);
+        *dst = v;
+        if (prev) diff |= v != prev[(row0 + row) * ldc + col0 + col];
+    }
+    if (prev && __any(diff) && (threadIdx.x & 63) == 0) *flag = 1;
+}
+
 // ---------------------------------------------------------------------------
 // Pivot tile: Warshall closure of the bs x bs tile at T (bs <= 128) by one
 // 256-thread workgroup.  Thread (ty, tx) = (t / 16, t % 16) holds rows
@@ -649,6 +689,24 @@ hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t 
                            const int *gate, const uint32_t *prev, int *flag) {
     const int64_t bmax = bspan >= 0 ? bspan : ldb;
     if (!flag) prev = nullptr;
+    // few output tiles and a long inner loop: split the inner loop over eight
+    // waves (a partial last column chunk goes to the edge tiles)
+    constexpr int KCW = 16, KS = 8;
+    const int64_t tiles16 = ((R + kRW - 1) / kRW) * (N / KCW);
+    if (tiles16 > 0 && tiles16 <= 2048 && K >= 256 && K <= INT32_MAX) {
+        const int kq = (int)((K + KS * 32 - 1) / (KS * 32) * 32);
+        hipLaunchKernelGGL((k_ad32_mul_ksplit<KCW, KS>),
+                           dim3((unsigned)(N / KCW), (unsigned)((R + kRW - 1) / kRW)),
+                           dim3(64 * KS), 0, stream, C, ldc, A, lda, B, ldb, R, (int)K, kq,
+                           accumulate ? 1 : 0, gate, prev, flag);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || N % KCW == 0) return e;
+        const unsigned gy = (unsigned)((R + 4 * kRW - 1) / (4 * kRW));
+        hipLaunchKernelGGL((k_ad32_mul<KCW, false>), dim3(1u, gy), dim3(256), 0, stream, C, ldc,
+                           A, lda, B, ldb, R, (int)K, N, N / KCW * KCW, accumulate ? 1 : 0, bmax,
+                           gate, prev, flag);
+        return hipGetLastError();
+    }
     // 16-column tiles when 32-column ones would leave the chip short of waves
     const int64_t waves32 = ((R + kRW - 1) / kRW) * ((N + 31) / 32);
     if (waves32 >= 8192)

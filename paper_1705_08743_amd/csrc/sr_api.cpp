@@ -80,14 +80,14 @@ constexpr int64_t kBoolMfmaClosureD = 2048;
 // 428, 1024 183 / 288 / 567, 1536 331 / 1135 / 853, 2048 644 / - / 1129,
 // 3072 1607 / - / 1766; uint8 alike; at 4096, where a round's products no
 // longer share a launch, the loop wins (3.3 vs 4.3 ms); 512 the best block
-// of 256 / 512 / 768 / 1024).  uint32 (no K-split product): squaring 776 / big 1007 / loop
-// 1385 at 1024, 1675 / 1788 / 2222 at 1536, big 2942 / loop 3021 at 2048, so
-// squaring up to 1536 and no big blocks.
+// of 256 / 512 / 768 / 1024; uint32: 640 205 / 284 / 861, 768 276 / 239 /
+// 1060, 1024 488 / 287 / 1385, 2048 - / 1012 / 3034, 3072 - / 2309 / 4545,
+// 4096 - / 4509 / 6702).
 constexpr int64_t kBigBlock = 512;
 constexpr int64_t kBigBlockMaxD16 = 3072;
-constexpr int64_t kBigBlockMaxD32 = 0;
+constexpr int64_t kBigBlockMaxD32 = 4096;
 constexpr int64_t kSquaringMaxD16 = 704;
-constexpr int64_t kSquaringMaxD32 = 1536;
+constexpr int64_t kSquaringMaxD32 = 704;
 
 // bytes per storage unit of the leading dimension
 int64_t unit_bytes(int kind) {

@@ -47,8 +47,11 @@ def host(t):
     return sr.to_host(t).astype(np.int64)
 
 
+# (the K-split kernel takes those with a long inner loop and few tiles:
+# 130 x 300 x 70, 512^3, 100 x 1000 x 37, 64 x 256 x 16, 1000 x 513 x 999)
 MUL_SHAPES = [(1, 1, 1), (3, 5, 2), (64, 64, 64), (65, 130, 129), (200, 37, 300),
-              (257, 8, 513), (130, 300, 70), (511, 129, 1000), (2100, 64, 2100)]
+              (257, 8, 513), (130, 300, 70), (511, 129, 1000), (2100, 64, 2100),
+              (512, 512, 512), (100, 1000, 37), (64, 256, 16), (1000, 513, 999)]
 
 
 @pytest.mark.parametrize("R,K,N", MUL_SHAPES)
@@ -63,12 +66,13 @@ def test_ad32_mul(R, K, N):
 
 def test_ad32_mul_accumulate_and_k0():
     gen = synthgen.generator(9001)
-    A = rand_antidist(70, 45, AD, gen)
-    B = rand_antidist(45, 90, AD, gen)
-    C0 = rand_antidist(70, 90, AD, gen, p=0.5)
-    C = dev(C0)
-    sr.semiring_mul(AD, C, dev(A), dev(B), flags=sr.SR_ACCUMULATE)
-    assert np.array_equal(host(C), oracle.ad_mul(A, B, S, C=C0))
+    for K in (45, 300):  # the second one on the K-split kernel
+        A = rand_antidist(70, K, AD, gen)
+        B = rand_antidist(K, 90, AD, gen)
+        C0 = rand_antidist(70, 90, AD, gen, p=0.5)
+        C = dev(C0)
+        sr.semiring_mul(AD, C, dev(A), dev(B), flags=sr.SR_ACCUMULATE)
+        assert np.array_equal(host(C), oracle.ad_mul(A, B, S, C=C0))
     Z = dev(C0)
     sr.semiring_mul(AD, Z, dev(A[:, :0]), dev(B[:0]), K=0)
     assert not host(Z).any()
@@ -302,11 +306,14 @@ def test_batched32(kind, flags):
 
 
 def test_ad32_closure_at_d4096():
-    """D = 4096 (32 pivot blocks): every entry against the oracle's int64
+    """D = 4096: the default (eight big pivot blocks of 512) and the forced
+    128-pivot loop (32 rounds), every entry against the oracle's int64
     Warshall loop."""
     gen = synthgen.generator(9700)
     D = 4096
     A = rand_antidist(D, D, AD, gen, p=3.0 / D, wmax=S // 8)
-    T = dev(A)
-    sr.closure(AD, T)
-    assert np.array_equal(host(T), oracle.ad_closure(A, S))
+    want = oracle.ad_closure(A, S)
+    for flags in (0, sr.SR_CLOSURE_WARSHALL):
+        T = dev(A)
+        sr.closure(AD, T, flags=flags)
+        assert np.array_equal(host(T), want), flags
