@@ -277,17 +277,22 @@ k_bool_fw_pivot(uint32_t *T, int64_t ld, int64_t k0, int bs, int nwv, int prio) 
             if (j < nwv) tile[(int64_t)t * ld + j] = r[j];
 }
 
-// An 8-word-wide tile with its B block staged in LDS: all 256 threads of the
-// workgroup call this (it has a barrier); B (K <= 256 rows of 8 words, from
-// the workgroup-uniform pointer B) is the same for the four waves, and each
-// wave updates its own 64-row tile C (|)= A * B (nrows <= 0: nothing).  The B
-// block is copied before any wave stores, so C may overlap B (the row panel:
-// the closed pivot tile makes the result independent of that order).  nw <= 8
-// output words; bspan: words of each B row readable from B.
+// An 8-word-wide tile with its B block staged in LDS: all 64 * 4 * KH threads
+// of the workgroup call this (it has barriers); B (K <= 256 rows of 8 words,
+// from the workgroup-uniform pointer B) is the same for every wave, and the
+// four row groups of waves (wave % 4) each update their own 64-row tile C
+// (|)= A * B (nrows <= 0: nothing).  KH = 2: the waves 4 .. 7 take the
+// second half of the inner steps of the same tiles and hand their partial
+// ORs to waves 0 .. 3 through LDS (`part`), which store; each wave then runs
+// half the dependent steps.  The B block is copied before any wave stores,
+// so C may overlap B (the row panel: the closed pivot tile makes the result
+// independent of that order).  nw <= 8 output words; bspan: words of each B
+// row readable from B.
+template <int KH>
 __device__ __forceinline__ void bool_tile8_lds(uint32_t *C, int64_t ldc, const uint32_t *A,
                                                int64_t lda, const uint32_t *B, int64_t ldb,
                                                int nrows, int nw, int64_t bspan, int K,
-                                               uint4 (*lds)[2]) {
+                                               uint4 (*lds)[2], uint4 (*part)[64][2] = nullptr) {
     const int t = threadIdx.x;
     if (t < K) {
         const uint32_t *brow = B + (int64_t)t * ldb;
@@ -304,54 +309,74 @@ __device__ __forceinline__ void bool_tile8_lds(uint32_t *C, int64_t ldc, const u
     }
     __syncthreads();
     const int lane = t & 63;
-    if (nrows <= 0 || nw <= 0) return;
+    const int half = KH == 2 ? __builtin_amdgcn_readfirstlane(t >> 8) : 0;  // uniform per wave
+    const int sub = (t >> 6) & 3;
+    const bool work = nrows > 0 && nw > 0;
     const bool live = lane < nrows;
     const int64_t r = live ? lane : 0;
     uint32_t *crow = C + r * ldc;
-    uint32_t acc[8];
-    if (nw == 8) {
-        const uint4 c0 = reinterpret_cast<const uint4 *>(crow)[0];
-        const uint4 c1 = reinterpret_cast<const uint4 *>(crow)[1];
-        acc[0] = c0.x, acc[1] = c0.y, acc[2] = c0.z, acc[3] = c0.w;
-        acc[4] = c1.x, acc[5] = c1.y, acc[6] = c1.z, acc[7] = c1.w;
-    } else {
+    uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    // inner steps [kb, ke) of this wave (the halves split at a word boundary)
+    const int kh = KH == 2 ? min(K, (K + 63) / 64 * 32) : K;
+    const int kb = half ? kh : 0, ke = half ? K : kh;
+    if (work) {
+        if (!half) {
+            if (nw == 8) {
+                const uint4 c0 = reinterpret_cast<const uint4 *>(crow)[0];
+                const uint4 c1 = reinterpret_cast<const uint4 *>(crow)[1];
+                acc[0] = c0.x, acc[1] = c0.y, acc[2] = c0.z, acc[3] = c0.w;
+                acc[4] = c1.x, acc[5] = c1.y, acc[6] = c1.z, acc[7] = c1.w;
+            } else {
 #pragma unroll
-        for (int w = 0; w < 8; w++) acc[w] = w < nw ? crow[w] : 0u;
-    }
-    const uint32_t *arow = A + r * lda;
-    for (int kw = 0; kw < K; kw += 32) {
-        const uint32_t a = arow[kw >> 5];
-        const int n = min(32, K - kw);
-        if (n == 32) {
-#pragma unroll
-            for (int b = 0; b < 32; b++) {
-                const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(a, b, 1);
-                const uint4 p0 = lds[kw + b][0], p1 = lds[kw + b][1];
-                acc[0] = __builtin_amdgcn_bitop3_b32(p0.x, m, acc[0], 0xEA);
-                acc[1] = __builtin_amdgcn_bitop3_b32(p0.y, m, acc[1], 0xEA);
-                acc[2] = __builtin_amdgcn_bitop3_b32(p0.z, m, acc[2], 0xEA);
-                acc[3] = __builtin_amdgcn_bitop3_b32(p0.w, m, acc[3], 0xEA);
-                acc[4] = __builtin_amdgcn_bitop3_b32(p1.x, m, acc[4], 0xEA);
-                acc[5] = __builtin_amdgcn_bitop3_b32(p1.y, m, acc[5], 0xEA);
-                acc[6] = __builtin_amdgcn_bitop3_b32(p1.z, m, acc[6], 0xEA);
-                acc[7] = __builtin_amdgcn_bitop3_b32(p1.w, m, acc[7], 0xEA);
+                for (int w = 0; w < 8; w++) acc[w] = w < nw ? crow[w] : 0u;
             }
-        } else {
-            for (int b = 0; b < n; b++) {
-                const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(a, b, 1);
-                const uint4 p0 = lds[kw + b][0], p1 = lds[kw + b][1];
-                acc[0] = __builtin_amdgcn_bitop3_b32(p0.x, m, acc[0], 0xEA);
-                acc[1] = __builtin_amdgcn_bitop3_b32(p0.y, m, acc[1], 0xEA);
-                acc[2] = __builtin_amdgcn_bitop3_b32(p0.z, m, acc[2], 0xEA);
-                acc[3] = __builtin_amdgcn_bitop3_b32(p0.w, m, acc[3], 0xEA);
-                acc[4] = __builtin_amdgcn_bitop3_b32(p1.x, m, acc[4], 0xEA);
-                acc[5] = __builtin_amdgcn_bitop3_b32(p1.y, m, acc[5], 0xEA);
-                acc[6] = __builtin_amdgcn_bitop3_b32(p1.z, m, acc[6], 0xEA);
-                acc[7] = __builtin_amdgcn_bitop3_b32(p1.w, m, acc[7], 0xEA);
+        }
+        const uint32_t *arow = A + r * lda;
+        for (int kw = kb; kw < ke; kw += 32) {
+            const uint32_t a = arow[kw >> 5];
+            const int n = min(32, ke - kw);
+            if (n == 32) {
+#pragma unroll
+                for (int b = 0; b < 32; b++) {
+                    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(a, b, 1);
+                    const uint4 p0 = lds[kw + b][0], p1 = lds[kw + b][1];
+                    acc[0] = __builtin_amdgcn_bitop3_b32(p0.x, m, acc[0], 0xEA);
+                    acc[1] = __builtin_amdgcn_bitop3_b32(p0.y, m, acc[1], 0xEA);
+                    acc[2] = __builtin_amdgcn_bitop3_b32(p0.z, m, acc[2], 0xEA);
+                    acc[3] = __builtin_amdgcn_bitop3_b32(p0.w, m, acc[3], 0xEA);
+                    acc[4] = __builtin_amdgcn_bitop3_b32(p1.x, m, acc[4], 0xEA);
+                    acc[5] = __builtin_amdgcn_bitop3_b32(p1.y, m, acc[5], 0xEA);
+                    acc[6] = __builtin_amdgcn_bitop3_b32(p1.z, m, acc[6], 0xEA);
+                    acc[7] = __builtin_amdgcn_bitop3_b32(p1.w, m, acc[7], 0xEA);
+                }
+            } else {
+                for (int b = 0; b < n; b++) {
+                    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(a, b, 1);
+                    const uint4 p0 = lds[kw + b][0], p1 = lds[kw + b][1];
+                    acc[0] = __builtin_amdgcn_bitop3_b32(p0.x, m, acc[0], 0xEA);
+                    acc[1] = __builtin_amdgcn_bitop3_b32(p0.y, m, acc[1], 0xEA);
+                    acc[2] = __builtin_amdgcn_bitop3_b32(p0.z, m, acc[2], 0xEA);
+                    acc[3] = __builtin_amdgcn_bitop3_b32(p0.w, m, acc[3], 0xEA);
+                    acc[4] = __builtin_amdgcn_bitop3_b32(p1.x, m, acc[4], 0xEA);
+                    acc[5] = __builtin_amdgcn_bitop3_b32(p1.y, m, acc[5], 0xEA);
+                    acc[6] = __builtin_amdgcn_bitop3_b32(p1.z, m, acc[6], 0xEA);
+                    acc[7] = __builtin_amdgcn_bitop3_b32(p1.w, m, acc[7], 0xEA);
+                }
             }
         }
     }
-    if (!live) return;
+    if constexpr (KH == 2) {
+        if (half && work) {
+            part[sub][lane][0] = uint4{acc[0], acc[1], acc[2], acc[3]};
+            part[sub][lane][1] = uint4{acc[4], acc[5], acc[6], acc[7]};
+        }
+        __syncthreads();
+        if (half || !work) return;
+        const uint4 q0 = part[sub][lane][0], q1 = part[sub][lane][1];
+        acc[0] |= q0.x, acc[1] |= q0.y, acc[2] |= q0.z, acc[3] |= q0.w;
+        acc[4] |= q1.x, acc[5] |= q1.y, acc[6] |= q1.z, acc[7] |= q1.w;
+    }
+    if (!work || !live) return;
     if (nw == 8) {
         reinterpret_cast<uint4 *>(crow)[0] = uint4{acc[0], acc[1], acc[2], acc[3]};
         reinterpret_cast<uint4 *>(crow)[1] = uint4{acc[4], acc[5], acc[6], acc[7]};
@@ -362,16 +387,19 @@ __device__ __forceinline__ void bool_tile8_lds(uint32_t *C, int64_t ldc, const u
     }
 }
 
-// Phase 2.  Workgroups [0, n_rowwg): the 256 pivot rows (4 waves x 64) times
-// one 8-word (256-column) chunk outside the pivot block.  The rest: column
-// panel, each wave 64 rows outside the pivot block times the 8 pivot words.
-// Either way the workgroup's four waves share one B block (the chunk's pivot
-// rows, or the pivot tile), staged in LDS.
-__global__ void __launch_bounds__(256)
+// Phase 2.  Workgroups [0, n_rowwg): the 256 pivot rows (4 x 64) times one
+// 8-word (256-column) chunk outside the pivot block.  The rest: column
+// panel, 4 x 64 rows outside the pivot block times the 8 pivot words.
+// Either way the workgroup shares one B block (the chunk's pivot rows, or
+// the pivot tile), staged in LDS, and its eight waves split the inner steps
+// in two halves (bool_tile8_lds<2>): the panels are on the critical path of
+// the overlapped closure, where half-length dependent chains pay.
+__global__ void __launch_bounds__(512)
 k_bool_fw_panels(uint32_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg, int prio) {
     if (prio) __builtin_amdgcn_s_setprio(2);
     __shared__ uint4 lds[256][2];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+    __shared__ uint4 part[4][64][2];
+    const int sub = __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) & 3);  // row group
     const int64_t nwd = ((int64_t)D + 31) >> 5;
     const int kw0 = k0 >> 5;
     const int kpw = (int)min<int64_t>(8, nwd - kw0);
@@ -379,18 +407,19 @@ k_bool_fw_panels(uint32_t *T, int64_t ld, int D, int k0, int bs, int n_rowwg, in
         const int cc = (int)blockIdx.x;
         const int64_t c = cc < (kw0 >> 3) ? cc : cc + 1;
         const int64_t w0 = c * 8;
-        const int rofs = wave * 64;
+        const int rofs = sub * 64;
         const int64_t r0 = (int64_t)k0 + rofs;
-        bool_tile8_lds(T + r0 * ld + w0, ld, T + r0 * ld + kw0, ld, T + (int64_t)k0 * ld + w0, ld,
-                       min(64, bs - rofs), (int)min<int64_t>(8, nwd - w0), ld - w0, bs, lds);
+        bool_tile8_lds<2>(T + r0 * ld + w0, ld, T + r0 * ld + kw0, ld, T + (int64_t)k0 * ld + w0,
+                          ld, min(64, bs - rofs), (int)min<int64_t>(8, nwd - w0), ld - w0, bs, lds,
+                          part);
     } else {
         const int kr0 = k0 / 64, kr1 = (k0 + bs + 63) / 64;
-        const int rc = ((int)blockIdx.x - n_rowwg) * 4 + wave;
+        const int rc = ((int)blockIdx.x - n_rowwg) * 4 + sub;
         const int rchunk = rc < kr0 ? rc : rc + (kr1 - kr0);
         const int64_t row0 = (int64_t)rchunk * 64;
         const int nrows = (int)min<int64_t>(64, (int64_t)D - row0);  // <= 0 past the end
-        bool_tile8_lds(T + row0 * ld + kw0, ld, T + row0 * ld + kw0, ld,
-                       T + (int64_t)k0 * ld + kw0, ld, nrows, kpw, ld - kw0, bs, lds);
+        bool_tile8_lds<2>(T + row0 * ld + kw0, ld, T + row0 * ld + kw0, ld,
+                          T + (int64_t)k0 * ld + kw0, ld, nrows, kpw, ld - kw0, bs, lds, part);
     }
 }
 
@@ -418,7 +447,7 @@ k_bool_fw_update(uint32_t *T, int64_t ld, int D, int k0, int bs, BRect q, int nc
         // narrow chunks (small matrices): the four waves share the chunk's B
         // block through LDS
         __shared__ uint4 lds[256][2];
-        bool_tile8_lds(C, ld, A, ld, B, ld, nrows, nw, ld - w0, bs, lds);
+        bool_tile8_lds<1>(C, ld, A, ld, B, ld, nrows, nw, ld - w0, bs, lds);
     } else {
         if (nrows <= 0) return;
         if (nw == NWB) {
@@ -759,7 +788,7 @@ hipError_t panels_b(uint32_t *T, int64_t ld, int64_t D, int64_t kb, hipStream_t 
     const int n_colwg = (int)((nrch - (b.rh - b.rl) + 3) / 4);
     const bool prof = prof_on();
     if (prof) prof_begin(st);
-    hipLaunchKernelGGL(k_bool_fw_panels, dim3(n_rowwg + n_colwg), dim3(256), 0, st, T, ld, (int)D,
+    hipLaunchKernelGGL(k_bool_fw_panels, dim3(n_rowwg + n_colwg), dim3(512), 0, st, T, ld, (int)D,
                        b.k0, b.bs, n_rowwg, crit_prio());
     hipError_t e = hipGetLastError();
     if (prof) prof_end(st, 0, 1, 2.0 * ((double)D - b.bs) * b.bs * b.bs);
