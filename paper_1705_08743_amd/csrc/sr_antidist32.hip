@@ -232,15 +232,12 @@ k_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint3
 // changes nothing in the result.  With prev, each stored word is compared
 // with prev's (the squaring's change flag).
 template <int CW, int KS>
-__global__ void __launch_bounds__(64 * KS)
-k_ad32_mul_ksplit(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
-                  int64_t ldb, int64_t R, int K, int kq, int accumulate, const int *gate,
-                  const uint32_t *prev, int *flag) {
-    __shared__ uint32_t part[KS][kRW][CW];
-    if (gate && *gate == 0) return;  // (uniform over the workgroup: before any barrier)
+__device__ __forceinline__ void ksplit32_tile(uint32_t (*part)[kRW][CW], uint32_t *C, int64_t ldc,
+                                              const uint32_t *A, int64_t lda, const uint32_t *B,
+                                              int64_t ldb, int64_t R, int K, int kq,
+                                              int accumulate, const uint32_t *prev, int *flag,
+                                              int64_t row0, int64_t col0) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t row0 = (int64_t)blockIdx.y * kRW;
-    const int64_t col0 = (int64_t)blockIdx.x * CW;
     const int nrows = (int)min<int64_t>(kRW, R - row0);
     const int k0 = min(K, wave * kq), k1 = min(K, k0 + kq);
     // this wave's partial product (rows >= nrows are not written)
@@ -260,6 +257,45 @@ k_ad32_mul_ksplit(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, cons
         if (prev) diff |= v != prev[(row0 + row) * ldc + col0 + col];
     }
     if (prev && __any(diff) && (threadIdx.x & 63) == 0) *flag = 1;
+}
+
+template <int CW, int KS>
+__global__ void __launch_bounds__(64 * KS)
+k_ad32_mul_ksplit(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
+                  int64_t ldb, int64_t R, int K, int kq, int accumulate, const int *gate,
+                  const uint32_t *prev, int *flag) {
+    __shared__ uint32_t part[KS][kRW][CW];
+    if (gate && *gate == 0) return;  // (uniform over the workgroup: before any barrier)
+    ksplit32_tile<CW, KS>(part, C, ldc, A, lda, B, ldb, R, K, kq, accumulate, prev, flag,
+                          (int64_t)blockIdx.y * kRW, (int64_t)blockIdx.x * CW);
+}
+
+// Up to four independent products in one launch of the K-split tiles (the
+// blocks of a big-block round; the 16-bit path's k_ad_mul_ksplit_group with
+// 32-bit tiles): workgroups [end_{q-1}, end_q) take the nx_q x ny_q tiles of
+// product q, row-major.
+struct Ksplit32Problem {
+    uint32_t *C;
+    const uint32_t *A, *B;
+    int64_t ldc, lda, ldb, R;
+    int K, kq, nx, end;
+};
+struct Ksplit32Group {
+    Ksplit32Problem p[4];
+    int n, accumulate;
+};
+
+template <int CW, int KS>
+__global__ void __launch_bounds__(64 * KS) k_ad32_mul_ksplit_group(Ksplit32Group g) {
+    __shared__ uint32_t part[KS][kRW][CW];
+    const int b = blockIdx.x;
+    int q = 0;
+    while (q + 1 < g.n && b >= g.p[q].end) q++;
+    const Ksplit32Problem &p = g.p[q];
+    const int local = b - (q > 0 ? g.p[q - 1].end : 0);
+    ksplit32_tile<CW, KS>(part, p.C, p.ldc, p.A, p.lda, p.B, p.ldb, p.R, p.K, p.kq, g.accumulate,
+                          nullptr, nullptr, (int64_t)(local / p.nx) * kRW,
+                          (int64_t)(local % p.nx) * CW);
 }
 
 // ---------------------------------------------------------------------------
@@ -713,6 +749,59 @@ hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t 
         return mul_cw<32>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, prev, flag,
                           stream);
     return mul_cw<16>(C, ldc, A, lda, B, ldb, R, K, N, accumulate, bmax, gate, prev, flag, stream);
+}
+
+hipError_t launch_ad32_mul_group(const MulDesc32 *d, int n, bool acc, hipStream_t st) {
+    constexpr int KCW = 16, KS = 8;
+    int64_t tiles = 0;
+    bool ok = n >= 2 && n <= 4;
+    for (int q = 0; q < n && ok; q++) {
+        ok = d[q].R > 0 && d[q].K >= 256 && d[q].N >= KCW && d[q].K <= INT32_MAX;
+        tiles += ((d[q].R + kRW - 1) / kRW) * (d[q].N / KCW);
+    }
+    if (!ok || tiles > 2048) {
+        for (int q = 0; q < n; q++) {
+            if (d[q].R <= 0 || d[q].K <= 0 || d[q].N <= 0) continue;
+            hipError_t e = launch_ad32_mul(d[q].C, d[q].ldc, d[q].A, d[q].lda, d[q].B, d[q].ldb,
+                                           d[q].R, d[q].K, d[q].N, acc, st, d[q].bspan);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    Ksplit32Group g{};
+    g.n = n;
+    g.accumulate = acc ? 1 : 0;
+    int end = 0;
+    for (int q = 0; q < n; q++) {
+        Ksplit32Problem &p = g.p[q];
+        p.C = d[q].C;
+        p.A = d[q].A;
+        p.B = d[q].B;
+        p.ldc = d[q].ldc;
+        p.lda = d[q].lda;
+        p.ldb = d[q].ldb;
+        p.R = d[q].R;
+        p.K = (int)d[q].K;
+        p.kq = (int)((d[q].K + KS * 32 - 1) / (KS * 32) * 32);
+        p.nx = (int)(d[q].N / KCW);
+        end += p.nx * (int)((d[q].R + kRW - 1) / kRW);
+        p.end = end;
+    }
+    hipLaunchKernelGGL((k_ad32_mul_ksplit_group<KCW, KS>), dim3((unsigned)end), dim3(64 * KS), 0,
+                       st, g);
+    hipError_t e = hipGetLastError();
+    // the partial last column chunks, as in launch_ad32_mul
+    for (int q = 0; q < n && e == hipSuccess; q++) {
+        if (d[q].N % KCW == 0) continue;
+        const unsigned gy = (unsigned)((d[q].R + 4 * kRW - 1) / (4 * kRW));
+        const int64_t bmax = d[q].bspan >= 0 ? d[q].bspan : d[q].ldb;
+        hipLaunchKernelGGL((k_ad32_mul<KCW, false>), dim3(1u, gy), dim3(256), 0, st, d[q].C,
+                           d[q].ldc, d[q].A, d[q].lda, d[q].B, d[q].ldb, d[q].R, (int)d[q].K,
+                           d[q].N, d[q].N / KCW * KCW, acc ? 1 : 0, bmax, (const int *)nullptr,
+                           (const uint32_t *)nullptr, (int *)nullptr);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, bool serial,

@@ -437,39 +437,32 @@ hipError_t closure_big_blocks(int es, bool s8, void *T, int64_t ld, int64_t D, i
                               void *work, hipStream_t st) {
     char *base = static_cast<char *>(T);
     auto at = [&](int64_t r, int64_t c) { return base + (r * ld + c) * es; };
-    // C (+)= A * B on blocks of T; B's rows end at column D of T
-    auto mul = [&](int64_t cr, int64_t cc, int64_t ar, int64_t ac, int64_t br, int64_t bc,
-                   int64_t R, int64_t K, int64_t N) -> hipError_t {
-        if (R <= 0 || K <= 0 || N <= 0) return hipSuccess;
-        if (es == 4)
-            return sr::launch_ad32_mul(reinterpret_cast<uint32_t *>(at(cr, cc)), ld,
-                                       reinterpret_cast<const uint32_t *>(at(ar, ac)), ld,
-                                       reinterpret_cast<const uint32_t *>(at(br, bc)), ld, R, K,
-                                       N, true, st, ld - bc);
-        return sr::launch_ad_mul(s8, reinterpret_cast<uint16_t *>(at(cr, cc)), ld,
-                                 reinterpret_cast<const uint16_t *>(at(ar, ac)), ld,
-                                 reinterpret_cast<const uint16_t *>(at(br, bc)), ld, R, K, N, true,
-                                 st, ld - bc);
-    };
-    // 16-bit entries: the up to four panel products of a round share one
-    // launch, and so do the up to four block products (they are independent:
-    // every panel product writes its own panel, and the block products read
-    // only the finished panels)
+    // C (+)= A * B on blocks of T (B's rows end at column D of T); the up to
+    // four panel products of a round share one launch, and so do the up to
+    // four block products (they are independent: every panel product writes
+    // its own panel, and the block products read only the finished panels)
     sr::MulDesc group[4];
+    sr::MulDesc32 group32[4];
     int ng = 0;
     auto add = [&](int64_t cr, int64_t cc, int64_t ar, int64_t ac, int64_t br, int64_t bc,
                    int64_t R, int64_t K, int64_t N) -> hipError_t {
         if (R <= 0 || K <= 0 || N <= 0) return hipSuccess;
-        if (es == 4) return mul(cr, cc, ar, ac, br, bc, R, K, N);
-        group[ng++] = {reinterpret_cast<uint16_t *>(at(cr, cc)),
-                       reinterpret_cast<const uint16_t *>(at(ar, ac)),
-                       reinterpret_cast<const uint16_t *>(at(br, bc)), ld, ld, ld, R, K, N,
-                       ld - bc};
+        if (es == 4)
+            group32[ng++] = {reinterpret_cast<uint32_t *>(at(cr, cc)),
+                             reinterpret_cast<const uint32_t *>(at(ar, ac)),
+                             reinterpret_cast<const uint32_t *>(at(br, bc)), ld, ld, ld, R, K, N,
+                             ld - bc};
+        else
+            group[ng++] = {reinterpret_cast<uint16_t *>(at(cr, cc)),
+                           reinterpret_cast<const uint16_t *>(at(ar, ac)),
+                           reinterpret_cast<const uint16_t *>(at(br, bc)), ld, ld, ld, R, K, N,
+                           ld - bc};
         return hipSuccess;
     };
     auto flush = [&]() -> hipError_t {
         if (ng == 0) return hipSuccess;
-        hipError_t e = sr::launch_ad_mul_group(s8, group, ng, true, st);
+        hipError_t e = es == 4 ? sr::launch_ad32_mul_group(group32, ng, true, st)
+                               : sr::launch_ad_mul_group(s8, group, ng, true, st);
         ng = 0;
         return e;
     };

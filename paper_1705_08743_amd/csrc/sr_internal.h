@@ -61,6 +61,15 @@ hipError_t launch_ad32_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t 
                            bool accumulate, hipStream_t stream, int64_t bspan = -1,
                            const int *gate = nullptr, const uint32_t *prev = nullptr,
                            int *flag = nullptr);
+// Up to four independent 32-bit products C (+)= A * B (launch_ad_mul_group
+// with 32-bit entries).
+struct MulDesc32 {
+    uint32_t *C;
+    const uint32_t *A, *B;
+    int64_t ldc, lda, ldb, R, K, N, bspan;
+};
+hipError_t launch_ad32_mul_group(const MulDesc32 *d, int n, bool accumulate,
+                                 hipStream_t stream);
 hipError_t launch_ad32_closure(uint32_t *T, int64_t ld, int64_t D, bool serial,
                                hipStream_t stream, bool aux_create = true);
 
