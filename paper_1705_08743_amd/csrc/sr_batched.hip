@@ -16,10 +16,12 @@
 // Every launch has thousands of workgroups (not one per graph), which keeps
 // the large graphs from finishing alone on a few compute units; the update
 // and panels launches hand their workgroups to the XCDs in chunks (below).
-// uint8 batches, and Boolean graphs of more than kBoolBatchSmall vertices,
-// are converted into 16-bit working copies (binary16 values) before the
-// rounds and back after them; smaller Boolean graphs are closed on their bit
-// rows by one workgroup each (k_batch_bool_small).  The launch
+// uint8 batches are closed in 16-bit working copies (binary16 values), into
+// which the rounds' own launches widen the data and from which they narrow it
+// back (round_c8 below); Boolean graphs of more than kBoolBatchSmall vertices
+// are unpacked into such copies before the rounds and packed after them, and
+// smaller ones are closed on their bit rows by one workgroup each
+// (k_batch_bool_small).  The launch
 // sequence holds no allocation, copy or host callback once the plan is in
 // device memory, so it can be captured into a graph.
 #include <hip/hip_runtime.h>
@@ -54,25 +56,54 @@ using dev::tile_closure;
 // batch_plan_create (1: 64 x 16, 2: 64 x 32, 3: 64 x 64; entry 0 unused).
 constexpr int kTileNW[4] = {16, 8, 16, 32};
 
+// uint8 data (io & kIoU8) stays in the caller's uint8 matrix T8 outside the
+// rounds: each entry is widened into the working copy T by the one launch of
+// round 0 that first reads it (pivot tile, panels or update), and narrowed
+// back by the one launch of the graph's last round that last writes it, so
+// the rounds need no separate conversion passes over the batch (kIoNeg:
+// complemented on the way, 255 - a, for the distance kind).  The three
+// launches of a round cover each graph's entries exactly once: the pivot
+// tile, the panels (pivot rows and columns outside it) and the rest.
+constexpr int kIoU8 = 1, kIoNeg = 2;
+
+// The uint8 side of graph d in round kb (none for S8 = false, where io is
+// 0).  The mode is a run-time value, uniform over a wave: the tile code
+// branches on it only around its loads and stores, so one copy of the inner
+// loop serves every round.  last_no16: the entries this launch writes in the
+// graph's last round are read by no later launch (no 16-bit copy needed).
 template <bool S8>
-__global__ void __launch_bounds__(256) k_batch_pivot(const BatchDesc *desc, const Item *items, int kb) {
-    __shared__ uint32_t lds_row[2 * 128];
-    __shared__ uint32_t lds_col[2 * 128];
-    const BatchDesc d = cdesc(desc, citems(items)[blockIdx.x].graph);
-    const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
-    tile_closure<S8>(d.T + (int64_t)k0 * d.ld + k0, d.ld, bs, lds_row, lds_col);
+__device__ __forceinline__ dev::C8 round_c8(const BatchDesc &d, int kb, int io, bool last_no16) {
+    if (!S8 || !(io & kIoU8)) return dev::C8{nullptr, 0, 0};
+    int m = (io & kIoNeg) ? dev::kC8Neg : 0;
+    if (kb == 0) m |= dev::kC8In;
+    if (kb == rounds_of(d.D) - 1) m |= dev::kC8Out | (last_no16 ? dev::kNo16 : 0);
+    return dev::C8{d.T8, d.ld8, m};
 }
 
 template <bool S8>
 __global__ void __launch_bounds__(256)
-k_batch_panels(const BatchDesc *desc, const Item *items, int n_items, int kb, int xmap) {
+k_batch_pivot(const BatchDesc *desc, const Item *items, int kb, int io) {
+    __shared__ uint32_t lds_row[2 * 128];
+    __shared__ uint32_t lds_col[2 * 128];
+    const BatchDesc d = cdesc(desc, citems(items)[blockIdx.x].graph);
+    const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
+    // a graph of one round: its pivot tile is the whole result
+    const dev::C8 c8 = round_c8<S8>(d, kb, io, rounds_of(d.D) == 1);
+    tile_closure<S8>(d.T + (int64_t)k0 * d.ld + k0, d.ld, bs, lds_row, lds_col, c8.at(k0, k0));
+}
+
+template <bool S8>
+__global__ void __launch_bounds__(256)
+k_batch_panels(const BatchDesc *desc, const Item *items, int n_items, int kb, int xmap, int io) {
     const int bid = xmap ? xcd_order((int)blockIdx.x, (int)gridDim.x, xmap) : (int)blockIdx.x;
     const int i = find_item(items, n_items, bid);
     const BatchDesc d = cdesc(desc, citems(items)[i].graph);
     const int k0 = kb * kAdBlock, bs = min(kAdBlock, d.D - k0);
     int n_rowwg = 0, n_colwg = 0;
     dev::panel_wgs(d.D, k0, bs, &n_rowwg, &n_colwg);
-    fw_panels_wg<S8>(d.T, d.ld, d.D, k0, bs, n_rowwg, bid - citems(items)[i].first);
+    const int wg = bid - citems(items)[i].first;
+    // (the panels are the update's operands: their 16-bit copy stays)
+    fw_panels_wg<S8>(d.T, d.ld, d.D, k0, bs, n_rowwg, wg, round_c8<S8>(d, kb, io, false));
 }
 
 // Phase 3: one 64 x 2 NW tile per wave.  The waves of all graphs are
@@ -82,7 +113,7 @@ k_batch_panels(const BatchDesc *desc, const Item *items, int n_items, int kb, in
 template <int NW, bool S8>
 __global__ void __launch_bounds__(256)
 k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, int n_waves,
-               int xmap) {
+               int xmap, int io) {
     constexpr int CW = 2 * NW;
     const int bid = xmap ? xcd_order((int)blockIdx.x, (int)gridDim.x, xmap) : (int)blockIdx.x;
     const int gw = bid * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -99,82 +130,17 @@ k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, in
     const int rsel = local % nr, csel = local / nr;
     int c = csel;
     if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
+    const dev::C8 c8 = round_c8<S8>(d, kb, io, true);
     if ((c + 1) * CW <= d.D)
-        dev::fw_update_wave<1, NW, S8, true, true>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
+        dev::fw_update_wave<1, NW, S8, true, true>(d.T, d.ld, d.D, k0, bs, q, csel, rsel, c8);
     else
-        dev::fw_update_wave<1, NW, S8, false, true>(d.T, d.ld, d.D, k0, bs, q, csel, rsel);
+        dev::fw_update_wave<1, NW, S8, false, true>(d.T, d.ld, d.D, k0, bs, q, csel, rsel, c8);
 }
 
-// uint8 <-> the 16-bit working form of uint8 data (binary16 values) for every
-// graph of a batch: workgroup (g, y) converts rows [32 y, 32 y + 32) of graph
-// g (the grid has ceil(max D / 32) rows of workgroups; those past a graph's
-// last row exit at once); with neg the entries are complemented on the way
-// (255 - a: distance <-> anti-distance).
+// Workgroup (g, y) of the conversion launches below takes rows [32 y, 32 y +
+// 32) of graph g (the grid has ceil(max D / 32) rows of workgroups; those past
+// a graph's last row exit at once).
 constexpr int kConvRows = 32;
-
-__global__ void __launch_bounds__(256) k_batch_widen(const BatchDesc *desc, int neg) {
-    const BatchDesc d = desc[blockIdx.x];
-    const int64_t r0 = (int64_t)blockIdx.y * kConvRows;
-    if (r0 >= d.D) return;
-    const int64_t nr = min<int64_t>(kConvRows, (int64_t)d.D - r0);
-    const int64_t gpr = ((int64_t)d.D + 7) >> 3;
-    for (int64_t g = threadIdx.x; g < nr * gpr; g += 256) {
-        const int64_t row = r0 + g / gpr, c0 = (g % gpr) * 8;
-        const uint8_t *s = d.T8 + row * d.ld8 + c0;
-        uint8_t b[8];
-        if (c0 + 8 <= d.D) {
-            // 8 bytes at once (rows of T8 are 16-byte aligned, c0 a multiple of 8)
-            const uint2 w = *reinterpret_cast<const uint2 *>(s);
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                b[i] = (uint8_t)(w.x >> (8 * i));
-                b[4 + i] = (uint8_t)(w.y >> (8 * i));
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 8; i++) b[i] = (c0 + i < d.D) ? s[i] : (uint8_t)0;
-        }
-        uint16_t v[8];
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-            v[i] = (c0 + i < d.D) ? dev::u8_to_work(neg ? (uint8_t)~b[i] : b[i]) : (uint16_t)0;
-        uint4 o;
-        o.x = v[0] | ((uint32_t)v[1] << 16);
-        o.y = v[2] | ((uint32_t)v[3] << 16);
-        o.z = v[4] | ((uint32_t)v[5] << 16);
-        o.w = v[6] | ((uint32_t)v[7] << 16);
-        *reinterpret_cast<uint4 *>(d.T + row * d.ld + c0) = o;
-    }
-}
-
-__global__ void __launch_bounds__(256) k_batch_narrow(const BatchDesc *desc, int neg) {
-    const BatchDesc d = desc[blockIdx.x];
-    const int64_t r0 = (int64_t)blockIdx.y * kConvRows;
-    if (r0 >= d.D) return;
-    const int64_t nr = min<int64_t>(kConvRows, (int64_t)d.D - r0);
-    const int64_t gpr = ((int64_t)d.D + 7) >> 3;
-    for (int64_t g = threadIdx.x; g < nr * gpr; g += 256) {
-        const int64_t row = r0 + g / gpr, c0 = (g % gpr) * 8;
-        const uint4 w = *reinterpret_cast<const uint4 *>(d.T + row * d.ld + c0);
-        const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
-        uint8_t *dst = d.T8 + row * d.ld8 + c0;
-        uint8_t b[8];
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const uint8_t x = dev::work_to_u8((uint16_t)(ww[i >> 1] >> (16 * (i & 1))));
-            b[i] = neg ? (uint8_t)~x : x;
-        }
-        if (c0 + 8 <= d.D) {
-            uint2 o;
-            o.x = b[0] | ((uint32_t)b[1] << 8) | ((uint32_t)b[2] << 16) | ((uint32_t)b[3] << 24);
-            o.y = b[4] | ((uint32_t)b[5] << 8) | ((uint32_t)b[6] << 16) | ((uint32_t)b[7] << 24);
-            *reinterpret_cast<uint2 *>(dst) = o;
-        } else {
-            for (int i = 0; i < 8; i++)
-                if (c0 + i < d.D) dst[i] = b[i];
-        }
-    }
-}
 
 // Boolean data (bit c of a row: bit c % 8 of byte c / 8, i.e. bit c % 64 of
 // 64-bit word c / 64 on this little-endian device; T8 = the bit rows, ld8 in
@@ -183,8 +149,7 @@ __global__ void __launch_bounds__(256) k_batch_narrow(const BatchDesc *desc, int
 // (+) = max and (x) (a + b - 255, floored at 0) stay in {0, 255} and act as OR
 // and AND, so the anti-distance closure of the copy is the Boolean closure
 // (Boolean matrices are the anti-distance matrices of S = 1, rescaled).
-// Workgroup (g, y) converts rows [32 y, 32 y + 32) of graph g, one byte of
-// bits (8 columns) per thread and step.
+// One byte of bits (8 columns) per thread and step.
 __global__ void __launch_bounds__(256) k_batch_unpack(const BatchDesc *desc) {
     const BatchDesc d = desc[blockIdx.x];
     const int64_t r0 = (int64_t)blockIdx.y * kConvRows;
@@ -230,8 +195,7 @@ __global__ void __launch_bounds__(256) k_batch_pack(const BatchDesc *desc) {
     }
 }
 
-// uint16 entries complemented in place (65535 - a), every graph; workgroup
-// (g, y) takes rows [32 y, 32 y + 32) of graph g, as the conversions above.
+// uint16 entries complemented in place (65535 - a), every graph.
 __global__ void __launch_bounds__(256) k_batch_not(const BatchDesc *desc) {
     const BatchDesc d = desc[blockIdx.x];
     const int64_t r0 = (int64_t)blockIdx.y * kConvRows;
@@ -488,13 +452,13 @@ hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, in
         }
         if (p.pivot.empty()) return hipGetLastError();  // no graph above kBoolBatchSmall
         hipLaunchKernelGGL(k_batch_unpack, conv, dim3(256), 0, st, desc);
-    } else if (s8)
-        hipLaunchKernelGGL(k_batch_widen, conv, dim3(256), 0, st, desc, dual ? 1 : 0);
-    else if (dual)
+    } else if (dual && !s8)
         hipLaunchKernelGGL(k_batch_not, conv, dim3(256), 0, st, desc);
+    // uint8 data: widened and narrowed by the rounds' own launches
+    const int io = (s8 && !bits) ? (kIoU8 | (dual ? kIoNeg : 0)) : 0;
     // the update kernel of the plan's tile shape, for 16-bit (S8 = false) or
     // binary16 (S8 = true) working data
-    using UpdateFn = void (*)(const BatchDesc *, const Item *, int, int, int, int);
+    using UpdateFn = void (*)(const BatchDesc *, const Item *, int, int, int, int, int);
     // XCD chunk of the update and panels launches (xcd_order; 0 = the plain
     // order).  64 workgroups measured best for configuration 4 (uint16 16.6
     // -> 15.8 ms, uint8 15.9 -> 14.3 ms; 4 / 16 / 256 in between); the
@@ -522,22 +486,22 @@ hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, in
         if (a.n_wg > 0) {
             if (s8)
                 hipLaunchKernelGGL(k_batch_pivot<true>, dim3(a.n_wg), dim3(256), 0, st, desc,
-                                   items + a.offset, (int)kb);
+                                   items + a.offset, (int)kb, io);
             else
                 hipLaunchKernelGGL(k_batch_pivot<false>, dim3(a.n_wg), dim3(256), 0, st, desc,
-                                   items + a.offset, (int)kb);
+                                   items + a.offset, (int)kb, io);
         }
         if (b.n_wg > 0) {
             if (s8)
                 hipLaunchKernelGGL(k_batch_panels<true>, dim3(b.n_wg), dim3(256), 0, st, desc,
-                                   items + b.offset, b.n_items + 1, (int)kb, xmapp);
+                                   items + b.offset, b.n_items + 1, (int)kb, xmapp, io);
             else
                 hipLaunchKernelGGL(k_batch_panels<false>, dim3(b.n_wg), dim3(256), 0, st, desc,
-                                   items + b.offset, b.n_items + 1, (int)kb, xmapp);
+                                   items + b.offset, b.n_items + 1, (int)kb, xmapp, io);
         }
         if (c.n_wg > 0)
             hipLaunchKernelGGL(upd, dim3(c.n_wg), dim3(256), 0, st, desc, items + c.offset,
-                               c.n_items + 1, (int)kb, c.n_units, xmap);
+                               c.n_items + 1, (int)kb, c.n_units, xmap, io);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (bits) {
@@ -548,10 +512,7 @@ hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, in
         hipLaunchKernelGGL(k_batch_pack, conv, dim3(256), 0, st, desc);
         return hipGetLastError();
     }
-    if (s8)
-        hipLaunchKernelGGL(k_batch_narrow, conv, dim3(256), 0, st, desc, dual ? 1 : 0);
-    else if (dual)
-        hipLaunchKernelGGL(k_batch_not, conv, dim3(256), 0, st, desc);
+    if (dual && !s8) hipLaunchKernelGGL(k_batch_not, conv, dim3(256), 0, st, desc);
     if (reflexive) {
         // the multiplicative identity's diagonal: S (anti-distance), 0 (distance)
         const uint32_t one = dual ? 0u : (s8 ? 255u : 65535u);

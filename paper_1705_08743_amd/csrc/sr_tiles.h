@@ -36,6 +36,43 @@ __device__ __forceinline__ uint8_t work_to_u8(uint16_t w) {
     return (uint8_t)(uint32_t)(float)__builtin_bit_cast(_Float16, w);
 }
 
+// Four uint8 values (one word, low byte first) -> their working forms as two
+// packed pairs.  Each byte b is placed under the high byte 0x64, the binary16
+// pattern of 1024 + b, and 1024 is subtracted in binary16: exact, with 0
+// giving +0, the same bits as u8_to_work.
+__device__ __forceinline__ void widen4(uint32_t w, uint32_t &lo, uint32_t &hi) {
+    const h16x2 k = {(_Float16)1024.0f, (_Float16)1024.0f};
+    lo = __builtin_bit_cast(uint32_t,
+                            __builtin_bit_cast(h16x2, __builtin_amdgcn_perm(0x64646464u, w, 0x04010400u)) - k);
+    hi = __builtin_bit_cast(uint32_t,
+                            __builtin_bit_cast(h16x2, __builtin_amdgcn_perm(0x64646464u, w, 0x04030402u)) - k);
+}
+// The way back for two pairs holding working forms of 0..255: + 1024 puts
+// each value in the low byte of its half, and one byte permute gathers them.
+__device__ __forceinline__ uint32_t narrow4(uint32_t lo, uint32_t hi) {
+    const h16x2 k = {(_Float16)1024.0f, (_Float16)1024.0f};
+    const uint32_t a = __builtin_bit_cast(uint32_t, __builtin_bit_cast(h16x2, lo) + k);
+    const uint32_t b = __builtin_bit_cast(uint32_t, __builtin_bit_cast(h16x2, hi) + k);
+    return __builtin_amdgcn_perm(b, a, 0x06040200u);
+}
+
+// The uint8 side of a tile's C, for closures that keep uint8 data in the
+// caller's uint8 matrix and compute on its 16-bit working copy: with kC8In
+// the tile's C is read from p (and widened) instead of the working copy, with
+// kC8Out the result is also narrowed into p, and with kNo16 it goes to p only;
+// kC8Neg complements the uint8 values both ways (255 - v).  p points at the
+// tile's first entry, ld in bytes (rows 16-byte aligned).  mode 0: no uint8
+// side.
+enum { kC8In = 1, kC8Out = 2, kNo16 = 4, kC8Neg = 8 };
+struct C8 {
+    uint8_t *p;
+    int64_t ld;
+    int mode;
+    __device__ __forceinline__ C8 at(int64_t row, int64_t col) const {
+        return C8{mode ? p + row * ld + col : p, ld, mode};
+    }
+};
+
 // The A-side operand of a packed pair: S - a (u16) or a - 255 (S8, binary16).
 template <bool S8>
 __device__ __forceinline__ uint32_t neg_pair(uint32_t a) {
@@ -138,11 +175,102 @@ __device__ __forceinline__ void row_store(const u16x2 (&acc)[NW], uint16_t *crow
     }
 }
 
+// row_load / row_store on the uint8 side of C (2 NW bytes per row; FULLC
+// rows are read and written as whole 16-byte or, for NW = 4, 8-byte words).
+template <int NW, bool FULLC>
+__device__ __forceinline__ void row_load8(u16x2 (&acc)[NW], const uint8_t *crow, int ncols,
+                                          bool neg) {
+    if (FULLC) {
+        uint32_t w[NW / 2];
+        if constexpr (NW >= 8) {
+#pragma unroll
+            for (int q = 0; q < NW / 8; q++) {
+                const uint4 v = reinterpret_cast<const uint4 *>(crow)[q];
+                w[4 * q + 0] = v.x;
+                w[4 * q + 1] = v.y;
+                w[4 * q + 2] = v.z;
+                w[4 * q + 3] = v.w;
+            }
+        } else {
+            const uint2 v = *reinterpret_cast<const uint2 *>(crow);
+            w[0] = v.x;
+            w[1] = v.y;
+        }
+#pragma unroll
+        for (int i = 0; i < NW / 2; i++) {
+            uint32_t lo, hi;
+            widen4(neg ? ~w[i] : w[i], lo, hi);
+            acc[2 * i] = as_pair(lo);
+            acc[2 * i + 1] = as_pair(hi);
+        }
+    } else {
+        const uint8_t m = neg ? 0xFF : 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            const uint16_t lo = (2 * w < ncols) ? u8_to_work((uint8_t)(crow[2 * w] ^ m)) : (uint16_t)0;
+            const uint16_t hi =
+                (2 * w + 1 < ncols) ? u8_to_work((uint8_t)(crow[2 * w + 1] ^ m)) : (uint16_t)0;
+            acc[w] = u16x2{lo, hi};
+        }
+    }
+}
+
+template <int NW, bool FULLC>
+__device__ __forceinline__ void row_store8(const u16x2 (&acc)[NW], uint8_t *crow, int ncols,
+                                           bool neg) {
+    if (FULLC) {
+        uint32_t w[NW / 2];
+#pragma unroll
+        for (int i = 0; i < NW / 2; i++) {
+            w[i] = narrow4(as_word(acc[2 * i]), as_word(acc[2 * i + 1]));
+            if (neg) w[i] = ~w[i];
+        }
+        if constexpr (NW >= 8) {
+#pragma unroll
+            for (int q = 0; q < NW / 8; q++)
+                reinterpret_cast<uint4 *>(crow)[q] =
+                    uint4{w[4 * q + 0], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
+        } else {
+            *reinterpret_cast<uint2 *>(crow) = uint2{w[0], w[1]};
+        }
+    } else {
+        const uint8_t m = neg ? 0xFF : 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            if (2 * w < ncols) crow[2 * w] = (uint8_t)(work_to_u8(acc[w].x) ^ m);
+            if (2 * w + 1 < ncols) crow[2 * w + 1] = (uint8_t)(work_to_u8(acc[w].y) ^ m);
+        }
+    }
+}
+
+// One wavefront widens an nrows x ncols block (nrows <= 64, lane = row) of
+// uint8 data at c8 into its working form at C (16-byte aligned rows on both
+// sides, the block's first column a multiple of 8).
+__device__ __forceinline__ void widen_block_wave(uint16_t *C, int64_t ldc, const C8 &c8, int nrows,
+                                                 int ncols) {
+    const int lane = threadIdx.x & 63;
+    if (lane >= nrows || ncols <= 0) return;
+    const uint8_t *src = c8.p + (int64_t)lane * c8.ld;
+    uint16_t *dst = C + (int64_t)lane * ldc;
+    const bool neg = c8.mode & kC8Neg;
+    for (int c = 0; c < ncols; c += 8) {
+        if (c + 8 <= ncols) {
+            const uint2 v = *reinterpret_cast<const uint2 *>(src + c);
+            uint32_t a, b, e, f;
+            widen4(neg ? ~v.x : v.x, a, b);
+            widen4(neg ? ~v.y : v.y, e, f);
+            *reinterpret_cast<uint4 *>(dst + c) = uint4{a, b, e, f};
+        } else {
+            for (int j = c; j < ncols; j++) dst[j] = u8_to_work((uint8_t)(neg ? ~src[j] : src[j]));
+        }
+    }
+}
+
 template <int TM, int NW, bool S8, bool FULLC, bool GROUPB = !S8>
 __device__ __forceinline__ void wave_tile_body(uint16_t *C, int64_t ldc, const uint16_t *A,
                                                int64_t lda, const uint16_t *B, int64_t ldb,
                                                int nrows, int ncols, int K, bool accumulate,
-                                               bool sync_before_store) {
+                                               bool sync_before_store, C8 c8 = C8{nullptr, 0, 0}) {
     static_assert(NW % 4 == 0, "NW must be a multiple of 4");
     const int lane = threadIdx.x & 63;
     int64_t r[TM];
@@ -153,10 +281,19 @@ __device__ __forceinline__ void wave_tile_body(uint16_t *C, int64_t ldc, const u
         r[t] = live[t] ? lane + 64 * t : 0;
     }
     u16x2 acc[TM][NW];
+    // the uint8 side: only the mode and each lane's row pointer stay live
+    // across the inner loop
+    const int m8 = __builtin_amdgcn_readfirstlane(c8.mode);
+    uint8_t *row8[TM];
+#pragma unroll
+    for (int t = 0; t < TM; t++) row8[t] = m8 ? c8.p + r[t] * c8.ld : nullptr;
 #pragma unroll
     for (int t = 0; t < TM; t++) {
         if (accumulate) {
-            row_load<NW, FULLC>(acc[t], C + r[t] * ldc, ncols);
+            if (m8 & kC8In)
+                row_load8<NW, FULLC>(acc[t], row8[t], ncols, m8 & kC8Neg);
+            else
+                row_load<NW, FULLC>(acc[t], C + r[t] * ldc, ncols);
         } else {
 #pragma unroll
             for (int w = 0; w < NW; w++) acc[t][w] = u16x2{0, 0};
@@ -302,23 +439,27 @@ __device__ __forceinline__ void wave_tile_body(uint16_t *C, int64_t ldc, const u
 
     if (sync_before_store) __syncthreads();
 #pragma unroll
-    for (int t = 0; t < TM; t++)
-        if (live[t]) row_store<NW, FULLC>(acc[t], C + r[t] * ldc, ncols);
+    for (int t = 0; t < TM; t++) {
+        if (!live[t]) continue;
+        if (!(m8 & kNo16)) row_store<NW, FULLC>(acc[t], C + r[t] * ldc, ncols);
+        if (m8 & kC8Out) row_store8<NW, FULLC>(acc[t], row8[t], ncols, m8 & kC8Neg);
+    }
 }
 
 // The 8-column fallback of wave_tile below.
 template <int TM, bool S8>
 __device__ __forceinline__ void wave_tile_narrow(uint16_t *C, int64_t ldc, const uint16_t *A,
                                                  int64_t lda, const uint16_t *B, int64_t ldb,
-                                                 int nrows, int ncols, int K, bool accumulate) {
+                                                 int nrows, int ncols, int K, bool accumulate,
+                                                 C8 c8 = C8{nullptr, 0, 0}) {
     for (int c = 0; c < ncols; c += 8) {
         const int nc = min(8, ncols - c);
         if (nc == 8)
             wave_tile_body<TM, 4, S8, true>(C + c, ldc, A, lda, B + c, ldb, nrows, 8, K,
-                                            accumulate, false);
+                                            accumulate, false, c8.at(0, c));
         else
             wave_tile_body<TM, 4, S8, false>(C + c, ldc, A, lda, B + c, ldb, nrows, nc, K,
-                                             accumulate, false);
+                                             accumulate, false, c8.at(0, c));
     }
 }
 
@@ -337,7 +478,7 @@ template <int TM, int NW, bool S8, bool GROUPB = !S8>
 __device__ __forceinline__ void wave_tile(uint16_t *C, int64_t ldc, const uint16_t *A, int64_t lda,
                                           const uint16_t *B, int64_t ldb, int nrows, int ncols,
                                           int64_t bspan, int K, bool accumulate,
-                                          bool sync_before_store) {
+                                          bool sync_before_store, C8 c8 = C8{nullptr, 0, 0}) {
     if (nrows <= 0 || ncols <= 0) {
         if (sync_before_store) __syncthreads();
         return;
@@ -345,15 +486,13 @@ __device__ __forceinline__ void wave_tile(uint16_t *C, int64_t ldc, const uint16
     if (bspan >= 2 * NW) {
         if (ncols >= 2 * NW)
             wave_tile_body<TM, NW, S8, true, GROUPB>(C, ldc, A, lda, B, ldb, nrows, 2 * NW, K,
-                                                     accumulate,
-                                             sync_before_store);
+                                                     accumulate, sync_before_store, c8);
         else
             wave_tile_body<TM, NW, S8, false, GROUPB>(C, ldc, A, lda, B, ldb, nrows, ncols, K,
-                                                      accumulate,
-                                              sync_before_store);
+                                                      accumulate, sync_before_store, c8);
         return;
     }
-    wave_tile_narrow<TM, S8>(C, ldc, A, lda, B, ldb, nrows, ncols, K, accumulate);
+    wave_tile_narrow<TM, S8>(C, ldc, A, lda, B, ldb, nrows, ncols, K, accumulate, c8);
     if (sync_before_store) __syncthreads();
 }
 
@@ -373,21 +512,47 @@ __device__ __forceinline__ void wave_tile(uint16_t *C, int64_t ldc, const uint16
 // primed row and column.  Two LDS buffer sets alternate, so that publishing
 // the next pair cannot overwrite what a slower thread still reads.  Entries
 // outside bs x bs are held as 0, the additive zero, and stay 0.
-// lds_row: 2 x 2 x 64 words, lds_col: 2 x 128 words.
+// lds_row: 2 x 2 x 64 words, lds_col: 2 x 128 words.  c8: the tile's uint8
+// side (read in place of T with kC8In, written with kC8Out).
 // ---------------------------------------------------------------------------
 template <bool S8>
 __device__ __forceinline__ void tile_closure(uint16_t *T, int64_t ld, int bs, uint32_t *lds_row,
-                                             uint32_t *lds_col) {
+                                             uint32_t *lds_col, C8 c8 = C8{nullptr, 0, 0}) {
     const int t = threadIdx.x;
     const int tx = t & 15, ty = t >> 4;
     u16x2 acc[8][4];
     const int c0 = 8 * tx;
+    const bool neg8 = c8.mode & kC8Neg;
 #pragma unroll
     for (int i = 0; i < 8; i++) {
         const int row = 8 * ty + i;
         if (row < bs && c0 < bs) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(T + (int64_t)row * ld + c0);
-            uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+            uint32_t w4[4];
+            if (c8.mode & kC8In) {
+                // uint8 side: the 8 bytes at once when all lie inside the
+                // tile, else entry by entry (the rest read as 0)
+                const uint8_t *src = c8.p + (int64_t)row * c8.ld + c0;
+                if (c0 + 8 <= bs) {
+                    const uint2 v = *reinterpret_cast<const uint2 *>(src);
+                    widen4(neg8 ? ~v.x : v.x, w4[0], w4[1]);
+                    widen4(neg8 ? ~v.y : v.y, w4[2], w4[3]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; c++) {
+                        const int j = c0 + 2 * c;
+                        const uint32_t lo = j < bs ? u8_to_work((uint8_t)(neg8 ? ~src[2 * c] : src[2 * c])) : 0u;
+                        const uint32_t hi =
+                            j + 1 < bs ? u8_to_work((uint8_t)(neg8 ? ~src[2 * c + 1] : src[2 * c + 1])) : 0u;
+                        w4[c] = lo | (hi << 16);
+                    }
+                }
+            } else {
+                const uint4 v = *reinterpret_cast<const uint4 *>(T + (int64_t)row * ld + c0);
+                w4[0] = v.x;
+                w4[1] = v.y;
+                w4[2] = v.z;
+                w4[3] = v.w;
+            }
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 u16x2 p = as_pair(w4[c]);
@@ -458,6 +623,22 @@ __device__ __forceinline__ void tile_closure(uint16_t *T, int64_t ld, int bs, ui
     for (int i = 0; i < 8; i++) {
         const int row = 8 * ty + i;
         if (row >= bs || c0 >= bs) continue;
+        if (c8.mode & kC8Out) {
+            uint8_t *d8 = c8.p + (int64_t)row * c8.ld + c0;
+            if (c0 + 8 <= bs) {
+                uint32_t x = narrow4(as_word(acc[i][0]), as_word(acc[i][1]));
+                uint32_t y = narrow4(as_word(acc[i][2]), as_word(acc[i][3]));
+                *reinterpret_cast<uint2 *>(d8) = uint2{neg8 ? ~x : x, neg8 ? ~y : y};
+            } else {
+                const uint8_t m = neg8 ? 0xFF : 0;
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    if (c0 + 2 * c < bs) d8[2 * c] = (uint8_t)(work_to_u8(acc[i][c].x) ^ m);
+                    if (c0 + 2 * c + 1 < bs) d8[2 * c + 1] = (uint8_t)(work_to_u8(acc[i][c].y) ^ m);
+                }
+            }
+        }
+        if (c8.mode & kNo16) continue;
         uint16_t *dst = T + (int64_t)row * ld + c0;
         if (c0 + 8 <= bs) {
             uint4 v;
@@ -496,11 +677,18 @@ __host__ __device__ inline void panel_wgs(int64_t D, int k0, int bs, int *n_roww
 // outside the pivot block times the four 32-column chunks of the pivot block.
 // Every panel tile is read and written by one workgroup only, and a barrier
 // separates its reads from its writes.
+//
+// c8 (the whole matrix's uint8 side, at entry (0, 0)): with kC8In each wave
+// first widens its own tile from there into T, and a barrier makes the
+// workgroup's tiles (which are also its operands: the row panel is its own B,
+// the column panel its own A) visible before any is read; kC8Out / kNo16
+// apply to the stores.
 template <bool S8>
 __device__ __forceinline__ void fw_panels_wg(uint16_t *T, int64_t ld, int D, int k0, int bs,
-                                             int n_rowwg, int bid) {
+                                             int n_rowwg, int bid, C8 c8 = C8{nullptr, 0, 0}) {
     constexpr int NW = kPanelNW, CW = 2 * NW;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+    const C8 tio{c8.p, c8.ld, c8.mode & ~kC8In};
     if (bid < n_rowwg) {
         const int kc0 = k0 / CW, kc1 = (k0 + bs + CW - 1) / CW;
         const int cc = 2 * bid + (wave >> 1);
@@ -510,9 +698,13 @@ __device__ __forceinline__ void fw_panels_wg(uint16_t *T, int64_t ld, int D, int
         const int nrows = min(64, bs - rofs);
         const int ncols = (int)min<int64_t>(CW, (int64_t)D - col0);
         const int64_t r0 = (int64_t)k0 + rofs;
+        if (c8.mode & kC8In) {
+            widen_block_wave(T + r0 * ld + col0, ld, c8.at(r0, col0), nrows, ncols);
+            __syncthreads();
+        }
         wave_tile<1, NW, S8>(T + r0 * ld + col0, ld, T + r0 * ld + k0, ld,
                              T + (int64_t)k0 * ld + col0, ld, nrows, ncols, ld - col0, bs, true,
-                             true);
+                             true, tio.at(r0, col0));
     } else {
         const int kr0 = k0 / 64, kr1 = (k0 + bs + 63) / 64;
         const int rc = bid - n_rowwg;
@@ -521,9 +713,13 @@ __device__ __forceinline__ void fw_panels_wg(uint16_t *T, int64_t ld, int D, int
         const int nrows = (int)min<int64_t>(64, (int64_t)D - row0);
         const int cofs = wave * CW;
         const int ncols = min(CW, bs - cofs);
+        if (c8.mode & kC8In) {
+            widen_block_wave(T + row0 * ld + k0 + cofs, ld, c8.at(row0, k0 + cofs), nrows, ncols);
+            __syncthreads();
+        }
         wave_tile<1, NW, S8>(T + row0 * ld + k0 + cofs, ld, T + row0 * ld + k0, ld,
                              T + (int64_t)k0 * ld + k0 + cofs, ld, nrows, ncols,
-                             ld - k0 - cofs, bs, true, true);
+                             ld - k0 - cofs, bs, true, true, tio.at(row0, k0 + cofs));
     }
 }
 
@@ -540,9 +736,11 @@ struct Rect {
 // launcher sends a partial last chunk to a FULL = false launch).
 // One wave's tile: selected column chunk csel, selected row chunk rsel
 // (wave-uniform).  Out-of-range indices do nothing.
+// c8: the whole matrix's uint8 side, at entry (0, 0) (mode 0: none).
 template <int TM, int NW, bool S8, bool FULL, bool GROUPB = !S8>
 __device__ __forceinline__ void fw_update_wave(uint16_t *T, int64_t ld, int D, int k0, int bs,
-                                               const Rect &q, int csel, int rsel) {
+                                               const Rect &q, int csel, int rsel,
+                                               C8 c8 = C8{nullptr, 0, 0}) {
     constexpr int CW = 2 * NW, RW = 64 * TM;
     int c = q.c_lo + csel;
     if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
@@ -554,12 +752,12 @@ __device__ __forceinline__ void fw_update_wave(uint16_t *T, int64_t ld, int D, i
     if (FULL) {
         wave_tile_body<TM, NW, S8, true, GROUPB>(T + row0 * ld + col0, ld, T + row0 * ld + k0,
                                                  ld, T + (int64_t)k0 * ld + col0, ld, nrows, CW,
-                                                 bs, true, false);
+                                                 bs, true, false, c8.at(row0, col0));
     } else {
         const int ncols = (int)min<int64_t>(CW, (int64_t)D - col0);
         wave_tile<TM, NW, S8, GROUPB>(T + row0 * ld + col0, ld, T + row0 * ld + k0, ld,
                                       T + (int64_t)k0 * ld + col0, ld, nrows, ncols, ld - col0, bs,
-                                      true, false);
+                                      true, false, c8.at(row0, col0));
     }
 }
 
