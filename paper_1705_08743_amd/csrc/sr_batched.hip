@@ -131,10 +131,27 @@ k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, in
     int c = csel;
     if (c >= q.c_ex0) c += q.c_ex1 - q.c_ex0;
     const dev::C8 c8 = round_c8<S8>(d, kb, io, true);
-    if ((c + 1) * CW <= d.D)
+    if ((c + 1) * CW <= d.D) {
         dev::fw_update_wave<1, NW, S8, true, true>(d.T, d.ld, d.D, k0, bs, q, csel, rsel, c8);
-    else
+    } else if (NW > 8) {
+        // the graph's last column chunk, D - c CW < CW columns: computed in
+        // 16-column pieces, so that at most 15 computed columns go unstored
+        // instead of up to CW - 1 (over configuration 4 the 64 x 64 tile
+        // computes 9.7 % more updates than the useful ones this way, 5.4 %)
+        int rc = rsel;
+        if (rc >= q.r_ex0) rc += q.r_ex1 - q.r_ex0;
+        const int64_t row0 = (int64_t)rc * 64, col0 = (int64_t)c * CW;
+        const int nrows = (int)min<int64_t>(64, (int64_t)d.D - row0);
+        const int ncols = (int)((int64_t)d.D - col0);
+        for (int j = 0; j < ncols; j += 16)
+            dev::wave_tile<1, 8, S8, true>(d.T + row0 * d.ld + col0 + j, d.ld,
+                                           d.T + row0 * d.ld + k0, d.ld,
+                                           d.T + (int64_t)k0 * d.ld + col0 + j, d.ld, nrows,
+                                           min(16, ncols - j), d.ld - col0 - j, bs, true, false,
+                                           c8.at(row0, col0 + j));
+    } else {
         dev::fw_update_wave<1, NW, S8, false, true>(d.T, d.ld, d.D, k0, bs, q, csel, rsel, c8);
+    }
 }
 
 // Workgroup (g, y) of the conversion launches below takes rows [32 y, 32 y +
