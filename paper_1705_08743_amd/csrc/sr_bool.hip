@@ -169,6 +169,76 @@ __device__ __forceinline__ void bool_tile(uint32_t *C, int64_t ldc, const uint32
     if (sync_before_store) __syncthreads();
 }
 
+// Products with few output tiles and a long inner dimension (configuration
+// 1's 256 x 256 product has four 64-row x 8-word tiles): a workgroup of KS
+// waves per tile, wave s taking a slice of the inner bits (a multiple of 8),
+// so that each wave runs KS times fewer dependent steps.  The waves' partial
+// rows are ORed together in LDS (exact in any order) and stored by the
+// workgroup: thread t < 64 * 8 owns word t % 8 of the tile's row t / 8.
+// Every B row segment read is 8 words from the tile's first word (the
+// launcher checks that the padded rows hold them).
+template <int KS>
+__global__ void __launch_bounds__(64 * KS)
+k_bool_mul_ksplit(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B,
+                  int64_t ldb, int64_t R, int K, int64_t nwords, int accumulate) {
+    constexpr int NWB = 8;
+    __shared__ uint32_t part[KS][64][NWB];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t row0 = (int64_t)blockIdx.y * 64, w0 = (int64_t)blockIdx.x * NWB;
+    const int nrows = (int)min<int64_t>(64, R - row0);
+    const int nw = (int)min<int64_t>(NWB, nwords - w0);
+    const int64_t r = lane < nrows ? lane : 0;
+    const uint32_t *arow = A + (row0 + r) * lda;
+    const int kc = ((K + KS - 1) / KS + 7) & ~7;
+    const int k0 = wave * kc, k1 = min(K, k0 + kc);
+    uint32_t acc[NWB];
+#pragma unroll
+    for (int w = 0; w < NWB; w++) acc[w] = 0u;
+    for (int k = k0; k < k1; k += 8) {
+        const uint32_t a = arow[k >> 5];
+        const uint32_t *b0 = B + (int64_t)k * ldb + w0;
+        if (k + 8 <= k1) {
+            // the group's eight rows of B loaded before its updates
+            uint32_t bg[8][NWB];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const kconst uint32_t *bp = (const kconst uint32_t *)(b0 + u * ldb);
+#pragma unroll
+                for (int w = 0; w < NWB; w++) bg[u][w] = bp[w];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(a, (k & 31) + u, 1);
+#pragma unroll
+                for (int w = 0; w < NWB; w++)
+                    acc[w] = __builtin_amdgcn_bitop3_b32(bg[u][w], m, acc[w], 0xEA);
+            }
+        } else {
+            for (int u = 0; k + u < k1; u++) {
+                const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(a, (k & 31) + u, 1);
+                const kconst uint32_t *bp = (const kconst uint32_t *)(b0 + u * ldb);
+#pragma unroll
+                for (int w = 0; w < NWB; w++)
+                    acc[w] = __builtin_amdgcn_bitop3_b32(bp[w], m, acc[w], 0xEA);
+            }
+        }
+    }
+    reinterpret_cast<uint4 *>(part[wave][lane])[0] = uint4{acc[0], acc[1], acc[2], acc[3]};
+    reinterpret_cast<uint4 *>(part[wave][lane])[1] = uint4{acc[4], acc[5], acc[6], acc[7]};
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t >= 64 * NWB) return;
+    const int row = t / NWB, w = t % NWB;
+    uint32_t v = 0;
+#pragma unroll
+    for (int q = 0; q < KS; q++) v |= part[q][row][w];
+    if (row < nrows && w < nw) {
+        uint32_t *c = C + (row0 + row) * ldc + w0 + w;
+        *c = accumulate ? (*c | v) : v;
+    }
+}
+
 template <int NWB>
 __global__ void __launch_bounds__(256)
 k_bool_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint32_t *B, int64_t ldb,
@@ -875,6 +945,18 @@ hipError_t launch_bool_mul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t 
     const uint32_t *a = reinterpret_cast<const uint32_t *>(A);
     const uint32_t *b = reinterpret_cast<const uint32_t *>(B);
     const int64_t nwords = (N + 31) / 32;
+    // few 64-row x 8-word output tiles and a long inner dimension: the
+    // inner bits split over sixteen waves per tile (configuration 1's
+    // product: one workgroup of 256 x 256 bits, 13.8 us, against four of
+    // sixteen waves)
+    const int64_t tiles8 = ((R + 63) / 64) * ((nwords + 7) / 8);
+    if (path != kBoolPathM4r && tiles8 <= 64 && K >= 128 && K <= INT32_MAX &&
+        2 * ldb >= (nwords + 7) / 8 * 8) {
+        const dim3 grid((unsigned)((nwords + 7) / 8), (unsigned)((R + 63) / 64));
+        hipLaunchKernelGGL(k_bool_mul_ksplit<16>, grid, dim3(1024), 0, stream, c, 2 * ldc, a,
+                           2 * lda, b, 2 * ldb, R, (int)K, nwords, accumulate ? 1 : 0);
+        return hipGetLastError();
+    }
     int nwb = 32;
     while (nwb > 8 && ((R + 63) / 64) * ((nwords + nwb - 1) / nwb) < 4096) nwb >>= 1;
     switch (nwb) {

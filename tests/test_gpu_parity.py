@@ -235,7 +235,10 @@ def test_closure_equals_repeated_squaring_on_gpu():
 # Boolean
 # ---------------------------------------------------------------------------
 BOOL_SHAPES = [(1, 1, 1), (5, 70, 3), (64, 64, 64), (100, 200, 300), (257, 33, 1000),
-               (300, 1100, 129)]
+               (300, 1100, 129),
+               # few output tiles, long inner dimension (the inner bits split
+               # over the waves of a workgroup): whole and ragged slices
+               (256, 256, 256), (4096, 300, 256), (70, 4000, 64), (33, 129, 512)]
 
 
 @pytest.mark.parametrize("R,K,N", BOOL_SHAPES)
