@@ -252,84 +252,137 @@ k_bool_mul(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda, const uint3
                          ldb - w0, K, accumulate != 0, false);
 }
 
-// Warshall step k = 64P + 32h + b on the calling wave's 64 rows (row k is in
-// lane 32h + b): rows with bit k set OR in row k, read with v_readlane.
-template <int P>
-__device__ __forceinline__ void pivot_step(uint32_t (&r)[8], int h, int b) {
+// Warshall step k = 64P + 32h + b of the pivot-tile closure, on the two
+// words (d0, d1) of the calling wave's 64 rows that hold the columns of block
+// P (row k is in lane 32h + b, read with v_readlane): rows with bit k set OR
+// in those two words of row k.
+__device__ __forceinline__ void diag_step(uint32_t &d0, uint32_t &d1, int h, int b) {
     const int src = 32 * h + b;
-    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(r[2 * P + h], b, 1);
-    uint32_t rk[8];
-#pragma unroll
-    for (int w = 0; w < 8; w++) rk[w] = __builtin_amdgcn_readlane(r[w], src);
-#pragma unroll
-    for (int w = 0; w < 8; w++) r[w] = __builtin_amdgcn_bitop3_b32(rk[w], m, r[w], 0xEA);
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(h ? d1 : d0, b, 1);
+    const uint32_t x0 = __builtin_amdgcn_readlane(d0, src);
+    const uint32_t x1 = __builtin_amdgcn_readlane(d1, src);
+    d0 = __builtin_amdgcn_bitop3_b32(x0, m, d0, 0xEA);
+    d1 = __builtin_amdgcn_bitop3_b32(x1, m, d1, 0xEA);
 }
 
-// One 64-pivot phase of the pivot-tile closure (see k_bool_fw_pivot).  P is
-// the phase, so the words holding the phase's pivot bits are registers known
-// at compile time.
+// LDS of the pivot-tile closure: block P's rows before the phase (orig), its
+// 64 x 64 diagonal block closed (cw), and its rows after the phase (fin, two
+// buffers used by alternate phases).
+struct PivotLds {
+    uint32_t orig[64][8];
+    uint32_t fin[2][64][8];
+    uint32_t cw[64][2];
+};
+
+// One 64-pivot phase of the pivot-tile closure (see k_bool_fw_pivot); P is
+// the phase, so the words holding its pivot bits are registers known at
+// compile time.  For the rows i of block P, Warshall's steps over the pivots
+// k of the block give T'_ij = T_ij | OR_k C_ik & T_kj, with C the closure of
+// the block's 64 x 64 diagonal block (paths whose inner vertices lie in the
+// block) and T the rows before the phase: so only C is computed step by step
+// (two words per row), and the other six words are that product.  The rows
+// of the other blocks then take T'_ij = T_ij | OR_k T_ik & T'_kj (k in the
+// block, T_ik before the phase), the block's final rows applied once each in
+// any order.
+//   1. wave P publishes its rows (orig) and closes its two diagonal words
+//      step by step (5 instructions per step instead of 17 for all eight
+//      words), then publishes them (cw, and as the diagonal words of fin);
+//   2. after a barrier, wave q != P forms words 2q and 2q + 1 of block P's
+//      rows as the product above (lane = row, row k of orig read by all lanes
+//      at one address);
+//   3. after a barrier, wave P takes its rows from fin and every other wave
+//      applies fin to its own rows.
+// Wave P + 1 rewrites orig and cw in the next phase only after passing this
+// phase's second barrier, when every wave has finished reading them (step 3
+// reads neither).  fin alternates between two buffers: the next phase writes
+// the other one while slower waves may still read this one in step 3, and the
+// phase after it writes this one only once every wave has passed the next
+// phase's barriers, i.e. has finished step 3 here.
 template <int P>
 __device__ __forceinline__ void pivot_phase(uint32_t (&r)[8], int wave, int lane, int bs,
-                                            uint4 (*pub)[64][2]) {
+                                            PivotLds &L) {
     const int kn = min(64, bs - 64 * P);
     if (kn <= 0) return;  // bs is uniform over the workgroup
-    uint4 (*buf)[2] = pub[P & 1];
+    uint32_t (*fin)[8] = L.fin[P & 1];
     if (wave == P) {
-        // Warshall steps k in [64P, 64P + kn) on this wave's rows; row k is
-        // lane k - 64P's registers.  A full half of 32 steps is unrolled
-        // (26 -> 19 us per pivot tile: the readlanes of a step then issue as
-        // soon as its words are ready, with no loop overhead between steps).
+        reinterpret_cast<uint4 *>(L.orig[lane])[0] = uint4{r[0], r[1], r[2], r[3]};
+        reinterpret_cast<uint4 *>(L.orig[lane])[1] = uint4{r[4], r[5], r[6], r[7]};
+        // the steps of a full half of 32 unrolled: the lane of row k is then
+        // a constant, and a step's readlanes issue as soon as its words are
+        // ready
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const int n = min(32, kn - 32 * h);
             if (n == 32) {
 #pragma unroll
-                for (int b = 0; b < 32; b++) pivot_step<P>(r, h, b);
+                for (int b = 0; b < 32; b++) diag_step(r[2 * P], r[2 * P + 1], h, b);
             } else {
-                for (int b = 0; b < n; b++) pivot_step<P>(r, h, b);
+                for (int b = 0; b < n; b++) diag_step(r[2 * P], r[2 * P + 1], h, b);
             }
         }
-        buf[lane][0] = uint4{r[0], r[1], r[2], r[3]};
-        buf[lane][1] = uint4{r[4], r[5], r[6], r[7]};
+        L.cw[lane][0] = r[2 * P];
+        L.cw[lane][1] = r[2 * P + 1];
+        fin[lane][2 * P] = r[2 * P];
+        fin[lane][2 * P + 1] = r[2 * P + 1];
     }
     __syncthreads();
     if (wave != P) {
-        // the published rows are closed over this phase's pivots, so each
-        // row k is applied once, in any order
+        const uint32_t c0 = L.cw[lane][0], c1 = L.cw[lane][1];
+        uint32_t a0 = L.orig[lane][2 * wave], a1 = L.orig[lane][2 * wave + 1];
+        const auto step = [&](uint32_t c, int k) __attribute__((always_inline)) {
+            const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(c, k & 31, 1);
+            const uint2 x = *reinterpret_cast<const uint2 *>(&L.orig[k][2 * wave]);
+            a0 = __builtin_amdgcn_bitop3_b32(x.x, m, a0, 0xEA);
+            a1 = __builtin_amdgcn_bitop3_b32(x.y, m, a1, 0xEA);
+        };
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const int n = min(32, kn - 32 * h);
-            const uint32_t a = r[2 * P + h];
-            for (int b = 0; b < n; b++) {
-                const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(a, b, 1);
-                const uint4 p0 = buf[32 * h + b][0], p1 = buf[32 * h + b][1];
-                r[0] = __builtin_amdgcn_bitop3_b32(p0.x, m, r[0], 0xEA);
-                r[1] = __builtin_amdgcn_bitop3_b32(p0.y, m, r[1], 0xEA);
-                r[2] = __builtin_amdgcn_bitop3_b32(p0.z, m, r[2], 0xEA);
-                r[3] = __builtin_amdgcn_bitop3_b32(p0.w, m, r[3], 0xEA);
-                r[4] = __builtin_amdgcn_bitop3_b32(p1.x, m, r[4], 0xEA);
-                r[5] = __builtin_amdgcn_bitop3_b32(p1.y, m, r[5], 0xEA);
-                r[6] = __builtin_amdgcn_bitop3_b32(p1.z, m, r[6], 0xEA);
-                r[7] = __builtin_amdgcn_bitop3_b32(p1.w, m, r[7], 0xEA);
-            }
+            const uint32_t c = h ? c1 : c0;
+            for (int b = 0; b < n; b++) step(c, 32 * h + b);
+        }
+        fin[lane][2 * wave] = a0;
+        fin[lane][2 * wave + 1] = a1;
+    }
+    __syncthreads();
+    if (wave == P) {
+        const uint4 f0 = reinterpret_cast<const uint4 *>(fin[lane])[0];
+        const uint4 f1 = reinterpret_cast<const uint4 *>(fin[lane])[1];
+        r[0] = f0.x, r[1] = f0.y, r[2] = f0.z, r[3] = f0.w;
+        r[4] = f1.x, r[5] = f1.y, r[6] = f1.z, r[7] = f1.w;
+    } else {
+        // the masks are this row's bits of block P as they were before the
+        // phase
+        const uint32_t a0 = r[2 * P], a1 = r[2 * P + 1];
+        const auto step = [&](uint32_t a, int k) __attribute__((always_inline)) {
+            const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe(a, k & 31, 1);
+            const uint4 p0 = reinterpret_cast<const uint4 *>(fin[k])[0];
+            const uint4 p1 = reinterpret_cast<const uint4 *>(fin[k])[1];
+            r[0] = __builtin_amdgcn_bitop3_b32(p0.x, m, r[0], 0xEA);
+            r[1] = __builtin_amdgcn_bitop3_b32(p0.y, m, r[1], 0xEA);
+            r[2] = __builtin_amdgcn_bitop3_b32(p0.z, m, r[2], 0xEA);
+            r[3] = __builtin_amdgcn_bitop3_b32(p0.w, m, r[3], 0xEA);
+            r[4] = __builtin_amdgcn_bitop3_b32(p1.x, m, r[4], 0xEA);
+            r[5] = __builtin_amdgcn_bitop3_b32(p1.y, m, r[5], 0xEA);
+            r[6] = __builtin_amdgcn_bitop3_b32(p1.z, m, r[6], 0xEA);
+            r[7] = __builtin_amdgcn_bitop3_b32(p1.w, m, r[7], 0xEA);
+        };
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int n = min(32, kn - 32 * h);
+            const uint32_t a = h ? a1 : a0;
+            for (int b = 0; b < n; b++) step(a, 32 * h + b);
         }
     }
-    // No second barrier: the next phase publishes into the other buffer, and
-    // the phase after it writes this one only after every wave has passed the
-    // next phase's barrier, i.e. has finished reading here.
 }
 
 // Pivot tile closure (bs <= 256): thread t holds row t of the tile as 8 words,
-// wave p rows [64p, 64p + 64).  Warshall's loop blocked by 64 pivots: in
-// phase P, wave P takes the steps k in [64P, 64P + 64) on its own rows over
-// all columns, reading row k from its own lanes (no barrier per step), which
-// closes block P and its row panel; it publishes its rows in LDS, and after
-// one barrier every other wave ORs row k into each of its rows with bit k
-// set.  nwv: valid words of a tile row.
+// wave p rows [64p, 64p + 64); Warshall's loop in four phases of 64 pivots
+// (pivot_phase).  nwv: valid words of a tile row.
 __global__ void __launch_bounds__(256)
 k_bool_fw_pivot(uint32_t *T, int64_t ld, int64_t k0, int bs, int nwv, int prio) {
     if (prio) __builtin_amdgcn_s_setprio(2);
-    __shared__ uint4 pub[2][64][2];
+    __shared__ PivotLds lds;
     uint32_t *tile = T + k0 * ld + (k0 >> 5);
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform per wave
@@ -337,10 +390,10 @@ k_bool_fw_pivot(uint32_t *T, int64_t ld, int64_t k0, int bs, int nwv, int prio) 
     uint32_t r[8];
 #pragma unroll
     for (int j = 0; j < 8; j++) r[j] = (live && j < nwv) ? tile[(int64_t)t * ld + j] : 0u;
-    pivot_phase<0>(r, wave, lane, bs, pub);
-    pivot_phase<1>(r, wave, lane, bs, pub);
-    pivot_phase<2>(r, wave, lane, bs, pub);
-    pivot_phase<3>(r, wave, lane, bs, pub);
+    pivot_phase<0>(r, wave, lane, bs, lds);
+    pivot_phase<1>(r, wave, lane, bs, lds);
+    pivot_phase<2>(r, wave, lane, bs, lds);
+    pivot_phase<3>(r, wave, lane, bs, lds);
     if (live)
 #pragma unroll
         for (int j = 0; j < 8; j++)

@@ -299,6 +299,38 @@ def test_bool_closure(D):
     assert synthgen.padding_bits_clear(got, D)
 
 
+@pytest.mark.parametrize("case", ["cycle", "descending", "ascending", "dense"])
+@pytest.mark.parametrize("D", [64, 100, 130, 200, 256])
+def test_bool_closure_pivot_tile(D, case):
+    """Graphs of at most 256 vertices are one pivot tile: its four phases
+    (each block's diagonal closed step by step, its other words as a product,
+    the block applied to the other rows) on inputs whose paths cross every
+    phase in the order the phases resolve last ('descending'), first
+    ('ascending'), all ones ('cycle') and dense ones."""
+    gen = synthgen.generator(3400 + D + len(case))
+    if case == "cycle":
+        order = gen.permutation(D)
+        A = np.zeros((D, D), dtype=np.uint8)
+        A[order, np.roll(order, -1)] = 1
+    elif case == "descending":
+        A = rand_bits(D, D, gen, 0.3 / D)
+        A[np.arange(1, D), np.arange(D - 1)] = 1
+    elif case == "ascending":
+        A = rand_bits(D, D, gen, 0.3 / D)
+        A[np.arange(D - 1), np.arange(1, D)] = 1
+    else:
+        A = rand_bits(D, D, gen, 0.3)
+    ldw = synthgen.aligned_ld_words(D)
+    Aw = synthgen.pack_bits(A, ldw)
+    T = dev(sr.SR_BOOL, Aw, cols=D)
+    sr.closure(sr.SR_BOOL, T, D=D)
+    want = oracle.bool_closure_words(Aw, D)
+    nw = (D + 63) // 64
+    got = host(T)
+    assert np.array_equal(got[:, :nw], want[:, :nw])
+    assert synthgen.padding_bits_clear(got, D)
+
+
 @pytest.mark.parametrize("path", [0, sr.SR_BOOL_BITWISE, sr.SR_BOOL_M4R, sr.SR_BOOL_MFMA])
 @pytest.mark.parametrize("D", [769, 2100, 4100])
 def test_bool_closure_lookahead_and_serial(D, path):
