@@ -943,13 +943,14 @@ hipError_t update_m4r(uint32_t *T, int64_t ld, int64_t D, const BBlock &b, const
 constexpr int kUpdateMfma = -1;
 hipError_t update_b(uint32_t *T, int64_t ld, int64_t D, int64_t kb, const BRect &q, int nwb,
                     double units, hipStream_t st, bool critical = false,
-                    uint32_t *pt = nullptr) {
+                    uint32_t *pt = nullptr, bool transposed = false) {
     const BBlock b = bblock(D, kb);
     const int prio = critical ? crit_prio() : 0;
     const bool prof = prof_on();
-    hipError_t e;
+    hipError_t e = hipSuccess;
     if (nwb == kUpdateMfma) {
-        e = launch_bool_pivot_transpose(pt, T, ld, D, b.k0, b.bs, st);
+        // (transposed: pt already holds round kb's pivot rows)
+        if (!transposed) e = launch_bool_pivot_transpose(pt, T, ld, D, b.k0, b.bs, st);
         if (prof) prof_begin(st);
         if (e == hipSuccess) e = launch_bool_fw_update_mfma(T, ld, D, b.k0, q, pt, st);
         if (prof) prof_end(st, 0, 2, units);
@@ -1066,7 +1067,11 @@ hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool seri
     // fills the device, else the bit-sliced kernel
     const bool m4r = path == kBoolPathM4r || (path == kBoolPathAuto && D >= 8192);
     const int nwb = path == kBoolPathMfma ? kUpdateMfma : m4r ? 0 : bool_update_nwb(D);
-    uint32_t *pt = static_cast<uint32_t *>(work);
+    // the matrix-core update reads the round's pivot rows bit-transposed:
+    // two buffers, round kb's in buffer kb % 2 (see below)
+    uint32_t *const pt0 = static_cast<uint32_t *>(work);
+    uint32_t *const pt1 =
+        pt0 ? pt0 + bool_mfma_closure_work_bytes(D) / 2 / sizeof(uint32_t) : nullptr;
     hipError_t e = pivot_b(T, ld, D, 0, st);
     if (e != hipSuccess || nb == 1) return e;
     if ((e = panels_b(T, ld, D, 0, st)) != hipSuccess) return e;
@@ -1074,6 +1079,7 @@ hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool seri
     for (int64_t kb = 0; kb < nb; kb++) {
         const BBlock b = bblock(D, kb);
         const double bs = b.bs;
+        uint32_t *const pt = (kb & 1) ? pt1 : pt0;
         if (kb + 1 == nb || !aux) {
             if (aux && kb > 0) e = hipStreamWaitEvent(st, aux->ev_aux[(kb - 1) & 1], 0);
             const double rest = (double)D - bs;
@@ -1087,12 +1093,18 @@ hipError_t launch_bool_closure(uint64_t *T64, int64_t ld64, int64_t D, bool seri
         }
         const BBlock n = bblock(D, kb + 1);
         const double bs1 = n.bs, rest2 = (double)D - bs - bs1;
+        // the matrix-core update's transposed pivot rows of round kb on this
+        // stream, right after panels(kb) (the chain is the shorter side), into
+        // buffer kb % 2: B(kb - 1) may still read the other one, and round
+        // kb + 2 rewrites this one only after A(kb + 1), which waits for B(kb)
+        const bool pre = nwb == kUpdateMfma;
+        if (pre) e = launch_bool_pivot_transpose(pt, T, ld, D, b.k0, b.bs, st);
         // B(kb) on the second stream, after panels(kb), behind B(kb-1)
-        e = hipEventRecord(aux->ev_main, st);
+        if (e == hipSuccess) e = hipEventRecord(aux->ev_main, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(aux->stream, aux->ev_main, 0);
         if (e == hipSuccess)
             e = update_b(T, ld, D, kb, BRect{0, nrc, b.rl, n.rh, 0, b.wl, n.wh, nwd}, nwb,
-                         rest2 * rest2 * bs, aux->stream, false, pt);
+                         rest2 * rest2 * bs, aux->stream, false, pt, pre);
         if (e == hipSuccess) e = hipEventRecord(aux->ev_aux[kb & 1], aux->stream);
         // A(kb) writes row block kb+1, which B(kb-1) writes too
         if (e == hipSuccess && kb > 0) e = hipStreamWaitEvent(st, aux->ev_aux[(kb - 1) & 1], 0);

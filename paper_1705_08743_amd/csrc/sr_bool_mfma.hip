@@ -392,7 +392,9 @@ hipError_t launch_bool_mul_mfma(uint64_t *C, int64_t ldc, const uint64_t *A, int
 }
 
 size_t bool_mfma_closure_work_bytes(int64_t D) {
-    return (size_t)(((D + 31) / 32 + 4) * 32) * 32;  // PT rows for every column word, 8 words each
+    // two PT buffers (consecutive rounds), rows for every column word, 8
+    // words each
+    return 2 * (size_t)(((D + 31) / 32 + 4) * 32) * 32;
 }
 
 hipError_t launch_bool_pivot_transpose(uint32_t *PT, const uint32_t *T, int64_t ld, int64_t D,

@@ -126,8 +126,9 @@ hipError_t launch_bool_mul_mfma(uint64_t *C, int64_t ldc, const uint64_t *A, int
                                 const uint64_t *B, int64_t ldb, int64_t R, int64_t K, int64_t N,
                                 bool accumulate, void *work, hipStream_t stream);
 // The closure's bulk update on the matrix cores: PT := the transposed pivot
-// rows [k0, k0 + bs) of T (strides in 32-bit words; PT holds
-// bool_mfma_closure_work_bytes(D) bytes), then T_ij (|)= T_iK * T_Kj over q.
+// rows [k0, k0 + bs) of T (strides in 32-bit words; PT holds half of
+// bool_mfma_closure_work_bytes(D) bytes, the closure's working memory being
+// two such buffers), then T_ij (|)= T_iK * T_Kj over q.
 size_t bool_mfma_closure_work_bytes(int64_t D);
 hipError_t launch_bool_pivot_transpose(uint32_t *PT, const uint32_t *T, int64_t ld, int64_t D,
                                        int k0, int bs, hipStream_t stream);

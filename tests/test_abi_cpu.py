@@ -290,8 +290,9 @@ def test_closure_work_bytes(L):
     assert f(sr.SR_BOOL, 1024, 0) == 0
     assert f(sr.SR_BOOL, 16384, sr.SR_BOOL_M4R) == 0
     # large Boolean closures update on the matrix cores by default: room for
-    # the transposed pivot rows, 32 bytes per column (+ 4 words' worth)
-    assert f(sr.SR_BOOL, 16384, 0) == (16384 // 32 + 4) * 32 * 32
+    # the transposed pivot rows of two consecutive rounds, 32 bytes per
+    # column (+ 4 words' worth) each
+    assert f(sr.SR_BOOL, 16384, 0) == 2 * (16384 // 32 + 4) * 32 * 32
     assert f(U16, 600, 0) == 2 * 600 * 640 * 2 + 256                     # squaring
     assert f(U16, 2000, 0) == 2 * 512 * 512 * 2 + 256                    # big blocks
     assert f(U8, 8192, 0) == 8192 * 8192 * 2                             # binary16 copy
