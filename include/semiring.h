@@ -238,14 +238,17 @@ int closure_noalloc(int kind, void *T, int64_t ldt, int64_t D, unsigned flags, v
  * vertices is closed by the first pivot launch.  The descriptors and the
  * per-round work lists are built on the host and uploaded stream-ordered
  * (the call returns without waiting); uint8 batches use stream-ordered
- * 16-bit working copies (binary16 values); 32-bit batches run the 32-bit
+ * 16-bit working copies (binary16 values), into which the first round's
+ * launches widen the data and from which each graph's last-round launches
+ * narrow it back; 32-bit batches run the 32-bit
  * wave tiles of closure() with update tiles of 64 x 32 entries (their only
- * shape).  Boolean batches are closed as
+ * shape).  Boolean graphs of at most 1024 vertices are closed in place on
+ * their bit rows (Warshall's loop, one workgroup per graph); larger ones as
  * anti-distance matrices with S = 255 whose entries are 255 for a set bit
  * and 0 otherwise (Sec. III: a set bit stands for distance 0, the entry S,
  * a clear one for distance infinity, the entry 0, and with S = 1 the
  * anti-distance matrices are the Boolean ones; on {0, S} entries max and (x)
- * act as OR and AND), in the same binary16 working copies, 2 * D[g] *
+ * act as OR and AND), in binary16 working copies, 2 * D[g] *
  * round_up(D[g], 8) bytes per graph; bits past column D[g] - 1 must be zero
  * and stay so.  The rounds are three launches
  * each, which is what synchronizes the whole grid between phases.  The
@@ -267,8 +270,9 @@ int closure_batched(int kind, void *const *T, const int64_t *ldt, const int64_t 
  * does, builds the descriptors and per-round work lists with update tiles of
  * shape `tile` (SR_BATCH_TILE_*; SR_BATCH_TILE_AUTO: the autotuned shape for
  * batches of this class, else 64 x 32; any other value is SR_EINVAL),
- * allocates device memory for them -- and for uint8 and Boolean kinds the
- * 16-bit working copies, 2 * sum(D[g] * round_up(D[g], 8)) bytes -- with
+ * allocates device memory for them -- and for uint8 batches and Boolean
+ * graphs of more than 1024 vertices the 16-bit working copies, 2 * D[g] *
+ * round_up(D[g], 8) bytes per graph -- with
  * hipMalloc, uploads
  * them on `stream`, waits for the upload and stores the handle in *out
  * (NULL on error).  The three arrays are copied (the caller may free them);
