@@ -136,8 +136,9 @@ k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, in
     } else if (NW > 8) {
         // the graph's last column chunk, D - c CW < CW columns: computed in
         // 16-column pieces, so that at most 15 computed columns go unstored
-        // instead of up to CW - 1 (over configuration 4 the 64 x 64 tile
-        // computes 9.7 % more updates than the useful ones this way, 5.4 %)
+        // instead of up to CW - 1 (over configuration 4, 64 x 64 tiles with
+        // whole-width edges compute 9.7 % more updates than the useful ones,
+        // with 16-column edge pieces 5.4 %)
         int rc = rsel;
         if (rc >= q.r_ex0) rc += q.r_ex1 - q.r_ex0;
         const int64_t row0 = (int64_t)rc * 64, col0 = (int64_t)c * CW;

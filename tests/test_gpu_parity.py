@@ -685,6 +685,35 @@ def test_dist_add_is_min(kind):
     assert np.array_equal(host(C).astype(np.int64), np.minimum(A, B).astype(np.int64))
 
 
+@pytest.mark.parametrize("dense", [True, False])
+@pytest.mark.parametrize("kind", [sr.SR_ANTIDIST_U8, sr.SR_DISTANCE_U8])
+def test_closure_batched_u8_every_byte(kind, dense):
+    """uint8 batches are widened by the first round's launches and narrowed
+    by each graph's last-round launches: every byte value 0..255 on the way
+    in (dense uniform bytes) and a wide spread of values on the way out
+    (sparse uniform bytes), graphs of one to three rounds, against the
+    oracle."""
+    gen = synthgen.generator(7800 + kind + (10 if dense else 0))
+    S = S_OF[kind]
+    sizes = [1, 7, 64, 128, 129, 200, 300]
+    mats = []
+    for n in sizes:
+        if dense:
+            m = gen.integers(0, 256, size=(n, n)).astype(np.uint8)
+        else:
+            vals = gen.integers(0, 256, size=(n, n))
+            m = np.where(gen.random((n, n)) < min(0.5, 2.0 / n), vals,
+                         S if kind in DIST_KINDS else 0).astype(np.uint8)
+        mats.append(m)
+    if dense:
+        assert len(np.unique(np.concatenate([m.ravel() for m in mats]))) == 256
+    devs = [dev(kind, m) for m in mats]
+    sr.closure_batched(kind, devs)
+    for d, m in zip(devs, mats):
+        want = oracle.dist_closure(m, S) if kind in DIST_KINDS else oracle.ad_closure(m, S)
+        assert np.array_equal(host(d).astype(np.int64), want), m.shape
+
+
 @pytest.mark.parametrize("kind", AD_KINDS + DIST_KINDS)
 def test_closure_batched_dist_and_reflexive(kind):
     """Batches of distance matrices, and the reflexive flag, for all kinds."""
