@@ -63,6 +63,7 @@ TRAFFIC = {
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, in bytes
     "fw8192": {"src_hash": "f8d45de227bbaa9f", "bytes_per_launch": 4.974e8},   # 1.794e5 + 1.270e5 KiB
     "u8fw8192": {"src_hash": "f8d45de227bbaa9f", "bytes_per_launch": 4.841e8},  # 1.729e5 + 1.270e5 KiB
+    "dfw8192": {"src_hash": "f8d45de227bbaa9f", "bytes_per_launch": 4.970e8},  # 1.792e5 + 1.270e5 KiB
     "u32fw8192": {"src_hash": "c4166400949ed0ba", "bytes_per_launch": 7.185e8},  # 2.219e5 + 2.579e5 KiB
     # full update launches (matrix-core kernel, 4-bit operands) of the
     # serialized D = 16384 Boolean closure
