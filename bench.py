@@ -11,7 +11,8 @@ Other workloads (--workload): bool16384 (Boolean closure, D = 16384, mean
 out-degree 3 plus planted strongly connected blocks), boolmul16384 (Boolean
 product A * A of that matrix, word-parallel and int8 matrix-core paths),
 mul1024 (uint16 product of two 1024 x 1024 graphs), small (latencies of the
-configuration 1 and 2 calls), u8fw8192 (uint8 closure,
+Boolean 256-vertex product and closure and the uint16 1024-vertex product and
+closure), u8fw8192 (uint8 closure,
 distances in [1, 200]), dfw8192 (the headline input as a distance matrix,
 closed with min and saturating +), u32fw8192 (the headline distances in
 uint32 entries, S = 2^32 - 1), batched (4096 graphs, log-uniform sizes in
@@ -358,7 +359,7 @@ def run_bool(args, torch, sr, synthgen):
         sr.SR_BOOL, t, D=D, flags=sr.SR_SERIAL_PHASES))
     up = phases["update"]
     achieved = up["updates_per_launch"] / (up["avg_us"] * 1e-6) if up["avg_us"] > 0 else 0.0
-    # configuration 3 compares the bulk update's paths: bit-sliced words,
+    # the D = 16384 Boolean closure compares the bulk update's paths: bit-sliced words,
     # four-Russians tables, and the matrix cores (4-bit float and int8
     # operands); the whole closure (overlapped) and its update launches
     # (serialized phases) for each, every result equal to the default's
@@ -429,7 +430,7 @@ def run_bool(args, torch, sr, synthgen):
 
 
 def run_mul(args, torch, sr, synthgen):
-    """uint16 product of two 1024 x 1024 graphs (configuration 2)."""
+    """uint16 product of two 1024 x 1024 graphs (p = 0.05)."""
     import numpy as np
     import oracle
     D = 1024
@@ -504,13 +505,13 @@ def run_small(args, torch, sr, synthgen):
         res[name] = {"us_median": 1e3 * med, "us_min": 1e3 * ts[0], "updates": upd,
                      "updates_per_s": upd / (med * 1e-3)}
     torch.cuda.synchronize()
-    out = {"metric": "latency (us per call, median) of the configuration 1 and 2 calls",
+    out = {"metric": "latency (us per call, median) of the Boolean 256 and uint16 1024 product and closure calls",
            "value": res["u16_1024_closure"]["us_median"], "unit": "us", "n_gpus": 1,
            "steps": steps, "warmup": args.warmup,
            "ms_per_step": res["u16_1024_closure"]["us_median"] * 1e-3,
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
            "dtype": "u16+bits", "data": "synthetic",
-           "config": {"workload": "cfg1_bool256_and_cfg2_u16_1024_latency",
+           "config": {"workload": "bool256_and_u16_1024_latency",
                       "parallelism": "single_gpu"},
            "cases": res}
     if not args.no_cpu_baseline:
@@ -540,7 +541,7 @@ def run_small(args, torch, sr, synthgen):
 
 
 def run_boolmul(args, torch, sr, synthgen):
-    """Boolean product A * A of configuration 3 (D = 16384, bit-packed): the
+    """Boolean product A * A of the D = 16384 Boolean input (bit-packed): the
     default path (value), with the bit-sliced, four-Russians and matrix-core
     (4-bit float and int8 operands) paths reported beside it; every path's
     product equal, the default's against the oracle's whole product."""

@@ -136,9 +136,9 @@ k_batch_update(const BatchDesc *desc, const Item *items, int n_items, int kb, in
     } else if (NW > 8) {
         // the graph's last column chunk, D - c CW < CW columns: computed in
         // 16-column pieces, so that at most 15 computed columns go unstored
-        // instead of up to CW - 1 (over configuration 4, 64 x 64 tiles with
-        // whole-width edges compute 9.7 % more updates than the useful ones,
-        // with 16-column edge pieces 5.4 %)
+        // instead of up to CW - 1 (over 4096 graphs of 32 to 1024 vertices,
+        // log-uniform, 64 x 64 tiles with whole-width edges compute 9.7 % more
+        // updates than the useful ones, with 16-column edge pieces 5.4 %)
         int rc = rsel;
         if (rc >= q.r_ex0) rc += q.r_ex1 - q.r_ex0;
         const int64_t row0 = (int64_t)rc * 64, col0 = (int64_t)c * CW;
@@ -478,8 +478,9 @@ hipError_t launch_ad_closure_batched_resident(bool s8, const BatchPlan *plan, in
     // binary16 (S8 = true) working data
     using UpdateFn = void (*)(const BatchDesc *, const Item *, int, int, int, int, int);
     // XCD chunk of the update and panels launches (xcd_order; 0 = the plain
-    // order).  64 workgroups measured best for configuration 4 (uint16 16.6
-    // -> 15.8 ms, uint8 15.9 -> 14.3 ms; 4 / 16 / 256 in between); the
+    // order).  64 workgroups measured best for 4096 graphs of 32 to 1024
+    // vertices (uint16 16.6 -> 15.8 ms, uint8 15.9 -> 14.3 ms; 4 / 16 / 256
+    // in between); the
     // environment variables SR_BATCH_XCD and SR_BATCH_XCDP override them.
     static const int xmap = [] {
         const char *v = getenv("SR_BATCH_XCD");

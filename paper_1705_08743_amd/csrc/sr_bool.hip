@@ -83,8 +83,8 @@ __device__ __forceinline__ void bool_tile_body(uint32_t *C, int64_t ldc, const u
             for (int g = 0; g < 32; g += KU) {
                 const uint32_t *b0 = B + (int64_t)(k + g) * ldb;
                 // with GROUPB the KU rows are loaded before the first update
-                // (one wait per group: the product of configuration 1's
-                // 256-vertex graph 26 -> 23 us; the closures' update kernels,
+                // (one wait per group: the square of a sparse 256-vertex
+                // graph 26 -> 23 us; the closures' update kernels,
                 // with many waves in flight, do not gain and keep per-row loads)
                 uint32_t bg[GROUPB ? KU : 1][NWB];
                 if constexpr (GROUPB) {
@@ -169,8 +169,8 @@ __device__ __forceinline__ void bool_tile(uint32_t *C, int64_t ldc, const uint32
     if (sync_before_store) __syncthreads();
 }
 
-// Products with few output tiles and a long inner dimension (configuration
-// 1's 256 x 256 product has four 64-row x 8-word tiles): a workgroup of KS
+// Products with few output tiles and a long inner dimension (a 256 x 256 x
+// 256 product has four 64-row x 8-word tiles): a workgroup of KS
 // waves per tile, wave s taking a slice of the inner bits (a multiple of 8),
 // so that each wave runs KS times fewer dependent steps.  The waves' partial
 // rows are ORed together in LDS (exact in any order) and stored by the
@@ -1000,9 +1000,9 @@ hipError_t launch_bool_mul(uint64_t *C, int64_t ldc, const uint64_t *A, int64_t 
     const uint32_t *b = reinterpret_cast<const uint32_t *>(B);
     const int64_t nwords = (N + 31) / 32;
     // few 64-row x 8-word output tiles and a long inner dimension: the
-    // inner bits split over sixteen waves per tile (configuration 1's
-    // product: one workgroup of 256 x 256 bits, 13.8 us, against four of
-    // sixteen waves)
+    // inner bits split over sixteen waves per tile (256 x 256 x 256: one
+    // workgroup of four waves, 13.8 us, against four of sixteen waves,
+    // 3.6 us)
     const int64_t tiles8 = ((R + 63) / 64) * ((nwords + 7) / 8);
     if (path != kBoolPathM4r && tiles8 <= 64 && K >= 128 && K <= INT32_MAX &&
         2 * ldb >= (nwords + 7) / 8 * 8) {

@@ -239,8 +239,9 @@ def serving_trace(count: int, nlo: int = 64, nhi: int = 8192, seed: int = None):
 
 
 def serving_request(n: int, kind: str, seed: int):
-    """Input matrix of one serving request: Boolean as configuration 1
-    (p = 0.02) or uint16 anti-distance as configuration 2."""
+    """Input matrix of one serving request: Boolean as the 256-vertex
+    workload (p = 0.02) or uint16 anti-distance as the 1024-vertex one
+    (p = 0.05)."""
     gen = generator(seed)
     if kind == "bool":
         return bool_graph_packed(n, 0.02, gen, ld_words=aligned_ld_words(n))

@@ -118,7 +118,7 @@ def test_product_d8192():
 
 @pytest.fixture(scope="module")
 def cfg3():
-    """Configuration 3's input and its closure by the oracle's bit-packed
+    """The D = 16384 Boolean input and its closure by the oracle's bit-packed
     Warshall loop (computed once for the tests below)."""
     D = 16384
     W = synthgen.cfg_bool16384(D=D)
@@ -129,7 +129,7 @@ def cfg3():
                                        (sr.SR_BOOL_M4R, None), (sr.SR_BOOL_MFMA, "f4"),
                                        (sr.SR_BOOL_MFMA, "i8")])
 def test_bool_closure_config3(cfg3, flags, fmt, monkeypatch):
-    """Configuration 3: Boolean D = 16384, mean out-degree 3 plus planted
+    """Boolean D = 16384, mean out-degree 3 plus planted
     strongly connected blocks; every word against the oracle for the default
     bulk update and each forced one (bit-sliced, four-Russians tables, the
     matrix cores with 4-bit float and with int8 operands); padding bits stay
@@ -149,7 +149,7 @@ def test_bool_closure_config3(cfg3, flags, fmt, monkeypatch):
 @pytest.mark.parametrize("flags,fmt", [(0, None), (sr.SR_BOOL_BITWISE, None),
                                        (sr.SR_BOOL_MFMA, "f4"), (sr.SR_BOOL_MFMA, "i8")])
 def test_bool_product_config3(cfg3, flags, fmt, monkeypatch):
-    """Configuration 3's product A * A (D = 16384) on each path: every word
+    """The D = 16384 Boolean product A * A on each path: every word
     against the oracle's bit-packed multiplication loop."""
     if fmt:
         monkeypatch.setenv("SR_MFMA_FORMAT", fmt)
@@ -181,7 +181,7 @@ def test_bool_product_d8192():
 
 @pytest.mark.parametrize("dtype", [np.uint16, np.uint8])
 def test_batched_config4_all_graphs(dtype):
-    """Configuration 4: 4096 graphs of log-uniform sizes in [32, 1024],
+    """4096 graphs of log-uniform sizes in [32, 1024],
     closed by one call; every entry of every graph against the oracle."""
     kind = sr.SR_ANTIDIST_U16 if dtype == np.uint16 else sr.SR_ANTIDIST_U8
     S = 65535 if dtype == np.uint16 else 255

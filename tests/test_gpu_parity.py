@@ -130,7 +130,7 @@ def test_ad_mul_padding_untouched():
 
 
 def test_ad_mul_config2():
-    """Configuration 2: two 1024 x 1024 uint16 random digraphs, p = 0.05,
+    """Two 1024 x 1024 uint16 random digraphs, p = 0.05,
     distances in [1, 1000], 1% near 65535."""
     A = synthgen.cfg_antidist(D=1024, which=0)
     B = synthgen.cfg_antidist(D=1024, which=1)
@@ -188,7 +188,7 @@ def test_ad_closure_saturation_cycle():
 
 
 def test_ad_closure_config2():
-    """Configuration 2 closure: D = 1024 uint16 with heavy edges."""
+    """Closure of a D = 1024 uint16 random digraph with heavy edges."""
     A = synthgen.cfg_antidist(D=1024, which=0)[:, :1024]
     kind = sr.SR_ANTIDIST_U16
     T = dev(kind, A)
@@ -274,7 +274,7 @@ def test_bool_mul_accumulate():
 
 
 def test_bool_config1():
-    """Configuration 1: 256 x 256, p = 0.02: A * A and the closure."""
+    """Boolean 256 x 256, p = 0.02: A * A and the closure."""
     W = synthgen.cfg_bool256()
     A = dev(sr.SR_BOOL, W, cols=256)
     C = sr.empty(sr.SR_BOOL, 256, 256)
@@ -784,7 +784,7 @@ def _squaring_input(case, kind, D, gen):
     edge, one weight: the first squaring leaves P unchanged), 'path' (a
     directed path 0 -> 1 -> ... of small weights plus random heavier edges
     from higher to lower vertices: best paths of D - 1 edges, so no squaring
-    is skipped), 'random' (configuration 2's generator: stops part way)."""
+    is skipped), 'random' (the 1024-vertex p = 0.05 generator: stops part way)."""
     S = S_OF[kind]
     if case == "dense":
         A = np.full((D, D), S - 3, dtype=np.int64)

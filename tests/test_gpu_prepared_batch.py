@@ -250,7 +250,7 @@ def test_prepared_batch_autotune(kind):
 
 
 def test_prepared_batch_config4_sample():
-    """Configuration 4 (4096 graphs, log-uniform sizes in [32, 1024]) through
+    """4096 graphs (log-uniform sizes in [32, 1024]) through
     the prepared, graph-captured form: every graph equal to closure_batched,
     a sample against the oracle."""
     kind = sr.SR_ANTIDIST_U16
