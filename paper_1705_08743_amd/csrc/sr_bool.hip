@@ -461,16 +461,31 @@ k_bool_fw_pivot(uint32_t *T, int64_t ld, int64_t k0, int bs, int nwv, int prio) 
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform per wave
     const bool live = t < bs;
     uint32_t r[8];
+    // rows are 16-byte aligned (base and stride), and the tile starts at a
+    // multiple of 8 words: a whole row of 8 words moves as two 16-byte words
+    uint32_t *row = tile + (int64_t)t * ld;
+    if (live && nwv == 8) {
+        const uint4 v0 = reinterpret_cast<const uint4 *>(row)[0];
+        const uint4 v1 = reinterpret_cast<const uint4 *>(row)[1];
+        r[0] = v0.x, r[1] = v0.y, r[2] = v0.z, r[3] = v0.w;
+        r[4] = v1.x, r[5] = v1.y, r[6] = v1.z, r[7] = v1.w;
+    } else {
 #pragma unroll
-    for (int j = 0; j < 8; j++) r[j] = (live && j < nwv) ? tile[(int64_t)t * ld + j] : 0u;
+        for (int j = 0; j < 8; j++) r[j] = (live && j < nwv) ? row[j] : 0u;
+    }
     pivot_phase<0, PIPE>(r, wave, lane, bs, lds);
     pivot_phase<1, PIPE>(r, wave, lane, bs, lds);
     pivot_phase<2, PIPE>(r, wave, lane, bs, lds);
     pivot_phase<3, PIPE>(r, wave, lane, bs, lds);
-    if (live)
+    if (!live) return;
+    if (nwv == 8) {
+        reinterpret_cast<uint4 *>(row)[0] = uint4{r[0], r[1], r[2], r[3]};
+        reinterpret_cast<uint4 *>(row)[1] = uint4{r[4], r[5], r[6], r[7]};
+    } else {
 #pragma unroll
         for (int j = 0; j < 8; j++)
-            if (j < nwv) tile[(int64_t)t * ld + j] = r[j];
+            if (j < nwv) row[j] = r[j];
+    }
 }
 
 // An 8-word-wide tile with its B block staged in LDS: all 64 * 4 * KH threads
