@@ -336,6 +336,42 @@ def test_closure_batched_boolean(flags):
         assert torch.equal(t, s_), n
 
 
+@pytest.mark.parametrize("case", ["cycle", "descending", "ascending", "random"])
+def test_closure_batched_boolean_small_phases(case):
+    """Boolean graphs of at most 1024 vertices are closed in place, one
+    workgroup each: every size class (up to 64, 128, 256, 512, 768, 1024
+    vertices) with ragged sizes, on paths through all vertices in descending
+    order (the order Warshall's loop resolves last), ascending order, one
+    cycle (closure all ones) and random graphs; against the oracle."""
+    sizes = [1024, 1000, 769, 700, 513, 300, 257, 200, 129, 100, 65, 64, 33, 2]
+    gen = synthgen.generator(6300 + len(case))
+    from gpu_util import rand_bits
+    mats = []
+    for n in sizes:
+        if case == "cycle":
+            order = gen.permutation(n)
+            m = np.zeros((n, n), dtype=np.uint8)
+            m[order, np.roll(order, -1)] = 1
+        elif case == "descending":
+            m = rand_bits(n, n, gen, 0.3 / n)
+            m[np.arange(1, n), np.arange(n - 1)] = 1
+        elif case == "ascending":
+            m = rand_bits(n, n, gen, 0.3 / n)
+            m[np.arange(n - 1), np.arange(1, n)] = 1
+        else:
+            m = rand_bits(n, n, gen, 1.5 / n)
+        mats.append(m)
+    devs = []
+    for m in mats:
+        n = m.shape[0]
+        words = synthgen.pack_bits(m, synthgen.aligned_ld_words(n))
+        devs.append(sr.to_device(sr.SR_BOOL, words, cols=n)[:n])
+    sr.closure_batched(sr.SR_BOOL, devs, Ds=sizes)
+    torch.cuda.synchronize()
+    for t, m in zip(devs, mats):
+        assert np.array_equal(_bool_got(t, m.shape[0]), oracle.bool_closure(m)), m.shape[0]
+
+
 @pytest.mark.parametrize("tile", TILES)
 def test_prepared_batch_boolean(tile):
     """A prepared Boolean batch with each update-tile shape, run eagerly and
