@@ -627,7 +627,7 @@ def run_add(args, torch, sr, synthgen):
             "vs_baseline": None, "dtype": "u16", "data": "synthetic",
             "config": {"workload": "antidist_u16_add_8192", "bytes_per_call": nbytes,
                        "parallelism": "single_gpu"},
-            "roofline": {"bound": "hbm", "kernel": "k_ewise<2, EW_OR>", "achieved": gbs, "peak": 8000.0,
+            "roofline": {"bound": "hbm", "kernel": "k_ewise<2, EW_OR, NT=true>", "achieved": gbs, "peak": 8000.0,
                          "unit": "GB/s", "frac": gbs / 8000.0, "traffic": None}}
 
 

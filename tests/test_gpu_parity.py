@@ -675,6 +675,48 @@ def test_ewise_bool(N, op, name):
     assert synthgen.padding_bits_clear(got, N)
 
 
+# operands above 16 MiB take the streaming (nontemporal) form of the kernel;
+# ragged rows end in a partial 16-byte group
+STREAM_SHAPES = {sr.SR_ANTIDIST_U8: (4200, 4001), sr.SR_ANTIDIST_U16: (2900, 3001),
+                 sr.SR_ANTIDIST_U32: (2100, 2001), sr.SR_DISTANCE_U16: (2900, 3001)}
+
+
+@pytest.mark.parametrize("kind", list(STREAM_SHAPES))
+@pytest.mark.parametrize("op,name", [(sr.SR_EW_AND, "and"), (sr.SR_EW_OR, "or"),
+                                     (sr.SR_EW_XOR, "xor"), (sr.SR_EW_NOT, "not")])
+def test_ewise_streaming_sizes(kind, op, name):
+    gen = synthgen.generator(7700 + kind * 10 + op)
+    S = S_OF[kind]
+    R, N = STREAM_SHAPES[kind]
+    A = gen.integers(0, S + 1, size=(R, N)).astype(np_dtype(kind))
+    B = gen.integers(0, S + 1, size=(R, N)).astype(np_dtype(kind))
+    C = sr.empty(kind, R, N)
+    sr.semiring_ewise(kind, op, C, dev(kind, A), None if name == "not" else dev(kind, B))
+    want = oracle.ewise(name, A, None if name == "not" else B, S)
+    assert np.array_equal(host(C).astype(np.int64), want)
+    Ad = dev(kind, A)
+    sr.semiring_ewise(kind, op, Ad, Ad, None if name == "not" else dev(kind, B))
+    assert np.array_equal(host(Ad).astype(np.int64), want)
+
+
+@pytest.mark.parametrize("op,name", [(sr.SR_EW_AND, "and"), (sr.SR_EW_OR, "or"),
+                                     (sr.SR_EW_XOR, "xor"), (sr.SR_EW_NOT, "not")])
+def test_ewise_bool_streaming_size(op, name):
+    gen = synthgen.generator(7800 + op)
+    R, N = 1040, 130001          # 2032 words a row, 16 MiB and more per operand
+    ld = synthgen.aligned_ld_words(N)
+    Aw = synthgen.pack_bits(rand_bits(R, N, gen, 0.5), ld)
+    Bw = synthgen.pack_bits(rand_bits(R, N, gen, 0.5), ld)
+    C = sr.empty(sr.SR_BOOL, R, N)
+    sr.semiring_ewise(sr.SR_BOOL, op, C, dev(sr.SR_BOOL, Aw, cols=N),
+                      None if name == "not" else dev(sr.SR_BOOL, Bw, cols=N), N=N)
+    want = oracle.ewise_words(name, Aw, N, None if name == "not" else Bw)
+    nw = (N + 63) // 64
+    got = host(C)
+    assert np.array_equal(got[:, :nw], want[:, :nw])
+    assert synthgen.padding_bits_clear(got, N)
+
+
 @pytest.mark.parametrize("kind", DIST_KINDS)
 def test_dist_add_is_min(kind):
     gen = synthgen.generator(7600 + kind)
