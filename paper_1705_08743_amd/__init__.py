@@ -168,9 +168,15 @@ def _check(rc):
         raise SemiringError(rc, lib().sr_last_error().decode())
 
 
+_TORCH = None
+
+
 def _torch():
-    import torch
-    return torch
+    global _TORCH
+    if _TORCH is None:
+        import torch
+        _TORCH = torch
+    return _TORCH
 
 
 _DTYPE_KIND = None
@@ -191,24 +197,38 @@ def kind_of(t):
 
 
 def _mat(t, name):
+    """(data pointer or None, row stride, rows, cols) of a 2-D device tensor
+    with unit column stride.  Few tensor attribute reads: at the smallest
+    sizes this marshalling is a visible part of a call's latency."""
     if t is None:
         return None, 0, 0, 0
-    if t.dim() != 2:
+    shape, stride = t.shape, t.stride()
+    if len(shape) != 2:
         raise ValueError("%s must be a 2-D tensor" % name)
-    if t.numel() and t.stride(1) != 1:
+    r, c = shape
+    s0, s1 = stride
+    ld = s0 if r > 1 else max(s0, c)
+    if not (r and c):
+        return None, ld, r, c
+    if s1 != 1:
         raise ValueError("%s must have unit column stride" % name)
-    if t.numel() and not t.is_cuda:
+    if not t.is_cuda:
         raise ValueError("%s must be a device tensor" % name)
-    ld = t.stride(0) if t.shape[0] > 1 else max(t.stride(0), t.shape[1])
-    return t.data_ptr() if t.numel() else None, ld, t.shape[0], t.shape[1]
+    return t.data_ptr(), ld, r, c
 
 
 def _stream(stream):
+    """The HIP stream handle (an int; 0 is the null stream): torch's current
+    stream of the current device when stream is None."""
     if stream is None:
-        return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+        C = _torch()._C
+        raw = getattr(C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:
+            return raw(C._cuda_getDevice())
+        return _torch().cuda.current_stream().cuda_stream
     if isinstance(stream, int):
-        return ctypes.c_void_p(stream)
-    return ctypes.c_void_p(stream.cuda_stream)
+        return stream
+    return stream.cuda_stream
 
 
 def semiring_mul(kind, C, A, B, R=None, K=None, N=None, flags=0, stream=None):
