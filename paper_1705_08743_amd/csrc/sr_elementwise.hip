@@ -5,7 +5,7 @@
 // on Boolean words (AND, OR, XOR, NOT with the padding bits kept zero).  One
 // thread per 16-byte group of a row; HBM-bound.  Operands too large to stay
 // in the caches are read and written with the nontemporal hint (the
-// streaming form: 76 -> 60 us at 8192 x 8192 uint16, 5.3 -> 6.7 TB/s); small
+// streaming form: 76.9 -> 62.0 us at 8192 x 8192 uint16, 5.2 -> 6.5 TB/s); small
 // ones keep the default policy, since the next kernel usually reads the
 // result.  Also the diagonal write of the reflexive closure I (+) T (eq. rtc).
 #include <hip/hip_runtime.h>
