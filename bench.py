@@ -608,11 +608,15 @@ def run_boolmul(args, torch, sr, synthgen):
 def run_add(args, torch, sr, synthgen):
     """Entrywise (+) of two 8192 x 8192 uint16 matrices (reads 256 MiB,
     writes 128 MiB): the HBM-bound step, and the streaming kernel of known
-    size that calibrates the FETCH_SIZE / WRITE_SIZE counters."""
+    size that calibrates the FETCH_SIZE / WRITE_SIZE counters.  The whole
+    result is compared with the oracle's entrywise maximum."""
+    import numpy as np
     D = 8192
     kind = sr.SR_ANTIDIST_U16
-    A = sr.to_device(kind, synthgen.cfg_antidist(D=D, which=0))
-    B = sr.to_device(kind, synthgen.cfg_antidist(D=D, which=1))
+    hA = synthgen.cfg_antidist(D=D, which=0)
+    hB = synthgen.cfg_antidist(D=D, which=1)
+    A = sr.to_device(kind, hA)
+    B = sr.to_device(kind, hB)
     C = sr.empty(kind, D, D)
     f = lambda i: sr.semiring_add(kind, C, A, B)
     for _ in range(args.warmup):
@@ -621,14 +625,29 @@ def run_add(args, torch, sr, synthgen):
     ms = timed(torch, f, steps)
     nbytes = 3 * D * D * 2
     gbs = nbytes / (ms * 1e-3) / 1e9
-    return {"metric": "HBM GB/s of semiring_add (entrywise max) 8192x8192 uint16",
-            "value": gbs, "unit": "GB/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
-            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "u16", "data": "synthetic",
-            "config": {"workload": "antidist_u16_add_8192", "bytes_per_call": nbytes,
-                       "parallelism": "single_gpu"},
-            "roofline": {"bound": "hbm", "kernel": "k_ewise<2, EW_OR, NT=true>", "achieved": gbs, "peak": 8000.0,
-                         "unit": "GB/s", "frac": gbs / 8000.0, "traffic": None}}
+    out = {"metric": "HBM GB/s of semiring_add (entrywise max) 8192x8192 uint16",
+           "value": gbs, "unit": "GB/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u16", "data": "synthetic",
+           "config": {"workload": "antidist_u16_add_8192", "bytes_per_call": nbytes,
+                      "parallelism": "single_gpu"},
+           "roofline": {"bound": "hbm", "kernel": "k_ewise<2, EW_OR, NT=true>", "achieved": gbs, "peak": 8000.0,
+                        "unit": "GB/s", "frac": gbs / 8000.0, "traffic": None}}
+    if not args.no_cpu_baseline or not args.no_parity:
+        import oracle
+        t0 = time.perf_counter()
+        want = oracle.ewise("or", hA, hB)
+        dt = time.perf_counter() - t0
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": 1,
+                                   "kind": "oracle",
+                                   "sample": "the whole 8192 x 8192 call (numpy, one thread)",
+                                   "cpu": host_cpu()}
+        if not args.no_parity:
+            got = sr.to_host(C)[:, :D].astype(np.int64)
+            out["parity"] = {"entries_compared": D * D, "whole_matrix": True,
+                             "bit_exact": bool(np.array_equal(got, want))}
+    return out
 
 
 def run_serve(args, torch, sr, synthgen):

@@ -116,6 +116,25 @@ def test_product_d8192():
     assert np.array_equal(sr.to_host(C).astype(np.int32), want)
 
 
+def test_add_d8192():
+    """semiring_add of the two D = 8192 uint16 inputs the HBM benchmark
+    times (its streaming form), out of place and in place: every entry
+    against the oracle's entrywise maximum."""
+    D = 8192
+    kind = sr.SR_ANTIDIST_U16
+    A = synthgen.cfg_antidist(D=D, which=0)
+    B = synthgen.cfg_antidist(D=D, which=1)
+    want = oracle.ewise("or", A, B)
+    dA, dB = sr.to_device(kind, A), sr.to_device(kind, B)
+    C = sr.empty(kind, D, D)
+    sr.semiring_add(kind, C, dA, dB)
+    torch.cuda.synchronize()
+    assert np.array_equal(sr.to_host(C).astype(np.int64), want)
+    sr.semiring_add(kind, dB, dA, dB)
+    torch.cuda.synchronize()
+    assert np.array_equal(sr.to_host(dB).astype(np.int64), want)
+
+
 @pytest.fixture(scope="module")
 def cfg3():
     """The D = 16384 Boolean input and its closure by the oracle's bit-packed
