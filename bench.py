@@ -451,9 +451,20 @@ def run_mul(args, torch, sr, synthgen):
            "config": {"workload": "antidist_u16_product_1024", "R": D, "K": D, "N": D,
                       "parallelism": "single_gpu"},
            "fraction_of_valu_roofline": float(D) ** 3 / (ms * 1e-3) / PEAK_ANTIDIST}
-    if not args.no_parity:
-        out["parity"] = {"full_matrix": True, "bit_exact": bool(np.array_equal(
-            sr.to_host(dC).astype(np.int64), oracle.ad_mul(A, B, 65535)))}
+    if not args.no_cpu_baseline or not args.no_parity:
+        # the oracle's product of the same two graphs on all host threads:
+        # the CPU baseline, and every entry of the parity check
+        oracle.set_threads(args.cpu_threads)
+        t0 = time.perf_counter()
+        want = oracle.ad_mul(A, B, 65535)
+        dt = time.perf_counter() - t0
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = {"value": float(D) ** 3 / dt, "unit": "updates/s",
+                                   "cores": args.cpu_threads, "kind": "oracle",
+                                   "sample": "the whole 1024^3 product", "cpu": host_cpu()}
+        if not args.no_parity:
+            out["parity"] = {"full_matrix": True, "bit_exact": bool(np.array_equal(
+                sr.to_host(dC).astype(np.int64), want))}
     return out
 
 
@@ -596,12 +607,24 @@ def run_boolmul(args, torch, sr, synthgen):
     torch.cuda.synchronize()
     out["paths_equal"] = bool(torch.equal(C1, C2) and torch.equal(C1, C3) and torch.equal(C1, C4)
                               and torch.equal(C1, C5))
-    if not args.no_parity:
+    if not args.no_cpu_baseline or not args.no_parity:
+        # the oracle's bit-packed product on all host threads: the CPU
+        # baseline, and every word of the parity check
         oracle.set_threads(args.cpu_threads)
+        t0 = time.perf_counter()
         want = oracle.bool_mul_words(W, W, D, D)
-        nw = D // 64
-        out["parity"] = {"words_compared": int(D * nw), "whole_matrix": True,
-                         "bit_exact": bool(np.array_equal(sr.to_host(C1)[:, :nw], want[:, :nw]))}
+        dt = time.perf_counter() - t0
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = {"value": float(D) ** 3 / dt, "unit": "updates/s",
+                                   "cores": args.cpu_threads, "kind": "oracle",
+                                   "sample": "the whole 16384^3 product (nominal updates; the "
+                                             "bit-packed loop skips rows whose bit is clear)",
+                                   "cpu": host_cpu()}
+        if not args.no_parity:
+            nw = D // 64
+            out["parity"] = {"words_compared": int(D * nw), "whole_matrix": True,
+                             "bit_exact": bool(np.array_equal(sr.to_host(C1)[:, :nw],
+                                                              want[:, :nw]))}
     return out
 
 
