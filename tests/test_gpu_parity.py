@@ -699,6 +699,20 @@ def test_ewise_streaming_sizes(kind, op, name):
     assert np.array_equal(host(Ad).astype(np.int64), want)
 
 
+@pytest.mark.parametrize("R", [1023, 1024])
+def test_ewise_streaming_threshold(R):
+    """Rows of 8192 uint16 entries (16 KiB): 1023 rows stay one row under
+    the 16 MiB operand size that switches to the streaming form, 1024 rows
+    reach it; both give the oracle's result."""
+    kind = sr.SR_ANTIDIST_U16
+    gen = synthgen.generator(7900 + R)
+    A = gen.integers(0, 65536, size=(R, 8192)).astype(np.uint16)
+    B = gen.integers(0, 65536, size=(R, 8192)).astype(np.uint16)
+    C = sr.empty(kind, R, 8192)
+    sr.semiring_add(kind, C, dev(kind, A), dev(kind, B))
+    assert np.array_equal(host(C).astype(np.int64), oracle.ewise("or", A, B))
+
+
 @pytest.mark.parametrize("op,name", [(sr.SR_EW_AND, "and"), (sr.SR_EW_OR, "or"),
                                      (sr.SR_EW_XOR, "xor"), (sr.SR_EW_NOT, "not")])
 def test_ewise_bool_streaming_size(op, name):
